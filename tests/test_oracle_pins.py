@@ -1,0 +1,376 @@
+"""Pins of the CPU oracle against things the paper and the mathematics fix
+(brute force, exact rational arithmetic, LP duality, closed forms, hand-derived
+fixtures).  CPU only."""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import kpgen
+import oracle
+from oracle import exact
+from util import make, random_instance, random_laminar
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _ulps(a, b):
+    return abs(a - b) / math.ulp(max(abs(a), abs(b), 1e-300))
+
+
+# ---------------------------------------------------------------- Alg.1 ----
+
+def test_alg1_hand_fixture():
+    g = json.load(open(os.path.join(GOLD, "alg1_hand_hier.json")))
+    tree = kpgen.Tree(np.array(g["parent"], np.int32), np.array(g["cap"], np.int32),
+                      np.array(g["leaf_of_item"], np.int32))
+    inst = make(np.zeros((1, 6)), np.zeros((1, 6, 1)), [1.0], tree)
+    for case in g["cases"]:
+        assert oracle.alg1(inst, case["z"]).tolist() == case["x"], case["why"]
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_alg1_is_optimal_and_matches_matroid_greedy(seed):
+    """Proposition 1: Alg.1 attains the brute-force optimum; with a strict
+    order it is the unique optimum, and it always equals the laminar-matroid
+    greedy written independently."""
+    rng = np.random.default_rng(seed)
+    M = int(rng.integers(2, 11))
+    tree = random_laminar(M, rng)
+    sets, caps = tree.sets(), list(tree.cap)
+    inst = make(np.zeros((1, M)), np.zeros((1, M, 1)), [1.0], tree)
+    for trial in range(5):
+        if trial % 2:
+            z = rng.integers(-3, 6, size=M).astype(np.float64)  # many ties
+        else:
+            z = rng.standard_normal(M)
+        x = oracle.alg1(inst, z)
+        assert exact.feasible(x, sets, caps)
+        best, args = exact.brute_user(list(z), sets, caps)
+        assert abs(float(z @ x) - best) <= 1e-12 * max(1.0, abs(best))
+        assert np.array_equal(x, exact.matroid_greedy(z, sets, caps))
+        pos = z[z > 0]
+        if len(set(pos.tolist())) == len(pos):
+            # strict order on the positive values -> x is the unique maximiser
+            # among vectors without zero-valued items
+            cand = [a for a in args if all(z[j] != 0 for j in range(M) if a[j])]
+            assert len(cand) == 1 and tuple(x) == cand[0]
+
+
+def test_topq_equals_stable_partial_sort():
+    rng = np.random.default_rng(7)
+    inst = random_instance(rng, N=300, M=12, K=3, Q=4)
+    lam = np.array([0.3, 0.2, 0.4])
+    ev = oracle.eval_dual(inst, lam)
+    pt = oracle.scores(inst, lam)
+    x = ev["x"].reshape(inst.N, inst.M)
+    for i in range(inst.N):
+        order = np.argsort(-pt[i], kind="stable")[:4]
+        ref = np.zeros(inst.M, np.uint8)
+        ref[[j for j in order if pt[i, j] > 0]] = 1
+        assert np.array_equal(x[i], ref)
+
+
+# ------------------------------------------------------------ scoring ------
+
+def test_scores_exact_on_dyadic_inputs():
+    """Multiples of 2^-8 in small ranges: every FP64 step is exact, so the
+    score equals the rational value p - sum lambda b."""
+    rng = np.random.default_rng(3)
+    N, M, K = 50, 6, 7
+    p = rng.integers(0, 256, (N, M)) / 256.0
+    b = rng.integers(0, 256, (N, M, K)) / 256.0
+    lam = rng.integers(0, 512, K) / 256.0
+    inst = make(p, b, np.ones(K), kpgen.tree_topq(M, 2))
+    pt = oracle.scores(inst, lam)
+    for i in range(N):
+        for j in range(M):
+            assert Fraction(pt[i, j]) == exact.exact_score(p[i, j], b[i, j], lam)
+
+
+def test_dense_and_csr_bit_identical():
+    rng = np.random.default_rng(11)
+    inst = random_instance(rng, N=400, M=8, K=6, Q=3, zero_frac=0.6)
+    csr = inst.to_csr()
+    lam = rng.random(6)
+    a, b = oracle.eval_dual(inst, lam), oracle.eval_dual(csr, lam)
+    assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["R"], b["R"])
+    assert a["g"] == b["g"] and a["P"] == b["P"]
+    assert np.array_equal(oracle.scd_sweep(inst, lam), oracle.scd_sweep(csr, lam))
+
+
+# ---------------------------------------------------------- reductions -----
+
+def test_consumption_exact_and_dual_identity():
+    """R is exact on the 2^-24 grid (integer sums), and g - P = lambda.(B - R)."""
+    inst = kpgen.config_instance(1, N=3000)
+    lam = np.array([0.7, 1.1])
+    ev = oracle.eval_dual(inst, lam)
+    x = ev["x"].reshape(inst.N, inst.M).astype(np.int64)
+    q = np.rint(inst.b.reshape(inst.N, inst.M, inst.K).astype(np.float64) * 2 ** 24).astype(np.int64)
+    R_int = np.einsum("ij,ijk->k", x, q)
+    assert np.array_equal(ev["R"], R_int.astype(np.float64) * 2.0 ** -24)
+    lhs = ev["g"] - ev["P"]
+    rhs = float(lam @ (inst.B - ev["R"]))
+    assert abs(lhs - rhs) <= 1e-12 * (abs(ev["g"]) + abs(ev["P"]))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_weak_duality_bruteforce(seed):
+    """g(lambda) >= integer optimum for every lambda >= 0 (Sec. 4.1)."""
+    rng = np.random.default_rng(100 + seed)
+    N, M, K = 3, 3, 2
+    inst = random_instance(rng, N, M, K, Q=2, frac=0.35)
+    opt = exact.brute_global(inst)
+    for _ in range(8):
+        lam = rng.random(K) * 2
+        assert oracle.eval_dual(inst, lam)["g"] >= opt - 1e-12
+
+
+def test_everett_shapiro():
+    """x(lambda) is optimal for budgets replaced by its own consumption where
+    lambda_k > 0 (Sec. 4.4, Shapiro/Everett)."""
+    rng = np.random.default_rng(5)
+    for _ in range(6):
+        inst = random_instance(rng, 3, 3, 2, Q=2)
+        lam = rng.random(2) * 1.5
+        lam[rng.integers(0, 2)] = 0.0 if rng.random() < 0.3 else lam[0]
+        ev = oracle.eval_dual(inst, lam)
+        B2 = np.where(lam > 0, ev["R"], 1e9)
+        sub = make(inst.p.reshape(3, 3), inst.b.reshape(3, 3, 2), B2, inst.tree)
+        assert abs(exact.brute_global(sub) - ev["P"]) <= 1e-9
+
+
+# ---------------------------------------------------------- SCD Map --------
+
+def test_scd_map_hand_fixture():
+    g = json.load(open(os.path.join(GOLD, "scd_hand_mckp.json")))
+    inst = make(g["p"], g["b"], [10.0], kpgen.tree_topq(3, g["Q"]))
+    kk, uu, v1, v2 = oracle.scd_map(inst, g["lambda"])
+    assert [[a, b] for a, b in zip(v1.tolist(), v2.tolist())] == g["pairs"]
+    two_v1 = np.concatenate([v1, v1])
+    two_v2 = np.concatenate([v2, v2])
+    for Bk, want in g["reduce_two_copies"]:
+        assert oracle.scd_reduce(two_v1, two_v2, Bk) == want
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_scd_map_matches_exact_step_function(seed):
+    """Emitted (v1, v2) equal the exact rational step function of the lines:
+    v2 exact, v1 within 2 ulp of the exact crossing (Alg.3/4)."""
+    rng = np.random.default_rng(200 + seed)
+    M = int(rng.integers(2, 8))
+    tree = random_laminar(M, rng) if seed % 2 else kpgen.tree_topq(M, int(rng.integers(1, M + 1)))
+    grid = 4 if seed % 3 == 0 else 24   # coarse grid -> ties, parallel lines, zeros
+    inst = random_instance(rng, 6, M, 3, tree=tree, grid=grid, zero_frac=0.2)
+    lam = rng.integers(0, 64, 3) / 64.0
+    kk, uu, v1, v2 = oracle.scd_map(inst, lam)
+    pt = oracle.scores(inst, lam)
+    bd = inst.b_dense().astype(np.float64)
+    sets, caps = tree.sets(), list(tree.cap)
+    for i in range(inst.N):
+        for k in range(inst.K):
+            c = pt[i] + lam[k] * bd[i, :, k]     # numpy: two roundings, no FMA
+            steps = exact.exact_steps(c, bd[i, :, k], sets, caps)
+            sel = (uu == i) & (kk == k)
+            got = list(zip(v1[sel].tolist(), v2[sel].tolist()))
+            assert len(got) == len(steps), (i, k, got, steps)
+            for (a, da), (u, du) in zip(got, steps):
+                assert Fraction(da) == du
+                assert abs(Fraction(a) - u) <= Fraction(2.5) * Fraction(math.ulp(float(u)))
+            assert sum(Fraction(d) for _, d in got) == sum((d for _, d in steps), Fraction(0))
+
+
+def test_scd_map_alg5_special_case():
+    """Alg.5 (Sec. 5.1): with M = K, diagonal b and one top-Q cap, the general
+    Map emits at most one candidate per k, equal to Alg.5's up to the rounding
+    of the intercept (a few ulp)."""
+    rng = np.random.default_rng(9)
+    N, K, Q = 200, 6, 2
+    p = rng.integers(1, 1 << 24, (N, K)) / float(1 << 24)
+    b = np.zeros((N, K, K))
+    for k in range(K):
+        b[:, k, k] = rng.integers(1, 1 << 24, N) / float(1 << 24)
+    inst = make(p, b, np.ones(K), kpgen.tree_topq(K, Q))
+    lam = rng.random(K) * 0.5
+    kk, uu, v1, v2 = oracle.scd_map(inst, lam)
+    for i in range(N):
+        k5, a5, b5 = oracle.alg5_map_user(inst, lam, i, Q)
+        sel = uu == i
+        assert sorted(kk[sel].tolist()) == sorted(k5.tolist())
+        for k, a, d in zip(k5, a5, b5):
+            m = sel & (kk == k)
+            assert m.sum() == 1
+            assert _ulps(float(v1[m][0]), float(a)) <= 8
+            assert float(v2[m][0]) == float(d)
+
+
+# ---------------------------------------------------------- SCD Reduce -----
+
+def test_scd_reduce_vs_sort_and_scan():
+    rng = np.random.default_rng(4)
+    for _ in range(50):
+        n = int(rng.integers(1, 60))
+        v1 = rng.integers(1, 20, n) / 8.0          # many equal v1
+        v2 = rng.integers(1, 9, n) / 16.0
+        Bk = float(rng.integers(0, int(v2.sum() * 16) + 3)) / 16.0
+        # independent statement: smallest lambda with consumption above it <= B
+        total = sum(Fraction(x) for x in v2)
+        if total <= Fraction(Bk):
+            want = 0.0
+        else:
+            want = None
+            for v in sorted(set(v1.tolist()), reverse=True):
+                if sum(Fraction(d) for a, d in zip(v1, v2) if a >= v) > Fraction(Bk):
+                    want = v
+                    break
+        assert oracle.scd_reduce(v1, v2, Bk) == want
+
+
+@pytest.mark.parametrize("hier", [False, True])
+def test_scd_K1_one_sweep_reaches_lp(hier):
+    """K = 1: the SCD threshold makes 0 a subgradient, so one sweep from any
+    lambda lands on argmin g, and min g equals the LP relaxation (laminar caps
+    give an integral polytope).  Also the Sec. 4.4 bound LP - P <= max p."""
+    rng = np.random.default_rng(21 + hier)
+    N, M = 400, 10
+    tree = kpgen.tree_hier_2_2_3(M) if hier else kpgen.tree_topq(M, 2)
+    inst = random_instance(rng, N, M, 1, tree=tree, frac=0.15)
+    lp = exact.lp_relaxation(inst)
+    for lam0 in (0.0, 0.37, 3.0):
+        lam1 = oracle.scd_sweep(inst, np.array([lam0]))
+        g1 = oracle.eval_dual(inst, lam1)["g"]
+        assert abs(g1 - lp) <= 1e-8 * abs(lp), (lam0, g1, lp)
+        # the greedy solution just above the threshold is feasible and within
+        # max p of the optimum (rounded fractional knapsack, Sec. 4.4)
+        above = oracle.eval_dual(inst, lam1 * (1 + 1e-12) + 1e-300)
+        assert np.all(above["R"] <= inst.B)
+        assert lp - above["P"] <= float(inst.p.max()) + 1e-9
+        fx = oracle.fixup(inst, lam1)
+        assert np.all(fx["R"] <= inst.B)
+
+
+def test_scd_coordinate_optimality():
+    """B_k - C_k(v*+) >= 0 >= B_k - C_k(v*-) at the new threshold."""
+    inst = kpgen.config_instance(1, N=2000)
+    lam = np.array([0.9, 1.6])
+    new = oracle.scd_sweep(inst, lam)
+    for k in range(inst.K):
+        v = new[k]
+        if v == 0:
+            assert oracle.consumption_at(inst, lam, k, 1e-300) <= inst.B[k]
+            continue
+        above = oracle.consumption_at(inst, lam, k, v * (1 + 1e-12))
+        below = oracle.consumption_at(inst, lam, k, v * (1 - 1e-12))
+        assert above <= inst.B[k] < below
+
+
+def test_scd_scaling_and_permutation():
+    """p -> 2p doubles every threshold; b_k, B_k -> 2x halves lambda_k;
+    permuting users changes nothing."""
+    rng = np.random.default_rng(8)
+    inst = random_instance(rng, 300, 6, 3, Q=2, frac=0.2)
+    lam = np.array([0.2, 0.5, 0.1])
+    base = oracle.scd_sweep(inst, lam)
+    P2 = make(2 * inst.p.reshape(300, 6), inst.b.reshape(300, 6, 3), inst.B, inst.tree)
+    assert np.array_equal(oracle.scd_sweep(P2, 2 * lam), 2 * base)
+    b2 = inst.b.reshape(300, 6, 3).copy()
+    b2[:, :, 1] *= 2
+    B2 = inst.B.copy()
+    B2[1] *= 2
+    lam2 = lam.copy()
+    lam2[1] /= 2
+    got = oracle.scd_sweep(make(inst.p.reshape(300, 6), b2, B2, inst.tree), lam2)
+    assert got[1] == base[1] / 2 and got[0] == base[0] and got[2] == base[2]
+    perm = rng.permutation(300)
+    Pp = make(inst.p.reshape(300, 6)[perm], inst.b.reshape(300, 6, 3)[perm], inst.B, inst.tree)
+    assert np.array_equal(oracle.scd_sweep(Pp, lam), base)
+
+
+# ------------------------------------------------------ DD and gradient ----
+
+def test_dd_update_closed_form():
+    lam = np.array([0.5, 0.0, 2.0])
+    R = np.array([10.0, 1.0, 3.0])
+    B = np.array([4.0, 2.0, 8.0])
+    out = oracle.dd_update(lam, 0.1, R, B)
+    assert out.tolist() == [max(0.5 + 0.1 * 6.0, 0), 0.0, max(2.0 + 0.1 * -5.0, 0)]
+
+
+def test_gradient_finite_difference_bracket():
+    """g is convex with subgradient B - R: the central difference along any
+    direction lies between the subgradients at the two end points."""
+    inst = kpgen.config_instance(1, N=2000)
+    rng = np.random.default_rng(2)
+    h = 1e-4
+    for _ in range(5):
+        lam = rng.random(2) * 2 + 0.1
+        d = rng.standard_normal(2)
+        gp = oracle.eval_dual(inst, lam + h * d, want_x=False)
+        gm = oracle.eval_dual(inst, lam - h * d, want_x=False)
+        fd = (gp["g"] - gm["g"]) / (2 * h)
+        lo = float((inst.B - gm["R"]) @ d)
+        hi = float((inst.B - gp["R"]) @ d)
+        g0 = oracle.eval_dual(inst, lam, want_x=False)
+        mid = float((inst.B - g0["R"]) @ d)
+        tol = 1e-7 * (abs(lo) + abs(hi) + 1)
+        assert lo - tol <= fd <= hi + tol and lo - tol <= mid <= hi + tol
+
+
+def test_gradient_exact_on_kink_free_interval():
+    """Away from every breakpoint the dual is linear: FD equals B - R."""
+    inst = make([[3.0, 2.0, 1.0]], [[[3.0], [1.0], [0.5]]], [1.0], kpgen.tree_topq(3, 1))
+    # breakpoints at 0.5, 0.8, 1, 2; pick lambda = 1.5 with h = 1e-4
+    lam = np.array([1.5])
+    h = 1e-4
+    fd = (oracle.eval_dual(inst, lam + h)["g"] - oracle.eval_dual(inst, lam - h)["g"]) / (2 * h)
+    R = oracle.eval_dual(inst, lam)["R"]
+    assert abs(fd - (inst.B[0] - R[0])) <= 1e-9
+
+
+# ------------------------------------------------------------- fix-up ------
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_fixup_feasible_and_prefix_minimal(mode):
+    inst = kpgen.config_instance(1, N=3000)
+    lam = np.array([1.2, 1.25])       # under-priced: both budgets violated
+    ev = oracle.eval_dual(inst, lam, want_G=True)
+    assert np.any(ev["R"] > inst.B)
+    fx = oracle.fixup(inst, lam, mode=mode)
+    assert np.all(fx["R"] <= inst.B)
+    assert fx["P"] <= ev["g"]
+    order = fx["reset"]
+    G = ev["G"]
+    keys = list(zip(G[order], order))
+    assert keys == sorted(keys)         # reset in (G asc, i asc) order
+    # minimal: without the last reset user some budget is still violated
+    x = ev["x"].reshape(inst.N, inst.M).copy()
+    bd = inst.b_dense().astype(np.float64)
+    x[order[:-1]] = 0
+    R = np.einsum("ij,ijk->k", x.astype(np.float64), bd)
+    assert np.any(R > inst.B)
+
+
+# ------------------------------------------------- paper-level claims ------
+
+@pytest.mark.parametrize("K,tree_kind", [(5, "hier"), (10, "q1")])
+def test_optimality_ratio_paper_claim(K, tree_kind):
+    """Sec. 6.1: at N = 10,000, M = 10 the solution is above 99.8% of the LP
+    relaxation bound (b uniform in [0,1] or [0,10] with equal probability).
+    Dense coupled knapsacks make the synchronous update cycle from lambda = 0,
+    so this uses cyclic CD, one of the CD modes of Sec. 4.3.2."""
+    N, M = 10_000, 10
+    seed = 77 + K
+    rng = np.random.default_rng(seed)
+    p = kpgen.gen_p(seed, N, M, kpgen.DIST_UNIFORM).reshape(N, M)
+    b = kpgen.gen_b_dense(seed, N, M, K).reshape(N, M, K).astype(np.float64)
+    b = np.where(rng.random(b.shape) < 0.5, b, 10.0 * b).astype(np.float32)
+    tree = kpgen.tree_hier_2_2_3(M) if tree_kind == "hier" else kpgen.tree_topq(M, 1)
+    B = 0.2 * b.astype(np.float64).sum(axis=(0, 1)) / M
+    inst = make(p, b, B, tree)
+    hist = oracle.solve(inst, "cyclic", tol=1e-4, max_iter=12 * K, fix_every=K)
+    lp = exact.lp_relaxation(inst)
+    assert hist[-1]["best_P"] / lp > 0.998
