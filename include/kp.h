@@ -1,0 +1,174 @@
+/*
+ * kp.h -- C ABI of the MI355X (gfx950) per-user subproblem sweep for the
+ * Lagrangian-dual knapsack solver of "Solving Billion-Scale Knapsack Problems"
+ * (Zhang, Qi, Hua, Yang, WWW'20).
+ *
+ * Problem (Eq.1-4, Sec. 2):  max sum_ij p_ij x_ij
+ *   s.t. sum_ij b_ijk x_ij <= B_k  for every knapsack k      (global, Eq.2)
+ *        sum_{j in S_l} x_ij <= C_l for every user i, set l  (local,  Eq.3)
+ *        x_ij in {0,1}                                        (Eq.4)
+ * with B_k, C_l > 0 and p, b >= 0, and local sets forming a laminar
+ * (hierarchical) family (Sec. 2.1).
+ *
+ * Memory and threading rules for every call below:
+ *  - Pointers marked DEV are device (HIP) pointers; HOST are host pointers.
+ *    The caller owns every buffer passed in; the library keeps no pointer to
+ *    caller memory after the call's work has been enqueued.
+ *  - Host-side validation runs synchronously before anything is enqueued.  On
+ *    any non-OK return nothing was enqueued (except KP_ERR_HIP, which reports
+ *    a HIP runtime failure) and kp_last_error() gives a message.
+ *  - All work is enqueued on the context's stream.  Outputs are valid once
+ *    that stream reaches them.  kp_scd_sweep and kp_primal_fixup synchronise
+ *    the stream internally (they read a small status word back per pass).
+ *  - A context is used by one host thread at a time.  Calls that share a
+ *    context serialise on its workspace.
+ *  - Non-finite or negative p, b are undefined behaviour unless
+ *    kp_validate_inputs reported them absent.
+ */
+#ifndef KP_H
+#define KP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  KP_OK = 0,
+  KP_ERR_INVALID = -1,      /* bad sizes, NULL pointers, B_k <= 0, cap < 1, bad tree links */
+  KP_ERR_NOT_LAMINAR = -2,  /* kp_tree_from_sets: two sets overlap without nesting */
+  KP_ERR_NONFINITE = -3,    /* kp_validate_inputs found NaN/Inf in p or b */
+  KP_ERR_NEGATIVE = -4,     /* kp_validate_inputs found a negative p or b */
+  KP_ERR_UNSUPPORTED = -5,  /* outside the built limits (M > 64, K too large for SCD, ...) */
+  KP_ERR_NOMEM = -6,        /* the workspace would exceed max_workspace_bytes, or hipMalloc failed */
+  KP_ERR_HIP = -7,          /* a HIP runtime call failed */
+  KP_ERR_INTERNAL = -8      /* an internal iteration limit was hit (reported, never silent) */
+} kp_status;
+
+enum { KP_B_DENSE = 0, KP_B_CSR = 1 };
+
+/* One knapsack instance.  Local constraints are a forest: node l has cap[l]
+   (C_l >= 1) and parent[l] (-1 for a root); S_l is every item whose ancestor
+   chain from leaf_of_item[j] passes through l.  Any laminar family is such a
+   forest (the containment DAG of Sec. 2.1 reduced to its covering arcs);
+   kp_tree_from_sets builds one from explicit sets.  A single top-Q cap is
+   {L=1, parent={-1}, cap={Q}, leaf_of_item[j]=0 for all j}.
+   The local constraints are the same for every user (Eq.3 indexes S_l, C_l
+   by l only). */
+typedef struct {
+  int64_t N;                  /* users, >= 0 */
+  int32_t M;                  /* items per user, 1..64 */
+  int32_t K;                  /* knapsacks (global constraints), >= 1 */
+  const float *p;             /* DEV [N*M] profits, item fastest */
+  int32_t b_format;           /* KP_B_DENSE or KP_B_CSR */
+  const float *b;             /* DEV dense [N*M*K] costs, k fastest */
+  const int64_t *b_rowptr;    /* DEV CSR [N*M+1] offsets per item row (row r = i*M + j) */
+  const int32_t *b_col;       /* DEV CSR column (knapsack) ids, strictly ascending per row */
+  const float *b_val;         /* DEV CSR values */
+  const double *B;            /* HOST [K] budgets, each finite and > 0 */
+  int32_t L;                  /* HOST number of local-constraint nodes, >= 0 */
+  const int32_t *parent;      /* HOST [L], -1 = root, else a node id in [0,L) */
+  const int32_t *cap;         /* HOST [L], >= 1 */
+  const int32_t *leaf_of_item;/* HOST [M], innermost node containing item j, or -1 */
+} kp_problem;
+
+/* Message for the last non-OK status returned on this thread. */
+const char *kp_last_error(void);
+
+/* Create a context bound to a HIP stream (hipStream_t passed as void*; NULL =
+   the null stream).  max_workspace_bytes caps the device workspace the
+   context may allocate (0 = no cap); exceeding it returns KP_ERR_NOMEM. */
+kp_status kp_create(void **ctx_out, void *hip_stream, size_t max_workspace_bytes);
+/* Free the context and its workspace (synchronises its stream first). */
+kp_status kp_destroy(void *ctx);
+/* Rebind the context to another stream. */
+kp_status kp_set_stream(void *ctx, void *hip_stream);
+
+/* Dual evaluation at lambda (Eq.5 with Alg.2's Map and Reduce):
+   every user scores its items p~_ij = p_ij - sum_k lambda_k b_ijk (FP64,
+   k ascending, no FMA), solves its local integer program with Alg.1 (ties in
+   p~ go to the lower item index; only p~ > 0 is selected), and the library
+   reduces R_k = sum_ij b_ijk x_ij, primal P = sum_ij p_ij x_ij and
+   g = sum_i sum_j p~_ij x_ij + sum_k lambda_k B_k in FP64.
+   lambda: DEV [K] >= 0.  R: DEV [K].  g, primal: DEV [1].
+   x: DEV [N*M] uint8 decisions, or NULL. */
+kp_status kp_eval_dual(void *ctx, const kp_problem *prob, const double *lambda,
+                       double *R, double *g, double *primal, uint8_t *x);
+
+/* One synchronous coordinate-descent iteration (Alg.4 with Alg.3's
+   candidates): for every knapsack k, the consumption step function of every
+   user as lambda_k alone moves (lines c_j - lambda_k b_ijk with
+   c_j = p~_ij + lambda_k^t b_ijk), and the global threshold: lambda_out[k] = 0
+   when the total increment fits in B_k, else the largest breakpoint at which
+   the cumulative increment from above exceeds B_k.  All k are updated from
+   the same lambda_in.  R, g, primal (DEV, may be NULL) are the statistics at
+   lambda_in.  lambda_in and lambda_out: DEV [K]; they may alias.
+   Synchronises the context stream. */
+kp_status kp_scd_sweep(void *ctx, const kp_problem *prob, const double *lambda_in,
+                       double *lambda_out, double *R, double *g, double *primal);
+
+/* Same, updating only the coordinates with kmask[k] != 0 (HOST [K]); the
+   others are copied from lambda_in.  Cyclic CD passes one coordinate per
+   call, block CD a block (Sec. 4.3.2). */
+kp_status kp_scd_sweep_masked(void *ctx, const kp_problem *prob, const double *lambda_in,
+                              double *lambda_out, const uint8_t *kmask, double *R, double *g,
+                              double *primal);
+
+/* One dual-descent step (Eq.14, Alg.2):
+   lambda_k <- max(lambda_k + alpha (R_k - B_k), 0), with R, g, primal (DEV,
+   may be NULL) the statistics at the old lambda.  lambda_inout: DEV [K]. */
+kp_status kp_dd_step(void *ctx, const kp_problem *prob, double alpha, double *lambda_inout,
+                     double *R, double *g, double *primal);
+
+/* Gradient of the dual for the autograd backward: grad_lambda[k] =
+   grad_out[0] * (B_k - R[k]) (g is convex with subgradient B - R, Sec. 4.1).
+   R: DEV [K] from kp_eval_dual at the same lambda.  grad_out: DEV [1].
+   grad_lambda: DEV [K]. */
+kp_status kp_dual_backward(void *ctx, const kp_problem *prob, const double *R,
+                           const double *grad_out, double *grad_lambda);
+
+/* Post-processing for feasibility (Sec. 5.4) at lambda: users that consume
+   at least one knapsack violated by x(lambda) are ordered by their group dual
+   value p~_i = sum_j p_ij x_ij - sum_k lambda_k sum_j b_ijk x_ij ascending
+   (ties: lower user index first) and the shortest prefix of that order whose
+   removal brings every violated knapsack within budget is reset to x_i = 0.
+   Outputs (DEV): x_out [N*M] (may be NULL), primal_out [1], R_out [K],
+   n_reset_out [1] (int64).  Synchronises the context stream. */
+kp_status kp_primal_fixup(void *ctx, const kp_problem *prob, const double *lambda,
+                          uint8_t *x_out, double *primal_out, double *R_out,
+                          int64_t *n_reset_out);
+
+/* Batched SCD: one iteration for n independent instances (probs: HOST [n]),
+   lambda_in[s] / lambda_out[s]: DEV [K_s] per instance (HOST arrays of n DEV
+   pointers).  stats: DEV [sum_s (K_s + 2)] -- per instance R[K_s], g, primal at
+   lambda_in, concatenated in instance order (may be NULL).
+   Synchronises the context stream. */
+kp_status kp_scd_sweep_batched(void *ctx, const kp_problem *probs, int32_t n,
+                               const double *const *lambda_in, double *const *lambda_out,
+                               double *stats);
+
+/* Optional full pass over p and b: KP_ERR_NONFINITE / KP_ERR_NEGATIVE if any
+   value is NaN/Inf or negative, KP_OK otherwise (a CSR column outside [0,K) or
+   not ascending is KP_ERR_INVALID).  Synchronises the context stream. */
+kp_status kp_validate_inputs(void *ctx, const kp_problem *prob);
+
+/* Host helper: explicit local sets {S_l, C_l} (set_offsets HOST [L+1] into
+   set_items HOST, caps HOST [L]) to the forest form above.  Identical sets are
+   merged keeping the smaller cap; KP_ERR_NOT_LAMINAR if two sets overlap
+   without one containing the other (Definition in Sec. 2.1).  Outputs (HOST,
+   sized L and M by the caller): L_out, parent_out, cap_out, leaf_of_item_out. */
+kp_status kp_tree_from_sets(int32_t M, int32_t L, const int32_t *set_offsets,
+                            const int32_t *set_items, const int32_t *caps, int32_t *L_out,
+                            int32_t *parent_out, int32_t *cap_out,
+                            int32_t *leaf_of_item_out);
+
+/* Size limits of this build. */
+int32_t kp_max_items(void);        /* 64 */
+int32_t kp_max_knapsacks_scd(void);/* largest K accepted by the SCD calls */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KP_H */

@@ -1,0 +1,274 @@
+"""MI355X (gfx950) per-user subproblem sweep of the Lagrangian-dual knapsack
+solver ("Solving Billion-Scale Knapsack Problems", Zhang et al., WWW'20).
+
+Thin Python binding of the C ABI in include/kp.h: argument marshalling only.
+Every step of the sweep runs in the HIP kernels of libkp.so; PyTorch provides
+device memory and the current HIP stream.  If the library is not built the
+calls raise -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_REPO = os.path.dirname(_HERE)
+LIB_PATH = os.path.join(_HERE, "libkp.so")
+SOURCES = [os.path.join(_HERE, "csrc", "kp_kernels.hip"), os.path.join(_HERE, "csrc", "kp_capi.hip")]
+HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+               "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+               "-Wno-unused-result"]
+
+KP_OK = 0
+STATUS = {0: "KP_OK", -1: "KP_ERR_INVALID", -2: "KP_ERR_NOT_LAMINAR", -3: "KP_ERR_NONFINITE",
+          -4: "KP_ERR_NEGATIVE", -5: "KP_ERR_UNSUPPORTED", -6: "KP_ERR_NOMEM", -7: "KP_ERR_HIP",
+          -8: "KP_ERR_INTERNAL"}
+KP_B_DENSE, KP_B_CSR = 0, 1
+
+
+def build() -> str:
+    """Compile libkp.so for gfx950 with hipcc (always recompiles)."""
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    tmp = LIB_PATH + ".tmp"
+    subprocess.check_call([hipcc, *HIPCC_FLAGS, "-o", tmp, *SOURCES])
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+class KPError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class kp_problem(ctypes.Structure):
+    _fields_ = [
+        ("N", ctypes.c_int64), ("M", ctypes.c_int32), ("K", ctypes.c_int32),
+        ("p", ctypes.c_void_p), ("b_format", ctypes.c_int32), ("b", ctypes.c_void_p),
+        ("b_rowptr", ctypes.c_void_p), ("b_col", ctypes.c_void_p), ("b_val", ctypes.c_void_p),
+        ("B", ctypes.c_void_p), ("L", ctypes.c_int32), ("parent", ctypes.c_void_p),
+        ("cap", ctypes.c_void_p), ("leaf_of_item", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+EXPORTS = ["kp_last_error", "kp_create", "kp_destroy", "kp_set_stream", "kp_eval_dual",
+           "kp_scd_sweep", "kp_scd_sweep_masked", "kp_dd_step", "kp_dual_backward",
+           "kp_primal_fixup", "kp_scd_sweep_batched", "kp_validate_inputs", "kp_tree_from_sets",
+           "kp_max_items", "kp_max_knapsacks_scd"]
+
+
+def lib():
+    """Load libkp.so (raises when it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        P = ctypes.POINTER(kp_problem)
+        L.kp_last_error.restype = ctypes.c_char_p
+        L.kp_create.argtypes = [ctypes.POINTER(vp), vp, ctypes.c_size_t]
+        L.kp_destroy.argtypes = [vp]
+        L.kp_set_stream.argtypes = [vp, vp]
+        L.kp_eval_dual.argtypes = [vp, P, vp, vp, vp, vp, vp]
+        L.kp_scd_sweep.argtypes = [vp, P, vp, vp, vp, vp, vp]
+        L.kp_scd_sweep_masked.argtypes = [vp, P, vp, vp, vp, vp, vp, vp]
+        L.kp_dd_step.argtypes = [vp, P, d, vp, vp, vp, vp]
+        L.kp_dual_backward.argtypes = [vp, P, vp, vp, vp]
+        L.kp_primal_fixup.argtypes = [vp, P, vp, vp, vp, vp, vp]
+        L.kp_scd_sweep_batched.argtypes = [vp, P, i32, vp, vp, vp]
+        L.kp_validate_inputs.argtypes = [vp, P]
+        L.kp_tree_from_sets.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp]
+        L.kp_max_items.restype = i32
+        L.kp_max_knapsacks_scd.restype = i32
+        for name in EXPORTS:
+            if name not in ("kp_last_error", "kp_max_items", "kp_max_knapsacks_scd"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != KP_OK:
+        raise KPError(status, lib().kp_last_error().decode())
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    return t.data_ptr()
+
+
+def _stream_handle():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Context:
+    """A kp context bound to the current torch HIP stream."""
+
+    def __init__(self, max_workspace_bytes: int = 0):
+        self.h = ctypes.c_void_p()
+        _check(lib().kp_create(ctypes.byref(self.h), _stream_handle(), max_workspace_bytes))
+
+    def sync_stream(self):
+        _check(lib().kp_set_stream(self.h, _stream_handle()))
+
+    def close(self):
+        if self.h:
+            lib().kp_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default_ctx: Optional[Context] = None
+
+
+def default_context() -> Context:
+    global _default_ctx
+    if _default_ctx is None:
+        _default_ctx = Context()
+    _default_ctx.sync_stream()
+    return _default_ctx
+
+
+class Problem:
+    """Device-resident instance: p, b (dense or CSR) as torch tensors on the
+    GPU; B and the local-constraint forest on the host."""
+
+    def __init__(self, p, B, parent, cap, leaf_of_item, *, b=None, rowptr=None, col=None,
+                 val=None, N=None, M=None, K=None):
+        import torch
+        self.p = p
+        self.b, self.rowptr, self.col, self.val = b, rowptr, col, val
+        self.B = np.ascontiguousarray(B, np.float64)
+        self.parent = np.ascontiguousarray(parent, np.int32)
+        self.cap = np.ascontiguousarray(cap, np.int32)
+        self.leaf = np.ascontiguousarray(leaf_of_item, np.int32)
+        self.N, self.M, self.K = int(N), int(M), int(K)
+        for t in (p, b, rowptr, col, val):
+            if t is not None and not (isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous()):
+                raise TypeError("p/b arrays must be contiguous GPU tensors")
+        s = kp_problem()
+        s.N, s.M, s.K = self.N, self.M, self.K
+        s.p = _ptr(p)
+        s.b_format = KP_B_DENSE if b is not None else KP_B_CSR
+        s.b, s.b_rowptr, s.b_col, s.b_val = _ptr(b), _ptr(rowptr), _ptr(col), _ptr(val)
+        s.B = _ptr(self.B)
+        s.L = len(self.parent)
+        s.parent, s.cap, s.leaf_of_item = _ptr(self.parent), _ptr(self.cap), _ptr(self.leaf)
+        self.s = s
+
+    @property
+    def ref(self):
+        return ctypes.byref(self.s)
+
+    @classmethod
+    def from_host(cls, inst, device="cuda"):
+        """Copy a host instance (kpgen.Instance-like) to the GPU."""
+        import torch
+        t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dt)).to(device)
+        kw = {}
+        if inst.b is not None:
+            kw["b"] = t(inst.b, np.float32)
+        else:
+            kw.update(rowptr=t(inst.rowptr, np.int64), col=t(inst.col, np.int32),
+                      val=t(inst.val, np.float32))
+        return cls(t(inst.p, np.float32), inst.B, inst.tree.parent, inst.tree.cap,
+                   inst.tree.leaf_of_item, N=inst.N, M=inst.M, K=inst.K, **kw)
+
+
+# ---------------------------------------------------------------------------
+# the C ABI, one Python function per entry point (tensors in, tensors out)
+# ---------------------------------------------------------------------------
+
+def _dev_f64(n):
+    import torch
+    return torch.empty(n, dtype=torch.float64, device="cuda")
+
+
+def kp_eval_dual(prob: Problem, lam, want_x: bool = False, ctx: Optional[Context] = None):
+    """g(lambda), R(lambda), P(x(lambda)) and optionally x (uint8 [N*M])."""
+    import torch
+    ctx = ctx or default_context()
+    R, g, P = _dev_f64(prob.K), _dev_f64(1), _dev_f64(1)
+    x = torch.empty(prob.N * prob.M, dtype=torch.uint8, device="cuda") if want_x else None
+    _check(lib().kp_eval_dual(ctx.h, prob.ref, _ptr(lam), _ptr(R), _ptr(g), _ptr(P), _ptr(x)))
+    return dict(R=R, g=g, P=P, x=x)
+
+
+def kp_scd_sweep(prob: Problem, lam_in, lam_out=None, kmask=None, ctx: Optional[Context] = None):
+    """One SCD iteration: returns lambda_out and the statistics at lambda_in."""
+    ctx = ctx or default_context()
+    lam_out = _dev_f64(prob.K) if lam_out is None else lam_out
+    R, g, P = _dev_f64(prob.K), _dev_f64(1), _dev_f64(1)
+    if kmask is None:
+        st = lib().kp_scd_sweep(ctx.h, prob.ref, _ptr(lam_in), _ptr(lam_out), _ptr(R), _ptr(g), _ptr(P))
+    else:
+        km = np.ascontiguousarray(kmask, np.uint8)
+        st = lib().kp_scd_sweep_masked(ctx.h, prob.ref, _ptr(lam_in), _ptr(lam_out), _ptr(km),
+                                       _ptr(R), _ptr(g), _ptr(P))
+    _check(st)
+    return dict(lam=lam_out, R=R, g=g, P=P)
+
+
+def kp_dd_step(prob: Problem, alpha: float, lam, ctx: Optional[Context] = None):
+    """One DD step in place on lam; returns the statistics at the old lambda."""
+    ctx = ctx or default_context()
+    R, g, P = _dev_f64(prob.K), _dev_f64(1), _dev_f64(1)
+    _check(lib().kp_dd_step(ctx.h, prob.ref, float(alpha), _ptr(lam), _ptr(R), _ptr(g), _ptr(P)))
+    return dict(lam=lam, R=R, g=g, P=P)
+
+
+def kp_dual_backward(prob: Problem, R, grad_out, ctx: Optional[Context] = None):
+    ctx = ctx or default_context()
+    gl = _dev_f64(prob.K)
+    _check(lib().kp_dual_backward(ctx.h, prob.ref, _ptr(R), _ptr(grad_out), _ptr(gl)))
+    return gl
+
+
+def kp_primal_fixup(prob: Problem, lam, want_x: bool = False, ctx: Optional[Context] = None):
+    import torch
+    ctx = ctx or default_context()
+    x = torch.empty(prob.N * prob.M, dtype=torch.uint8, device="cuda") if want_x else None
+    P, R = _dev_f64(1), _dev_f64(prob.K)
+    nres = torch.zeros(1, dtype=torch.int64, device="cuda")
+    _check(lib().kp_primal_fixup(ctx.h, prob.ref, _ptr(lam), _ptr(x), _ptr(P), _ptr(R), _ptr(nres)))
+    return dict(x=x, P=P, R=R, n_reset=nres)
+
+
+def kp_validate_inputs(prob: Problem, ctx: Optional[Context] = None):
+    ctx = ctx or default_context()
+    _check(lib().kp_validate_inputs(ctx.h, prob.ref))
+
+
+def kp_tree_from_sets(M: int, sets: Sequence[Sequence[int]], caps: Sequence[int]):
+    """Explicit local sets -> (parent, cap, leaf_of_item) forest (host helper)."""
+    L = len(sets)
+    off = np.zeros(L + 1, np.int32)
+    off[1:] = np.cumsum([len(s) for s in sets])
+    items = np.array([j for s in sets for j in s] or [0], np.int32)
+    caps = np.ascontiguousarray(caps, np.int32) if L else np.zeros(1, np.int32)
+    Lo = ctypes.c_int32()
+    par = np.zeros(max(L, 1), np.int32)
+    cp = np.zeros(max(L, 1), np.int32)
+    leaf = np.zeros(M, np.int32)
+    _check(lib().kp_tree_from_sets(M, L, _ptr(off), _ptr(items), _ptr(caps), ctypes.byref(Lo),
+                                   _ptr(par), _ptr(cp), _ptr(leaf)))
+    n = Lo.value
+    return par[:n].copy(), cp[:n].copy(), leaf
+
+
+from .driver import DualFn, solve  # noqa: E402  (autograd and the solve loop)

@@ -1,0 +1,551 @@
+// C ABI of the sweep library: validation, context and workspace, and the
+// host orchestration of the kernels in kp_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/kp.h"
+#include "kp_internal.h"
+
+// launchers (kp_kernels.hip)
+size_t kp_sweep_lds_bytes(int U, int M, int K, bool scd);
+hipError_t kp_launch_sweep(const SweepArgs &a, int U, int grid, bool scd, hipStream_t stream);
+hipError_t kp_launch_reduce_stats(const double *partials, int nblk, int K, const double *lam,
+                                  const double *B, double *R, double *g, double *P,
+                                  hipStream_t stream);
+hipError_t kp_launch_scd_init(KState *st, int K, const double *lam_in, const uint8_t *kmask,
+                              const double *delta_hint, hipStream_t stream);
+hipError_t kp_launch_scd_locate_select(KState *st, int K, const double *B, double *hist_sum,
+                                       uint32_t *hist_cnt, const double *ev1, const double *ev2,
+                                       uint32_t emit_cap, int *pending, hipStream_t stream);
+hipError_t kp_launch_scd_finish(const KState *st, int K, const double *lam_in, double *lam_out,
+                                double *delta_next, hipStream_t stream);
+hipError_t kp_launch_dd_update(int K, double alpha, const double *R, const double *B, double *lam,
+                               hipStream_t stream);
+hipError_t kp_launch_dual_backward(int K, const double *R, const double *B, const double *gout,
+                                   double *glam, hipStream_t stream);
+hipError_t kp_launch_validate(const float *v, int64_t n, unsigned int *flags, hipStream_t stream);
+hipError_t kp_launch_validate_csr(const int64_t *rowptr, const int32_t *col, int64_t nrows, int K,
+                                  unsigned int *flags, hipStream_t stream);
+
+namespace {
+
+thread_local std::string g_err;
+
+kp_status fail(kp_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                 \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(KP_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));          \
+  } while (0)
+
+constexpr int kTileBudget = 24 * 1024;   // bytes of staged costs per tile
+constexpr int kMaxGrid = 2048;
+constexpr uint32_t kEmitCapDefault = 1u << 20;
+constexpr int kMaxPasses = 96;
+
+struct Ctx {
+  hipStream_t stream = nullptr;
+  size_t max_ws = 0;
+  void *ws = nullptr;
+  size_t ws_cap = 0;
+  int *pinned = nullptr;          // host-visible status word
+  // central-window hint for the next SCD call (performance only)
+  double *delta_dev = nullptr;
+  int delta_K = 0;
+  bool delta_valid = false;
+};
+
+// Workspace carve: every block 256-byte aligned.
+struct Carve {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    size_t o = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return o;
+  }
+};
+
+kp_status ensure_ws(Ctx *c, size_t bytes) {
+  if (!c->pinned) {
+    if (hipHostMalloc((void **)&c->pinned, 64, hipHostMallocDefault) != hipSuccess) {
+      c->pinned = nullptr;
+      return fail(KP_ERR_HIP, "hipHostMalloc of the status word failed");
+    }
+  }
+  if (bytes <= c->ws_cap) return KP_OK;
+  if (c->max_ws && bytes > c->max_ws)
+    return fail(KP_ERR_NOMEM, "workspace of %zu bytes exceeds the context cap of %zu bytes", bytes,
+                c->max_ws);
+  if (c->ws) {
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipFree(c->ws));
+    c->ws = nullptr;
+    c->ws_cap = 0;
+  }
+  size_t want = std::max(bytes, (size_t)1 << 20);
+  if (c->max_ws) want = std::min(want, c->max_ws);
+  if (hipMalloc(&c->ws, want) != hipSuccess) {
+    c->ws = nullptr;
+    return fail(KP_ERR_NOMEM, "hipMalloc of %zu workspace bytes failed", want);
+  }
+  c->ws_cap = want;
+  return KP_OK;
+}
+
+// ---- problem validation and tree preparation ----
+struct Prepared {
+  ProbDev pr;
+  TreeDev tree;
+  std::vector<double> B;
+  int U = 1;
+  int64_t ntiles = 0;
+  int grid = 1;
+};
+
+kp_status prepare(const kp_problem *p, bool scd, Prepared &out) {
+  if (!p) return fail(KP_ERR_INVALID, "problem is NULL");
+  if (p->N < 0) return fail(KP_ERR_INVALID, "N must be >= 0 (got %lld)", (long long)p->N);
+  if (p->M < 1) return fail(KP_ERR_INVALID, "M must be >= 1 (got %d)", p->M);
+  if (p->M > KP_MAX_M) return fail(KP_ERR_UNSUPPORTED, "M = %d exceeds the built limit %d", p->M, KP_MAX_M);
+  if (p->K < 1) return fail(KP_ERR_INVALID, "K must be >= 1 (got %d)", p->K);
+  if (scd && p->K > KP_MAX_K_SCD)
+    return fail(KP_ERR_UNSUPPORTED, "K = %d exceeds the SCD limit %d", p->K, KP_MAX_K_SCD);
+  if (p->b_format != KP_B_DENSE && p->b_format != KP_B_CSR)
+    return fail(KP_ERR_INVALID, "b_format must be KP_B_DENSE or KP_B_CSR");
+  if (p->N > 0) {
+    if (!p->p) return fail(KP_ERR_INVALID, "p is NULL");
+    if (p->b_format == KP_B_DENSE && !p->b) return fail(KP_ERR_INVALID, "b is NULL");
+    if (p->b_format == KP_B_CSR && (!p->b_rowptr || !p->b_col || !p->b_val))
+      return fail(KP_ERR_INVALID, "CSR arrays must not be NULL");
+  }
+  if (!p->B) return fail(KP_ERR_INVALID, "B is NULL");
+  out.B.assign(p->B, p->B + p->K);
+  for (int k = 0; k < p->K; ++k)
+    if (!(std::isfinite(out.B[k]) && out.B[k] > 0.0))
+      return fail(KP_ERR_INVALID, "B[%d] = %g must be finite and > 0", k, out.B[k]);
+  const int L = p->L, M = p->M;
+  if (L < 0) return fail(KP_ERR_INVALID, "L must be >= 0");
+  if (L > 0 && (!p->parent || !p->cap)) return fail(KP_ERR_INVALID, "parent/cap is NULL");
+  if (!p->leaf_of_item) return fail(KP_ERR_INVALID, "leaf_of_item is NULL");
+  for (int l = 0; l < L; ++l) {
+    if (p->cap[l] < 1) return fail(KP_ERR_INVALID, "cap[%d] = %d must be >= 1", l, p->cap[l]);
+    if (p->parent[l] < -1 || p->parent[l] >= L || p->parent[l] == l)
+      return fail(KP_ERR_INVALID, "parent[%d] = %d out of range", l, p->parent[l]);
+  }
+  // acyclic: every chain reaches a root within L steps
+  for (int l = 0; l < L; ++l) {
+    int x = l, steps = 0;
+    while (x >= 0 && steps <= L) { x = p->parent[x]; ++steps; }
+    if (x >= 0) return fail(KP_ERR_INVALID, "parent links contain a cycle (node %d)", l);
+  }
+  std::vector<uint64_t> mask(L, 0);
+  for (int j = 0; j < M; ++j) {
+    const int lf = p->leaf_of_item[j];
+    if (lf < -1 || lf >= L) return fail(KP_ERR_INVALID, "leaf_of_item[%d] = %d out of range", j, lf);
+    for (int x = lf; x >= 0; x = p->parent[x]) mask[x] |= 1ull << j;
+  }
+  // keep sets that can bind; merge duplicates with the smaller cap
+  std::map<uint64_t, int> keep;
+  for (int l = 0; l < L; ++l) {
+    const int sz = __builtin_popcountll(mask[l]);
+    if (p->cap[l] >= sz) continue;
+    auto it = keep.find(mask[l]);
+    if (it == keep.end()) keep[mask[l]] = p->cap[l];
+    else it->second = std::min(it->second, p->cap[l]);
+  }
+  std::vector<std::pair<uint64_t, int>> nodes(keep.begin(), keep.end());
+  if ((int)nodes.size() > KP_MAX_NODES)
+    return fail(KP_ERR_UNSUPPORTED, "%zu binding local sets exceed the limit %d", nodes.size(), KP_MAX_NODES);
+  std::stable_sort(nodes.begin(), nodes.end(), [](const std::pair<uint64_t, int> &a, const std::pair<uint64_t, int> &b) {
+    const int sa = __builtin_popcountll(a.first), sb = __builtin_popcountll(b.first);
+    if (sa != sb) return sa < sb;
+    return __builtin_ctzll(a.first) < __builtin_ctzll(b.first);
+  });
+  memset(&out.tree, 0, sizeof(out.tree));
+  out.tree.L = (int)nodes.size();
+  for (size_t t = 0; t < nodes.size(); ++t) {
+    out.tree.mask[t] = nodes[t].first;
+    out.tree.cap[t] = nodes[t].second;
+  }
+  ProbDev &pr = out.pr;
+  memset(&pr, 0, sizeof(pr));
+  pr.N = p->N;
+  pr.M = M;
+  pr.K = p->K;
+  pr.fmt = p->b_format;
+  pr.p = p->p;
+  pr.b = p->b;
+  pr.rowptr = p->b_rowptr;
+  pr.col = p->b_col;
+  pr.val = p->b_val;
+  // tile: as many users as fit the staged-cost budget, at most 64
+  const size_t per_user = (size_t)M * p->K * 4;
+  int U = (int)std::max<size_t>(1, std::min<size_t>(64, kTileBudget / per_user));
+  if (U >= 4) U &= ~3;   // keeps 16-byte alignment of dense tiles when M*K is odd
+  while (U > 1 && kp_sweep_lds_bytes(U, M, p->K, scd) > 64 * 1024) --U;
+  if (kp_sweep_lds_bytes(U, M, p->K, scd) > 64 * 1024)
+    return fail(KP_ERR_UNSUPPORTED, "M*K = %d too large for one tile", M * p->K);
+  out.U = U;
+  out.ntiles = (p->N + U - 1) / U;
+  out.grid = (int)std::max<int64_t>(1, std::min<int64_t>(out.ntiles, kMaxGrid));
+  return KP_OK;
+}
+
+struct SweepWs {
+  double *partials, *B, *hist_sum, *ev1, *ev2, *Rtmp, *gtmp, *Ptmp;
+  uint32_t *hist_cnt;
+  KState *st;
+  uint8_t *kmask;
+  unsigned long long *err;
+  int *pending;
+  uint32_t emit_cap;
+};
+
+kp_status carve_ws(Ctx *c, const Prepared &P, bool scd, SweepWs &w) {
+  const int K = P.pr.K;
+  Carve cv;
+  size_t o_part = cv.take((size_t)P.grid * (K + 2) * 8);
+  size_t o_B = cv.take((size_t)K * 8);
+  size_t o_R = cv.take((size_t)K * 8);
+  size_t o_g = cv.take(8);
+  size_t o_P = cv.take(8);
+  size_t o_err = cv.take(8);
+  size_t o_pend = cv.take(8);
+  size_t o_st = 0, o_hs = 0, o_hc = 0, o_km = 0, o_e1 = 0, o_e2 = 0;
+  uint32_t cap = 0;
+  if (scd) {
+    o_st = cv.take((size_t)K * sizeof(KState));
+    o_hs = cv.take((size_t)K * KP_NB * 8);
+    o_hc = cv.take((size_t)K * KP_NB * 4);
+    o_km = cv.take((size_t)K);
+    cap = kEmitCapDefault;
+    o_e1 = cv.take((size_t)K * cap * 8);
+    o_e2 = cv.take((size_t)K * cap * 8);
+  }
+  kp_status s = ensure_ws(c, cv.off);
+  if (s != KP_OK) return s;
+  char *b = (char *)c->ws;
+  w.partials = (double *)(b + o_part);
+  w.B = (double *)(b + o_B);
+  w.Rtmp = (double *)(b + o_R);
+  w.gtmp = (double *)(b + o_g);
+  w.Ptmp = (double *)(b + o_P);
+  w.err = (unsigned long long *)(b + o_err);
+  w.pending = (int *)(b + o_pend);
+  w.st = scd ? (KState *)(b + o_st) : nullptr;
+  w.hist_sum = scd ? (double *)(b + o_hs) : nullptr;
+  w.hist_cnt = scd ? (uint32_t *)(b + o_hc) : nullptr;
+  w.kmask = scd ? (uint8_t *)(b + o_km) : nullptr;
+  w.ev1 = scd ? (double *)(b + o_e1) : nullptr;
+  w.ev2 = scd ? (double *)(b + o_e2) : nullptr;
+  w.emit_cap = cap;
+  return KP_OK;
+}
+
+SweepArgs make_args(const Prepared &P, const double *lam, const SweepWs &w, uint8_t *x,
+                    bool stats) {
+  SweepArgs a;
+  memset(&a, 0, sizeof(a));
+  a.pr = P.pr;
+  a.tree = P.tree;
+  a.lam = lam;
+  a.ntiles = P.ntiles;
+  a.want_stats = stats ? 1 : 0;
+  a.partials = w.partials;
+  a.x_out = x;
+  a.st = w.st;
+  a.hist_sum = w.hist_sum;
+  a.hist_cnt = w.hist_cnt;
+  a.emit_v1 = w.ev1;
+  a.emit_v2 = w.ev2;
+  a.emit_cap = w.emit_cap;
+  a.err = w.err;
+  return a;
+}
+
+kp_status eval_into(Ctx *c, const Prepared &P, const SweepWs &w, const double *lam, double *R,
+                    double *g, double *primal, uint8_t *x) {
+  if (P.pr.N == 0) {
+    // nothing to sweep: R = 0, P = 0, g = lambda . B
+    HIP_TRY(hipMemsetAsync(w.partials, 0, (size_t)(P.pr.K + 2) * 8, c->stream));
+    HIP_TRY(kp_launch_reduce_stats(w.partials, 1, P.pr.K, lam, w.B, R, g, primal, c->stream));
+    return KP_OK;
+  }
+  SweepArgs a = make_args(P, lam, w, x, true);
+  HIP_TRY(kp_launch_sweep(a, P.U, P.grid, false, c->stream));
+  HIP_TRY(kp_launch_reduce_stats(w.partials, P.grid, P.pr.K, lam, w.B, R, g, primal, c->stream));
+  return KP_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+const char *kp_last_error(void) { return g_err.c_str(); }
+
+int32_t kp_max_items(void) { return KP_MAX_M; }
+int32_t kp_max_knapsacks_scd(void) { return KP_MAX_K_SCD; }
+
+kp_status kp_create(void **ctx_out, void *hip_stream, size_t max_workspace_bytes) {
+  if (!ctx_out) return fail(KP_ERR_INVALID, "ctx_out is NULL");
+  Ctx *c = new Ctx();
+  c->stream = (hipStream_t)hip_stream;
+  c->max_ws = max_workspace_bytes;
+  *ctx_out = c;   // device resources are allocated on first use
+  return KP_OK;
+}
+
+kp_status kp_destroy(void *ctx) {
+  if (!ctx) return KP_OK;
+  Ctx *c = (Ctx *)ctx;
+  if (c->ws || c->delta_dev || c->pinned) (void)hipStreamSynchronize(c->stream);
+  if (c->ws) (void)hipFree(c->ws);
+  if (c->delta_dev) (void)hipFree(c->delta_dev);
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  delete c;
+  return KP_OK;
+}
+
+kp_status kp_set_stream(void *ctx, void *hip_stream) {
+  if (!ctx) return fail(KP_ERR_INVALID, "ctx is NULL");
+  ((Ctx *)ctx)->stream = (hipStream_t)hip_stream;
+  return KP_OK;
+}
+
+kp_status kp_eval_dual(void *ctx, const kp_problem *prob, const double *lambda, double *R,
+                       double *g, double *primal, uint8_t *x) {
+  if (!ctx) return fail(KP_ERR_INVALID, "ctx is NULL");
+  if (!lambda) return fail(KP_ERR_INVALID, "lambda is NULL");
+  Ctx *c = (Ctx *)ctx;
+  Prepared P;
+  kp_status s = prepare(prob, false, P);
+  if (s != KP_OK) return s;
+  SweepWs w;
+  if ((s = carve_ws(c, P, false, w)) != KP_OK) return s;
+  HIP_TRY(hipMemcpyAsync(w.B, P.B.data(), (size_t)P.pr.K * 8, hipMemcpyHostToDevice, c->stream));
+  return eval_into(c, P, w, lambda, R ? R : w.Rtmp, g ? g : w.gtmp, primal ? primal : w.Ptmp, x);
+}
+
+kp_status kp_dd_step(void *ctx, const kp_problem *prob, double alpha, double *lambda_inout,
+                     double *R, double *g, double *primal) {
+  if (!ctx) return fail(KP_ERR_INVALID, "ctx is NULL");
+  if (!lambda_inout) return fail(KP_ERR_INVALID, "lambda is NULL");
+  if (!std::isfinite(alpha) || alpha < 0) return fail(KP_ERR_INVALID, "alpha must be finite and >= 0");
+  Ctx *c = (Ctx *)ctx;
+  Prepared P;
+  kp_status s = prepare(prob, false, P);
+  if (s != KP_OK) return s;
+  SweepWs w;
+  if ((s = carve_ws(c, P, false, w)) != KP_OK) return s;
+  HIP_TRY(hipMemcpyAsync(w.B, P.B.data(), (size_t)P.pr.K * 8, hipMemcpyHostToDevice, c->stream));
+  double *Rd = R ? R : w.Rtmp;
+  if ((s = eval_into(c, P, w, lambda_inout, Rd, g ? g : w.gtmp, primal ? primal : w.Ptmp, nullptr)) != KP_OK)
+    return s;
+  HIP_TRY(kp_launch_dd_update(P.pr.K, alpha, Rd, w.B, lambda_inout, c->stream));
+  return KP_OK;
+}
+
+kp_status kp_dual_backward(void *ctx, const kp_problem *prob, const double *R,
+                           const double *grad_out, double *grad_lambda) {
+  if (!ctx) return fail(KP_ERR_INVALID, "ctx is NULL");
+  if (!prob || !prob->B || prob->K < 1) return fail(KP_ERR_INVALID, "problem/B invalid");
+  if (!R || !grad_out || !grad_lambda) return fail(KP_ERR_INVALID, "NULL argument");
+  Ctx *c = (Ctx *)ctx;
+  const int K = prob->K;
+  for (int k = 0; k < K; ++k)
+    if (!(std::isfinite(prob->B[k]) && prob->B[k] > 0.0))
+      return fail(KP_ERR_INVALID, "B[%d] must be finite and > 0", k);
+  Carve cv;
+  size_t oB = cv.take((size_t)K * 8);
+  kp_status s = ensure_ws(c, cv.off);
+  if (s != KP_OK) return s;
+  double *Bd = (double *)((char *)c->ws + oB);
+  HIP_TRY(hipMemcpyAsync(Bd, prob->B, (size_t)K * 8, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(kp_launch_dual_backward(K, R, Bd, grad_out, grad_lambda, c->stream));
+  return KP_OK;
+}
+
+kp_status kp_scd_sweep_masked(void *ctx, const kp_problem *prob, const double *lambda_in,
+                              double *lambda_out, const uint8_t *kmask, double *R, double *g,
+                              double *primal) {
+  if (!ctx) return fail(KP_ERR_INVALID, "ctx is NULL");
+  if (!lambda_in || !lambda_out) return fail(KP_ERR_INVALID, "lambda is NULL");
+  Ctx *c = (Ctx *)ctx;
+  Prepared P;
+  kp_status s = prepare(prob, true, P);
+  if (s != KP_OK) return s;
+  SweepWs w;
+  if ((s = carve_ws(c, P, true, w)) != KP_OK) return s;
+  const int K = P.pr.K;
+  HIP_TRY(hipMemcpyAsync(w.B, P.B.data(), (size_t)K * 8, hipMemcpyHostToDevice, c->stream));
+  if (kmask) HIP_TRY(hipMemcpyAsync(w.kmask, kmask, (size_t)K, hipMemcpyHostToDevice, c->stream));
+  // window hint from the previous call with the same K (performance only)
+  if (!c->delta_dev || c->delta_K != K) {
+    if (c->delta_dev) HIP_TRY(hipFree(c->delta_dev));
+    HIP_TRY(hipMalloc(&c->delta_dev, (size_t)K * 8));
+    c->delta_K = K;
+    c->delta_valid = false;
+  }
+  HIP_TRY(kp_launch_scd_init(w.st, K, lambda_in, kmask ? w.kmask : nullptr,
+                             c->delta_valid ? c->delta_dev : nullptr, c->stream));
+  HIP_TRY(hipMemsetAsync(w.hist_sum, 0, (size_t)K * KP_NB * 8, c->stream));
+  HIP_TRY(hipMemsetAsync(w.hist_cnt, 0, (size_t)K * KP_NB * 4, c->stream));
+  HIP_TRY(hipMemsetAsync(w.err, 0, 8, c->stream));
+  double *Rd = R ? R : w.Rtmp;
+  double *gd = g ? g : w.gtmp;
+  double *Pd = primal ? primal : w.Ptmp;
+  int pass = 0;
+  for (;; ++pass) {
+    if (pass >= kMaxPasses) return fail(KP_ERR_INTERNAL, "SCD threshold search exceeded %d passes", kMaxPasses);
+    if (P.pr.N > 0) {
+      SweepArgs a = make_args(P, lambda_in, w, nullptr, pass == 0);
+      a.pass = pass;
+      HIP_TRY(kp_launch_sweep(a, P.U, P.grid, true, c->stream));
+    }
+    if (pass == 0) {
+      if (P.pr.N > 0) {
+        HIP_TRY(kp_launch_reduce_stats(w.partials, P.grid, K, lambda_in, w.B, Rd, gd, Pd, c->stream));
+      } else {
+        HIP_TRY(hipMemsetAsync(w.partials, 0, (size_t)(K + 2) * 8, c->stream));
+        HIP_TRY(kp_launch_reduce_stats(w.partials, 1, K, lambda_in, w.B, Rd, gd, Pd, c->stream));
+      }
+    }
+    HIP_TRY(kp_launch_scd_locate_select(w.st, K, w.B, w.hist_sum, w.hist_cnt, w.ev1, w.ev2,
+                                        w.emit_cap, w.pending, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->pinned, w.pending, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->pinned + 2, w.err, 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (*(unsigned long long *)(c->pinned + 2))
+      return fail(KP_ERR_INTERNAL, "breakpoint walk exceeded its event limit");
+    if (c->pinned[0] == 0) break;
+  }
+  HIP_TRY(kp_launch_scd_finish(w.st, K, lambda_in, lambda_out, c->delta_dev, c->stream));
+  c->delta_valid = true;
+  return KP_OK;
+}
+
+kp_status kp_scd_sweep(void *ctx, const kp_problem *prob, const double *lambda_in,
+                       double *lambda_out, double *R, double *g, double *primal) {
+  return kp_scd_sweep_masked(ctx, prob, lambda_in, lambda_out, nullptr, R, g, primal);
+}
+
+kp_status kp_validate_inputs(void *ctx, const kp_problem *prob) {
+  if (!ctx) return fail(KP_ERR_INVALID, "ctx is NULL");
+  Ctx *c = (Ctx *)ctx;
+  Prepared P;
+  kp_status s = prepare(prob, false, P);
+  if (s != KP_OK) return s;
+  Carve cv;
+  size_t of = cv.take(16);
+  if ((s = ensure_ws(c, cv.off)) != KP_OK) return s;
+  unsigned int *flags = (unsigned int *)((char *)c->ws + of);
+  HIP_TRY(hipMemsetAsync(flags, 0, 16, c->stream));
+  const int64_t nrows = prob->N * prob->M;
+  HIP_TRY(kp_launch_validate(prob->p, nrows, flags, c->stream));
+  if (prob->b_format == KP_B_DENSE) {
+    HIP_TRY(kp_launch_validate(prob->b, nrows * prob->K, flags, c->stream));
+  } else {
+    int64_t nnz = 0;
+    if (nrows > 0)
+      HIP_TRY(hipMemcpyAsync(&nnz, prob->b_rowptr + nrows, 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(kp_launch_validate(prob->b_val, nnz, flags, c->stream));
+    HIP_TRY(kp_launch_validate_csr(prob->b_rowptr, prob->b_col, nrows, prob->K, flags, c->stream));
+  }
+  HIP_TRY(hipMemcpyAsync(c->pinned, flags, 12, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  const unsigned int *f = (const unsigned int *)c->pinned;
+  if (f[2]) return fail(KP_ERR_INVALID, "CSR rows must have ascending columns in [0,K)");
+  if (f[0]) return fail(KP_ERR_NONFINITE, "p or b holds a NaN or Inf");
+  if (f[1]) return fail(KP_ERR_NEGATIVE, "p or b holds a negative value");
+  return KP_OK;
+}
+
+kp_status kp_tree_from_sets(int32_t M, int32_t L, const int32_t *set_offsets,
+                            const int32_t *set_items, const int32_t *caps, int32_t *L_out,
+                            int32_t *parent_out, int32_t *cap_out, int32_t *leaf_of_item_out) {
+  if (M < 1 || M > KP_MAX_M) return fail(KP_ERR_UNSUPPORTED, "M must be in 1..%d", KP_MAX_M);
+  if (L < 0) return fail(KP_ERR_INVALID, "L must be >= 0");
+  if (L > 0 && (!set_offsets || !set_items || !caps))
+    return fail(KP_ERR_INVALID, "NULL set arrays");
+  if (!L_out || !leaf_of_item_out || (L > 0 && (!parent_out || !cap_out)))
+    return fail(KP_ERR_INVALID, "NULL outputs");
+  std::vector<uint64_t> mask;
+  std::vector<int> cap;
+  for (int l = 0; l < L; ++l) {
+    if (caps[l] < 1) return fail(KP_ERR_INVALID, "caps[%d] must be >= 1", l);
+    uint64_t m = 0;
+    for (int e = set_offsets[l]; e < set_offsets[l + 1]; ++e) {
+      const int j = set_items[e];
+      if (j < 0 || j >= M) return fail(KP_ERR_INVALID, "set %d holds item %d outside [0,M)", l, j);
+      m |= 1ull << j;
+    }
+    if (!m) continue;  // an empty set constrains nothing
+    bool merged = false;
+    for (size_t t = 0; t < mask.size(); ++t)
+      if (mask[t] == m) { cap[t] = std::min(cap[t], caps[l]); merged = true; break; }
+    if (!merged) { mask.push_back(m); cap.push_back(caps[l]); }
+  }
+  const int n = (int)mask.size();
+  for (int a = 0; a < n; ++a)
+    for (int b = a + 1; b < n; ++b) {
+      const uint64_t x = mask[a] & mask[b];
+      if (x && x != mask[a] && x != mask[b])
+        return fail(KP_ERR_NOT_LAMINAR, "sets %d and %d overlap without nesting", a, b);
+    }
+  // parent = smallest strict superset
+  for (int a = 0; a < n; ++a) {
+    int best = -1;
+    for (int b = 0; b < n; ++b) {
+      if (b == a) continue;
+      if ((mask[a] & mask[b]) == mask[a] && mask[b] != mask[a]) {
+        if (best < 0 || __builtin_popcountll(mask[b]) < __builtin_popcountll(mask[best])) best = b;
+      }
+    }
+    parent_out[a] = best;
+    cap_out[a] = cap[a];
+  }
+  for (int j = 0; j < M; ++j) {
+    int best = -1;
+    for (int a = 0; a < n; ++a)
+      if ((mask[a] >> j & 1) && (best < 0 || __builtin_popcountll(mask[a]) < __builtin_popcountll(mask[best])))
+        best = a;
+    leaf_of_item_out[j] = best;
+  }
+  *L_out = n;
+  return KP_OK;
+}
+
+kp_status kp_primal_fixup(void *ctx, const kp_problem *prob, const double *lambda, uint8_t *x_out,
+                          double *primal_out, double *R_out, int64_t *n_reset_out) {
+  (void)ctx; (void)prob; (void)lambda; (void)x_out; (void)primal_out; (void)R_out; (void)n_reset_out;
+  return fail(KP_ERR_UNSUPPORTED, "kp_primal_fixup is not built yet");
+}
+
+kp_status kp_scd_sweep_batched(void *ctx, const kp_problem *probs, int32_t n,
+                               const double *const *lambda_in, double *const *lambda_out,
+                               double *stats) {
+  (void)ctx; (void)probs; (void)n; (void)lambda_in; (void)lambda_out; (void)stats;
+  return fail(KP_ERR_UNSUPPORTED, "kp_scd_sweep_batched is not built yet");
+}
+
+}  // extern "C"

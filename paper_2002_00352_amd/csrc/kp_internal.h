@@ -1,0 +1,77 @@
+// Shared host/device definitions of the gfx950 sweep library.
+#pragma once
+#include <stdint.h>
+
+#define KP_MAX_M 64
+#define KP_MAX_NODES 128
+#define KP_NB 64               // histogram bins per knapsack per pass
+#define KP_MAX_K_SCD 64        // per-block LDS histograms bound K for the SCD calls
+#define KP_CENTRAL_W 2         // exponential buckets |id| <= W are emitted in the first pass
+#define KP_SORT_MAX 4096       // candidates sorted in LDS by the selection kernel
+
+// Laminar local constraints after pruning: only sets that can bind
+// (C_l < |S_l|), duplicates merged with the smaller cap, ordered subsets
+// first (size ascending, then first item).
+struct TreeDev {
+  int L;
+  int pad;
+  uint64_t mask[KP_MAX_NODES];
+  int cap[KP_MAX_NODES];
+};
+
+struct ProbDev {
+  int64_t N;
+  int M, K, fmt, pad;
+  const float *p;
+  const float *b;
+  const int64_t *rowptr;
+  const int32_t *col;
+  const float *val;
+};
+
+// Per-knapsack state of the threshold search of one SCD iteration.
+enum {
+  KS_DONE = 0,
+  KS_EXP = 1,          // first pass: exponential-bucket histogram + central emission
+  KS_EMIT_BUCKET = 2,  // emit the events of exponential bucket bstar (+ their key hull)
+  KS_HULL_BUCKET = 3,  // only the key hull of bucket bstar (too many events to emit)
+  KS_REFINE = 4,       // linear key bins over [klo, khi]
+  KS_EMIT_RANGE = 5,   // emit the events with key in [klo, khi]
+  KS_SELECT_BUCKET = 6,// emitted events of bucket bstar are complete: select
+  KS_SELECT_RANGE = 7  // emitted events of [klo, khi] are complete: select
+};
+
+struct KState {
+  int mode;
+  int bstar;           // exponential bucket id (-31..31) for the bucket modes
+  int shift;           // key-bin shift for KS_REFINE
+  int overflow;        // emission exceeded the buffer
+  uint32_t n_emit;     // emitted events (atomic)
+  uint32_t pad;
+  double center;       // lambda_k^t
+  double delta;        // central bucket half-width (a power of two)
+  double F_above;      // sum of increments strictly above the current target
+  double result;       // lambda_k^{t+1} once mode == KS_DONE
+  uint64_t klo, khi;   // inclusive key range
+  uint64_t hull_lo, hull_hi;  // atomics: key hull of the bucket's events
+};
+
+struct SweepArgs {
+  ProbDev pr;
+  TreeDev tree;
+  const double *lam;       // [K]
+  int64_t ntiles;
+  // statistics (first pass only)
+  int want_stats;
+  double *partials;        // [gridDim.x][K + 2]
+  uint8_t *x_out;          // [N*M] or null
+  // SCD
+  KState *st;              // [K]
+  double *hist_sum;        // [K][KP_NB]
+  uint32_t *hist_cnt;      // [K][KP_NB]
+  double *emit_v1;         // [K][emit_cap]
+  double *emit_v2;
+  uint32_t emit_cap;
+  int pass;
+  unsigned long long *err; // walk-limit counter
+};

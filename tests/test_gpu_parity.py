@@ -1,0 +1,169 @@
+"""GPU path (through the C ABI) against the CPU oracle on the same seeded
+inputs.  Bars: decisions x bit-exact; R bit-exact (values on the 2^-24 grid
+sum exactly in FP64); g and P within 1e-9 relative; DD and SCD multipliers
+bit-exact."""
+import numpy as np
+import pytest
+
+import kpgen
+import oracle
+from util import random_instance, random_laminar
+
+gpu = pytest.mark.gpu
+REL = 1e-9
+
+
+def _kp():
+    import torch
+    import paper_2002_00352_amd as kp
+    assert torch.cuda.is_available()
+    return kp, torch
+
+
+def _lamd(torch, lam):
+    return torch.tensor(np.asarray(lam, np.float64), device="cuda")
+
+
+def _cases():
+    rng = np.random.default_rng(1234)
+    out = [
+        ("c1-N10000", kpgen.config_instance(1)),
+        ("c3-hier-csr-N3001", kpgen.config_instance(3, N=3001)),
+        ("c2-lognormal-N2049", kpgen.config_instance(2, N=2049)),
+        ("c4-M20K50-N700", kpgen.config_instance(4, N=700)),
+        ("dense-ties-grid4", random_instance(rng, 500, 7, 3, Q=2, grid=4, zero_frac=0.3)),
+        ("laminar-random-M12", random_instance(rng, 777, 12, 4, tree=random_laminar(12, rng))),
+        ("csr-random-M9", random_instance(rng, 613, 9, 5, tree=random_laminar(9, rng), zero_frac=0.7).to_csr()),
+        ("N1", random_instance(rng, 1, 5, 2, Q=2)),
+        ("M1-K1", random_instance(rng, 300, 1, 1, Q=1)),
+        ("M40-K3", random_instance(rng, 200, 40, 3, Q=7)),
+    ]
+    return out
+
+
+CASES = _cases()
+
+
+@gpu
+@pytest.mark.parametrize("name,inst", CASES, ids=[c[0] for c in CASES])
+def test_eval_parity(name, inst):
+    kp, torch = _kp()
+    print("case", name, flush=True)
+    prob = kp.Problem.from_host(inst)
+    rng = np.random.default_rng(5)
+    for lam in (np.zeros(inst.K), rng.random(inst.K) * 0.3, rng.random(inst.K) * 2.0):
+        ev = kp.kp_eval_dual(prob, _lamd(torch, lam), want_x=True)
+        ref = oracle.eval_dual(inst, lam)
+        assert np.array_equal(ev["x"].cpu().numpy(), ref["x"])
+        assert np.array_equal(ev["R"].cpu().numpy(), ref["R"])
+        for key in ("g", "P"):
+            a, b = ev[key].item(), ref[key]
+            assert abs(a - b) <= REL * max(1.0, abs(b)), (key, a, b)
+
+
+@gpu
+@pytest.mark.parametrize("name,inst", CASES[:4], ids=[c[0] for c in CASES[:4]])
+def test_dd_step_parity(name, inst):
+    kp, torch = _kp()
+    print("case", name, flush=True)
+    prob = kp.Problem.from_host(inst)
+    lam = np.full(inst.K, 0.05)
+    lam_d = _lamd(torch, lam)
+    for t in range(5):
+        st = kp.kp_dd_step(prob, 1e-4, lam_d)
+        ref = oracle.eval_dual(inst, lam, want_x=False)
+        lam = oracle.dd_update(lam, 1e-4, ref["R"], inst.B)
+        assert np.array_equal(lam_d.cpu().numpy(), lam), t
+
+
+@gpu
+@pytest.mark.parametrize("name,inst", CASES, ids=[c[0] for c in CASES])
+def test_scd_sweep_parity(name, inst):
+    """Three SCD iterations along the oracle's own trajectory: the GPU's
+    lambda^{t+1} must equal the oracle's bit for bit at each step."""
+    kp, torch = _kp()
+    print("case", name, flush=True)
+    prob = kp.Problem.from_host(inst)
+    lam = np.zeros(inst.K)
+    for t in range(3):
+        sw = kp.kp_scd_sweep(prob, _lamd(torch, lam))
+        want = oracle.scd_sweep(inst, lam)
+        got = sw["lam"].cpu().numpy()
+        assert np.array_equal(got, want), (t, got, want)
+        ref = oracle.eval_dual(inst, lam, want_x=False)
+        assert np.array_equal(sw["R"].cpu().numpy(), ref["R"])
+        lam = want
+
+
+@gpu
+def test_scd_sweep_parity_from_random_points():
+    kp, torch = _kp()
+    inst = kpgen.config_instance(1, N=5000)
+    prob = kp.Problem.from_host(inst)
+    rng = np.random.default_rng(9)
+    for _ in range(6):
+        lam = rng.random(inst.K) * 3
+        got = kp.kp_scd_sweep(prob, _lamd(torch, lam))["lam"].cpu().numpy()
+        assert np.array_equal(got, oracle.scd_sweep(inst, lam))
+
+
+@gpu
+def test_scd_masked_cyclic_parity():
+    kp, torch = _kp()
+    inst = kpgen.config_instance(3, N=2000)
+    prob = kp.Problem.from_host(inst)
+    lam = np.full(inst.K, 0.5)
+    for k in (0, 7, 19):
+        mask = np.zeros(inst.K, np.uint8)
+        mask[k] = 1
+        got = kp.kp_scd_sweep(prob, _lamd(torch, lam), kmask=mask)["lam"].cpu().numpy()
+        want = oracle.scd_sweep(inst, lam, ks=[k])
+        assert np.array_equal(got, want)
+
+
+@gpu
+def test_dual_autograd_matches_oracle_gradient():
+    kp, torch = _kp()
+    inst = kpgen.config_instance(4, N=3000)
+    prob = kp.Problem.from_host(inst)
+    rng = np.random.default_rng(3)
+    for _ in range(3):
+        lam = rng.random(inst.K) / inst.K
+        lam_t = torch.tensor(lam, device="cuda", requires_grad=True)
+        g = kp.DualFn.apply(lam_t, prob)
+        g.backward()
+        ref = oracle.eval_dual(inst, lam, want_x=False)
+        assert abs(g.item() - ref["g"]) <= REL * abs(ref["g"])
+        assert np.array_equal(lam_t.grad.cpu().numpy(), inst.B - ref["R"])
+
+
+@gpu
+def test_empty_instance():
+    kp, torch = _kp()
+    rng = np.random.default_rng(0)
+    inst = random_instance(rng, 4, 3, 2, Q=1)
+    prob = kp.Problem.from_host(inst)
+    prob.s.N = 0
+    lam = np.array([0.5, 0.25])
+    ev = kp.kp_eval_dual(prob, _lamd(torch, lam))
+    assert ev["R"].cpu().numpy().tolist() == [0.0, 0.0]
+    assert ev["g"].item() == 0.5 * inst.B[0] + 0.25 * inst.B[1]
+    sw = kp.kp_scd_sweep(prob, _lamd(torch, lam))
+    assert sw["lam"].cpu().numpy().tolist() == [0.0, 0.0]
+
+
+@gpu
+def test_validate_inputs_flags_bad_values():
+    kp, torch = _kp()
+    rng = np.random.default_rng(0)
+    inst = random_instance(rng, 50, 4, 3, Q=2)
+    prob = kp.Problem.from_host(inst)
+    kp.kp_validate_inputs(prob)
+    prob.b[17] = float("nan")
+    with pytest.raises(kp.KPError) as e:
+        kp.kp_validate_inputs(prob)
+    assert e.value.status == -3
+    prob.b[17] = -1.0
+    with pytest.raises(kp.KPError) as e:
+        kp.kp_validate_inputs(prob)
+    assert e.value.status == -4
