@@ -1,0 +1,158 @@
+#!/usr/bin/env python3
+"""Benchmark of the per-user subproblem sweep on one MI355X.
+
+A step is one synchronous coordinate-descent (SCD) iteration over the whole
+instance: scoring, the local greedy, the consumption / dual reductions, every
+user's breakpoint walk for every knapsack, the global threshold search and
+the multiplier update, starting from lambda = 0 and feeding each step's
+lambda to the next.  Inputs are generated on the GPU and resident in HBM
+before the timed region.  Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOADS = {"c1": 1, "c2": 2, "c3": 3, "c4": 4}
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_2002_00352_amd/csrc/kp_kernels.hip", "paper_2002_00352_amd/csrc/kp_internal.h"]
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(workload, bytes_per_launch):
+    """HBM traffic per launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"sweep_traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except Exception:
+        return None
+    if rec.get("kernel_hash") != kernel_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(cfg_id, seconds):
+    """The oracle's SCD sweep timed on a bounded prefix of the same workload
+    (host-generated users, lambda = 0), on all host threads."""
+    import numpy as np
+    import kpgen
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    n = 2000
+    inst = kpgen.config_instance(cfg_id, N=n)
+    t0 = time.perf_counter()
+    oracle.scd_sweep(inst, np.zeros(inst.K))
+    dt = time.perf_counter() - t0
+    # scale the sample to about `seconds` of work
+    n = int(max(2000, min(2_000_000, n * seconds / max(dt, 1e-3))))
+    inst = kpgen.config_instance(cfg_id, N=n)
+    t0 = time.perf_counter()
+    oracle.scd_sweep(inst, np.zeros(inst.K))
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "user-solves/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n} users of the same workload, one SCD sweep from lambda=0 "
+                      f"({dt:.1f} s on {threads} threads)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
+    ap.add_argument("--users", type=int, default=None, help="override N (testing only)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sweep shards by users; see the design notes). Run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2002_00352_amd as kp
+    import kpgen
+    from kpgen import device as kgd
+
+    torch.cuda.set_device(0)
+    cfg_id = WORKLOADS[args.workload]
+    t_gen = time.perf_counter()
+    arrs, B, tree, meta = kgd.device_instance(cfg_id, 0, N=args.users)
+    prob = kp.Problem(arrs["p"], B, tree.parent, tree.cap, tree.leaf_of_item, b=arrs.get("b"),
+                      rowptr=arrs.get("rowptr"), col=arrs.get("col"), val=arrs.get("val"),
+                      N=meta["N"], M=meta["M"], K=meta["K"])
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t_gen
+    ctx = kp.default_context()
+    K = meta["K"]
+    lam = torch.zeros(K, dtype=torch.float64, device="cuda")
+    out = torch.zeros(K, dtype=torch.float64, device="cuda")
+    for _ in range(args.warmup):
+        kp.kp_scd_sweep(prob, lam, out, ctx=ctx)
+        lam, out = out, lam
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        kp.kp_scd_sweep(prob, lam, out, ctx=ctx)
+        lam, out = out, lam
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_k, launches, bytes_k = ctx.timing()
+    ctx.set_timing(False)
+    dt = t1 - t0
+    N = meta["N"]
+    value = N * args.steps / dt
+    per_launch_bytes = bytes_k / max(launches, 1)
+    avg_ms = ms_k / max(launches, 1)
+    achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
+    traffic = traffic_for(args.workload, per_launch_bytes)
+    rec = {
+        "metric": "user-subproblem solves/s per SCD sweep",
+        "value": value,
+        "unit": "user-solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded counter-based generator, generated on the GPU)",
+        "config": {"workload": meta["name"], "N": N, "M": meta["M"], "K": meta["K"],
+                   "b_format": "csr" if meta["csr_d"] else "dense", "seed": meta["seed"],
+                   "lambda0": 0.0},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_sweep (scd)", "launches": launches,
+                     "avg_launch_ms": avg_ms, "algo_bytes_per_launch": per_launch_bytes},
+        "passes_per_step": launches / args.steps,
+        "pct_hbm_peak": 100.0 * achieved / HBM_PEAK_GBS,
+        "lambda_final_head": [float(v) for v in lam[:4].cpu().numpy()],
+        "gen_s": t_gen,
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(cfg_id, args.cpu_seconds)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

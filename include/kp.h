@@ -164,6 +164,18 @@ kp_status kp_tree_from_sets(int32_t M, int32_t L, const int32_t *set_offsets,
                             int32_t *parent_out, int32_t *cap_out,
                             int32_t *leaf_of_item_out);
 
+/* Optional timing of the sweep kernel: when on, every launch of the sweep
+   kernel made through this context is bracketed by HIP events on the
+   context's stream.  kp_get_timing waits for them and returns the summed
+   kernel time (ms), the launch count and the algorithmic input bytes of those
+   launches (p and b once per launch in the layout above: dense
+   4*N*M*(1+K) bytes; CSR 4*N*M + 8*(N*M+1) + 8*nnz bytes, with nnz read
+   once from rowptr[N*M]).
+   kp_set_timing resets the totals. */
+kp_status kp_set_timing(void *ctx, int32_t on);
+kp_status kp_get_timing(void *ctx, double *sweep_ms_total, int64_t *sweep_launches,
+                        double *sweep_bytes_total);
+
 /* Size limits of this build. */
 int32_t kp_max_items(void);        /* 64 */
 int32_t kp_max_knapsacks_scd(void);/* largest K accepted by the SCD calls */

@@ -59,7 +59,7 @@ _lib = None
 EXPORTS = ["kp_last_error", "kp_create", "kp_destroy", "kp_set_stream", "kp_eval_dual",
            "kp_scd_sweep", "kp_scd_sweep_masked", "kp_dd_step", "kp_dual_backward",
            "kp_primal_fixup", "kp_scd_sweep_batched", "kp_validate_inputs", "kp_tree_from_sets",
-           "kp_max_items", "kp_max_knapsacks_scd"]
+           "kp_max_items", "kp_max_knapsacks_scd", "kp_set_timing", "kp_get_timing"]
 
 
 def lib():
@@ -84,6 +84,8 @@ def lib():
         L.kp_scd_sweep_batched.argtypes = [vp, P, i32, vp, vp, vp]
         L.kp_validate_inputs.argtypes = [vp, P]
         L.kp_tree_from_sets.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp]
+        L.kp_set_timing.argtypes = [vp, i32]
+        L.kp_get_timing.argtypes = [vp, vp, vp, vp]
         L.kp_max_items.restype = i32
         L.kp_max_knapsacks_scd.restype = i32
         for name in EXPORTS:
@@ -120,6 +122,15 @@ class Context:
 
     def sync_stream(self):
         _check(lib().kp_set_stream(self.h, _stream_handle()))
+
+    def set_timing(self, on: bool):
+        _check(lib().kp_set_timing(self.h, 1 if on else 0))
+
+    def timing(self):
+        """(sweep kernel ms total, launches, algorithmic bytes total)."""
+        ms, n, by = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        _check(lib().kp_get_timing(self.h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by)))
+        return ms.value, n.value, by.value
 
     def close(self):
         if self.h:

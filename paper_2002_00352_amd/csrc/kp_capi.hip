@@ -15,7 +15,7 @@
 #include "kp_internal.h"
 
 // launchers (kp_kernels.hip)
-size_t kp_sweep_lds_bytes(int U, int M, int K, bool scd);
+size_t kp_sweep_lds_bytes(int U, int M, int K, bool scd, int fmt);
 hipError_t kp_launch_sweep(const SweepArgs &a, int U, int grid, bool scd, hipStream_t stream);
 hipError_t kp_launch_reduce_stats(const double *partials, int nblk, int K, const double *lam,
                                   const double *B, double *R, double *g, double *P,
@@ -57,9 +57,11 @@ kp_status fail(kp_status st, const char *fmt, ...) {
   } while (0)
 
 constexpr int kTileBudget = 24 * 1024;   // bytes of staged costs per tile
+constexpr size_t kMaxLds = 160 * 1024;   // LDS per workgroup on gfx950
 constexpr int kMaxGrid = 2048;
 constexpr uint32_t kEmitCapDefault = 1u << 20;
 constexpr int kMaxPasses = 96;
+constexpr uint32_t kStageCap = 4096;    // staged events per block per pass
 
 struct Ctx {
   hipStream_t stream = nullptr;
@@ -71,7 +73,44 @@ struct Ctx {
   double *delta_dev = nullptr;
   int delta_K = 0;
   bool delta_valid = false;
+  // optional timing of the sweep kernel launches (HIP events on the stream)
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
+  std::vector<hipEvent_t> ev_free;
+  double sweep_ms = 0.0;
+  int64_t sweep_launches = 0;
+  double sweep_bytes = 0.0;
+  const int64_t *nnz_rowptr = nullptr;
+  int64_t nnz_rows = -1, nnz = 0;
 };
+
+hipEvent_t take_event(Ctx *c) {
+  if (!c->ev_free.empty()) {
+    hipEvent_t e = c->ev_free.back();
+    c->ev_free.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Resolve finished event pairs into the running totals.
+void drain_events(Ctx *c, bool wait) {
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> keep;
+  for (auto &pr : c->ev_pending) {
+    if (wait) (void)hipEventSynchronize(pr.second);
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
+      c->sweep_ms += ms;
+      c->ev_free.push_back(pr.first);
+      c->ev_free.push_back(pr.second);
+    } else {
+      keep.push_back(pr);
+    }
+  }
+  c->ev_pending.swap(keep);
+}
 
 // Workspace carve: every block 256-byte aligned.
 struct Carve {
@@ -118,6 +157,7 @@ struct Prepared {
   int U = 1;
   int64_t ntiles = 0;
   int grid = 1;
+  double bytes = 0.0;   // algorithmic input bytes of one sweep launch
 };
 
 kp_status prepare(const kp_problem *p, bool scd, Prepared &out) {
@@ -199,18 +239,31 @@ kp_status prepare(const kp_problem *p, bool scd, Prepared &out) {
   // tile: as many users as fit the staged-cost budget, at most 64
   const size_t per_user = (size_t)M * p->K * 4;
   int U = (int)std::max<size_t>(1, std::min<size_t>(64, kTileBudget / per_user));
+  U = std::min(U, std::max(1, 1024 / M));   // rows per tile <= the prefetched rows
   if (U >= 4) U &= ~3;   // keeps 16-byte alignment of dense tiles when M*K is odd
-  while (U > 1 && kp_sweep_lds_bytes(U, M, p->K, scd) > 64 * 1024) --U;
-  if (kp_sweep_lds_bytes(U, M, p->K, scd) > 64 * 1024)
+  while (U > 1 && kp_sweep_lds_bytes(U, M, p->K, scd, p->b_format) > 64 * 1024) --U;
+  if (kp_sweep_lds_bytes(U, M, p->K, scd, p->b_format) > kMaxLds)
     return fail(KP_ERR_UNSUPPORTED, "M*K = %d too large for one tile", M * p->K);
   out.U = U;
   out.ntiles = (p->N + U - 1) / U;
+  {
+    const double Nd = (double)p->N;
+    if (p->b_format == KP_B_DENSE) {
+      out.bytes = Nd * M * 4.0 + Nd * M * (double)p->K * 4.0;
+    } else {
+      // p and rowptr here; the stored entries (col + val) are added by the
+      // timed launch, which reads the entry count from rowptr[N*M]
+      out.bytes = Nd * M * 4.0 + (Nd * M + 1) * 8.0;
+    }
+  }
   out.grid = (int)std::max<int64_t>(1, std::min<int64_t>(out.ntiles, kMaxGrid));
   return KP_OK;
 }
 
 struct SweepWs {
-  double *partials, *B, *hist_sum, *ev1, *ev2, *Rtmp, *gtmp, *Ptmp;
+  double *partials, *B, *hist_sum, *ev1, *ev2, *Rtmp, *gtmp, *Ptmp, *sv1, *sv2;
+  uint16_t *sk;
+  uint32_t stage_cap;
   uint32_t *hist_cnt;
   KState *st;
   uint8_t *kmask;
@@ -240,6 +293,13 @@ kp_status carve_ws(Ctx *c, const Prepared &P, bool scd, SweepWs &w) {
     o_e1 = cv.take((size_t)K * cap * 8);
     o_e2 = cv.take((size_t)K * cap * 8);
   }
+  size_t o_s1 = 0, o_s2 = 0, o_sk = 0;
+  const uint32_t scap = scd ? kStageCap : 0;
+  if (scd) {
+    o_s1 = cv.take((size_t)P.grid * scap * 8);
+    o_s2 = cv.take((size_t)P.grid * scap * 8);
+    o_sk = cv.take((size_t)P.grid * scap * 2);
+  }
   kp_status s = ensure_ws(c, cv.off);
   if (s != KP_OK) return s;
   char *b = (char *)c->ws;
@@ -257,7 +317,50 @@ kp_status carve_ws(Ctx *c, const Prepared &P, bool scd, SweepWs &w) {
   w.ev1 = scd ? (double *)(b + o_e1) : nullptr;
   w.ev2 = scd ? (double *)(b + o_e2) : nullptr;
   w.emit_cap = cap;
+  w.sv1 = scd ? (double *)(b + o_s1) : nullptr;
+  w.sv2 = scd ? (double *)(b + o_s2) : nullptr;
+  w.sk = scd ? (uint16_t *)(b + o_sk) : nullptr;
+  w.stage_cap = scap;
   return KP_OK;
+}
+
+// Algorithmic bytes of one sweep launch: every input byte of p and b once.
+double algo_bytes(const Prepared &P) {
+  const double N = (double)P.pr.N, M = P.pr.M, K = P.pr.K;
+  if (P.pr.fmt == KP_B_DENSE) return N * M * 4.0 + N * M * K * 4.0;
+  return -1.0;  // CSR: filled in by the caller from rowptr[N*M]
+}
+
+hipError_t timed_sweep(Ctx *c, const SweepArgs &a, const Prepared &P, bool scd, double bytes) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (c->timing && P.pr.fmt == KP_B_CSR && P.pr.N > 0) {
+    // stored entries (col + val, 8 bytes each) -- read once per rowptr array
+    const int64_t nrows = P.pr.N * P.pr.M;
+    if (c->nnz_rowptr != P.pr.rowptr || c->nnz_rows != nrows) {
+      int64_t nnz = 0;
+      hipError_t e = hipMemcpyAsync(&nnz, P.pr.rowptr + nrows, 8, hipMemcpyDeviceToHost, c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+      if (e != hipSuccess) return e;
+      c->nnz_rowptr = P.pr.rowptr;
+      c->nnz_rows = nrows;
+      c->nnz = nnz;
+    }
+    bytes += (double)c->nnz * 8.0;
+  }
+  if (c->timing) {
+    e0 = take_event(c);
+    e1 = take_event(c);
+    if (e0 && e1) (void)hipEventRecord(e0, c->stream);
+  }
+  hipError_t err = kp_launch_sweep(a, P.U, P.grid, scd, c->stream);
+  if (c->timing && e0 && e1) {
+    (void)hipEventRecord(e1, c->stream);
+    c->ev_pending.push_back({e0, e1});
+    c->sweep_launches += 1;
+    c->sweep_bytes += bytes;
+    if (c->ev_pending.size() > 256) drain_events(c, true);
+  }
+  return err;
 }
 
 SweepArgs make_args(const Prepared &P, const double *lam, const SweepWs &w, uint8_t *x,
@@ -277,6 +380,10 @@ SweepArgs make_args(const Prepared &P, const double *lam, const SweepWs &w, uint
   a.emit_v1 = w.ev1;
   a.emit_v2 = w.ev2;
   a.emit_cap = w.emit_cap;
+  a.stage_v1 = w.sv1;
+  a.stage_v2 = w.sv2;
+  a.stage_k = w.sk;
+  a.stage_cap = w.stage_cap;
   a.err = w.err;
   return a;
 }
@@ -290,7 +397,7 @@ kp_status eval_into(Ctx *c, const Prepared &P, const SweepWs &w, const double *l
     return KP_OK;
   }
   SweepArgs a = make_args(P, lam, w, x, true);
-  HIP_TRY(kp_launch_sweep(a, P.U, P.grid, false, c->stream));
+  HIP_TRY(timed_sweep(c, a, P, false, P.bytes));
   HIP_TRY(kp_launch_reduce_stats(w.partials, P.grid, P.pr.K, lam, w.B, R, g, primal, c->stream));
   return KP_OK;
 }
@@ -318,6 +425,8 @@ kp_status kp_destroy(void *ctx) {
   if (!ctx) return KP_OK;
   Ctx *c = (Ctx *)ctx;
   if (c->ws || c->delta_dev || c->pinned) (void)hipStreamSynchronize(c->stream);
+  drain_events(c, true);
+  for (hipEvent_t e : c->ev_free) (void)hipEventDestroy(e);
   if (c->ws) (void)hipFree(c->ws);
   if (c->delta_dev) (void)hipFree(c->delta_dev);
   if (c->pinned) (void)hipHostFree(c->pinned);
@@ -419,7 +528,7 @@ kp_status kp_scd_sweep_masked(void *ctx, const kp_problem *prob, const double *l
     if (P.pr.N > 0) {
       SweepArgs a = make_args(P, lambda_in, w, nullptr, pass == 0);
       a.pass = pass;
-      HIP_TRY(kp_launch_sweep(a, P.U, P.grid, true, c->stream));
+      HIP_TRY(timed_sweep(c, a, P, true, P.bytes));
     }
     if (pass == 0) {
       if (P.pr.N > 0) {
@@ -532,6 +641,28 @@ kp_status kp_tree_from_sets(int32_t M, int32_t L, const int32_t *set_offsets,
     leaf_of_item_out[j] = best;
   }
   *L_out = n;
+  return KP_OK;
+}
+
+kp_status kp_set_timing(void *ctx, int32_t on) {
+  if (!ctx) return fail(KP_ERR_INVALID, "ctx is NULL");
+  Ctx *c = (Ctx *)ctx;
+  drain_events(c, true);
+  c->timing = on != 0;
+  c->sweep_ms = 0.0;
+  c->sweep_launches = 0;
+  c->sweep_bytes = 0.0;
+  return KP_OK;
+}
+
+kp_status kp_get_timing(void *ctx, double *sweep_ms_total, int64_t *sweep_launches,
+                        double *sweep_bytes_total) {
+  if (!ctx) return fail(KP_ERR_INVALID, "ctx is NULL");
+  Ctx *c = (Ctx *)ctx;
+  drain_events(c, true);
+  if (sweep_ms_total) *sweep_ms_total = c->sweep_ms;
+  if (sweep_launches) *sweep_launches = c->sweep_launches;
+  if (sweep_bytes_total) *sweep_bytes_total = c->sweep_bytes;
   return KP_OK;
 }
 

@@ -72,6 +72,12 @@ struct SweepArgs {
   double *emit_v1;         // [K][emit_cap]
   double *emit_v2;
   uint32_t emit_cap;
+  // per-block staging regions of emitted events (one global reservation per
+  // (block, k) at the end of the kernel instead of one atomic per event)
+  double *stage_v1;        // [gridDim.x][stage_cap]
+  double *stage_v2;
+  uint16_t *stage_k;
+  uint32_t stage_cap;
   int pass;
   unsigned long long *err; // walk-limit counter
 };

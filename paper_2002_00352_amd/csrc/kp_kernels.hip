@@ -45,6 +45,7 @@ __device__ __forceinline__ int exp_bucket(double v, double center, double delta)
 struct TileGeom {
   int U;            // users per tile
   int M, K;
+  int aligned;      // dense costs: 16-byte aligned base and U*M*K % 4 == 0
 };
 
 // Laminar-matroid greedy over the ranked items: accept an eligible item when
@@ -70,6 +71,59 @@ __device__ __forceinline__ uint64_t greedy_mask(const uint8_t *perm, int M, uint
 // ---------------------------------------------------------------------------
 // the sweep kernel
 // ---------------------------------------------------------------------------
+typedef float v4f __attribute__((ext_vector_type(4)));
+#define CH 8      // prefetched 16-byte chunks of dense costs per thread and tile
+#define PCH 4     // prefetched profits (and CSR row offsets) per thread and tile
+#define ECH 8     // prefetched CSR entries per thread and tile
+
+// Register-resident copy of one tile's inputs, loaded one tile ahead so the
+// loads overlap the previous tile's compute.
+struct Prefetch {
+  v4f b4[CH];
+  float pv[PCH];
+  int64_t rp[PCH];      // CSR: rowptr of the rows this thread scores
+  int64_t rp_end;       // CSR: rowptr one past the tile (valid in thread 0)
+  int32_t ec[ECH];      // CSR entries of the tile, cooperative layout
+  float ev[ECH];
+};
+
+template <int FMT>
+__device__ __forceinline__ void issue_rows(Prefetch &f, const ProbDev &pr, int64_t u0, int nr, int K,
+                                           int tid, int aligned) {
+  // profits (all formats) and, for CSR, the row offsets
+  #pragma unroll
+  for (int i = 0; i < PCH; ++i) {
+    const int r = tid + i * NT;
+    if (r < nr) {
+      f.pv[i] = __builtin_nontemporal_load(pr.p + u0 * pr.M + r);
+      if (FMT == 1) f.rp[i] = pr.rowptr[u0 * pr.M + r];
+    }
+  }
+  if (FMT == 1 && tid == 0) f.rp_end = pr.rowptr[u0 * pr.M + nr];
+  if (FMT == 0 && aligned) {
+    const float *src = pr.b + u0 * (int64_t)pr.M * K;
+    const int n4 = (nr * K) >> 2;
+    const v4f *s4 = (const v4f *)src;
+    #pragma unroll
+    for (int i = 0; i < CH; ++i) {
+      const int t = tid + i * NT;
+      if (t < n4) f.b4[i] = __builtin_nontemporal_load(s4 + t);
+    }
+  }
+}
+
+__device__ __forceinline__ void issue_entries(Prefetch &f, const ProbDev &pr, int64_t e0, int64_t e1,
+                                              int tid) {
+  #pragma unroll
+  for (int i = 0; i < ECH; ++i) {
+    const int64_t e = e0 + tid + (int64_t)i * NT;
+    if (e < e1) {
+      f.ec[i] = __builtin_nontemporal_load(pr.col + e);
+      f.ev[i] = __builtin_nontemporal_load(pr.val + e);
+    }
+  }
+}
+
 template <int FMT, bool SCD>
 __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs a, const TileGeom g) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -88,46 +142,121 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs a, const TileGeom 
   double *vk = (double *)carve((size_t)Q * 8);            // per (user,k) consumption
   double *uPG = (double *)carve((size_t)U * 16);          // per user P_i, G_i
   double *acc = (double *)carve((size_t)(K + 2) * 8);     // block running sums
+  double *lam = (double *)carve((size_t)K * 8);           // lambda^t staged once per block
+  float *pl = (float *)carve((size_t)R * 4);              // staged profits
+  int32_t *rpl = (int32_t *)carve((size_t)(R + 1) * 4);   // CSR: row offsets relative to the tile
+  int32_t *ecl = (int32_t *)carve(FMT == 1 ? (size_t)NT * ECH * 4 : 0);  // CSR: staged entries
+  float *evl = (float *)carve(FMT == 1 ? (size_t)NT * ECH * 4 : 0);
+  int64_t *ebase = (int64_t *)carve(16);                  // CSR: first entry of the next tile
+  KState *kst = SCD ? (KState *)carve((size_t)K * sizeof(KState)) : nullptr;
   double *hs = nullptr;
   uint32_t *hc = nullptr;
   int *kmode = nullptr;
+  uint32_t *kcnt = nullptr, *kpos = nullptr, *kovf = nullptr, *nstage = nullptr;
+  unsigned long long *hmin = nullptr, *hmax = nullptr;
   if (SCD) {
     hs = (double *)carve((size_t)K * KP_NB * 8);
     hc = (uint32_t *)carve((size_t)K * KP_NB * 4);
     kmode = (int *)carve((size_t)K * 4);
+    kcnt = (uint32_t *)carve((size_t)K * 4);
+    kpos = (uint32_t *)carve((size_t)K * 4);
+    kovf = (uint32_t *)carve((size_t)K * 4);
+    hmin = (unsigned long long *)carve((size_t)K * 8);
+    hmax = (unsigned long long *)carve((size_t)K * 8);
+    nstage = (uint32_t *)carve(16);
   }
   for (int t = tid; t < K + 2; t += NT) acc[t] = 0.0;
+  for (int t = tid; t < K; t += NT) lam[t] = a.lam[t];
   if (SCD) {
+    for (int t = tid; t < K; t += NT) kst[t] = a.st[t];
     for (int t = tid; t < K * KP_NB; t += NT) { hs[t] = 0.0; hc[t] = 0u; }
-    for (int t = tid; t < K; t += NT) kmode[t] = a.st[t].mode;
+    for (int t = tid; t < K; t += NT) {
+      kmode[t] = a.st[t].mode;
+      kcnt[t] = 0u;
+      kpos[t] = 0u;
+      kovf[t] = 0u;
+      hmin[t] = ~0ull;
+      hmax[t] = 0ull;
+    }
+    if (tid == 0) *nstage = 0u;
   }
   const int64_t N = a.pr.N;
-  const double *lam = a.lam;
 
-  for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+  // ---- software pipeline: prefetch tile blockIdx.x ----
+  Prefetch f;
+  int64_t tile = blockIdx.x;
+  if (tile < a.ntiles) {
+    const int64_t u0 = tile * (int64_t)U;
+    const int nu = (int)((N - u0) < U ? (N - u0) : U);
+    issue_rows<FMT>(f, a.pr, u0, nu * M, K, tid, g.aligned);
+    if (FMT == 1) {
+      if (tid == 0) { ebase[0] = a.pr.rowptr[u0 * M]; ebase[1] = f.rp_end; }
+      __syncthreads();
+      issue_entries(f, a.pr, ebase[0], ebase[1], tid);
+    }
+  }
+
+  for (; tile < a.ntiles; tile += gridDim.x) {
     const int64_t u0 = tile * (int64_t)U;
     const int nu = (int)((N - u0) < U ? (N - u0) : U);     // users in this tile
     const int nr = nu * M;
     __syncthreads();   // previous tile's readers are done with the LDS tile
-    // ---- phase 0 + A: stage costs, score ----
+    // ---- store the prefetched tile into LDS ----
+    int64_t e_first = 0;
+    int n_ent = 0;
+    #pragma unroll
+    for (int i = 0; i < PCH; ++i) {
+      const int r = tid + i * NT;
+      if (r < nr) pl[r] = f.pv[i];
+    }
     if (FMT == 0) {
-      // dense: the tile's costs are one contiguous run of nr*K floats
       const float *src = a.pr.b + u0 * (int64_t)M * K;
-      const int64_t nf = (int64_t)nr * K;
-      const bool al = ((((uintptr_t)src) & 15) == 0);
-      if (al) {
-        const int n4 = (int)(nf >> 2);
-        typedef float v4f __attribute__((ext_vector_type(4)));
-        const v4f *s4 = (const v4f *)src;
+      const int nf = nr * K;
+      if (g.aligned) {
+        const int n4 = nf >> 2;
         v4f *d4 = (v4f *)bt;
-        for (int t = tid; t < n4; t += NT) d4[t] = __builtin_nontemporal_load(s4 + t);
+        #pragma unroll
+        for (int i = 0; i < CH; ++i) {
+          const int t = tid + i * NT;
+          if (t < n4) d4[t] = f.b4[i];
+        }
+        // beyond the prefetched chunks, and the ragged tail: direct loads
+        const v4f *s4 = (const v4f *)src;
+        for (int t = tid + CH * NT; t < n4; t += NT) d4[t] = s4[t];
         for (int t = (n4 << 2) + tid; t < nf; t += NT) bt[t] = src[t];
       } else {
         for (int t = tid; t < nf; t += NT) bt[t] = src[t];
       }
-      __syncthreads();
+    } else {
+      e_first = ebase[0];
+      n_ent = (int)(ebase[1] - ebase[0]);
+      #pragma unroll
+      for (int i = 0; i < PCH; ++i) {
+        const int r = tid + i * NT;
+        if (r < nr) rpl[r] = (int32_t)(f.rp[i] - e_first);
+      }
+      if (tid == 0) rpl[nr] = n_ent;
+      #pragma unroll
+      for (int i = 0; i < ECH; ++i) {
+        const int t = tid + i * NT;
+        if (t < n_ent && t < NT * ECH) { ecl[t] = f.ec[i]; evl[t] = f.ev[i]; }
+      }
+      for (int t = tid; t < R * K; t += NT) bt[t] = 0.0f;
+    }
+    // ---- issue the next tile's loads (they land during this tile's compute) ----
+    const int64_t ntile = tile + gridDim.x;
+    int64_t nu0 = 0;
+    int nnr = 0;
+    if (ntile < a.ntiles) {
+      nu0 = ntile * (int64_t)U;
+      nnr = (int)((N - nu0) < U ? (N - nu0) : U) * M;
+      issue_rows<FMT>(f, a.pr, nu0, nnr, K, tid, g.aligned);
+    }
+    __syncthreads();
+    // ---- phase A: scores ----
+    if (FMT == 0) {
       for (int r = tid; r < nr; r += NT) {
-        double accp = (double)a.pr.p[u0 * M + r];
+        double accp = (double)pl[r];
         const float *br = bt + (size_t)r * K;
         for (int k = 0; k < K; ++k) {
           const double prod = lam[k] * (double)br[k];
@@ -136,19 +265,18 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs a, const TileGeom 
         pt[r] = accp;
       }
     } else {
-      // CSR: zero the dense tile, scatter each row's stored entries and
-      // score over the stored columns in ascending order (skipping zeros is
-      // bit-identical: acc - lambda*0 == acc).
-      for (int t = tid; t < R * K; t += NT) bt[t] = 0.0f;
-      __syncthreads();
+      // CSR: scatter each row's stored entries into the dense tile and score
+      // over the stored columns in ascending order (skipping zeros is
+      // bit-identical: acc - lambda*0 == acc)
       for (int r = tid; r < nr; r += NT) {
-        const int64_t row = u0 * M + r;
-        const int64_t e0 = a.pr.rowptr[row], e1 = a.pr.rowptr[row + 1];
-        double accp = (double)a.pr.p[row];
-        for (int64_t e = e0; e < e1; ++e) {
-          const int k = a.pr.col[e];
+        const int e0 = rpl[r], e1 = rpl[r + 1];
+        double accp = (double)pl[r];
+        for (int e = e0; e < e1; ++e) {
+          int k;
+          float v;
+          if (e < NT * ECH) { k = ecl[e]; v = evl[e]; }
+          else { k = a.pr.col[e_first + e]; v = a.pr.val[e_first + e]; }   // tile beyond the staging
           if ((unsigned)k >= (unsigned)K) continue;   // malformed column: ignored (kp_validate_inputs reports it)
-          const float v = a.pr.val[e];
           bt[(size_t)r * K + k] = v;
           const double prod = lam[k] * (double)v;
           accp = accp - prod;
@@ -157,28 +285,36 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs a, const TileGeom 
       }
     }
     __syncthreads();
-    // ---- phase B1: rank items and run the greedy, one thread per user ----
+    // ---- phase B1a: rank of every item of every user (one thread per row) ----
+    for (int r = tid; r < nr; r += NT) {
+      const int u = r / M, j = r - u * M;
+      const double *z = pt + u * M;
+      const double zj = z[j];
+      int rank = 0;
+      for (int jj = 0; jj < M; ++jj) {
+        const double zz = z[jj];
+        rank += (zz > zj) || (zz == zj && jj < j);
+      }
+      perm[u * M + rank] = (uint8_t)j;
+    }
+    // CSR: the next tile's entry range is known now that its row offsets have
+    // landed; start those loads too
+    if (FMT == 1 && ntile < a.ntiles) {
+      if (tid == 0) { ebase[0] = f.rp[0]; ebase[1] = f.rp_end; }
+    }
+    __syncthreads();
+    if (FMT == 1 && ntile < a.ntiles) issue_entries(f, a.pr, ebase[0], ebase[1], tid);
+    // ---- phase B1b: the greedy, one thread per user ----
     if (tid < nu) {
       const int u = tid;
       const double *z = pt + u * M;
-      uint8_t rank[KP_MAX_M];
       uint64_t pos = 0;
-      for (int j = 0; j < M; ++j) { rank[j] = 0; if (z[j] > 0.0) pos |= 1ull << j; }
-      for (int j = 0; j < M; ++j) {
-        const double zj = z[j];
-        int rj = rank[j];
-        for (int jj = j + 1; jj < M; ++jj) {
-          if (z[jj] > zj) ++rj; else rank[jj]++;
-        }
-        rank[j] = (uint8_t)rj;
-      }
-      uint8_t *pu = perm + u * M;
-      for (int j = 0; j < M; ++j) pu[rank[j]] = (uint8_t)j;
-      const uint64_t S = greedy_mask(pu, M, pos, a.tree);
+      for (int j = 0; j < M; ++j) if (z[j] > 0.0) pos |= 1ull << j;
+      const uint64_t S = greedy_mask(perm + u * M, M, pos, a.tree);
       Sm[u] = S;
       Pm[u] = pos;
       double Pi = 0.0, Gi = 0.0;
-      const float *pp = a.pr.p + (u0 + u) * M;
+      const float *pp = pl + u * M;
       for (int j = 0; j < M; ++j) {
         if (S >> j & 1) { Pi = Pi + (double)pp[j]; Gi = Gi + z[j]; }
       }
@@ -211,7 +347,7 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs a, const TileGeom 
             // start above every breakpoint: only horizontal positive lines,
             // ranked by p~ (their lines are c_j = p~_j exactly)
             uint64_t S = greedy_mask(perm + u * M, M, Pm[u] & ~A, a.tree);
-            const KState &ks = a.st[k];
+            const KState &ks = kst[k];
             const double center = ks.center, delta = ks.delta;
             const int bstar = ks.bstar;
             const uint64_t klo = ks.klo, khi = ks.khi;
@@ -271,8 +407,8 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs a, const TileGeom 
                 emit = (id >= -KP_CENTRAL_W && id <= KP_CENTRAL_W);
               } else if (mode == KS_EMIT_BUCKET || mode == KS_HULL_BUCKET) {
                 if (exp_bucket(best, center, delta) == bstar) {
-                  atomicMin((unsigned long long *)&a.st[k].hull_lo, (unsigned long long)key);
-                  atomicMax((unsigned long long *)&a.st[k].hull_hi, (unsigned long long)key);
+                  atomicMin(&hmin[k], (unsigned long long)key);
+                  atomicMax(&hmax[k], (unsigned long long)key);
                   emit = (mode == KS_EMIT_BUCKET);
                 }
               } else if (mode == KS_REFINE) {
@@ -285,12 +421,15 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs a, const TileGeom 
                 emit = (key >= klo && key <= khi);
               }
               if (emit) {
-                const uint32_t slot = atomicAdd(&a.st[k].n_emit, 1u);
-                if (slot < a.emit_cap) {
-                  a.emit_v1[(size_t)k * a.emit_cap + slot] = best;
-                  a.emit_v2[(size_t)k * a.emit_cap + slot] = v2;
+                const uint32_t slot = atomicAdd(nstage, 1u);
+                if (slot < a.stage_cap) {
+                  const size_t e = (size_t)blockIdx.x * a.stage_cap + slot;
+                  a.stage_v1[e] = best;
+                  a.stage_v2[e] = v2;
+                  a.stage_k[e] = (uint16_t)k;
+                  atomicAdd(&kcnt[k], 1u);
                 } else {
-                  a.st[k].overflow = 1;
+                  kovf[k] = 1u;
                 }
               }
             }
@@ -325,26 +464,59 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs a, const TileGeom 
         atomicAdd(&a.hist_cnt[t], hc[t]);
       }
     }
+    // publish the staged events: one reservation per (block, k)
+    for (int k = tid; k < K; k += NT) {
+      if (kcnt[k]) kpos[k] = atomicAdd(&a.st[k].n_emit, kcnt[k]);
+      if (kovf[k]) atomicOr(&a.st[k].overflow, 1);
+      if (hmin[k] != ~0ull) {
+        atomicMin((unsigned long long *)&a.st[k].hull_lo, hmin[k]);
+        atomicMax((unsigned long long *)&a.st[k].hull_hi, hmax[k]);
+      }
+      kcnt[k] = 0u;
+    }
+    __syncthreads();
+    const uint32_t ns = *nstage < a.stage_cap ? *nstage : a.stage_cap;
+    for (uint32_t t = tid; t < ns; t += NT) {
+      const size_t e = (size_t)blockIdx.x * a.stage_cap + t;
+      const int k = a.stage_k[e];
+      const uint32_t dst = kpos[k] + atomicAdd(&kcnt[k], 1u);
+      if (dst < a.emit_cap) {
+        a.emit_v1[(size_t)k * a.emit_cap + dst] = a.stage_v1[e];
+        a.emit_v2[(size_t)k * a.emit_cap + dst] = a.stage_v2[e];
+      } else {
+        atomicOr(&a.st[k].overflow, 1);
+      }
+    }
   }
 }
 
 // ---------------------------------------------------------------------------
 // second-level reduction of the block partials (fixed order), dual value
 // ---------------------------------------------------------------------------
-__global__ void k_reduce_stats(const double *partials, int nblk, int K, const double *lam,
-                               const double *B, double *R, double *g, double *P) {
-  // one thread per output column; columns K (G) and K+1 (P)
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= K + 2) return;
+__global__ void __launch_bounds__(256) k_reduce_stats(const double *partials, int nblk, int K,
+                                                      const double *lam, const double *B,
+                                                      double *R, double *g, double *P) {
+  // one block per output column (K consumptions, then sum G_i, then sum P_i);
+  // every thread adds a fixed strided subset, then a fixed tree: deterministic
+  __shared__ double red[256];
+  const int c = blockIdx.x, t = threadIdx.x;
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s = s + partials[(size_t)b * (K + 2) + c];
+  for (int b = t; b < nblk; b += 256) s = s + partials[(size_t)b * (K + 2) + c];
+  red[t] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) red[t] = red[t] + red[t + w];
+    __syncthreads();
+  }
+  if (t != 0) return;
+  s = red[0];
   if (c < K) {
     if (R) R[c] = s;
   } else if (c == K) {
     // g = sum_i G_i + sum_k lambda_k B_k
-    double t = s;
-    for (int k = 0; k < K; ++k) { const double lb = lam[k] * B[k]; t = t + lb; }
-    if (g) *g = t;
+    double tt = s;
+    for (int k = 0; k < K; ++k) { const double lb = lam[k] * B[k]; tt = tt + lb; }
+    if (g) *g = tt;
   } else {
     if (P) *P = s;
   }
@@ -419,7 +591,7 @@ __global__ void k_scd_locate(KState *st, int K, const double *B, double *hist_su
       if (central && !s.overflow) {
         s.mode = KS_SELECT_BUCKET;
       } else {
-        s.mode = hcnt[bin] <= emit_cap ? KS_EMIT_BUCKET : KS_HULL_BUCKET;
+        s.mode = hcnt[bin] <= emit_cap / 2 ? KS_EMIT_BUCKET : KS_HULL_BUCKET;
         s.n_emit = 0;
         s.overflow = 0;
         s.hull_lo = ~0ull;
@@ -451,7 +623,7 @@ __global__ void k_scd_locate(KState *st, int K, const double *B, double *hist_su
     if (lo == hi) {
       s.mode = KS_DONE;
       s.result = kdbl(lo);
-    } else if (hcnt[bin] <= emit_cap) {
+    } else if (hcnt[bin] <= emit_cap / 2) {
       s.klo = lo;
       s.khi = hi;
       s.mode = KS_EMIT_RANGE;
@@ -684,12 +856,17 @@ __global__ void k_validate_csr(const int64_t *rowptr, const int32_t *col, int64_
 // ---------------------------------------------------------------------------
 // host-side launch helpers (called from the C ABI)
 // ---------------------------------------------------------------------------
-size_t kp_sweep_lds_bytes(int U, int M, int K, bool scd) {
+size_t kp_sweep_lds_bytes(int U, int M, int K, bool scd, int fmt) {
   auto r16 = [](size_t b) { return (b + 15) & ~(size_t)15; };
   const size_t R = (size_t)U * M, Q = (size_t)U * K;
   size_t s = r16(R * K * 4) + r16(R * 8) + r16(R) + r16((size_t)U * 8) * 2 + r16(Q * 8) +
              r16((size_t)U * 16) + r16((size_t)(K + 2) * 8);
-  if (scd) s += r16((size_t)K * KP_NB * 8) + r16((size_t)K * KP_NB * 4) + r16((size_t)K * 4);
+  s += r16((size_t)K * 8);   // lambda
+  s += r16(R * 4) + r16((R + 1) * 4) + r16(16);   // staged profits, row offsets, entry base
+  if (fmt == 1) s += 2 * r16((size_t)NT * ECH * 4);  // staged CSR entries
+  if (scd)
+    s += r16((size_t)K * sizeof(KState)) + r16((size_t)K * KP_NB * 8) +
+         r16((size_t)K * KP_NB * 4) + 4 * r16((size_t)K * 4) + 2 * r16((size_t)K * 8) + r16(16);
   return s;
 }
 
@@ -698,7 +875,17 @@ hipError_t kp_launch_sweep(const SweepArgs &a, int U, int grid, bool scd, hipStr
   g.U = U;
   g.M = a.pr.M;
   g.K = a.pr.K;
-  const size_t lds = kp_sweep_lds_bytes(U, g.M, g.K, scd);
+  g.aligned = a.pr.fmt == 0 && ((uintptr_t)a.pr.b & 15) == 0 &&
+              (((int64_t)U * g.M * g.K) & 3) == 0;
+  const size_t lds = kp_sweep_lds_bytes(U, g.M, g.K, scd, a.pr.fmt);
+  if (lds > 64 * 1024) {
+    // shapes with many knapsacks need more than the default 64 KB of LDS
+    // (gfx950 has 160 KB per workgroup)
+    const void *fn = a.pr.fmt == 0 ? (scd ? (const void *)k_sweep<0, true> : (const void *)k_sweep<0, false>)
+                                   : (scd ? (const void *)k_sweep<1, true> : (const void *)k_sweep<1, false>);
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
   if (a.pr.fmt == 0) {
     if (scd) hipLaunchKernelGGL((k_sweep<0, true>), dim3(grid), dim3(NT), lds, stream, a, g);
     else hipLaunchKernelGGL((k_sweep<0, false>), dim3(grid), dim3(NT), lds, stream, a, g);
@@ -712,9 +899,8 @@ hipError_t kp_launch_sweep(const SweepArgs &a, int U, int grid, bool scd, hipStr
 hipError_t kp_launch_reduce_stats(const double *partials, int nblk, int K, const double *lam,
                                   const double *B, double *R, double *g, double *P,
                                   hipStream_t stream) {
-  const int n = K + 2;
-  hipLaunchKernelGGL(k_reduce_stats, dim3((n + 255) / 256), dim3(256), 0, stream, partials, nblk,
-                     K, lam, B, R, g, P);
+  hipLaunchKernelGGL(k_reduce_stats, dim3(K + 2), dim3(256), 0, stream, partials, nblk, K, lam, B,
+                     R, g, P);
   return hipGetLastError();
 }
 

@@ -37,6 +37,8 @@ def _cases():
         ("N1", random_instance(rng, 1, 5, 2, Q=2)),
         ("M1-K1", random_instance(rng, 300, 1, 1, Q=1)),
         ("M40-K3", random_instance(rng, 200, 40, 3, Q=7)),
+        ("M63-K27-odd-tiles", random_instance(rng, 50, 63, 27, Q=9)),
+        ("csr-wide-rows", random_instance(rng, 300, 16, 60, Q=4, zero_frac=0.2).to_csr()),
     ]
     return out
 
@@ -135,6 +137,28 @@ def test_dual_autograd_matches_oracle_gradient():
         ref = oracle.eval_dual(inst, lam, want_x=False)
         assert abs(g.item() - ref["g"]) <= REL * abs(ref["g"])
         assert np.array_equal(lam_t.grad.cpu().numpy(), inst.B - ref["R"])
+
+
+@gpu
+def test_unaligned_dense_costs():
+    """A dense cost array that is not 16-byte aligned takes the scalar
+    staging path and gives the same results."""
+    kp, torch = _kp()
+    rng = np.random.default_rng(77)
+    inst = random_instance(rng, 900, 9, 5, Q=3)
+    prob = kp.Problem.from_host(inst)
+    big = torch.empty(inst.N * inst.M * inst.K + 1, dtype=torch.float32, device="cuda")
+    big[1:] = prob.b
+    prob2 = kp.Problem(prob.p, inst.B, inst.tree.parent, inst.tree.cap, inst.tree.leaf_of_item,
+                       b=big[1:], N=inst.N, M=inst.M, K=inst.K)
+    assert prob2.b.data_ptr() % 16 != 0
+    lam = np.array([0.1, 0.2, 0.05, 0.3, 0.15])
+    ev = kp.kp_eval_dual(prob2, _lamd(torch, lam), want_x=True)
+    ref = oracle.eval_dual(inst, lam)
+    assert np.array_equal(ev["x"].cpu().numpy(), ref["x"])
+    assert np.array_equal(ev["R"].cpu().numpy(), ref["R"])
+    got = kp.kp_scd_sweep(prob2, _lamd(torch, lam))["lam"].cpu().numpy()
+    assert np.array_equal(got, oracle.scd_sweep(inst, lam))
 
 
 @gpu
