@@ -32,6 +32,11 @@ hipError_t kp_launch_dd_update(int K, double alpha, const double *R, const doubl
 hipError_t kp_launch_dual_backward(int K, const double *R, const double *B, const double *gout,
                                    double *glam, hipStream_t stream);
 hipError_t kp_launch_validate(const float *v, int64_t n, unsigned int *flags, hipStream_t stream);
+hipError_t kp_launch_fixup_pipeline(const double *uv, int nv, const double *G, int64_t N,
+                                    const double *RB, ProbDev pr, uint8_t *x, const double *R,
+                                    const double *P, double *R_out, double *P_out, int64_t *n_reset,
+                                    void *scratch, hipStream_t stream, uint32_t *ncand_host_pinned);
+size_t kp_fixup_scratch_bytes(int64_t N, int nv, int K);
 hipError_t kp_launch_validate_csr(const int64_t *rowptr, const int32_t *col, int64_t nrows, int K,
                                   unsigned int *flags, hipStream_t stream);
 
@@ -668,8 +673,71 @@ kp_status kp_get_timing(void *ctx, double *sweep_ms_total, int64_t *sweep_launch
 
 kp_status kp_primal_fixup(void *ctx, const kp_problem *prob, const double *lambda, uint8_t *x_out,
                           double *primal_out, double *R_out, int64_t *n_reset_out) {
-  (void)ctx; (void)prob; (void)lambda; (void)x_out; (void)primal_out; (void)R_out; (void)n_reset_out;
-  return fail(KP_ERR_UNSUPPORTED, "kp_primal_fixup is not built yet");
+  if (!ctx) return fail(KP_ERR_INVALID, "ctx is NULL");
+  if (!lambda || !primal_out || !R_out || !n_reset_out) return fail(KP_ERR_INVALID, "NULL argument");
+  Ctx *c = (Ctx *)ctx;
+  Prepared P;
+  kp_status s = prepare(prob, false, P);
+  if (s != KP_OK) return s;
+  if (P.pr.N >= (int64_t)1 << 32) return fail(KP_ERR_UNSUPPORTED, "post-processing supports N < 2^32");
+  const int K = P.pr.K;
+  const int64_t N = P.pr.N;
+  // pass 1: x(lambda), R, P
+  SweepWs w;
+  if ((s = carve_ws(c, P, false, w)) != KP_OK) return s;
+  // workspace beyond the sweep's: x (when the caller gives none), G, uv, kv map, RB, sort scratch
+  Carve cv;
+  cv.off = 0;
+  {
+    Carve base;
+    base.take((size_t)P.grid * (K + 2) * 8); base.take((size_t)K * 8); base.take((size_t)K * 8);
+    base.take(8); base.take(8); base.take(8); base.take(8);
+    cv.off = base.off;
+  }
+  const size_t o_x = cv.take(x_out ? 0 : (size_t)N * P.pr.M);
+  const size_t o_Rv = cv.take((size_t)K * 8);
+  const size_t o_Pv = cv.take(8);
+  // size the rest for the worst case (every knapsack violated)
+  const size_t o_G = cv.take((size_t)N * 8);
+  const size_t o_uv = cv.take((size_t)N * K * 8);
+  const size_t o_map = cv.take((size_t)K * 4);
+  const size_t o_RB = cv.take((size_t)K * 16);
+  const size_t o_scr = cv.take(kp_fixup_scratch_bytes(N, K, K));
+  if ((s = ensure_ws(c, cv.off)) != KP_OK) return s;
+  if ((s = carve_ws(c, P, false, w)) != KP_OK) return s;   // re-carve after a possible regrow
+  char *b = (char *)c->ws;
+  uint8_t *xd = x_out ? x_out : (uint8_t *)(b + o_x);
+  double *Rv = (double *)(b + o_Rv), *Pv = (double *)(b + o_Pv);
+  double *Gd = (double *)(b + o_G), *uv = (double *)(b + o_uv), *RB = (double *)(b + o_RB);
+  int *map = (int *)(b + o_map);
+  HIP_TRY(hipMemcpyAsync(w.B, P.B.data(), (size_t)K * 8, hipMemcpyHostToDevice, c->stream));
+  if ((s = eval_into(c, P, w, lambda, Rv, w.gtmp, Pv, xd)) != KP_OK) return s;
+  std::vector<double> Rh(K);
+  HIP_TRY(hipMemcpyAsync(Rh.data(), Rv, (size_t)K * 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  std::vector<int> kv(K, -1);
+  std::vector<double> rb;
+  int nv = 0;
+  for (int k = 0; k < K; ++k)
+    if (Rh[k] > P.B[k]) { kv[k] = nv++; rb.push_back(Rh[k]); rb.push_back(P.B[k]); }
+  if (nv == 0) {
+    HIP_TRY(hipMemcpyAsync(R_out, Rv, (size_t)K * 8, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(primal_out, Pv, 8, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(hipMemsetAsync(n_reset_out, 0, 8, c->stream));
+    return KP_OK;
+  }
+  HIP_TRY(hipMemcpyAsync(map, kv.data(), (size_t)K * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(RB, rb.data(), rb.size() * 8, hipMemcpyHostToDevice, c->stream));
+  // pass 2: per-user group dual value and consumption of the violated knapsacks
+  SweepArgs a = make_args(P, lambda, w, nullptr, false);
+  a.G_out = Gd;
+  a.uv_out = uv;
+  a.kv_map = map;
+  a.nv = nv;
+  HIP_TRY(kp_launch_sweep(a, P.U, P.grid, false, c->stream));
+  HIP_TRY(kp_launch_fixup_pipeline(uv, nv, Gd, N, RB, P.pr, xd, Rv, Pv, R_out, primal_out,
+                                   n_reset_out, b + o_scr, c->stream, (uint32_t *)(c->pinned + 4)));
+  return KP_OK;
 }
 
 kp_status kp_scd_sweep_batched(void *ctx, const kp_problem *probs, int32_t n,

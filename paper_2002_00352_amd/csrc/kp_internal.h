@@ -80,4 +80,9 @@ struct SweepArgs {
   uint32_t stage_cap;
   int pass;
   unsigned long long *err; // walk-limit counter
+  // per-user outputs for the post-processing (eval only)
+  double *G_out;           // [N] group dual value p~_i, or null
+  double *uv_out;          // [N][nv] consumption of the selected knapsacks, or null
+  const int *kv_map;       // [K] column in uv_out, or -1
+  int nv;
 };

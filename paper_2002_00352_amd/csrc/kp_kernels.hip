@@ -139,6 +139,7 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs a, const TileGeom 
   uint8_t *perm = (uint8_t *)carve((size_t)R);            // [U][M] rank -> item
   uint64_t *Sm = (uint64_t *)carve((size_t)U * 8);        // greedy set at lambda^t
   uint64_t *Pm = (uint64_t *)carve((size_t)U * 8);        // items with p~ > 0
+  int8_t *tau = (int8_t *)carve(SCD ? (size_t)R : 0);     // per item: threshold element (-1 = zero level)
   double *vk = (double *)carve((size_t)Q * 8);            // per (user,k) consumption
   double *uPG = (double *)carve((size_t)U * 16);          // per user P_i, G_i
   double *acc = (double *)carve((size_t)(K + 2) * 8);     // block running sums
@@ -313,6 +314,67 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs a, const TileGeom 
       const uint64_t S = greedy_mask(perm + u * M, M, pos, a.tree);
       Sm[u] = S;
       Pm[u] = pos;
+      if (SCD) {
+        // Threshold element of every item o against the greedy solution G_o of
+        // the other items (their order does not depend on lambda_k when o is
+        // the only item that moves with it): o is selected exactly when its
+        // line beats that element (or is positive, for the zero level -1).
+        //   o not in S: G_o = S; the lowest-ranked member of S in the smallest
+        //     full set containing o, or the zero level if no set containing o
+        //     is full.
+        //   o in S: G_o = S - o + r(o) with r(o) the best positive item outside
+        //     S whose smallest full set contains o; the threshold is r(o), or
+        //     the zero level when there is none.
+        const uint8_t *pu = perm + u * M;
+        int8_t *tu = tau + u * M;
+        uint64_t assigned = S;   // items outside S get their value below
+        for (int l = 0; l < a.tree.L; ++l) {
+          const uint64_t m = a.tree.mask[l];
+          if (popc64(S & m) < a.tree.cap[l]) continue;
+          uint64_t pend = m & ~assigned;
+          if (!pend) continue;
+          int low = -1;
+          for (int r = M - 1; r >= 0; --r) {
+            const int j = pu[r];
+            if ((S & m) >> j & 1) { low = j; break; }
+          }
+          assigned |= pend;
+          while (pend) {
+            const int o = __ffsll((long long)pend) - 1;
+            pend &= pend - 1;
+            tu[o] = (int8_t)low;
+          }
+        }
+        uint64_t rest = ~assigned & ((M == 64) ? ~0ull : ((1ull << M) - 1));
+        while (rest) {
+          const int o = __ffsll((long long)rest) - 1;
+          rest &= rest - 1;
+          tu[o] = -1;
+        }
+        uint64_t resolved = 0;
+        for (int r = 0; r < M && resolved != S; ++r) {
+          const int e = pu[r];
+          if ((S >> e & 1) || !(pos >> e & 1)) continue;
+          uint64_t lm = 0;
+          for (int l = 0; l < a.tree.L; ++l) {
+            const uint64_t m = a.tree.mask[l];
+            if ((m >> e & 1) && popc64(S & m) >= a.tree.cap[l]) { lm = m; break; }
+          }
+          uint64_t nw = S & lm & ~resolved;
+          resolved |= nw;
+          while (nw) {
+            const int o = __ffsll((long long)nw) - 1;
+            nw &= nw - 1;
+            tu[o] = (int8_t)e;
+          }
+        }
+        uint64_t left = S & ~resolved;
+        while (left) {
+          const int o = __ffsll((long long)left) - 1;
+          left &= left - 1;
+          tu[o] = -1;
+        }
+      }
       double Pi = 0.0, Gi = 0.0;
       const float *pp = pl + u * M;
       for (int j = 0; j < M; ++j) {
@@ -320,6 +382,7 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs a, const TileGeom 
       }
       uPG[2 * u] = Pi;
       uPG[2 * u + 1] = Gi;
+      if (a.G_out) a.G_out[u0 + u] = Gi;
       if (a.x_out) {
         uint8_t *xo = a.x_out + (u0 + u) * M;
         for (int j = 0; j < M; ++j) xo[j] = (uint8_t)(S >> j & 1);
@@ -335,6 +398,10 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs a, const TileGeom 
       for (int j = 0; j < M; ++j)
         if (S0 >> j & 1) v = v + (double)bu[j * K + k];
       vk[q] = v;
+      if (a.uv_out) {
+        const int col = a.kv_map[k];
+        if (col >= 0) a.uv_out[(size_t)(u0 + u) * a.nv + col] = v;
+      }
       if (SCD) {
         const int mode = kmode[k];
         if (mode == KS_EXP || mode == KS_EMIT_BUCKET || mode == KS_HULL_BUCKET ||
@@ -344,20 +411,42 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs a, const TileGeom 
           uint64_t A = 0;   // moving lines: b_jk > 0
           for (int j = 0; j < M; ++j) if (bu[j * K + k] > 0.0f) A |= 1ull << j;
           if (A) {
-            // start above every breakpoint: only horizontal positive lines,
-            // ranked by p~ (their lines are c_j = p~_j exactly)
-            uint64_t S = greedy_mask(perm + u * M, M, Pm[u] & ~A, a.tree);
             const KState &ks = kst[k];
             const double center = ks.center, delta = ks.delta;
             const int bstar = ks.bstar;
             const uint64_t klo = ks.klo, khi = ks.khi;
             const int shift = ks.shift;
             const int maxev = M * M + M + 8;
+            const bool single = (A & (A - 1)) == 0;
+            // start above every breakpoint: only horizontal positive lines,
+            // ranked by p~ (their lines are c_j = p~_j exactly)
+            uint64_t S = single ? 0ull : greedy_mask(perm + u * M, M, Pm[u] & ~A, a.tree);
             for (int ev = 0; ; ++ev) {
               if (ev >= maxev) { atomicAdd(a.err, 1ull); break; }
+              if (single && ev > 0) break;
               double best = 0.0;
               int bo = -1, bs = -1;
-              uint64_t cand = A & ~S;
+              uint64_t cand = single ? 0ull : (A & ~S);
+              if (single) {
+                // one moving line: its only breakpoint is where it crosses its
+                // threshold element (a horizontal line) or the zero level
+                const int o = __ffsll((long long)A) - 1;
+                const int th = tau[u * M + o];
+                const double bo_d = (double)bu[o * K + k];
+                const double add_o = lk * bo_d;
+                const double co = zu[o] + add_o;
+                if (th < 0) {
+                  if (co > 0.0) { best = co / bo_d; bo = o; bs = -1; }
+                } else {
+                  const double bs_d = 0.0;
+                  const double add_s = lk * bs_d;
+                  const double cs = zu[th] + add_s;
+                  const double num = co - cs;
+                  const double den = bo_d - bs_d;
+                  const double val = num / den;
+                  if (val > 0.0) { best = val; bo = o; bs = th; }
+                }
+              }
               while (cand) {
                 const int o = __ffsll((long long)cand) - 1;
                 cand &= cand - 1;
@@ -854,6 +943,324 @@ __global__ void k_validate_csr(const int64_t *rowptr, const int32_t *col, int64_
 }
 
 // ---------------------------------------------------------------------------
+// post-processing for feasibility: candidate compaction, stable LSD radix
+// sort of (group dual value, user) keys, per-knapsack prefix search, reset
+// ---------------------------------------------------------------------------
+#define FX_NT 256
+#define FX_IPT 16                       // items per thread in the sort / scan kernels
+#define FX_CHUNK (FX_NT * FX_IPT)
+
+// candidate = a user whose solution consumes at least one violated knapsack
+__global__ void __launch_bounds__(FX_NT) k_fix_count(const double *uv, int nv, int64_t N,
+                                                     uint32_t *bcnt) {
+  __shared__ uint32_t c;
+  if (threadIdx.x == 0) c = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * FX_CHUNK;
+  uint32_t mine = 0;
+  for (int t = 0; t < FX_IPT; ++t) {
+    const int64_t i = base + (int64_t)threadIdx.x * FX_IPT + t;
+    if (i >= N) break;
+    bool cand = false;
+    for (int v = 0; v < nv; ++v) cand |= uv[(size_t)i * nv + v] > 0.0;
+    mine += cand;
+  }
+  atomicAdd(&c, mine);
+  __syncthreads();
+  if (threadIdx.x == 0) bcnt[blockIdx.x] = c;
+}
+
+// exclusive scan of n counts in one block (n up to a few million; sequential
+// chunks per thread, then a block scan of the chunk totals)
+__global__ void __launch_bounds__(1024) k_scan_u32(const uint32_t *in, uint32_t *out, int64_t n,
+                                                   uint32_t *total) {
+  __shared__ uint64_t part[1024];
+  const int t = threadIdx.x;
+  const int64_t per = (n + 1023) / 1024;
+  const int64_t b0 = t * per, b1 = (b0 + per < n) ? b0 + per : n;
+  uint64_t s = 0;
+  for (int64_t i = b0; i < b1; ++i) s += in[i];
+  part[t] = s;
+  __syncthreads();
+  if (t == 0) {
+    uint64_t run = 0;
+    for (int i = 0; i < 1024; ++i) { const uint64_t v = part[i]; part[i] = run; run += v; }
+    if (total) *total = (uint32_t)run;
+  }
+  __syncthreads();
+  uint64_t run = part[t];
+  for (int64_t i = b0; i < b1; ++i) { const uint32_t v = in[i]; out[i] = (uint32_t)run; run += v; }
+}
+
+// stable compaction of the candidates in user order
+__global__ void __launch_bounds__(FX_NT) k_fix_compact(const double *uv, int nv, const double *G,
+                                                       int64_t N, const uint32_t *boff,
+                                                       uint64_t *ckey, uint32_t *cidx) {
+  __shared__ uint32_t tcnt[FX_NT];
+  const int64_t base = (int64_t)blockIdx.x * FX_CHUNK;
+  uint32_t mine = 0;
+  for (int t = 0; t < FX_IPT; ++t) {
+    const int64_t i = base + (int64_t)threadIdx.x * FX_IPT + t;
+    if (i >= N) break;
+    bool cand = false;
+    for (int v = 0; v < nv; ++v) cand |= uv[(size_t)i * nv + v] > 0.0;
+    mine += cand;
+  }
+  tcnt[threadIdx.x] = mine;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int t = 0; t < FX_NT; ++t) { const uint32_t v = tcnt[t]; tcnt[t] = run; run += v; }
+  }
+  __syncthreads();
+  uint32_t pos = boff[blockIdx.x] + tcnt[threadIdx.x];
+  for (int t = 0; t < FX_IPT; ++t) {
+    const int64_t i = base + (int64_t)threadIdx.x * FX_IPT + t;
+    if (i >= N) break;
+    bool cand = false;
+    for (int v = 0; v < nv; ++v) cand |= uv[(size_t)i * nv + v] > 0.0;
+    if (cand) {
+      // G_i >= 0 (a sum of positive scores), so its bits order like the values
+      ckey[pos] = dkey(G[i] + 0.0);
+      cidx[pos] = (uint32_t)i;
+      ++pos;
+    }
+  }
+}
+
+// one 4-bit digit of a stable LSD radix sort: per-block digit counts
+__global__ void __launch_bounds__(FX_NT) k_rs_hist(const uint64_t *key, uint32_t n, int shift,
+                                                   uint32_t *hist, uint32_t nblk) {
+  __shared__ uint32_t h[16];
+  if (threadIdx.x < 16) h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t base = blockIdx.x * FX_CHUNK;
+  for (int t = 0; t < FX_IPT; ++t) {
+    const uint32_t i = base + threadIdx.x * FX_IPT + t;
+    if (i >= n) break;
+    atomicAdd(&h[(key[i] >> shift) & 15], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < 16) hist[(size_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+}
+
+// stable scatter: each thread owns FX_IPT consecutive items; ranks come from
+// per-thread digit counts scanned across the block in thread order
+__global__ void __launch_bounds__(FX_NT) k_rs_scatter(const uint64_t *key, const uint32_t *val,
+                                                      uint32_t n, int shift, const uint32_t *hoff,
+                                                      uint32_t nblk, uint64_t *okey,
+                                                      uint32_t *oval) {
+  __shared__ uint32_t cnt[16][FX_NT + 1];
+  const int t = threadIdx.x;
+  const uint32_t base = blockIdx.x * FX_CHUNK + t * FX_IPT;
+  uint32_t c[16];
+  for (int d = 0; d < 16; ++d) c[d] = 0;
+  for (int q = 0; q < FX_IPT; ++q) {
+    const uint32_t i = base + q;
+    if (i >= n) break;
+    c[(key[i] >> shift) & 15]++;
+  }
+  for (int d = 0; d < 16; ++d) cnt[d][t] = c[d];
+  __syncthreads();
+  if (t < 16) {
+    uint32_t run = hoff[(size_t)t * nblk + blockIdx.x];
+    for (int q = 0; q < FX_NT; ++q) { const uint32_t v = cnt[t][q]; cnt[t][q] = run; run += v; }
+  }
+  __syncthreads();
+  for (int d = 0; d < 16; ++d) c[d] = cnt[d][t];
+  for (int q = 0; q < FX_IPT; ++q) {
+    const uint32_t i = base + q;
+    if (i >= n) break;
+    const uint64_t kk = key[i];
+    const int d = (int)((kk >> shift) & 15);
+    const uint32_t dst = c[d]++;
+    okey[dst] = kk;
+    oval[dst] = val[i];
+  }
+}
+
+// per (block, violated knapsack): sum of the consumptions of the block's
+// sorted candidates
+__global__ void __launch_bounds__(FX_NT) k_fix_bsum(const uint32_t *sidx, uint32_t n, const double *uv,
+                                                    int nv, double *bsum, uint32_t nblk) {
+  __shared__ double red[FX_NT];
+  for (int v = 0; v < nv; ++v) {
+    double s = 0.0;
+    for (int q = 0; q < FX_IPT; ++q) {
+      const uint32_t i = blockIdx.x * FX_CHUNK + threadIdx.x * FX_IPT + q;
+      if (i >= n) break;
+      s = s + uv[(size_t)sidx[i] * nv + v];
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = FX_NT / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) bsum[(size_t)v * nblk + blockIdx.x] = red[0];
+    __syncthreads();
+  }
+}
+
+// one block per violated knapsack: the shortest prefix of the sorted
+// candidates whose consumption covers the excess R_k - B_k
+__global__ void __launch_bounds__(256) k_fix_prefix(const uint32_t *sidx, uint32_t n, const double *uv,
+                                                    int nv, const double *bsum, uint32_t nblk,
+                                                    const double *RB, unsigned int *tstar) {
+  // RB[2v], RB[2v+1]: consumption and budget of the v-th violated knapsack;
+  // covered when R - cumulative <= B (the reset loop's own test)
+  const int v = blockIdx.x;
+  const double Rk = RB[2 * v], Bk = RB[2 * v + 1];
+  __shared__ uint32_t blk;
+  __shared__ double before;
+  if (threadIdx.x == 0) {
+    double run = 0.0;
+    uint32_t b = nblk;
+    for (uint32_t q = 0; q < nblk; ++q) {
+      const double nx = run + bsum[(size_t)v * nblk + q];
+      if (Rk - nx <= Bk) { b = q; break; }
+      run = nx;
+    }
+    blk = b;
+    before = run;
+  }
+  __syncthreads();
+  if (blk >= nblk) {  // cannot happen: every violated knapsack is covered by its consumers
+    if (threadIdx.x == 0) atomicMax(tstar, n);
+    return;
+  }
+  if (threadIdx.x == 0) {
+    double run = before;
+    uint32_t t = blk * FX_CHUNK;
+    const uint32_t end = (blk + 1) * FX_CHUNK < n ? (blk + 1) * FX_CHUNK : n;
+    for (; t < end; ++t) {
+      run = run + uv[(size_t)sidx[t] * nv + v];
+      if (Rk - run <= Bk) break;
+    }
+    atomicMax(tstar, (t < end ? t + 1 : end));
+  }
+}
+
+// reset the first tstar sorted candidates; each thread accumulates its users'
+// removed profit and consumption in its own LDS row (fixed user order), rows
+// are added in thread order into a per-block slot
+#define FX_RT 64
+__global__ void __launch_bounds__(FX_RT) k_fix_reset(const uint32_t *sidx, const unsigned int *tstar,
+                                                     ProbDev pr, uint8_t *x, double *partials) {
+  extern __shared__ double rows[];   // [FX_RT][K + 1]
+  const int K = pr.K, M = pr.M, W = K + 1;
+  double *mine = rows + (size_t)threadIdx.x * W;
+  for (int c = 0; c < W; ++c) mine[c] = 0.0;
+  const uint32_t ts = *tstar;
+  for (uint32_t t = blockIdx.x * FX_RT + threadIdx.x; t < ts; t += gridDim.x * FX_RT) {
+    const int64_t i = sidx[t];
+    for (int j = 0; j < M; ++j) {
+      const int64_t r = i * M + j;
+      if (!x[r]) continue;
+      x[r] = 0;
+      mine[K] = mine[K] + (double)pr.p[r];
+      if (pr.fmt == 0) {
+        for (int k = 0; k < K; ++k) mine[k] = mine[k] + (double)pr.b[r * K + k];
+      } else {
+        for (int64_t e = pr.rowptr[r]; e < pr.rowptr[r + 1]; ++e) {
+          const int k = pr.col[e];
+          if ((unsigned)k < (unsigned)K) mine[k] = mine[k] + (double)pr.val[e];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < W; c += FX_RT) {
+    double s = 0.0;
+    for (int q = 0; q < FX_RT; ++q) s = s + rows[(size_t)q * W + c];
+    partials[(size_t)blockIdx.x * W + c] = s;
+  }
+}
+
+__global__ void k_fix_final(const double *partials, int nblk, int K, const double *R, const double *P,
+                            double *R_out, double *P_out, const unsigned int *tstar, int64_t *n_reset) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c > K) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s = s + partials[(size_t)b * (K + 1) + c];
+  if (c < K) {
+    R_out[c] = R[c] - s;
+  } else {
+    *P_out = *P - s;
+    *n_reset = (int64_t)*tstar;
+  }
+}
+
+hipError_t kp_launch_fixup_pipeline(const double *uv, int nv, const double *G, int64_t N,
+                                    const double *RB, ProbDev pr, uint8_t *x, const double *R,
+                                    const double *P, double *R_out, double *P_out, int64_t *n_reset,
+                                    void *scratch, hipStream_t stream, uint32_t *ncand_host_pinned) {
+  // scratch layout (all sized by the caller): bcnt/boff [nb], ckey/tkey [N], cidx/tidx [N],
+  // hist/hoff [16*nbs], bsum [nv*nbs], partials [nblk_reset*(K+1)], tstar, total
+  const uint32_t nb = (uint32_t)((N + FX_CHUNK - 1) / FX_CHUNK);
+  char *w = (char *)scratch;
+  auto take = [&](size_t bytes) { char *p = w; w += (bytes + 255) & ~(size_t)255; return (void *)p; };
+  uint32_t *bcnt = (uint32_t *)take((size_t)nb * 4);
+  uint32_t *boff = (uint32_t *)take((size_t)nb * 4);
+  uint64_t *ckey = (uint64_t *)take((size_t)N * 8);
+  uint64_t *tkey = (uint64_t *)take((size_t)N * 8);
+  uint32_t *cidx = (uint32_t *)take((size_t)N * 4);
+  uint32_t *tidx = (uint32_t *)take((size_t)N * 4);
+  uint32_t *hist = (uint32_t *)take((size_t)16 * nb * 4);
+  uint32_t *hoff = (uint32_t *)take((size_t)16 * nb * 4);
+  double *bsum = (double *)take((size_t)(nv > 0 ? nv : 1) * nb * 8);
+  const int nblk_reset = 1024;
+  double *partials = (double *)take((size_t)nblk_reset * (pr.K + 1) * 8);
+  unsigned int *tstar = (unsigned int *)take(8);
+  uint32_t *total = (uint32_t *)take(8);
+  hipLaunchKernelGGL(k_fix_count, dim3(nb), dim3(FX_NT), 0, stream, uv, nv, N, bcnt);
+  hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, stream, bcnt, boff, (int64_t)nb, total);
+  hipLaunchKernelGGL(k_fix_compact, dim3(nb), dim3(FX_NT), 0, stream, uv, nv, G, N, boff, ckey, cidx);
+  hipError_t e = hipMemcpyAsync(ncand_host_pinned, total, 4, hipMemcpyDeviceToHost, stream);
+  if (e != hipSuccess) return e;
+  e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return e;
+  const uint32_t n = *ncand_host_pinned;
+  uint64_t *k0 = ckey, *k1 = tkey;
+  uint32_t *v0 = cidx, *v1 = tidx;
+  const uint32_t nbs = (n + FX_CHUNK - 1) / FX_CHUNK;
+  if (n > 0) {
+    for (int shift = 0; shift < 64; shift += 4) {
+      hipLaunchKernelGGL(k_rs_hist, dim3(nbs), dim3(FX_NT), 0, stream, k0, n, shift, hist, nbs);
+      hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, stream, hist, hoff, (int64_t)16 * nbs,
+                         (uint32_t *)nullptr);
+      hipLaunchKernelGGL(k_rs_scatter, dim3(nbs), dim3(FX_NT), 0, stream, k0, v0, n, shift, hoff, nbs,
+                         k1, v1);
+      uint64_t *tk = k0; k0 = k1; k1 = tk;
+      uint32_t *tv = v0; v0 = v1; v1 = tv;
+    }
+  }
+  e = hipMemsetAsync(tstar, 0, 4, stream);
+  if (e != hipSuccess) return e;
+  if (n > 0 && nv > 0) {
+    hipLaunchKernelGGL(k_fix_bsum, dim3(nbs), dim3(FX_NT), 0, stream, v0, n, uv, nv, bsum, nbs);
+    hipLaunchKernelGGL(k_fix_prefix, dim3(nv), dim3(256), 0, stream, v0, n, uv, nv, bsum, nbs, RB,
+                       tstar);
+  }
+  const size_t rl = (size_t)FX_RT * (pr.K + 1) * 8;
+  if (rl > 64 * 1024) {
+    e = hipFuncSetAttribute((const void *)k_fix_reset, hipFuncAttributeMaxDynamicSharedMemorySize, (int)rl);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_fix_reset, dim3(nblk_reset), dim3(FX_RT), rl, stream, v0, tstar, pr, x, partials);
+  hipLaunchKernelGGL(k_fix_final, dim3((pr.K + 1 + 255) / 256), dim3(256), 0, stream, partials,
+                     nblk_reset, pr.K, R, P, R_out, P_out, tstar, n_reset);
+  return hipGetLastError();
+}
+
+size_t kp_fixup_scratch_bytes(int64_t N, int nv, int K) {
+  const size_t nb = (size_t)((N + FX_CHUNK - 1) / FX_CHUNK) + 1;
+  auto r = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  return r(nb * 4) * 2 + r((size_t)N * 8) * 2 + r((size_t)N * 4) * 2 + r(16 * nb * 4) * 2 +
+         r((size_t)(nv > 0 ? nv : 1) * nb * 8) + r((size_t)1024 * (K + 1) * 8) + 512;
+}
+
+// ---------------------------------------------------------------------------
 // host-side launch helpers (called from the C ABI)
 // ---------------------------------------------------------------------------
 size_t kp_sweep_lds_bytes(int U, int M, int K, bool scd, int fmt) {
@@ -863,6 +1270,7 @@ size_t kp_sweep_lds_bytes(int U, int M, int K, bool scd, int fmt) {
              r16((size_t)U * 16) + r16((size_t)(K + 2) * 8);
   s += r16((size_t)K * 8);   // lambda
   s += r16(R * 4) + r16((R + 1) * 4) + r16(16);   // staged profits, row offsets, entry base
+  if (scd) s += r16(R);                            // per-item threshold elements
   if (fmt == 1) s += 2 * r16((size_t)NT * ECH * 4);  // staged CSR entries
   if (scd)
     s += r16((size_t)K * sizeof(KState)) + r16((size_t)K * KP_NB * 8) +

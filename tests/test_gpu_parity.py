@@ -191,3 +191,48 @@ def test_validate_inputs_flags_bad_values():
     with pytest.raises(kp.KPError) as e:
         kp.kp_validate_inputs(prob)
     assert e.value.status == -4
+
+
+FIX_CASES = [
+    ("c1-underpriced", lambda: kpgen.config_instance(1, N=6000), [1.2, 1.25]),
+    ("c3-hier-csr", lambda: kpgen.config_instance(3, N=4000), None),
+    ("dense-ties", lambda: random_instance(np.random.default_rng(3), 700, 6, 4, Q=2, grid=6), None),
+    ("feasible-already", lambda: kpgen.config_instance(1, N=3000), [3.0, 3.0]),
+]
+
+
+@gpu
+@pytest.mark.parametrize("name,mk,lam", FIX_CASES, ids=[c[0] for c in FIX_CASES])
+def test_primal_fixup_parity(name, mk, lam):
+    """Post-processing (Sec. 5.4): the reset users, x, R and n_reset equal the
+    oracle's; P within 1e-9; the result is feasible."""
+    kp, torch = _kp()
+    print("case", name, flush=True)
+    inst = mk()
+    if lam is None:
+        lam = np.full(inst.K, 0.05)
+    lam = np.asarray(lam, np.float64)
+    prob = kp.Problem.from_host(inst)
+    fx = kp.kp_primal_fixup(prob, _lamd(torch, lam), want_x=True)
+    ref = oracle.fixup(inst, lam, mode=0)
+    assert fx["n_reset"].item() == ref["n_reset"]
+    assert np.array_equal(fx["x"].cpu().numpy(), ref["x"])
+    assert np.array_equal(fx["R"].cpu().numpy(), ref["R"])
+    assert abs(fx["P"].item() - ref["P"]) <= REL * abs(ref["P"])
+    assert np.all(fx["R"].cpu().numpy() <= inst.B)
+
+
+@gpu
+def test_solve_to_gap_c1():
+    """The driver reaches a relative duality gap <= 1e-3 on the small
+    plain-SCD workload, like the oracle's own driver."""
+    kp, torch = _kp()
+    inst = kpgen.config_instance(1)
+    prob = kp.Problem.from_host(inst)
+    lam, hist = kp.solve(prob, "scd", tol=1e-3, max_iter=60)
+    assert hist[-1]["gap_rel"] <= 1e-3
+    ref = oracle.solve(inst, "scd", tol=1e-3, max_iter=60)
+    assert ref[-1]["gap_rel"] <= 1e-3
+    # same iterates: the multipliers are bit-exact at every step
+    for a, b in zip(hist, ref):
+        assert np.array_equal(a["lam"], b["lam"])
