@@ -68,6 +68,32 @@ def cpu_baseline(cfg_id, seconds):
                       f"({dt:.1f} s on {threads} threads)"}
 
 
+def time_to_gap(tol=1e-3):
+    """Wall time of the GPU SCD driver (sweep + post-processing) on the small
+    plain-SCD workload until the relative duality gap is <= tol, and the
+    oracle's driver on the same instance."""
+    import numpy as np
+    import torch
+    import paper_2002_00352_amd as kp
+    import kpgen
+    import oracle
+    inst = kpgen.config_instance(1)
+    prob = kp.Problem.from_host(inst)
+    kp.solve(prob, "scd", tol=tol, max_iter=3)          # warm the context
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lam, hist = kp.solve(prob, "scd", tol=tol, max_iter=100)
+    torch.cuda.synchronize()
+    t_gpu = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ref = oracle.solve(inst, "scd", tol=tol, max_iter=100)
+    t_cpu = time.perf_counter() - t0
+    return {"workload": kpgen.CONFIGS[1]["name"], "tol": tol, "gpu_seconds": t_gpu,
+            "iterations": len(hist), "gap_rel": hist[-1]["gap_rel"],
+            "oracle_seconds": t_cpu, "oracle_iterations": len(ref),
+            "oracle_gap_rel": ref[-1]["gap_rel"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -149,8 +175,11 @@ def main():
         "lambda_final_head": [float(v) for v in lam[:4].cpu().numpy()],
         "gen_s": t_gen,
     }
+    del prob, arrs
+    torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(cfg_id, args.cpu_seconds)
+        rec["time_to_gap"] = time_to_gap()
     print(json.dumps(rec), flush=True)
 
 

@@ -260,6 +260,23 @@ def kp_primal_fixup(prob: Problem, lam, want_x: bool = False, ctx: Optional[Cont
     return dict(x=x, P=P, R=R, n_reset=nres)
 
 
+def kp_scd_sweep_batched(probs: Sequence[Problem], lams_in, lams_out=None,
+                         ctx: Optional[Context] = None):
+    """One SCD iteration for every instance in one persistent launch per
+    pass.  Returns (lams_out, stats) with stats the per-instance [R, g, P] at
+    lams_in, concatenated."""
+    import torch
+    ctx = ctx or default_context()
+    n = len(probs)
+    arr = (kp_problem * n)(*[pr.s for pr in probs])
+    lams_out = [_dev_f64(pr.K) for pr in probs] if lams_out is None else lams_out
+    pin = (ctypes.c_void_p * n)(*[t.data_ptr() for t in lams_in])
+    pout = (ctypes.c_void_p * n)(*[t.data_ptr() for t in lams_out])
+    stats = _dev_f64(sum(pr.K + 2 for pr in probs))
+    _check(lib().kp_scd_sweep_batched(ctx.h, arr, n, pin, pout, _ptr(stats)))
+    return lams_out, stats
+
+
 def kp_validate_inputs(prob: Problem, ctx: Optional[Context] = None):
     ctx = ctx or default_context()
     _check(lib().kp_validate_inputs(ctx.h, prob.ref))

@@ -37,6 +37,16 @@ hipError_t kp_launch_fixup_pipeline(const double *uv, int nv, const double *G, i
                                     const double *P, double *R_out, double *P_out, int64_t *n_reset,
                                     void *scratch, hipStream_t stream, uint32_t *ncand_host_pinned);
 size_t kp_fixup_scratch_bytes(int64_t N, int nv, int K);
+hipError_t kp_launch_sweep_batched(const SweepArgs *descs, const TileGeom *geoms,
+                                   const int *block_off, int n_inst, int total_blocks, size_t lds,
+                                   hipStream_t stream);
+hipError_t kp_launch_batched_aux(int which, const void *tab, int n, KState *st, const void *lam_ptrs,
+                                 const int *kinst, const int *klocal, hipStream_t stream);
+TileGeom kp_tile_geom(const SweepArgs &a, int U);
+size_t kp_coldesc_size();
+void kp_coldesc_fill(void *dst, const double *partials, const double *lam, const double *B,
+                     double *out, int nblk, int K, int col);
+
 hipError_t kp_launch_validate_csr(const int64_t *rowptr, const int32_t *col, int64_t nrows, int K,
                                   unsigned int *flags, hipStream_t stream);
 
@@ -67,6 +77,7 @@ constexpr int kMaxGrid = 2048;
 constexpr uint32_t kEmitCapDefault = 1u << 20;
 constexpr int kMaxPasses = 96;
 constexpr uint32_t kStageCap = 4096;    // staged events per block per pass
+constexpr uint32_t kEmitCapBatched = 1u << 16;   // emitted events per (instance, knapsack) per pass
 
 struct Ctx {
   hipStream_t stream = nullptr;
@@ -743,8 +754,146 @@ kp_status kp_primal_fixup(void *ctx, const kp_problem *prob, const double *lambd
 kp_status kp_scd_sweep_batched(void *ctx, const kp_problem *probs, int32_t n,
                                const double *const *lambda_in, double *const *lambda_out,
                                double *stats) {
-  (void)ctx; (void)probs; (void)n; (void)lambda_in; (void)lambda_out; (void)stats;
-  return fail(KP_ERR_UNSUPPORTED, "kp_scd_sweep_batched is not built yet");
+  if (!ctx) return fail(KP_ERR_INVALID, "ctx is NULL");
+  if (n < 1 || !probs || !lambda_in || !lambda_out) return fail(KP_ERR_INVALID, "bad batch arguments");
+  Ctx *c = (Ctx *)ctx;
+  std::vector<Prepared> P(n);
+  for (int s = 0; s < n; ++s) {
+    kp_status st = prepare(&probs[s], true, P[s]);
+    if (st != KP_OK) {
+      std::string m = g_err;
+      return fail(st, "instance %d: %s", s, m.c_str());
+    }
+    if (!lambda_in[s] || !lambda_out[s]) return fail(KP_ERR_INVALID, "instance %d: lambda is NULL", s);
+  }
+  // blocks per instance, proportional to its tiles
+  int64_t T = 0;
+  int Kf = 0;
+  for (auto &p : P) { T += p.ntiles; Kf += p.pr.K; }
+  const int G = (int)std::max<int64_t>(n, std::min<int64_t>(T, kMaxGrid));
+  std::vector<int> boff(n + 1, 0), koff(n + 1, 0);
+  std::vector<size_t> poff(n + 1, 0);
+  size_t lds = 0;
+  for (int s = 0; s < n; ++s) {
+    int64_t b = T ? (int64_t)std::llround((double)G * P[s].ntiles / (double)T) : 1;
+    b = std::max<int64_t>(1, std::min<int64_t>(b, std::max<int64_t>(1, P[s].ntiles)));
+    boff[s + 1] = boff[s] + (int)b;
+    koff[s + 1] = koff[s] + P[s].pr.K;
+    poff[s + 1] = poff[s] + (size_t)b * (P[s].pr.K + 2);
+    lds = std::max(lds, kp_sweep_lds_bytes(P[s].U, P[s].pr.M, P[s].pr.K, true, P[s].pr.fmt));
+  }
+  const int GB = boff[n];
+  if (lds > kMaxLds) return fail(KP_ERR_UNSUPPORTED, "an instance needs too much LDS");
+  const uint32_t cap = kEmitCapBatched;
+  Carve cv;
+  const size_t o_desc0 = cv.take((size_t)n * sizeof(SweepArgs));
+  const size_t o_desc1 = cv.take((size_t)n * sizeof(SweepArgs));
+  const size_t o_geom = cv.take((size_t)n * sizeof(TileGeom));
+  const size_t o_boff = cv.take((size_t)(n + 1) * 4);
+  const size_t o_part = cv.take(poff[n] * 8);
+  const size_t o_B = cv.take((size_t)Kf * 8);
+  const size_t o_st = cv.take((size_t)Kf * sizeof(KState));
+  const size_t o_hs = cv.take((size_t)Kf * KP_NB * 8);
+  const size_t o_hc = cv.take((size_t)Kf * KP_NB * 4);
+  const size_t o_e1 = cv.take((size_t)Kf * cap * 8);
+  const size_t o_e2 = cv.take((size_t)Kf * cap * 8);
+  const size_t o_s1 = cv.take((size_t)GB * kStageCap * 8);
+  const size_t o_s2 = cv.take((size_t)GB * kStageCap * 8);
+  const size_t o_sk = cv.take((size_t)GB * kStageCap * 2);
+  const size_t o_err = cv.take(8);
+  const size_t o_pend = cv.take(8);
+  const size_t o_kin = cv.take((size_t)Kf * 4);
+  const size_t o_klo = cv.take((size_t)Kf * 4);
+  const size_t o_lin = cv.take((size_t)n * 8);
+  const size_t o_lout = cv.take((size_t)n * 8);
+  const size_t o_tab = cv.take((size_t)(Kf + 2 * n) * kp_coldesc_size());
+  const size_t o_stat = cv.take((size_t)(Kf + 2 * n) * 8);
+  kp_status st = ensure_ws(c, cv.off);
+  if (st != KP_OK) return st;
+  char *w = (char *)c->ws;
+  SweepArgs *d0 = (SweepArgs *)(w + o_desc0), *d1 = (SweepArgs *)(w + o_desc1);
+  KState *kst = (KState *)(w + o_st);
+  double *Bf = (double *)(w + o_B);
+  // host images of the tables
+  std::vector<SweepArgs> h0(n), h1(n);
+  std::vector<TileGeom> hg(n);
+  std::vector<double> hB(Kf);
+  std::vector<int> kin(Kf), klo(Kf);
+  std::vector<const double *> lin(n);
+  std::vector<double *> lout(n);
+  std::vector<unsigned char> tab((size_t)(Kf + 2 * n) * kp_coldesc_size());
+  double *stat_dst = stats ? stats : (double *)(w + o_stat);
+  size_t so = 0;
+  int ncol = 0;
+  for (int s = 0; s < n; ++s) {
+    const int K = P[s].pr.K, nb = boff[s + 1] - boff[s];
+    SweepArgs a;
+    memset(&a, 0, sizeof a);
+    a.pr = P[s].pr;
+    a.tree = P[s].tree;
+    a.lam = lambda_in[s];
+    a.ntiles = P[s].ntiles;
+    a.want_stats = 1;
+    a.partials = (double *)(w + o_part) + poff[s];
+    a.st = kst + koff[s];
+    a.hist_sum = (double *)(w + o_hs) + (size_t)koff[s] * KP_NB;
+    a.hist_cnt = (uint32_t *)(w + o_hc) + (size_t)koff[s] * KP_NB;
+    a.emit_v1 = (double *)(w + o_e1) + (size_t)koff[s] * cap;
+    a.emit_v2 = (double *)(w + o_e2) + (size_t)koff[s] * cap;
+    a.emit_cap = cap;
+    a.stage_v1 = (double *)(w + o_s1) + (size_t)boff[s] * kStageCap;
+    a.stage_v2 = (double *)(w + o_s2) + (size_t)boff[s] * kStageCap;
+    a.stage_k = (uint16_t *)(w + o_sk) + (size_t)boff[s] * kStageCap;
+    a.stage_cap = kStageCap;
+    a.err = (unsigned long long *)(w + o_err);
+    h0[s] = a;
+    a.want_stats = 0;
+    h1[s] = a;
+    hg[s] = kp_tile_geom(h0[s], P[s].U);
+    for (int k = 0; k < K; ++k) { hB[koff[s] + k] = P[s].B[k]; kin[koff[s] + k] = s; klo[koff[s] + k] = k; }
+    lin[s] = lambda_in[s];
+    lout[s] = lambda_out[s];
+    for (int col = 0; col < K + 2; ++col) {
+      kp_coldesc_fill(tab.data() + (size_t)ncol * kp_coldesc_size(), a.partials, lambda_in[s],
+                      Bf + koff[s], stat_dst + so + col, P[s].ntiles ? nb : 0, K, col);
+      ++ncol;
+    }
+    so += (size_t)K + 2;
+  }
+  HIP_TRY(hipMemcpyAsync(d0, h0.data(), (size_t)n * sizeof(SweepArgs), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(d1, h1.data(), (size_t)n * sizeof(SweepArgs), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(w + o_geom, hg.data(), (size_t)n * sizeof(TileGeom), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(w + o_boff, boff.data(), (size_t)(n + 1) * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(Bf, hB.data(), (size_t)Kf * 8, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(w + o_kin, kin.data(), (size_t)Kf * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(w + o_klo, klo.data(), (size_t)Kf * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(w + o_lin, lin.data(), (size_t)n * 8, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(w + o_lout, lout.data(), (size_t)n * 8, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(w + o_tab, tab.data(), tab.size(), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemsetAsync(w + o_hs, 0, (size_t)Kf * KP_NB * 8, c->stream));
+  HIP_TRY(hipMemsetAsync(w + o_hc, 0, (size_t)Kf * KP_NB * 4, c->stream));
+  HIP_TRY(hipMemsetAsync(w + o_err, 0, 8, c->stream));
+  HIP_TRY(kp_launch_batched_aux(1, nullptr, Kf, kst, w + o_lin, (int *)(w + o_kin), (int *)(w + o_klo),
+                                c->stream));
+  for (int pass = 0;; ++pass) {
+    if (pass >= kMaxPasses) return fail(KP_ERR_INTERNAL, "SCD threshold search exceeded %d passes", kMaxPasses);
+    if (T > 0)
+      HIP_TRY(kp_launch_sweep_batched(pass == 0 ? d0 : d1, (TileGeom *)(w + o_geom), (int *)(w + o_boff),
+                                      n, GB, lds, c->stream));
+    if (pass == 0) HIP_TRY(kp_launch_batched_aux(0, w + o_tab, ncol, nullptr, nullptr, nullptr, nullptr, c->stream));
+    HIP_TRY(kp_launch_scd_locate_select(kst, Kf, Bf, (double *)(w + o_hs), (uint32_t *)(w + o_hc),
+                                        (double *)(w + o_e1), (double *)(w + o_e2), cap,
+                                        (int *)(w + o_pend), c->stream));
+    HIP_TRY(hipMemcpyAsync(c->pinned, w + o_pend, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->pinned + 2, w + o_err, 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (*(unsigned long long *)(c->pinned + 2))
+      return fail(KP_ERR_INTERNAL, "breakpoint walk exceeded its event limit");
+    if (c->pinned[0] == 0) break;
+  }
+  HIP_TRY(kp_launch_batched_aux(2, nullptr, Kf, kst, w + o_lout, (int *)(w + o_kin), (int *)(w + o_klo),
+                                c->stream));
+  return KP_OK;
 }
 
 }  // extern "C"

@@ -19,6 +19,12 @@ struct TreeDev {
   int cap[KP_MAX_NODES];
 };
 
+struct TileGeom {
+  int U;            // users per tile
+  int M, K;
+  int aligned;      // dense costs: 16-byte aligned base and U*M*K % 4 == 0
+};
+
 struct ProbDev {
   int64_t N;
   int M, K, fmt, pad;

@@ -16,6 +16,7 @@
 // block order by a second kernel.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <string.h>
 #include "kp_internal.h"
 
 #define NT 256
@@ -42,11 +43,6 @@ __device__ __forceinline__ int exp_bucket(double v, double center, double delta)
   return d < 0.0 ? -id : id;
 }
 
-struct TileGeom {
-  int U;            // users per tile
-  int M, K;
-  int aligned;      // dense costs: 16-byte aligned base and U*M*K % 4 == 0
-};
 
 // Laminar-matroid greedy over the ranked items: accept an eligible item when
 // no node containing it is full.  Equivalent to Alg.1 (both return the unique
@@ -125,8 +121,8 @@ __device__ __forceinline__ void issue_entries(Prefetch &f, const ProbDev &pr, in
 }
 
 template <int FMT, bool SCD>
-__global__ void __launch_bounds__(NT) k_sweep(const SweepArgs a, const TileGeom g) {
-  extern __shared__ __align__(16) unsigned char smem[];
+__device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g, const int bid,
+                                           const int nblk, unsigned char *smem) {
   const int tid = threadIdx.x;
   const int M = g.M, K = g.K, U = g.U;
   const int R = U * M;             // item rows per tile
@@ -182,10 +178,23 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs a, const TileGeom 
     if (tid == 0) *nstage = 0u;
   }
   const int64_t N = a.pr.N;
+  if (SCD && !a.want_stats) {
+    __syncthreads();
+    __shared__ int busy;
+    if (tid == 0) busy = 0;
+    __syncthreads();
+    for (int t = tid; t < K; t += NT) {
+      const int m = kmode[t];
+      if (m == KS_EXP || m == KS_EMIT_BUCKET || m == KS_HULL_BUCKET || m == KS_REFINE || m == KS_EMIT_RANGE)
+        busy = 1;
+    }
+    __syncthreads();
+    if (!busy) return;
+  }
 
-  // ---- software pipeline: prefetch tile blockIdx.x ----
+  // ---- software pipeline: prefetch tile bid ----
   Prefetch f;
-  int64_t tile = blockIdx.x;
+  int64_t tile = bid;
   if (tile < a.ntiles) {
     const int64_t u0 = tile * (int64_t)U;
     const int nu = (int)((N - u0) < U ? (N - u0) : U);
@@ -197,7 +206,7 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs a, const TileGeom 
     }
   }
 
-  for (; tile < a.ntiles; tile += gridDim.x) {
+  for (; tile < a.ntiles; tile += nblk) {
     const int64_t u0 = tile * (int64_t)U;
     const int nu = (int)((N - u0) < U ? (N - u0) : U);     // users in this tile
     const int nr = nu * M;
@@ -245,7 +254,7 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs a, const TileGeom 
       for (int t = tid; t < R * K; t += NT) bt[t] = 0.0f;
     }
     // ---- issue the next tile's loads (they land during this tile's compute) ----
-    const int64_t ntile = tile + gridDim.x;
+    const int64_t ntile = tile + nblk;
     int64_t nu0 = 0;
     int nnr = 0;
     if (ntile < a.ntiles) {
@@ -512,7 +521,7 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs a, const TileGeom 
               if (emit) {
                 const uint32_t slot = atomicAdd(nstage, 1u);
                 if (slot < a.stage_cap) {
-                  const size_t e = (size_t)blockIdx.x * a.stage_cap + slot;
+                  const size_t e = (size_t)bid * a.stage_cap + slot;
                   a.stage_v1[e] = best;
                   a.stage_v2[e] = v2;
                   a.stage_k[e] = (uint16_t)k;
@@ -544,7 +553,7 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs a, const TileGeom 
   }
   __syncthreads();
   if (a.want_stats) {
-    for (int t = tid; t < K + 2; t += NT) a.partials[(size_t)blockIdx.x * (K + 2) + t] = acc[t];
+    for (int t = tid; t < K + 2; t += NT) a.partials[(size_t)bid * (K + 2) + t] = acc[t];
   }
   if (SCD) {
     for (int t = tid; t < K * KP_NB; t += NT) {
@@ -566,7 +575,7 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs a, const TileGeom 
     __syncthreads();
     const uint32_t ns = *nstage < a.stage_cap ? *nstage : a.stage_cap;
     for (uint32_t t = tid; t < ns; t += NT) {
-      const size_t e = (size_t)blockIdx.x * a.stage_cap + t;
+      const size_t e = (size_t)bid * a.stage_cap + t;
       const int k = a.stage_k[e];
       const uint32_t dst = kpos[k] + atomicAdd(&kcnt[k], 1u);
       if (dst < a.emit_cap) {
@@ -577,6 +586,44 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs a, const TileGeom 
       }
     }
   }
+}
+
+
+template <int FMT, bool SCD>
+__global__ void __launch_bounds__(NT) k_sweep(const SweepArgs a, const TileGeom g) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  sweep_body<FMT, SCD>(a, g, blockIdx.x, gridDim.x, smem);
+}
+
+// Batched: blocks [block_off[s], block_off[s+1]) work on instance s, whose
+// arguments are copied into LDS; one launch covers every instance.
+__global__ void __launch_bounds__(NT) k_sweep_batched(const SweepArgs *descs, const TileGeom *geoms,
+                                                      const int *block_off, int n_inst) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ SweepArgs sa;
+  __shared__ TileGeom sg;
+  __shared__ int inst;
+  if (threadIdx.x == 0) {
+    int lo = 0, hi = n_inst - 1;
+    while (lo < hi) {   // last s with block_off[s] <= blockIdx.x
+      const int mid = (lo + hi + 1) >> 1;
+      if (block_off[mid] <= (int)blockIdx.x) lo = mid; else hi = mid - 1;
+    }
+    inst = lo;
+  }
+  __syncthreads();
+  const int s = inst;
+  {
+    const int *src = (const int *)(descs + s);
+    int *dst = (int *)&sa;
+    for (int t = threadIdx.x; t < (int)(sizeof(SweepArgs) / 4); t += NT) dst[t] = src[t];
+    if (threadIdx.x == 0) sg = geoms[s];
+  }
+  __syncthreads();
+  const int bid = blockIdx.x - block_off[s];
+  const int nblk = block_off[s + 1] - block_off[s];
+  if (sa.pr.fmt == 0) sweep_body<0, true>(sa, sg, bid, nblk, smem);
+  else sweep_body<1, true>(sa, sg, bid, nblk, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -1258,6 +1305,114 @@ size_t kp_fixup_scratch_bytes(int64_t N, int nv, int K) {
   auto r = [](size_t b) { return (b + 255) & ~(size_t)255; };
   return r(nb * 4) * 2 + r((size_t)N * 8) * 2 + r((size_t)N * 4) * 2 + r(16 * nb * 4) * 2 +
          r((size_t)(nv > 0 ? nv : 1) * nb * 8) + r((size_t)1024 * (K + 1) * 8) + 512;
+}
+
+// ---------------------------------------------------------------------------
+// batched helpers: statistics by column table, flat per-(instance, k) init
+// and finish
+// ---------------------------------------------------------------------------
+struct ColDesc {
+  const double *partials;  // [nblk][K + 2] of the instance
+  const double *lam;       // [K]
+  const double *B;         // [K]
+  double *out;             // destination of this column
+  int nblk, K, col, pad;
+};
+
+__global__ void __launch_bounds__(256) k_reduce_stats_tab(const ColDesc *tab) {
+  __shared__ double red[256];
+  const ColDesc d = tab[blockIdx.x];
+  const int t = threadIdx.x;
+  double s = 0.0;
+  for (int b = t; b < d.nblk; b += 256) s = s + d.partials[(size_t)b * (d.K + 2) + d.col];
+  red[t] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) red[t] = red[t] + red[t + w];
+    __syncthreads();
+  }
+  if (t != 0) return;
+  s = red[0];
+  if (d.col == d.K) {
+    for (int k = 0; k < d.K; ++k) { const double lb = d.lam[k] * d.B[k]; s = s + lb; }
+  }
+  *d.out = s;
+}
+
+__global__ void k_scd_init_flat(KState *st, int Kf, const double *const *lam_in, const int *kinst,
+                                const int *klocal) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= Kf) return;
+  const double l = lam_in[kinst[f]][klocal[f]];
+  KState s;
+  s.mode = KS_EXP;
+  s.bstar = 0;
+  s.shift = 0;
+  s.overflow = 0;
+  s.n_emit = 0;
+  s.pad = 0;
+  s.center = l;
+  const double base = l > 0x1p-20 ? l : 0x1p-20;
+  s.delta = ldexp(1.0, ilogb(base) - 10);
+  s.F_above = 0.0;
+  s.result = l;
+  s.klo = 0;
+  s.khi = ~0ull;
+  s.hull_lo = ~0ull;
+  s.hull_hi = 0;
+  st[f] = s;
+}
+
+__global__ void k_scd_finish_flat(const KState *st, int Kf, double *const *lam_out, const int *kinst,
+                                  const int *klocal) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= Kf) return;
+  lam_out[kinst[f]][klocal[f]] = st[f].result;
+}
+
+hipError_t kp_launch_sweep_batched(const SweepArgs *descs, const TileGeom *geoms, const int *block_off,
+                                   int n_inst, int total_blocks, size_t lds, hipStream_t stream) {
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void *)k_sweep_batched,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_sweep_batched, dim3(total_blocks), dim3(NT), lds, stream, descs, geoms,
+                     block_off, n_inst);
+  return hipGetLastError();
+}
+
+hipError_t kp_launch_batched_aux(int which, const void *tab, int n, KState *st, const void *lam_ptrs,
+                                 const int *kinst, const int *klocal, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  if (which == 0) {
+    hipLaunchKernelGGL(k_reduce_stats_tab, dim3(n), dim3(256), 0, stream, (const ColDesc *)tab);
+  } else if (which == 1) {
+    hipLaunchKernelGGL(k_scd_init_flat, dim3((n + 63) / 64), dim3(64), 0, stream, st, n,
+                       (const double *const *)lam_ptrs, kinst, klocal);
+  } else {
+    hipLaunchKernelGGL(k_scd_finish_flat, dim3((n + 63) / 64), dim3(64), 0, stream, (const KState *)st,
+                       n, (double *const *)lam_ptrs, kinst, klocal);
+  }
+  return hipGetLastError();
+}
+
+TileGeom kp_tile_geom(const SweepArgs &a, int U) {
+  TileGeom g;
+  g.U = U;
+  g.M = a.pr.M;
+  g.K = a.pr.K;
+  g.aligned = a.pr.fmt == 0 && ((uintptr_t)a.pr.b & 15) == 0 && (((int64_t)U * g.M * g.K) & 3) == 0;
+  return g;
+}
+
+size_t kp_coldesc_size() { return sizeof(ColDesc); }
+void kp_coldesc_fill(void *dst, const double *partials, const double *lam, const double *B, double *out,
+                     int nblk, int K, int col) {
+  ColDesc d;
+  d.partials = partials; d.lam = lam; d.B = B; d.out = out;
+  d.nblk = nblk; d.K = K; d.col = col; d.pad = 0;
+  memcpy(dst, &d, sizeof d);
 }
 
 // ---------------------------------------------------------------------------

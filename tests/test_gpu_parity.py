@@ -236,3 +236,28 @@ def test_solve_to_gap_c1():
     # same iterates: the multipliers are bit-exact at every step
     for a, b in zip(hist, ref):
         assert np.array_equal(a["lam"], b["lam"])
+
+
+@gpu
+def test_batched_sweep_parity():
+    """Ragged batch (uneven N, M, K, Q): one launch per pass; every
+    instance's lambda^{t+1} and statistics equal the oracle's."""
+    kp, torch = _kp()
+    insts = kpgen.batched_instances(run=0, n=24, max_N=2500)
+    probs = [kp.Problem.from_host(i) for i in insts]
+    lams = [np.zeros(i.K) for i in insts]
+    for t in range(2):
+        outs, stats = kp.kp_scd_sweep_batched(probs, [_lamd(torch, l) for l in lams])
+        stats = stats.cpu().numpy()
+        off = 0
+        for s, inst in enumerate(insts):
+            want = oracle.scd_sweep(inst, lams[s])
+            got = outs[s].cpu().numpy()
+            assert np.array_equal(got, want), (t, s, got, want)
+            ref = oracle.eval_dual(inst, lams[s], want_x=False)
+            K = inst.K
+            assert np.array_equal(stats[off:off + K], ref["R"])
+            assert abs(stats[off + K] - ref["g"]) <= REL * max(1.0, abs(ref["g"]))
+            assert abs(stats[off + K + 1] - ref["P"]) <= REL * max(1.0, abs(ref["P"]))
+            off += K + 2
+            lams[s] = want
