@@ -149,6 +149,23 @@ kp_status kp_scd_sweep_batched(void *ctx, const kp_problem *probs, int32_t n,
                                const double *const *lambda_in, double *const *lambda_out,
                                double *stats);
 
+/* Batched plan for repeated iterations: validates the instances and builds
+   the device tables once for two multiplier buffers per instance, lam_a[s]
+   and lam_b[s] (HOST arrays of n DEV pointers, each [K_s]).
+   kp_batched_step(plan, dir, stats, use_graph) runs one SCD iteration from
+   lam_a into lam_b (dir 0) or from lam_b into lam_a (dir 1); stats as in
+   kp_scd_sweep_batched (DEV, may be NULL).  With use_graph != 0 the first
+   pass of the iteration (init, sweep, statistics, threshold search, update)
+   is captured once per direction as a HIP graph and replayed; further
+   refinement passes, when a threshold is not resolved in the first pass, run
+   eagerly.  The plan borrows the context's stream and owns its workspace;
+   the caller keeps the instances' buffers alive until kp_batched_destroy.
+   Synchronises the stream at the end of every step. */
+kp_status kp_batched_create(void *ctx, const kp_problem *probs, int32_t n,
+                            const double *const *lam_a, double *const *lam_b, void **plan_out);
+kp_status kp_batched_step(void *plan, int32_t dir, double *stats, int32_t use_graph);
+kp_status kp_batched_destroy(void *plan);
+
 /* Optional full pass over p and b: KP_ERR_NONFINITE / KP_ERR_NEGATIVE if any
    value is NaN/Inf or negative, KP_OK otherwise (a CSR column outside [0,K) or
    not ascending is KP_ERR_INVALID).  Synchronises the context stream. */

@@ -59,7 +59,8 @@ _lib = None
 EXPORTS = ["kp_last_error", "kp_create", "kp_destroy", "kp_set_stream", "kp_eval_dual",
            "kp_scd_sweep", "kp_scd_sweep_masked", "kp_dd_step", "kp_dual_backward",
            "kp_primal_fixup", "kp_scd_sweep_batched", "kp_validate_inputs", "kp_tree_from_sets",
-           "kp_max_items", "kp_max_knapsacks_scd", "kp_set_timing", "kp_get_timing"]
+           "kp_max_items", "kp_max_knapsacks_scd", "kp_set_timing", "kp_get_timing",
+           "kp_batched_create", "kp_batched_step", "kp_batched_destroy"]
 
 
 def lib():
@@ -84,6 +85,9 @@ def lib():
         L.kp_scd_sweep_batched.argtypes = [vp, P, i32, vp, vp, vp]
         L.kp_validate_inputs.argtypes = [vp, P]
         L.kp_tree_from_sets.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp]
+        L.kp_batched_create.argtypes = [vp, P, i32, vp, vp, ctypes.POINTER(vp)]
+        L.kp_batched_step.argtypes = [vp, i32, vp, i32]
+        L.kp_batched_destroy.argtypes = [vp]
         L.kp_set_timing.argtypes = [vp, i32]
         L.kp_get_timing.argtypes = [vp, vp, vp, vp]
         L.kp_max_items.restype = i32
@@ -275,6 +279,56 @@ def kp_scd_sweep_batched(probs: Sequence[Problem], lams_in, lams_out=None,
     stats = _dev_f64(sum(pr.K + 2 for pr in probs))
     _check(lib().kp_scd_sweep_batched(ctx.h, arr, n, pin, pout, _ptr(stats)))
     return lams_out, stats
+
+
+class BatchedSCD:
+    """Repeated SCD iterations over a batch of instances: device tables built
+    once, each iteration's first pass replayed from a captured HIP graph."""
+
+    def __init__(self, probs: Sequence[Problem], lam0=None, use_graph: bool = True,
+                 ctx: Optional[Context] = None):
+        import torch
+        # graph capture needs a stream other than the legacy default stream
+        self.stream = torch.cuda.Stream()
+        with torch.cuda.stream(self.stream):
+            self.ctx = ctx or Context()
+        self.probs = list(probs)
+        n = len(self.probs)
+        self.a = [torch.zeros(pr.K, dtype=torch.float64, device="cuda") if lam0 is None
+                  else torch.as_tensor(np.asarray(lam0[s], np.float64)).to("cuda").clone()
+                  for s, pr in enumerate(self.probs)]
+        self.b = [torch.zeros(pr.K, dtype=torch.float64, device="cuda") for pr in self.probs]
+        self.use_graph = use_graph
+        self.dir = 0
+        torch.cuda.synchronize()   # buffers made on other streams are ready
+        arr = (kp_problem * n)(*[pr.s for pr in self.probs])
+        pa = (ctypes.c_void_p * n)(*[t.data_ptr() for t in self.a])
+        pb = (ctypes.c_void_p * n)(*[t.data_ptr() for t in self.b])
+        self.h = ctypes.c_void_p()
+        _check(lib().kp_batched_create(self.ctx.h, arr, n, pa, pb, ctypes.byref(self.h)))
+        self.stats = _dev_f64(sum(pr.K + 2 for pr in self.probs))
+
+    @property
+    def lam(self):
+        """Current multipliers (the buffer the last step wrote)."""
+        return self.a if self.dir == 0 else self.b
+
+    def step(self):
+        """One iteration; returns (new lambdas, stats at the old lambdas)."""
+        _check(lib().kp_batched_step(self.h, self.dir, _ptr(self.stats), 1 if self.use_graph else 0))
+        self.dir ^= 1
+        return self.lam, self.stats
+
+    def close(self):
+        if self.h:
+            lib().kp_batched_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def kp_validate_inputs(prob: Problem, ctx: Optional[Context] = None):

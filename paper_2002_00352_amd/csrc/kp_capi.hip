@@ -751,12 +751,92 @@ kp_status kp_primal_fixup(void *ctx, const kp_problem *prob, const double *lambd
   return KP_OK;
 }
 
-kp_status kp_scd_sweep_batched(void *ctx, const kp_problem *probs, int32_t n,
-                               const double *const *lambda_in, double *const *lambda_out,
-                               double *stats) {
-  if (!ctx) return fail(KP_ERR_INVALID, "ctx is NULL");
-  if (n < 1 || !probs || !lambda_in || !lambda_out) return fail(KP_ERR_INVALID, "bad batch arguments");
-  Ctx *c = (Ctx *)ctx;
+// ---- batched plan: tables built once, one iteration replayable as a graph ----
+struct BatchPlan {
+  Ctx *c = nullptr;
+  int n = 0, Kf = 0, GB = 0, ncol = 0;
+  int64_t T = 0;
+  size_t lds = 0;
+  uint32_t cap = 0;
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+  // device tables
+  SweepArgs *d[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [dir][first pass?]
+  TileGeom *geom = nullptr;
+  int *boff = nullptr, *kin = nullptr, *klo = nullptr, *pend = nullptr;
+  void *lam_tab[2] = {nullptr, nullptr};   // [dir]: lambda_in pointer table; the other dir's is lambda_out
+  void *coltab[2] = {nullptr, nullptr};    // [dir]: statistics column table (reads lambda_in)
+  KState *kst = nullptr;
+  double *Bf = nullptr, *hs = nullptr, *e1 = nullptr, *e2 = nullptr, *stats = nullptr;
+  uint32_t *hc = nullptr;
+  unsigned long long *err = nullptr;
+  int *pinned = nullptr;
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+};
+
+kp_status plan_first_pass(BatchPlan *p, int dir, hipStream_t s) {
+  HIP_TRY(kp_launch_batched_aux(1, nullptr, p->Kf, p->kst, p->lam_tab[dir], p->kin, p->klo, s));
+  if (p->T > 0) HIP_TRY(kp_launch_sweep_batched(p->d[dir][1], p->geom, p->boff, p->n, p->GB, p->lds, s));
+  HIP_TRY(kp_launch_batched_aux(0, p->coltab[dir], p->ncol, nullptr, nullptr, nullptr, nullptr, s));
+  HIP_TRY(kp_launch_scd_locate_select(p->kst, p->Kf, p->Bf, p->hs, p->hc, p->e1, p->e2, p->cap, p->pend, s));
+  HIP_TRY(kp_launch_batched_aux(2, nullptr, p->Kf, p->kst, p->lam_tab[1 - dir], p->kin, p->klo, s));
+  HIP_TRY(hipMemcpyAsync(p->pinned, p->pend, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(p->pinned + 2, p->err, 8, hipMemcpyDeviceToHost, s));
+  return KP_OK;
+}
+
+kp_status plan_step(BatchPlan *p, int dir, double *stats_out, bool graph) {
+  hipStream_t s = p->c->stream;
+  if (graph) {
+    if (!p->exec[dir]) {
+      HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      kp_status st = plan_first_pass(p, dir, s);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(s, &g);
+      if (st != KP_OK) return st;
+      if (e != hipSuccess) return fail(KP_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
+      p->graph[dir] = g;
+      HIP_TRY(hipGraphInstantiate(&p->exec[dir], g, nullptr, nullptr, 0));
+    }
+    HIP_TRY(hipGraphLaunch(p->exec[dir], s));
+  } else {
+    kp_status st = plan_first_pass(p, dir, s);
+    if (st != KP_OK) return st;
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int pass = 1;; ++pass) {
+    if (*(unsigned long long *)(p->pinned + 2))
+      return fail(KP_ERR_INTERNAL, "breakpoint walk exceeded its event limit");
+    if (p->pinned[0] == 0) break;
+    if (pass >= kMaxPasses) return fail(KP_ERR_INTERNAL, "SCD threshold search exceeded %d passes", kMaxPasses);
+    if (p->T > 0) HIP_TRY(kp_launch_sweep_batched(p->d[dir][0], p->geom, p->boff, p->n, p->GB, p->lds, s));
+    HIP_TRY(kp_launch_scd_locate_select(p->kst, p->Kf, p->Bf, p->hs, p->hc, p->e1, p->e2, p->cap, p->pend, s));
+    HIP_TRY(kp_launch_batched_aux(2, nullptr, p->Kf, p->kst, p->lam_tab[1 - dir], p->kin, p->klo, s));
+    HIP_TRY(hipMemcpyAsync(p->pinned, p->pend, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(p->pinned + 2, p->err, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  if (stats_out)
+    HIP_TRY(hipMemcpyAsync(stats_out, p->stats, (size_t)p->ncol * 8, hipMemcpyDeviceToDevice, s));
+  return KP_OK;
+}
+
+void plan_free(BatchPlan *p) {
+  if (!p) return;
+  if (p->c) (void)hipStreamSynchronize(p->c->stream);
+  for (int d = 0; d < 2; ++d) {
+    if (p->exec[d]) (void)hipGraphExecDestroy(p->exec[d]);
+    if (p->graph[d]) (void)hipGraphDestroy(p->graph[d]);
+  }
+  if (p->ws) (void)hipFree(p->ws);
+  if (p->pinned) (void)hipHostFree(p->pinned);
+  delete p;
+}
+
+kp_status plan_create(Ctx *c, const kp_problem *probs, int n, const double *const *lam_a,
+                      double *const *lam_b, BatchPlan **out) {
+  if (n < 1 || !probs || !lam_a || !lam_b) return fail(KP_ERR_INVALID, "bad batch arguments");
   std::vector<Prepared> P(n);
   for (int s = 0; s < n; ++s) {
     kp_status st = prepare(&probs[s], true, P[s]);
@@ -764,12 +844,14 @@ kp_status kp_scd_sweep_batched(void *ctx, const kp_problem *probs, int32_t n,
       std::string m = g_err;
       return fail(st, "instance %d: %s", s, m.c_str());
     }
-    if (!lambda_in[s] || !lambda_out[s]) return fail(KP_ERR_INVALID, "instance %d: lambda is NULL", s);
+    if (!lam_a[s] || !lam_b[s]) return fail(KP_ERR_INVALID, "instance %d: lambda is NULL", s);
   }
-  // blocks per instance, proportional to its tiles
+  BatchPlan *p = new BatchPlan();
+  p->c = c;
+  p->n = n;
   int64_t T = 0;
   int Kf = 0;
-  for (auto &p : P) { T += p.ntiles; Kf += p.pr.K; }
+  for (auto &q : P) { T += q.ntiles; Kf += q.pr.K; }
   const int G = (int)std::max<int64_t>(n, std::min<int64_t>(T, kMaxGrid));
   std::vector<int> boff(n + 1, 0), koff(n + 1, 0);
   std::vector<size_t> poff(n + 1, 0);
@@ -782,12 +864,14 @@ kp_status kp_scd_sweep_batched(void *ctx, const kp_problem *probs, int32_t n,
     poff[s + 1] = poff[s] + (size_t)b * (P[s].pr.K + 2);
     lds = std::max(lds, kp_sweep_lds_bytes(P[s].U, P[s].pr.M, P[s].pr.K, true, P[s].pr.fmt));
   }
-  const int GB = boff[n];
-  if (lds > kMaxLds) return fail(KP_ERR_UNSUPPORTED, "an instance needs too much LDS");
-  const uint32_t cap = kEmitCapBatched;
+  if (lds > kMaxLds) { plan_free(p); return fail(KP_ERR_UNSUPPORTED, "an instance needs too much LDS"); }
+  p->T = T; p->Kf = Kf; p->GB = boff[n]; p->lds = lds; p->cap = kEmitCapBatched;
+  const uint32_t cap = p->cap;
+  const int ncol = Kf + 2 * n;
+  p->ncol = ncol;
   Carve cv;
-  const size_t o_desc0 = cv.take((size_t)n * sizeof(SweepArgs));
-  const size_t o_desc1 = cv.take((size_t)n * sizeof(SweepArgs));
+  size_t o_d[2][2];
+  for (int d = 0; d < 2; ++d) for (int f = 0; f < 2; ++f) o_d[d][f] = cv.take((size_t)n * sizeof(SweepArgs));
   const size_t o_geom = cv.take((size_t)n * sizeof(TileGeom));
   const size_t o_boff = cv.take((size_t)(n + 1) * 4);
   const size_t o_part = cv.take(poff[n] * 8);
@@ -797,103 +881,157 @@ kp_status kp_scd_sweep_batched(void *ctx, const kp_problem *probs, int32_t n,
   const size_t o_hc = cv.take((size_t)Kf * KP_NB * 4);
   const size_t o_e1 = cv.take((size_t)Kf * cap * 8);
   const size_t o_e2 = cv.take((size_t)Kf * cap * 8);
-  const size_t o_s1 = cv.take((size_t)GB * kStageCap * 8);
-  const size_t o_s2 = cv.take((size_t)GB * kStageCap * 8);
-  const size_t o_sk = cv.take((size_t)GB * kStageCap * 2);
+  const size_t o_s1 = cv.take((size_t)p->GB * kStageCap * 8);
+  const size_t o_s2 = cv.take((size_t)p->GB * kStageCap * 8);
+  const size_t o_sk = cv.take((size_t)p->GB * kStageCap * 2);
   const size_t o_err = cv.take(8);
   const size_t o_pend = cv.take(8);
   const size_t o_kin = cv.take((size_t)Kf * 4);
   const size_t o_klo = cv.take((size_t)Kf * 4);
-  const size_t o_lin = cv.take((size_t)n * 8);
-  const size_t o_lout = cv.take((size_t)n * 8);
-  const size_t o_tab = cv.take((size_t)(Kf + 2 * n) * kp_coldesc_size());
-  const size_t o_stat = cv.take((size_t)(Kf + 2 * n) * 8);
-  kp_status st = ensure_ws(c, cv.off);
-  if (st != KP_OK) return st;
-  char *w = (char *)c->ws;
-  SweepArgs *d0 = (SweepArgs *)(w + o_desc0), *d1 = (SweepArgs *)(w + o_desc1);
-  KState *kst = (KState *)(w + o_st);
-  double *Bf = (double *)(w + o_B);
-  // host images of the tables
-  std::vector<SweepArgs> h0(n), h1(n);
+  const size_t o_lt0 = cv.take((size_t)n * 8);
+  const size_t o_lt1 = cv.take((size_t)n * 8);
+  const size_t o_tab0 = cv.take((size_t)ncol * kp_coldesc_size());
+  const size_t o_tab1 = cv.take((size_t)ncol * kp_coldesc_size());
+  const size_t o_stat = cv.take((size_t)ncol * 8);
+  if (c->max_ws && cv.off > c->max_ws) {
+    plan_free(p);
+    return fail(KP_ERR_NOMEM, "batched plan needs %zu bytes, above the context cap", cv.off);
+  }
+  if (hipMalloc(&p->ws, cv.off) != hipSuccess) {
+    p->ws = nullptr;
+    plan_free(p);
+    return fail(KP_ERR_NOMEM, "hipMalloc of %zu plan bytes failed", cv.off);
+  }
+  if (hipHostMalloc((void **)&p->pinned, 64, hipHostMallocDefault) != hipSuccess) {
+    p->pinned = nullptr;
+    plan_free(p);
+    return fail(KP_ERR_HIP, "hipHostMalloc failed");
+  }
+  p->ws_bytes = cv.off;
+  char *w = (char *)p->ws;
+  for (int d = 0; d < 2; ++d) for (int f = 0; f < 2; ++f) p->d[d][f] = (SweepArgs *)(w + o_d[d][f]);
+  p->geom = (TileGeom *)(w + o_geom);
+  p->boff = (int *)(w + o_boff);
+  p->kst = (KState *)(w + o_st);
+  p->Bf = (double *)(w + o_B);
+  p->hs = (double *)(w + o_hs);
+  p->hc = (uint32_t *)(w + o_hc);
+  p->e1 = (double *)(w + o_e1);
+  p->e2 = (double *)(w + o_e2);
+  p->err = (unsigned long long *)(w + o_err);
+  p->pend = (int *)(w + o_pend);
+  p->kin = (int *)(w + o_kin);
+  p->klo = (int *)(w + o_klo);
+  p->lam_tab[0] = w + o_lt0;
+  p->lam_tab[1] = w + o_lt1;
+  p->coltab[0] = w + o_tab0;
+  p->coltab[1] = w + o_tab1;
+  p->stats = (double *)(w + o_stat);
+  std::vector<SweepArgs> hd[2][2];
+  for (int d = 0; d < 2; ++d) for (int f = 0; f < 2; ++f) hd[d][f].resize(n);
   std::vector<TileGeom> hg(n);
   std::vector<double> hB(Kf);
   std::vector<int> kin(Kf), klo(Kf);
-  std::vector<const double *> lin(n);
-  std::vector<double *> lout(n);
-  std::vector<unsigned char> tab((size_t)(Kf + 2 * n) * kp_coldesc_size());
-  double *stat_dst = stats ? stats : (double *)(w + o_stat);
+  std::vector<const double *> lt0(n), lt1(n);
+  std::vector<unsigned char> tab0((size_t)ncol * kp_coldesc_size()), tab1(tab0.size());
   size_t so = 0;
-  int ncol = 0;
+  int col_i = 0;
   for (int s = 0; s < n; ++s) {
     const int K = P[s].pr.K, nb = boff[s + 1] - boff[s];
     SweepArgs a;
     memset(&a, 0, sizeof a);
     a.pr = P[s].pr;
     a.tree = P[s].tree;
-    a.lam = lambda_in[s];
     a.ntiles = P[s].ntiles;
-    a.want_stats = 1;
     a.partials = (double *)(w + o_part) + poff[s];
-    a.st = kst + koff[s];
-    a.hist_sum = (double *)(w + o_hs) + (size_t)koff[s] * KP_NB;
-    a.hist_cnt = (uint32_t *)(w + o_hc) + (size_t)koff[s] * KP_NB;
-    a.emit_v1 = (double *)(w + o_e1) + (size_t)koff[s] * cap;
-    a.emit_v2 = (double *)(w + o_e2) + (size_t)koff[s] * cap;
+    a.st = p->kst + koff[s];
+    a.hist_sum = p->hs + (size_t)koff[s] * KP_NB;
+    a.hist_cnt = p->hc + (size_t)koff[s] * KP_NB;
+    a.emit_v1 = p->e1 + (size_t)koff[s] * cap;
+    a.emit_v2 = p->e2 + (size_t)koff[s] * cap;
     a.emit_cap = cap;
     a.stage_v1 = (double *)(w + o_s1) + (size_t)boff[s] * kStageCap;
     a.stage_v2 = (double *)(w + o_s2) + (size_t)boff[s] * kStageCap;
     a.stage_k = (uint16_t *)(w + o_sk) + (size_t)boff[s] * kStageCap;
     a.stage_cap = kStageCap;
-    a.err = (unsigned long long *)(w + o_err);
-    h0[s] = a;
-    a.want_stats = 0;
-    h1[s] = a;
-    hg[s] = kp_tile_geom(h0[s], P[s].U);
+    a.err = p->err;
+    for (int d = 0; d < 2; ++d) {
+      a.lam = d == 0 ? lam_a[s] : lam_b[s];
+      a.want_stats = 1;
+      hd[d][1][s] = a;
+      a.want_stats = 0;
+      hd[d][0][s] = a;
+    }
+    hg[s] = kp_tile_geom(hd[0][1][s], P[s].U);
     for (int k = 0; k < K; ++k) { hB[koff[s] + k] = P[s].B[k]; kin[koff[s] + k] = s; klo[koff[s] + k] = k; }
-    lin[s] = lambda_in[s];
-    lout[s] = lambda_out[s];
-    for (int col = 0; col < K + 2; ++col) {
-      kp_coldesc_fill(tab.data() + (size_t)ncol * kp_coldesc_size(), a.partials, lambda_in[s],
-                      Bf + koff[s], stat_dst + so + col, P[s].ntiles ? nb : 0, K, col);
-      ++ncol;
+    lt0[s] = lam_a[s];
+    lt1[s] = lam_b[s];
+    // statistics of the first pass are at the direction's input lambda
+    for (int cc = 0; cc < K + 2; ++cc) {
+      kp_coldesc_fill(tab0.data() + (size_t)col_i * kp_coldesc_size(), hd[0][1][s].partials, lam_a[s],
+                      p->Bf + koff[s], p->stats + so + cc, P[s].ntiles ? nb : 0, K, cc);
+      kp_coldesc_fill(tab1.data() + (size_t)col_i * kp_coldesc_size(), hd[0][1][s].partials, lam_b[s],
+                      p->Bf + koff[s], p->stats + so + cc, P[s].ntiles ? nb : 0, K, cc);
+      ++col_i;
     }
     so += (size_t)K + 2;
   }
-  HIP_TRY(hipMemcpyAsync(d0, h0.data(), (size_t)n * sizeof(SweepArgs), hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(hipMemcpyAsync(d1, h1.data(), (size_t)n * sizeof(SweepArgs), hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(hipMemcpyAsync(w + o_geom, hg.data(), (size_t)n * sizeof(TileGeom), hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(hipMemcpyAsync(w + o_boff, boff.data(), (size_t)(n + 1) * 4, hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(hipMemcpyAsync(Bf, hB.data(), (size_t)Kf * 8, hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(hipMemcpyAsync(w + o_kin, kin.data(), (size_t)Kf * 4, hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(hipMemcpyAsync(w + o_klo, klo.data(), (size_t)Kf * 4, hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(hipMemcpyAsync(w + o_lin, lin.data(), (size_t)n * 8, hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(hipMemcpyAsync(w + o_lout, lout.data(), (size_t)n * 8, hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(hipMemcpyAsync(w + o_tab, tab.data(), tab.size(), hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(hipMemsetAsync(w + o_hs, 0, (size_t)Kf * KP_NB * 8, c->stream));
-  HIP_TRY(hipMemsetAsync(w + o_hc, 0, (size_t)Kf * KP_NB * 4, c->stream));
-  HIP_TRY(hipMemsetAsync(w + o_err, 0, 8, c->stream));
-  HIP_TRY(kp_launch_batched_aux(1, nullptr, Kf, kst, w + o_lin, (int *)(w + o_kin), (int *)(w + o_klo),
-                                c->stream));
-  for (int pass = 0;; ++pass) {
-    if (pass >= kMaxPasses) return fail(KP_ERR_INTERNAL, "SCD threshold search exceeded %d passes", kMaxPasses);
-    if (T > 0)
-      HIP_TRY(kp_launch_sweep_batched(pass == 0 ? d0 : d1, (TileGeom *)(w + o_geom), (int *)(w + o_boff),
-                                      n, GB, lds, c->stream));
-    if (pass == 0) HIP_TRY(kp_launch_batched_aux(0, w + o_tab, ncol, nullptr, nullptr, nullptr, nullptr, c->stream));
-    HIP_TRY(kp_launch_scd_locate_select(kst, Kf, Bf, (double *)(w + o_hs), (uint32_t *)(w + o_hc),
-                                        (double *)(w + o_e1), (double *)(w + o_e2), cap,
-                                        (int *)(w + o_pend), c->stream));
-    HIP_TRY(hipMemcpyAsync(c->pinned, w + o_pend, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipMemcpyAsync(c->pinned + 2, w + o_err, 8, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    if (*(unsigned long long *)(c->pinned + 2))
-      return fail(KP_ERR_INTERNAL, "breakpoint walk exceeded its event limit");
-    if (c->pinned[0] == 0) break;
+  hipStream_t st = c->stream;
+  auto up = [&](void *dst, const void *src, size_t bytes) { return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st); };
+  hipError_t e = hipSuccess;
+  for (int d = 0; d < 2 && e == hipSuccess; ++d)
+    for (int f = 0; f < 2 && e == hipSuccess; ++f) e = up(p->d[d][f], hd[d][f].data(), (size_t)n * sizeof(SweepArgs));
+  if (e == hipSuccess) e = up(p->geom, hg.data(), (size_t)n * sizeof(TileGeom));
+  if (e == hipSuccess) e = up(p->boff, boff.data(), (size_t)(n + 1) * 4);
+  if (e == hipSuccess) e = up(p->Bf, hB.data(), (size_t)Kf * 8);
+  if (e == hipSuccess) e = up(p->kin, kin.data(), (size_t)Kf * 4);
+  if (e == hipSuccess) e = up(p->klo, klo.data(), (size_t)Kf * 4);
+  if (e == hipSuccess) e = up(p->lam_tab[0], lt0.data(), (size_t)n * 8);
+  if (e == hipSuccess) e = up(p->lam_tab[1], lt1.data(), (size_t)n * 8);
+  if (e == hipSuccess) e = up(p->coltab[0], tab0.data(), tab0.size());
+  if (e == hipSuccess) e = up(p->coltab[1], tab1.data(), tab1.size());
+  if (e == hipSuccess) e = hipMemsetAsync(p->hs, 0, (size_t)Kf * KP_NB * 8, st);
+  if (e == hipSuccess) e = hipMemsetAsync(p->hc, 0, (size_t)Kf * KP_NB * 4, st);
+  if (e == hipSuccess) e = hipMemsetAsync(p->err, 0, 8, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);   // host tables go out of scope
+  if (e != hipSuccess) {
+    plan_free(p);
+    return fail(KP_ERR_HIP, "plan upload failed: %s", hipGetErrorString(e));
   }
-  HIP_TRY(kp_launch_batched_aux(2, nullptr, Kf, kst, w + o_lout, (int *)(w + o_kin), (int *)(w + o_klo),
-                                c->stream));
+  *out = p;
   return KP_OK;
+}
+
+kp_status kp_batched_create(void *ctx, const kp_problem *probs, int32_t n, const double *const *lam_a,
+                            double *const *lam_b, void **plan_out) {
+  if (!ctx || !plan_out) return fail(KP_ERR_INVALID, "NULL argument");
+  BatchPlan *p = nullptr;
+  kp_status st = plan_create((Ctx *)ctx, probs, n, lam_a, lam_b, &p);
+  if (st != KP_OK) return st;
+  *plan_out = p;
+  return KP_OK;
+}
+
+kp_status kp_batched_step(void *plan, int32_t dir, double *stats, int32_t use_graph) {
+  if (!plan || (dir != 0 && dir != 1)) return fail(KP_ERR_INVALID, "bad plan or direction");
+  return plan_step((BatchPlan *)plan, dir, stats, use_graph != 0);
+}
+
+kp_status kp_batched_destroy(void *plan) {
+  plan_free((BatchPlan *)plan);
+  return KP_OK;
+}
+
+kp_status kp_scd_sweep_batched(void *ctx, const kp_problem *probs, int32_t n,
+                               const double *const *lambda_in, double *const *lambda_out,
+                               double *stats) {
+  if (!ctx) return fail(KP_ERR_INVALID, "ctx is NULL");
+  BatchPlan *p = nullptr;
+  kp_status st = plan_create((Ctx *)ctx, probs, n, lambda_in, lambda_out, &p);
+  if (st != KP_OK) return st;
+  st = plan_step(p, 0, stats, false);
+  plan_free(p);
+  return st;
 }
 
 }  // extern "C"

@@ -261,3 +261,24 @@ def test_batched_sweep_parity():
             assert abs(stats[off + K + 1] - ref["P"]) <= REL * max(1.0, abs(ref["P"]))
             off += K + 2
             lams[s] = want
+
+
+@gpu
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batched_plan_graph_replays(use_graph):
+    """A batched plan stepped several times (graph replays alternating the
+    two multiplier buffers, with host work in between) follows the oracle's
+    SCD trajectory for every instance at every step."""
+    kp, torch = _kp()
+    insts = kpgen.batched_instances(run=1, n=12, max_N=2000)
+    probs = [kp.Problem.from_host(i) for i in insts]
+    plan = kp.BatchedSCD(probs, use_graph=use_graph)
+    lams = [np.zeros(i.K) for i in insts]
+    for t in range(4):
+        outs, stats = plan.step()
+        torch.cuda.synchronize()
+        for s, inst in enumerate(insts):
+            want = oracle.scd_sweep(inst, lams[s])
+            assert np.array_equal(outs[s].cpu().numpy(), want), (use_graph, t, s)
+            lams[s] = want
+    plan.close()
