@@ -193,6 +193,14 @@ kp_status kp_set_timing(void *ctx, int32_t on);
 kp_status kp_get_timing(void *ctx, double *sweep_ms_total, int64_t *sweep_launches,
                         double *sweep_bytes_total);
 
+/* Tile-size override for one problem shape (M, K, b_format): users per tile
+   and grid size (blocks) used by every later call on this context for that
+   shape; 0 keeps the built-in choice, (0, 0) removes the override.  x, lambda
+   and R do not depend on these values; g and P are FP64 sums whose grouping
+   follows the grid, so their last bits may.  Used by the autotuner. */
+kp_status kp_set_tuning(void *ctx, int32_t M, int32_t K, int32_t b_format, int32_t users_per_tile,
+                        int32_t grid);
+
 /* Size limits of this build. */
 int32_t kp_max_items(void);        /* 64 */
 int32_t kp_max_knapsacks_scd(void);/* largest K accepted by the SCD calls */

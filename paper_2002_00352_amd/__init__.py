@@ -60,7 +60,7 @@ EXPORTS = ["kp_last_error", "kp_create", "kp_destroy", "kp_set_stream", "kp_eval
            "kp_scd_sweep", "kp_scd_sweep_masked", "kp_dd_step", "kp_dual_backward",
            "kp_primal_fixup", "kp_scd_sweep_batched", "kp_validate_inputs", "kp_tree_from_sets",
            "kp_max_items", "kp_max_knapsacks_scd", "kp_set_timing", "kp_get_timing",
-           "kp_batched_create", "kp_batched_step", "kp_batched_destroy"]
+           "kp_batched_create", "kp_batched_step", "kp_batched_destroy", "kp_set_tuning"]
 
 
 def lib():
@@ -88,6 +88,7 @@ def lib():
         L.kp_batched_create.argtypes = [vp, P, i32, vp, vp, ctypes.POINTER(vp)]
         L.kp_batched_step.argtypes = [vp, i32, vp, i32]
         L.kp_batched_destroy.argtypes = [vp]
+        L.kp_set_tuning.argtypes = [vp, i32, i32, i32, i32, i32]
         L.kp_set_timing.argtypes = [vp, i32]
         L.kp_get_timing.argtypes = [vp, vp, vp, vp]
         L.kp_max_items.restype = i32
@@ -135,6 +136,9 @@ class Context:
         ms, n, by = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
         _check(lib().kp_get_timing(self.h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by)))
         return ms.value, n.value, by.value
+
+    def set_tuning(self, M: int, K: int, b_format: int, users_per_tile: int, grid: int):
+        _check(lib().kp_set_tuning(self.h, M, K, b_format, users_per_tile, grid))
 
     def close(self):
         if self.h:

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -98,6 +99,8 @@ struct Ctx {
   double sweep_bytes = 0.0;
   const int64_t *nnz_rowptr = nullptr;
   int64_t nnz_rows = -1, nnz = 0;
+  // tuned tile sizes per shape (M, K, format) -> (users per tile, grid)
+  std::map<std::tuple<int, int, int>, std::pair<int, int>> tuning;
 };
 
 hipEvent_t take_event(Ctx *c) {
@@ -176,7 +179,7 @@ struct Prepared {
   double bytes = 0.0;   // algorithmic input bytes of one sweep launch
 };
 
-kp_status prepare(const kp_problem *p, bool scd, Prepared &out) {
+kp_status prepare(const kp_problem *p, bool scd, Prepared &out, const Ctx *ctx = nullptr) {
   if (!p) return fail(KP_ERR_INVALID, "problem is NULL");
   if (p->N < 0) return fail(KP_ERR_INVALID, "N must be >= 0 (got %lld)", (long long)p->N);
   if (p->M < 1) return fail(KP_ERR_INVALID, "M must be >= 1 (got %d)", p->M);
@@ -257,6 +260,14 @@ kp_status prepare(const kp_problem *p, bool scd, Prepared &out) {
   int U = (int)std::max<size_t>(1, std::min<size_t>(64, kTileBudget / per_user));
   U = std::min(U, std::max(1, 1024 / M));   // rows per tile <= the prefetched rows
   if (U >= 4) U &= ~3;   // keeps 16-byte alignment of dense tiles when M*K is odd
+  int grid_override = 0;
+  if (ctx) {
+    auto it = ctx->tuning.find(std::make_tuple(M, p->K, p->b_format));
+    if (it != ctx->tuning.end()) {
+      if (it->second.first > 0) U = std::min(it->second.first, std::max(1, 1024 / M));
+      grid_override = it->second.second;
+    }
+  }
   while (U > 1 && kp_sweep_lds_bytes(U, M, p->K, scd, p->b_format) > 64 * 1024) --U;
   if (kp_sweep_lds_bytes(U, M, p->K, scd, p->b_format) > kMaxLds)
     return fail(KP_ERR_UNSUPPORTED, "M*K = %d too large for one tile", M * p->K);
@@ -272,7 +283,7 @@ kp_status prepare(const kp_problem *p, bool scd, Prepared &out) {
       out.bytes = Nd * M * 4.0 + (Nd * M + 1) * 8.0;
     }
   }
-  out.grid = (int)std::max<int64_t>(1, std::min<int64_t>(out.ntiles, kMaxGrid));
+  out.grid = (int)std::max<int64_t>(1, std::min<int64_t>(out.ntiles, grid_override > 0 ? grid_override : kMaxGrid));
   return KP_OK;
 }
 
@@ -462,7 +473,7 @@ kp_status kp_eval_dual(void *ctx, const kp_problem *prob, const double *lambda, 
   if (!lambda) return fail(KP_ERR_INVALID, "lambda is NULL");
   Ctx *c = (Ctx *)ctx;
   Prepared P;
-  kp_status s = prepare(prob, false, P);
+  kp_status s = prepare(prob, false, P, c);
   if (s != KP_OK) return s;
   SweepWs w;
   if ((s = carve_ws(c, P, false, w)) != KP_OK) return s;
@@ -477,7 +488,7 @@ kp_status kp_dd_step(void *ctx, const kp_problem *prob, double alpha, double *la
   if (!std::isfinite(alpha) || alpha < 0) return fail(KP_ERR_INVALID, "alpha must be finite and >= 0");
   Ctx *c = (Ctx *)ctx;
   Prepared P;
-  kp_status s = prepare(prob, false, P);
+  kp_status s = prepare(prob, false, P, c);
   if (s != KP_OK) return s;
   SweepWs w;
   if ((s = carve_ws(c, P, false, w)) != KP_OK) return s;
@@ -516,7 +527,7 @@ kp_status kp_scd_sweep_masked(void *ctx, const kp_problem *prob, const double *l
   if (!lambda_in || !lambda_out) return fail(KP_ERR_INVALID, "lambda is NULL");
   Ctx *c = (Ctx *)ctx;
   Prepared P;
-  kp_status s = prepare(prob, true, P);
+  kp_status s = prepare(prob, true, P, c);
   if (s != KP_OK) return s;
   SweepWs w;
   if ((s = carve_ws(c, P, true, w)) != KP_OK) return s;
@@ -577,7 +588,7 @@ kp_status kp_validate_inputs(void *ctx, const kp_problem *prob) {
   if (!ctx) return fail(KP_ERR_INVALID, "ctx is NULL");
   Ctx *c = (Ctx *)ctx;
   Prepared P;
-  kp_status s = prepare(prob, false, P);
+  kp_status s = prepare(prob, false, P, c);
   if (s != KP_OK) return s;
   Carve cv;
   size_t of = cv.take(16);
@@ -660,6 +671,16 @@ kp_status kp_tree_from_sets(int32_t M, int32_t L, const int32_t *set_offsets,
   return KP_OK;
 }
 
+kp_status kp_set_tuning(void *ctx, int32_t M, int32_t K, int32_t b_format, int32_t users_per_tile,
+                        int32_t grid) {
+  if (!ctx) return fail(KP_ERR_INVALID, "ctx is NULL");
+  if (users_per_tile < 0 || grid < 0) return fail(KP_ERR_INVALID, "negative tuning value");
+  Ctx *c = (Ctx *)ctx;
+  if (users_per_tile == 0 && grid == 0) c->tuning.erase(std::make_tuple(M, K, b_format));
+  else c->tuning[std::make_tuple(M, K, b_format)] = std::make_pair(users_per_tile, grid);
+  return KP_OK;
+}
+
 kp_status kp_set_timing(void *ctx, int32_t on) {
   if (!ctx) return fail(KP_ERR_INVALID, "ctx is NULL");
   Ctx *c = (Ctx *)ctx;
@@ -688,7 +709,7 @@ kp_status kp_primal_fixup(void *ctx, const kp_problem *prob, const double *lambd
   if (!lambda || !primal_out || !R_out || !n_reset_out) return fail(KP_ERR_INVALID, "NULL argument");
   Ctx *c = (Ctx *)ctx;
   Prepared P;
-  kp_status s = prepare(prob, false, P);
+  kp_status s = prepare(prob, false, P, c);
   if (s != KP_OK) return s;
   if (P.pr.N >= (int64_t)1 << 32) return fail(KP_ERR_UNSUPPORTED, "post-processing supports N < 2^32");
   const int K = P.pr.K;
@@ -839,7 +860,7 @@ kp_status plan_create(Ctx *c, const kp_problem *probs, int n, const double *cons
   if (n < 1 || !probs || !lam_a || !lam_b) return fail(KP_ERR_INVALID, "bad batch arguments");
   std::vector<Prepared> P(n);
   for (int s = 0; s < n; ++s) {
-    kp_status st = prepare(&probs[s], true, P[s]);
+    kp_status st = prepare(&probs[s], true, P[s], c);
     if (st != KP_OK) {
       std::string m = g_err;
       return fail(st, "instance %d: %s", s, m.c_str());

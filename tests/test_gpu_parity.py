@@ -282,3 +282,28 @@ def test_batched_plan_graph_replays(use_graph):
             assert np.array_equal(outs[s].cpu().numpy(), want), (use_graph, t, s)
             lams[s] = want
     plan.close()
+
+
+@gpu
+def test_autotuner_choice_keeps_results(tmp_path):
+    """Every tile shape the autotuner may pick gives the same decisions,
+    consumption and SCD update; the choice is cached as JSON."""
+    kp, torch = _kp()
+    from paper_2002_00352_amd import autotune
+    inst = kpgen.config_instance(3, N=5000)
+    prob = kp.Problem.from_host(inst)
+    ctx = kp.Context()
+    lam = np.full(inst.K, 0.3)
+    want = oracle.scd_sweep(inst, lam)
+    ref = oracle.eval_dual(inst, lam)
+    for u, g in [(4, 512), (16, 1024), (64, 4096)]:
+        autotune.apply(ctx, prob, (u, g))
+        ev = kp.kp_eval_dual(prob, _lamd(torch, lam), want_x=True, ctx=ctx)
+        assert np.array_equal(ev["x"].cpu().numpy(), ref["x"])
+        assert np.array_equal(ev["R"].cpu().numpy(), ref["R"])
+        got = kp.kp_scd_sweep(prob, _lamd(torch, lam), ctx=ctx)["lam"].cpu().numpy()
+        assert np.array_equal(got, want), (u, g)
+    path = str(tmp_path / "tune.json")
+    choice = autotune.tune(prob, ctx=ctx, candidates=[(8, 512), (32, 2048)], path=path)
+    assert choice in [(8, 512), (32, 2048)]
+    assert autotune.shape_key(prob) + "|scd" in autotune.load_cache(path)
