@@ -201,6 +201,16 @@ kp_status kp_get_timing(void *ctx, double *sweep_ms_total, int64_t *sweep_launch
 kp_status kp_set_tuning(void *ctx, int32_t M, int32_t K, int32_t b_format, int32_t users_per_tile,
                         int32_t grid);
 
+/* Kernel choice for CSR costs: when every item row holds the same number of
+   stored entries (1 or 2) at offsets r*D and M <= 16, a lean per-user kernel
+   is used that never reads b_rowptr during sweeps.  The structure check reads
+   b_rowptr once and is cached per (b_rowptr, N*M) in the context;
+   kp_forget_structure clears that cache (call it after rewriting a rowptr
+   array in place).  kp_set_kernel_choice(ctx, 0) forces the general kernel
+   (results are identical either way). */
+kp_status kp_set_kernel_choice(void *ctx, int32_t allow_uniform_rows);
+kp_status kp_forget_structure(void *ctx);
+
 /* Size limits of this build. */
 int32_t kp_max_items(void);        /* 64 */
 int32_t kp_max_knapsacks_scd(void);/* largest K accepted by the SCD calls */

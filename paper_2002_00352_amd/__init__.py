@@ -18,7 +18,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _REPO = os.path.dirname(_HERE)
 LIB_PATH = os.path.join(_HERE, "libkp.so")
-SOURCES = [os.path.join(_HERE, "csrc", "kp_kernels.hip"), os.path.join(_HERE, "csrc", "kp_capi.hip")]
+SOURCES = [os.path.join(_HERE, "csrc", "kp_kernels.hip"), os.path.join(_HERE, "csrc", "kp_ell.hip"),
+           os.path.join(_HERE, "csrc", "kp_capi.hip")]
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
                "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                "-Wno-unused-result"]
@@ -60,7 +61,8 @@ EXPORTS = ["kp_last_error", "kp_create", "kp_destroy", "kp_set_stream", "kp_eval
            "kp_scd_sweep", "kp_scd_sweep_masked", "kp_dd_step", "kp_dual_backward",
            "kp_primal_fixup", "kp_scd_sweep_batched", "kp_validate_inputs", "kp_tree_from_sets",
            "kp_max_items", "kp_max_knapsacks_scd", "kp_set_timing", "kp_get_timing",
-           "kp_batched_create", "kp_batched_step", "kp_batched_destroy", "kp_set_tuning"]
+           "kp_batched_create", "kp_batched_step", "kp_batched_destroy", "kp_set_tuning",
+           "kp_set_kernel_choice", "kp_forget_structure"]
 
 
 def lib():
@@ -89,6 +91,8 @@ def lib():
         L.kp_batched_step.argtypes = [vp, i32, vp, i32]
         L.kp_batched_destroy.argtypes = [vp]
         L.kp_set_tuning.argtypes = [vp, i32, i32, i32, i32, i32]
+        L.kp_set_kernel_choice.argtypes = [vp, i32]
+        L.kp_forget_structure.argtypes = [vp]
         L.kp_set_timing.argtypes = [vp, i32]
         L.kp_get_timing.argtypes = [vp, vp, vp, vp]
         L.kp_max_items.restype = i32
@@ -139,6 +143,9 @@ class Context:
 
     def set_tuning(self, M: int, K: int, b_format: int, users_per_tile: int, grid: int):
         _check(lib().kp_set_tuning(self.h, M, K, b_format, users_per_tile, grid))
+
+    def set_kernel_choice(self, allow_uniform_rows: bool):
+        _check(lib().kp_set_kernel_choice(self.h, 1 if allow_uniform_rows else 0))
 
     def close(self):
         if self.h:

@@ -38,6 +38,10 @@ hipError_t kp_launch_fixup_pipeline(const double *uv, int nv, const double *G, i
                                     const double *P, double *R_out, double *P_out, int64_t *n_reset,
                                     void *scratch, hipStream_t stream, uint32_t *ncand_host_pinned);
 size_t kp_fixup_scratch_bytes(int64_t N, int nv, int K);
+size_t kp_ell_lds_bytes(int M, int K, int D, int L, bool scd, int *region_out);
+hipError_t kp_launch_ell(const SweepArgs &a, int D, int grid, bool scd, hipStream_t stream);
+hipError_t kp_launch_ell_check(const int64_t *rowptr, int64_t nrows, int D, unsigned int *bad,
+                               hipStream_t stream);
 hipError_t kp_launch_sweep_batched(const SweepArgs *descs, const TileGeom *geoms,
                                    const int *block_off, int n_inst, int total_blocks, size_t lds,
                                    hipStream_t stream);
@@ -101,6 +105,9 @@ struct Ctx {
   int64_t nnz_rows = -1, nnz = 0;
   // tuned tile sizes per shape (M, K, format) -> (users per tile, grid)
   std::map<std::tuple<int, int, int>, std::pair<int, int>> tuning;
+  // uniform-row CSR structure found per (rowptr, rows): entries per row, or 0
+  std::map<std::pair<const int64_t *, int64_t>, std::pair<int, int64_t>> ell;
+  bool ell_enabled = true;
 };
 
 hipEvent_t take_event(Ctx *c) {
@@ -177,6 +184,12 @@ struct Prepared {
   int64_t ntiles = 0;
   int grid = 1;
   double bytes = 0.0;   // algorithmic input bytes of one sweep launch
+  // uniform-row CSR kernel (0 = not used)
+  int ell_D = 0;
+  int64_t ell_ntiles = 0;
+  int ell_grid = 0;
+  double ell_bytes = 0.0;
+  int stage_grid() const { return std::max(grid, ell_grid); }
 };
 
 kp_status prepare(const kp_problem *p, bool scd, Prepared &out, const Ctx *ctx = nullptr) {
@@ -287,6 +300,58 @@ kp_status prepare(const kp_problem *p, bool scd, Prepared &out, const Ctx *ctx =
   return KP_OK;
 }
 
+constexpr int kEllGrid = 1024;
+
+// Decide whether the uniform-row CSR kernel applies: CSR, M <= 16, every item
+// row holding the same D in {1, 2} entries at r*D (checked once on the device
+// per rowptr array and cached), and its LDS fits.
+kp_status choose_kernel(Ctx *c, Prepared &P, bool scd) {
+  P.ell_D = 0;
+  P.ell_grid = 0;
+  if (!c->ell_enabled || P.pr.fmt != KP_B_CSR || P.pr.M > 16 || P.pr.N == 0) return KP_OK;
+  const int64_t nrows = P.pr.N * P.pr.M;
+  const auto key = std::make_pair(P.pr.rowptr, nrows);
+  auto it = c->ell.find(key);
+  int D = 0;
+  int64_t nnz = 0;
+  if (it != c->ell.end()) {
+    D = it->second.first;
+    nnz = it->second.second;
+  } else {
+    if (!c->pinned) {
+      if (hipHostMalloc((void **)&c->pinned, 64, hipHostMallocDefault) != hipSuccess) {
+        c->pinned = nullptr;
+        return fail(KP_ERR_HIP, "hipHostMalloc failed");
+      }
+    }
+    int64_t *h = (int64_t *)(c->pinned + 8);
+    HIP_TRY(hipMemcpyAsync(h, P.pr.rowptr + nrows, 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    nnz = *h;
+    if (nnz > 0 && nnz % nrows == 0 && nnz / nrows <= 2) {
+      const int Dc = (int)(nnz / nrows);
+      Carve cv;
+      size_t ob = cv.take(16);
+      kp_status s = ensure_ws(c, std::max(cv.off, c->ws_cap));
+      if (s != KP_OK) return s;
+      unsigned int *bad = (unsigned int *)((char *)c->ws + ob);
+      HIP_TRY(hipMemsetAsync(bad, 0, 4, c->stream));
+      HIP_TRY(kp_launch_ell_check(P.pr.rowptr, nrows, Dc, bad, c->stream));
+      HIP_TRY(hipMemcpyAsync(c->pinned + 12, bad, 4, hipMemcpyDeviceToHost, c->stream));
+      HIP_TRY(hipStreamSynchronize(c->stream));
+      if (c->pinned[12] == 0) D = Dc;
+    }
+    c->ell[key] = std::make_pair(D, nnz);
+  }
+  if (D == 0) return KP_OK;
+  if (kp_ell_lds_bytes(P.pr.M, P.pr.K, D, P.tree.L, scd, nullptr) > kMaxLds) return KP_OK;
+  P.ell_D = D;
+  P.ell_ntiles = (P.pr.N + 63) / 64;
+  P.ell_grid = (int)std::max<int64_t>(1, std::min<int64_t>((P.ell_ntiles + 3) / 4, kEllGrid));
+  P.ell_bytes = (double)P.pr.N * P.pr.M * 4.0 + (double)nnz * 8.0;   // rowptr is not read
+  return KP_OK;
+}
+
 struct SweepWs {
   double *partials, *B, *hist_sum, *ev1, *ev2, *Rtmp, *gtmp, *Ptmp, *sv1, *sv2;
   uint16_t *sk;
@@ -302,7 +367,7 @@ struct SweepWs {
 kp_status carve_ws(Ctx *c, const Prepared &P, bool scd, SweepWs &w) {
   const int K = P.pr.K;
   Carve cv;
-  size_t o_part = cv.take((size_t)P.grid * (K + 2) * 8);
+  size_t o_part = cv.take((size_t)P.stage_grid() * (K + 2) * 8);
   size_t o_B = cv.take((size_t)K * 8);
   size_t o_R = cv.take((size_t)K * 8);
   size_t o_g = cv.take(8);
@@ -323,9 +388,9 @@ kp_status carve_ws(Ctx *c, const Prepared &P, bool scd, SweepWs &w) {
   size_t o_s1 = 0, o_s2 = 0, o_sk = 0;
   const uint32_t scap = scd ? kStageCap : 0;
   if (scd) {
-    o_s1 = cv.take((size_t)P.grid * scap * 8);
-    o_s2 = cv.take((size_t)P.grid * scap * 8);
-    o_sk = cv.take((size_t)P.grid * scap * 2);
+    o_s1 = cv.take((size_t)P.stage_grid() * scap * 8);
+    o_s2 = cv.take((size_t)P.stage_grid() * scap * 8);
+    o_sk = cv.take((size_t)P.stage_grid() * scap * 2);
   }
   kp_status s = ensure_ws(c, cv.off);
   if (s != KP_OK) return s;
@@ -360,7 +425,9 @@ double algo_bytes(const Prepared &P) {
 
 hipError_t timed_sweep(Ctx *c, const SweepArgs &a, const Prepared &P, bool scd, double bytes) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (c->timing && P.pr.fmt == KP_B_CSR && P.pr.N > 0) {
+  if (c->timing && P.ell_D) {
+    bytes = P.ell_bytes;
+  } else if (c->timing && P.pr.fmt == KP_B_CSR && P.pr.N > 0) {
     // stored entries (col + val, 8 bytes each) -- read once per rowptr array
     const int64_t nrows = P.pr.N * P.pr.M;
     if (c->nnz_rowptr != P.pr.rowptr || c->nnz_rows != nrows) {
@@ -379,7 +446,14 @@ hipError_t timed_sweep(Ctx *c, const SweepArgs &a, const Prepared &P, bool scd, 
     e1 = take_event(c);
     if (e0 && e1) (void)hipEventRecord(e0, c->stream);
   }
-  hipError_t err = kp_launch_sweep(a, P.U, P.grid, scd, c->stream);
+  hipError_t err;
+  if (P.ell_D) {
+    SweepArgs ae = a;
+    ae.ntiles = P.ell_ntiles;
+    err = kp_launch_ell(ae, P.ell_D, P.ell_grid, scd, c->stream);
+  } else {
+    err = kp_launch_sweep(a, P.U, P.grid, scd, c->stream);
+  }
   if (c->timing && e0 && e1) {
     (void)hipEventRecord(e1, c->stream);
     c->ev_pending.push_back({e0, e1});
@@ -425,7 +499,8 @@ kp_status eval_into(Ctx *c, const Prepared &P, const SweepWs &w, const double *l
   }
   SweepArgs a = make_args(P, lam, w, x, true);
   HIP_TRY(timed_sweep(c, a, P, false, P.bytes));
-  HIP_TRY(kp_launch_reduce_stats(w.partials, P.grid, P.pr.K, lam, w.B, R, g, primal, c->stream));
+  HIP_TRY(kp_launch_reduce_stats(w.partials, P.ell_D ? P.ell_grid : P.grid, P.pr.K, lam, w.B, R, g,
+                                 primal, c->stream));
   return KP_OK;
 }
 
@@ -475,6 +550,7 @@ kp_status kp_eval_dual(void *ctx, const kp_problem *prob, const double *lambda, 
   Prepared P;
   kp_status s = prepare(prob, false, P, c);
   if (s != KP_OK) return s;
+  if ((s = choose_kernel(c, P, false)) != KP_OK) return s;
   SweepWs w;
   if ((s = carve_ws(c, P, false, w)) != KP_OK) return s;
   HIP_TRY(hipMemcpyAsync(w.B, P.B.data(), (size_t)P.pr.K * 8, hipMemcpyHostToDevice, c->stream));
@@ -490,6 +566,7 @@ kp_status kp_dd_step(void *ctx, const kp_problem *prob, double alpha, double *la
   Prepared P;
   kp_status s = prepare(prob, false, P, c);
   if (s != KP_OK) return s;
+  if ((s = choose_kernel(c, P, false)) != KP_OK) return s;
   SweepWs w;
   if ((s = carve_ws(c, P, false, w)) != KP_OK) return s;
   HIP_TRY(hipMemcpyAsync(w.B, P.B.data(), (size_t)P.pr.K * 8, hipMemcpyHostToDevice, c->stream));
@@ -529,6 +606,7 @@ kp_status kp_scd_sweep_masked(void *ctx, const kp_problem *prob, const double *l
   Prepared P;
   kp_status s = prepare(prob, true, P, c);
   if (s != KP_OK) return s;
+  if ((s = choose_kernel(c, P, true)) != KP_OK) return s;
   SweepWs w;
   if ((s = carve_ws(c, P, true, w)) != KP_OK) return s;
   const int K = P.pr.K;
@@ -559,7 +637,8 @@ kp_status kp_scd_sweep_masked(void *ctx, const kp_problem *prob, const double *l
     }
     if (pass == 0) {
       if (P.pr.N > 0) {
-        HIP_TRY(kp_launch_reduce_stats(w.partials, P.grid, K, lambda_in, w.B, Rd, gd, Pd, c->stream));
+        HIP_TRY(kp_launch_reduce_stats(w.partials, P.ell_D ? P.ell_grid : P.grid, K, lambda_in, w.B, Rd,
+                                       gd, Pd, c->stream));
       } else {
         HIP_TRY(hipMemsetAsync(w.partials, 0, (size_t)(K + 2) * 8, c->stream));
         HIP_TRY(kp_launch_reduce_stats(w.partials, 1, K, lambda_in, w.B, Rd, gd, Pd, c->stream));
@@ -681,6 +760,18 @@ kp_status kp_set_tuning(void *ctx, int32_t M, int32_t K, int32_t b_format, int32
   return KP_OK;
 }
 
+kp_status kp_set_kernel_choice(void *ctx, int32_t allow_uniform_rows) {
+  if (!ctx) return fail(KP_ERR_INVALID, "ctx is NULL");
+  ((Ctx *)ctx)->ell_enabled = allow_uniform_rows != 0;
+  return KP_OK;
+}
+
+kp_status kp_forget_structure(void *ctx) {
+  if (!ctx) return fail(KP_ERR_INVALID, "ctx is NULL");
+  ((Ctx *)ctx)->ell.clear();
+  return KP_OK;
+}
+
 kp_status kp_set_timing(void *ctx, int32_t on) {
   if (!ctx) return fail(KP_ERR_INVALID, "ctx is NULL");
   Ctx *c = (Ctx *)ctx;
@@ -712,6 +803,7 @@ kp_status kp_primal_fixup(void *ctx, const kp_problem *prob, const double *lambd
   kp_status s = prepare(prob, false, P, c);
   if (s != KP_OK) return s;
   if (P.pr.N >= (int64_t)1 << 32) return fail(KP_ERR_UNSUPPORTED, "post-processing supports N < 2^32");
+  if ((s = choose_kernel(c, P, false)) != KP_OK) return s;
   const int K = P.pr.K;
   const int64_t N = P.pr.N;
   // pass 1: x(lambda), R, P
@@ -722,7 +814,7 @@ kp_status kp_primal_fixup(void *ctx, const kp_problem *prob, const double *lambd
   cv.off = 0;
   {
     Carve base;
-    base.take((size_t)P.grid * (K + 2) * 8); base.take((size_t)K * 8); base.take((size_t)K * 8);
+    base.take((size_t)P.stage_grid() * (K + 2) * 8); base.take((size_t)K * 8); base.take((size_t)K * 8);
     base.take(8); base.take(8); base.take(8); base.take(8);
     cv.off = base.off;
   }

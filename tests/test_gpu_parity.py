@@ -307,3 +307,41 @@ def test_autotuner_choice_keeps_results(tmp_path):
     choice = autotune.tune(prob, ctx=ctx, candidates=[(8, 512), (32, 2048)], path=path)
     assert choice in [(8, 512), (32, 2048)]
     assert autotune.shape_key(prob) + "|scd" in autotune.load_cache(path)
+
+
+ELL_CASES = [
+    ("c3-ragged-N12345", lambda: kpgen.config_instance(3, N=12345)),
+    ("csr-d1-topq", lambda: kpgen.make_instance(3001, 12, 9, seed=41, Q=3, csr_d=1, budget_frac=0.1)),
+    ("csr-d2-laminar-M16", lambda: kpgen.make_instance(1500, 16, 7, seed=42, csr_d=2, budget_frac=0.08,
+                                                       tree=random_laminar(16, np.random.default_rng(4)))),
+    ("c3-single-user", lambda: kpgen.config_instance(3, N=1)),
+]
+
+
+@gpu
+@pytest.mark.parametrize("name,mk", ELL_CASES, ids=[c[0] for c in ELL_CASES])
+def test_uniform_row_kernel_parity(name, mk):
+    """CSR with the same number of entries per item row takes the lean
+    per-user kernel: decisions, statistics and SCD updates equal the
+    oracle's and the general kernel's."""
+    kp, torch = _kp()
+    print("case", name, flush=True)
+    inst = mk()
+    prob = kp.Problem.from_host(inst)
+    lean = kp.Context()
+    general = kp.Context()
+    general.set_kernel_choice(False)
+    lam = np.zeros(inst.K)
+    for t in range(3):
+        for ctx in (lean, general):
+            ev = kp.kp_eval_dual(prob, _lamd(torch, lam), want_x=True, ctx=ctx)
+            ref = oracle.eval_dual(inst, lam)
+            assert np.array_equal(ev["x"].cpu().numpy(), ref["x"])
+            assert np.array_equal(ev["R"].cpu().numpy(), ref["R"])
+            for key in ("g", "P"):
+                assert abs(ev[key].item() - ref[key]) <= REL * max(1.0, abs(ref[key]))
+        want = oracle.scd_sweep(inst, lam)
+        for ctx in (lean, general):
+            got = kp.kp_scd_sweep(prob, _lamd(torch, lam), ctx=ctx)["lam"].cpu().numpy()
+            assert np.array_equal(got, want), (t, got, want)
+        lam = want if t < 2 else np.random.default_rng(t).random(inst.K) * 2
