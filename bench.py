@@ -135,6 +135,7 @@ def main():
         lam, out = out, lam
     torch.cuda.synchronize()
     ctx.set_timing(True)
+    win0 = ctx.window_stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -144,6 +145,7 @@ def main():
     t1 = time.perf_counter()
     ms_k, launches, bytes_k = ctx.timing()
     ctx.set_timing(False)
+    win = [b - a for a, b in zip(win0, ctx.window_stats())]
     dt = t1 - t0
     N = meta["N"]
     value = N * args.steps / dt
@@ -151,6 +153,8 @@ def main():
     avg_ms = ms_k / max(launches, 1)
     achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
     traffic = traffic_for(args.workload, per_launch_bytes)
+    kernel_name = ("k_ell (uniform-row CSR, scd)" if meta["csr_d"] and meta["M"] <= 16
+                   else "k_sweep (scd)")
     rec = {
         "metric": "user-subproblem solves/s per SCD sweep",
         "value": value,
@@ -169,9 +173,12 @@ def main():
                    "lambda0": 0.0},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_sweep (scd)", "launches": launches,
+                     "kernel": kernel_name, "launches": launches,
                      "avg_launch_ms": avg_ms, "algo_bytes_per_launch": per_launch_bytes},
         "passes_per_step": launches / args.steps,
+        "threshold_search": {"window_tried": win[0], "window_missed_above": win[1],
+                             "window_missed_below": win[2], "window_events": win[3],
+                             "knapsack_searches": K * args.steps},
         "pct_hbm_peak": 100.0 * achieved / HBM_PEAK_GBS,
         "lambda_final_head": [float(v) for v in lam[:4].cpu().numpy()],
         "gen_s": t_gen,

@@ -211,6 +211,23 @@ kp_status kp_set_tuning(void *ctx, int32_t M, int32_t K, int32_t b_format, int32
 kp_status kp_set_kernel_choice(void *ctx, int32_t allow_uniform_rows);
 kp_status kp_forget_structure(void *ctx);
 
+/* Threshold search of kp_scd_sweep with the lean kernel (Alg.4 reduce,
+   located near the previous multiplier).  After one sweep on a context, each
+   knapsack whose last step was small against its multiplier starts with a
+   window around lambda_k^t: users whose greedy set stays optimal over the
+   whole window are checked in O(M) instead of walked, and only the
+   breakpoints inside the window are emitted.  A threshold outside the window
+   costs one more pass with the full search.  The result is the same
+   lambda_out either way; kp_set_window(ctx, 0) turns the window off
+   (default on). */
+kp_status kp_set_window(void *ctx, int32_t on);
+/* Window searches on this context since its creation: knapsack searches
+   that started with a window, how many of them found the threshold above /
+   below it (and so took the full search), and the breakpoints emitted inside
+   windows.  HOST outputs, each may be NULL. */
+kp_status kp_get_window_stats(void *ctx, int64_t *tried, int64_t *above, int64_t *below,
+                              int64_t *emitted);
+
 /* Size limits of this build. */
 int32_t kp_max_items(void);        /* 64 */
 int32_t kp_max_knapsacks_scd(void);/* largest K accepted by the SCD calls */

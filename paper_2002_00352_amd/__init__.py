@@ -62,7 +62,8 @@ EXPORTS = ["kp_last_error", "kp_create", "kp_destroy", "kp_set_stream", "kp_eval
            "kp_primal_fixup", "kp_scd_sweep_batched", "kp_validate_inputs", "kp_tree_from_sets",
            "kp_max_items", "kp_max_knapsacks_scd", "kp_set_timing", "kp_get_timing",
            "kp_batched_create", "kp_batched_step", "kp_batched_destroy", "kp_set_tuning",
-           "kp_set_kernel_choice", "kp_forget_structure"]
+           "kp_set_kernel_choice", "kp_forget_structure", "kp_set_window",
+           "kp_get_window_stats"]
 
 
 def lib():
@@ -93,6 +94,9 @@ def lib():
         L.kp_set_tuning.argtypes = [vp, i32, i32, i32, i32, i32]
         L.kp_set_kernel_choice.argtypes = [vp, i32]
         L.kp_forget_structure.argtypes = [vp]
+        L.kp_set_window.argtypes = [vp, i32]
+        L.kp_get_window_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                          ctypes.POINTER(i64), ctypes.POINTER(i64)]
         L.kp_set_timing.argtypes = [vp, i32]
         L.kp_get_timing.argtypes = [vp, vp, vp, vp]
         L.kp_max_items.restype = i32
@@ -146,6 +150,17 @@ class Context:
 
     def set_kernel_choice(self, allow_uniform_rows: bool):
         _check(lib().kp_set_kernel_choice(self.h, 1 if allow_uniform_rows else 0))
+
+    def set_window(self, on: bool):
+        _check(lib().kp_set_window(self.h, 1 if on else 0))
+
+    def window_stats(self):
+        """(window searches tried, threshold found above, below, breakpoints
+        emitted inside windows) since creation."""
+        t, a, b, e = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().kp_get_window_stats(self.h, ctypes.byref(t), ctypes.byref(a), ctypes.byref(b),
+                                         ctypes.byref(e)))
+        return t.value, a.value, b.value, e.value
 
     def close(self):
         if self.h:

@@ -22,10 +22,11 @@ hipError_t kp_launch_reduce_stats(const double *partials, int nblk, int K, const
                                   const double *B, double *R, double *g, double *P,
                                   hipStream_t stream);
 hipError_t kp_launch_scd_init(KState *st, int K, const double *lam_in, const uint8_t *kmask,
-                              const double *delta_hint, hipStream_t stream);
-hipError_t kp_launch_scd_locate_select(KState *st, int K, const double *B, double *hist_sum,
-                                       uint32_t *hist_cnt, const double *ev1, const double *ev2,
-                                       uint32_t emit_cap, int *pending, hipStream_t stream);
+                              const double *delta_hint, int window, hipStream_t stream);
+hipError_t kp_launch_scd_locate_select(KState *st, int K, const double *B, const double *R,
+                                       double *hist_sum, uint32_t *hist_cnt, const double *ev1,
+                                       const double *ev2, uint32_t emit_cap, int *pending,
+                                       unsigned int *win, hipStream_t stream);
 hipError_t kp_launch_scd_finish(const KState *st, int K, const double *lam_in, double *lam_out,
                                 double *delta_next, hipStream_t stream);
 hipError_t kp_launch_dd_update(int K, double alpha, const double *R, const double *B, double *lam,
@@ -81,7 +82,8 @@ constexpr size_t kMaxLds = 160 * 1024;   // LDS per workgroup on gfx950
 constexpr int kMaxGrid = 2048;
 constexpr uint32_t kEmitCapDefault = 1u << 20;
 constexpr int kMaxPasses = 96;
-constexpr uint32_t kStageCap = 4096;    // staged events per block per pass
+constexpr uint32_t kStageCap = 4096;    // staged events per block per pass (at least)
+constexpr uint32_t kStageCapMax = 32768;
 constexpr uint32_t kEmitCapBatched = 1u << 16;   // emitted events per (instance, knapsack) per pass
 
 struct Ctx {
@@ -108,6 +110,9 @@ struct Ctx {
   // uniform-row CSR structure found per (rowptr, rows): entries per row, or 0
   std::map<std::pair<const int64_t *, int64_t>, std::pair<int, int64_t>> ell;
   bool ell_enabled = true;
+  bool window_enabled = true;
+  int64_t win_tried = 0, win_above = 0, win_below = 0;   // window searches since creation
+  int64_t win_emitted = 0;                                 // breakpoints emitted inside windows
 };
 
 hipEvent_t take_event(Ctx *c) {
@@ -150,7 +155,7 @@ struct Carve {
 
 kp_status ensure_ws(Ctx *c, size_t bytes) {
   if (!c->pinned) {
-    if (hipHostMalloc((void **)&c->pinned, 64, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void **)&c->pinned, 128, hipHostMallocDefault) != hipSuccess) {
       c->pinned = nullptr;
       return fail(KP_ERR_HIP, "hipHostMalloc of the status word failed");
     }
@@ -319,7 +324,7 @@ kp_status choose_kernel(Ctx *c, Prepared &P, bool scd) {
     nnz = it->second.second;
   } else {
     if (!c->pinned) {
-      if (hipHostMalloc((void **)&c->pinned, 64, hipHostMallocDefault) != hipSuccess) {
+      if (hipHostMalloc((void **)&c->pinned, 128, hipHostMallocDefault) != hipSuccess) {
         c->pinned = nullptr;
         return fail(KP_ERR_HIP, "hipHostMalloc failed");
       }
@@ -361,6 +366,7 @@ struct SweepWs {
   uint8_t *kmask;
   unsigned long long *err;
   int *pending;
+  unsigned int *win;    // window searches: [0] tried, [1] threshold above, [2] below
   uint32_t emit_cap;
 };
 
@@ -373,7 +379,7 @@ kp_status carve_ws(Ctx *c, const Prepared &P, bool scd, SweepWs &w) {
   size_t o_g = cv.take(8);
   size_t o_P = cv.take(8);
   size_t o_err = cv.take(8);
-  size_t o_pend = cv.take(8);
+  size_t o_pend = cv.take(32);
   size_t o_st = 0, o_hs = 0, o_hc = 0, o_km = 0, o_e1 = 0, o_e2 = 0;
   uint32_t cap = 0;
   if (scd) {
@@ -386,7 +392,13 @@ kp_status carve_ws(Ctx *c, const Prepared &P, bool scd, SweepWs &w) {
     o_e2 = cv.take((size_t)K * cap * 8);
   }
   size_t o_s1 = 0, o_s2 = 0, o_sk = 0;
-  const uint32_t scap = scd ? kStageCap : 0;
+  // staged events per block: scale with the block's share of (user, knapsack)
+  // pairs so that large window passes do not overflow
+  uint32_t scap = 0;
+  if (scd) {
+    const double share = (double)P.pr.N * K / std::max(1, P.stage_grid()) / 64.0;
+    scap = (uint32_t)std::min<double>(kStageCapMax, std::max<double>(kStageCap, share));
+  }
   if (scd) {
     o_s1 = cv.take((size_t)P.stage_grid() * scap * 8);
     o_s2 = cv.take((size_t)P.stage_grid() * scap * 8);
@@ -402,6 +414,7 @@ kp_status carve_ws(Ctx *c, const Prepared &P, bool scd, SweepWs &w) {
   w.Ptmp = (double *)(b + o_P);
   w.err = (unsigned long long *)(b + o_err);
   w.pending = (int *)(b + o_pend);
+  w.win = (unsigned int *)(b + o_pend + 16);
   w.st = scd ? (KState *)(b + o_st) : nullptr;
   w.hist_sum = scd ? (double *)(b + o_hs) : nullptr;
   w.hist_cnt = scd ? (uint32_t *)(b + o_hc) : nullptr;
@@ -619,11 +632,15 @@ kp_status kp_scd_sweep_masked(void *ctx, const kp_problem *prob, const double *l
     c->delta_K = K;
     c->delta_valid = false;
   }
+  // the window pass needs the statistics of the same pass (R at lambda_in)
+  // and is implemented by the uniform-row kernel
+  const int window = (c->window_enabled && P.ell_D && P.pr.N > 0) ? 1 : 0;
   HIP_TRY(kp_launch_scd_init(w.st, K, lambda_in, kmask ? w.kmask : nullptr,
-                             c->delta_valid ? c->delta_dev : nullptr, c->stream));
+                             c->delta_valid ? c->delta_dev : nullptr, window, c->stream));
   HIP_TRY(hipMemsetAsync(w.hist_sum, 0, (size_t)K * KP_NB * 8, c->stream));
   HIP_TRY(hipMemsetAsync(w.hist_cnt, 0, (size_t)K * KP_NB * 4, c->stream));
   HIP_TRY(hipMemsetAsync(w.err, 0, 8, c->stream));
+  HIP_TRY(hipMemsetAsync(w.win, 0, 16, c->stream));
   double *Rd = R ? R : w.Rtmp;
   double *gd = g ? g : w.gtmp;
   double *Pd = primal ? primal : w.Ptmp;
@@ -644,11 +661,19 @@ kp_status kp_scd_sweep_masked(void *ctx, const kp_problem *prob, const double *l
         HIP_TRY(kp_launch_reduce_stats(w.partials, 1, K, lambda_in, w.B, Rd, gd, Pd, c->stream));
       }
     }
-    HIP_TRY(kp_launch_scd_locate_select(w.st, K, w.B, w.hist_sum, w.hist_cnt, w.ev1, w.ev2,
-                                        w.emit_cap, w.pending, c->stream));
+    HIP_TRY(kp_launch_scd_locate_select(w.st, K, w.B, Rd, w.hist_sum, w.hist_cnt, w.ev1, w.ev2,
+                                        w.emit_cap, w.pending, w.win, c->stream));
     HIP_TRY(hipMemcpyAsync(c->pinned, w.pending, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync(c->pinned + 2, w.err, 8, hipMemcpyDeviceToHost, c->stream));
+    if (pass == 0 && window)
+      HIP_TRY(hipMemcpyAsync(c->pinned + 16, w.win, 16, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
+    if (pass == 0 && window) {
+      c->win_tried += (unsigned)c->pinned[16];
+      c->win_above += (unsigned)c->pinned[17];
+      c->win_below += (unsigned)c->pinned[18];
+      c->win_emitted += (unsigned)c->pinned[19];
+    }
     if (*(unsigned long long *)(c->pinned + 2))
       return fail(KP_ERR_INTERNAL, "breakpoint walk exceeded its event limit");
     if (c->pinned[0] == 0) break;
@@ -763,6 +788,23 @@ kp_status kp_set_tuning(void *ctx, int32_t M, int32_t K, int32_t b_format, int32
 kp_status kp_set_kernel_choice(void *ctx, int32_t allow_uniform_rows) {
   if (!ctx) return fail(KP_ERR_INVALID, "ctx is NULL");
   ((Ctx *)ctx)->ell_enabled = allow_uniform_rows != 0;
+  return KP_OK;
+}
+
+kp_status kp_set_window(void *ctx, int32_t on) {
+  if (!ctx) return fail(KP_ERR_INVALID, "ctx is NULL");
+  ((Ctx *)ctx)->window_enabled = on != 0;
+  return KP_OK;
+}
+
+kp_status kp_get_window_stats(void *ctx, int64_t *tried, int64_t *above, int64_t *below,
+                              int64_t *emitted) {
+  if (!ctx) return fail(KP_ERR_INVALID, "ctx is NULL");
+  const Ctx *c = (const Ctx *)ctx;
+  if (tried) *tried = c->win_tried;
+  if (above) *above = c->win_above;
+  if (below) *below = c->win_below;
+  if (emitted) *emitted = c->win_emitted;
   return KP_OK;
 }
 
@@ -892,7 +934,7 @@ kp_status plan_first_pass(BatchPlan *p, int dir, hipStream_t s) {
   HIP_TRY(kp_launch_batched_aux(1, nullptr, p->Kf, p->kst, p->lam_tab[dir], p->kin, p->klo, s));
   if (p->T > 0) HIP_TRY(kp_launch_sweep_batched(p->d[dir][1], p->geom, p->boff, p->n, p->GB, p->lds, s));
   HIP_TRY(kp_launch_batched_aux(0, p->coltab[dir], p->ncol, nullptr, nullptr, nullptr, nullptr, s));
-  HIP_TRY(kp_launch_scd_locate_select(p->kst, p->Kf, p->Bf, p->hs, p->hc, p->e1, p->e2, p->cap, p->pend, s));
+  HIP_TRY(kp_launch_scd_locate_select(p->kst, p->Kf, p->Bf, nullptr, p->hs, p->hc, p->e1, p->e2, p->cap, p->pend, nullptr, s));
   HIP_TRY(kp_launch_batched_aux(2, nullptr, p->Kf, p->kst, p->lam_tab[1 - dir], p->kin, p->klo, s));
   HIP_TRY(hipMemcpyAsync(p->pinned, p->pend, sizeof(int), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(p->pinned + 2, p->err, 8, hipMemcpyDeviceToHost, s));
@@ -924,7 +966,7 @@ kp_status plan_step(BatchPlan *p, int dir, double *stats_out, bool graph) {
     if (p->pinned[0] == 0) break;
     if (pass >= kMaxPasses) return fail(KP_ERR_INTERNAL, "SCD threshold search exceeded %d passes", kMaxPasses);
     if (p->T > 0) HIP_TRY(kp_launch_sweep_batched(p->d[dir][0], p->geom, p->boff, p->n, p->GB, p->lds, s));
-    HIP_TRY(kp_launch_scd_locate_select(p->kst, p->Kf, p->Bf, p->hs, p->hc, p->e1, p->e2, p->cap, p->pend, s));
+    HIP_TRY(kp_launch_scd_locate_select(p->kst, p->Kf, p->Bf, nullptr, p->hs, p->hc, p->e1, p->e2, p->cap, p->pend, nullptr, s));
     HIP_TRY(kp_launch_batched_aux(2, nullptr, p->Kf, p->kst, p->lam_tab[1 - dir], p->kin, p->klo, s));
     HIP_TRY(hipMemcpyAsync(p->pinned, p->pend, sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(p->pinned + 2, p->err, 8, hipMemcpyDeviceToHost, s));

@@ -27,6 +27,48 @@ __device__ __forceinline__ int exp_bucket(double v, double center, double delta)
 }
 
 
+// Breakpoint arithmetic of the walks.  For lines z_a = c_a - lambda b_a and
+// z_b = c_b - lambda b_b with b_a > b_b, the crossing is
+// fl(fl(c_a - c_b) / fl(b_a - b_b)) and line a ranks above line b for lambda
+// below it; a line's zero crossing is fl(c_a / b_a).  cr_gt / cr_ge decide
+// fl(num / den) > t and >= t for den > 0 from exact fma residual signs and
+// divide only when the quotient lies within one ulp of t, so that the
+// decisions agree with the divided crossings bit for bit.
+__device__ __forceinline__ bool cr_gt(double num, double den, double t) {   // t >= 0
+  const double r = fma(-t, den, num);            // sign of num - t*den, exact
+  if (!(r > 0.0)) return false;                  // quotient <= t
+  const double up = kdbl(dkey(t) + 1);           // next double above t
+  const double r2 = fma(-up, den, num);
+  if (r2 >= 0.0) return true;                    // quotient >= up
+  return num / den > t;
+}
+__device__ __forceinline__ bool cr_ge(double num, double den, double t) {   // t > 0
+  const double r = fma(-t, den, num);
+  if (r >= 0.0) return true;                     // quotient >= t
+  const double dn = kdbl(dkey(t) - 1);           // next double below t
+  const double r2 = fma(-dn, den, num);
+  if (!(r2 > 0.0)) return false;                 // quotient <= dn
+  return num / den >= t;
+}
+// Is the line (c, b), b >= 0, positive just above t (side > 0) or just below
+// t (side < 0, t > 0)?
+__device__ __forceinline__ bool line_pos(double c, double b, double t, int side) {
+  if (b == 0.0) return c > 0.0;
+  return side > 0 ? cr_gt(c, b, t) : cr_ge(c, b, t);
+}
+// Does line o rank above line s just above / below t?  Parallel lines keep
+// the order (c desc, index asc).
+__device__ __forceinline__ bool line_beats(double co, double bo, int o, double cs, double bs, int s,
+                                           double t, int side) {
+  if (bo == bs) return co > cs || (co == cs && o < s);
+  if (bo > bs) {
+    const double num = co - cs, den = bo - bs;
+    return side > 0 ? cr_gt(num, den, t) : cr_ge(num, den, t);
+  }
+  const double num = cs - co, den = bs - bo;
+  return side > 0 ? !cr_gt(num, den, t) : !cr_ge(num, den, t);
+}
+
 // Laminar-matroid greedy over the ranked items: accept an eligible item when
 // no node containing it is full.  Equivalent to Alg.1 (both return the unique
 // maximum-weight independent set under the strict order (p~ desc, j asc)).
@@ -100,7 +142,8 @@ __device__ __forceinline__ void record_event(const SweepArgs &a, const KState &k
 __device__ __forceinline__ void publish_block(const SweepArgs &a, int K, double *hs, uint32_t *hc,
                                               unsigned long long *hmin, unsigned long long *hmax,
                                               uint32_t *kcnt, uint32_t *kpos, uint32_t *kovf,
-                                              uint32_t *nstage, int tid, int nthreads, int bid) {
+                                              uint32_t *nstage, int tid, int nthreads, int bid,
+                                              const double *kcorr = nullptr) {
   for (int t = tid; t < K * KP_NB; t += nthreads) {
     if (hc[t]) {
       atomicAdd(&a.hist_sum[t], hs[t]);
@@ -110,6 +153,7 @@ __device__ __forceinline__ void publish_block(const SweepArgs &a, int K, double 
   for (int k = tid; k < K; k += nthreads) {
     if (kcnt[k]) kpos[k] = atomicAdd(&a.st[k].n_emit, kcnt[k]);
     if (kovf[k]) atomicOr(&a.st[k].overflow, 1);
+    if (kcorr && kcorr[k] != 0.0) atomicAdd(&a.st[k].corr, kcorr[k]);
     if (hmin[k] != ~0ull) {
       atomicMin((unsigned long long *)&a.st[k].hull_lo, hmin[k]);
       atomicMax((unsigned long long *)&a.st[k].hull_hi, hmax[k]);

@@ -20,7 +20,6 @@
 
 #define EW 4                 // waves per block
 #define ENT (EW * 64)
-#define EM 16                // largest M of this kernel
 
 // wave-wide sum in a fixed butterfly order; every lane gets lane 0's value
 __device__ __forceinline__ double wave_sum(double v) {
@@ -43,12 +42,318 @@ __device__ __forceinline__ void stage_dwords(const void *src, int n, void *dst, 
   }
 }
 
+// Per-wave scratch of the breakpoint phase (byte offsets in the wave's region).
+struct EllScratch {
+  int pt, bt, kt, msk, end;
+};
+__host__ __device__ inline EllScratch ell_scratch(int M, int D, int K) {
+  auto r16 = [](int b) { return (b + 15) & ~15; };
+  EllScratch x;
+  x.pt = 0;
+  x.bt = x.pt + r16(M * 64 * 8);
+  x.kt = x.bt + r16(M * D * 64 * 4);
+  x.msk = x.kt + r16(M * D * 64);
+  x.end = x.msk + r16(K * 64 * 2);
+  return x;
+}
+
+__device__ __forceinline__ bool walk_mode(int m) {
+  return m == KS_EXP || m == KS_EMIT_BUCKET || m == KS_HULL_BUCKET || m == KS_REFINE ||
+         m == KS_EMIT_RANGE || m == KS_WINDOW;
+}
+
+// Is S, the greedy set at lambda^t, still the greedy solution of the lines
+// z_j = c_j - lambda_k b_jk just above t (side > 0) or just below t (side < 0)?
+// Only relations that involve an item moving with k (A) can differ from those
+// at lambda^t.  S is the greedy solution iff its members stay positive and
+// every positive non-member closes a circuit with S (the members of the
+// innermost full set containing it) and ranks below every member of it.
+template <class BK>
+__device__ __forceinline__ bool window_keeps(uint64_t S, uint64_t A, uint64_t Bpos, const double *ptl,
+                                             int lane, BK bk, int k, const uint64_t *tmask,
+                                             const int *tcap, int L, double lk, double t, int side) {
+  auto circuit = [&](int o) -> uint64_t {
+    for (int l = 0; l < L; ++l) {
+      const uint64_t m = tmask[l];
+      if ((m >> o & 1) && popc64(S & m) >= tcap[l]) return S & m;
+    }
+    return 0;
+  };
+  auto line = [&](int j, double &c, double &b) {
+    b = (A >> j & 1) ? bk(j, k) : 0.0;
+    const double add = lk * b;
+    c = ptl[j * 64 + lane] + add;
+  };
+  for (uint64_t m = S & A; m; m &= m - 1) {
+    const int s = __ffsll((long long)m) - 1;
+    double c, b;
+    line(s, c, b);
+    if (!line_pos(c, b, t, side)) return false;
+  }
+  for (uint64_t m = A & ~S; m; m &= m - 1) {
+    const int o = __ffsll((long long)m) - 1;
+    double co, bo;
+    line(o, co, bo);
+    if (!line_pos(co, bo, t, side)) continue;
+    uint64_t circ = circuit(o);
+    if (!circ) return false;
+    for (; circ; circ &= circ - 1) {
+      const int s = __ffsll((long long)circ) - 1;
+      double cs, bs;
+      line(s, cs, bs);
+      if (line_beats(co, bo, o, cs, bs, s, t, side)) return false;
+    }
+  }
+  for (uint64_t m = Bpos & ~A; m; m &= m - 1) {
+    const int o = __ffsll((long long)m) - 1;
+    uint64_t circ = circuit(o) & A;
+    if (!circ) continue;
+    const double co = ptl[o * 64 + lane];
+    for (; circ; circ &= circ - 1) {
+      const int s = __ffsll((long long)circ) - 1;
+      double cs, bs;
+      line(s, cs, bs);
+      if (line_beats(co, 0.0, o, cs, bs, s, t, side)) return false;
+    }
+  }
+  return true;
+}
+
 struct EllGeom {
   int M, K, region;   // region: bytes of per-wave LDS
   int pad;
 };
 
-template <int D, bool SCD>
+// Breakpoint phase of one user (one lane) from its per-lane LDS scratch:
+// p~ (ptl), stored costs (btl) and their knapsacks (ktl), and the items
+// moving with each knapsack (mskl).  S is the greedy set at lambda^t, pos the
+// items with p~ > 0, perm the items ranked by (p~ desc, index asc).
+template <int D>
+__device__ __forceinline__ void scd_user(const SweepArgs &a, int M, int K, int L, int lane, bool act,
+                                         uint64_t S, uint64_t pos, uint64_t perm, double bmax,
+                                         const double *ptl, const float *btl, const uint8_t *ktl,
+                                         const uint16_t *mskl, const double *lam, const uint64_t *tmask,
+                                         const int *tcap, const KState *kst, const int *kmode,
+                                         const double *hwin, double *kcorr, double *hs, uint32_t *hc,
+                                         unsigned long long *hmin, unsigned long long *hmax,
+                                         uint32_t *kcnt, uint32_t *kovf, uint32_t *nstage) {
+  if (!act) return;
+  // cost of item j in knapsack k (j moves with k)
+  auto bk = [&](int j, int k) -> double {
+    if (D == 1) return (double)btl[j * 64 + lane];
+    const int t = ktl[(j * D) * 64 + lane] == k ? 0 : 1;
+    return (double)btl[(j * D + t) * 64 + lane];
+  };
+  // Window filter: no crossing of two of the user's lines (or of a line and
+  // zero) lies within h of lambda_k^t when every line that can turn positive
+  // there is farther than h * bmax (plus a rounding margin) from zero and from
+  // every other line: lines move against each other by at most
+  // |b_a - b_b| <= bmax per unit of lambda_k.  Lines below -H stay negative
+  // over every window and never matter.
+  double gmin = 1e300, gscale = 0.0;
+  if (hwin[K] > 0.0) {
+    const double H = hwin[K] * bmax * (1.0 + 0x1p-30) + 0x1p-36 * (1.0 + bmax * hwin[K]);
+    double prev = 0.0;
+    for (int r = 0; r < M; ++r) {
+      const int j = (int)((perm >> (4 * r)) & 15);
+      const double v = ptl[j * 64 + lane];
+      if (r == 0) gscale = fabs(v);
+      if (!(v > -H)) break;
+      const double av = fabs(v);
+      gmin = av < gmin ? av : gmin;
+      if (r > 0) { const double d = prev - v; gmin = d < gmin ? d : gmin; }
+      prev = v;
+    }
+    gscale = gscale + H;
+  }
+  // true when no breakpoint of this user lies in knapsack k's window
+  auto calm = [&](int k) -> bool {
+    const double h = hwin[k];
+    const double need = h * bmax * (1.0 + 0x1p-30) + 0x1p-36 * (1.0 + gscale + lam[k] * bmax + h * bmax);
+    return gmin > need;
+  };
+  // threshold element of every item against the greedy solution of the other
+  // items (valid when it is the only item that moves with lambda_k): the
+  // lowest member of the innermost full set holding a non-member, or for a
+  // member the best positive non-member whose innermost full set holds it;
+  // zlev marks items whose only competitor is zero
+  uint64_t tau = 0, zlev = 0;
+  {
+    uint64_t assigned = S;
+    for (int l = 0; l < L; ++l) {
+      const uint64_t m = tmask[l];
+      if (popc64(S & m) < tcap[l]) continue;
+      uint64_t pend = m & ~assigned;
+      if (!pend) continue;
+      int low = 0;
+      for (int r = M - 1; r >= 0; --r) {
+        const int j = (int)((perm >> (4 * r)) & 15);
+        if ((S & m) >> j & 1) { low = j; break; }
+      }
+      assigned |= pend;
+      while (pend) {
+        const int o = __ffsll((long long)pend) - 1;
+        pend &= pend - 1;
+        tau |= (uint64_t)low << (4 * o);
+      }
+    }
+    const uint64_t all = (M == 64) ? ~0ull : ((1ull << M) - 1);
+    zlev |= ~assigned & all;
+    uint64_t resolved = 0;
+    for (int r = 0; r < M && resolved != S; ++r) {
+      const int e = (int)((perm >> (4 * r)) & 15);
+      if ((S >> e & 1) || !(pos >> e & 1)) continue;
+      uint64_t lm = 0;
+      for (int l = 0; l < L; ++l) {
+        const uint64_t m = tmask[l];
+        if ((m >> e & 1) && popc64(S & m) >= tcap[l]) { lm = m; break; }
+      }
+      uint64_t nw = S & lm & ~resolved;
+      resolved |= nw;
+      while (nw) {
+        const int o = __ffsll((long long)nw) - 1;
+        nw &= nw - 1;
+        tau |= (uint64_t)e << (4 * o);
+      }
+    }
+    zlev |= S & ~resolved;
+  }
+  // one breakpoint per (item, knapsack) that moves alone; queue the others
+  uint64_t pending = 0;
+  for (int j = 0; j < M; ++j) {
+    for (int t = 0; t < D; ++t) {
+      const int k = ktl[(j * D + t) * 64 + lane];
+      if (k >= K) continue;
+      const int mode = kmode[k];
+      if (!walk_mode(mode)) continue;
+      if (mode == KS_WINDOW && calm(k)) continue;
+      const uint32_t A = mskl[k * 64 + lane];
+      if (A != (1u << j)) {
+        if (j == __ffs((int)A) - 1) pending |= 1ull << k;
+        continue;
+      }
+      const double lk = lam[k];
+      const double bo_d = (double)btl[(j * D + t) * 64 + lane];
+      const double add_o = lk * bo_d;
+      const double co = ptl[j * 64 + lane] + add_o;
+      double best = 0.0;
+      if (zlev >> j & 1) {
+        if (co > 0.0) best = co / bo_d;
+      } else {
+        const int th = (int)((tau >> (4 * j)) & 15);
+        const double bs_d = 0.0;
+        const double add_s = lk * bs_d;
+        const double cs = ptl[th * 64 + lane] + add_s;
+        const double num = co - cs;
+        const double den = bo_d - bs_d;
+        const double val = num / den;
+        if (val > 0.0) best = val;
+      }
+      if (best > 0.0)
+        record_event(a, kst[k], k, best, bo_d, mode, hs, hc, hmin, hmax, kcnt, kovf, nstage, blockIdx.x);
+      if (mode == KS_WINDOW) {
+        // consumption just above the window against the one at lambda^t
+        const double above = (best > 0.0 && dkey(best) > kst[k].khi) ? bo_d : 0.0;
+        const double now = (S >> j & 1) ? bo_d : 0.0;
+        if (above != now) atomicAdd(&kcorr[k], above - now);
+      }
+    }
+  }
+  // knapsacks moving several items: in a window pass, keep the greedy set
+  // when it stays optimal at both edges; otherwise walk exactly from above
+  // every breakpoint
+  while (pending) {
+    const int k = __ffsll((long long)pending) - 1;
+    pending &= pending - 1;
+    const int mode = kmode[k];
+    const uint64_t A = mskl[k * 64 + lane];
+    const double lk = lam[k];
+    if (mode == KS_WINDOW) {
+      const double whi = kst[k].whi, wlo = kst[k].wlo;
+      if (window_keeps(S, A, pos & ~S, ptl, lane, bk, k, tmask, tcap, L, lk, whi, 1) &&
+          window_keeps(S, A, pos & ~S, ptl, lane, bk, k, tmask, tcap, L, lk, wlo, wlo > 0.0 ? -1 : 1))
+        continue;
+    }
+    // start: only horizontal positive lines, in p~ order
+    uint64_t Sw = 0;
+    {
+      uint64_t blocked = 0;
+      const uint64_t elig = pos & ~A;
+      for (int r = 0; r < M; ++r) {
+        const int j = (int)((perm >> (4 * r)) & 15);
+        const uint64_t bit = 1ull << j;
+        if ((elig & bit) && !(blocked & bit)) {
+          Sw |= bit;
+          for (int l = 0; l < L; ++l) {
+            const uint64_t m = tmask[l];
+            if ((m & bit) && popc64(Sw & m) >= tcap[l]) blocked |= m;
+          }
+        }
+      }
+    }
+    double above = 0.0;
+    const int maxev = M * M + M + 8;
+    for (int ev = 0;; ++ev) {
+      if (ev >= maxev) { atomicAdd(a.err, 1ull); break; }
+      double best = 0.0;
+      int bo = -1, bs = -1;
+      uint64_t cand = A & ~Sw;
+      while (cand) {
+        const int o = __ffsll((long long)cand) - 1;
+        cand &= cand - 1;
+        const double bo_d = bk(o, k);
+        const double add_o = lk * bo_d;
+        const double co = ptl[o * 64 + lane] + add_o;
+        uint64_t circ = 0;
+        bool tight = false;
+        for (int l = 0; l < L; ++l) {
+          const uint64_t m = tmask[l];
+          if ((m >> o & 1) && popc64(Sw & m) >= tcap[l]) { circ = Sw & m; tight = true; break; }
+        }
+        if (!tight) {
+          if (co > 0.0) {
+            const double val = co / bo_d;
+            if (val > best) { best = val; bo = o; bs = -1; }
+          }
+        } else {
+          while (circ) {
+            const int s2 = __ffsll((long long)circ) - 1;
+            circ &= circ - 1;
+            const double bs_d = (A >> s2 & 1) ? bk(s2, k) : 0.0;
+            if (bs_d < bo_d) {
+              const double add_s = lk * bs_d;
+              const double cs = ptl[s2 * 64 + lane] + add_s;
+              const double num = co - cs;
+              const double den = bo_d - bs_d;
+              const double val = num / den;
+              if (val > best) { best = val; bo = o; bs = s2; }
+            }
+          }
+        }
+      }
+      if (bo < 0) break;
+      const double bo_d = bk(bo, k);
+      const double bsv = (bs >= 0 && (A >> bs & 1)) ? bk(bs, k) : 0.0;
+      const double v2 = bs >= 0 ? bo_d - bsv : bo_d;
+      if (mode == KS_WINDOW) {
+        const uint64_t key = dkey(best);
+        if (key < kst[k].klo) break;          // every later breakpoint is lower
+        if (key > kst[k].khi) above = above + v2;
+        else record_event(a, kst[k], k, best, v2, mode, hs, hc, hmin, hmax, kcnt, kovf, nstage, blockIdx.x);
+      } else {
+        record_event(a, kst[k], k, best, v2, mode, hs, hc, hmin, hmax, kcnt, kovf, nstage, blockIdx.x);
+      }
+      Sw = (Sw | (1ull << bo)) & ~(bs >= 0 ? (1ull << bs) : 0ull);
+    }
+    if (mode == KS_WINDOW) {
+      double now = 0.0;
+      for (uint64_t m = S & A; m; m &= m - 1) now = now + bk(__ffsll((long long)m) - 1, k);
+      if (above != now) atomicAdd(&kcorr[k], above - now);
+    }
+  }
+}
+
+template <int D, bool SCD, int EM>
 __global__ void __launch_bounds__(ENT) k_ell(const SweepArgs a, const EllGeom g) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -64,7 +369,11 @@ __global__ void __launch_bounds__(ENT) k_ell(const SweepArgs a, const EllGeom g)
   uint32_t *hc = nullptr, *kcnt = nullptr, *kpos = nullptr, *kovf = nullptr, *nstage = nullptr;
   int *kmode = nullptr;
   unsigned long long *hmin = nullptr, *hmax = nullptr;
+  double *kcorr = nullptr;
+  double *hwin = nullptr;
   if (SCD) {
+    kcorr = (double *)carve((size_t)K * 8);
+    hwin = (double *)carve((size_t)K * 8 + 8);   // [K] window half-widths (0: no window), [K] their max
     hs = (double *)carve((size_t)K * KP_NB * 8);
     hc = (uint32_t *)carve((size_t)K * KP_NB * 4);
     kmode = (int *)carve((size_t)K * 4);
@@ -85,9 +394,17 @@ __global__ void __launch_bounds__(ENT) k_ell(const SweepArgs a, const EllGeom g)
       kmode[t] = a.st[t].mode;
       kcnt[t] = 0u; kpos[t] = 0u; kovf[t] = 0u;
       hmin[t] = ~0ull; hmax[t] = 0ull;
+      kcorr[t] = 0.0;
+      hwin[t] = a.st[t].mode == KS_WINDOW ? KP_WIN_MULT * a.st[t].delta : 0.0;
     }
     for (int t = tid; t < K * KP_NB; t += ENT) { hs[t] = 0.0; hc[t] = 0u; }
     if (tid == 0) *nstage = 0u;
+  }
+  __syncthreads();
+  if (SCD && tid == 0) {
+    double m = 0.0;
+    for (int k = 0; k < K; ++k) m = hwin[k] > m ? hwin[k] : m;
+    hwin[K] = m;
   }
   __syncthreads();
   const int L = a.tree.L;
@@ -194,6 +511,11 @@ __global__ void __launch_bounds__(ENT) k_ell(const SweepArgs a, const EllGeom g)
       uint8_t *xo = a.x_out + (u0 + lane) * M;
       for (int j = 0; j < M; ++j) xo[j] = (uint8_t)(S >> j & 1);
     }
+    double bmax = 0.0;
+    if (SCD) {
+      #pragma unroll
+      for (int j = 0; j < EM * D; ++j) bmax = (double)vl[j] > bmax ? (double)vl[j] : bmax;
+    }
     if (a.want_stats) {
       const double sP = wave_sum(Pi), sG = wave_sum(Gi);
       if (lane == 0) {
@@ -225,180 +547,30 @@ __global__ void __launch_bounds__(ENT) k_ell(const SweepArgs a, const EllGeom g)
       __builtin_amdgcn_wave_barrier();
     }
     if (SCD) {
-      // per-lane scratch: p~ copy [EM][64], costs of the walked knapsack [EM][64],
-      // moving-item masks per knapsack [K][64]
-      double *ptl = (double *)wreg;
-      float *bkl = (float *)(wreg + (size_t)EM * 64 * 8);
-      uint16_t *mskl = (uint16_t *)(wreg + (size_t)EM * 64 * 12);
-      #pragma unroll
-      for (int j = 0; j < EM; ++j) if (j < M) ptl[j * 64 + lane] = pt[j];
+      // per-lane scratch over the dead staging area: p~ [M][64], the stored
+      // costs and their knapsacks [M*D][64], moving-item masks [K][64]
+      const EllScratch sl = ell_scratch(M, D, K);
+      double *ptl = (double *)(wreg + sl.pt);
+      float *btl = (float *)(wreg + sl.bt);
+      uint8_t *ktl = (uint8_t *)(wreg + sl.kt);
+      uint16_t *mskl = (uint16_t *)(wreg + sl.msk);
       for (int k = 0; k < K; ++k) mskl[k * 64 + lane] = 0;
       #pragma unroll
       for (int j = 0; j < EM; ++j) {
-        #pragma unroll
-        for (int t = 0; t < D; ++t) {
-          const int k = cl[j * D + t];
-          if ((unsigned)k < (unsigned)K) mskl[k * 64 + lane] = (uint16_t)(mskl[k * 64 + lane] | (1u << j));
-        }
-      }
-      // threshold element of every item against the greedy solution of the
-      // other items (valid when it is the only item that moves with lambda_k)
-      uint64_t tau = 0, zlev = 0;
-      {
-        uint64_t assigned = S;
-        for (int l = 0; l < L; ++l) {
-          const uint64_t m = tmask[l];
-          if (popc64(S & m) < tcap[l]) continue;
-          uint64_t pend = m & ~assigned;
-          if (!pend) continue;
-          int low = 0;
-          for (int r = M - 1; r >= 0; --r) {
-            const int j = (int)((perm >> (4 * r)) & 15);
-            if ((S & m) >> j & 1) { low = j; break; }
-          }
-          assigned |= pend;
-          while (pend) {
-            const int o = __ffsll((long long)pend) - 1;
-            pend &= pend - 1;
-            tau |= (uint64_t)low << (4 * o);
-          }
-        }
-        const uint64_t all = (M == 64) ? ~0ull : ((1ull << M) - 1);
-        zlev |= ~assigned & all;
-        uint64_t resolved = 0;
-        for (int r = 0; r < M && resolved != S; ++r) {
-          const int e = (int)((perm >> (4 * r)) & 15);
-          if ((S >> e & 1) || !(pos >> e & 1)) continue;
-          uint64_t lm = 0;
-          for (int l = 0; l < L; ++l) {
-            const uint64_t m = tmask[l];
-            if ((m >> e & 1) && popc64(S & m) >= tcap[l]) { lm = m; break; }
-          }
-          uint64_t nw = S & lm & ~resolved;
-          resolved |= nw;
-          while (nw) {
-            const int o = __ffsll((long long)nw) - 1;
-            nw &= nw - 1;
-            tau |= (uint64_t)e << (4 * o);
-          }
-        }
-        zlev |= S & ~resolved;
-      }
-      // one event per (item, knapsack) that moves alone; queue the others
-      uint64_t pending = 0;
-      #pragma unroll
-      for (int j = 0; j < EM; ++j) {
-        #pragma unroll
-        for (int t = 0; t < D; ++t) {
-          const int k = cl[j * D + t];
-          if (!act || (unsigned)k >= (unsigned)K) continue;
-          const int mode = kmode[k];
-          if (!(mode == KS_EXP || mode == KS_EMIT_BUCKET || mode == KS_HULL_BUCKET ||
-                mode == KS_REFINE || mode == KS_EMIT_RANGE))
-            continue;
-          const uint32_t A = mskl[k * 64 + lane];
-          if (A != (1u << j)) {
-            if (j == __ffs((int)A) - 1) pending |= 1ull << k;
-            continue;
-          }
-          const double lk = lam[k];
-          const double bo_d = (double)vl[j * D + t];
-          const double add_o = lk * bo_d;
-          const double co = pt[j] + add_o;
-          double best = 0.0;
-          if (zlev >> j & 1) {
-            if (co > 0.0) best = co / bo_d;
-          } else {
-            const int th = (int)((tau >> (4 * j)) & 15);
-            const double bs_d = 0.0;
-            const double add_s = lk * bs_d;
-            const double cs = ptl[th * 64 + lane] + add_s;
-            const double num = co - cs;
-            const double den = bo_d - bs_d;
-            const double val = num / den;
-            if (val > 0.0) best = val;
-          }
-          if (best > 0.0)
-            record_event(a, kst[k], k, best, bo_d, mode, hs, hc, hmin, hmax, kcnt, kovf, nstage, blockIdx.x);
-        }
-      }
-      // knapsacks moving several items: exact walk from above every breakpoint
-      while (pending) {
-        const int k = __ffsll((long long)pending) - 1;
-        pending &= pending - 1;
-        const int mode = kmode[k];
-        const uint64_t A = mskl[k * 64 + lane];
-        #pragma unroll
-        for (int j = 0; j < EM; ++j) {
+        if (j < M) {
+          ptl[j * 64 + lane] = pt[j];
           #pragma unroll
-          for (int t = 0; t < D; ++t)
-            if (cl[j * D + t] == k) bkl[j * 64 + lane] = vl[j * D + t];
-        }
-        const double lk = lam[k];
-        // start: only horizontal positive lines, in p~ order
-        uint64_t Sw = 0;
-        {
-          uint64_t blocked = 0;
-          const uint64_t elig = pos & ~A;
-          for (int r = 0; r < M; ++r) {
-            const int j = (int)((perm >> (4 * r)) & 15);
-            const uint64_t bit = 1ull << j;
-            if ((elig & bit) && !(blocked & bit)) {
-              Sw |= bit;
-              for (int l = 0; l < L; ++l) {
-                const uint64_t m = tmask[l];
-                if ((m & bit) && popc64(Sw & m) >= tcap[l]) blocked |= m;
-              }
-            }
+          for (int t = 0; t < D; ++t) {
+            const int k = cl[j * D + t];
+            const bool ok = (unsigned)k < (unsigned)K;
+            btl[(j * D + t) * 64 + lane] = vl[j * D + t];
+            ktl[(j * D + t) * 64 + lane] = (uint8_t)(ok ? k : 255);
+            if (ok) mskl[k * 64 + lane] = (uint16_t)(mskl[k * 64 + lane] | (1u << j));
           }
-        }
-        const int maxev = M * M + M + 8;
-        for (int ev = 0;; ++ev) {
-          if (ev >= maxev) { atomicAdd(a.err, 1ull); break; }
-          double best = 0.0;
-          int bo = -1, bs = -1;
-          uint64_t cand = A & ~Sw;
-          while (cand) {
-            const int o = __ffsll((long long)cand) - 1;
-            cand &= cand - 1;
-            const double bo_d = (double)bkl[o * 64 + lane];
-            const double add_o = lk * bo_d;
-            const double co = ptl[o * 64 + lane] + add_o;
-            uint64_t circ = 0;
-            bool tight = false;
-            for (int l = 0; l < L; ++l) {
-              const uint64_t m = tmask[l];
-              if ((m >> o & 1) && popc64(Sw & m) >= tcap[l]) { circ = Sw & m; tight = true; break; }
-            }
-            if (!tight) {
-              if (co > 0.0) {
-                const double val = co / bo_d;
-                if (val > best) { best = val; bo = o; bs = -1; }
-              }
-            } else {
-              while (circ) {
-                const int s = __ffsll((long long)circ) - 1;
-                circ &= circ - 1;
-                const double bs_d = (A >> s & 1) ? (double)bkl[s * 64 + lane] : 0.0;
-                if (bs_d < bo_d) {
-                  const double add_s = lk * bs_d;
-                  const double cs = ptl[s * 64 + lane] + add_s;
-                  const double num = co - cs;
-                  const double den = bo_d - bs_d;
-                  const double val = num / den;
-                  if (val > best) { best = val; bo = o; bs = s; }
-                }
-              }
-            }
-          }
-          if (bo < 0) break;
-          const double bo_d = (double)bkl[bo * 64 + lane];
-          const double bsv = (bs >= 0 && (A >> bs & 1)) ? (double)bkl[bs * 64 + lane] : 0.0;
-          const double v2 = bs >= 0 ? bo_d - bsv : bo_d;
-          Sw = (Sw | (1ull << bo)) & ~(bs >= 0 ? (1ull << bs) : 0ull);
-          record_event(a, kst[k], k, best, v2, mode, hs, hc, hmin, hmax, kcnt, kovf, nstage, blockIdx.x);
         }
       }
+      scd_user<D>(a, M, K, L, lane, act, S, pos, perm, bmax, ptl, btl, ktl, mskl, lam, tmask, tcap, kst,
+                  kmode, hwin, kcorr, hs, hc, hmin, hmax, kcnt, kovf, nstage);
       __builtin_amdgcn_s_waitcnt(0);
       __builtin_amdgcn_wave_barrier();
     }
@@ -411,7 +583,7 @@ __global__ void __launch_bounds__(ENT) k_ell(const SweepArgs a, const EllGeom g)
       a.partials[(size_t)blockIdx.x * (K + 2) + c] = s;
     }
   }
-  if (SCD) publish_block(a, K, hs, hc, hmin, hmax, kcnt, kpos, kovf, nstage, tid, ENT, blockIdx.x);
+  if (SCD) publish_block(a, K, hs, hc, hmin, hmax, kcnt, kpos, kovf, nstage, tid, ENT, blockIdx.x, kcorr);
 }
 
 size_t kp_ell_lds_bytes(int M, int K, int D, int L, bool scd, int *region_out) {
@@ -419,18 +591,39 @@ size_t kp_ell_lds_bytes(int M, int K, int D, int L, bool scd, int *region_out) {
   size_t region = (size_t)64 * M * 4 + (size_t)64 * M * D * 8;        // staged tile
   region = region > 4096 ? region : 4096;                               // consumption rows
   if (scd) {
-    const size_t need = (size_t)EM * 64 * 12 + (size_t)K * 64 * 2;     // p~, costs, masks
+    const size_t need = (size_t)ell_scratch(M, D, K).end;               // p~, costs, masks
     region = region > need ? region : need;
   }
   region = r16(region);
   size_t s = r16((size_t)K * 8) + r16((size_t)L * 8 + 8) + r16((size_t)L * 4 + 4) +
+             (scd ? r16((size_t)K * 8 + 8) : 0) +
              r16((size_t)EW * (K + 2) * 8);
   if (scd)
-    s += r16((size_t)K * sizeof(KState)) + r16((size_t)K * KP_NB * 8) + r16((size_t)K * KP_NB * 4) +
+    s += r16((size_t)K * 8) + r16((size_t)K * sizeof(KState)) + r16((size_t)K * KP_NB * 8) + r16((size_t)K * KP_NB * 4) +
          4 * r16((size_t)K * 4) + 2 * r16((size_t)K * 8) + r16(16);
   s += (size_t)EW * region;
   if (region_out) *region_out = (int)region;
   return s;
+}
+
+template <int D, bool SCD, int EM>
+static hipError_t launch_ell_t(const SweepArgs &a, const EllGeom &g, size_t lds, int grid,
+                               hipStream_t stream) {
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void *)k_ell<D, SCD, EM>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((k_ell<D, SCD, EM>), dim3(grid), dim3(ENT), lds, stream, a, g);
+  return hipGetLastError();
+}
+
+template <int D, bool SCD>
+static hipError_t launch_ell_m(const SweepArgs &a, const EllGeom &g, size_t lds, int grid,
+                               hipStream_t stream) {
+  if (g.M <= 8) return launch_ell_t<D, SCD, 8>(a, g, lds, grid, stream);
+  if (g.M <= 12) return launch_ell_t<D, SCD, 12>(a, g, lds, grid, stream);
+  return launch_ell_t<D, SCD, 16>(a, g, lds, grid, stream);
 }
 
 hipError_t kp_launch_ell(const SweepArgs &a, int D, int grid, bool scd, hipStream_t stream) {
@@ -438,21 +631,10 @@ hipError_t kp_launch_ell(const SweepArgs &a, int D, int grid, bool scd, hipStrea
   g.M = a.pr.M;
   g.K = a.pr.K;
   g.pad = 0;
+  if (g.M < 1 || g.M > 16 || (D != 1 && D != 2)) return hipErrorInvalidValue;
   const size_t lds = kp_ell_lds_bytes(g.M, g.K, D, a.tree.L, scd, &g.region);
-  const void *fn = D == 1 ? (scd ? (const void *)k_ell<1, true> : (const void *)k_ell<1, false>)
-                          : (scd ? (const void *)k_ell<2, true> : (const void *)k_ell<2, false>);
-  if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
-  if (D == 1) {
-    if (scd) hipLaunchKernelGGL((k_ell<1, true>), dim3(grid), dim3(ENT), lds, stream, a, g);
-    else hipLaunchKernelGGL((k_ell<1, false>), dim3(grid), dim3(ENT), lds, stream, a, g);
-  } else {
-    if (scd) hipLaunchKernelGGL((k_ell<2, true>), dim3(grid), dim3(ENT), lds, stream, a, g);
-    else hipLaunchKernelGGL((k_ell<2, false>), dim3(grid), dim3(ENT), lds, stream, a, g);
-  }
-  return hipGetLastError();
+  if (D == 1) return scd ? launch_ell_m<1, true>(a, g, lds, grid, stream) : launch_ell_m<1, false>(a, g, lds, grid, stream);
+  return scd ? launch_ell_m<2, true>(a, g, lds, grid, stream) : launch_ell_m<2, false>(a, g, lds, grid, stream);
 }
 
 // row r's entries start at r*D for every row (and row 0 at 0)

@@ -8,6 +8,8 @@
 #define KP_MAX_K_SCD 64        // per-block LDS histograms bound K for the SCD calls
 #define KP_CENTRAL_W 2         // exponential buckets |id| <= W are emitted in the first pass
 #define KP_SORT_MAX 4096       // candidates sorted in LDS by the selection kernel
+#define KP_WIN_MULT 2.0        // window half-width around lambda_k^t, in units of the last step bound
+#define KP_WIN_MAX_REL 0.125   // windows wider than this fraction of lambda_k^t are not tried
 
 // Laminar local constraints after pruning: only sets that can bind
 // (C_l < |S_l|), duplicates merged with the smaller cap, ordered subsets
@@ -44,8 +46,13 @@ enum {
   KS_REFINE = 4,       // linear key bins over [klo, khi]
   KS_EMIT_RANGE = 5,   // emit the events with key in [klo, khi]
   KS_SELECT_BUCKET = 6,// emitted events of bucket bstar are complete: select
-  KS_SELECT_RANGE = 7  // emitted events of [klo, khi] are complete: select
+  KS_SELECT_RANGE = 7, // emitted events of [klo, khi] are complete: select
+  KS_WINDOW = 8        // first pass around lambda_k^t: users whose greedy set stays optimal over
+                       // [wlo, whi] are only checked; the others emit the breakpoints inside it
+                       // and report how their consumption just above whi differs from x(lambda^t)
 };
+
+#define KS_FLAG_WINDOW 1u  // the key range of KS_SELECT_RANGE is a window: the threshold may lie outside
 
 struct KState {
   int mode;
@@ -53,13 +60,15 @@ struct KState {
   int shift;           // key-bin shift for KS_REFINE
   int overflow;        // emission exceeded the buffer
   uint32_t n_emit;     // emitted events (atomic)
-  uint32_t pad;
+  uint32_t flags;      // KS_FLAG_*
   double center;       // lambda_k^t
   double delta;        // central bucket half-width (a power of two)
   double F_above;      // sum of increments strictly above the current target
   double result;       // lambda_k^{t+1} once mode == KS_DONE
   uint64_t klo, khi;   // inclusive key range
   uint64_t hull_lo, hull_hi;  // atomics: key hull of the bucket's events
+  double wlo, whi;     // KS_WINDOW: breakpoints with wlo <= v1 <= whi are emitted (wlo may be 0)
+  double corr;         // KS_WINDOW (atomic): sum over users of C_ik(whi+) - v_ik(x(lambda^t))
 };
 
 struct SweepArgs {

@@ -557,7 +557,7 @@ __global__ void __launch_bounds__(256) k_reduce_stats(const double *partials, in
 // SCD threshold search
 // ---------------------------------------------------------------------------
 __global__ void k_scd_init(KState *st, int K, const double *lam_in, const uint8_t *kmask,
-                           const double *delta_hint) {
+                           const double *delta_hint, int window) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= K) return;
   KState s;
@@ -566,10 +566,11 @@ __global__ void k_scd_init(KState *st, int K, const double *lam_in, const uint8_
   s.shift = 0;
   s.overflow = 0;
   s.n_emit = 0;
-  s.pad = 0;
+  s.flags = 0;
   s.center = lam_in[k];
   double d = delta_hint ? delta_hint[k] : 0.0;
-  if (!(d > 0.0)) {
+  const bool hinted = d > 0.0;
+  if (!hinted) {
     // no history: 2^-10 of the multiplier (or 2^-30 absolute), a power of two
     const double base = lam_in[k] > 0x1p-20 ? lam_in[k] : 0x1p-20;
     d = ldexp(1.0, ilogb(base) - 10);
@@ -581,10 +582,35 @@ __global__ void k_scd_init(KState *st, int K, const double *lam_in, const uint8_
   s.khi = ~0ull;
   s.hull_lo = ~0ull;
   s.hull_hi = 0;
+  s.wlo = 0.0;
+  s.whi = 0.0;
+  s.corr = 0.0;
+  // a window around lambda_k^t when the last step was small against it
+  const double h = KP_WIN_MULT * d;
+  if (window && hinted && s.mode == KS_EXP && h <= KP_WIN_MAX_REL * s.center) {
+    s.mode = KS_WINDOW;
+    s.whi = s.center + h;
+    s.wlo = s.center - h > 0.0 ? s.center - h : 0.0;
+    s.klo = dkey(s.wlo);
+    s.khi = dkey(s.whi);
+  }
   st[k] = s;
 }
 
 __device__ __forceinline__ int bits_needed(uint64_t x) { return x ? 64 - __clzll((long long)x) : 0; }
+
+// Full search of the next pass: exponential buckets over every breakpoint.
+__device__ __forceinline__ void restart_full(KState &s) {
+  s.mode = KS_EXP;
+  s.flags = 0;
+  s.n_emit = 0;
+  s.overflow = 0;
+  s.F_above = 0.0;
+  s.klo = 0;
+  s.khi = ~0ull;
+  s.hull_lo = ~0ull;
+  s.hull_hi = 0;
+}
 
 __device__ __forceinline__ void set_refine(KState &s, uint64_t lo, uint64_t hi) {
   s.klo = lo;
@@ -595,8 +621,8 @@ __device__ __forceinline__ void set_refine(KState &s, uint64_t lo, uint64_t hi) 
 }
 
 // After a pass: pick the bin holding the threshold and choose the next step.
-__global__ void k_scd_locate(KState *st, int K, const double *B, double *hist_sum,
-                             uint32_t *hist_cnt, uint32_t emit_cap) {
+__global__ void k_scd_locate(KState *st, int K, const double *B, const double *R, double *hist_sum,
+                             uint32_t *hist_cnt, uint32_t emit_cap, unsigned int *win) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= K) return;
   KState s = st[k];
@@ -666,6 +692,18 @@ __global__ void k_scd_locate(KState *st, int K, const double *B, double *hist_su
   } else if (s.mode == KS_EMIT_RANGE) {
     if (!s.overflow) s.mode = KS_SELECT_RANGE;
     else set_refine(s, s.klo, s.khi);
+  } else if (s.mode == KS_WINDOW) {
+    // consumption just above the window, summed over users
+    const double above = R[k] + s.corr;
+    if (win) { atomicAdd(&win[0], 1u); atomicAdd(&win[3], s.n_emit); }
+    if (s.overflow || above > Bk) {
+      if (win) atomicAdd(&win[1], 1u);
+      restart_full(s);                  // the threshold lies above the window
+    } else {
+      s.mode = KS_SELECT_RANGE;         // [klo, khi] is the window
+      s.F_above = above;
+      s.flags |= KS_FLAG_WINDOW;
+    }
   }
   st[k] = s;
   for (int b = 0; b < KP_NB; ++b) { hist_sum[(size_t)k * KP_NB + b] = 0.0; hist_cnt[(size_t)k * KP_NB + b] = 0u; }
@@ -678,7 +716,7 @@ __global__ void k_scd_locate(KState *st, int K, const double *B, double *hist_su
 #define SEL_NT 1024
 __global__ void __launch_bounds__(SEL_NT) k_scd_select(KState *st, const double *B,
                                                        const double *emit_v1, const double *emit_v2,
-                                                       uint32_t emit_cap) {
+                                                       uint32_t emit_cap, unsigned int *win) {
   const int k = blockIdx.x;
   __shared__ KState s;
   __shared__ double hsum[256];
@@ -706,6 +744,34 @@ __global__ void __launch_bounds__(SEL_NT) k_scd_select(KState *st, const double 
     done = 0;
   }
   __syncthreads();
+  if (s.flags & KS_FLAG_WINDOW) {
+    // the threshold lies in the window iff the window's increments take the
+    // running sum past B_k
+    __shared__ double part[SEL_NT / 64];
+    double v = 0.0;
+    for (uint32_t e = tid; e < n; e += SEL_NT) v = v + V2[e];
+    for (int off = 32; off > 0; off >>= 1) v = v + __shfl_xor(v, off, 64);
+    if ((tid & 63) == 0) part[tid >> 6] = v;
+    __syncthreads();
+    if (tid == 0) {
+      double tot = Fab;
+      for (int w = 0; w < SEL_NT / 64; ++w) tot = tot + part[w];
+      if (!(tot > Bk)) {
+        if (s.wlo == 0.0) {             // every breakpoint is in the window
+          st[k].result = 0.0;
+          st[k].mode = KS_DONE;
+        } else {
+          KState r = s;                 // below the window: full search
+          restart_full(r);
+          st[k] = r;
+          if (win) atomicAdd(&win[2], 1u);
+        }
+        done = 2;
+      }
+    }
+    __syncthreads();
+    if (done == 2) return;
+  }
   // narrowing loop
   for (int it = 0; it < 80; ++it) {
     if (tid == 0) nsel = 0;
@@ -1245,7 +1311,7 @@ __global__ void k_scd_init_flat(KState *st, int Kf, const double *const *lam_in,
   s.shift = 0;
   s.overflow = 0;
   s.n_emit = 0;
-  s.pad = 0;
+  s.flags = 0;
   s.center = l;
   const double base = l > 0x1p-20 ? l : 0x1p-20;
   s.delta = ldexp(1.0, ilogb(base) - 10);
@@ -1363,18 +1429,19 @@ hipError_t kp_launch_reduce_stats(const double *partials, int nblk, int K, const
 }
 
 hipError_t kp_launch_scd_init(KState *st, int K, const double *lam_in, const uint8_t *kmask,
-                              const double *delta_hint, hipStream_t stream) {
+                              const double *delta_hint, int window, hipStream_t stream) {
   hipLaunchKernelGGL(k_scd_init, dim3((K + 63) / 64), dim3(64), 0, stream, st, K, lam_in, kmask,
-                     delta_hint);
+                     delta_hint, window);
   return hipGetLastError();
 }
 
-hipError_t kp_launch_scd_locate_select(KState *st, int K, const double *B, double *hist_sum,
-                                       uint32_t *hist_cnt, const double *ev1, const double *ev2,
-                                       uint32_t emit_cap, int *pending, hipStream_t stream) {
-  hipLaunchKernelGGL(k_scd_locate, dim3((K + 63) / 64), dim3(64), 0, stream, st, K, B, hist_sum,
-                     hist_cnt, emit_cap);
-  hipLaunchKernelGGL(k_scd_select, dim3(K), dim3(SEL_NT), 0, stream, st, B, ev1, ev2, emit_cap);
+hipError_t kp_launch_scd_locate_select(KState *st, int K, const double *B, const double *R,
+                                       double *hist_sum, uint32_t *hist_cnt, const double *ev1,
+                                       const double *ev2, uint32_t emit_cap, int *pending,
+                                       unsigned int *win, hipStream_t stream) {
+  hipLaunchKernelGGL(k_scd_locate, dim3((K + 63) / 64), dim3(64), 0, stream, st, K, B, R, hist_sum,
+                     hist_cnt, emit_cap, win);
+  hipLaunchKernelGGL(k_scd_select, dim3(K), dim3(SEL_NT), 0, stream, st, B, ev1, ev2, emit_cap, win);
   hipLaunchKernelGGL(k_count_pending, dim3(1), dim3(256), 0, stream, st, K, pending);
   return hipGetLastError();
 }

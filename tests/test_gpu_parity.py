@@ -345,3 +345,40 @@ def test_uniform_row_kernel_parity(name, mk):
             got = kp.kp_scd_sweep(prob, _lamd(torch, lam), ctx=ctx)["lam"].cpu().numpy()
             assert np.array_equal(got, want), (t, got, want)
         lam = want if t < 2 else np.random.default_rng(t).random(inst.K) * 2
+
+
+WINDOW_CASES = [
+    ("c3-N20000", lambda: kpgen.config_instance(3, N=20000)),
+    ("csr-d1-topq-N9000", lambda: kpgen.make_instance(9000, 12, 9, seed=43, Q=3, csr_d=1, budget_frac=0.1)),
+    ("csr-d2-laminar-M16", lambda: kpgen.make_instance(6000, 16, 7, seed=44, csr_d=2, budget_frac=0.08,
+                                                       tree=random_laminar(16, np.random.default_rng(5)))),
+]
+
+
+@gpu
+@pytest.mark.parametrize("name,mk", WINDOW_CASES, ids=[c[0] for c in WINDOW_CASES])
+def test_scd_window_trajectory(name, mk):
+    """SCD iterations whose threshold search starts with a window around the
+    previous multiplier (after the first sweep on a context): every update
+    equals the oracle's at the same lambda, with the window on and off,
+    including after a jump that puts the threshold outside the window."""
+    kp, torch = _kp()
+    print("case", name, flush=True)
+    inst = mk()
+    prob = kp.Problem.from_host(inst)
+    win = kp.Context()
+    full = kp.Context()
+    full.set_window(False)
+    lam = np.zeros(inst.K)
+    for t in range(14):
+        want = oracle.scd_sweep(inst, lam)
+        for ctx in (win, full):
+            got = kp.kp_scd_sweep(prob, _lamd(torch, lam), ctx=ctx)["lam"].cpu().numpy()
+            assert np.array_equal(got, want), (t, np.flatnonzero(got != want), got, want)
+        lam = want
+        if t == 9:   # jump: the next windows miss
+            lam = lam * np.where(np.arange(inst.K) % 2 == 0, 1.5, 0.5)
+    tried, above, below, emitted = win.window_stats()
+    print("window searches", tried, "above", above, "below", below, "emitted", emitted, flush=True)
+    assert tried > 0 and tried - above - below > 0
+    assert full.window_stats() == (0, 0, 0, 0)
