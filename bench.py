@@ -95,6 +95,85 @@ def time_to_gap(tol=1e-3):
             "oracle_gap_rel": ref[-1]["gap_rel"]}
 
 
+def copy_probe(nbytes):
+    """A plain device copy of known size (the scale reference for the HBM
+    byte counters)."""
+    import torch
+    torch.cuda.set_device(0)
+    n = nbytes // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "calls": 3}))
+
+
+def _csv_rows(path):
+    import csv
+    with open(path) as f:
+        return list(csv.DictReader(f))
+
+
+def summarize_trace(trace_dir, bench_log, kernel_sub):
+    """Markdown summary of a rocprofv3 --kernel-trace --stats run of bench.py:
+    the per-kernel statistics and the average duration of the timed sweep
+    launches (the last `launches` dispatches of the sweep kernel)."""
+    rec = next(json.loads(l) for l in open(bench_log) if l.startswith("{"))
+    stats = _csv_rows(os.path.join(trace_dir, "run_kernel_stats.csv"))
+    trace = _csv_rows(os.path.join(trace_dir, "run_kernel_trace.csv"))
+    disp = [r for r in trace if kernel_sub in r["Kernel_Name"]]
+    disp.sort(key=lambda r: int(r["Start_Timestamp"]))
+    n = rec["roofline"]["launches"]
+    timed = disp[-n:]
+    durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6 for r in timed]
+    avg = sum(durs) / len(durs)
+    out = [f"| kernel | calls | avg ms | total ms | % |", "|---|---|---|---|---|"]
+    for r in stats[:12]:
+        out.append(f"| `{r['Name'][:60]}` | {r['Calls']} | {float(r['AverageNs']) * 1e-6:.3f} | "
+                   f"{float(r['TotalDurationNs']) * 1e-6:.1f} | {float(r['Percentage']):.2f} |")
+    out.append("")
+    out.append(f"Timed sweep launches (last {n} dispatches of `{kernel_sub}`): "
+               f"average {avg:.3f} ms, min {min(durs):.3f}, max {max(durs):.3f}.")
+    out.append(f"bench.py's own HIP-event average over the same launches: "
+               f"{rec['roofline']['avg_launch_ms']:.3f} ms; "
+               f"{rec['roofline']['algo_bytes_per_launch'] / 1e9:.2f} GB algorithmic bytes per launch "
+               f"-> {rec['roofline']['algo_bytes_per_launch'] / (avg * 1e-3) / 1e9:.1f} GB/s "
+               f"from the trace.")
+    out.append(f"bench line: value {rec['value']:.4g} {rec['unit']}, ms_per_step {rec['ms_per_step']:.2f}, "
+               f"passes_per_step {rec['passes_per_step']}.")
+    print("\n".join(out))
+
+
+def summarize_pmc(fetch_dir, write_dir, cfetch_dir, cwrite_dir, kernel_sub, launches, workload,
+                  copy_bytes):
+    """HBM bytes per sweep launch from FETCH_SIZE / WRITE_SIZE (KiB per
+    dispatch), each scaled by what the same counter reads for a plain copy of
+    known size; written with the hash of the kernel sources they were taken on."""
+    def per_dispatch(d, counter, sub):
+        rows = [r for r in _csv_rows(os.path.join(d, "run_counter_collection.csv"))
+                if sub in r["Kernel_Name"] and r["Counter_Name"] == counter]
+        vals = {}
+        for r in rows:
+            vals[r["Dispatch_Id"]] = vals.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
+        return [vals[k] for k in sorted(vals, key=int)]
+    f = per_dispatch(fetch_dir, "FETCH_SIZE", kernel_sub)[-launches:]
+    w = per_dispatch(write_dir, "WRITE_SIZE", kernel_sub)[-launches:]
+    cf = per_dispatch(cfetch_dir, "FETCH_SIZE", "")
+    cw = per_dispatch(cwrite_dir, "WRITE_SIZE", "")
+    cf_k, cw_k = max(cf), max(cw)          # the copy dispatches (KiB)
+    sf = copy_bytes / (cf_k * 1024.0)
+    sw = copy_bytes / (cw_k * 1024.0)
+    fb = sum(f) / len(f) * 1024.0 * sf
+    wb = sum(w) / len(w) * 1024.0 * sw
+    rec = {"workload": workload, "kernel": kernel_sub, "kernel_hash": kernel_hash(),
+           "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
+           "hbm_bytes_per_launch": fb + wb, "fetch_scale": sf, "write_scale": sw,
+           "launches_averaged": len(f), "copy_probe_bytes": copy_bytes,
+           "copy_fetch_kib": cf_k, "copy_write_kib": cw_k}
+    print(json.dumps(rec, indent=1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,7 +183,25 @@ def main():
     ap.add_argument("--users", type=int, default=None, help="override N (testing only)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="run a plain device copy of BYTES (counter calibration) and exit")
+    ap.add_argument("--summarize-trace", nargs=3, metavar=("TRACE_DIR", "BENCH_LOG", "KERNEL"),
+                    help="print a markdown summary of a rocprofv3 kernel trace of bench.py and exit")
+    ap.add_argument("--summarize-pmc", nargs=8,
+                    metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR", "KERNEL",
+                             "LAUNCHES", "WORKLOAD", "COPY_BYTES"),
+                    help="print the HBM traffic record from rocprofv3 counter runs and exit")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
+        return
+    if args.summarize_pmc:
+        a = args.summarize_pmc
+        summarize_pmc(a[0], a[1], a[2], a[3], a[4], int(a[5]), a[6], int(a[7]))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the sweep shards by users; see the design notes). Run with --gpus 1.",
