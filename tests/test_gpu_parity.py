@@ -382,3 +382,98 @@ def test_scd_window_trajectory(name, mk):
     print("window searches", tried, "above", above, "below", below, "emitted", emitted, flush=True)
     assert tried > 0 and tried - above - below > 0
     assert full.window_stats() == (0, 0, 0, 0)
+
+
+@gpu
+@pytest.mark.parametrize("c,N", [(1, 10_000), (2, 2049), (3, 3001), (4, 700)])
+def test_device_generator_matches_host(c, N):
+    """The device generator writes the host generator's bytes and budgets."""
+    kp, torch = _kp()
+    from kpgen import device as kgd
+    print("config", c, "N", N, flush=True)
+    arrs, B, tree, meta = kgd.device_instance(c, 0, N=N)
+    host = kpgen.config_instance(c, N=N)
+    assert np.array_equal(arrs["p"].cpu().numpy(), host.p)
+    if host.b is not None:
+        assert np.array_equal(arrs["b"].cpu().numpy(), host.b)
+    else:
+        for key in ("rowptr", "col", "val"):
+            assert np.array_equal(arrs[key].cpu().numpy(), getattr(host, key)), key
+    assert np.array_equal(np.asarray(B), host.B)
+
+
+def _full_size_problem(kp, c):
+    from kpgen import device as kgd
+    arrs, B, tree, meta = kgd.device_instance(c, 0)
+    prob = kp.Problem(arrs["p"], B, tree.parent, tree.cap, tree.leaf_of_item, b=arrs.get("b"),
+                      rowptr=arrs.get("rowptr"), col=arrs.get("col"), val=arrs.get("val"),
+                      N=meta["N"], M=meta["M"], K=meta["K"])
+    return arrs, B, tree, meta, prob
+
+
+@gpu
+@pytest.mark.parametrize("c", [3, 2])
+def test_full_size_scd_sampled_parity(c):
+    """At the benchmark's full size and launch configuration: decisions of
+    sampled users equal the oracle's, g - P = lambda.(B - R), and every SCD
+    threshold satisfies coordinate optimality (consumption just above it fits
+    B_k, just below it does not), which holds at any size."""
+    kp, torch = _kp()
+    from kpgen import device as kgd
+    print("config", c, "full size", flush=True)
+    arrs, B, tree, meta, prob = _full_size_problem(kp, c)
+    N, M, K = meta["N"], meta["M"], meta["K"]
+    ctx = kp.Context()
+    lam = torch.zeros(K, dtype=torch.float64, device="cuda")
+    for t in range(7):
+        out = kp.kp_scd_sweep(prob, lam, ctx=ctx)
+        lam_prev, lam = lam, out["lam"]
+    print("window stats", ctx.window_stats(), flush=True)
+    # sampled users at lambda^t
+    ev = kp.kp_eval_dual(prob, lam_prev, want_x=True, ctx=ctx)
+    users = np.sort(np.random.default_rng(7).choice(N, 4096, replace=False))
+    sub = kgd.host_users(meta, B, tree, users)
+    ref = oracle.eval_dual(sub, lam_prev.cpu().numpy())
+    xg = ev["x"].view(N, M)[torch.from_numpy(users).cuda()].cpu().numpy().reshape(-1)
+    assert np.array_equal(xg, ref["x"])
+    R = ev["R"].cpu().numpy()
+    lp = lam_prev.cpu().numpy()
+    ident = ev["g"].item() - ev["P"].item() - float(np.dot(lp, np.asarray(B) - R))
+    assert abs(ident) <= 1e-9 * (abs(ev["g"].item()) + abs(ev["P"].item()))
+    # coordinate optimality of lambda^{t+1}
+    v = lam.cpu().numpy()
+    for k in range(K):
+        lo = lp.copy()
+        hi = lp.copy()
+        if v[k] > 0:
+            hi[k] = v[k] * (1 + 1e-9)
+            lo[k] = v[k] * (1 - 1e-9)
+            R_hi = kp.kp_eval_dual(prob, _lamd(torch, hi), ctx=ctx)["R"][k].item()
+            R_lo = kp.kp_eval_dual(prob, _lamd(torch, lo), ctx=ctx)["R"][k].item()
+            assert R_hi <= B[k] < R_lo, (k, R_hi, B[k], R_lo)
+        else:
+            hi[k] = 0.0
+            assert kp.kp_eval_dual(prob, _lamd(torch, hi), ctx=ctx)["R"][k].item() <= B[k]
+
+
+@gpu
+def test_full_size_autograd_sampled_parity():
+    """Configuration 4 at full size (N = 1e7, M = 20, K = 50): sampled users'
+    decisions at a random lambda equal the oracle's and the autograd gradient
+    is B - R."""
+    kp, torch = _kp()
+    from kpgen import device as kgd
+    print("config 4 full size", flush=True)
+    arrs, B, tree, meta, prob = _full_size_problem(kp, 4)
+    N, M, K = meta["N"], meta["M"], meta["K"]
+    lam_np = kpgen.random_lambdas(4000, 1, K, 1.0 / K)[0]
+    lam = torch.tensor(lam_np, device="cuda", requires_grad=True)
+    g = kp.DualFn.apply(lam, prob)
+    g.backward()
+    ev = kp.kp_eval_dual(prob, _lamd(torch, lam_np), want_x=True)
+    assert np.array_equal(lam.grad.cpu().numpy(), np.asarray(B) - ev["R"].cpu().numpy())
+    users = np.sort(np.random.default_rng(8).choice(N, 2048, replace=False))
+    sub = kgd.host_users(meta, B, tree, users)
+    ref = oracle.eval_dual(sub, lam_np)
+    xg = ev["x"].view(N, M)[torch.from_numpy(users).cuda()].cpu().numpy().reshape(-1)
+    assert np.array_equal(xg, ref["x"])
