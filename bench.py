@@ -48,22 +48,22 @@ def traffic_for(workload, bytes_per_launch):
 
 def cpu_baseline(cfg_id, seconds):
     """The oracle's SCD sweep timed on a bounded prefix of the same workload
-    (host-generated users, lambda = 0), on all host threads."""
+    (host-generated users, lambda = 0), on all host threads.  The prefix grows
+    until one sweep takes about `seconds`."""
     import numpy as np
     import kpgen
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    n = 2000
-    inst = kpgen.config_instance(cfg_id, N=n)
-    t0 = time.perf_counter()
-    oracle.scd_sweep(inst, np.zeros(inst.K))
-    dt = time.perf_counter() - t0
-    # scale the sample to about `seconds` of work
-    n = int(max(2000, min(2_000_000, n * seconds / max(dt, 1e-3))))
-    inst = kpgen.config_instance(cfg_id, N=n)
-    t0 = time.perf_counter()
-    oracle.scd_sweep(inst, np.zeros(inst.K))
-    dt = time.perf_counter() - t0
+    n_max = kpgen.CONFIGS[cfg_id]["N"]
+    n, dt = 20_000, 0.0
+    while True:
+        inst = kpgen.config_instance(cfg_id, N=n)
+        t0 = time.perf_counter()
+        oracle.scd_sweep(inst, np.zeros(inst.K))
+        dt = time.perf_counter() - t0
+        if dt >= 0.5 * seconds or n >= n_max:
+            break
+        n = int(min(n_max, n * min(16.0, max(1.5, seconds / max(dt, 1e-3)))))
     return {"value": n / dt, "unit": "user-solves/s", "cores": threads, "kind": "oracle",
             "sample": f"first {n} users of the same workload, one SCD sweep from lambda=0 "
                       f"({dt:.1f} s on {threads} threads)"}

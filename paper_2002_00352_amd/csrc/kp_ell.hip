@@ -121,7 +121,7 @@ __device__ __forceinline__ bool window_keeps(uint64_t S, uint64_t A, uint64_t Bp
 
 struct EllGeom {
   int M, K, region;   // region: bytes of per-wave LDS
-  int pad;
+  int rows;           // statistics rows (of 65 doubles) per chunk
 };
 
 // Breakpoint phase of one user (one lane) from its per-lane LDS scratch:
@@ -517,34 +517,41 @@ __global__ void __launch_bounds__(ENT) k_ell(const SweepArgs a, const EllGeom g)
       for (int j = 0; j < EM * D; ++j) bmax = (double)vl[j] > bmax ? (double)vl[j] : bmax;
     }
     if (a.want_stats) {
-      const double sP = wave_sum(Pi), sG = wave_sum(Gi);
-      if (lane == 0) {
-        wacc[wv * (K + 2) + K] = wacc[wv * (K + 2) + K] + sG;
-        wacc[wv * (K + 2) + K + 1] = wacc[wv * (K + 2) + K + 1] + sP;
-      }
-      // consumption, 8 knapsacks at a time through per-lane rows in the region
-      double *rows = (double *)wreg;   // [8][64]
-      for (int c0 = 0; c0 < K; c0 += 8) {
-        #pragma unroll
-        for (int q = 0; q < 8; ++q) rows[q * 64 + lane] = 0.0;
+      // per-lane rows [K + 2][65] (consumption per knapsack, G_i, P_i) over
+      // the dead staging area, g.rows of them at a time; lane q then sums row
+      // q over the users in lane order (fixed order; the odd row stride keeps
+      // the lanes on distinct banks)
+      double *rows = (double *)wreg;
+      const int KT = K + 2;
+      for (int c0 = 0; c0 < KT; c0 += g.rows) {
+        const int nq = KT - c0 < g.rows ? KT - c0 : g.rows;
+        for (int q = 0; q < nq; ++q) rows[q * 65 + lane] = 0.0;
+        if ((unsigned)(K - c0) < (unsigned)nq) rows[(K - c0) * 65 + lane] = Gi;
+        if ((unsigned)(K + 1 - c0) < (unsigned)nq) rows[(K + 1 - c0) * 65 + lane] = Pi;
         #pragma unroll
         for (int j = 0; j < EM; ++j) {
           if (S >> j & 1) {
             #pragma unroll
             for (int t = 0; t < D; ++t) {
               const int q = cl[j * D + t] - c0;
-              if ((unsigned)q < 8u) rows[q * 64 + lane] = rows[q * 64 + lane] + (double)vl[j * D + t];
+              if ((unsigned)q < (unsigned)nq && q < K - c0)
+                rows[q * 65 + lane] = rows[q * 65 + lane] + (double)vl[j * D + t];
             }
           }
         }
-        const int nq = K - c0 < 8 ? K - c0 : 8;
-        for (int q = 0; q < nq; ++q) {
-          const double s = wave_sum(rows[q * 64 + lane]);
-          if (lane == 0) wacc[wv * (K + 2) + c0 + q] = wacc[wv * (K + 2) + c0 + q] + s;
+        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_wave_barrier();
+        __asm__ volatile("" ::: "memory");
+        if (lane < nq) {
+          double sum = 0.0;
+          const double *row = rows + lane * 65;
+          for (int u = 0; u < 64; ++u) sum = sum + row[u];
+          wacc[wv * KT + c0 + lane] = wacc[wv * KT + c0 + lane] + sum;
         }
+        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_wave_barrier();
+        __asm__ volatile("" ::: "memory");
       }
-      __builtin_amdgcn_s_waitcnt(0);
-      __builtin_amdgcn_wave_barrier();
     }
     if (SCD) {
       // per-lane scratch over the dead staging area: p~ [M][64], the stored
@@ -589,7 +596,7 @@ __global__ void __launch_bounds__(ENT) k_ell(const SweepArgs a, const EllGeom g)
 size_t kp_ell_lds_bytes(int M, int K, int D, int L, bool scd, int *region_out) {
   auto r16 = [](size_t b) { return (b + 15) & ~(size_t)15; };
   size_t region = (size_t)64 * M * 4 + (size_t)64 * M * D * 8;        // staged tile
-  region = region > 4096 ? region : 4096;                               // consumption rows
+  region = region > (size_t)8 * 65 * 8 ? region : (size_t)8 * 65 * 8;  // statistics rows
   if (scd) {
     const size_t need = (size_t)ell_scratch(M, D, K).end;               // p~, costs, masks
     region = region > need ? region : need;
@@ -622,6 +629,7 @@ template <int D, bool SCD>
 static hipError_t launch_ell_m(const SweepArgs &a, const EllGeom &g, size_t lds, int grid,
                                hipStream_t stream) {
   if (g.M <= 8) return launch_ell_t<D, SCD, 8>(a, g, lds, grid, stream);
+  if (g.M <= 10) return launch_ell_t<D, SCD, 10>(a, g, lds, grid, stream);
   if (g.M <= 12) return launch_ell_t<D, SCD, 12>(a, g, lds, grid, stream);
   return launch_ell_t<D, SCD, 16>(a, g, lds, grid, stream);
 }
@@ -630,9 +638,10 @@ hipError_t kp_launch_ell(const SweepArgs &a, int D, int grid, bool scd, hipStrea
   EllGeom g;
   g.M = a.pr.M;
   g.K = a.pr.K;
-  g.pad = 0;
   if (g.M < 1 || g.M > 16 || (D != 1 && D != 2)) return hipErrorInvalidValue;
   const size_t lds = kp_ell_lds_bytes(g.M, g.K, D, a.tree.L, scd, &g.region);
+  g.rows = g.region / (65 * 8);
+  if (g.rows > g.K + 2) g.rows = g.K + 2;
   if (D == 1) return scd ? launch_ell_m<1, true>(a, g, lds, grid, stream) : launch_ell_m<1, false>(a, g, lds, grid, stream);
   return scd ? launch_ell_m<2, true>(a, g, lds, grid, stream) : launch_ell_m<2, false>(a, g, lds, grid, stream);
 }
