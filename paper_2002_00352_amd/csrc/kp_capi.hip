@@ -39,8 +39,9 @@ hipError_t kp_launch_fixup_pipeline(const double *uv, int nv, const double *G, i
                                     const double *P, double *R_out, double *P_out, int64_t *n_reset,
                                     void *scratch, hipStream_t stream, uint32_t *ncand_host_pinned);
 size_t kp_fixup_scratch_bytes(int64_t N, int nv, int K);
-size_t kp_ell_lds_bytes(int M, int K, int D, int L, bool scd, int *region_out);
-hipError_t kp_launch_ell(const SweepArgs &a, int D, int grid, bool scd, hipStream_t stream);
+size_t kp_ell_lds_bytes(int M, int K, int D, int L, int mode, int *region_out);
+hipError_t kp_launch_ell(const SweepArgs &a, int D, int grid, int mode, hipStream_t stream);
+hipError_t kp_launch_count_modes(const KState *st, int K, int *out, hipStream_t stream);
 hipError_t kp_launch_ell_check(const int64_t *rowptr, int64_t nrows, int D, unsigned int *bad,
                                hipStream_t stream);
 hipError_t kp_launch_sweep_batched(const SweepArgs *descs, const TileGeom *geoms,
@@ -349,7 +350,7 @@ kp_status choose_kernel(Ctx *c, Prepared &P, bool scd) {
     c->ell[key] = std::make_pair(D, nnz);
   }
   if (D == 0) return KP_OK;
-  if (kp_ell_lds_bytes(P.pr.M, P.pr.K, D, P.tree.L, scd, nullptr) > kMaxLds) return KP_OK;
+  if (kp_ell_lds_bytes(P.pr.M, P.pr.K, D, P.tree.L, scd ? 1 : 0, nullptr) > kMaxLds) return KP_OK;
   P.ell_D = D;
   P.ell_ntiles = (P.pr.N + 63) / 64;
   P.ell_grid = (int)std::max<int64_t>(1, std::min<int64_t>((P.ell_ntiles + 3) / 4, kEllGrid));
@@ -368,6 +369,9 @@ struct SweepWs {
   int *pending;
   unsigned int *win;    // window searches: [0] tried, [1] threshold above, [2] below
   uint32_t emit_cap;
+  unsigned int *flist, *fcount;   // users listed by the window pass
+  uint32_t fcap;
+  int *modes;           // [0] knapsacks with a window, [1] with another search mode
 };
 
 kp_status carve_ws(Ctx *c, const Prepared &P, bool scd, SweepWs &w) {
@@ -404,6 +408,15 @@ kp_status carve_ws(Ctx *c, const Prepared &P, bool scd, SweepWs &w) {
     o_s2 = cv.take((size_t)P.stage_grid() * scap * 8);
     o_sk = cv.take((size_t)P.stage_grid() * scap * 2);
   }
+  // users listed by a window pass of the uniform-row kernel (room for all)
+  size_t o_fl = 0, o_fc = 0, o_md = 0;
+  uint32_t fcap = 0;
+  if (scd && P.ell_D && P.pr.N < ((int64_t)1 << 32)) {
+    fcap = (uint32_t)std::max<int64_t>(64, P.pr.N);
+    o_fl = cv.take((size_t)fcap * 4);
+    o_fc = cv.take(16);
+  }
+  if (scd) o_md = cv.take(16);
   kp_status s = ensure_ws(c, cv.off);
   if (s != KP_OK) return s;
   char *b = (char *)c->ws;
@@ -426,6 +439,10 @@ kp_status carve_ws(Ctx *c, const Prepared &P, bool scd, SweepWs &w) {
   w.sv2 = scd ? (double *)(b + o_s2) : nullptr;
   w.sk = scd ? (uint16_t *)(b + o_sk) : nullptr;
   w.stage_cap = scap;
+  w.fcap = fcap;
+  w.flist = fcap ? (unsigned int *)(b + o_fl) : nullptr;
+  w.fcount = fcap ? (unsigned int *)(b + o_fc) : nullptr;
+  w.modes = scd ? (int *)(b + o_md) : nullptr;
   return KP_OK;
 }
 
@@ -436,7 +453,10 @@ double algo_bytes(const Prepared &P) {
   return -1.0;  // CSR: filled in by the caller from rowptr[N*M]
 }
 
-hipError_t timed_sweep(Ctx *c, const SweepArgs &a, const Prepared &P, bool scd, double bytes) {
+// One sweep pass between timing events.  split: the window pass of the
+// uniform-row kernel as two launches (all users, then the listed ones).
+hipError_t timed_sweep(Ctx *c, const SweepArgs &a, const Prepared &P, bool scd, double bytes,
+                       bool split = false) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (c->timing && P.ell_D) {
     bytes = P.ell_bytes;
@@ -460,10 +480,21 @@ hipError_t timed_sweep(Ctx *c, const SweepArgs &a, const Prepared &P, bool scd, 
     if (e0 && e1) (void)hipEventRecord(e0, c->stream);
   }
   hipError_t err;
-  if (P.ell_D) {
+  if (P.ell_D && split) {
     SweepArgs ae = a;
     ae.ntiles = P.ell_ntiles;
-    err = kp_launch_ell(ae, P.ell_D, P.ell_grid, scd, c->stream);
+    err = hipMemsetAsync(ae.fcount, 0, 4, c->stream);
+    if (err == hipSuccess) err = kp_launch_ell(ae, P.ell_D, P.ell_grid, 2, c->stream);
+    if (err == hipSuccess) {
+      SweepArgs af = ae;
+      af.want_stats = 0;
+      af.x_out = nullptr;
+      err = kp_launch_ell(af, P.ell_D, P.ell_grid, 3, c->stream);
+    }
+  } else if (P.ell_D) {
+    SweepArgs ae = a;
+    ae.ntiles = P.ell_ntiles;
+    err = kp_launch_ell(ae, P.ell_D, P.ell_grid, scd ? 1 : 0, c->stream);
   } else {
     err = kp_launch_sweep(a, P.U, P.grid, scd, c->stream);
   }
@@ -499,6 +530,9 @@ SweepArgs make_args(const Prepared &P, const double *lam, const SweepWs &w, uint
   a.stage_k = w.sk;
   a.stage_cap = w.stage_cap;
   a.err = w.err;
+  a.flist = w.flist;
+  a.fcount = w.fcount;
+  a.fcap = w.fcap;
   return a;
 }
 
@@ -637,6 +671,15 @@ kp_status kp_scd_sweep_masked(void *ctx, const kp_problem *prob, const double *l
   const int window = (c->window_enabled && P.ell_D && P.pr.N > 0) ? 1 : 0;
   HIP_TRY(kp_launch_scd_init(w.st, K, lambda_in, kmask ? w.kmask : nullptr,
                              c->delta_valid ? c->delta_dev : nullptr, window, c->stream));
+  // the first pass runs split (all users, then the listed ones) when every
+  // knapsack still searching starts with a window
+  bool split = false;
+  if (window && c->delta_valid && w.fcap) {
+    HIP_TRY(kp_launch_count_modes(w.st, K, w.modes, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->pinned + 20, w.modes, 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    split = c->pinned[20] > 0 && c->pinned[21] == 0;
+  }
   HIP_TRY(hipMemsetAsync(w.hist_sum, 0, (size_t)K * KP_NB * 8, c->stream));
   HIP_TRY(hipMemsetAsync(w.hist_cnt, 0, (size_t)K * KP_NB * 4, c->stream));
   HIP_TRY(hipMemsetAsync(w.err, 0, 8, c->stream));
@@ -650,7 +693,7 @@ kp_status kp_scd_sweep_masked(void *ctx, const kp_problem *prob, const double *l
     if (P.pr.N > 0) {
       SweepArgs a = make_args(P, lambda_in, w, nullptr, pass == 0);
       a.pass = pass;
-      HIP_TRY(timed_sweep(c, a, P, true, P.bytes));
+      HIP_TRY(timed_sweep(c, a, P, true, P.bytes, split && pass == 0));
     }
     if (pass == 0) {
       if (P.pr.N > 0) {

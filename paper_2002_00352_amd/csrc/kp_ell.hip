@@ -353,8 +353,17 @@ __device__ __forceinline__ void scd_user(const SweepArgs &a, int M, int K, int L
   }
 }
 
-template <int D, bool SCD, int EM>
+// Kernel modes: evaluation; full SCD pass (every search mode); the window
+// pass split in two -- the main kernel evaluates every user and lists the
+// users whose lines may cross inside some knapsack's window, the second kernel
+// gathers the listed users 64 per wave and runs their breakpoint phase with
+// every lane busy.
+enum { KM_EVAL = 0, KM_SCD = 1, KM_WMAIN = 2, KM_WFAIL = 3 };
+
+template <int D, int MODE, int EM>
 __global__ void __launch_bounds__(ENT) k_ell(const SweepArgs a, const EllGeom g) {
+  constexpr bool BREAK = (MODE == KM_SCD || MODE == KM_WFAIL);   // breakpoint phase
+  constexpr bool STAGED = (MODE != KM_WFAIL);                    // contiguous tiles
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int M = g.M, K = g.K;
@@ -364,19 +373,21 @@ __global__ void __launch_bounds__(ENT) k_ell(const SweepArgs a, const EllGeom g)
   uint64_t *tmask = (uint64_t *)carve((size_t)a.tree.L * 8 + 8);
   int *tcap = (int *)carve((size_t)a.tree.L * 4 + 4);
   double *wacc = (double *)carve((size_t)EW * (K + 2) * 8);
-  KState *kst = SCD ? (KState *)carve((size_t)K * sizeof(KState)) : nullptr;
+  KState *kst = BREAK ? (KState *)carve((size_t)K * sizeof(KState)) : nullptr;
   double *hs = nullptr;
   uint32_t *hc = nullptr, *kcnt = nullptr, *kpos = nullptr, *kovf = nullptr, *nstage = nullptr;
   int *kmode = nullptr;
   unsigned long long *hmin = nullptr, *hmax = nullptr;
   double *kcorr = nullptr;
   double *hwin = nullptr;
-  if (SCD) {
-    kcorr = (double *)carve((size_t)K * 8);
+  if (MODE != KM_EVAL) {
+    kmode = (int *)carve((size_t)K * 4);
     hwin = (double *)carve((size_t)K * 8 + 8);   // [K] window half-widths (0: no window), [K] their max
+  }
+  if (BREAK) {
+    kcorr = (double *)carve((size_t)K * 8);
     hs = (double *)carve((size_t)K * KP_NB * 8);
     hc = (uint32_t *)carve((size_t)K * KP_NB * 4);
-    kmode = (int *)carve((size_t)K * 4);
     kcnt = (uint32_t *)carve((size_t)K * 4);
     kpos = (uint32_t *)carve((size_t)K * 4);
     kovf = (uint32_t *)carve((size_t)K * 4);
@@ -388,66 +399,102 @@ __global__ void __launch_bounds__(ENT) k_ell(const SweepArgs a, const EllGeom g)
   for (int t = tid; t < K; t += ENT) lam[t] = a.lam[t];
   for (int t = tid; t < a.tree.L; t += ENT) { tmask[t] = a.tree.mask[t]; tcap[t] = a.tree.cap[t]; }
   for (int t = tid; t < EW * (K + 2); t += ENT) wacc[t] = 0.0;
-  if (SCD) {
+  if (MODE != KM_EVAL) {
+    for (int t = tid; t < K; t += ENT) {
+      kmode[t] = a.st[t].mode;
+      hwin[t] = a.st[t].mode == KS_WINDOW ? KP_WIN_MULT * a.st[t].delta : 0.0;
+    }
+  }
+  if (BREAK) {
     for (int t = tid; t < K; t += ENT) {
       kst[t] = a.st[t];
-      kmode[t] = a.st[t].mode;
       kcnt[t] = 0u; kpos[t] = 0u; kovf[t] = 0u;
       hmin[t] = ~0ull; hmax[t] = 0ull;
       kcorr[t] = 0.0;
-      hwin[t] = a.st[t].mode == KS_WINDOW ? KP_WIN_MULT * a.st[t].delta : 0.0;
     }
     for (int t = tid; t < K * KP_NB; t += ENT) { hs[t] = 0.0; hc[t] = 0u; }
     if (tid == 0) *nstage = 0u;
   }
   __syncthreads();
-  if (SCD && tid == 0) {
+  if (MODE != KM_EVAL && tid == 0) {
     double m = 0.0;
     for (int k = 0; k < K; ++k) m = hwin[k] > m ? hwin[k] : m;
     hwin[K] = m;
+  }
+  uint32_t nlisted = 0;
+  if (MODE == KM_WFAIL) {
+    const uint32_t cnt = *a.fcount;
+    nlisted = cnt < a.fcap ? cnt : a.fcap;
+    // a list that overflowed cannot be processed whole: full search instead
+    if (blockIdx.x == 0 && tid < K && cnt > a.fcap && a.st[tid].mode == KS_WINDOW)
+      atomicOr(&a.st[tid].overflow, 1);
   }
   __syncthreads();
   const int L = a.tree.L;
   const int64_t N = a.pr.N;
   const int64_t W = (int64_t)gridDim.x * EW;
+  const int64_t ntiles = MODE == KM_WFAIL ? ((int64_t)nlisted + 63) / 64 : a.ntiles;
 
-  for (int64_t tile = (int64_t)blockIdx.x * EW + wv; tile < a.ntiles; tile += W) {
+  for (int64_t tile = (int64_t)blockIdx.x * EW + wv; tile < ntiles; tile += W) {
     const int64_t u0 = tile * 64;
-    const int nu = (int)((N - u0) < 64 ? (N - u0) : 64);
-    const bool act = lane < nu;
-    // ---- stage the tile (coalesced) and move the lane's user into registers ----
-    float *sp = (float *)wreg;
-    int32_t *sc = (int32_t *)(wreg + (size_t)64 * M * 4);
-    float *sv = (float *)(wreg + (size_t)64 * M * 4 + (size_t)64 * M * D * 4);
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_wave_barrier();
-    stage_dwords(a.pr.p + u0 * M, nu * M, sp, lane);
-    stage_dwords(a.pr.col + u0 * M * D, nu * M * D, sc, lane);
-    stage_dwords(a.pr.val + u0 * M * D, nu * M * D, sv, lane);
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_wave_barrier();
-    __asm__ volatile("" ::: "memory");
     float pv[EM];
     int cl[EM * D];
     float vl[EM * D];
-    #pragma unroll
-    for (int j = 0; j < EM; ++j) {
-      if (j < M) {
-        pv[j] = act ? sp[lane * M + j] : 0.0f;
-        #pragma unroll
-        for (int t = 0; t < D; ++t) {
-          cl[j * D + t] = act ? sc[(lane * M + j) * D + t] : -1;
-          vl[j * D + t] = act ? sv[(lane * M + j) * D + t] : 0.0f;
+    bool act;
+    if (STAGED) {
+      // ---- stage the tile (coalesced) and move the lane's user into registers ----
+      const int nu = (int)((N - u0) < 64 ? (N - u0) : 64);
+      act = lane < nu;
+      float *sp = (float *)wreg;
+      int32_t *sc = (int32_t *)(wreg + (size_t)64 * M * 4);
+      float *sv = (float *)(wreg + (size_t)64 * M * 4 + (size_t)64 * M * D * 4);
+      __builtin_amdgcn_s_waitcnt(0);
+      __builtin_amdgcn_wave_barrier();
+      stage_dwords(a.pr.p + u0 * M, nu * M, sp, lane);
+      stage_dwords(a.pr.col + u0 * M * D, nu * M * D, sc, lane);
+      stage_dwords(a.pr.val + u0 * M * D, nu * M * D, sv, lane);
+      __builtin_amdgcn_s_waitcnt(0);
+      __builtin_amdgcn_wave_barrier();
+      __asm__ volatile("" ::: "memory");
+      #pragma unroll
+      for (int j = 0; j < EM; ++j) {
+        if (j < M) {
+          pv[j] = act ? sp[lane * M + j] : 0.0f;
+          #pragma unroll
+          for (int t = 0; t < D; ++t) {
+            cl[j * D + t] = act ? sc[(lane * M + j) * D + t] : -1;
+            vl[j * D + t] = act ? sv[(lane * M + j) * D + t] : 0.0f;
+          }
+        } else {
+          pv[j] = 0.0f;
+          #pragma unroll
+          for (int t = 0; t < D; ++t) { cl[j * D + t] = -1; vl[j * D + t] = 0.0f; }
         }
-      } else {
-        pv[j] = 0.0f;
-        #pragma unroll
-        for (int t = 0; t < D; ++t) { cl[j * D + t] = -1; vl[j * D + t] = 0.0f; }
+      }
+      __builtin_amdgcn_s_waitcnt(0);
+      __builtin_amdgcn_wave_barrier();
+      __asm__ volatile("" ::: "memory");
+    } else {
+      // ---- gather the listed user into registers ----
+      const int64_t idx = u0 + lane;
+      act = idx < (int64_t)nlisted;
+      const int64_t u = act ? (int64_t)a.flist[idx] : 0;
+      #pragma unroll
+      for (int j = 0; j < EM; ++j) {
+        if (j < M) {
+          pv[j] = act ? a.pr.p[u * M + j] : 0.0f;
+          #pragma unroll
+          for (int t = 0; t < D; ++t) {
+            cl[j * D + t] = act ? a.pr.col[(u * M + j) * D + t] : -1;
+            vl[j * D + t] = act ? a.pr.val[(u * M + j) * D + t] : 0.0f;
+          }
+        } else {
+          pv[j] = 0.0f;
+          #pragma unroll
+          for (int t = 0; t < D; ++t) { cl[j * D + t] = -1; vl[j * D + t] = 0.0f; }
+        }
       }
     }
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_wave_barrier();
-    __asm__ volatile("" ::: "memory");
     // ---- cost-adjusted profits ----
     double pt[EM];
     #pragma unroll
@@ -501,59 +548,105 @@ __global__ void __launch_bounds__(ENT) k_ell(const SweepArgs a, const EllGeom g)
         }
       }
     }
-    // ---- statistics: profit, group dual value, consumption ----
-    double Pi = 0.0, Gi = 0.0;
-    #pragma unroll
-    for (int j = 0; j < EM; ++j) {
-      if (S >> j & 1) { Pi = Pi + (double)pv[j]; Gi = Gi + pt[j]; }
-    }
-    if (a.x_out && act) {
-      uint8_t *xo = a.x_out + (u0 + lane) * M;
-      for (int j = 0; j < M; ++j) xo[j] = (uint8_t)(S >> j & 1);
-    }
     double bmax = 0.0;
-    if (SCD) {
+    if (MODE != KM_EVAL) {
       #pragma unroll
       for (int j = 0; j < EM * D; ++j) bmax = (double)vl[j] > bmax ? (double)vl[j] : bmax;
     }
-    if (a.want_stats) {
-      // per-lane rows [K + 2][65] (consumption per knapsack, G_i, P_i) over
-      // the dead staging area, g.rows of them at a time; lane q then sums row
-      // q over the users in lane order (fixed order; the odd row stride keeps
-      // the lanes on distinct banks)
-      double *rows = (double *)wreg;
-      const int KT = K + 2;
-      for (int c0 = 0; c0 < KT; c0 += g.rows) {
-        const int nq = KT - c0 < g.rows ? KT - c0 : g.rows;
-        for (int q = 0; q < nq; ++q) rows[q * 65 + lane] = 0.0;
-        if ((unsigned)(K - c0) < (unsigned)nq) rows[(K - c0) * 65 + lane] = Gi;
-        if ((unsigned)(K + 1 - c0) < (unsigned)nq) rows[(K + 1 - c0) * 65 + lane] = Pi;
-        #pragma unroll
-        for (int j = 0; j < EM; ++j) {
-          if (S >> j & 1) {
+    if (STAGED) {
+      // ---- statistics: profit, group dual value, consumption ----
+      double Pi = 0.0, Gi = 0.0;
+      #pragma unroll
+      for (int j = 0; j < EM; ++j) {
+        if (S >> j & 1) { Pi = Pi + (double)pv[j]; Gi = Gi + pt[j]; }
+      }
+      if (a.x_out && act) {
+        uint8_t *xo = a.x_out + (u0 + lane) * M;
+        for (int j = 0; j < M; ++j) xo[j] = (uint8_t)(S >> j & 1);
+      }
+      if (a.want_stats) {
+        // per-lane rows [K + 2][65] (consumption per knapsack, G_i, P_i) over
+        // the dead staging area, g.rows of them at a time; lane q then sums
+        // row q over the users in lane order (fixed order; the odd row stride
+        // keeps the lanes on distinct banks)
+        double *rows = (double *)wreg;
+        const int KT = K + 2;
+        for (int c0 = 0; c0 < KT; c0 += g.rows) {
+          const int nq = KT - c0 < g.rows ? KT - c0 : g.rows;
+          for (int q = 0; q < nq; ++q) rows[q * 65 + lane] = 0.0;
+          if ((unsigned)(K - c0) < (unsigned)nq) rows[(K - c0) * 65 + lane] = Gi;
+          if ((unsigned)(K + 1 - c0) < (unsigned)nq) rows[(K + 1 - c0) * 65 + lane] = Pi;
+          #pragma unroll
+          for (int j = 0; j < EM; ++j) {
+            if (S >> j & 1) {
+              #pragma unroll
+              for (int t = 0; t < D; ++t) {
+                const int q = cl[j * D + t] - c0;
+                if ((unsigned)q < (unsigned)nq && q < K - c0)
+                  rows[q * 65 + lane] = rows[q * 65 + lane] + (double)vl[j * D + t];
+              }
+            }
+          }
+          __builtin_amdgcn_s_waitcnt(0);
+          __builtin_amdgcn_wave_barrier();
+          __asm__ volatile("" ::: "memory");
+          if (lane < nq) {
+            double sum = 0.0;
+            const double *row = rows + lane * 65;
+            for (int u = 0; u < 64; ++u) sum = sum + row[u];
+            wacc[wv * KT + c0 + lane] = wacc[wv * KT + c0 + lane] + sum;
+          }
+          __builtin_amdgcn_s_waitcnt(0);
+          __builtin_amdgcn_wave_barrier();
+          __asm__ volatile("" ::: "memory");
+        }
+      }
+    }
+    if (MODE == KM_WMAIN) {
+      // Window filter from registers (the same test as the breakpoint phase):
+      // the smallest distance between two lines that can turn positive inside
+      // the widest window, or between such a line and zero.
+      const double H = hwin[K] * bmax * (1.0 + 0x1p-30) + 0x1p-36 * (1.0 + bmax * hwin[K]);
+      double gmin = 1e300, top = -1e300;
+      #pragma unroll
+      for (int j = 0; j < EM; ++j) {
+        if (j < M) {
+          top = pt[j] > top ? pt[j] : top;
+          if (pt[j] > -H) {
+            const double av = fabs(pt[j]);
+            gmin = av < gmin ? av : gmin;
             #pragma unroll
-            for (int t = 0; t < D; ++t) {
-              const int q = cl[j * D + t] - c0;
-              if ((unsigned)q < (unsigned)nq && q < K - c0)
-                rows[q * 65 + lane] = rows[q * 65 + lane] + (double)vl[j * D + t];
+            for (int jj = j + 1; jj < EM; ++jj) {
+              if (jj < M && pt[jj] > -H) {
+                const double d = fabs(pt[j] - pt[jj]);
+                gmin = d < gmin ? d : gmin;
+              }
             }
           }
         }
-        __builtin_amdgcn_s_waitcnt(0);
-        __builtin_amdgcn_wave_barrier();
-        __asm__ volatile("" ::: "memory");
-        if (lane < nq) {
-          double sum = 0.0;
-          const double *row = rows + lane * 65;
-          for (int u = 0; u < 64; ++u) sum = sum + row[u];
-          wacc[wv * KT + c0 + lane] = wacc[wv * KT + c0 + lane] + sum;
+      }
+      const double gscale = fabs(top) + H;
+      bool listed = false;
+      #pragma unroll
+      for (int j = 0; j < EM * D; ++j) {
+        const int k = cl[j];
+        if ((unsigned)k < (unsigned)K && kmode[k] == KS_WINDOW) {
+          const double h = hwin[k];
+          const double need = h * bmax * (1.0 + 0x1p-30) + 0x1p-36 * (1.0 + gscale + lam[k] * bmax + h * bmax);
+          if (!(gmin > need)) listed = true;
         }
-        __builtin_amdgcn_s_waitcnt(0);
-        __builtin_amdgcn_wave_barrier();
-        __asm__ volatile("" ::: "memory");
+      }
+      listed = listed && act;
+      const uint64_t mask = __ballot(listed);
+      if (mask) {
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(a.fcount, (uint32_t)__popcll(mask));
+        base = __shfl(base, 0, 64);
+        const uint32_t slot = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1));
+        if (listed && slot < a.fcap) a.flist[slot] = (uint32_t)(u0 + lane);
       }
     }
-    if (SCD) {
+    if (BREAK) {
       // per-lane scratch over the dead staging area: p~ [M][64], the stored
       // costs and their knapsacks [M*D][64], moving-item masks [K][64]
       const EllScratch sl = ell_scratch(M, D, K);
@@ -583,67 +676,84 @@ __global__ void __launch_bounds__(ENT) k_ell(const SweepArgs a, const EllGeom g)
     }
   }
   __syncthreads();
-  if (a.want_stats) {
+  if (a.want_stats && STAGED) {
     for (int c = tid; c < K + 2; c += ENT) {
       double s = 0.0;
       for (int w = 0; w < EW; ++w) s = s + wacc[w * (K + 2) + c];
       a.partials[(size_t)blockIdx.x * (K + 2) + c] = s;
     }
   }
-  if (SCD) publish_block(a, K, hs, hc, hmin, hmax, kcnt, kpos, kovf, nstage, tid, ENT, blockIdx.x, kcorr);
+  if (BREAK) publish_block(a, K, hs, hc, hmin, hmax, kcnt, kpos, kovf, nstage, tid, ENT, blockIdx.x, kcorr);
 }
 
-size_t kp_ell_lds_bytes(int M, int K, int D, int L, bool scd, int *region_out) {
+size_t kp_ell_lds_bytes(int M, int K, int D, int L, int mode, int *region_out) {
   auto r16 = [](size_t b) { return (b + 15) & ~(size_t)15; };
-  size_t region = (size_t)64 * M * 4 + (size_t)64 * M * D * 8;        // staged tile
-  region = region > (size_t)8 * 65 * 8 ? region : (size_t)8 * 65 * 8;  // statistics rows
-  if (scd) {
-    const size_t need = (size_t)ell_scratch(M, D, K).end;               // p~, costs, masks
+  const bool brk = mode == KM_SCD || mode == KM_WFAIL;
+  size_t region = 0;
+  if (mode != KM_WFAIL) {
+    region = (size_t)64 * M * 4 + (size_t)64 * M * D * 8;                     // staged tile
+    region = region > (size_t)8 * 65 * 8 ? region : (size_t)8 * 65 * 8;      // statistics rows
+  }
+  if (brk) {
+    const size_t need = (size_t)ell_scratch(M, D, K).end;                     // p~, costs, masks
     region = region > need ? region : need;
   }
   region = r16(region);
   size_t s = r16((size_t)K * 8) + r16((size_t)L * 8 + 8) + r16((size_t)L * 4 + 4) +
-             (scd ? r16((size_t)K * 8 + 8) : 0) +
              r16((size_t)EW * (K + 2) * 8);
-  if (scd)
-    s += r16((size_t)K * 8) + r16((size_t)K * sizeof(KState)) + r16((size_t)K * KP_NB * 8) + r16((size_t)K * KP_NB * 4) +
-         4 * r16((size_t)K * 4) + 2 * r16((size_t)K * 8) + r16(16);
+  if (mode != KM_EVAL) s += r16((size_t)K * 4) + r16((size_t)K * 8 + 8);
+  if (brk)
+    s += r16((size_t)K * 8) + r16((size_t)K * sizeof(KState)) + r16((size_t)K * KP_NB * 8) +
+         r16((size_t)K * KP_NB * 4) + 3 * r16((size_t)K * 4) + 2 * r16((size_t)K * 8) + r16(16);
   s += (size_t)EW * region;
   if (region_out) *region_out = (int)region;
   return s;
 }
 
-template <int D, bool SCD, int EM>
+template <int D, int MODE, int EM>
 static hipError_t launch_ell_t(const SweepArgs &a, const EllGeom &g, size_t lds, int grid,
                                hipStream_t stream) {
   if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_ell<D, SCD, EM>,
+    hipError_t e = hipFuncSetAttribute((const void *)k_ell<D, MODE, EM>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((k_ell<D, SCD, EM>), dim3(grid), dim3(ENT), lds, stream, a, g);
+  hipLaunchKernelGGL((k_ell<D, MODE, EM>), dim3(grid), dim3(ENT), lds, stream, a, g);
   return hipGetLastError();
 }
 
-template <int D, bool SCD>
+template <int D, int MODE>
 static hipError_t launch_ell_m(const SweepArgs &a, const EllGeom &g, size_t lds, int grid,
                                hipStream_t stream) {
-  if (g.M <= 8) return launch_ell_t<D, SCD, 8>(a, g, lds, grid, stream);
-  if (g.M <= 10) return launch_ell_t<D, SCD, 10>(a, g, lds, grid, stream);
-  if (g.M <= 12) return launch_ell_t<D, SCD, 12>(a, g, lds, grid, stream);
-  return launch_ell_t<D, SCD, 16>(a, g, lds, grid, stream);
+  if (g.M <= 8) return launch_ell_t<D, MODE, 8>(a, g, lds, grid, stream);
+  if (g.M <= 10) return launch_ell_t<D, MODE, 10>(a, g, lds, grid, stream);
+  if (g.M <= 12) return launch_ell_t<D, MODE, 12>(a, g, lds, grid, stream);
+  return launch_ell_t<D, MODE, 16>(a, g, lds, grid, stream);
 }
 
-hipError_t kp_launch_ell(const SweepArgs &a, int D, int grid, bool scd, hipStream_t stream) {
+template <int D>
+static hipError_t launch_ell_d(const SweepArgs &a, const EllGeom &g, size_t lds, int grid, int mode,
+                               hipStream_t stream) {
+  switch (mode) {
+    case KM_EVAL: return launch_ell_m<D, KM_EVAL>(a, g, lds, grid, stream);
+    case KM_SCD: return launch_ell_m<D, KM_SCD>(a, g, lds, grid, stream);
+    case KM_WMAIN: return launch_ell_m<D, KM_WMAIN>(a, g, lds, grid, stream);
+    case KM_WFAIL: return launch_ell_m<D, KM_WFAIL>(a, g, lds, grid, stream);
+  }
+  return hipErrorInvalidValue;
+}
+
+// mode: 0 evaluation, 1 full SCD pass, 2 window main pass, 3 listed users of a window pass
+hipError_t kp_launch_ell(const SweepArgs &a, int D, int grid, int mode, hipStream_t stream) {
   EllGeom g;
   g.M = a.pr.M;
   g.K = a.pr.K;
-  if (g.M < 1 || g.M > 16 || (D != 1 && D != 2)) return hipErrorInvalidValue;
-  const size_t lds = kp_ell_lds_bytes(g.M, g.K, D, a.tree.L, scd, &g.region);
+  if (g.M < 1 || g.M > 16 || (D != 1 && D != 2) || mode < 0 || mode > 3) return hipErrorInvalidValue;
+  const size_t lds = kp_ell_lds_bytes(g.M, g.K, D, a.tree.L, mode, &g.region);
   g.rows = g.region / (65 * 8);
   if (g.rows > g.K + 2) g.rows = g.K + 2;
-  if (D == 1) return scd ? launch_ell_m<1, true>(a, g, lds, grid, stream) : launch_ell_m<1, false>(a, g, lds, grid, stream);
-  return scd ? launch_ell_m<2, true>(a, g, lds, grid, stream) : launch_ell_m<2, false>(a, g, lds, grid, stream);
+  if (D == 1) return launch_ell_d<1>(a, g, lds, grid, mode, stream);
+  return launch_ell_d<2>(a, g, lds, grid, mode, stream);
 }
 
 // row r's entries start at r*D for every row (and row 0 at 0)

@@ -100,4 +100,8 @@ struct SweepArgs {
   double *uv_out;          // [N][nv] consumption of the selected knapsacks, or null
   const int *kv_map;       // [K] column in uv_out, or -1
   int nv;
+  // window pass split in two kernels: users listed by the first
+  unsigned int *flist;     // [fcap] user indices
+  unsigned int *fcount;    // listed users (atomic; may exceed fcap)
+  unsigned int fcap;
 };

@@ -887,6 +887,20 @@ __global__ void k_scd_finish(const KState *st, int K, const double *lam_in, doub
   }
 }
 
+// Knapsacks starting with a window and those needing another search mode.
+__global__ void k_count_modes(const KState *st, int K, int *out) {
+  __shared__ int c[2];
+  if (threadIdx.x < 2) c[threadIdx.x] = 0;
+  __syncthreads();
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    const int m = st[k].mode;
+    if (m == KS_WINDOW) atomicAdd(&c[0], 1);
+    else if (m != KS_DONE) atomicAdd(&c[1], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) out[threadIdx.x] = c[threadIdx.x];
+}
+
 __global__ void k_count_pending(const KState *st, int K, int *pending) {
   __shared__ int c;
   if (threadIdx.x == 0) c = 0;
@@ -1443,6 +1457,11 @@ hipError_t kp_launch_scd_locate_select(KState *st, int K, const double *B, const
                      hist_cnt, emit_cap, win);
   hipLaunchKernelGGL(k_scd_select, dim3(K), dim3(SEL_NT), 0, stream, st, B, ev1, ev2, emit_cap, win);
   hipLaunchKernelGGL(k_count_pending, dim3(1), dim3(256), 0, stream, st, K, pending);
+  return hipGetLastError();
+}
+
+hipError_t kp_launch_count_modes(const KState *st, int K, int *out, hipStream_t stream) {
+  hipLaunchKernelGGL(k_count_modes, dim3(1), dim3(256), 0, stream, st, K, out);
   return hipGetLastError();
 }
 
