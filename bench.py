@@ -21,7 +21,8 @@ sys.path.insert(0, ROOT)
 WORKLOADS = {"c1": 1, "c2": 2, "c3": 3, "c4": 4}
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_2002_00352_amd/csrc/kp_kernels.hip", "paper_2002_00352_amd/csrc/kp_ell.hip",
-                  "paper_2002_00352_amd/csrc/kp_device.h", "paper_2002_00352_amd/csrc/kp_internal.h"]
+                  "paper_2002_00352_amd/csrc/kp_ell_impl.h", "paper_2002_00352_amd/csrc/kp_device.h",
+                  "paper_2002_00352_amd/csrc/kp_internal.h"]
 
 
 def kernel_hash():

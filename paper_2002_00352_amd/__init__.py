@@ -18,8 +18,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _REPO = os.path.dirname(_HERE)
 LIB_PATH = os.path.join(_HERE, "libkp.so")
-SOURCES = [os.path.join(_HERE, "csrc", "kp_kernels.hip"), os.path.join(_HERE, "csrc", "kp_ell.hip"),
-           os.path.join(_HERE, "csrc", "kp_capi.hip")]
+SOURCES = [os.path.join(_HERE, "csrc", f) for f in
+           ("kp_kernels.hip", "kp_ell.hip", "kp_ell_m0.hip", "kp_ell_m1.hip", "kp_ell_m2.hip",
+            "kp_ell_m3.hip", "kp_capi.hip")]
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
                "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                "-Wno-unused-result"]
@@ -32,10 +33,22 @@ KP_B_DENSE, KP_B_CSR = 0, 1
 
 
 def build() -> str:
-    """Compile libkp.so for gfx950 with hipcc (always recompiles)."""
+    """Compile libkp.so for gfx950 with hipcc (always recompiles; the sources
+    are compiled in parallel, then linked)."""
+    import tempfile
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB_PATH + ".tmp"
-    subprocess.check_call([hipcc, *HIPCC_FLAGS, "-o", tmp, *SOURCES])
+    flags = [f for f in HIPCC_FLAGS if f != "-shared"]
+    with tempfile.TemporaryDirectory() as td:
+        objs, procs = [], []
+        for src in SOURCES:
+            obj = os.path.join(td, os.path.basename(src) + ".o")
+            objs.append(obj)
+            procs.append(subprocess.Popen([hipcc, *flags, "-c", "-o", obj, src]))
+        rcs = [p.wait() for p in procs]
+        if any(rcs):
+            raise subprocess.CalledProcessError(max(rcs, key=abs), hipcc)
+        tmp = LIB_PATH + ".tmp"
+        subprocess.check_call([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs])
     os.replace(tmp, LIB_PATH)
     return LIB_PATH
 

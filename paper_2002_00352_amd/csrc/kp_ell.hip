@@ -1,690 +1,6 @@
-// Lean sweep kernel for per-item CSR costs whose item rows all hold the same
-// number D of stored entries (row r's entries at [r*D, r*D + D)), M <= 16.
-//
-// One wave owns a tile of 64 users, one lane per user; waves never wait for
-// each other inside the tile loop.  The tile's profits and entries are staged
-// with coalesced direct-to-LDS loads and then moved into the lane's registers;
-// the staging area is reused as per-lane scratch for the rest of the tile.
-// Per lane: cost-adjusted profits (FP64, stored columns ascending, no FMA),
-// ranks by (p~ desc, index asc), the laminar greedy (Alg.1 as the matroid
-// greedy), its consumption / profit / dual sums, and for SCD every knapsack's
-// breakpoints: a knapsack moving one item of the user has at most one, at the
-// item's threshold element; knapsacks moving several items of the user are
-// queued and walked exactly once the one-item cases are done, so lanes walk
-// together.  Sums across users are atomic-free (fixed-order wave reductions,
-// waves added in order per block, blocks added in order by a second kernel).
-#include <hip/hip_runtime.h>
-#include <stdint.h>
-#include <string.h>
-#include "kp_device.h"
-
-#define EW 4                 // waves per block
-#define ENT (EW * 64)
-
-// wave-wide sum in a fixed butterfly order; every lane gets lane 0's value
-__device__ __forceinline__ double wave_sum(double v) {
-  #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = v + __shfl_xor(v, off, 64);
-  return __shfl(v, 0, 64);
-}
-
-typedef __attribute__((address_space(3))) void lds_void_t;
-
-// Copy n dwords from global src to LDS dst (coalesced; lanes past the end
-// reload the last dword into the padded tail of dst).
-__device__ __forceinline__ void stage_dwords(const void *src, int n, void *dst, int lane) {
-  const uint32_t *s = (const uint32_t *)src;
-  uint32_t *d = (uint32_t *)dst;
-  for (int c = 0; c * 64 < n; ++c) {
-    int i = c * 64 + lane;
-    i = i < n ? i : n - 1;
-    __builtin_amdgcn_global_load_lds((const void *)(s + i), (lds_void_t *)(d + c * 64), 4, 0, 0);
-  }
-}
-
-// Per-wave scratch of the breakpoint phase (byte offsets in the wave's region).
-struct EllScratch {
-  int pt, bt, kt, msk, end;
-};
-__host__ __device__ inline EllScratch ell_scratch(int M, int D, int K) {
-  auto r16 = [](int b) { return (b + 15) & ~15; };
-  EllScratch x;
-  x.pt = 0;
-  x.bt = x.pt + r16(M * 64 * 8);
-  x.kt = x.bt + r16(M * D * 64 * 4);
-  x.msk = x.kt + r16(M * D * 64);
-  x.end = x.msk + r16(K * 64 * 2);
-  return x;
-}
-
-__device__ __forceinline__ bool walk_mode(int m) {
-  return m == KS_EXP || m == KS_EMIT_BUCKET || m == KS_HULL_BUCKET || m == KS_REFINE ||
-         m == KS_EMIT_RANGE || m == KS_WINDOW;
-}
-
-// Is S, the greedy set at lambda^t, still the greedy solution of the lines
-// z_j = c_j - lambda_k b_jk just above t (side > 0) or just below t (side < 0)?
-// Only relations that involve an item moving with k (A) can differ from those
-// at lambda^t.  S is the greedy solution iff its members stay positive and
-// every positive non-member closes a circuit with S (the members of the
-// innermost full set containing it) and ranks below every member of it.
-template <class BK>
-__device__ __forceinline__ bool window_keeps(uint64_t S, uint64_t A, uint64_t Bpos, const double *ptl,
-                                             int lane, BK bk, int k, const uint64_t *tmask,
-                                             const int *tcap, int L, double lk, double t, int side) {
-  auto circuit = [&](int o) -> uint64_t {
-    for (int l = 0; l < L; ++l) {
-      const uint64_t m = tmask[l];
-      if ((m >> o & 1) && popc64(S & m) >= tcap[l]) return S & m;
-    }
-    return 0;
-  };
-  auto line = [&](int j, double &c, double &b) {
-    b = (A >> j & 1) ? bk(j, k) : 0.0;
-    const double add = lk * b;
-    c = ptl[j * 64 + lane] + add;
-  };
-  for (uint64_t m = S & A; m; m &= m - 1) {
-    const int s = __ffsll((long long)m) - 1;
-    double c, b;
-    line(s, c, b);
-    if (!line_pos(c, b, t, side)) return false;
-  }
-  for (uint64_t m = A & ~S; m; m &= m - 1) {
-    const int o = __ffsll((long long)m) - 1;
-    double co, bo;
-    line(o, co, bo);
-    if (!line_pos(co, bo, t, side)) continue;
-    uint64_t circ = circuit(o);
-    if (!circ) return false;
-    for (; circ; circ &= circ - 1) {
-      const int s = __ffsll((long long)circ) - 1;
-      double cs, bs;
-      line(s, cs, bs);
-      if (line_beats(co, bo, o, cs, bs, s, t, side)) return false;
-    }
-  }
-  for (uint64_t m = Bpos & ~A; m; m &= m - 1) {
-    const int o = __ffsll((long long)m) - 1;
-    uint64_t circ = circuit(o) & A;
-    if (!circ) continue;
-    const double co = ptl[o * 64 + lane];
-    for (; circ; circ &= circ - 1) {
-      const int s = __ffsll((long long)circ) - 1;
-      double cs, bs;
-      line(s, cs, bs);
-      if (line_beats(co, 0.0, o, cs, bs, s, t, side)) return false;
-    }
-  }
-  return true;
-}
-
-struct EllGeom {
-  int M, K, region;   // region: bytes of per-wave LDS
-  int rows;           // statistics rows (of 65 doubles) per chunk
-};
-
-// Breakpoint phase of one user (one lane) from its per-lane LDS scratch:
-// p~ (ptl), stored costs (btl) and their knapsacks (ktl), and the items
-// moving with each knapsack (mskl).  S is the greedy set at lambda^t, pos the
-// items with p~ > 0, perm the items ranked by (p~ desc, index asc).
-template <int D>
-__device__ __forceinline__ void scd_user(const SweepArgs &a, int M, int K, int L, int lane, bool act,
-                                         uint64_t S, uint64_t pos, uint64_t perm, double bmax,
-                                         const double *ptl, const float *btl, const uint8_t *ktl,
-                                         const uint16_t *mskl, const double *lam, const uint64_t *tmask,
-                                         const int *tcap, const KState *kst, const int *kmode,
-                                         const double *hwin, double *kcorr, double *hs, uint32_t *hc,
-                                         unsigned long long *hmin, unsigned long long *hmax,
-                                         uint32_t *kcnt, uint32_t *kovf, uint32_t *nstage) {
-  if (!act) return;
-  // cost of item j in knapsack k (j moves with k)
-  auto bk = [&](int j, int k) -> double {
-    if (D == 1) return (double)btl[j * 64 + lane];
-    const int t = ktl[(j * D) * 64 + lane] == k ? 0 : 1;
-    return (double)btl[(j * D + t) * 64 + lane];
-  };
-  // Window filter: no crossing of two of the user's lines (or of a line and
-  // zero) lies within h of lambda_k^t when every line that can turn positive
-  // there is farther than h * bmax (plus a rounding margin) from zero and from
-  // every other line: lines move against each other by at most
-  // |b_a - b_b| <= bmax per unit of lambda_k.  Lines below -H stay negative
-  // over every window and never matter.
-  double gmin = 1e300, gscale = 0.0;
-  if (hwin[K] > 0.0) {
-    const double H = hwin[K] * bmax * (1.0 + 0x1p-30) + 0x1p-36 * (1.0 + bmax * hwin[K]);
-    double prev = 0.0;
-    for (int r = 0; r < M; ++r) {
-      const int j = (int)((perm >> (4 * r)) & 15);
-      const double v = ptl[j * 64 + lane];
-      if (r == 0) gscale = fabs(v);
-      if (!(v > -H)) break;
-      const double av = fabs(v);
-      gmin = av < gmin ? av : gmin;
-      if (r > 0) { const double d = prev - v; gmin = d < gmin ? d : gmin; }
-      prev = v;
-    }
-    gscale = gscale + H;
-  }
-  // true when no breakpoint of this user lies in knapsack k's window
-  auto calm = [&](int k) -> bool {
-    const double h = hwin[k];
-    const double need = h * bmax * (1.0 + 0x1p-30) + 0x1p-36 * (1.0 + gscale + lam[k] * bmax + h * bmax);
-    return gmin > need;
-  };
-  // threshold element of every item against the greedy solution of the other
-  // items (valid when it is the only item that moves with lambda_k): the
-  // lowest member of the innermost full set holding a non-member, or for a
-  // member the best positive non-member whose innermost full set holds it;
-  // zlev marks items whose only competitor is zero
-  uint64_t tau = 0, zlev = 0;
-  {
-    uint64_t assigned = S;
-    for (int l = 0; l < L; ++l) {
-      const uint64_t m = tmask[l];
-      if (popc64(S & m) < tcap[l]) continue;
-      uint64_t pend = m & ~assigned;
-      if (!pend) continue;
-      int low = 0;
-      for (int r = M - 1; r >= 0; --r) {
-        const int j = (int)((perm >> (4 * r)) & 15);
-        if ((S & m) >> j & 1) { low = j; break; }
-      }
-      assigned |= pend;
-      while (pend) {
-        const int o = __ffsll((long long)pend) - 1;
-        pend &= pend - 1;
-        tau |= (uint64_t)low << (4 * o);
-      }
-    }
-    const uint64_t all = (M == 64) ? ~0ull : ((1ull << M) - 1);
-    zlev |= ~assigned & all;
-    uint64_t resolved = 0;
-    for (int r = 0; r < M && resolved != S; ++r) {
-      const int e = (int)((perm >> (4 * r)) & 15);
-      if ((S >> e & 1) || !(pos >> e & 1)) continue;
-      uint64_t lm = 0;
-      for (int l = 0; l < L; ++l) {
-        const uint64_t m = tmask[l];
-        if ((m >> e & 1) && popc64(S & m) >= tcap[l]) { lm = m; break; }
-      }
-      uint64_t nw = S & lm & ~resolved;
-      resolved |= nw;
-      while (nw) {
-        const int o = __ffsll((long long)nw) - 1;
-        nw &= nw - 1;
-        tau |= (uint64_t)e << (4 * o);
-      }
-    }
-    zlev |= S & ~resolved;
-  }
-  // one breakpoint per (item, knapsack) that moves alone; queue the others
-  uint64_t pending = 0;
-  for (int j = 0; j < M; ++j) {
-    for (int t = 0; t < D; ++t) {
-      const int k = ktl[(j * D + t) * 64 + lane];
-      if (k >= K) continue;
-      const int mode = kmode[k];
-      if (!walk_mode(mode)) continue;
-      if (mode == KS_WINDOW && calm(k)) continue;
-      const uint32_t A = mskl[k * 64 + lane];
-      if (A != (1u << j)) {
-        if (j == __ffs((int)A) - 1) pending |= 1ull << k;
-        continue;
-      }
-      const double lk = lam[k];
-      const double bo_d = (double)btl[(j * D + t) * 64 + lane];
-      const double add_o = lk * bo_d;
-      const double co = ptl[j * 64 + lane] + add_o;
-      double best = 0.0;
-      if (zlev >> j & 1) {
-        if (co > 0.0) best = co / bo_d;
-      } else {
-        const int th = (int)((tau >> (4 * j)) & 15);
-        const double bs_d = 0.0;
-        const double add_s = lk * bs_d;
-        const double cs = ptl[th * 64 + lane] + add_s;
-        const double num = co - cs;
-        const double den = bo_d - bs_d;
-        const double val = num / den;
-        if (val > 0.0) best = val;
-      }
-      if (best > 0.0)
-        record_event(a, kst[k], k, best, bo_d, mode, hs, hc, hmin, hmax, kcnt, kovf, nstage, blockIdx.x);
-      if (mode == KS_WINDOW) {
-        // consumption just above the window against the one at lambda^t
-        const double above = (best > 0.0 && dkey(best) > kst[k].khi) ? bo_d : 0.0;
-        const double now = (S >> j & 1) ? bo_d : 0.0;
-        if (above != now) atomicAdd(&kcorr[k], above - now);
-      }
-    }
-  }
-  // knapsacks moving several items: in a window pass, keep the greedy set
-  // when it stays optimal at both edges; otherwise walk exactly from above
-  // every breakpoint
-  while (pending) {
-    const int k = __ffsll((long long)pending) - 1;
-    pending &= pending - 1;
-    const int mode = kmode[k];
-    const uint64_t A = mskl[k * 64 + lane];
-    const double lk = lam[k];
-    if (mode == KS_WINDOW) {
-      const double whi = kst[k].whi, wlo = kst[k].wlo;
-      if (window_keeps(S, A, pos & ~S, ptl, lane, bk, k, tmask, tcap, L, lk, whi, 1) &&
-          window_keeps(S, A, pos & ~S, ptl, lane, bk, k, tmask, tcap, L, lk, wlo, wlo > 0.0 ? -1 : 1))
-        continue;
-    }
-    // start: only horizontal positive lines, in p~ order
-    uint64_t Sw = 0;
-    {
-      uint64_t blocked = 0;
-      const uint64_t elig = pos & ~A;
-      for (int r = 0; r < M; ++r) {
-        const int j = (int)((perm >> (4 * r)) & 15);
-        const uint64_t bit = 1ull << j;
-        if ((elig & bit) && !(blocked & bit)) {
-          Sw |= bit;
-          for (int l = 0; l < L; ++l) {
-            const uint64_t m = tmask[l];
-            if ((m & bit) && popc64(Sw & m) >= tcap[l]) blocked |= m;
-          }
-        }
-      }
-    }
-    double above = 0.0;
-    const int maxev = M * M + M + 8;
-    for (int ev = 0;; ++ev) {
-      if (ev >= maxev) { atomicAdd(a.err, 1ull); break; }
-      double best = 0.0;
-      int bo = -1, bs = -1;
-      uint64_t cand = A & ~Sw;
-      while (cand) {
-        const int o = __ffsll((long long)cand) - 1;
-        cand &= cand - 1;
-        const double bo_d = bk(o, k);
-        const double add_o = lk * bo_d;
-        const double co = ptl[o * 64 + lane] + add_o;
-        uint64_t circ = 0;
-        bool tight = false;
-        for (int l = 0; l < L; ++l) {
-          const uint64_t m = tmask[l];
-          if ((m >> o & 1) && popc64(Sw & m) >= tcap[l]) { circ = Sw & m; tight = true; break; }
-        }
-        if (!tight) {
-          if (co > 0.0) {
-            const double val = co / bo_d;
-            if (val > best) { best = val; bo = o; bs = -1; }
-          }
-        } else {
-          while (circ) {
-            const int s2 = __ffsll((long long)circ) - 1;
-            circ &= circ - 1;
-            const double bs_d = (A >> s2 & 1) ? bk(s2, k) : 0.0;
-            if (bs_d < bo_d) {
-              const double add_s = lk * bs_d;
-              const double cs = ptl[s2 * 64 + lane] + add_s;
-              const double num = co - cs;
-              const double den = bo_d - bs_d;
-              const double val = num / den;
-              if (val > best) { best = val; bo = o; bs = s2; }
-            }
-          }
-        }
-      }
-      if (bo < 0) break;
-      const double bo_d = bk(bo, k);
-      const double bsv = (bs >= 0 && (A >> bs & 1)) ? bk(bs, k) : 0.0;
-      const double v2 = bs >= 0 ? bo_d - bsv : bo_d;
-      if (mode == KS_WINDOW) {
-        const uint64_t key = dkey(best);
-        if (key < kst[k].klo) break;          // every later breakpoint is lower
-        if (key > kst[k].khi) above = above + v2;
-        else record_event(a, kst[k], k, best, v2, mode, hs, hc, hmin, hmax, kcnt, kovf, nstage, blockIdx.x);
-      } else {
-        record_event(a, kst[k], k, best, v2, mode, hs, hc, hmin, hmax, kcnt, kovf, nstage, blockIdx.x);
-      }
-      Sw = (Sw | (1ull << bo)) & ~(bs >= 0 ? (1ull << bs) : 0ull);
-    }
-    if (mode == KS_WINDOW) {
-      double now = 0.0;
-      for (uint64_t m = S & A; m; m &= m - 1) now = now + bk(__ffsll((long long)m) - 1, k);
-      if (above != now) atomicAdd(&kcorr[k], above - now);
-    }
-  }
-}
-
-// Kernel modes: evaluation; full SCD pass (every search mode); the window
-// pass split in two -- the main kernel evaluates every user and lists the
-// users whose lines may cross inside some knapsack's window, the second kernel
-// gathers the listed users 64 per wave and runs their breakpoint phase with
-// every lane busy.
-enum { KM_EVAL = 0, KM_SCD = 1, KM_WMAIN = 2, KM_WFAIL = 3 };
-
-template <int D, int MODE, int EM>
-__global__ void __launch_bounds__(ENT) k_ell(const SweepArgs a, const EllGeom g) {
-  constexpr bool BREAK = (MODE == KM_SCD || MODE == KM_WFAIL);   // breakpoint phase
-  constexpr bool STAGED = (MODE != KM_WFAIL);                    // contiguous tiles
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int M = g.M, K = g.K;
-  size_t off = 0;
-  auto carve = [&](size_t bytes) { unsigned char *p = smem + off; off += (bytes + 15) & ~(size_t)15; return p; };
-  double *lam = (double *)carve((size_t)K * 8);
-  uint64_t *tmask = (uint64_t *)carve((size_t)a.tree.L * 8 + 8);
-  int *tcap = (int *)carve((size_t)a.tree.L * 4 + 4);
-  double *wacc = (double *)carve((size_t)EW * (K + 2) * 8);
-  KState *kst = BREAK ? (KState *)carve((size_t)K * sizeof(KState)) : nullptr;
-  double *hs = nullptr;
-  uint32_t *hc = nullptr, *kcnt = nullptr, *kpos = nullptr, *kovf = nullptr, *nstage = nullptr;
-  int *kmode = nullptr;
-  unsigned long long *hmin = nullptr, *hmax = nullptr;
-  double *kcorr = nullptr;
-  double *hwin = nullptr;
-  if (MODE != KM_EVAL) {
-    kmode = (int *)carve((size_t)K * 4);
-    hwin = (double *)carve((size_t)K * 8 + 8);   // [K] window half-widths (0: no window), [K] their max
-  }
-  if (BREAK) {
-    kcorr = (double *)carve((size_t)K * 8);
-    hs = (double *)carve((size_t)K * KP_NB * 8);
-    hc = (uint32_t *)carve((size_t)K * KP_NB * 4);
-    kcnt = (uint32_t *)carve((size_t)K * 4);
-    kpos = (uint32_t *)carve((size_t)K * 4);
-    kovf = (uint32_t *)carve((size_t)K * 4);
-    hmin = (unsigned long long *)carve((size_t)K * 8);
-    hmax = (unsigned long long *)carve((size_t)K * 8);
-    nstage = (uint32_t *)carve(16);
-  }
-  unsigned char *wreg = smem + off + (size_t)wv * g.region;   // this wave's region
-  for (int t = tid; t < K; t += ENT) lam[t] = a.lam[t];
-  for (int t = tid; t < a.tree.L; t += ENT) { tmask[t] = a.tree.mask[t]; tcap[t] = a.tree.cap[t]; }
-  for (int t = tid; t < EW * (K + 2); t += ENT) wacc[t] = 0.0;
-  if (MODE != KM_EVAL) {
-    for (int t = tid; t < K; t += ENT) {
-      kmode[t] = a.st[t].mode;
-      hwin[t] = a.st[t].mode == KS_WINDOW ? KP_WIN_MULT * a.st[t].delta : 0.0;
-    }
-  }
-  if (BREAK) {
-    for (int t = tid; t < K; t += ENT) {
-      kst[t] = a.st[t];
-      kcnt[t] = 0u; kpos[t] = 0u; kovf[t] = 0u;
-      hmin[t] = ~0ull; hmax[t] = 0ull;
-      kcorr[t] = 0.0;
-    }
-    for (int t = tid; t < K * KP_NB; t += ENT) { hs[t] = 0.0; hc[t] = 0u; }
-    if (tid == 0) *nstage = 0u;
-  }
-  __syncthreads();
-  if (MODE != KM_EVAL && tid == 0) {
-    double m = 0.0;
-    for (int k = 0; k < K; ++k) m = hwin[k] > m ? hwin[k] : m;
-    hwin[K] = m;
-  }
-  uint32_t nlisted = 0;
-  if (MODE == KM_WFAIL) {
-    const uint32_t cnt = *a.fcount;
-    nlisted = cnt < a.fcap ? cnt : a.fcap;
-    // a list that overflowed cannot be processed whole: full search instead
-    if (blockIdx.x == 0 && tid < K && cnt > a.fcap && a.st[tid].mode == KS_WINDOW)
-      atomicOr(&a.st[tid].overflow, 1);
-  }
-  __syncthreads();
-  const int L = a.tree.L;
-  const int64_t N = a.pr.N;
-  const int64_t W = (int64_t)gridDim.x * EW;
-  const int64_t ntiles = MODE == KM_WFAIL ? ((int64_t)nlisted + 63) / 64 : a.ntiles;
-
-  for (int64_t tile = (int64_t)blockIdx.x * EW + wv; tile < ntiles; tile += W) {
-    const int64_t u0 = tile * 64;
-    float pv[EM];
-    int cl[EM * D];
-    float vl[EM * D];
-    bool act;
-    if (STAGED) {
-      // ---- stage the tile (coalesced) and move the lane's user into registers ----
-      const int nu = (int)((N - u0) < 64 ? (N - u0) : 64);
-      act = lane < nu;
-      float *sp = (float *)wreg;
-      int32_t *sc = (int32_t *)(wreg + (size_t)64 * M * 4);
-      float *sv = (float *)(wreg + (size_t)64 * M * 4 + (size_t)64 * M * D * 4);
-      __builtin_amdgcn_s_waitcnt(0);
-      __builtin_amdgcn_wave_barrier();
-      stage_dwords(a.pr.p + u0 * M, nu * M, sp, lane);
-      stage_dwords(a.pr.col + u0 * M * D, nu * M * D, sc, lane);
-      stage_dwords(a.pr.val + u0 * M * D, nu * M * D, sv, lane);
-      __builtin_amdgcn_s_waitcnt(0);
-      __builtin_amdgcn_wave_barrier();
-      __asm__ volatile("" ::: "memory");
-      #pragma unroll
-      for (int j = 0; j < EM; ++j) {
-        if (j < M) {
-          pv[j] = act ? sp[lane * M + j] : 0.0f;
-          #pragma unroll
-          for (int t = 0; t < D; ++t) {
-            cl[j * D + t] = act ? sc[(lane * M + j) * D + t] : -1;
-            vl[j * D + t] = act ? sv[(lane * M + j) * D + t] : 0.0f;
-          }
-        } else {
-          pv[j] = 0.0f;
-          #pragma unroll
-          for (int t = 0; t < D; ++t) { cl[j * D + t] = -1; vl[j * D + t] = 0.0f; }
-        }
-      }
-      __builtin_amdgcn_s_waitcnt(0);
-      __builtin_amdgcn_wave_barrier();
-      __asm__ volatile("" ::: "memory");
-    } else {
-      // ---- gather the listed user into registers ----
-      const int64_t idx = u0 + lane;
-      act = idx < (int64_t)nlisted;
-      const int64_t u = act ? (int64_t)a.flist[idx] : 0;
-      #pragma unroll
-      for (int j = 0; j < EM; ++j) {
-        if (j < M) {
-          pv[j] = act ? a.pr.p[u * M + j] : 0.0f;
-          #pragma unroll
-          for (int t = 0; t < D; ++t) {
-            cl[j * D + t] = act ? a.pr.col[(u * M + j) * D + t] : -1;
-            vl[j * D + t] = act ? a.pr.val[(u * M + j) * D + t] : 0.0f;
-          }
-        } else {
-          pv[j] = 0.0f;
-          #pragma unroll
-          for (int t = 0; t < D; ++t) { cl[j * D + t] = -1; vl[j * D + t] = 0.0f; }
-        }
-      }
-    }
-    // ---- cost-adjusted profits ----
-    double pt[EM];
-    #pragma unroll
-    for (int j = 0; j < EM; ++j) {
-      double acc = (double)pv[j];
-      #pragma unroll
-      for (int t = 0; t < D; ++t) {
-        const int k = cl[j * D + t];
-        if ((unsigned)k < (unsigned)K) {
-          const double prod = lam[k] * (double)vl[j * D + t];
-          acc = acc - prod;
-        }
-      }
-      pt[j] = acc;
-    }
-    // ---- ranks by (p~ desc, index asc), packed permutation ----
-    int rk[EM];
-    #pragma unroll
-    for (int j = 0; j < EM; ++j) rk[j] = 0;
-    #pragma unroll
-    for (int j = 0; j < EM; ++j) {
-      #pragma unroll
-      for (int jj = j + 1; jj < EM; ++jj) {
-        if (jj < M) {
-          if (pt[jj] > pt[j]) rk[j]++; else rk[jj]++;
-        }
-      }
-    }
-    uint64_t perm = 0, pos = 0;
-    #pragma unroll
-    for (int j = 0; j < EM; ++j) {
-      if (j < M) {
-        perm |= (uint64_t)j << (4 * rk[j]);
-        if (pt[j] > 0.0) pos |= 1ull << j;
-      }
-    }
-    if (!act) pos = 0;
-    // ---- greedy over the ranked items ----
-    uint64_t S = 0;
-    {
-      uint64_t blocked = 0;
-      for (int r = 0; r < M; ++r) {
-        const int j = (int)((perm >> (4 * r)) & 15);
-        const uint64_t bit = 1ull << j;
-        if ((pos & bit) && !(blocked & bit)) {
-          S |= bit;
-          for (int l = 0; l < L; ++l) {
-            const uint64_t m = tmask[l];
-            if ((m & bit) && popc64(S & m) >= tcap[l]) blocked |= m;
-          }
-        }
-      }
-    }
-    double bmax = 0.0;
-    if (MODE != KM_EVAL) {
-      #pragma unroll
-      for (int j = 0; j < EM * D; ++j) bmax = (double)vl[j] > bmax ? (double)vl[j] : bmax;
-    }
-    if (STAGED) {
-      // ---- statistics: profit, group dual value, consumption ----
-      double Pi = 0.0, Gi = 0.0;
-      #pragma unroll
-      for (int j = 0; j < EM; ++j) {
-        if (S >> j & 1) { Pi = Pi + (double)pv[j]; Gi = Gi + pt[j]; }
-      }
-      if (a.x_out && act) {
-        uint8_t *xo = a.x_out + (u0 + lane) * M;
-        for (int j = 0; j < M; ++j) xo[j] = (uint8_t)(S >> j & 1);
-      }
-      if (a.want_stats) {
-        // per-lane rows [K + 2][65] (consumption per knapsack, G_i, P_i) over
-        // the dead staging area, g.rows of them at a time; lane q then sums
-        // row q over the users in lane order (fixed order; the odd row stride
-        // keeps the lanes on distinct banks)
-        double *rows = (double *)wreg;
-        const int KT = K + 2;
-        for (int c0 = 0; c0 < KT; c0 += g.rows) {
-          const int nq = KT - c0 < g.rows ? KT - c0 : g.rows;
-          for (int q = 0; q < nq; ++q) rows[q * 65 + lane] = 0.0;
-          if ((unsigned)(K - c0) < (unsigned)nq) rows[(K - c0) * 65 + lane] = Gi;
-          if ((unsigned)(K + 1 - c0) < (unsigned)nq) rows[(K + 1 - c0) * 65 + lane] = Pi;
-          #pragma unroll
-          for (int j = 0; j < EM; ++j) {
-            if (S >> j & 1) {
-              #pragma unroll
-              for (int t = 0; t < D; ++t) {
-                const int q = cl[j * D + t] - c0;
-                if ((unsigned)q < (unsigned)nq && q < K - c0)
-                  rows[q * 65 + lane] = rows[q * 65 + lane] + (double)vl[j * D + t];
-              }
-            }
-          }
-          __builtin_amdgcn_s_waitcnt(0);
-          __builtin_amdgcn_wave_barrier();
-          __asm__ volatile("" ::: "memory");
-          if (lane < nq) {
-            double sum = 0.0;
-            const double *row = rows + lane * 65;
-            for (int u = 0; u < 64; ++u) sum = sum + row[u];
-            wacc[wv * KT + c0 + lane] = wacc[wv * KT + c0 + lane] + sum;
-          }
-          __builtin_amdgcn_s_waitcnt(0);
-          __builtin_amdgcn_wave_barrier();
-          __asm__ volatile("" ::: "memory");
-        }
-      }
-    }
-    if (MODE == KM_WMAIN) {
-      // Window filter from registers (the same test as the breakpoint phase):
-      // the smallest distance between two lines that can turn positive inside
-      // the widest window, or between such a line and zero.
-      const double H = hwin[K] * bmax * (1.0 + 0x1p-30) + 0x1p-36 * (1.0 + bmax * hwin[K]);
-      double gmin = 1e300, top = -1e300;
-      #pragma unroll
-      for (int j = 0; j < EM; ++j) {
-        if (j < M) {
-          top = pt[j] > top ? pt[j] : top;
-          if (pt[j] > -H) {
-            const double av = fabs(pt[j]);
-            gmin = av < gmin ? av : gmin;
-            #pragma unroll
-            for (int jj = j + 1; jj < EM; ++jj) {
-              if (jj < M && pt[jj] > -H) {
-                const double d = fabs(pt[j] - pt[jj]);
-                gmin = d < gmin ? d : gmin;
-              }
-            }
-          }
-        }
-      }
-      const double gscale = fabs(top) + H;
-      bool listed = false;
-      #pragma unroll
-      for (int j = 0; j < EM * D; ++j) {
-        const int k = cl[j];
-        if ((unsigned)k < (unsigned)K && kmode[k] == KS_WINDOW) {
-          const double h = hwin[k];
-          const double need = h * bmax * (1.0 + 0x1p-30) + 0x1p-36 * (1.0 + gscale + lam[k] * bmax + h * bmax);
-          if (!(gmin > need)) listed = true;
-        }
-      }
-      listed = listed && act;
-      const uint64_t mask = __ballot(listed);
-      if (mask) {
-        uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(a.fcount, (uint32_t)__popcll(mask));
-        base = __shfl(base, 0, 64);
-        const uint32_t slot = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1));
-        if (listed && slot < a.fcap) a.flist[slot] = (uint32_t)(u0 + lane);
-      }
-    }
-    if (BREAK) {
-      // per-lane scratch over the dead staging area: p~ [M][64], the stored
-      // costs and their knapsacks [M*D][64], moving-item masks [K][64]
-      const EllScratch sl = ell_scratch(M, D, K);
-      double *ptl = (double *)(wreg + sl.pt);
-      float *btl = (float *)(wreg + sl.bt);
-      uint8_t *ktl = (uint8_t *)(wreg + sl.kt);
-      uint16_t *mskl = (uint16_t *)(wreg + sl.msk);
-      for (int k = 0; k < K; ++k) mskl[k * 64 + lane] = 0;
-      #pragma unroll
-      for (int j = 0; j < EM; ++j) {
-        if (j < M) {
-          ptl[j * 64 + lane] = pt[j];
-          #pragma unroll
-          for (int t = 0; t < D; ++t) {
-            const int k = cl[j * D + t];
-            const bool ok = (unsigned)k < (unsigned)K;
-            btl[(j * D + t) * 64 + lane] = vl[j * D + t];
-            ktl[(j * D + t) * 64 + lane] = (uint8_t)(ok ? k : 255);
-            if (ok) mskl[k * 64 + lane] = (uint16_t)(mskl[k * 64 + lane] | (1u << j));
-          }
-        }
-      }
-      scd_user<D>(a, M, K, L, lane, act, S, pos, perm, bmax, ptl, btl, ktl, mskl, lam, tmask, tcap, kst,
-                  kmode, hwin, kcorr, hs, hc, hmin, hmax, kcnt, kovf, nstage);
-      __builtin_amdgcn_s_waitcnt(0);
-      __builtin_amdgcn_wave_barrier();
-    }
-  }
-  __syncthreads();
-  if (a.want_stats && STAGED) {
-    for (int c = tid; c < K + 2; c += ENT) {
-      double s = 0.0;
-      for (int w = 0; w < EW; ++w) s = s + wacc[w * (K + 2) + c];
-      a.partials[(size_t)blockIdx.x * (K + 2) + c] = s;
-    }
-  }
-  if (BREAK) publish_block(a, K, hs, hc, hmin, hmax, kcnt, kpos, kovf, nstage, tid, ENT, blockIdx.x, kcorr);
-}
+// Host entry points of the lean sweep kernel (kp_ell_impl.h): LDS sizing,
+// dispatch to the per-mode instantiations, and the uniform-row check.
+#include "kp_ell_impl.h"
 
 size_t kp_ell_lds_bytes(int M, int K, int D, int L, int mode, int *region_out) {
   auto r16 = [](size_t b) { return (b + 15) & ~(size_t)15; };
@@ -701,46 +17,14 @@ size_t kp_ell_lds_bytes(int M, int K, int D, int L, int mode, int *region_out) {
   region = r16(region);
   size_t s = r16((size_t)K * 8) + r16((size_t)L * 8 + 8) + r16((size_t)L * 4 + 4) +
              r16((size_t)EW * (K + 2) * 8);
-  if (mode != KM_EVAL) s += r16((size_t)K * 4) + r16((size_t)K * 8 + 8);
+  if (mode != KM_EVAL) s += r16((size_t)K * 4) + r16((size_t)K * 8 + 16);
+  if (mode == KM_WMAIN) s += r16((size_t)K * 8);
   if (brk)
     s += r16((size_t)K * 8) + r16((size_t)K * sizeof(KState)) + r16((size_t)K * KP_NB * 8) +
          r16((size_t)K * KP_NB * 4) + 3 * r16((size_t)K * 4) + 2 * r16((size_t)K * 8) + r16(16);
   s += (size_t)EW * region;
   if (region_out) *region_out = (int)region;
   return s;
-}
-
-template <int D, int MODE, int EM>
-static hipError_t launch_ell_t(const SweepArgs &a, const EllGeom &g, size_t lds, int grid,
-                               hipStream_t stream) {
-  if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_ell<D, MODE, EM>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL((k_ell<D, MODE, EM>), dim3(grid), dim3(ENT), lds, stream, a, g);
-  return hipGetLastError();
-}
-
-template <int D, int MODE>
-static hipError_t launch_ell_m(const SweepArgs &a, const EllGeom &g, size_t lds, int grid,
-                               hipStream_t stream) {
-  if (g.M <= 8) return launch_ell_t<D, MODE, 8>(a, g, lds, grid, stream);
-  if (g.M <= 10) return launch_ell_t<D, MODE, 10>(a, g, lds, grid, stream);
-  if (g.M <= 12) return launch_ell_t<D, MODE, 12>(a, g, lds, grid, stream);
-  return launch_ell_t<D, MODE, 16>(a, g, lds, grid, stream);
-}
-
-template <int D>
-static hipError_t launch_ell_d(const SweepArgs &a, const EllGeom &g, size_t lds, int grid, int mode,
-                               hipStream_t stream) {
-  switch (mode) {
-    case KM_EVAL: return launch_ell_m<D, KM_EVAL>(a, g, lds, grid, stream);
-    case KM_SCD: return launch_ell_m<D, KM_SCD>(a, g, lds, grid, stream);
-    case KM_WMAIN: return launch_ell_m<D, KM_WMAIN>(a, g, lds, grid, stream);
-    case KM_WFAIL: return launch_ell_m<D, KM_WFAIL>(a, g, lds, grid, stream);
-  }
-  return hipErrorInvalidValue;
 }
 
 // mode: 0 evaluation, 1 full SCD pass, 2 window main pass, 3 listed users of a window pass
@@ -752,8 +36,12 @@ hipError_t kp_launch_ell(const SweepArgs &a, int D, int grid, int mode, hipStrea
   const size_t lds = kp_ell_lds_bytes(g.M, g.K, D, a.tree.L, mode, &g.region);
   g.rows = g.region / (65 * 8);
   if (g.rows > g.K + 2) g.rows = g.K + 2;
-  if (D == 1) return launch_ell_d<1>(a, g, lds, grid, mode, stream);
-  return launch_ell_d<2>(a, g, lds, grid, mode, stream);
+  switch (mode) {
+    case KM_EVAL: return kp_launch_ell_mode<KM_EVAL>(a, g, lds, grid, D, stream);
+    case KM_SCD: return kp_launch_ell_mode<KM_SCD>(a, g, lds, grid, D, stream);
+    case KM_WMAIN: return kp_launch_ell_mode<KM_WMAIN>(a, g, lds, grid, D, stream);
+    default: return kp_launch_ell_mode<KM_WFAIL>(a, g, lds, grid, D, stream);
+  }
 }
 
 // row r's entries start at r*D for every row (and row 0 at 0)
