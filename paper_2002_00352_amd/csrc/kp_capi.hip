@@ -40,7 +40,8 @@ hipError_t kp_launch_fixup_pipeline(const double *uv, int nv, const double *G, i
                                     void *scratch, hipStream_t stream, uint32_t *ncand_host_pinned);
 size_t kp_fixup_scratch_bytes(int64_t N, int nv, int K);
 size_t kp_ell_lds_bytes(int M, int K, int D, int L, int mode, int *region_out);
-hipError_t kp_launch_ell(const SweepArgs &a, int D, int grid, int mode, hipStream_t stream);
+hipError_t kp_launch_ell(const SweepArgs &a, int D, int grid, int mode, hipStream_t stream, int *used);
+int kp_ell_resident_grid(int D, int mode, int M, int K, int L);
 hipError_t kp_launch_count_modes(const KState *st, int K, int *out, hipStream_t stream);
 hipError_t kp_launch_ell_check(const int64_t *rowptr, int64_t nrows, int D, unsigned int *bad,
                                hipStream_t stream);
@@ -84,7 +85,7 @@ constexpr int kMaxGrid = 2048;
 constexpr uint32_t kEmitCapDefault = 1u << 20;
 constexpr int kMaxPasses = 96;
 constexpr uint32_t kStageCap = 4096;    // staged events per block per pass (at least)
-constexpr uint32_t kStageCapMax = 32768;
+constexpr uint32_t kStageCapMax = 65536;
 constexpr uint32_t kEmitCapBatched = 1u << 16;   // emitted events per (instance, knapsack) per pass
 
 struct Ctx {
@@ -112,6 +113,8 @@ struct Ctx {
   std::map<std::pair<const int64_t *, int64_t>, std::pair<int, int64_t>> ell;
   bool ell_enabled = true;
   bool window_enabled = true;
+  int stats_grid = 0;     // blocks of the last sweep launch (slots of the per-block partials)
+  std::map<std::tuple<int, int, int, int>, std::pair<int, int>> ell_grids;  // (D, M, K, L) -> resident grids
   int64_t win_tried = 0, win_above = 0, win_below = 0;   // window searches since creation
   int64_t win_emitted = 0;                                 // breakpoints emitted inside windows
 };
@@ -194,6 +197,7 @@ struct Prepared {
   int ell_D = 0;
   int64_t ell_ntiles = 0;
   int ell_grid = 0;
+  int ell_brk_grid = 0;   // smallest grid of the lean kernel's breakpoint launches
   double ell_bytes = 0.0;
   int stage_grid() const { return std::max(grid, ell_grid); }
 };
@@ -353,7 +357,26 @@ kp_status choose_kernel(Ctx *c, Prepared &P, bool scd) {
   if (kp_ell_lds_bytes(P.pr.M, P.pr.K, D, P.tree.L, scd ? 1 : 0, nullptr) > kMaxLds) return KP_OK;
   P.ell_D = D;
   P.ell_ntiles = (P.pr.N + 63) / 64;
-  P.ell_grid = (int)std::max<int64_t>(1, std::min<int64_t>((P.ell_ntiles + 3) / 4, kEllGrid));
+  // per-block buffers for the largest resident grid of the lean kernel's
+  // modes; the staging of emitted events is sized for the smallest grid of
+  // its breakpoint modes (those blocks each take a larger share of the users)
+  int gmax = 0, gbrk = 0;
+  const auto gkey = std::make_tuple(D, (int)P.pr.M, (int)P.pr.K, (int)P.tree.L);
+  auto git = c->ell_grids.find(gkey);
+  if (git != c->ell_grids.end()) {
+    gmax = git->second.first;
+    gbrk = git->second.second;
+  } else {
+    for (int mode = 0; mode < 4; ++mode) {
+      const int r = kp_ell_resident_grid(D, mode, P.pr.M, P.pr.K, P.tree.L);
+      if (r <= 0) return fail(KP_ERR_HIP, "occupancy query failed");
+      gmax = std::max(gmax, r);
+      if (mode == 1 || mode == 3) gbrk = gbrk ? std::min(gbrk, r) : r;
+    }
+    c->ell_grids[gkey] = std::make_pair(gmax, gbrk);
+  }
+  P.ell_grid = (int)std::max<int64_t>(1, std::min<int64_t>((P.ell_ntiles + 3) / 4, std::min(gmax, kEllGrid)));
+  P.ell_brk_grid = std::max(1, std::min(gbrk, P.ell_grid));
   P.ell_bytes = (double)P.pr.N * P.pr.M * 4.0 + (double)nnz * 8.0;   // rowptr is not read
   return KP_OK;
 }
@@ -400,7 +423,8 @@ kp_status carve_ws(Ctx *c, const Prepared &P, bool scd, SweepWs &w) {
   // pairs so that large window passes do not overflow
   uint32_t scap = 0;
   if (scd) {
-    const double share = (double)P.pr.N * K / std::max(1, P.stage_grid()) / 64.0;
+    const int blocks = P.ell_D ? P.ell_brk_grid : P.stage_grid();
+    const double share = (double)P.pr.N * K / std::max(1, blocks) / 64.0;
     scap = (uint32_t)std::min<double>(kStageCapMax, std::max<double>(kStageCap, share));
   }
   if (scd) {
@@ -484,19 +508,20 @@ hipError_t timed_sweep(Ctx *c, const SweepArgs &a, const Prepared &P, bool scd, 
     SweepArgs ae = a;
     ae.ntiles = P.ell_ntiles;
     err = hipMemsetAsync(ae.fcount, 0, 4, c->stream);
-    if (err == hipSuccess) err = kp_launch_ell(ae, P.ell_D, P.ell_grid, 2, c->stream);
+    if (err == hipSuccess) err = kp_launch_ell(ae, P.ell_D, P.ell_grid, 2, c->stream, &c->stats_grid);
     if (err == hipSuccess) {
       SweepArgs af = ae;
       af.want_stats = 0;
       af.x_out = nullptr;
-      err = kp_launch_ell(af, P.ell_D, P.ell_grid, 3, c->stream);
+      err = kp_launch_ell(af, P.ell_D, P.ell_grid, 3, c->stream, nullptr);
     }
   } else if (P.ell_D) {
     SweepArgs ae = a;
     ae.ntiles = P.ell_ntiles;
-    err = kp_launch_ell(ae, P.ell_D, P.ell_grid, scd ? 1 : 0, c->stream);
+    err = kp_launch_ell(ae, P.ell_D, P.ell_grid, scd ? 1 : 0, c->stream, &c->stats_grid);
   } else {
     err = kp_launch_sweep(a, P.U, P.grid, scd, c->stream);
+    c->stats_grid = P.grid;
   }
   if (c->timing && e0 && e1) {
     (void)hipEventRecord(e1, c->stream);
@@ -546,7 +571,7 @@ kp_status eval_into(Ctx *c, const Prepared &P, const SweepWs &w, const double *l
   }
   SweepArgs a = make_args(P, lam, w, x, true);
   HIP_TRY(timed_sweep(c, a, P, false, P.bytes));
-  HIP_TRY(kp_launch_reduce_stats(w.partials, P.ell_D ? P.ell_grid : P.grid, P.pr.K, lam, w.B, R, g,
+  HIP_TRY(kp_launch_reduce_stats(w.partials, c->stats_grid, P.pr.K, lam, w.B, R, g,
                                  primal, c->stream));
   return KP_OK;
 }
@@ -697,7 +722,7 @@ kp_status kp_scd_sweep_masked(void *ctx, const kp_problem *prob, const double *l
     }
     if (pass == 0) {
       if (P.pr.N > 0) {
-        HIP_TRY(kp_launch_reduce_stats(w.partials, P.ell_D ? P.ell_grid : P.grid, K, lambda_in, w.B, Rd,
+        HIP_TRY(kp_launch_reduce_stats(w.partials, c->stats_grid, K, lambda_in, w.B, Rd,
                                        gd, Pd, c->stream));
       } else {
         HIP_TRY(hipMemsetAsync(w.partials, 0, (size_t)(K + 2) * 8, c->stream));

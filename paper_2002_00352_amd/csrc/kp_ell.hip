@@ -27,8 +27,10 @@ size_t kp_ell_lds_bytes(int M, int K, int D, int L, int mode, int *region_out) {
   return s;
 }
 
-// mode: 0 evaluation, 1 full SCD pass, 2 window main pass, 3 listed users of a window pass
-hipError_t kp_launch_ell(const SweepArgs &a, int D, int grid, int mode, hipStream_t stream) {
+// mode: 0 evaluation, 1 full SCD pass, 2 window main pass, 3 listed users of a window pass.
+// grid is an upper bound (the size of the per-block buffers); *used receives
+// the grid launched (the blocks that can be resident at once, at most grid).
+hipError_t kp_launch_ell(const SweepArgs &a, int D, int grid, int mode, hipStream_t stream, int *used) {
   EllGeom g;
   g.M = a.pr.M;
   g.K = a.pr.K;
@@ -37,10 +39,23 @@ hipError_t kp_launch_ell(const SweepArgs &a, int D, int grid, int mode, hipStrea
   g.rows = g.region / (65 * 8);
   if (g.rows > g.K + 2) g.rows = g.K + 2;
   switch (mode) {
-    case KM_EVAL: return kp_launch_ell_mode<KM_EVAL>(a, g, lds, grid, D, stream);
-    case KM_SCD: return kp_launch_ell_mode<KM_SCD>(a, g, lds, grid, D, stream);
-    case KM_WMAIN: return kp_launch_ell_mode<KM_WMAIN>(a, g, lds, grid, D, stream);
-    default: return kp_launch_ell_mode<KM_WFAIL>(a, g, lds, grid, D, stream);
+    case KM_EVAL: return kp_launch_ell_mode<KM_EVAL>(a, g, lds, grid, D, stream, used);
+    case KM_SCD: return kp_launch_ell_mode<KM_SCD>(a, g, lds, grid, D, stream, used);
+    case KM_WMAIN: return kp_launch_ell_mode<KM_WMAIN>(a, g, lds, grid, D, stream, used);
+    default: return kp_launch_ell_mode<KM_WFAIL>(a, g, lds, grid, D, stream, used);
+  }
+}
+
+// Blocks of the given mode that can be resident on the device at once (the
+// grid kp_launch_ell launches at most); 0 when the query fails.
+int kp_ell_resident_grid(int D, int mode, int M, int K, int L) {
+  if (M < 1 || M > 16 || (D != 1 && D != 2) || mode < 0 || mode > 3) return 0;
+  const size_t lds = kp_ell_lds_bytes(M, K, D, L, mode, nullptr);
+  switch (mode) {
+    case KM_EVAL: return kp_ell_resident_mode<KM_EVAL>(D, M, lds);
+    case KM_SCD: return kp_ell_resident_mode<KM_SCD>(D, M, lds);
+    case KM_WMAIN: return kp_ell_resident_mode<KM_WMAIN>(D, M, lds);
+    default: return kp_ell_resident_mode<KM_WFAIL>(D, M, lds);
   }
 }
 

@@ -706,28 +706,68 @@ __global__ void __launch_bounds__(ENT) k_ell(const SweepArgs a, const EllGeom g)
 
 size_t kp_ell_lds_bytes(int M, int K, int D, int L, int mode, int *region_out);
 
+// Persistent launch: never more blocks than can be resident at once (the
+// tile loop strides over the rest), so no block waits for another to finish
+// and every CU stays busy to the end.  grid <= 0 asks for exactly that many.
 template <int D, int MODE, int EM>
 static hipError_t launch_ell_t(const SweepArgs &a, const EllGeom &g, size_t lds, int grid,
-                               hipStream_t stream) {
+                               hipStream_t stream, int *used) {
+  const void *fn = (const void *)k_ell<D, MODE, EM>;
   if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_ell<D, MODE, EM>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      cus = 256;
+  }
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, ENT, lds) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  const int resident = cus * per_cu;
+  if (grid <= 0 || grid > resident) grid = resident;
+  if (used) *used = grid;
   hipLaunchKernelGGL((k_ell<D, MODE, EM>), dim3(grid), dim3(ENT), lds, stream, a, g);
   return hipGetLastError();
 }
 
 template <int D, int MODE>
 static hipError_t launch_ell_m(const SweepArgs &a, const EllGeom &g, size_t lds, int grid,
-                               hipStream_t stream) {
-  if (g.M <= 8) return launch_ell_t<D, MODE, 8>(a, g, lds, grid, stream);
-  if (g.M <= 10) return launch_ell_t<D, MODE, 10>(a, g, lds, grid, stream);
-  if (g.M <= 12) return launch_ell_t<D, MODE, 12>(a, g, lds, grid, stream);
-  return launch_ell_t<D, MODE, 16>(a, g, lds, grid, stream);
+                               hipStream_t stream, int *used) {
+  if (g.M <= 8) return launch_ell_t<D, MODE, 8>(a, g, lds, grid, stream, used);
+  if (g.M <= 10) return launch_ell_t<D, MODE, 10>(a, g, lds, grid, stream, used);
+  if (g.M <= 12) return launch_ell_t<D, MODE, 12>(a, g, lds, grid, stream, used);
+  return launch_ell_t<D, MODE, 16>(a, g, lds, grid, stream, used);
+}
+
+template <int D, int MODE, int EM>
+static int resident_blocks_t(size_t lds) {
+  const void *fn = (const void *)k_ell<D, MODE, EM>;
+  if (lds > 64 * 1024 &&
+      hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return 0;
+  int per_cu = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, ENT, lds) != hipSuccess) return 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  return per_cu * cus;
+}
+
+template <int D, int MODE>
+static int resident_blocks_m(int M, size_t lds) {
+  if (M <= 8) return resident_blocks_t<D, MODE, 8>(lds);
+  if (M <= 10) return resident_blocks_t<D, MODE, 10>(lds);
+  if (M <= 12) return resident_blocks_t<D, MODE, 12>(lds);
+  return resident_blocks_t<D, MODE, 16>(lds);
 }
 
 // one translation unit per mode instantiates these (kp_ell_m<mode>.hip)
 template <int MODE>
 hipError_t kp_launch_ell_mode(const SweepArgs &a, const EllGeom &g, size_t lds, int grid, int D,
-                              hipStream_t stream);
+                              hipStream_t stream, int *used);
+template <int MODE>
+int kp_ell_resident_mode(int D, int M, size_t lds);

@@ -4,7 +4,12 @@
 
 template <>
 hipError_t kp_launch_ell_mode<KM_EVAL>(const SweepArgs &a, const EllGeom &g, size_t lds, int grid, int D,
-                                   hipStream_t stream) {
-  if (D == 1) return launch_ell_m<1, KM_EVAL>(a, g, lds, grid, stream);
-  return launch_ell_m<2, KM_EVAL>(a, g, lds, grid, stream);
+                                   hipStream_t stream, int *used) {
+  if (D == 1) return launch_ell_m<1, KM_EVAL>(a, g, lds, grid, stream, used);
+  return launch_ell_m<2, KM_EVAL>(a, g, lds, grid, stream, used);
+}
+
+template <>
+int kp_ell_resident_mode<KM_EVAL>(int D, int M, size_t lds) {
+  return D == 1 ? resident_blocks_m<1, KM_EVAL>(M, lds) : resident_blocks_m<2, KM_EVAL>(M, lds);
 }
