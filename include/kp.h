@@ -166,6 +166,17 @@ kp_status kp_batched_create(void *ctx, const kp_problem *probs, int32_t n,
 kp_status kp_batched_step(void *plan, int32_t dir, double *stats, int32_t use_graph);
 kp_status kp_batched_destroy(void *plan);
 
+/* Pre-solving by sampling (Sec. 5.3): SCD iterations on the sub-instance of
+   the sampled users, with every budget scaled by n/N (B_k * (n / N) in
+   FP64), from lambda_inout until the multipliers repeat or max_iter sweeps;
+   the result (a starting point lambda^0 for the full instance) is written
+   back to lambda_inout (DEV [K]).  users: HOST [n] distinct indices in
+   [0, N), drawn by the caller.  iterations_out (HOST, may be NULL): sweeps
+   run.  Allocates and frees one device buffer for the sample; synchronises
+   the context stream; resets the context's window hints. */
+kp_status kp_presolve(void *ctx, const kp_problem *prob, const int64_t *users, int64_t n,
+                      int32_t max_iter, double *lambda_inout, int32_t *iterations_out);
+
 /* Optional full pass over p and b: KP_ERR_NONFINITE / KP_ERR_NEGATIVE if any
    value is NaN/Inf or negative, KP_OK otherwise (a CSR column outside [0,K) or
    not ascending is KP_ERR_INVALID).  Synchronises the context stream. */

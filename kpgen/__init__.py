@@ -35,7 +35,7 @@ _M1 = np.uint64(0xBF58476D1CE4E5B9)
 _M2 = np.uint64(0x94D049BB133111EB)
 
 # stream ids (8 bits each)
-S_P, S_B, S_COL, S_VAL, S_LAMBDA, S_SEED, S_SHAPE = 1, 2, 3, 4, 5, 6, 7
+S_P, S_B, S_COL, S_VAL, S_LAMBDA, S_SEED, S_SHAPE, S_SAMPLE = 1, 2, 3, 4, 5, 6, 7, 8
 
 DIST_UNIFORM, DIST_EXP1, DIST_LOGNORMAL = 0, 1, 2
 _DIST_NAMES = {"uniform": DIST_UNIFORM, "exp1": DIST_EXP1, "lognormal": DIST_LOGNORMAL}
@@ -329,6 +329,20 @@ def random_lambdas(seed: int, n: int, K: int, hi: float) -> np.ndarray:
     """n points lambda ~ U(0, hi)^K, fp64 built from 24-bit draws."""
     u = u24(seed, S_LAMBDA, np.arange(n * K, dtype=np.uint64)).astype(np.float64)
     return (u * 2.0 ** -24 * hi).reshape(n, K)
+
+
+def sample_users(seed: int, N: int, n: int) -> np.ndarray:
+    """n distinct users of [0, N) for pre-solving by sampling: one user drawn
+    uniformly from each of n consecutive strata [floor(s N / n), floor((s+1) N / n)).
+    (The draw is an input of the pre-solve, so every side uses the same sample.)"""
+    if not 1 <= n <= N:
+        raise ValueError("need 1 <= n <= N")
+    s = np.arange(n, dtype=np.int64)
+    lo = (s * N) // n
+    hi = ((s + 1) * N) // n
+    u = draw(seed, S_SAMPLE, s.astype(np.uint64)) >> np.uint64(11)        # 53 bits
+    off = (u.astype(np.float64) * 2.0 ** -53 * (hi - lo)).astype(np.int64)
+    return lo + np.minimum(off, hi - lo - 1)
 
 
 def checksum(a: np.ndarray) -> str:

@@ -258,6 +258,26 @@ def metrics(g, P_hat, R, B):
                 max_viol=float(np.max(np.maximum(R - B, 0.0) / B)) if len(B) else 0.0)
 
 
+def presolve(inst, users, max_iter=100, lam0=None):
+    """Pre-solving by sampling (Sec. 5.3): SCD on the sub-instance of the
+    sampled users with every budget scaled by n / N, from lam0 until the
+    multipliers repeat or max_iter sweeps.  Returns (lambda, sweeps)."""
+    users = np.asarray(users, np.int64)
+    n, N = len(users), inst.N
+    scale = float(n) / float(N)
+    sub = inst.subset(users, B=inst.B * scale)
+    pr = OracleProblem(sub)
+    lam = np.zeros(inst.K) if lam0 is None else np.array(lam0, np.float64)
+    it = 0
+    while it < max_iter:
+        new = scd_sweep(pr, lam)
+        it += 1
+        if np.array_equal(new, lam):
+            break
+        lam = new
+    return lam, it
+
+
 def solve(inst, method="scd", lam0=None, tol=1e-3, max_iter=100, alpha=1e-3, fix_every=1,
           block=1):
     """Reference driver: coordinate descent (Alg.4 loop) or DD (Alg.2 loop)

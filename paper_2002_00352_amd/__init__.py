@@ -76,7 +76,7 @@ EXPORTS = ["kp_last_error", "kp_create", "kp_destroy", "kp_set_stream", "kp_eval
            "kp_max_items", "kp_max_knapsacks_scd", "kp_set_timing", "kp_get_timing",
            "kp_batched_create", "kp_batched_step", "kp_batched_destroy", "kp_set_tuning",
            "kp_set_kernel_choice", "kp_forget_structure", "kp_set_window",
-           "kp_get_window_stats"]
+           "kp_get_window_stats", "kp_presolve"]
 
 
 def lib():
@@ -108,6 +108,7 @@ def lib():
         L.kp_set_kernel_choice.argtypes = [vp, i32]
         L.kp_forget_structure.argtypes = [vp]
         L.kp_set_window.argtypes = [vp, i32]
+        L.kp_presolve.argtypes = [vp, P, vp, i64, i32, vp, ctypes.POINTER(i32)]
         L.kp_get_window_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64),
                                           ctypes.POINTER(i64), ctypes.POINTER(i64)]
         L.kp_set_timing.argtypes = [vp, i32]
@@ -368,6 +369,19 @@ class BatchedSCD:
             self.close()
         except Exception:
             pass
+
+
+def kp_presolve(prob: Problem, users, lam, max_iter: int = 30, ctx: Optional[Context] = None):
+    """Pre-solving by sampling (Sec. 5.3): SCD on the sampled users with the
+    budgets scaled by n/N, from lam (a K-vector of FP64 on the device, updated
+    in place).  users: distinct user indices (host integers).  Returns
+    (lam, sweeps)."""
+    ctx = ctx or default_context()
+    u = np.ascontiguousarray(np.asarray(users, dtype=np.int64))
+    it = ctypes.c_int32()
+    _check(lib().kp_presolve(ctx.h, prob.ref, u.ctypes.data, len(u), int(max_iter),
+                             _ptr(lam), ctypes.byref(it)))
+    return lam, it.value
 
 
 def kp_validate_inputs(prob: Problem, ctx: Optional[Context] = None):

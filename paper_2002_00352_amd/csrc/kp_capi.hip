@@ -31,6 +31,13 @@ hipError_t kp_launch_scd_finish(const KState *st, int K, const double *lam_in, d
                                 double *delta_next, hipStream_t stream);
 hipError_t kp_launch_dd_update(int K, double alpha, const double *R, const double *B, double *lam,
                                hipStream_t stream);
+hipError_t kp_launch_gather_dense(const float *p, const float *b, const int64_t *users, int64_t n, int M,
+                                  int K, float *sp, float *sb, hipStream_t stream);
+hipError_t kp_launch_gather_csr_ptr(const int64_t *rowptr, const int64_t *users, int64_t n, int M,
+                                    int64_t *len, int64_t *subptr, hipStream_t stream);
+hipError_t kp_launch_gather_csr(const int64_t *rowptr, const int32_t *col, const float *val,
+                                const int64_t *users, int64_t n, int M, const int64_t *subptr,
+                                int32_t *scol, float *sval, hipStream_t stream);
 hipError_t kp_launch_dual_backward(int K, const double *R, const double *B, const double *gout,
                                    double *glam, hipStream_t stream);
 hipError_t kp_launch_validate(const float *v, int64_t n, unsigned int *flags, hipStream_t stream);
@@ -754,6 +761,106 @@ kp_status kp_scd_sweep_masked(void *ctx, const kp_problem *prob, const double *l
 kp_status kp_scd_sweep(void *ctx, const kp_problem *prob, const double *lambda_in,
                        double *lambda_out, double *R, double *g, double *primal) {
   return kp_scd_sweep_masked(ctx, prob, lambda_in, lambda_out, nullptr, R, g, primal);
+}
+
+// Device buffer owned by one call (freed on every exit path).
+struct DevBuf {
+  void *p = nullptr;
+  ~DevBuf() { if (p) (void)hipFree(p); }
+};
+
+kp_status kp_presolve(void *ctx, const kp_problem *prob, const int64_t *users, int64_t n,
+                      int32_t max_iter, double *lambda_inout, int32_t *iterations_out) {
+  if (!ctx) return fail(KP_ERR_INVALID, "ctx is NULL");
+  if (!users || !lambda_inout) return fail(KP_ERR_INVALID, "NULL argument");
+  if (max_iter < 1) return fail(KP_ERR_INVALID, "max_iter must be >= 1");
+  Ctx *c = (Ctx *)ctx;
+  Prepared P;
+  kp_status s = prepare(prob, true, P, c);
+  if (s != KP_OK) return s;
+  const int64_t N = prob->N;
+  const int M = prob->M, K = prob->K;
+  if (n < 1 || n > N) return fail(KP_ERR_INVALID, "sample size must be in [1, N]");
+  {
+    std::vector<int64_t> u(users, users + n);
+    std::sort(u.begin(), u.end());
+    if (u.front() < 0 || u.back() >= N) return fail(KP_ERR_INVALID, "sampled user out of [0, N)");
+    if (std::adjacent_find(u.begin(), u.end()) != u.end())
+      return fail(KP_ERR_INVALID, "sampled users must be distinct");
+  }
+  const bool csr = prob->b_format == KP_B_CSR;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  // the sub-instance: users, p, costs (dense rows, or CSR rows with new offsets)
+  Carve cv;
+  const size_t o_u = cv.take((size_t)n * 8);
+  const size_t o_p = cv.take((size_t)n * M * 4);
+  const size_t o_b = csr ? 0 : cv.take((size_t)n * M * K * 4);
+  const size_t o_len = csr ? cv.take((size_t)n * M * 8) : 0;
+  const size_t o_ptr = csr ? cv.take((size_t)(n * M + 1) * 8) : 0;
+  const size_t o_lam = cv.take((size_t)K * 8);
+  DevBuf buf;
+  if (hipMalloc(&buf.p, cv.off) != hipSuccess) { buf.p = nullptr; return fail(KP_ERR_NOMEM, "hipMalloc failed"); }
+  char *b = (char *)buf.p;
+  int64_t *ud = (int64_t *)(b + o_u);
+  HIP_TRY(hipMemcpyAsync(ud, users, (size_t)n * 8, hipMemcpyHostToDevice, c->stream));
+  kp_problem sub = *prob;
+  sub.N = n;
+  sub.p = (const float *)(b + o_p);
+  DevBuf ent;
+  if (!csr) {
+    sub.b = (const float *)(b + o_b);
+    HIP_TRY(kp_launch_gather_dense(prob->p, prob->b, ud, n, M, K, (float *)(b + o_p), (float *)(b + o_b),
+                                   c->stream));
+  } else {
+    HIP_TRY(kp_launch_gather_dense(prob->p, nullptr, ud, n, M, K, (float *)(b + o_p), nullptr, c->stream));
+    int64_t *subptr = (int64_t *)(b + o_ptr);
+    HIP_TRY(kp_launch_gather_csr_ptr(prob->b_rowptr, ud, n, M, (int64_t *)(b + o_len), subptr, c->stream));
+    int64_t nnz = 0;
+    HIP_TRY(hipMemcpyAsync(&nnz, subptr + n * M, 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (hipMalloc(&ent.p, (size_t)std::max<int64_t>(nnz, 1) * 8) != hipSuccess) {
+      ent.p = nullptr;
+      return fail(KP_ERR_NOMEM, "hipMalloc failed");
+    }
+    int32_t *scol = (int32_t *)ent.p;
+    float *sval = (float *)((char *)ent.p + (size_t)std::max<int64_t>(nnz, 1) * 4);
+    HIP_TRY(kp_launch_gather_csr(prob->b_rowptr, prob->b_col, prob->b_val, ud, n, M, subptr, scol, sval,
+                                 c->stream));
+    sub.b_rowptr = subptr;
+    sub.b_col = scol;
+    sub.b_val = sval;
+  }
+  // budgets scaled by the sample's share of the users
+  std::vector<double> Bs(K);
+  const double scale = (double)n / (double)N;
+  for (int k = 0; k < K; ++k) Bs[k] = prob->B[k] * scale;
+  sub.B = Bs.data();
+  // SCD on the sample until the multipliers repeat (the window hints of the
+  // full problem do not carry over)
+  c->delta_valid = false;
+  double *lam_b = (double *)(b + o_lam);
+  double *cur = lambda_inout, *nxt = lam_b;
+  std::vector<double> hc(K), hn(K);
+  int it = 0;
+  kp_status rs = KP_OK;
+  while (it < max_iter) {
+    rs = kp_scd_sweep(ctx, &sub, cur, nxt, nullptr, nullptr, nullptr);
+    if (rs != KP_OK) break;
+    ++it;
+    HIP_TRY(hipMemcpyAsync(hc.data(), cur, (size_t)K * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(hn.data(), nxt, (size_t)K * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    std::swap(cur, nxt);
+    if (memcmp(hc.data(), hn.data(), (size_t)K * 8) == 0) break;
+  }
+  if (rs == KP_OK && cur != lambda_inout)
+    HIP_TRY(hipMemcpyAsync(lambda_inout, cur, (size_t)K * 8, hipMemcpyDeviceToDevice, c->stream));
+  (void)hipStreamSynchronize(c->stream);
+  if (csr) c->ell.erase(std::make_pair((const int64_t *)sub.b_rowptr, n * (int64_t)M));
+  c->delta_valid = false;
+  if (rs != KP_OK) return rs;
+  if (iterations_out) *iterations_out = it;
+  return KP_OK;
 }
 
 kp_status kp_validate_inputs(void *ctx, const kp_problem *prob) {

@@ -912,6 +912,72 @@ __global__ void k_count_pending(const KState *st, int K, int *pending) {
 }
 
 // ---------------------------------------------------------------------------
+// Pre-solving by sampling (Sec. 5.3): the sub-instance of the sampled users
+// ---------------------------------------------------------------------------
+// dst[s * rowlen + c] = src[users[s] * rowlen + c]
+__global__ void k_gather_rows(const float *src, float *dst, const int64_t *users, int64_t n,
+                              int64_t rowlen) {
+  const int64_t total = n * rowlen;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = e / rowlen, c = e - s * rowlen;
+    dst[e] = src[users[s] * rowlen + c];
+  }
+}
+
+// stored entries of every sampled item row
+__global__ void k_gather_len(const int64_t *rowptr, const int64_t *users, int64_t n, int M,
+                             int64_t *len) {
+  const int64_t total = n * M;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = e / M, j = e - s * M;
+    const int64_t r = users[s] * M + j;
+    len[e] = rowptr[r + 1] - rowptr[r];
+  }
+}
+
+// out[0] = 0, out[i + 1] = len[0] + ... + len[i]  (one block; chunk per thread,
+// then a scan of the chunk sums in LDS)
+__global__ void __launch_bounds__(1024) k_scan_i64(const int64_t *len, int64_t *out, int64_t n) {
+  __shared__ int64_t part[1024];
+  const int t = threadIdx.x;
+  const int64_t chunk = (n + 1023) / 1024;
+  const int64_t lo = t * chunk < n ? t * chunk : n;
+  const int64_t hi = lo + chunk < n ? lo + chunk : n;
+  int64_t sum = 0;
+  for (int64_t i = lo; i < hi; ++i) sum += len[i];
+  part[t] = sum;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int64_t v = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int64_t run = part[t] - sum;
+  if (t == 0) out[0] = 0;
+  for (int64_t i = lo; i < hi; ++i) { run += len[i]; out[i + 1] = run; }
+}
+
+// copy the sampled item rows' entries (rows are short: one thread per row)
+__global__ void k_gather_csr(const int64_t *rowptr, const int32_t *col, const float *val,
+                             const int64_t *users, int64_t n, int M, const int64_t *subptr,
+                             int32_t *scol, float *sval) {
+  const int64_t total = n * M;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = e / M, j = e - s * M;
+    const int64_t r = users[s] * M + j;
+    int64_t o = subptr[e];
+    for (int64_t q = rowptr[r]; q < rowptr[r + 1]; ++q, ++o) {
+      scol[o] = col[q];
+      sval[o] = val[q];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // DD step (Eq.14) and the dual gradient
 // ---------------------------------------------------------------------------
 __global__ void k_dd_update(int K, double alpha, const double *R, const double *B, double *lam) {
@@ -1469,6 +1535,37 @@ hipError_t kp_launch_scd_finish(const KState *st, int K, const double *lam_in, d
                                 double *delta_next, hipStream_t stream) {
   hipLaunchKernelGGL(k_scd_finish, dim3((K + 63) / 64), dim3(64), 0, stream, st, K, lam_in,
                      lam_out, delta_next, (int *)nullptr);
+  return hipGetLastError();
+}
+
+static unsigned gather_blocks(int64_t total) {
+  int64_t b = (total + 255) / 256;
+  return (unsigned)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
+}
+
+hipError_t kp_launch_gather_dense(const float *p, const float *b, const int64_t *users, int64_t n, int M,
+                                  int K, float *sp, float *sb, hipStream_t stream) {
+  hipLaunchKernelGGL(k_gather_rows, dim3(gather_blocks(n * M)), dim3(256), 0, stream, p, sp, users, n,
+                     (int64_t)M);
+  if (b)
+    hipLaunchKernelGGL(k_gather_rows, dim3(gather_blocks(n * M * K)), dim3(256), 0, stream, b, sb,
+                       users, n, (int64_t)M * K);
+  return hipGetLastError();
+}
+
+hipError_t kp_launch_gather_csr_ptr(const int64_t *rowptr, const int64_t *users, int64_t n, int M,
+                                    int64_t *len, int64_t *subptr, hipStream_t stream) {
+  hipLaunchKernelGGL(k_gather_len, dim3(gather_blocks(n * M)), dim3(256), 0, stream, rowptr, users, n,
+                     M, len);
+  hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, stream, len, subptr, n * M);
+  return hipGetLastError();
+}
+
+hipError_t kp_launch_gather_csr(const int64_t *rowptr, const int32_t *col, const float *val,
+                                const int64_t *users, int64_t n, int M, const int64_t *subptr,
+                                int32_t *scol, float *sval, hipStream_t stream) {
+  hipLaunchKernelGGL(k_gather_csr, dim3(gather_blocks(n * M)), dim3(256), 0, stream, rowptr, col, val,
+                     users, n, M, subptr, scol, sval);
   return hipGetLastError();
 }
 

@@ -43,18 +43,21 @@ class DualFn:
 
 
 def solve(prob, method: str = "scd", lam0=None, tol: float = 1e-3, max_iter: int = 100,
-          alpha: float = 1e-3, block: int = 1, log=None):
+          alpha: float = 1e-3, block: int = 1, log=None, presolve_users=None, presolve_iter: int = 30):
     """Iterate until the relative duality gap (best dual - best feasible
     primal) / |best feasible primal| <= tol, lambda stops changing, or
     max_iter.  method: "scd" | "cyclic" | "block" | "dd".  The feasible primal
     of an iterate is P(x) when x already meets every budget, else the
-    post-processed value.  Returns (lambda, history)."""
+    post-processed value.  presolve_users: sampled users whose pre-solve
+    (Sec. 5.3) replaces lam0 as the starting point.  Returns (lambda, history)."""
     import torch
-    from . import kp_scd_sweep, kp_dd_step, kp_primal_fixup
+    from . import kp_scd_sweep, kp_dd_step, kp_primal_fixup, kp_presolve
     K = prob.K
     B = prob.B
     lam = torch.zeros(K, dtype=torch.float64, device="cuda") if lam0 is None else \
         torch.as_tensor(np.asarray(lam0, np.float64)).to("cuda").clone()
+    if presolve_users is not None:
+        kp_presolve(prob, presolve_users, lam, max_iter=presolve_iter)
     best_g, best_P = np.inf, -np.inf
     hist = []
     t0 = time.perf_counter()
