@@ -442,8 +442,9 @@ kp_status carve_ws(Ctx *c, const Prepared &P, bool scd, SweepWs &w) {
   // users listed by a window pass of the uniform-row kernel (room for all)
   size_t o_fl = 0, o_fc = 0, o_md = 0;
   uint32_t fcap = 0;
-  if (scd && P.ell_D && P.pr.N < ((int64_t)1 << 32)) {
-    fcap = (uint32_t)std::max<int64_t>(64, P.pr.N);
+  if (scd && P.ell_D && P.pr.N < ((int64_t)1 << 32) - ((int64_t)1 << 28)) {
+    // every user, plus the unused tails of the waves' reserved chunks
+    fcap = (uint32_t)(P.pr.N + (int64_t)KP_LIST_CHUNK * P.ell_grid * 4);
     o_fl = cv.take((size_t)fcap * 4);
     o_fc = cv.take(16);
   }

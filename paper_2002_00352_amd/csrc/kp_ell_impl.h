@@ -361,8 +361,13 @@ __device__ __forceinline__ void scd_user(const SweepArgs &a, int M, int K, int L
 // every lane busy.
 enum { KM_EVAL = 0, KM_SCD = 1, KM_WMAIN = 2, KM_WFAIL = 3 };
 
+// The window main pass is held to 3 waves per SIMD, the occupancy its LDS
+// allows (without the hint it compiles just above the register limit).
+template <int MODE> struct EllWaves { static constexpr int value = MODE == 2 ? 3 : 1; };
+
 template <int D, int MODE, int EM>
-__global__ void __launch_bounds__(ENT) k_ell(const SweepArgs a, const EllGeom g) {
+__global__ void __launch_bounds__(ENT) __attribute__((amdgpu_waves_per_eu(EllWaves<MODE>::value, 8)))
+k_ell(const SweepArgs a, const EllGeom g) {
   constexpr bool BREAK = (MODE == KM_SCD || MODE == KM_WFAIL);   // breakpoint phase
   constexpr bool STAGED = (MODE != KM_WFAIL);                    // contiguous tiles
   extern __shared__ __align__(16) unsigned char smem[];
@@ -452,6 +457,7 @@ __global__ void __launch_bounds__(ENT) k_ell(const SweepArgs a, const EllGeom g)
   float *sv = (float *)(wreg + (size_t)64 * M * 4 + (size_t)64 * M * D * 4);
   double *rowbuf = (double *)wreg;
 
+  uint32_t ch_pos = 0, ch_end = 0;   // the wave's reserved list chunk (window main pass)
   for (int64_t tile = (int64_t)blockIdx.x * EW + wv; tile < ntiles; tile += W) {
     const int64_t u0 = tile * 64;
     float pv[EM];
@@ -491,8 +497,9 @@ __global__ void __launch_bounds__(ENT) k_ell(const SweepArgs a, const EllGeom g)
     } else {
       // ---- gather the listed user into registers ----
       const int64_t idx = u0 + lane;
-      act = idx < (int64_t)nlisted;
-      const int64_t u = act ? (int64_t)a.flist[idx] : 0;
+      const uint32_t entry = idx < (int64_t)nlisted ? a.flist[idx] : KP_LIST_HOLE;
+      act = entry != KP_LIST_HOLE;
+      const int64_t u = act ? (int64_t)entry : 0;
       #pragma unroll
       for (int j = 0; j < EM; ++j) {
         if (j < M) {
@@ -566,8 +573,11 @@ __global__ void __launch_bounds__(ENT) k_ell(const SweepArgs a, const EllGeom g)
     }
     double bmax = 0.0;
     if (MODE != KM_EVAL) {
+      // largest stored cost (exact in fp32; widened once)
+      float bm = 0.0f;
       #pragma unroll
-      for (int j = 0; j < EM * D; ++j) bmax = (double)vl[j] > bmax ? (double)vl[j] : bmax;
+      for (int j = 0; j < EM * D; ++j) bm = vl[j] > bm ? vl[j] : bm;
+      bmax = (double)bm;
     }
     // ---- statistics: profit, group dual value, consumption ----
     double Pi = 0.0, Gi = 0.0;
@@ -581,8 +591,7 @@ __global__ void __launch_bounds__(ENT) k_ell(const SweepArgs a, const EllGeom g)
       // The same test as the breakpoint phase: the smallest distance between
       // two lines that can turn positive inside the window, or between such a
       // line and zero, against the bound of the user's knapsacks with a
-      // window.  Lines below -H never can; they are moved far apart so that
-      // they never set the minimum.  The bound of knapsack k is
+      // window.  Lines below -H never can.  The bound of knapsack k is
       // bmax * wA[k] + 2^-36 (1 + gscale), wA[k] = h_k (1 + 2^-30) +
       // 2^-36 (lambda_k + h_k) (0 without a window).
       double amax = 0.0;
@@ -592,22 +601,28 @@ __global__ void __launch_bounds__(ENT) k_ell(const SweepArgs a, const EllGeom g)
         if ((unsigned)k < (unsigned)K) amax = wA[k] > amax ? wA[k] : amax;
       }
       const double H = hwin[K] * bmax * (1.0 + 0x1p-30) + 0x1p-36 * (1.0 + bmax * hwin[K]);
-      double gmin = 1e300, top = -1e300;
+      // p~ by rank into the dead staging area, then the gaps between
+      // neighbours in rank order (the smallest pairwise distance is between
+      // neighbours) down to the first line below -H
+      double *srt = (double *)wreg;
       #pragma unroll
-      for (int j = 0; j < EM; ++j) {
-        const bool rel = j < M && pt[j] > -H;
-        if (rel) gmin = fabs(pt[j]) < gmin ? fabs(pt[j]) : gmin;
-        if (j < M) top = pt[j] > top ? pt[j] : top;
-        pt[j] = rel ? pt[j] : -0x1p900 * (double)(j + 1);
+      for (int j = 0; j < EM; ++j)
+        if (j < M) srt[rk[j] * 64 + lane] = pt[j];
+      __builtin_amdgcn_s_waitcnt(0);
+      __builtin_amdgcn_wave_barrier();
+      __asm__ volatile("" ::: "memory");
+      const double top = srt[lane];
+      double gmin = 1e300, prev = 0.0;
+      for (int r = 0; r < M; ++r) {
+        const double v = srt[r * 64 + lane];
+        if (!(v > -H)) break;
+        gmin = fabs(v) < gmin ? fabs(v) : gmin;
+        if (r > 0) gmin = prev - v < gmin ? prev - v : gmin;
+        prev = v;
       }
-      #pragma unroll
-      for (int j = 0; j < EM; ++j) {
-        #pragma unroll
-        for (int jj = j + 1; jj < EM; ++jj) {
-          const double d = fabs(pt[j] - pt[jj]);
-          gmin = d < gmin ? d : gmin;
-        }
-      }
+      __builtin_amdgcn_s_waitcnt(0);
+      __builtin_amdgcn_wave_barrier();
+      __asm__ volatile("" ::: "memory");
       const double need = bmax * amax + 0x1p-36 * (1.0 + fabs(top) + H);
       listed = act && amax > 0.0 && !(gmin > need);
     }
@@ -655,12 +670,25 @@ __global__ void __launch_bounds__(ENT) k_ell(const SweepArgs a, const EllGeom g)
       }
     }
     if (MODE == KM_WMAIN) {
+      // append to the wave's reserved chunk of the list (one counter atomic
+      // per KP_LIST_CHUNK entries instead of one per tile)
       const uint64_t mask = __ballot(listed);
       if (mask) {
-        uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(a.fcount, (uint32_t)__popcll(mask));
-        base = __shfl(base, 0, 64);
-        const uint32_t slot = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1));
+        const uint32_t cnt = (uint32_t)__popcll(mask);
+        const uint32_t rank = (uint32_t)__popcll(mask & ((1ull << lane) - 1));
+        // entries that still fit the current chunk, the rest opens a new one
+        const uint32_t room = ch_end - ch_pos;
+        uint32_t slot = ch_pos + rank;
+        if (cnt > room) {
+          uint32_t nb = 0;
+          if (lane == 0) nb = atomicAdd(a.fcount, (uint32_t)KP_LIST_CHUNK);
+          nb = (uint32_t)__builtin_amdgcn_readfirstlane((int)__shfl(nb, 0, 64));
+          if (rank >= room) slot = nb + (rank - room);
+          ch_pos = nb + (cnt - room);
+          ch_end = nb + KP_LIST_CHUNK;
+        } else {
+          ch_pos += cnt;
+        }
         if (listed && slot < a.fcap) a.flist[slot] = (uint32_t)(u0 + lane);
       }
     }
@@ -692,6 +720,11 @@ __global__ void __launch_bounds__(ENT) k_ell(const SweepArgs a, const EllGeom g)
       __builtin_amdgcn_s_waitcnt(0);
       __builtin_amdgcn_wave_barrier();
     }
+  }
+  if (MODE == KM_WMAIN) {
+    // mark the unused tail of the wave's last chunk
+    for (uint32_t e = ch_pos + lane; e < ch_end; e += 64)
+      if (e < a.fcap) a.flist[e] = KP_LIST_HOLE;
   }
   __syncthreads();
   if (a.want_stats && STAGED) {

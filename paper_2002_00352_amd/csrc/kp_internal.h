@@ -10,6 +10,8 @@
 #define KP_SORT_MAX 4096       // candidates sorted in LDS by the selection kernel
 #define KP_WIN_MULT 2.0        // window half-width around lambda_k^t, in units of the last step bound
 #define KP_WIN_MAX_REL 0.125   // windows wider than this fraction of lambda_k^t are not tried
+#define KP_LIST_CHUNK 256u     // list slots a wave reserves at a time in the window pass
+#define KP_LIST_HOLE 0xFFFFFFFFu  // unused list slot
 
 // Laminar local constraints after pruning: only sets that can bind
 // (C_l < |S_l|), duplicates merged with the smaller cap, ordered subsets
