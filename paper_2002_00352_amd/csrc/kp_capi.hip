@@ -695,7 +695,7 @@ kp_status kp_scd_sweep_masked(void *ctx, const kp_problem *prob, const double *l
   // window hint from the previous call with the same K (performance only)
   if (!c->delta_dev || c->delta_K != K) {
     if (c->delta_dev) HIP_TRY(hipFree(c->delta_dev));
-    HIP_TRY(hipMalloc(&c->delta_dev, (size_t)K * 8));
+    HIP_TRY(hipMalloc(&c->delta_dev, (size_t)K * 16));   // [K] bucket widths, [K] last steps
     c->delta_K = K;
     c->delta_valid = false;
   }

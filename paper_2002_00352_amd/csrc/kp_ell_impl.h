@@ -410,7 +410,7 @@ k_ell(const SweepArgs a, const EllGeom g) {
   if (MODE != KM_EVAL) {
     for (int t = tid; t < K; t += ENT) {
       kmode[t] = a.st[t].mode;
-      hwin[t] = a.st[t].mode == KS_WINDOW ? KP_WIN_MULT * a.st[t].delta : 0.0;
+      hwin[t] = a.st[t].mode == KS_WINDOW ? a.st[t].hw : 0.0;
       if (MODE == KM_WMAIN) {
         const double h = hwin[t];
         wA[t] = h > 0.0 ? h * (1.0 + 0x1p-30) + 0x1p-36 * (a.lam[t] + h) : 0.0;

@@ -8,8 +8,8 @@
 #define KP_MAX_K_SCD 64        // per-block LDS histograms bound K for the SCD calls
 #define KP_CENTRAL_W 2         // exponential buckets |id| <= W are emitted in the first pass
 #define KP_SORT_MAX 4096       // candidates sorted in LDS by the selection kernel
-#define KP_WIN_MULT 2.0        // window half-width around lambda_k^t, in units of the last step bound
-#define KP_WIN_MAX_REL 0.125   // windows wider than this fraction of lambda_k^t are not tried
+#define KP_WIN_MULT 1.25       // window half-width around lambda_k^t, in units of the last step
+#define KP_WIN_MAX_REL 0.03125 // windows wider than this fraction of lambda_k^t are not tried
 #define KP_LIST_CHUNK 256u     // list slots a wave reserves at a time in the window pass
 #define KP_LIST_HOLE 0xFFFFFFFFu  // unused list slot
 
@@ -70,6 +70,7 @@ struct KState {
   uint64_t klo, khi;   // inclusive key range
   uint64_t hull_lo, hull_hi;  // atomics: key hull of the bucket's events
   double wlo, whi;     // KS_WINDOW: breakpoints with wlo <= v1 <= whi are emitted (wlo may be 0)
+  double hw;           // KS_WINDOW: half-width h (whi = center + h, wlo = max(center - h, 0))
   double corr;         // KS_WINDOW (atomic): sum over users of C_ik(whi+) - v_ik(x(lambda^t))
 };
 

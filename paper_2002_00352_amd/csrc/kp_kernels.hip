@@ -584,11 +584,14 @@ __global__ void k_scd_init(KState *st, int K, const double *lam_in, const uint8_
   s.hull_hi = 0;
   s.wlo = 0.0;
   s.whi = 0.0;
+  s.hw = 0.0;
   s.corr = 0.0;
-  // a window around lambda_k^t when the last step was small against it
-  const double h = KP_WIN_MULT * d;
-  if (window && hinted && s.mode == KS_EXP && h <= KP_WIN_MAX_REL * s.center) {
+  // a window around lambda_k^t sized from the last step, when that step was
+  // small against the multiplier
+  const double h = hinted ? KP_WIN_MULT * delta_hint[K + k] : 0.0;
+  if (window && h > 0.0 && s.mode == KS_EXP && h <= KP_WIN_MAX_REL * s.center) {
     s.mode = KS_WINDOW;
+    s.hw = h;
     s.whi = s.center + h;
     s.wlo = s.center - h > 0.0 ? s.center - h : 0.0;
     s.klo = dkey(s.wlo);
@@ -879,11 +882,13 @@ __global__ void k_scd_finish(const KState *st, int K, const double *lam_in, doub
   const double nl = st[k].result;
   lam_out[k] = nl;
   if (delta_next) {
-    // next central window: the power of two at or above this step
+    // next search: the bucket width, a power of two above this step, and the
+    // step itself (bounded below) for the window
     const double step = fabs(nl - lam_in[k]);
     const double floor_ = (nl > 0x1p-20 ? nl : 0x1p-20) * 0x1p-30;
     const double w = step > floor_ ? step : floor_;
     delta_next[k] = ldexp(1.0, ilogb(w) + 1);
+    delta_next[K + k] = w;
   }
 }
 
@@ -1401,6 +1406,10 @@ __global__ void k_scd_init_flat(KState *st, int Kf, const double *const *lam_in,
   s.khi = ~0ull;
   s.hull_lo = ~0ull;
   s.hull_hi = 0;
+  s.wlo = 0.0;
+  s.whi = 0.0;
+  s.hw = 0.0;
+  s.corr = 0.0;
   st[f] = s;
 }
 
