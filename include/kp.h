@@ -222,8 +222,8 @@ kp_status kp_set_tuning(void *ctx, int32_t M, int32_t K, int32_t b_format, int32
 kp_status kp_set_kernel_choice(void *ctx, int32_t allow_uniform_rows);
 kp_status kp_forget_structure(void *ctx);
 
-/* Threshold search of kp_scd_sweep with the lean kernel (Alg.4 reduce,
-   located near the previous multiplier).  After one sweep on a context, each
+/* Threshold search of kp_scd_sweep (Alg.4 reduce, located near the
+   previous multiplier).  After one sweep on a context, each
    knapsack whose last step was small against its multiplier starts with a
    window around lambda_k^t: users whose greedy set stays optimal over the
    whole window are checked in O(M) instead of walked, and only the

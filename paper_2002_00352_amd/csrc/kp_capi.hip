@@ -17,7 +17,9 @@
 
 // launchers (kp_kernels.hip)
 size_t kp_sweep_lds_bytes(int U, int M, int K, bool scd, int fmt);
-hipError_t kp_launch_sweep(const SweepArgs &a, int U, int grid, bool scd, hipStream_t stream);
+hipError_t kp_launch_sweep(const SweepArgs &a, int U, int grid, bool scd, hipStream_t stream,
+                           int *used);
+int kp_sweep_resident_grid(int U, int M, int K, bool scd, int fmt);
 hipError_t kp_launch_reduce_stats(const double *partials, int nblk, int K, const double *lam,
                                   const double *B, double *R, double *g, double *P,
                                   hipStream_t stream);
@@ -314,6 +316,11 @@ kp_status prepare(const kp_problem *p, bool scd, Prepared &out, const Ctx *ctx =
     }
   }
   out.grid = (int)std::max<int64_t>(1, std::min<int64_t>(out.ntiles, grid_override > 0 ? grid_override : kMaxGrid));
+  // persistent launch: no more blocks than can be resident at once
+  if (p->N > 0) {
+    const int res = kp_sweep_resident_grid(U, M, p->K, scd, p->b_format);
+    if (res > 0) out.grid = std::min(out.grid, res);
+  }
   return KP_OK;
 }
 
@@ -528,8 +535,7 @@ hipError_t timed_sweep(Ctx *c, const SweepArgs &a, const Prepared &P, bool scd, 
     ae.ntiles = P.ell_ntiles;
     err = kp_launch_ell(ae, P.ell_D, P.ell_grid, scd ? 1 : 0, c->stream, &c->stats_grid);
   } else {
-    err = kp_launch_sweep(a, P.U, P.grid, scd, c->stream);
-    c->stats_grid = P.grid;
+    err = kp_launch_sweep(a, P.U, P.grid, scd, c->stream, &c->stats_grid);
   }
   if (c->timing && e0 && e1) {
     (void)hipEventRecord(e1, c->stream);
@@ -700,8 +706,7 @@ kp_status kp_scd_sweep_masked(void *ctx, const kp_problem *prob, const double *l
     c->delta_valid = false;
   }
   // the window pass needs the statistics of the same pass (R at lambda_in)
-  // and is implemented by the uniform-row kernel
-  const int window = (c->window_enabled && P.ell_D && P.pr.N > 0) ? 1 : 0;
+  const int window = (c->window_enabled && P.pr.N > 0) ? 1 : 0;
   HIP_TRY(kp_launch_scd_init(w.st, K, lambda_in, kmask ? w.kmask : nullptr,
                              c->delta_valid ? c->delta_dev : nullptr, window, c->stream));
   // the first pass runs split (all users, then the listed ones) when every
@@ -1076,7 +1081,8 @@ kp_status kp_primal_fixup(void *ctx, const kp_problem *prob, const double *lambd
   a.uv_out = uv;
   a.kv_map = map;
   a.nv = nv;
-  HIP_TRY(kp_launch_sweep(a, P.U, P.grid, false, c->stream));
+  int fx_grid = 0;
+  HIP_TRY(kp_launch_sweep(a, P.U, P.grid, false, c->stream, &fx_grid));
   HIP_TRY(kp_launch_fixup_pipeline(uv, nv, Gd, N, RB, P.pr, xd, Rv, Pv, R_out, primal_out,
                                    n_reset_out, b + o_scr, c->stream, (uint32_t *)(c->pinned + 4)));
   return KP_OK;

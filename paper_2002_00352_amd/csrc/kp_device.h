@@ -174,3 +174,70 @@ __device__ __forceinline__ void publish_block(const SweepArgs &a, int K, double 
     }
   }
 }
+
+// Is S, the greedy set at lambda^t, still the greedy solution of the lines
+// z_j = c_j - lambda_k b_jk just above t (side > 0) or just below t
+// (side < 0)?  Only relations that involve an item moving with k (A) can
+// differ from those at lambda^t.  S is the greedy solution iff its members
+// stay positive and every positive non-member closes a circuit with S (the
+// members of the innermost full set containing it) and ranks below every
+// member of it.  line(j, c, b) gives item j's line (b = 0 outside A); Bpos:
+// the items with p~ > 0 outside S.
+template <class LINE>
+__device__ __forceinline__ bool window_keeps(uint64_t S, uint64_t A, uint64_t Bpos, LINE line,
+                                             const uint64_t *tmask, const int *tcap, int L, double t,
+                                             int side) {
+  auto circuit = [&](int o) -> uint64_t {
+    for (int l = 0; l < L; ++l) {
+      const uint64_t m = tmask[l];
+      if ((m >> o & 1) && popc64(S & m) >= tcap[l]) return S & m;
+    }
+    return 0;
+  };
+  for (uint64_t m = S & A; m; m &= m - 1) {
+    const int s = __ffsll((long long)m) - 1;
+    double c, b;
+    line(s, c, b);
+    if (!line_pos(c, b, t, side)) return false;
+  }
+  for (uint64_t m = A & ~S; m; m &= m - 1) {
+    const int o = __ffsll((long long)m) - 1;
+    double co, bo;
+    line(o, co, bo);
+    if (!line_pos(co, bo, t, side)) continue;
+    uint64_t circ = circuit(o);
+    if (!circ) return false;
+    for (; circ; circ &= circ - 1) {
+      const int s = __ffsll((long long)circ) - 1;
+      double cs, bs;
+      line(s, cs, bs);
+      if (line_beats(co, bo, o, cs, bs, s, t, side)) return false;
+    }
+  }
+  for (uint64_t m = Bpos & ~A; m; m &= m - 1) {
+    const int o = __ffsll((long long)m) - 1;
+    uint64_t circ = circuit(o) & A;
+    if (!circ) continue;
+    double co, bo;
+    line(o, co, bo);
+    for (; circ; circ &= circ - 1) {
+      const int s = __ffsll((long long)circ) - 1;
+      double cs, bs;
+      line(s, cs, bs);
+      if (line_beats(co, bo, o, cs, bs, s, t, side)) return false;
+    }
+  }
+  return true;
+}
+
+// Window filter (one user): the smallest distance between two of its lines
+// that can turn positive within h of lambda_k^t, or between such a line and
+// zero, must exceed h * bmax (plus a rounding margin): lines move against
+// each other by at most |b_a - b_b| <= bmax per unit of lambda_k.  gmin and
+// gscale come from the user's p~ in rank order (lines below -H, H the widest
+// window's bound, never turn positive).
+__device__ __forceinline__ bool window_calm(double gmin, double gscale, double h, double bmax,
+                                           double lk) {
+  const double need = h * bmax * (1.0 + 0x1p-30) + 0x1p-36 * (1.0 + gscale + lk * bmax + h * bmax);
+  return gmin > need;
+}

@@ -63,63 +63,6 @@ __device__ __forceinline__ bool walk_mode(int m) {
          m == KS_EMIT_RANGE || m == KS_WINDOW;
 }
 
-// Is S, the greedy set at lambda^t, still the greedy solution of the lines
-// z_j = c_j - lambda_k b_jk just above t (side > 0) or just below t (side < 0)?
-// Only relations that involve an item moving with k (A) can differ from those
-// at lambda^t.  S is the greedy solution iff its members stay positive and
-// every positive non-member closes a circuit with S (the members of the
-// innermost full set containing it) and ranks below every member of it.
-template <class BK>
-__device__ __forceinline__ bool window_keeps(uint64_t S, uint64_t A, uint64_t Bpos, const double *ptl,
-                                             int lane, BK bk, int k, const uint64_t *tmask,
-                                             const int *tcap, int L, double lk, double t, int side) {
-  auto circuit = [&](int o) -> uint64_t {
-    for (int l = 0; l < L; ++l) {
-      const uint64_t m = tmask[l];
-      if ((m >> o & 1) && popc64(S & m) >= tcap[l]) return S & m;
-    }
-    return 0;
-  };
-  auto line = [&](int j, double &c, double &b) {
-    b = (A >> j & 1) ? bk(j, k) : 0.0;
-    const double add = lk * b;
-    c = ptl[j * 64 + lane] + add;
-  };
-  for (uint64_t m = S & A; m; m &= m - 1) {
-    const int s = __ffsll((long long)m) - 1;
-    double c, b;
-    line(s, c, b);
-    if (!line_pos(c, b, t, side)) return false;
-  }
-  for (uint64_t m = A & ~S; m; m &= m - 1) {
-    const int o = __ffsll((long long)m) - 1;
-    double co, bo;
-    line(o, co, bo);
-    if (!line_pos(co, bo, t, side)) continue;
-    uint64_t circ = circuit(o);
-    if (!circ) return false;
-    for (; circ; circ &= circ - 1) {
-      const int s = __ffsll((long long)circ) - 1;
-      double cs, bs;
-      line(s, cs, bs);
-      if (line_beats(co, bo, o, cs, bs, s, t, side)) return false;
-    }
-  }
-  for (uint64_t m = Bpos & ~A; m; m &= m - 1) {
-    const int o = __ffsll((long long)m) - 1;
-    uint64_t circ = circuit(o) & A;
-    if (!circ) continue;
-    const double co = ptl[o * 64 + lane];
-    for (; circ; circ &= circ - 1) {
-      const int s = __ffsll((long long)circ) - 1;
-      double cs, bs;
-      line(s, cs, bs);
-      if (line_beats(co, 0.0, o, cs, bs, s, t, side)) return false;
-    }
-  }
-  return true;
-}
-
 struct EllGeom {
   int M, K, region;   // region: bytes of per-wave LDS
   int rows;           // statistics rows (of 65 doubles) per chunk
@@ -271,8 +214,13 @@ __device__ __forceinline__ void scd_user(const SweepArgs &a, int M, int K, int L
     const double lk = lam[k];
     if (mode == KS_WINDOW) {
       const double whi = kst[k].whi, wlo = kst[k].wlo;
-      if (window_keeps(S, A, pos & ~S, ptl, lane, bk, k, tmask, tcap, L, lk, whi, 1) &&
-          window_keeps(S, A, pos & ~S, ptl, lane, bk, k, tmask, tcap, L, lk, wlo, wlo > 0.0 ? -1 : 1))
+      auto line = [&](int j, double &c, double &b) {
+        b = (A >> j & 1) ? bk(j, k) : 0.0;
+        const double add = lk * b;
+        c = ptl[j * 64 + lane] + add;
+      };
+      if (window_keeps(S, A, pos & ~S, line, tmask, tcap, L, whi, 1) &&
+          window_keeps(S, A, pos & ~S, line, tmask, tcap, L, wlo, wlo > 0.0 ? -1 : 1))
         continue;
     }
     // start: only horizontal positive lines, in p~ order

@@ -110,7 +110,10 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
   int *kmode = nullptr;
   uint32_t *kcnt = nullptr, *kpos = nullptr, *kovf = nullptr, *nstage = nullptr;
   unsigned long long *hmin = nullptr, *hmax = nullptr;
+  double *kcorr = nullptr, *ugap = nullptr;
   if (SCD) {
+    kcorr = (double *)carve((size_t)K * 8 + 8);   // [K] window corrections, [K] widest window
+    ugap = (double *)carve((size_t)U * 16);        // per user: gap and scale of the window filter
     hs = (double *)carve((size_t)K * KP_NB * 8);
     hc = (uint32_t *)carve((size_t)K * KP_NB * 4);
     kmode = (int *)carve((size_t)K * 4);
@@ -133,8 +136,15 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
       kovf[t] = 0u;
       hmin[t] = ~0ull;
       hmax[t] = 0ull;
+      kcorr[t] = 0.0;
     }
-    if (tid == 0) *nstage = 0u;
+    if (tid == 0) {
+      *nstage = 0u;
+      double m = 0.0;
+      for (int k = 0; k < K; ++k)
+        if (a.st[k].mode == KS_WINDOW) m = a.st[k].hw > m ? a.st[k].hw : m;
+      kcorr[K] = m;
+    }
   }
   const int64_t N = a.pr.N;
   if (SCD && !a.want_stats) {
@@ -144,7 +154,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
     __syncthreads();
     for (int t = tid; t < K; t += NT) {
       const int m = kmode[t];
-      if (m == KS_EXP || m == KS_EMIT_BUCKET || m == KS_HULL_BUCKET || m == KS_REFINE || m == KS_EMIT_RANGE)
+      if (m == KS_EXP || m == KS_EMIT_BUCKET || m == KS_HULL_BUCKET || m == KS_REFINE || m == KS_EMIT_RANGE ||
+          m == KS_WINDOW)
         busy = 1;
     }
     __syncthreads();
@@ -343,6 +354,27 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
           tu[o] = -1;
         }
       }
+      if (SCD && kcorr[K] > 0.0) {
+        // window filter of this user: the smallest gap between its p~ (in
+        // rank order) and between them and zero, over the lines that can
+        // turn positive inside the widest window
+        float bm = 0.0f;
+        const float *bu = bt + (size_t)u * M * K;
+        for (int e = 0; e < M * K; ++e) bm = bu[e] > bm ? bu[e] : bm;
+        const double hm = kcorr[K];
+        const double H = hm * (double)bm * (1.0 + 0x1p-30) + 0x1p-36 * (1.0 + (double)bm * hm);
+        double gmin = 1e300, prev = 0.0;
+        const double top = z[perm[u * M]];
+        for (int r = 0; r < M; ++r) {
+          const double v = z[perm[u * M + r]];
+          if (!(v > -H)) break;
+          gmin = fabs(v) < gmin ? fabs(v) : gmin;
+          if (r > 0) gmin = prev - v < gmin ? prev - v : gmin;
+          prev = v;
+        }
+        ugap[2 * u] = gmin;
+        ugap[2 * u + 1] = fabs(top) + H;
+      }
       double Pi = 0.0, Gi = 0.0;
       const float *pp = pl + u * M;
       for (int j = 0; j < M; ++j) {
@@ -373,12 +405,37 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
       if (SCD) {
         const int mode = kmode[k];
         if (mode == KS_EXP || mode == KS_EMIT_BUCKET || mode == KS_HULL_BUCKET ||
-            mode == KS_REFINE || mode == KS_EMIT_RANGE) {
+            mode == KS_REFINE || mode == KS_EMIT_RANGE || mode == KS_WINDOW) {
           const double lk = lam[k];
           const double *zu = pt + u * M;
           uint64_t A = 0;   // moving lines: b_jk > 0
-          for (int j = 0; j < M; ++j) if (bu[j * K + k] > 0.0f) A |= 1ull << j;
-          if (A) {
+          float bmk = 0.0f;
+          for (int j = 0; j < M; ++j) {
+            const float bj = bu[j * K + k];
+            if (bj > 0.0f) A |= 1ull << j;
+            bmk = bj > bmk ? bj : bmk;
+          }
+          bool walk = A != 0;
+          if (walk && mode == KS_WINDOW) {
+            // no breakpoint of this user inside the window: nothing to emit
+            // and its consumption just above the window is v_ik (no correction)
+            if (window_calm(ugap[2 * u], ugap[2 * u + 1], kst[k].hw, (double)bmk, lk)) {
+              walk = false;
+            } else {
+              auto line = [&](int j, double &c, double &b) {
+                b = (A >> j & 1) ? (double)bu[j * K + k] : 0.0;
+                const double add = lk * b;
+                c = zu[j] + add;
+              };
+              const double whi = kst[k].whi, wlo = kst[k].wlo;
+              if (window_keeps(S0, A, Pm[u] & ~S0, line, a.tree.mask, a.tree.cap, a.tree.L, whi, 1) &&
+                  window_keeps(S0, A, Pm[u] & ~S0, line, a.tree.mask, a.tree.cap, a.tree.L, wlo,
+                               wlo > 0.0 ? -1 : 1))
+                walk = false;
+            }
+          }
+          if (walk) {
+            double above = 0.0;   // window: increments of the breakpoints above it
             const KState &ks = kst[k];
             const double center = ks.center, delta = ks.delta;
             const int bstar = ks.bstar;
@@ -454,8 +511,14 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
               const double bo_d = (double)bu[bo * K + k];
               const double v2 = bs >= 0 ? bo_d - (double)bu[bs * K + k] : bo_d;
               S = (S | (1ull << bo)) & ~(bs >= 0 ? (1ull << bs) : 0ull);
+              if (mode == KS_WINDOW) {
+                const uint64_t key = dkey(best);
+                if (key < klo) break;                 // every later breakpoint is lower
+                if (key > khi) { above = above + v2; continue; }
+              }
               record_event(a, ks, k, best, v2, mode, hs, hc, hmin, hmax, kcnt, kovf, nstage, bid);
             }
+            if (mode == KS_WINDOW && above != v) atomicAdd(&kcorr[k], above - v);
           }
         }
       }
@@ -480,7 +543,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
   if (a.want_stats) {
     for (int t = tid; t < K + 2; t += NT) a.partials[(size_t)bid * (K + 2) + t] = acc[t];
   }
-  if (SCD) publish_block(a, K, hs, hc, hmin, hmax, kcnt, kpos, kovf, nstage, tid, NT, bid);
+  if (SCD) publish_block(a, K, hs, hc, hmin, hmax, kcnt, kpos, kovf, nstage, tid, NT, bid, kcorr);
 }
 
 
@@ -1479,11 +1542,28 @@ size_t kp_sweep_lds_bytes(int U, int M, int K, bool scd, int fmt) {
   if (fmt == 1) s += 2 * r16((size_t)NT * ECH * 4);  // staged CSR entries
   if (scd)
     s += r16((size_t)K * sizeof(KState)) + r16((size_t)K * KP_NB * 8) +
-         r16((size_t)K * KP_NB * 4) + 4 * r16((size_t)K * 4) + 2 * r16((size_t)K * 8) + r16(16);
+         r16((size_t)K * KP_NB * 4) + 4 * r16((size_t)K * 4) + 2 * r16((size_t)K * 8) + r16(16) +
+         r16((size_t)K * 8 + 8) + r16((size_t)U * 16);   // window corrections, per-user filter
   return s;
 }
 
-hipError_t kp_launch_sweep(const SweepArgs &a, int U, int grid, bool scd, hipStream_t stream) {
+// Blocks of the general sweep kernel that can be resident at once (0 if unknown).
+int kp_sweep_resident_grid(int U, int M, int K, bool scd, int fmt) {
+  const size_t lds = kp_sweep_lds_bytes(U, M, K, scd, fmt);
+  const void *fn = fmt == 0 ? (scd ? (const void *)k_sweep<0, true> : (const void *)k_sweep<0, false>)
+                            : (scd ? (const void *)k_sweep<1, true> : (const void *)k_sweep<1, false>);
+  if (lds > 64 * 1024 && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return 0;
+  int per_cu = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, NT, lds) != hipSuccess || per_cu < 1) return 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  return per_cu * cus;
+}
+
+hipError_t kp_launch_sweep(const SweepArgs &a, int U, int grid, bool scd, hipStream_t stream,
+                           int *used) {
   TileGeom g;
   g.U = U;
   g.M = a.pr.M;
@@ -1491,14 +1571,22 @@ hipError_t kp_launch_sweep(const SweepArgs &a, int U, int grid, bool scd, hipStr
   g.aligned = a.pr.fmt == 0 && ((uintptr_t)a.pr.b & 15) == 0 &&
               (((int64_t)U * g.M * g.K) & 3) == 0;
   const size_t lds = kp_sweep_lds_bytes(U, g.M, g.K, scd, a.pr.fmt);
+  const void *fn = a.pr.fmt == 0 ? (scd ? (const void *)k_sweep<0, true> : (const void *)k_sweep<0, false>)
+                                 : (scd ? (const void *)k_sweep<1, true> : (const void *)k_sweep<1, false>);
   if (lds > 64 * 1024) {
     // shapes with many knapsacks need more than the default 64 KB of LDS
     // (gfx950 has 160 KB per workgroup)
-    const void *fn = a.pr.fmt == 0 ? (scd ? (const void *)k_sweep<0, true> : (const void *)k_sweep<0, false>)
-                                   : (scd ? (const void *)k_sweep<1, true> : (const void *)k_sweep<1, false>);
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
+  // persistent launch: at most the blocks that can be resident at once
+  int per_cu = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, NT, lds) == hipSuccess && per_cu > 0 &&
+      hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0) {
+    if (grid > per_cu * cus) grid = per_cu * cus;
+  }
+  if (used) *used = grid;
   if (a.pr.fmt == 0) {
     if (scd) hipLaunchKernelGGL((k_sweep<0, true>), dim3(grid), dim3(NT), lds, stream, a, g);
     else hipLaunchKernelGGL((k_sweep<0, false>), dim3(grid), dim3(NT), lds, stream, a, g);
