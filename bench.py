@@ -116,41 +116,45 @@ def _csv_rows(path):
         return list(csv.DictReader(f))
 
 
-def summarize_trace(trace_dir, bench_log, kernel_sub):
+def summarize_trace(trace_dir, bench_log, kernel_subs):
     """Markdown summary of a rocprofv3 --kernel-trace --stats run of bench.py:
     the per-kernel statistics and the average duration of the timed sweep
-    launches (the last `launches` dispatches of the sweep kernel)."""
+    passes (the last `launches` dispatches of each kernel of a pass;
+    kernel_subs: "|"-separated name fragments of the kernels of one pass)."""
     rec = next(json.loads(l) for l in open(bench_log) if l.startswith("{"))
     stats = _csv_rows(os.path.join(trace_dir, "run_kernel_stats.csv"))
     trace = _csv_rows(os.path.join(trace_dir, "run_kernel_trace.csv"))
-    disp = [r for r in trace if kernel_sub in r["Kernel_Name"]]
-    disp.sort(key=lambda r: int(r["Start_Timestamp"]))
     n = rec["roofline"]["launches"]
-    timed = disp[-n:]
-    durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6 for r in timed]
+    subs = kernel_subs.split("|")
+    per = []
+    for sub in subs:
+        disp = sorted((r for r in trace if sub in r["Kernel_Name"]), key=lambda r: int(r["Start_Timestamp"]))
+        per.append([(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6 for r in disp[-n:]])
+    durs = [sum(x) for x in zip(*per)]
     avg = sum(durs) / len(durs)
     out = [f"| kernel | calls | avg ms | total ms | % |", "|---|---|---|---|---|"]
     for r in stats[:12]:
         out.append(f"| `{r['Name'][:60]}` | {r['Calls']} | {float(r['AverageNs']) * 1e-6:.3f} | "
                    f"{float(r['TotalDurationNs']) * 1e-6:.1f} | {float(r['Percentage']):.2f} |")
     out.append("")
-    out.append(f"Timed sweep launches (last {n} dispatches of `{kernel_sub}`): "
-               f"average {avg:.3f} ms, min {min(durs):.3f}, max {max(durs):.3f}.")
-    out.append(f"bench.py's own HIP-event average over the same launches: "
-               f"{rec['roofline']['avg_launch_ms']:.3f} ms; "
-               f"{rec['roofline']['algo_bytes_per_launch'] / 1e9:.2f} GB algorithmic bytes per launch "
-               f"-> {rec['roofline']['algo_bytes_per_launch'] / (avg * 1e-3) / 1e9:.1f} GB/s "
-               f"from the trace.")
+    out.append(f"Timed sweep passes (the last {n} dispatches of " + " + ".join(f"`{x}`" for x in subs) +
+               f"): average {avg:.3f} ms per pass (kernels only), min {min(durs):.3f}, max {max(durs):.3f}; "
+               + ", ".join(f"`{x}` {sum(p) / len(p):.3f} ms" for x, p in zip(subs, per)) + ".")
+    out.append(f"bench.py's own HIP-event average per pass (both launches and the list reset "
+               f"between the events): {rec['roofline']['avg_launch_ms']:.3f} ms; "
+               f"{rec['roofline']['algo_bytes_per_launch'] / 1e9:.2f} GB algorithmic bytes per pass "
+               f"-> {rec['roofline']['algo_bytes_per_launch'] / (avg * 1e-3) / 1e9:.1f} GB/s from the trace.")
     out.append(f"bench line: value {rec['value']:.4g} {rec['unit']}, ms_per_step {rec['ms_per_step']:.2f}, "
                f"passes_per_step {rec['passes_per_step']}.")
     print("\n".join(out))
 
 
-def summarize_pmc(fetch_dir, write_dir, cfetch_dir, cwrite_dir, kernel_sub, launches, workload,
+def summarize_pmc(fetch_dir, write_dir, cfetch_dir, cwrite_dir, kernel_subs, launches, workload,
                   copy_bytes):
-    """HBM bytes per sweep launch from FETCH_SIZE / WRITE_SIZE (KiB per
-    dispatch), each scaled by what the same counter reads for a plain copy of
-    known size; written with the hash of the kernel sources they were taken on."""
+    """HBM bytes per sweep pass from FETCH_SIZE / WRITE_SIZE (KiB per
+    dispatch) of the pass's kernels ("|"-separated name fragments), each
+    scaled by what the same counter reads for a plain copy of known size;
+    written with the hash of the kernel sources they were taken on."""
     def per_dispatch(d, counter, sub):
         rows = [r for r in _csv_rows(os.path.join(d, "run_counter_collection.csv"))
                 if sub in r["Kernel_Name"] and r["Counter_Name"] == counter]
@@ -158,16 +162,16 @@ def summarize_pmc(fetch_dir, write_dir, cfetch_dir, cwrite_dir, kernel_sub, laun
         for r in rows:
             vals[r["Dispatch_Id"]] = vals.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
         return [vals[k] for k in sorted(vals, key=int)]
-    f = per_dispatch(fetch_dir, "FETCH_SIZE", kernel_sub)[-launches:]
-    w = per_dispatch(write_dir, "WRITE_SIZE", kernel_sub)[-launches:]
-    cf = per_dispatch(cfetch_dir, "FETCH_SIZE", "")
-    cw = per_dispatch(cwrite_dir, "WRITE_SIZE", "")
-    cf_k, cw_k = max(cf), max(cw)          # the copy dispatches (KiB)
+    subs = kernel_subs.split("|")
+    f = [sum(x) for x in zip(*[per_dispatch(fetch_dir, "FETCH_SIZE", s)[-launches:] for s in subs])]
+    w = [sum(x) for x in zip(*[per_dispatch(write_dir, "WRITE_SIZE", s)[-launches:] for s in subs])]
+    cf_k = max(per_dispatch(cfetch_dir, "FETCH_SIZE", ""))    # the copy dispatches (KiB)
+    cw_k = max(per_dispatch(cwrite_dir, "WRITE_SIZE", ""))
     sf = copy_bytes / (cf_k * 1024.0)
     sw = copy_bytes / (cw_k * 1024.0)
     fb = sum(f) / len(f) * 1024.0 * sf
     wb = sum(w) / len(w) * 1024.0 * sw
-    rec = {"workload": workload, "kernel": kernel_sub, "kernel_hash": kernel_hash(),
+    rec = {"workload": workload, "kernels": subs, "kernel_hash": kernel_hash(),
            "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
            "hbm_bytes_per_launch": fb + wb, "fetch_scale": sf, "write_scale": sw,
            "launches_averaged": len(f), "copy_probe_bytes": copy_bytes,
@@ -186,10 +190,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="run a plain device copy of BYTES (counter calibration) and exit")
-    ap.add_argument("--summarize-trace", nargs=3, metavar=("TRACE_DIR", "BENCH_LOG", "KERNEL"),
+    ap.add_argument("--summarize-trace", nargs=3, metavar=("TRACE_DIR", "BENCH_LOG", "KERNELS"),
                     help="print a markdown summary of a rocprofv3 kernel trace of bench.py and exit")
     ap.add_argument("--summarize-pmc", nargs=8,
-                    metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR", "KERNEL",
+                    metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR", "KERNELS",
                              "LAUNCHES", "WORKLOAD", "COPY_BYTES"),
                     help="print the HBM traffic record from rocprofv3 counter runs and exit")
     args = ap.parse_args()
@@ -251,7 +255,7 @@ def main():
     avg_ms = ms_k / max(launches, 1)
     achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
     traffic = traffic_for(args.workload, per_launch_bytes)
-    kernel_name = ("k_ell (uniform-row CSR, scd)" if meta["csr_d"] and meta["M"] <= 16
+    kernel_name = ("k_ell window pass (all users, then the listed ones)" if meta["csr_d"] and meta["M"] <= 16
                    else "k_sweep (scd)")
     rec = {
         "metric": "user-subproblem solves/s per SCD sweep",
