@@ -102,6 +102,30 @@ def device_instance(c: int, run: int = 0, N=None):
     return out, B, tree, meta
 
 
+def device_batched(run: int = 0, n: int = 256):
+    """The batched ragged workload generated on the GPU: the same bytes and
+    budgets as kpgen.batched_instances (dense U(0,1) p and b, B_k = 0.1 D_k,
+    one top-Q cap).  Returns a list of (tensors, B, tree, meta)."""
+    import torch
+    seed = 1000 * 5 + run
+    L = lib()
+    st = _stream()
+    out = []
+    for s_, (N, M, K, Q, sd) in enumerate(kpgen.batched_shapes(seed, n)):
+        p = torch.empty(N * M, dtype=torch.float32, device="cuda")
+        b = torch.empty(N * M * K, dtype=torch.float32, device="cuda")
+        _ok(L.kpgen_values(sd, kpgen.S_P, 0, N * M, None, p.data_ptr(), st))
+        _ok(L.kpgen_values(sd, kpgen.S_B, 0, N * M * K, None, b.data_ptr(), st))
+        sums = torch.zeros(K, dtype=torch.int64, device="cuda")
+        _ok(L.kpgen_colsum_dense(b.data_ptr(), N * M, K, sums.data_ptr(), st))
+        D = sums.cpu().numpy().astype(np.float64) * 2.0 ** -24
+        B = kpgen.budgets(D, 0.1, 1)
+        tree = kpgen.tree_topq(M, Q)
+        meta = dict(N=N, M=M, K=K, Q=Q, seed=sd, name=f"c5 instance {s_}", dist=kpgen.DIST_UNIFORM, csr_d=0)
+        out.append((dict(p=p, b=b), B, tree, meta))
+    return out
+
+
 def host_users(meta, B, tree, users):
     """Host-generated copy of the given users of a device instance (for the
     oracle), with the full instance's budgets."""

@@ -332,6 +332,7 @@ class BatchedSCD:
         self.stream = torch.cuda.Stream()
         with torch.cuda.stream(self.stream):
             self.ctx = ctx or Context()
+            self.ctx.sync_stream()   # a given context is rebound to the plan's stream
         self.probs = list(probs)
         n = len(self.probs)
         self.a = [torch.zeros(pr.K, dtype=torch.float64, device="cuda") if lam0 is None

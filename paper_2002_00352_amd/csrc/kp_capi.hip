@@ -20,15 +20,16 @@ size_t kp_sweep_lds_bytes(int U, int M, int K, bool scd, int fmt);
 hipError_t kp_launch_sweep(const SweepArgs &a, int U, int grid, bool scd, hipStream_t stream,
                            int *used);
 int kp_sweep_resident_grid(int U, int M, int K, bool scd, int fmt);
+int kp_sweep_batched_resident(size_t lds);
 hipError_t kp_launch_reduce_stats(const double *partials, int nblk, int K, const double *lam,
                                   const double *B, double *R, double *g, double *P,
                                   hipStream_t stream);
 hipError_t kp_launch_scd_init(KState *st, int K, const double *lam_in, const uint8_t *kmask,
-                              const double *delta_hint, int window, hipStream_t stream);
+                              double *hist, int hinted, int window, hipStream_t stream);
 hipError_t kp_launch_scd_locate_select(KState *st, int K, const double *B, const double *R,
-                                       double *hist_sum, uint32_t *hist_cnt, const double *ev1,
-                                       const double *ev2, uint32_t emit_cap, int *pending,
-                                       unsigned int *win, hipStream_t stream);
+                                       const int *rinst, double *hist_sum, uint32_t *hist_cnt,
+                                       const double *ev1, const double *ev2, uint32_t emit_cap,
+                                       int *pending, unsigned int *win, hipStream_t stream);
 hipError_t kp_launch_scd_finish(const KState *st, int K, const double *lam_in, double *lam_out,
                                 double *delta_next, hipStream_t stream);
 hipError_t kp_launch_dd_update(int K, double alpha, const double *R, const double *B, double *lam,
@@ -58,7 +59,8 @@ hipError_t kp_launch_sweep_batched(const SweepArgs *descs, const TileGeom *geoms
                                    const int *block_off, int n_inst, int total_blocks, size_t lds,
                                    hipStream_t stream);
 hipError_t kp_launch_batched_aux(int which, const void *tab, int n, KState *st, const void *lam_ptrs,
-                                 const int *kinst, const int *klocal, hipStream_t stream);
+                                 const int *kinst, const int *klocal, double *hint, const uint64_t *eoff,
+                                 const uint32_t *ecap, hipStream_t stream);
 TileGeom kp_tile_geom(const SweepArgs &a, int U);
 size_t kp_coldesc_size();
 void kp_coldesc_fill(void *dst, const double *partials, const double *lam, const double *B,
@@ -95,7 +97,8 @@ constexpr uint32_t kEmitCapDefault = 1u << 20;
 constexpr int kMaxPasses = 96;
 constexpr uint32_t kStageCap = 4096;    // staged events per block per pass (at least)
 constexpr uint32_t kStageCapMax = 65536;
-constexpr uint32_t kEmitCapBatched = 1u << 16;   // emitted events per (instance, knapsack) per pass
+constexpr uint32_t kEmitCapBatched = 1u << 16;   // emitted events per (instance, knapsack) per pass (at least)
+constexpr double kEmitBytesBatched = 8.0e9;        // bound on a batch's emission buffers
 
 struct Ctx {
   hipStream_t stream = nullptr;
@@ -701,14 +704,17 @@ kp_status kp_scd_sweep_masked(void *ctx, const kp_problem *prob, const double *l
   // window hint from the previous call with the same K (performance only)
   if (!c->delta_dev || c->delta_K != K) {
     if (c->delta_dev) HIP_TRY(hipFree(c->delta_dev));
-    HIP_TRY(hipMalloc(&c->delta_dev, (size_t)K * 16));   // [K] bucket widths, [K] last steps
+    // [K] bucket widths, [K] last steps, [K] lambda^{t-1}, [K] lambda^{t-2}
+    HIP_TRY(hipMalloc(&c->delta_dev, (size_t)K * 32));
     c->delta_K = K;
     c->delta_valid = false;
   }
+  if (!c->delta_valid)   // no history: NaN multipliers (all bits set)
+    HIP_TRY(hipMemsetAsync(c->delta_dev + 2 * K, 0xFF, (size_t)K * 16, c->stream));
   // the window pass needs the statistics of the same pass (R at lambda_in)
   const int window = (c->window_enabled && P.pr.N > 0) ? 1 : 0;
-  HIP_TRY(kp_launch_scd_init(w.st, K, lambda_in, kmask ? w.kmask : nullptr,
-                             c->delta_valid ? c->delta_dev : nullptr, window, c->stream));
+  HIP_TRY(kp_launch_scd_init(w.st, K, lambda_in, kmask ? w.kmask : nullptr, c->delta_dev,
+                             c->delta_valid ? 1 : 0, window, c->stream));
   // the first pass runs split (all users, then the listed ones) when every
   // knapsack still searching starts with a window
   bool split = false;
@@ -742,7 +748,7 @@ kp_status kp_scd_sweep_masked(void *ctx, const kp_problem *prob, const double *l
         HIP_TRY(kp_launch_reduce_stats(w.partials, 1, K, lambda_in, w.B, Rd, gd, Pd, c->stream));
       }
     }
-    HIP_TRY(kp_launch_scd_locate_select(w.st, K, w.B, Rd, w.hist_sum, w.hist_cnt, w.ev1, w.ev2,
+    HIP_TRY(kp_launch_scd_locate_select(w.st, K, w.B, Rd, nullptr, w.hist_sum, w.hist_cnt, w.ev1, w.ev2,
                                         w.emit_cap, w.pending, w.win, c->stream));
     HIP_TRY(hipMemcpyAsync(c->pinned, w.pending, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync(c->pinned + 2, w.err, 8, hipMemcpyDeviceToHost, c->stream));
@@ -1092,6 +1098,7 @@ kp_status kp_primal_fixup(void *ctx, const kp_problem *prob, const double *lambd
 struct BatchPlan {
   Ctx *c = nullptr;
   int n = 0, Kf = 0, GB = 0, ncol = 0;
+  double bytes = 0.0;   // algorithmic bytes of one sweep pass over every instance
   int64_t T = 0;
   size_t lds = 0;
   uint32_t cap = 0;
@@ -1104,6 +1111,10 @@ struct BatchPlan {
   void *lam_tab[2] = {nullptr, nullptr};   // [dir]: lambda_in pointer table; the other dir's is lambda_out
   void *coltab[2] = {nullptr, nullptr};    // [dir]: statistics column table (reads lambda_in)
   KState *kst = nullptr;
+  double *hint = nullptr;   // [2 Kf] bucket widths and last steps carried between iterations
+  uint64_t *eoff = nullptr; // [Kf] start of each knapsack's emission buffer
+  uint32_t *ecap = nullptr; // [Kf] its capacity
+  bool window = true;       // iterations start with a window where the last step allows
   double *Bf = nullptr, *hs = nullptr, *e1 = nullptr, *e2 = nullptr, *stats = nullptr;
   uint32_t *hc = nullptr;
   unsigned long long *err = nullptr;
@@ -1113,11 +1124,14 @@ struct BatchPlan {
 };
 
 kp_status plan_first_pass(BatchPlan *p, int dir, hipStream_t s) {
-  HIP_TRY(kp_launch_batched_aux(1, nullptr, p->Kf, p->kst, p->lam_tab[dir], p->kin, p->klo, s));
+  HIP_TRY(kp_launch_batched_aux(p->window ? 3 : 1, nullptr, p->Kf, p->kst, p->lam_tab[dir], p->kin, p->klo, p->hint,
+                                p->eoff, p->ecap, s));
   if (p->T > 0) HIP_TRY(kp_launch_sweep_batched(p->d[dir][1], p->geom, p->boff, p->n, p->GB, p->lds, s));
-  HIP_TRY(kp_launch_batched_aux(0, p->coltab[dir], p->ncol, nullptr, nullptr, nullptr, nullptr, s));
-  HIP_TRY(kp_launch_scd_locate_select(p->kst, p->Kf, p->Bf, nullptr, p->hs, p->hc, p->e1, p->e2, p->cap, p->pend, nullptr, s));
-  HIP_TRY(kp_launch_batched_aux(2, nullptr, p->Kf, p->kst, p->lam_tab[1 - dir], p->kin, p->klo, s));
+  HIP_TRY(kp_launch_batched_aux(0, p->coltab[dir], p->ncol, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                nullptr, s));
+  HIP_TRY(kp_launch_scd_locate_select(p->kst, p->Kf, p->Bf, p->stats, p->kin, p->hs, p->hc, p->e1, p->e2, p->cap, p->pend, nullptr, s));
+  HIP_TRY(kp_launch_batched_aux(2, nullptr, p->Kf, p->kst, p->lam_tab[1 - dir], p->kin, p->klo, p->hint, nullptr,
+                                nullptr, s));
   HIP_TRY(hipMemcpyAsync(p->pinned, p->pend, sizeof(int), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(p->pinned + 2, p->err, 8, hipMemcpyDeviceToHost, s));
   return KP_OK;
@@ -1125,6 +1139,14 @@ kp_status plan_first_pass(BatchPlan *p, int dir, hipStream_t s) {
 
 kp_status plan_step(BatchPlan *p, int dir, double *stats_out, bool graph) {
   hipStream_t s = p->c->stream;
+  Ctx *c = p->c;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (c->timing) {
+    e0 = take_event(c);
+    e1 = take_event(c);
+    if (e0 && e1) (void)hipEventRecord(e0, s);
+  }
+  int passes = 1;
   if (graph) {
     if (!p->exec[dir]) {
       HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -1148,11 +1170,21 @@ kp_status plan_step(BatchPlan *p, int dir, double *stats_out, bool graph) {
     if (p->pinned[0] == 0) break;
     if (pass >= kMaxPasses) return fail(KP_ERR_INTERNAL, "SCD threshold search exceeded %d passes", kMaxPasses);
     if (p->T > 0) HIP_TRY(kp_launch_sweep_batched(p->d[dir][0], p->geom, p->boff, p->n, p->GB, p->lds, s));
-    HIP_TRY(kp_launch_scd_locate_select(p->kst, p->Kf, p->Bf, nullptr, p->hs, p->hc, p->e1, p->e2, p->cap, p->pend, nullptr, s));
-    HIP_TRY(kp_launch_batched_aux(2, nullptr, p->Kf, p->kst, p->lam_tab[1 - dir], p->kin, p->klo, s));
+    ++passes;
+    HIP_TRY(kp_launch_scd_locate_select(p->kst, p->Kf, p->Bf, p->stats, p->kin, p->hs, p->hc, p->e1, p->e2, p->cap, p->pend, nullptr, s));
+    HIP_TRY(kp_launch_batched_aux(2, nullptr, p->Kf, p->kst, p->lam_tab[1 - dir], p->kin, p->klo, p->hint, nullptr,
+                                nullptr, s));
     HIP_TRY(hipMemcpyAsync(p->pinned, p->pend, sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(p->pinned + 2, p->err, 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+  }
+  if (c->timing && e0 && e1) {
+    // the whole iteration (every pass and the search kernels between them)
+    (void)hipEventRecord(e1, s);
+    c->ev_pending.push_back({e0, e1});
+    c->sweep_launches += passes;
+    c->sweep_bytes += passes * p->bytes;
+    if (c->ev_pending.size() > 256) drain_events(c, true);
   }
   if (stats_out)
     HIP_TRY(hipMemcpyAsync(stats_out, p->stats, (size_t)p->ncol * 8, hipMemcpyDeviceToDevice, s));
@@ -1189,21 +1221,53 @@ kp_status plan_create(Ctx *c, const kp_problem *probs, int n, const double *cons
   int64_t T = 0;
   int Kf = 0;
   for (auto &q : P) { T += q.ntiles; Kf += q.pr.K; }
-  const int G = (int)std::max<int64_t>(n, std::min<int64_t>(T, kMaxGrid));
+  size_t lds = 0;
+  for (int s = 0; s < n; ++s)
+    lds = std::max(lds, kp_sweep_lds_bytes(P[s].U, P[s].pr.M, P[s].pr.K, true, P[s].pr.fmt));
+  // blocks are split among the instances in proportion to their tiles; many
+  // more blocks than can be resident at once keep the split fine-grained, and
+  // the hardware dispatcher balances them (every instance gets at least one)
+  int gmax = 8192;
+  const int res = kp_sweep_batched_resident(lds);
+  if (res > 0) gmax = std::min(gmax, 16 * res);
+  const int G = (int)std::max<int64_t>(n, std::min<int64_t>(T, gmax));
+  // algorithmic bytes of one pass over every instance
+  double bytes = 0.0;
+  for (int s = 0; s < n; ++s) {
+    bytes += P[s].bytes;
+    if (P[s].pr.fmt == KP_B_CSR && P[s].pr.N > 0) {
+      int64_t nnz = 0;
+      HIP_TRY(hipMemcpy(&nnz, P[s].pr.rowptr + P[s].pr.N * P[s].pr.M, 8, hipMemcpyDeviceToHost));
+      bytes += (double)nnz * 8.0;
+    }
+  }
   std::vector<int> boff(n + 1, 0), koff(n + 1, 0);
   std::vector<size_t> poff(n + 1, 0);
-  size_t lds = 0;
   for (int s = 0; s < n; ++s) {
     int64_t b = T ? (int64_t)std::llround((double)G * P[s].ntiles / (double)T) : 1;
     b = std::max<int64_t>(1, std::min<int64_t>(b, std::max<int64_t>(1, P[s].ntiles)));
     boff[s + 1] = boff[s] + (int)b;
     koff[s + 1] = koff[s] + P[s].pr.K;
     poff[s + 1] = poff[s] + (size_t)b * (P[s].pr.K + 2);
-    lds = std::max(lds, kp_sweep_lds_bytes(P[s].U, P[s].pr.M, P[s].pr.K, true, P[s].pr.fmt));
   }
   if (lds > kMaxLds) { plan_free(p); return fail(KP_ERR_UNSUPPORTED, "an instance needs too much LDS"); }
   p->T = T; p->Kf = Kf; p->GB = boff[n]; p->lds = lds; p->cap = kEmitCapBatched;
+  p->bytes = bytes;
   const uint32_t cap = p->cap;
+  // emission buffers per instance: room for two breakpoints per user and
+  // knapsack (at least the uniform capacity, at most 2^20), scaled down when
+  // the whole batch would exceed kEmitBytesBatched
+  std::vector<uint32_t> icap(n);
+  double ebytes = 0.0;
+  for (int s = 0; s < n; ++s) {
+    icap[s] = (uint32_t)std::min<int64_t>(1 << 20, std::max<int64_t>(cap, 2 * P[s].pr.N));
+    ebytes += (double)P[s].pr.K * icap[s] * 16.0;
+  }
+  if (ebytes > kEmitBytesBatched)
+    for (int s = 0; s < n; ++s)
+      icap[s] = std::max<uint32_t>(cap, (uint32_t)(icap[s] * (kEmitBytesBatched / ebytes)));
+  std::vector<uint64_t> ioff(n + 1, 0);
+  for (int s = 0; s < n; ++s) ioff[s + 1] = ioff[s] + (uint64_t)P[s].pr.K * icap[s];
   const int ncol = Kf + 2 * n;
   p->ncol = ncol;
   Carve cv;
@@ -1216,8 +1280,10 @@ kp_status plan_create(Ctx *c, const kp_problem *probs, int n, const double *cons
   const size_t o_st = cv.take((size_t)Kf * sizeof(KState));
   const size_t o_hs = cv.take((size_t)Kf * KP_NB * 8);
   const size_t o_hc = cv.take((size_t)Kf * KP_NB * 4);
-  const size_t o_e1 = cv.take((size_t)Kf * cap * 8);
-  const size_t o_e2 = cv.take((size_t)Kf * cap * 8);
+  const size_t o_e1 = cv.take((size_t)ioff[n] * 8);
+  const size_t o_e2 = cv.take((size_t)ioff[n] * 8);
+  const size_t o_eo = cv.take((size_t)Kf * 8);
+  const size_t o_ec = cv.take((size_t)Kf * 4);
   const size_t o_s1 = cv.take((size_t)p->GB * kStageCap * 8);
   const size_t o_s2 = cv.take((size_t)p->GB * kStageCap * 8);
   const size_t o_sk = cv.take((size_t)p->GB * kStageCap * 2);
@@ -1230,6 +1296,7 @@ kp_status plan_create(Ctx *c, const kp_problem *probs, int n, const double *cons
   const size_t o_tab0 = cv.take((size_t)ncol * kp_coldesc_size());
   const size_t o_tab1 = cv.take((size_t)ncol * kp_coldesc_size());
   const size_t o_stat = cv.take((size_t)ncol * 8);
+  const size_t o_hint = cv.take((size_t)Kf * 32);  // per knapsack: bucket width, last step, two past multipliers
   if (c->max_ws && cv.off > c->max_ws) {
     plan_free(p);
     return fail(KP_ERR_NOMEM, "batched plan needs %zu bytes, above the context cap", cv.off);
@@ -1250,6 +1317,15 @@ kp_status plan_create(Ctx *c, const kp_problem *probs, int n, const double *cons
   p->geom = (TileGeom *)(w + o_geom);
   p->boff = (int *)(w + o_boff);
   p->kst = (KState *)(w + o_st);
+  p->hint = (double *)(w + o_hint);
+  p->eoff = (uint64_t *)(w + o_eo);
+  p->ecap = (uint32_t *)(w + o_ec);
+  p->window = c->window_enabled;
+  if (hipMemset(p->hint, 0, (size_t)Kf * 16) != hipSuccess ||
+      hipMemset(p->hint + 2 * (size_t)Kf, 0xFF, (size_t)Kf * 16) != hipSuccess) {
+    plan_free(p);
+    return fail(KP_ERR_HIP, "hipMemset failed");
+  }
   p->Bf = (double *)(w + o_B);
   p->hs = (double *)(w + o_hs);
   p->hc = (uint32_t *)(w + o_hc);
@@ -1269,6 +1345,8 @@ kp_status plan_create(Ctx *c, const kp_problem *probs, int n, const double *cons
   std::vector<TileGeom> hg(n);
   std::vector<double> hB(Kf);
   std::vector<int> kin(Kf), klo(Kf);
+  std::vector<uint64_t> heo(Kf);
+  std::vector<uint32_t> hec(Kf);
   std::vector<const double *> lt0(n), lt1(n);
   std::vector<unsigned char> tab0((size_t)ncol * kp_coldesc_size()), tab1(tab0.size());
   size_t so = 0;
@@ -1284,9 +1362,9 @@ kp_status plan_create(Ctx *c, const kp_problem *probs, int n, const double *cons
     a.st = p->kst + koff[s];
     a.hist_sum = p->hs + (size_t)koff[s] * KP_NB;
     a.hist_cnt = p->hc + (size_t)koff[s] * KP_NB;
-    a.emit_v1 = p->e1 + (size_t)koff[s] * cap;
-    a.emit_v2 = p->e2 + (size_t)koff[s] * cap;
-    a.emit_cap = cap;
+    a.emit_v1 = p->e1 + ioff[s];
+    a.emit_v2 = p->e2 + ioff[s];
+    a.emit_cap = icap[s];
     a.stage_v1 = (double *)(w + o_s1) + (size_t)boff[s] * kStageCap;
     a.stage_v2 = (double *)(w + o_s2) + (size_t)boff[s] * kStageCap;
     a.stage_k = (uint16_t *)(w + o_sk) + (size_t)boff[s] * kStageCap;
@@ -1300,7 +1378,13 @@ kp_status plan_create(Ctx *c, const kp_problem *probs, int n, const double *cons
       hd[d][0][s] = a;
     }
     hg[s] = kp_tile_geom(hd[0][1][s], P[s].U);
-    for (int k = 0; k < K; ++k) { hB[koff[s] + k] = P[s].B[k]; kin[koff[s] + k] = s; klo[koff[s] + k] = k; }
+    for (int k = 0; k < K; ++k) {
+      hB[koff[s] + k] = P[s].B[k];
+      kin[koff[s] + k] = s;
+      klo[koff[s] + k] = k;
+      heo[koff[s] + k] = ioff[s] + (uint64_t)k * icap[s];
+      hec[koff[s] + k] = icap[s];
+    }
     lt0[s] = lam_a[s];
     lt1[s] = lam_b[s];
     // statistics of the first pass are at the direction's input lambda
@@ -1323,6 +1407,8 @@ kp_status plan_create(Ctx *c, const kp_problem *probs, int n, const double *cons
   if (e == hipSuccess) e = up(p->Bf, hB.data(), (size_t)Kf * 8);
   if (e == hipSuccess) e = up(p->kin, kin.data(), (size_t)Kf * 4);
   if (e == hipSuccess) e = up(p->klo, klo.data(), (size_t)Kf * 4);
+  if (e == hipSuccess) e = up(p->eoff, heo.data(), (size_t)Kf * 8);
+  if (e == hipSuccess) e = up(p->ecap, hec.data(), (size_t)Kf * 4);
   if (e == hipSuccess) e = up(p->lam_tab[0], lt0.data(), (size_t)n * 8);
   if (e == hipSuccess) e = up(p->lam_tab[1], lt1.data(), (size_t)n * 8);
   if (e == hipSuccess) e = up(p->coltab[0], tab0.data(), tab0.size());

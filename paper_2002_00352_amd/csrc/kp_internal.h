@@ -71,6 +71,9 @@ struct KState {
   uint64_t hull_lo, hull_hi;  // atomics: key hull of the bucket's events
   double wlo, whi;     // KS_WINDOW: breakpoints with wlo <= v1 <= whi are emitted (wlo may be 0)
   double hw;           // KS_WINDOW: half-width h (whi = center + h, wlo = max(center - h, 0))
+  uint64_t eoff;       // batched: this knapsack's emission buffer (elements from the base), when ecap > 0
+  uint32_t ecap;       // batched: its capacity (0: the uniform capacity of the call)
+  uint32_t pad2;
   double corr;         // KS_WINDOW (atomic): sum over users of C_ik(whi+) - v_ik(x(lambda^t))
 };
 

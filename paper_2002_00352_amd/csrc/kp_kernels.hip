@@ -619,8 +619,36 @@ __global__ void __launch_bounds__(256) k_reduce_stats(const double *partials, in
 // ---------------------------------------------------------------------------
 // SCD threshold search
 // ---------------------------------------------------------------------------
+// The window a search starts with, from the multiplier's history: around
+// lambda_k^t, 1.25x the last step wide, when that step was small against
+// lambda_k^t; else, when the multiplier alternates (it returns close to
+// lambda_k^{t-1}: the drift |lambda^t - lambda^{t-2}| is under 1/8 of the
+// last step), around lambda_k^{t-1}, 1.25x the drift wide.  hw is the
+// farthest window edge from lambda_k^t (the filters bound the lines'
+// movement by it).  step, prev, drift < 0 or NaN: unknown.
+__device__ __forceinline__ void choose_window(KState &s, double step, double prev, double drift) {
+  double c = 0.0, h = 0.0;
+  if (step > 0.0 && KP_WIN_MULT * step <= KP_WIN_MAX_REL * s.center) {
+    c = s.center;
+    h = KP_WIN_MULT * step;
+  } else if (step > 0.0 && drift >= 0.0 && prev >= 0.0 && drift * 8.0 <= step) {
+    const double floor_ = (prev > 0x1p-20 ? prev : 0x1p-20) * 0x1p-30;
+    c = prev;
+    h = KP_WIN_MULT * (drift > floor_ ? drift : floor_);
+  } else {
+    return;
+  }
+  s.mode = KS_WINDOW;
+  s.whi = c + h;
+  s.wlo = c - h > 0.0 ? c - h : 0.0;
+  const double up = s.whi - s.center, dn = s.center - s.wlo;
+  s.hw = fmax(fabs(up), fabs(dn));
+  s.klo = dkey(s.wlo);
+  s.khi = dkey(s.whi);
+}
+
 __global__ void k_scd_init(KState *st, int K, const double *lam_in, const uint8_t *kmask,
-                           const double *delta_hint, int window) {
+                           double *hist, int hinted_in, int window) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= K) return;
   KState s;
@@ -631,8 +659,20 @@ __global__ void k_scd_init(KState *st, int K, const double *lam_in, const uint8_
   s.n_emit = 0;
   s.flags = 0;
   s.center = lam_in[k];
+  // hist: [K] bucket widths and [K] last steps (valid when hinted_in), then
+  // [K] lambda^{t-1} and [K] lambda^{t-2} (NaN while unknown), shifted here
+  // once per iteration
+  const double *delta_hint = (hist && hinted_in) ? hist : nullptr;
   double d = delta_hint ? delta_hint[k] : 0.0;
   const bool hinted = d > 0.0;
+  double prev = -1.0, drift = -1.0;
+  if (hist) {
+    prev = hist[2 * K + k];
+    const double prev2 = hist[3 * K + k];
+    drift = fabs(lam_in[k] - prev2);   // NaN while unknown
+    hist[3 * K + k] = prev;
+    hist[2 * K + k] = lam_in[k];
+  }
   if (!hinted) {
     // no history: 2^-10 of the multiplier (or 2^-30 absolute), a power of two
     const double base = lam_in[k] > 0x1p-20 ? lam_in[k] : 0x1p-20;
@@ -649,17 +689,10 @@ __global__ void k_scd_init(KState *st, int K, const double *lam_in, const uint8_
   s.whi = 0.0;
   s.hw = 0.0;
   s.corr = 0.0;
-  // a window around lambda_k^t sized from the last step, when that step was
-  // small against the multiplier
-  const double h = hinted ? KP_WIN_MULT * delta_hint[K + k] : 0.0;
-  if (window && h > 0.0 && s.mode == KS_EXP && h <= KP_WIN_MAX_REL * s.center) {
-    s.mode = KS_WINDOW;
-    s.hw = h;
-    s.whi = s.center + h;
-    s.wlo = s.center - h > 0.0 ? s.center - h : 0.0;
-    s.klo = dkey(s.wlo);
-    s.khi = dkey(s.whi);
-  }
+  s.eoff = 0;
+  s.ecap = 0;
+  s.pad2 = 0;
+  if (window && hinted && s.mode == KS_EXP) choose_window(s, delta_hint[K + k], prev, drift);
   st[k] = s;
 }
 
@@ -687,11 +720,12 @@ __device__ __forceinline__ void set_refine(KState &s, uint64_t lo, uint64_t hi) 
 }
 
 // After a pass: pick the bin holding the threshold and choose the next step.
-__global__ void k_scd_locate(KState *st, int K, const double *B, const double *R, double *hist_sum,
-                             uint32_t *hist_cnt, uint32_t emit_cap, unsigned int *win) {
+__global__ void k_scd_locate(KState *st, int K, const double *B, const double *R, const int *rinst,
+                             double *hist_sum, uint32_t *hist_cnt, uint32_t emit_cap, unsigned int *win) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= K) return;
   KState s = st[k];
+  if (s.ecap) emit_cap = s.ecap;   // batched: this knapsack's own buffer
   const double Bk = B[k];
   const double *hsum = hist_sum + (size_t)k * KP_NB;
   const uint32_t *hcnt = hist_cnt + (size_t)k * KP_NB;
@@ -760,7 +794,10 @@ __global__ void k_scd_locate(KState *st, int K, const double *B, const double *R
     else set_refine(s, s.klo, s.khi);
   } else if (s.mode == KS_WINDOW) {
     // consumption just above the window, summed over users
-    const double above = R[k] + s.corr;
+    // consumption of knapsack k (batched: R of instance rinst[k] sits after
+    // the R, g, P columns of the instances before it)
+    const double Rk = rinst ? R[k + 2 * rinst[k]] : R[k];
+    const double above = Rk + s.corr;
     if (win) { atomicAdd(&win[0], 1u); atomicAdd(&win[3], s.n_emit); }
     if (s.overflow || above > Bk) {
       if (win) atomicAdd(&win[1], 1u);
@@ -798,9 +835,11 @@ __global__ void __launch_bounds__(SEL_NT) k_scd_select(KState *st, const double 
   if (tid == 0) s = st[k];
   __syncthreads();
   if (s.mode != KS_SELECT_BUCKET && s.mode != KS_SELECT_RANGE) return;
+  const size_t eo = s.ecap ? (size_t)s.eoff : (size_t)k * emit_cap;
+  if (s.ecap) emit_cap = s.ecap;
   const uint32_t n = s.n_emit < emit_cap ? s.n_emit : emit_cap;
-  const double *V1 = emit_v1 + (size_t)k * emit_cap;
-  const double *V2 = emit_v2 + (size_t)k * emit_cap;
+  const double *V1 = emit_v1 + eo;
+  const double *V2 = emit_v2 + eo;
   const bool bucket = s.mode == KS_SELECT_BUCKET;
   const double Bk = B[k];
   if (tid == 0) {
@@ -1449,7 +1488,8 @@ __global__ void __launch_bounds__(256) k_reduce_stats_tab(const ColDesc *tab) {
 }
 
 __global__ void k_scd_init_flat(KState *st, int Kf, const double *const *lam_in, const int *kinst,
-                                const int *klocal) {
+                                const int *klocal, double *hint, int window, const uint64_t *eoff,
+                                const uint32_t *ecap) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= Kf) return;
   const double l = lam_in[kinst[f]][klocal[f]];
@@ -1462,7 +1502,8 @@ __global__ void k_scd_init_flat(KState *st, int Kf, const double *const *lam_in,
   s.flags = 0;
   s.center = l;
   const double base = l > 0x1p-20 ? l : 0x1p-20;
-  s.delta = ldexp(1.0, ilogb(base) - 10);
+  // bucket width: a power of two above the last step when there is one
+  s.delta = (hint && hint[f] > 0.0) ? hint[f] : ldexp(1.0, ilogb(base) - 10);
   s.F_above = 0.0;
   s.result = l;
   s.klo = 0;
@@ -1473,14 +1514,35 @@ __global__ void k_scd_init_flat(KState *st, int Kf, const double *const *lam_in,
   s.whi = 0.0;
   s.hw = 0.0;
   s.corr = 0.0;
+  s.eoff = eoff ? eoff[f] : 0;
+  s.ecap = ecap ? ecap[f] : 0;
+  s.pad2 = 0;
+  // a window from the multiplier's history (as the single-instance search);
+  // the history columns shift once per iteration, here
+  if (hint) {
+    const double prev = hint[2 * Kf + f];
+    const double drift = fabs(l - hint[3 * Kf + f]);
+    hint[3 * Kf + f] = prev;
+    hint[2 * Kf + f] = l;
+    if (window && hint[f] > 0.0) choose_window(s, hint[Kf + f], prev, drift);
+  }
   st[f] = s;
 }
 
 __global__ void k_scd_finish_flat(const KState *st, int Kf, double *const *lam_out, const int *kinst,
-                                  const int *klocal) {
+                                  const int *klocal, double *hint) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= Kf) return;
-  lam_out[kinst[f]][klocal[f]] = st[f].result;
+  const double nl = st[f].result;
+  lam_out[kinst[f]][klocal[f]] = nl;
+  if (hint) {
+    // the next iteration's bucket width: the power of two above this step
+    const double step = fabs(nl - st[f].center);
+    const double floor_ = (nl > 0x1p-20 ? nl : 0x1p-20) * 0x1p-30;
+    const double w = step > floor_ ? step : floor_;
+    hint[f] = ldexp(1.0, ilogb(w) + 1);
+    hint[Kf + f] = w;
+  }
 }
 
 hipError_t kp_launch_sweep_batched(const SweepArgs *descs, const TileGeom *geoms, const int *block_off,
@@ -1496,16 +1558,18 @@ hipError_t kp_launch_sweep_batched(const SweepArgs *descs, const TileGeom *geoms
 }
 
 hipError_t kp_launch_batched_aux(int which, const void *tab, int n, KState *st, const void *lam_ptrs,
-                                 const int *kinst, const int *klocal, hipStream_t stream) {
+                                 const int *kinst, const int *klocal, double *hint, const uint64_t *eoff,
+                                 const uint32_t *ecap, hipStream_t stream) {
   if (n <= 0) return hipSuccess;
   if (which == 0) {
     hipLaunchKernelGGL(k_reduce_stats_tab, dim3(n), dim3(256), 0, stream, (const ColDesc *)tab);
-  } else if (which == 1) {
+  } else if (which == 1 || which == 3) {   // 3: with a window where the last step allows
     hipLaunchKernelGGL(k_scd_init_flat, dim3((n + 63) / 64), dim3(64), 0, stream, st, n,
-                       (const double *const *)lam_ptrs, kinst, klocal);
+                       (const double *const *)lam_ptrs, kinst, klocal, hint,
+                       which == 3 ? 1 : 0, eoff, ecap);
   } else {
     hipLaunchKernelGGL(k_scd_finish_flat, dim3((n + 63) / 64), dim3(64), 0, stream, (const KState *)st,
-                       n, (double *const *)lam_ptrs, kinst, klocal);
+                       n, (double *const *)lam_ptrs, kinst, klocal, hint);
   }
   return hipGetLastError();
 }
@@ -1545,6 +1609,19 @@ size_t kp_sweep_lds_bytes(int U, int M, int K, bool scd, int fmt) {
          r16((size_t)K * KP_NB * 4) + 4 * r16((size_t)K * 4) + 2 * r16((size_t)K * 8) + r16(16) +
          r16((size_t)K * 8 + 8) + r16((size_t)U * 16);   // window corrections, per-user filter
   return s;
+}
+
+// Blocks of the batched sweep kernel that can be resident at once (0 if unknown).
+int kp_sweep_batched_resident(size_t lds) {
+  const void *fn = (const void *)k_sweep_batched;
+  if (lds > 64 * 1024 && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return 0;
+  int per_cu = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, NT, lds) != hipSuccess || per_cu < 1) return 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  return per_cu * cus;
 }
 
 // Blocks of the general sweep kernel that can be resident at once (0 if unknown).
@@ -1606,17 +1683,17 @@ hipError_t kp_launch_reduce_stats(const double *partials, int nblk, int K, const
 }
 
 hipError_t kp_launch_scd_init(KState *st, int K, const double *lam_in, const uint8_t *kmask,
-                              const double *delta_hint, int window, hipStream_t stream) {
+                              double *hist, int hinted, int window, hipStream_t stream) {
   hipLaunchKernelGGL(k_scd_init, dim3((K + 63) / 64), dim3(64), 0, stream, st, K, lam_in, kmask,
-                     delta_hint, window);
+                     hist, hinted, window);
   return hipGetLastError();
 }
 
 hipError_t kp_launch_scd_locate_select(KState *st, int K, const double *B, const double *R,
-                                       double *hist_sum, uint32_t *hist_cnt, const double *ev1,
-                                       const double *ev2, uint32_t emit_cap, int *pending,
-                                       unsigned int *win, hipStream_t stream) {
-  hipLaunchKernelGGL(k_scd_locate, dim3((K + 63) / 64), dim3(64), 0, stream, st, K, B, R, hist_sum,
+                                       const int *rinst, double *hist_sum, uint32_t *hist_cnt,
+                                       const double *ev1, const double *ev2, uint32_t emit_cap,
+                                       int *pending, unsigned int *win, hipStream_t stream) {
+  hipLaunchKernelGGL(k_scd_locate, dim3((K + 63) / 64), dim3(64), 0, stream, st, K, B, R, rinst, hist_sum,
                      hist_cnt, emit_cap, win);
   hipLaunchKernelGGL(k_scd_select, dim3(K), dim3(SEL_NT), 0, stream, st, B, ev1, ev2, emit_cap, win);
   hipLaunchKernelGGL(k_count_pending, dim3(1), dim3(256), 0, stream, st, K, pending);

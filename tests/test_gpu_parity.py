@@ -520,3 +520,61 @@ def test_presolve_rejects_bad_samples():
     for bad in ([0, 0, 1], [-1, 2], [inst.N], []):
         with pytest.raises(kp.KPError):
             kp.kp_presolve(prob, np.asarray(bad, np.int64), lam)
+
+
+@gpu
+def test_batched_plan_window_trajectory():
+    """Batched plans start each iteration's threshold search with a window
+    around the previous multiplier (per knapsack, from its last step): every
+    instance still follows the oracle's SCD trajectory bit for bit, with the
+    window on and off (the pass counts are reported)."""
+    kp, torch = _kp()
+    insts = [kpgen.config_instance(3, N=4000), kpgen.config_instance(3, run=1, N=2500),
+             kpgen.make_instance(3000, 12, 9, seed=45, Q=3, csr_d=1, budget_frac=0.1),
+             kpgen.make_instance(2000, 8, 3, seed=46, Q=2, budget_frac=0.1),
+             kpgen.config_instance(1)]
+    probs = [kp.Problem.from_host(i) for i in insts]
+    passes = {}
+    for window in (True, False):
+        ctx = kp.Context()
+        ctx.set_window(window)
+        ctx.set_timing(True)
+        plan = kp.BatchedSCD(probs, ctx=ctx)
+        lams = [np.zeros(i.K) for i in insts]
+        for t in range(12):
+            outs, _ = plan.step()
+            torch.cuda.synchronize()
+            for s, inst in enumerate(insts):
+                want = oracle.scd_sweep(inst, lams[s])
+                assert np.array_equal(outs[s].cpu().numpy(), want), (window, t, s)
+                lams[s] = want
+        passes[window] = ctx.timing()[1]
+        plan.close()
+    print("passes with / without the window", passes[True], passes[False], flush=True)
+
+
+@gpu
+@pytest.mark.parametrize("name,mk", [
+    ("c2-dense-N3000", lambda: kpgen.config_instance(2, N=3000)),
+    ("c5-inst-dense", lambda: kpgen.batched_instances(run=0, n=40, max_N=6000)[39]),
+], ids=["c2-dense-N3000", "c5-inst-dense"])
+def test_scd_alternating_trajectory(name, mk):
+    """Dense instances whose synchronous iterations alternate between two
+    multiplier vectors: searches that start with a window around the
+    multiplier of two iterations back (and the general kernel's window pass)
+    keep every update equal to the oracle's, window on and off."""
+    kp, torch = _kp()
+    print("case", name, flush=True)
+    inst = mk()
+    prob = kp.Problem.from_host(inst)
+    win = kp.Context()
+    full = kp.Context()
+    full.set_window(False)
+    lam = np.zeros(inst.K)
+    for t in range(10):
+        want = oracle.scd_sweep(inst, lam)
+        for ctx in (win, full):
+            got = kp.kp_scd_sweep(prob, _lamd(torch, lam), ctx=ctx)["lam"].cpu().numpy()
+            assert np.array_equal(got, want), (t, np.flatnonzero(got != want), got, want)
+        lam = want
+    print("window searches", win.window_stats(), flush=True)
