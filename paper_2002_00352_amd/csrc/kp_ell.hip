@@ -7,7 +7,9 @@ size_t kp_ell_lds_bytes(int M, int K, int D, int L, int mode, int *region_out) {
   const bool brk = mode == KM_SCD || mode == KM_WFAIL;
   size_t region = 0;
   if (mode != KM_WFAIL) {
-    region = (size_t)64 * M * 4 + (size_t)64 * M * D * 8;                     // staged tile
+    // staged tile, plus slack for the reads of up to 16 items per lane past
+    // the last lane's row
+    region = (size_t)64 * M * 4 + (size_t)64 * M * D * 8 + (size_t)16 * D * 4;
     region = region > (size_t)8 * 65 * 8 ? region : (size_t)8 * 65 * 8;      // statistics rows
   }
   if (brk) {
@@ -38,6 +40,7 @@ hipError_t kp_launch_ell(const SweepArgs &a, int D, int grid, int mode, hipStrea
   const size_t lds = kp_ell_lds_bytes(g.M, g.K, D, a.tree.L, mode, &g.region);
   g.rows = g.region / (65 * 8);
   if (g.rows > g.K + 2) g.rows = g.K + 2;
+  g.x4 = (((uintptr_t)a.pr.p | (uintptr_t)a.pr.col | (uintptr_t)a.pr.val) & 15) == 0;
   switch (mode) {
     case KM_EVAL: return kp_launch_ell_mode<KM_EVAL>(a, g, lds, grid, D, stream, used);
     case KM_SCD: return kp_launch_ell_mode<KM_SCD>(a, g, lds, grid, D, stream, used);

@@ -43,6 +43,19 @@ __device__ __forceinline__ void stage_dwords(const void *src, int n, void *dst, 
   }
 }
 
+// Copy nbytes (a multiple of 256) from 16-byte aligned global src to LDS dst
+// with 16-byte direct-to-LDS loads: lane i carries bytes [16 i, 16 i + 16) of
+// each 1 KB chunk; in the last, partial chunk the lanes past the end stay idle.
+__device__ __forceinline__ void stage_x4(const void *src, int nbytes, void *dst, int lane) {
+  const unsigned char *s = (const unsigned char *)src + lane * 16;
+  unsigned char *d = (unsigned char *)dst;
+  int c = 0;
+  for (; c + 1024 <= nbytes; c += 1024)
+    __builtin_amdgcn_global_load_lds((const void *)(s + c), (lds_void_t *)(d + c), 16, 0, 0);
+  if (c < nbytes && lane * 16 < nbytes - c)
+    __builtin_amdgcn_global_load_lds((const void *)(s + c), (lds_void_t *)(d + c), 16, 0, 0);
+}
+
 // Per-wave scratch of the breakpoint phase (byte offsets in the wave's region).
 struct EllScratch {
   int pt, bt, kt, msk, end;
@@ -66,6 +79,7 @@ __device__ __forceinline__ bool walk_mode(int m) {
 struct EllGeom {
   int M, K, region;   // region: bytes of per-wave LDS
   int rows;           // statistics rows (of 65 doubles) per chunk
+  int x4;             // p, col and val are 16-byte aligned: full tiles use 16-byte loads
 };
 
 // Breakpoint phase of one user (one lane) from its per-lane LDS scratch:
@@ -418,25 +432,35 @@ k_ell(const SweepArgs a, const EllGeom g) {
       act = lane < nu;
       __builtin_amdgcn_s_waitcnt(0);
       __builtin_amdgcn_wave_barrier();
-      stage_dwords(a.pr.p + u0 * M, nu * M, sp, lane);
-      stage_dwords(a.pr.col + u0 * M * D, nu * M * D, sc, lane);
-      stage_dwords(a.pr.val + u0 * M * D, nu * M * D, sv, lane);
+      if (nu == 64 && g.x4) {
+        stage_x4(a.pr.p + u0 * M, 256 * M, sp, lane);
+        stage_x4(a.pr.col + u0 * M * D, 256 * M * D, sc, lane);
+        stage_x4(a.pr.val + u0 * M * D, 256 * M * D, sv, lane);
+      } else {
+        stage_dwords(a.pr.p + u0 * M, nu * M, sp, lane);
+        stage_dwords(a.pr.col + u0 * M * D, nu * M * D, sc, lane);
+        stage_dwords(a.pr.val + u0 * M * D, nu * M * D, sv, lane);
+      }
       __builtin_amdgcn_s_waitcnt(0);
       __builtin_amdgcn_wave_barrier();
       __asm__ volatile("" ::: "memory");
+      // unconditional reads of EM items (the region has slack past the last
+      // lane's row), then selects: no divergent branches, and neighbouring
+      // dwords merge into wide LDS reads
+      const float *spl = sp + lane * M;
+      const int32_t *scl = sc + lane * M * D;
+      const float *svl = sv + lane * M * D;
       #pragma unroll
       for (int j = 0; j < EM; ++j) {
-        if (j < M) {
-          pv[j] = act ? sp[lane * M + j] : 0.0f;
-          #pragma unroll
-          for (int t = 0; t < D; ++t) {
-            cl[j * D + t] = act ? sc[(lane * M + j) * D + t] : -1;
-            vl[j * D + t] = act ? sv[(lane * M + j) * D + t] : 0.0f;
-          }
-        } else {
-          pv[j] = 0.0f;
-          #pragma unroll
-          for (int t = 0; t < D; ++t) { cl[j * D + t] = -1; vl[j * D + t] = 0.0f; }
+        const bool in = act && j < M;
+        const float p0 = spl[j];
+        pv[j] = in ? p0 : 0.0f;
+        #pragma unroll
+        for (int t = 0; t < D; ++t) {
+          const int32_t c0 = scl[j * D + t];
+          const float v0 = svl[j * D + t];
+          cl[j * D + t] = in ? c0 : -1;
+          vl[j * D + t] = in ? v0 : 0.0f;
         }
       }
       __builtin_amdgcn_s_waitcnt(0);
