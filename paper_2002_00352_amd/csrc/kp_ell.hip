@@ -17,7 +17,7 @@ size_t kp_ell_lds_bytes(int M, int K, int D, int L, int mode, int *region_out) {
     region = region > need ? region : need;
   }
   region = r16(region);
-  size_t s = r16((size_t)K * 8) + r16((size_t)L * 8 + 8) + r16((size_t)L * 4 + 4) +
+  size_t s = r16((size_t)(K + 1) * 8) + r16((size_t)L * 8 + 8) + r16((size_t)L * 4 + 4) +
              r16((size_t)EW * (K + 2) * 8);
   if (mode != KM_EVAL) s += r16((size_t)K * 4) + r16((size_t)K * 8 + 16);
   if (mode == KM_WMAIN) s += r16((size_t)K * 8);

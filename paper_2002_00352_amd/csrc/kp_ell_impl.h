@@ -337,7 +337,7 @@ k_ell(const SweepArgs a, const EllGeom g) {
   const int M = g.M, K = g.K;
   size_t off = 0;
   auto carve = [&](size_t bytes) { unsigned char *p = smem + off; off += (bytes + 15) & ~(size_t)15; return p; };
-  double *lam = (double *)carve((size_t)K * 8);
+  double *lam = (double *)carve((size_t)(K + 1) * 8);   // [K] = 0 for the clamped reads
   uint64_t *tmask = (uint64_t *)carve((size_t)a.tree.L * 8 + 8);
   int *tcap = (int *)carve((size_t)a.tree.L * 4 + 4);
   double *wacc = (double *)carve((size_t)EW * (K + 2) * 8);
@@ -366,7 +366,7 @@ k_ell(const SweepArgs a, const EllGeom g) {
     nstage = (uint32_t *)carve(16);
   }
   unsigned char *wreg = smem + off + (size_t)wv * g.region;   // this wave's region
-  for (int t = tid; t < K; t += ENT) lam[t] = a.lam[t];
+  for (int t = tid; t <= K; t += ENT) lam[t] = t < K ? a.lam[t] : 0.0;
   for (int t = tid; t < a.tree.L; t += ENT) { tmask[t] = a.tree.mask[t]; tcap[t] = a.tree.cap[t]; }
   for (int t = tid; t < EW * (K + 2); t += ENT) wacc[t] = 0.0;
   if (MODE != KM_EVAL) {
@@ -495,11 +495,13 @@ k_ell(const SweepArgs a, const EllGeom g) {
       double acc = (double)pv[j];
       #pragma unroll
       for (int t = 0; t < D; ++t) {
-        const int k = cl[j * D + t];
-        if ((unsigned)k < (unsigned)K) {
-          const double prod = lam[k] * (double)vl[j * D + t];
-          acc = acc - prod;
-        }
+        // every lane reads: entries outside [0, K) (and the padding) read
+        // the zero slot lam[K], and subtracting 0 * v (v finite) leaves acc
+        // unchanged bit for bit, so no branch or select is needed
+        const unsigned k = (unsigned)cl[j * D + t];
+        const unsigned kc = k < (unsigned)K ? k : (unsigned)K;
+        const double prod = lam[kc] * (double)vl[j * D + t];
+        acc = acc - prod;
       }
       pt[j] = acc;
     }
@@ -512,7 +514,9 @@ k_ell(const SweepArgs a, const EllGeom g) {
       #pragma unroll
       for (int jj = j + 1; jj < EM; ++jj) {
         if (jj < M) {
-          if (pt[jj] > pt[j]) rk[j]++; else rk[jj]++;
+          const int c = pt[jj] > pt[j] ? 1 : 0;
+          rk[j] += c;
+          rk[jj] += 1 - c;
         }
       }
     }
@@ -525,22 +529,36 @@ k_ell(const SweepArgs a, const EllGeom g) {
       }
     }
     if (!act) pos = 0;
-    // ---- greedy over the ranked items (M <= 16: 32-bit masks) ----
+    // ---- Alg.1's cap pass, in rank space (M <= 16: 32-bit masks) ----
+    // Bit r of `alive` stands for the item of rank r; starting from the
+    // items with p~ > 0, every laminar set (subsets first) keeps its cap
+    // best live members.  The sets are uniform: their masks and caps come
+    // from the kernel arguments into scalar registers.
     uint64_t S = 0;
+    uint32_t rbit[EM];   // 1 << rank (the rank itself is its lowest set bit)
     {
-      const uint32_t pos32 = (uint32_t)pos;
-      uint32_t S32 = 0, blocked = 0;
-      for (int r = 0; r < M; ++r) {
-        const int j = (int)((perm >> (4 * r)) & 15);
-        const uint32_t bit = 1u << j;
-        if ((pos32 & bit) && !(blocked & bit)) {
-          S32 |= bit;
-          for (int l = 0; l < L; ++l) {
-            const uint32_t m = (uint32_t)tmask[l];
-            if ((m & bit) && __popc(S32 & m) >= tcap[l]) blocked |= m;
-          }
-        }
+      uint32_t alive = 0;
+      #pragma unroll
+      for (int j = 0; j < EM; ++j) {
+        rbit[j] = j < M ? 1u << rk[j] : 0u;
+        if (pt[j] > 0.0) alive |= rbit[j];
       }
+      if (!act) alive = 0;
+      for (int l = 0; l < L; ++l) {
+        const uint32_t m = (uint32_t)a.tree.mask[l];
+        const int cap = a.tree.cap[l];
+        uint32_t mr = 0;
+        #pragma unroll
+        for (int j = 0; j < EM; ++j)
+          if (m >> j & 1u) mr |= rbit[j];
+        uint32_t x = alive & mr;
+        for (int c = 0; c < cap; ++c) x &= x - 1u;   // drop the cap best: x = the rest
+        alive &= ~x;
+      }
+      uint32_t S32 = 0;
+      #pragma unroll
+      for (int j = 0; j < EM; ++j)
+        if (alive & rbit[j]) S32 |= 1u << j;
       S = S32;
     }
     double bmax = 0.0;
@@ -569,7 +587,8 @@ k_ell(const SweepArgs a, const EllGeom g) {
       double amax = 0.0;
       #pragma unroll
       for (int j = 0; j < EM * D; ++j) {
-        const int k = cl[j];
+        int k = cl[j];
+        __asm__("" : "+v"(k));   // a fresh test, not the scoring's (its lane masks would stay live)
         if ((unsigned)k < (unsigned)K) amax = wA[k] > amax ? wA[k] : amax;
       }
       const double H = hwin[K] * bmax * (1.0 + 0x1p-30) + 0x1p-36 * (1.0 + bmax * hwin[K]);
@@ -579,7 +598,7 @@ k_ell(const SweepArgs a, const EllGeom g) {
       double *srt = (double *)wreg;
       #pragma unroll
       for (int j = 0; j < EM; ++j)
-        if (j < M) srt[rk[j] * 64 + lane] = pt[j];
+        if (j < M) srt[__builtin_ctz(rbit[j]) * 64 + lane] = pt[j];
       __builtin_amdgcn_s_waitcnt(0);
       __builtin_amdgcn_wave_barrier();
       __asm__ volatile("" ::: "memory");
@@ -621,8 +640,12 @@ k_ell(const SweepArgs a, const EllGeom g) {
               #pragma unroll
               for (int t = 0; t < D; ++t) {
                 const int q = cl[j * D + t] - c0;
+                // widened again here (an opaque copy): keeping the scoring's
+                // widened costs alive until now would cost 2 registers each
+                float v = vl[j * D + t];
+                __asm__("" : "+v"(v));
                 if ((unsigned)q < (unsigned)nq && q < K - c0)
-                  rows[q * 65 + lane] = rows[q * 65 + lane] + (double)vl[j * D + t];
+                  rows[q * 65 + lane] = rows[q * 65 + lane] + (double)v;
               }
             }
           }
