@@ -327,14 +327,16 @@ enum { KM_EVAL = 0, KM_SCD = 1, KM_WMAIN = 2, KM_WFAIL = 3 };
 // allows (without the hint it compiles just above the register limit).
 template <int MODE> struct EllWaves { static constexpr int value = MODE == 2 ? 3 : 1; };
 
-template <int D, int MODE, int EM>
+// EM: the item-count class (8, 10, 12, 16); EXACT: M equals EM, so every
+// test of an item index against M folds away.
+template <int D, int MODE, int EM, bool EXACT>
 __global__ void __launch_bounds__(ENT) __attribute__((amdgpu_waves_per_eu(EllWaves<MODE>::value, 8)))
 k_ell(const SweepArgs a, const EllGeom g) {
   constexpr bool BREAK = (MODE == KM_SCD || MODE == KM_WFAIL);   // breakpoint phase
   constexpr bool STAGED = (MODE != KM_WFAIL);                    // contiguous tiles
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int M = g.M, K = g.K;
+  const int M = EXACT ? EM : g.M, K = g.K;
   size_t off = 0;
   auto carve = [&](size_t bytes) { unsigned char *p = smem + off; off += (bytes + 15) & ~(size_t)15; return p; };
   double *lam = (double *)carve((size_t)(K + 1) * 8);   // [K] = 0 for the clamped reads
@@ -353,7 +355,9 @@ k_ell(const SweepArgs a, const EllGeom g) {
     hwin = (double *)carve((size_t)K * 8 + 16);  // [K] window half-widths (0: no window), [K] their max,
                                                  // [K+1] the largest multiplier with a window
   }
-  double *wA = MODE == KM_WMAIN ? (double *)carve((size_t)K * 8) : nullptr;
+  // window main pass: (lambda_k, wA_k) pairs read together by the scoring,
+  // [K] = (0, 0) for the clamped reads
+  double2 *lw = MODE == KM_WMAIN ? (double2 *)carve((size_t)(K + 1) * 16) : nullptr;
   if (BREAK) {
     kcorr = (double *)carve((size_t)K * 8);
     hs = (double *)carve((size_t)K * KP_NB * 8);
@@ -367,6 +371,7 @@ k_ell(const SweepArgs a, const EllGeom g) {
   }
   unsigned char *wreg = smem + off + (size_t)wv * g.region;   // this wave's region
   for (int t = tid; t <= K; t += ENT) lam[t] = t < K ? a.lam[t] : 0.0;
+  if (MODE == KM_WMAIN && tid == 0) lw[K] = make_double2(0.0, 0.0);
   for (int t = tid; t < a.tree.L; t += ENT) { tmask[t] = a.tree.mask[t]; tcap[t] = a.tree.cap[t]; }
   for (int t = tid; t < EW * (K + 2); t += ENT) wacc[t] = 0.0;
   if (MODE != KM_EVAL) {
@@ -375,7 +380,7 @@ k_ell(const SweepArgs a, const EllGeom g) {
       hwin[t] = a.st[t].mode == KS_WINDOW ? a.st[t].hw : 0.0;
       if (MODE == KM_WMAIN) {
         const double h = hwin[t];
-        wA[t] = h > 0.0 ? h * (1.0 + 0x1p-30) + 0x1p-36 * (a.lam[t] + h) : 0.0;
+        lw[t] = make_double2(a.lam[t], h > 0.0 ? h * (1.0 + 0x1p-30) + 0x1p-36 * (a.lam[t] + h) : 0.0);
       }
     }
   }
@@ -490,6 +495,7 @@ k_ell(const SweepArgs a, const EllGeom g) {
     }
     // ---- cost-adjusted profits ----
     double pt[EM];
+    double amax = 0.0;   // window main pass: the largest wA over the user's knapsacks
     #pragma unroll
     for (int j = 0; j < EM; ++j) {
       double acc = (double)pv[j];
@@ -500,7 +506,16 @@ k_ell(const SweepArgs a, const EllGeom g) {
         // unchanged bit for bit, so no branch or select is needed
         const unsigned k = (unsigned)cl[j * D + t];
         const unsigned kc = k < (unsigned)K ? k : (unsigned)K;
-        const double prod = lam[kc] * (double)vl[j * D + t];
+        double lk;
+        if (MODE == KM_WMAIN) {
+          const double2 e = lw[kc];
+          lk = e.x;
+          amax = fmax(amax, e.y);
+          __asm__ volatile("" : "+v"(amax));   // fold now: e.y dies here
+        } else {
+          lk = lam[kc];
+        }
+        const double prod = lk * (double)vl[j * D + t];
         acc = acc - prod;
       }
       pt[j] = acc;
@@ -508,7 +523,7 @@ k_ell(const SweepArgs a, const EllGeom g) {
     // ---- ranks by (p~ desc, index asc), packed permutation ----
     int rk[EM];
     #pragma unroll
-    for (int j = 0; j < EM; ++j) rk[j] = 0;
+    for (int j = 0; j < EM; ++j) rk[j] = j;   // rank = j + (later items ahead) - (earlier items behind)
     #pragma unroll
     for (int j = 0; j < EM; ++j) {
       #pragma unroll
@@ -516,7 +531,7 @@ k_ell(const SweepArgs a, const EllGeom g) {
         if (jj < M) {
           const int c = pt[jj] > pt[j] ? 1 : 0;
           rk[j] += c;
-          rk[jj] += 1 - c;
+          rk[jj] -= c;
         }
       }
     }
@@ -584,13 +599,6 @@ k_ell(const SweepArgs a, const EllGeom g) {
       // window.  Lines below -H never can.  The bound of knapsack k is
       // bmax * wA[k] + 2^-36 (1 + gscale), wA[k] = h_k (1 + 2^-30) +
       // 2^-36 (lambda_k + h_k) (0 without a window).
-      double amax = 0.0;
-      #pragma unroll
-      for (int j = 0; j < EM * D; ++j) {
-        int k = cl[j];
-        __asm__("" : "+v"(k));   // a fresh test, not the scoring's (its lane masks would stay live)
-        if ((unsigned)k < (unsigned)K) amax = wA[k] > amax ? wA[k] : amax;
-      }
       const double H = hwin[K] * bmax * (1.0 + 0x1p-30) + 0x1p-36 * (1.0 + bmax * hwin[K]);
       // p~ by rank into the dead staging area, then the gaps between
       // neighbours in rank order (the smallest pairwise distance is between
@@ -624,9 +632,12 @@ k_ell(const SweepArgs a, const EllGeom g) {
       }
       if (a.want_stats) {
         // per-lane rows [K + 2][65] (consumption per knapsack, G_i, P_i) over
-        // the dead staging area, g.rows of them at a time; lane q then sums
-        // row q over the users in lane order (fixed order; the odd row stride
-        // keeps the lanes on distinct banks)
+        // the dead staging area, g.rows of them at a time.  Each lane adds its
+        // selected costs into its own column with LDS atomic adds (one lane
+        // per address, so the adds happen in program order and the sums are
+        // the plain sequential ones); then lpr lanes per row sum contiguous
+        // parts of it and combine them in a fixed butterfly (fixed order; the
+        // odd row stride keeps the lanes on distinct banks)
         double *rows = rowbuf;
         const int KT = K + 2;
         for (int c0 = 0; c0 < KT; c0 += g.rows) {
@@ -636,28 +647,34 @@ k_ell(const SweepArgs a, const EllGeom g) {
           if ((unsigned)(K + 1 - c0) < (unsigned)nq) rows[(K + 1 - c0) * 65 + lane] = Pi;
           #pragma unroll
           for (int j = 0; j < EM; ++j) {
-            if (S >> j & 1) {
-              #pragma unroll
-              for (int t = 0; t < D; ++t) {
-                const int q = cl[j * D + t] - c0;
-                // widened again here (an opaque copy): keeping the scoring's
-                // widened costs alive until now would cost 2 registers each
-                float v = vl[j * D + t];
-                __asm__("" : "+v"(v));
-                if ((unsigned)q < (unsigned)nq && q < K - c0)
-                  rows[q * 65 + lane] = rows[q * 65 + lane] + (double)v;
-              }
+            #pragma unroll
+            for (int t = 0; t < D; ++t) {
+              const int q = cl[j * D + t] - c0;
+              // widened again here (an opaque copy): keeping the scoring's
+              // widened costs alive until now would cost 2 registers each
+              float v = vl[j * D + t];
+              __asm__("" : "+v"(v));
+              // unselected or foreign entries add +0 to row 0 (a consumption
+              // row, never -0): no branch
+              const bool ok = (S >> j & 1) && (unsigned)q < (unsigned)nq && q < K - c0;
+              __hip_atomic_fetch_add(&rows[(ok ? q : 0) * 65 + lane], ok ? (double)v : 0.0,
+                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
             }
           }
           __builtin_amdgcn_s_waitcnt(0);
           __builtin_amdgcn_wave_barrier();
           __asm__ volatile("" ::: "memory");
-          if (lane < nq) {
-            double sum = 0.0;
-            const double *row = rows + lane * 65;
-            for (int u = 0; u < 64; ++u) sum = sum + row[u];
-            wacc[wv * KT + c0 + lane] = wacc[wv * KT + c0 + lane] + sum;
+          int lg = 0;
+          while ((2 << lg) * nq <= 64) ++lg;
+          const int q = lane >> lg, len = 64 >> lg;
+          double sum = 0.0;
+          if (q < nq) {
+            const double *row = rows + q * 65 + (lane & ((1 << lg) - 1)) * len;
+            for (int u = 0; u < len; ++u) sum = sum + row[u];
           }
+          for (int o = 1; o < (1 << lg); o <<= 1) sum = sum + __shfl_xor(sum, o, 64);
+          if (q < nq && (lane & ((1 << lg) - 1)) == 0)
+            wacc[wv * KT + c0 + q] = wacc[wv * KT + c0 + q] + sum;
           __builtin_amdgcn_s_waitcnt(0);
           __builtin_amdgcn_wave_barrier();
           __asm__ volatile("" ::: "memory");
@@ -737,10 +754,10 @@ size_t kp_ell_lds_bytes(int M, int K, int D, int L, int mode, int *region_out);
 // Persistent launch: never more blocks than can be resident at once (the
 // tile loop strides over the rest), so no block waits for another to finish
 // and every CU stays busy to the end.  grid <= 0 asks for exactly that many.
-template <int D, int MODE, int EM>
+template <int D, int MODE, int EM, bool EXACT>
 static hipError_t launch_ell_t(const SweepArgs &a, const EllGeom &g, size_t lds, int grid,
                                hipStream_t stream, int *used) {
-  const void *fn = (const void *)k_ell<D, MODE, EM>;
+  const void *fn = (const void *)k_ell<D, MODE, EM, EXACT>;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -758,22 +775,29 @@ static hipError_t launch_ell_t(const SweepArgs &a, const EllGeom &g, size_t lds,
   const int resident = cus * per_cu;
   if (grid <= 0 || grid > resident) grid = resident;
   if (used) *used = grid;
-  hipLaunchKernelGGL((k_ell<D, MODE, EM>), dim3(grid), dim3(ENT), lds, stream, a, g);
+  hipLaunchKernelGGL((k_ell<D, MODE, EM, EXACT>), dim3(grid), dim3(ENT), lds, stream, a, g);
   return hipGetLastError();
 }
 
 template <int D, int MODE>
 static hipError_t launch_ell_m(const SweepArgs &a, const EllGeom &g, size_t lds, int grid,
                                hipStream_t stream, int *used) {
-  if (g.M <= 8) return launch_ell_t<D, MODE, 8>(a, g, lds, grid, stream, used);
-  if (g.M <= 10) return launch_ell_t<D, MODE, 10>(a, g, lds, grid, stream, used);
-  if (g.M <= 12) return launch_ell_t<D, MODE, 12>(a, g, lds, grid, stream, used);
-  return launch_ell_t<D, MODE, 16>(a, g, lds, grid, stream, used);
+  switch (g.M) {
+    case 8: return launch_ell_t<D, MODE, 8, true>(a, g, lds, grid, stream, used);
+    case 10: return launch_ell_t<D, MODE, 10, true>(a, g, lds, grid, stream, used);
+    case 12: return launch_ell_t<D, MODE, 12, true>(a, g, lds, grid, stream, used);
+    case 16: return launch_ell_t<D, MODE, 16, true>(a, g, lds, grid, stream, used);
+    default: break;
+  }
+  if (g.M <= 8) return launch_ell_t<D, MODE, 8, false>(a, g, lds, grid, stream, used);
+  if (g.M <= 10) return launch_ell_t<D, MODE, 10, false>(a, g, lds, grid, stream, used);
+  if (g.M <= 12) return launch_ell_t<D, MODE, 12, false>(a, g, lds, grid, stream, used);
+  return launch_ell_t<D, MODE, 16, false>(a, g, lds, grid, stream, used);
 }
 
-template <int D, int MODE, int EM>
+template <int D, int MODE, int EM, bool EXACT>
 static int resident_blocks_t(size_t lds) {
-  const void *fn = (const void *)k_ell<D, MODE, EM>;
+  const void *fn = (const void *)k_ell<D, MODE, EM, EXACT>;
   if (lds > 64 * 1024 &&
       hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return 0;
@@ -787,10 +811,17 @@ static int resident_blocks_t(size_t lds) {
 
 template <int D, int MODE>
 static int resident_blocks_m(int M, size_t lds) {
-  if (M <= 8) return resident_blocks_t<D, MODE, 8>(lds);
-  if (M <= 10) return resident_blocks_t<D, MODE, 10>(lds);
-  if (M <= 12) return resident_blocks_t<D, MODE, 12>(lds);
-  return resident_blocks_t<D, MODE, 16>(lds);
+  switch (M) {
+    case 8: return resident_blocks_t<D, MODE, 8, true>(lds);
+    case 10: return resident_blocks_t<D, MODE, 10, true>(lds);
+    case 12: return resident_blocks_t<D, MODE, 12, true>(lds);
+    case 16: return resident_blocks_t<D, MODE, 16, true>(lds);
+    default: break;
+  }
+  if (M <= 8) return resident_blocks_t<D, MODE, 8, false>(lds);
+  if (M <= 10) return resident_blocks_t<D, MODE, 10, false>(lds);
+  if (M <= 12) return resident_blocks_t<D, MODE, 12, false>(lds);
+  return resident_blocks_t<D, MODE, 16, false>(lds);
 }
 
 // one translation unit per mode instantiates these (kp_ell_m<mode>.hip)
