@@ -37,6 +37,7 @@ hipError_t kp_launch_ell(const SweepArgs &a, int D, int grid, int mode, hipStrea
   g.M = a.pr.M;
   g.K = a.pr.K;
   if (g.M < 1 || g.M > 16 || (D != 1 && D != 2) || mode < 0 || mode > 3) return hipErrorInvalidValue;
+  if (a.ntiles > 0x7fffffffLL) return hipErrorInvalidValue;  // the kernel's tile indices are 32-bit
   const size_t lds = kp_ell_lds_bytes(g.M, g.K, D, a.tree.L, mode, &g.region);
   g.rows = g.region / (65 * 8);
   if (g.rows > g.K + 2) g.rows = g.K + 2;

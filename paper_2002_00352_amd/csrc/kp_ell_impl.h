@@ -425,8 +425,9 @@ k_ell(const SweepArgs a, const EllGeom g) {
   double *rowbuf = (double *)wreg;
 
   uint32_t ch_pos = 0, ch_end = 0;   // the wave's reserved list chunk (window main pass)
-  for (int64_t tile = (int64_t)blockIdx.x * EW + wv; tile < ntiles; tile += W) {
-    const int64_t u0 = tile * 64;
+  // tile indices fit 32 bits (the launcher rejects more than 2^31 - 1 tiles)
+  for (int tile = (int)blockIdx.x * EW + wv; tile < (int)ntiles; tile += (int)W) {
+    const int64_t u0 = (int64_t)tile * 64;
     float pv[EM];
     int cl[EM * D];
     float vl[EM * D];
@@ -450,22 +451,46 @@ k_ell(const SweepArgs a, const EllGeom g) {
       __builtin_amdgcn_wave_barrier();
       __asm__ volatile("" ::: "memory");
       // unconditional reads of EM items (the region has slack past the last
-      // lane's row), then selects: no divergent branches, and neighbouring
-      // dwords merge into wide LDS reads
+      // lane's row), no selects: the padding items (j >= M) are cleared, and
+      // lanes past the end of the last tile keep whatever the staging area
+      // holds (they select nothing, emit nothing and are never listed).
+      // With M known and the rows 16-byte aligned (M * D a multiple of 4),
+      // costs are read 16 bytes at a time, which keeps the lanes (80 bytes
+      // apart for M = 10, D = 2) on distinct LDS banks.
       const float *spl = sp + lane * M;
       const int32_t *scl = sc + lane * M * D;
       const float *svl = sv + lane * M * D;
-      #pragma unroll
-      for (int j = 0; j < EM; ++j) {
-        const bool in = act && j < M;
-        const float p0 = spl[j];
-        pv[j] = in ? p0 : 0.0f;
+      if (EXACT && (EM * D) % 4 == 0) {
         #pragma unroll
-        for (int t = 0; t < D; ++t) {
-          const int32_t c0 = scl[j * D + t];
-          const float v0 = svl[j * D + t];
-          cl[j * D + t] = in ? c0 : -1;
-          vl[j * D + t] = in ? v0 : 0.0f;
+        for (int q = 0; q < EM * D / 4; ++q) {
+          const int4 c4 = ((const int4 *)scl)[q];
+          const float4 v4 = ((const float4 *)svl)[q];
+          cl[4 * q] = c4.x; cl[4 * q + 1] = c4.y; cl[4 * q + 2] = c4.z; cl[4 * q + 3] = c4.w;
+          vl[4 * q] = v4.x; vl[4 * q + 1] = v4.y; vl[4 * q + 2] = v4.z; vl[4 * q + 3] = v4.w;
+        }
+      } else {
+        #pragma unroll
+        for (int j = 0; j < EM; ++j) {
+          #pragma unroll
+          for (int t = 0; t < D; ++t) {
+            const int32_t c0 = scl[j * D + t];
+            const float v0 = svl[j * D + t];
+            cl[j * D + t] = j < M ? c0 : -1;
+            vl[j * D + t] = j < M ? v0 : 0.0f;
+          }
+        }
+      }
+      if (EXACT && EM % 2 == 0) {
+        #pragma unroll
+        for (int q = 0; q < EM / 2; ++q) {
+          const float2 p2 = ((const float2 *)spl)[q];
+          pv[2 * q] = p2.x; pv[2 * q + 1] = p2.y;
+        }
+      } else {
+        #pragma unroll
+        for (int j = 0; j < EM; ++j) {
+          const float p0 = spl[j];
+          pv[j] = j < M ? p0 : 0.0f;
         }
       }
       __builtin_amdgcn_s_waitcnt(0);
@@ -581,7 +606,7 @@ k_ell(const SweepArgs a, const EllGeom g) {
       // largest stored cost (exact in fp32; widened once)
       float bm = 0.0f;
       #pragma unroll
-      for (int j = 0; j < EM * D; ++j) bm = vl[j] > bm ? vl[j] : bm;
+      for (int j = 0; j < EM * D; ++j) bm = fmaxf(bm, vl[j]);
       bmax = (double)bm;
     }
     // ---- statistics: profit, group dual value, consumption ----
