@@ -323,6 +323,7 @@ def main():
     torch.cuda.synchronize()
     ctx.set_timing(True)
     win0 = ctx.window_stats()
+    listed0 = ctx.window_listed()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -333,6 +334,7 @@ def main():
     ms_k, launches, bytes_k = ctx.timing()
     ctx.set_timing(False)
     win = [b - a for a, b in zip(win0, ctx.window_stats())]
+    listed = ctx.window_listed() - listed0
     dt = t1 - t0
     N = meta["N"]
     value = N * args.steps / dt
@@ -365,7 +367,8 @@ def main():
         "passes_per_step": launches / args.steps,
         "threshold_search": {"window_tried": win[0], "window_missed_above": win[1],
                              "window_missed_below": win[2], "window_events": win[3],
-                             "knapsack_searches": K * args.steps},
+                             "knapsack_searches": K * args.steps,
+                             "users_listed_per_sweep": listed / args.steps},
         "pct_hbm_peak": 100.0 * achieved / HBM_PEAK_GBS,
         "lambda_final_head": [float(v) for v in lam[:4].cpu().numpy()],
         "gen_s": t_gen,

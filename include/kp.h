@@ -238,6 +238,11 @@ kp_status kp_set_window(void *ctx, int32_t on);
    windows.  HOST outputs, each may be NULL. */
 kp_status kp_get_window_stats(void *ctx, int64_t *tried, int64_t *above, int64_t *below,
                               int64_t *emitted);
+/* Users that the uniform-row kernel's window passes on this context listed
+   for exact checks (their lines may cross inside a window; the others were
+   proven calm by the gap filter), summed over sweeps.  HOST output, may be
+   NULL.  Diagnostic: the results do not depend on it. */
+kp_status kp_get_window_listed(void *ctx, int64_t *listed);
 
 /* Size limits of this build. */
 int32_t kp_max_items(void);        /* 64 */

@@ -76,7 +76,7 @@ EXPORTS = ["kp_last_error", "kp_create", "kp_destroy", "kp_set_stream", "kp_eval
            "kp_max_items", "kp_max_knapsacks_scd", "kp_set_timing", "kp_get_timing",
            "kp_batched_create", "kp_batched_step", "kp_batched_destroy", "kp_set_tuning",
            "kp_set_kernel_choice", "kp_forget_structure", "kp_set_window",
-           "kp_get_window_stats", "kp_presolve"]
+           "kp_get_window_stats", "kp_presolve", "kp_get_window_listed"]
 
 
 def lib():
@@ -111,6 +111,7 @@ def lib():
         L.kp_presolve.argtypes = [vp, P, vp, i64, i32, vp, ctypes.POINTER(i32)]
         L.kp_get_window_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64),
                                           ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        L.kp_get_window_listed.argtypes = [vp, ctypes.POINTER(i64)]
         L.kp_set_timing.argtypes = [vp, i32]
         L.kp_get_timing.argtypes = [vp, vp, vp, vp]
         L.kp_max_items.restype = i32
@@ -175,6 +176,13 @@ class Context:
         _check(lib().kp_get_window_stats(self.h, ctypes.byref(t), ctypes.byref(a), ctypes.byref(b),
                                          ctypes.byref(e)))
         return t.value, a.value, b.value, e.value
+
+    def window_listed(self) -> int:
+        """Users listed for exact checks by the uniform-row kernel's window
+        passes since creation."""
+        n = ctypes.c_int64()
+        _check(lib().kp_get_window_listed(self.h, ctypes.byref(n)))
+        return n.value
 
     def close(self):
         if self.h:

@@ -129,6 +129,7 @@ struct Ctx {
   std::map<std::tuple<int, int, int, int>, std::pair<int, int>> ell_grids;  // (D, M, K, L) -> resident grids
   int64_t win_tried = 0, win_above = 0, win_below = 0;   // window searches since creation
   int64_t win_emitted = 0;                                 // breakpoints emitted inside windows
+  int64_t win_listed = 0;                                  // users listed by split window passes
 };
 
 hipEvent_t take_event(Ctx *c) {
@@ -525,7 +526,7 @@ hipError_t timed_sweep(Ctx *c, const SweepArgs &a, const Prepared &P, bool scd, 
   if (P.ell_D && split) {
     SweepArgs ae = a;
     ae.ntiles = P.ell_ntiles;
-    err = hipMemsetAsync(ae.fcount, 0, 4, c->stream);
+    err = hipMemsetAsync(ae.fcount, 0, 8, c->stream);   // [0] reserved slots, [1] listed users
     if (err == hipSuccess) err = kp_launch_ell(ae, P.ell_D, P.ell_grid, 2, c->stream, &c->stats_grid);
     if (err == hipSuccess) {
       SweepArgs af = ae;
@@ -754,6 +755,8 @@ kp_status kp_scd_sweep_masked(void *ctx, const kp_problem *prob, const double *l
     HIP_TRY(hipMemcpyAsync(c->pinned + 2, w.err, 8, hipMemcpyDeviceToHost, c->stream));
     if (pass == 0 && window)
       HIP_TRY(hipMemcpyAsync(c->pinned + 16, w.win, 16, hipMemcpyDeviceToHost, c->stream));
+    if (pass == 0 && split)
+      HIP_TRY(hipMemcpyAsync(c->pinned + 22, w.fcount + 1, 4, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     if (pass == 0 && window) {
       c->win_tried += (unsigned)c->pinned[16];
@@ -761,6 +764,7 @@ kp_status kp_scd_sweep_masked(void *ctx, const kp_problem *prob, const double *l
       c->win_below += (unsigned)c->pinned[18];
       c->win_emitted += (unsigned)c->pinned[19];
     }
+    if (pass == 0 && split) c->win_listed += (unsigned)c->pinned[22];
     if (*(unsigned long long *)(c->pinned + 2))
       return fail(KP_ERR_INTERNAL, "breakpoint walk exceeded its event limit");
     if (c->pinned[0] == 0) break;
@@ -992,6 +996,12 @@ kp_status kp_get_window_stats(void *ctx, int64_t *tried, int64_t *above, int64_t
   if (above) *above = c->win_above;
   if (below) *below = c->win_below;
   if (emitted) *emitted = c->win_emitted;
+  return KP_OK;
+}
+
+kp_status kp_get_window_listed(void *ctx, int64_t *listed) {
+  if (!ctx) return fail(KP_ERR_INVALID, "ctx is NULL");
+  if (listed) *listed = ((const Ctx *)ctx)->win_listed;
   return KP_OK;
 }
 

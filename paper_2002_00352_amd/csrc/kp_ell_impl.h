@@ -102,33 +102,45 @@ __device__ __forceinline__ void scd_user(const SweepArgs &a, int M, int K, int L
     const int t = ktl[(j * D) * 64 + lane] == k ? 0 : 1;
     return (double)btl[(j * D + t) * 64 + lane];
   };
-  // Window filter: no crossing of two of the user's lines (or of a line and
-  // zero) lies within h of lambda_k^t when every line that can turn positive
-  // there is farther than h * bmax (plus a rounding margin) from zero and from
-  // every other line: lines move against each other by at most
-  // |b_a - b_b| <= bmax per unit of lambda_k.  Lines below -H stay negative
-  // over every window and never matter.
-  double gmin = 1e300, gscale = 0.0;
+  // Window filter per (user, knapsack): over knapsack k's window (within h of
+  // lambda_k^t) item a's line moves by at most h b_ak against the fixed lines
+  // of the items that do not move with k, and by at most h max(b_ak, b_bk)
+  // against another moving item b.  So no crossing with another line (or
+  // with zero) lies in the window when every moving item's distance to its
+  // nearest neighbour in rank order (and to zero) exceeds h b_ak plus a
+  // rounding margin.  Lines below -H (H: the widest window times the
+  // largest cost) never turn positive in any window and never matter.
+  double H = 0.0, gscale = 0.0;
+  uint64_t rinv = 0;   // rank of every item, 4 bits each
   if (hwin[K] > 0.0) {
-    const double H = hwin[K] * bmax * (1.0 + 0x1p-30) + 0x1p-36 * (1.0 + bmax * hwin[K]);
-    double prev = 0.0;
-    for (int r = 0; r < M; ++r) {
-      const int j = (int)((perm >> (4 * r)) & 15);
-      const double v = ptl[j * 64 + lane];
-      if (r == 0) gscale = fabs(v);
-      if (!(v > -H)) break;
-      const double av = fabs(v);
-      gmin = av < gmin ? av : gmin;
-      if (r > 0) { const double d = prev - v; gmin = d < gmin ? d : gmin; }
-      prev = v;
-    }
-    gscale = gscale + H;
+    H = hwin[K] * bmax * (1.0 + 0x1p-30) + 0x1p-36 * (1.0 + bmax * hwin[K]);
+    for (int r = 0; r < M; ++r) rinv |= (uint64_t)r << (4 * ((perm >> (4 * r)) & 15));
+    gscale = fabs(ptl[(int)(perm & 15) * 64 + lane]) + H;
   }
-  // true when no breakpoint of this user lies in knapsack k's window
-  auto calm = [&](int k) -> bool {
-    const double h = hwin[k];
-    const double need = h * bmax * (1.0 + 0x1p-30) + 0x1p-36 * (1.0 + gscale + lam[k] * bmax + h * bmax);
-    return gmin > need;
+  // distance from item j's line to its rank neighbours above -H and to zero
+  auto gap = [&](int j) -> double {
+    const double v = ptl[j * 64 + lane];
+    if (!(v > -H)) return 1e300;
+    const int r = (int)((rinv >> (4 * j)) & 15);
+    double d = fabs(v);
+    if (r > 0) d = fmin(d, ptl[(int)((perm >> (4 * (r - 1))) & 15) * 64 + lane] - v);
+    if (r + 1 < M) {
+      const double w = ptl[(int)((perm >> (4 * (r + 1))) & 15) * 64 + lane];
+      if (w > -H) d = fmin(d, v - w);
+    }
+    return d;
+  };
+  // true when no breakpoint of this user lies in knapsack k's window (A: the
+  // items moving with k)
+  auto calm = [&](int k, uint32_t A) -> bool {
+    const double h = hwin[k], lk = lam[k];
+    for (uint32_t m = A; m; m &= m - 1) {
+      const int o = __ffs((int)m) - 1;
+      const double b = bk(o, k);
+      const double need = h * b * (1.0 + 0x1p-30) + 0x1p-36 * (1.0 + gscale + lk * b + h * b);
+      if (!(gap(o) > need)) return false;
+    }
+    return true;
   };
   // threshold element of every item against the greedy solution of the other
   // items (valid when it is the only item that moves with lambda_k): the
@@ -184,12 +196,12 @@ __device__ __forceinline__ void scd_user(const SweepArgs &a, int M, int K, int L
       if (k >= K) continue;
       const int mode = kmode[k];
       if (!walk_mode(mode)) continue;
-      if (mode == KS_WINDOW && calm(k)) continue;
       const uint32_t A = mskl[k * 64 + lane];
       if (A != (1u << j)) {
-        if (j == __ffs((int)A) - 1) pending |= 1ull << k;
+        if (j == __ffs((int)A) - 1 && !(mode == KS_WINDOW && calm(k, A))) pending |= 1ull << k;
         continue;
       }
+      if (mode == KS_WINDOW && calm(k, A)) continue;
       const double lk = lam[k];
       const double bo_d = (double)btl[(j * D + t) * 64 + lane];
       const double add_o = lk * bo_d;
@@ -425,6 +437,7 @@ k_ell(const SweepArgs a, const EllGeom g) {
   double *rowbuf = (double *)wreg;
 
   uint32_t ch_pos = 0, ch_end = 0;   // the wave's reserved list chunk (window main pass)
+  uint32_t nlist = 0;                 // users the wave listed
   // tile indices fit 32 bits (the launcher rejects more than 2^31 - 1 tiles)
   for (int tile = (int)blockIdx.x * EW + wv; tile < (int)ntiles; tile += (int)W) {
     const int64_t u0 = (int64_t)tile * 64;
@@ -712,6 +725,7 @@ k_ell(const SweepArgs a, const EllGeom g) {
       const uint64_t mask = __ballot(listed);
       if (mask) {
         const uint32_t cnt = (uint32_t)__popcll(mask);
+        nlist += cnt;
         const uint32_t rank = (uint32_t)__popcll(mask & ((1ull << lane) - 1));
         // entries that still fit the current chunk, the rest opens a new one
         const uint32_t room = ch_end - ch_pos;
@@ -762,6 +776,7 @@ k_ell(const SweepArgs a, const EllGeom g) {
     // mark the unused tail of the wave's last chunk
     for (uint32_t e = ch_pos + lane; e < ch_end; e += 64)
       if (e < a.fcap) a.flist[e] = KP_LIST_HOLE;
+    if (lane == 0 && nlist) atomicAdd(a.fcount + 1, nlist);
   }
   __syncthreads();
   if (a.want_stats && STAGED) {

@@ -108,6 +108,6 @@ struct SweepArgs {
   int nv;
   // window pass split in two kernels: users listed by the first
   unsigned int *flist;     // [fcap] user indices
-  unsigned int *fcount;    // listed users (atomic; may exceed fcap)
+  unsigned int *fcount;    // [0] reserved list slots (atomic; may exceed fcap), [1] listed users
   unsigned int fcap;
 };
