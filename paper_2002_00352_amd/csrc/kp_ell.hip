@@ -11,6 +11,7 @@ size_t kp_ell_lds_bytes(int M, int K, int D, int L, int mode, int *region_out) {
     // the last lane's row
     region = (size_t)64 * M * 4 + (size_t)64 * M * D * 8 + (size_t)16 * D * 4;
     region = region > (size_t)8 * 65 * 8 ? region : (size_t)8 * 65 * 8;      // statistics rows
+    if (mode == KM_WMAIN && region < (size_t)64 * M * 12) region = (size_t)64 * M * 12;  // filter: p~ and bounds by rank
   }
   if (brk) {
     const size_t need = (size_t)ell_scratch(M, D, K).end;                     // p~, costs, masks
@@ -20,7 +21,7 @@ size_t kp_ell_lds_bytes(int M, int K, int D, int L, int mode, int *region_out) {
   size_t s = r16((size_t)(K + 1) * 8) + r16((size_t)L * 8 + 8) + r16((size_t)L * 4 + 4) +
              r16((size_t)EW * (K + 2) * 8);
   if (mode != KM_EVAL) s += r16((size_t)K * 4) + r16((size_t)K * 8 + 16);
-  if (mode == KM_WMAIN) s += r16((size_t)(K + 1) * 16);
+  if (mode == KM_WMAIN) s += r16((size_t)(K + 1) * sizeof(LamW));
   if (brk)
     s += r16((size_t)K * 8) + r16((size_t)K * sizeof(KState)) + r16((size_t)K * KP_NB * 8) +
          r16((size_t)K * KP_NB * 4) + 3 * r16((size_t)K * 4) + 2 * r16((size_t)K * 8) + r16(16);

@@ -56,6 +56,13 @@ __device__ __forceinline__ void stage_x4(const void *src, int nbytes, void *dst,
     __builtin_amdgcn_global_load_lds((const void *)(s + c), (lds_void_t *)(d + c), 16, 0, 0);
 }
 
+// lambda_k and the window bound wA_k (fp32, rounded up) of the window main pass
+struct LamW {
+  double lam;
+  float w;
+  float pad;
+};
+
 // Per-wave scratch of the breakpoint phase (byte offsets in the wave's region).
 struct EllScratch {
   int pt, bt, kt, msk, end;
@@ -369,7 +376,7 @@ k_ell(const SweepArgs a, const EllGeom g) {
   }
   // window main pass: (lambda_k, wA_k) pairs read together by the scoring,
   // [K] = (0, 0) for the clamped reads
-  double2 *lw = MODE == KM_WMAIN ? (double2 *)carve((size_t)(K + 1) * 16) : nullptr;
+  LamW *lw = MODE == KM_WMAIN ? (LamW *)carve((size_t)(K + 1) * sizeof(LamW)) : nullptr;
   if (BREAK) {
     kcorr = (double *)carve((size_t)K * 8);
     hs = (double *)carve((size_t)K * KP_NB * 8);
@@ -383,7 +390,7 @@ k_ell(const SweepArgs a, const EllGeom g) {
   }
   unsigned char *wreg = smem + off + (size_t)wv * g.region;   // this wave's region
   for (int t = tid; t <= K; t += ENT) lam[t] = t < K ? a.lam[t] : 0.0;
-  if (MODE == KM_WMAIN && tid == 0) lw[K] = make_double2(0.0, 0.0);
+  if (MODE == KM_WMAIN && tid == 0) lw[K] = LamW{0.0, 0.0f, 0.0f};
   for (int t = tid; t < a.tree.L; t += ENT) { tmask[t] = a.tree.mask[t]; tcap[t] = a.tree.cap[t]; }
   for (int t = tid; t < EW * (K + 2); t += ENT) wacc[t] = 0.0;
   if (MODE != KM_EVAL) {
@@ -392,7 +399,10 @@ k_ell(const SweepArgs a, const EllGeom g) {
       hwin[t] = a.st[t].mode == KS_WINDOW ? a.st[t].hw : 0.0;
       if (MODE == KM_WMAIN) {
         const double h = hwin[t];
-        lw[t] = make_double2(a.lam[t], h > 0.0 ? h * (1.0 + 0x1p-30) + 0x1p-36 * (a.lam[t] + h) : 0.0);
+        // wA_k, widened by 2^-20 before rounding to fp32 so that the fp32
+        // product with a cost still bounds the exact one from above
+        const double w = h > 0.0 ? h * (1.0 + 0x1p-30) + 0x1p-36 * (a.lam[t] + h) : 0.0;
+        lw[t] = LamW{a.lam[t], (float)(w * (1.0 + 0x1p-20)), 0.0f};
       }
     }
   }
@@ -533,10 +543,13 @@ k_ell(const SweepArgs a, const EllGeom g) {
     }
     // ---- cost-adjusted profits ----
     double pt[EM];
-    double amax = 0.0;   // window main pass: the largest wA over the user's knapsacks
+    // window main pass: nd[j] = item j's largest b_jk wA_k over its knapsacks
+    // (0 when none has a window), an fp32 upper bound
+    float nd[EM];
     #pragma unroll
     for (int j = 0; j < EM; ++j) {
       double acc = (double)pv[j];
+      nd[j] = 0.0f;
       #pragma unroll
       for (int t = 0; t < D; ++t) {
         // every lane reads: entries outside [0, K) (and the padding) read
@@ -546,10 +559,10 @@ k_ell(const SweepArgs a, const EllGeom g) {
         const unsigned kc = k < (unsigned)K ? k : (unsigned)K;
         double lk;
         if (MODE == KM_WMAIN) {
-          const double2 e = lw[kc];
-          lk = e.x;
-          amax = fmax(amax, e.y);
-          __asm__ volatile("" : "+v"(amax));   // fold now: e.y dies here
+          const LamW e = lw[kc];
+          lk = e.lam;
+          nd[j] = fmaxf(nd[j], e.w * vl[j * D + t]);
+          __asm__ volatile("" : "+v"(nd[j]));   // fold now: e.w dies here
         } else {
           lk = lam[kc];
         }
@@ -631,37 +644,50 @@ k_ell(const SweepArgs a, const EllGeom g) {
     // ---- window filter (main window pass), before the arrays die ----
     bool listed = false;
     if (MODE == KM_WMAIN) {
-      // The same test as the breakpoint phase: the smallest distance between
-      // two lines that can turn positive inside the window, or between such a
-      // line and zero, against the bound of the user's knapsacks with a
-      // window.  Lines below -H never can.  The bound of knapsack k is
-      // bmax * wA[k] + 2^-36 (1 + gscale), wA[k] = h_k (1 + 2^-30) +
-      // 2^-36 (lambda_k + h_k) (0 without a window).
+      // The breakpoint phase's test for all knapsacks at once: over the
+      // windows, item a's line moves against any other line by at most
+      // max_k b_ak wA_k (wA_k = h_k (1 + 2^-30) + 2^-36 (lambda_k + h_k), the
+      // other item's own bound covering the pairs where its cost is the
+      // larger), so the user is calm when every item with a window knapsack
+      // is farther than that (plus 2^-36 (1 + gscale)) from its rank
+      // neighbours above -H and from zero.  Lines below -H never turn
+      // positive.  p~ and the bounds by rank go into the dead staging area.
       const double H = hwin[K] * bmax * (1.0 + 0x1p-30) + 0x1p-36 * (1.0 + bmax * hwin[K]);
-      // p~ by rank into the dead staging area, then the gaps between
-      // neighbours in rank order (the smallest pairwise distance is between
-      // neighbours) down to the first line below -H
       double *srt = (double *)wreg;
+      float *srn = (float *)(srt + (size_t)M * 64);
       #pragma unroll
-      for (int j = 0; j < EM; ++j)
-        if (j < M) srt[__builtin_ctz(rbit[j]) * 64 + lane] = pt[j];
-      __builtin_amdgcn_s_waitcnt(0);
-      __builtin_amdgcn_wave_barrier();
-      __asm__ volatile("" ::: "memory");
-      const double top = srt[lane];
-      double gmin = 1e300, prev = 0.0;
-      for (int r = 0; r < M; ++r) {
-        const double v = srt[r * 64 + lane];
-        if (!(v > -H)) break;
-        gmin = fabs(v) < gmin ? fabs(v) : gmin;
-        if (r > 0) gmin = prev - v < gmin ? prev - v : gmin;
-        prev = v;
+      for (int j = 0; j < EM; ++j) {
+        if (j < M) {
+          const int r = __builtin_ctz(rbit[j]);
+          srt[r * 64 + lane] = pt[j];
+          srn[r * 64 + lane] = nd[j];
+        }
       }
       __builtin_amdgcn_s_waitcnt(0);
       __builtin_amdgcn_wave_barrier();
       __asm__ volatile("" ::: "memory");
-      const double need = bmax * amax + 0x1p-36 * (1.0 + fabs(top) + H);
-      listed = act && amax > 0.0 && !(gmin > need);
+      const double marg = 0x1p-36 * (1.0 + fabs(srt[lane]) + H);
+      // item r - 1 is decided once its lower neighbour is known
+      bool fail = false, have = false;
+      double pv0 = 0.0, pd = 0.0, pn = 0.0;   // previous item: p~, gap so far, bound
+      for (int r = 0; r < M; ++r) {
+        const double v = srt[r * 64 + lane];
+        if (!(v > -H)) break;
+        const double n = (double)srn[r * 64 + lane];
+        double d = fabs(v);
+        if (have) {
+          const double gg = pv0 - v;
+          d = fmin(d, gg);
+          pd = fmin(pd, gg);
+          fail = fail || (pn > 0.0 && !(pd > pn + marg));
+        }
+        pv0 = v; pd = d; pn = n; have = true;
+      }
+      if (have) fail = fail || (pn > 0.0 && !(pd > pn + marg));
+      __builtin_amdgcn_s_waitcnt(0);
+      __builtin_amdgcn_wave_barrier();
+      __asm__ volatile("" ::: "memory");
+      listed = act && fail;
     }
     if (STAGED) {
       if (a.x_out && act) {

@@ -384,6 +384,50 @@ def test_scd_window_trajectory(name, mk):
     assert full.window_stats() == (0, 0, 0, 0)
 
 
+def _alg5_instance(N, K, Q, seed):
+    """Alg.5's setting (Sec. 5.1): M = K, item j consumes only knapsack j
+    (diagonal b, every entry nonzero), one top-Q cap."""
+    from util import make
+    rng = np.random.default_rng(seed)
+    p = rng.integers(1, 1 << 24, (N, K)) / float(1 << 24)
+    b = np.zeros((N, K, K))
+    for k in range(K):
+        b[:, k, k] = rng.integers(1, 1 << 24, N) / float(1 << 24)
+    B = 0.15 * b.sum(axis=(0, 1))
+    return make(p, b, B, kpgen.tree_topq(K, Q), name="alg5")
+
+
+@gpu
+@pytest.mark.parametrize("K,Q", [(12, 3), (7, 2)])
+def test_alg5_setting_scd_trajectory(K, Q):
+    """Alg.5's special case on the GPU: stored per-item CSR with one entry per
+    row takes the uniform-row kernel (one moving item per knapsack: the
+    threshold-element path), dense storage the general kernel; both follow
+    the oracle's SCD trajectory bit for bit, window on and off.  The oracle's
+    general Map equals its Alg.5 Map on this instance (checked on a sample of
+    users at every iterate)."""
+    kp, torch = _kp()
+    print("case alg5 K", K, "Q", Q, flush=True)
+    inst = _alg5_instance(4097, K, Q, seed=50 + K)
+    csr = inst.to_csr()
+    assert np.all(np.diff(csr.rowptr) == 1)
+    pc, pd = kp.Problem.from_host(csr), kp.Problem.from_host(inst)
+    ctxs = [kp.Context(), kp.Context(), kp.Context()]
+    ctxs[1].set_window(False)
+    lam = np.zeros(K)
+    for t in range(8):
+        want = oracle.scd_sweep(inst, lam)
+        kk, uu, v1, v2 = oracle.scd_map(inst, lam)
+        for i in range(0, inst.N, 257):
+            k5, a5, b5 = oracle.alg5_map_user(inst, lam, i, Q)
+            assert sorted(kk[uu == i].tolist()) == sorted(k5.tolist())
+        for prob, ctx in ((pc, ctxs[0]), (pc, ctxs[1]), (pd, ctxs[2])):
+            got = kp.kp_scd_sweep(prob, _lamd(torch, lam), ctx=ctx)["lam"].cpu().numpy()
+            assert np.array_equal(got, want), (t, np.flatnonzero(got != want))
+        lam = want
+    print("window searches", ctxs[0].window_stats(), flush=True)
+
+
 @gpu
 @pytest.mark.parametrize("c,N", [(1, 10_000), (2, 2049), (3, 3001), (4, 700)])
 def test_device_generator_matches_host(c, N):
