@@ -130,6 +130,10 @@ struct Ctx {
   int64_t win_tried = 0, win_above = 0, win_below = 0;   // window searches since creation
   int64_t win_emitted = 0;                                 // breakpoints emitted inside windows
   int64_t win_listed = 0;                                  // users listed by split window passes
+  // budgets on the device (uploaded again only when they change)
+  double *B_dev = nullptr;
+  int B_cap = 0;
+  std::vector<double> B_host;
 };
 
 hipEvent_t take_event(Ctx *c) {
@@ -172,7 +176,7 @@ struct Carve {
 
 kp_status ensure_ws(Ctx *c, size_t bytes) {
   if (!c->pinned) {
-    if (hipHostMalloc((void **)&c->pinned, 128, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void **)&c->pinned, 256, hipHostMallocDefault) != hipSuccess) {
       c->pinned = nullptr;
       return fail(KP_ERR_HIP, "hipHostMalloc of the status word failed");
     }
@@ -347,7 +351,7 @@ kp_status choose_kernel(Ctx *c, Prepared &P, bool scd) {
     nnz = it->second.second;
   } else {
     if (!c->pinned) {
-      if (hipHostMalloc((void **)&c->pinned, 128, hipHostMallocDefault) != hipSuccess) {
+      if (hipHostMalloc((void **)&c->pinned, 256, hipHostMallocDefault) != hipSuccess) {
         c->pinned = nullptr;
         return fail(KP_ERR_HIP, "hipHostMalloc failed");
       }
@@ -413,6 +417,8 @@ struct SweepWs {
   unsigned int *flist, *fcount;   // users listed by the window pass
   uint32_t fcap;
   int *modes;           // [0] knapsacks with a window, [1] with another search mode
+  char *stat;           // status block, followed by the histograms (SCD)
+  size_t stat_bytes;    // the status block and the histograms
 };
 
 kp_status carve_ws(Ctx *c, const Prepared &P, bool scd, SweepWs &w) {
@@ -423,12 +429,14 @@ kp_status carve_ws(Ctx *c, const Prepared &P, bool scd, SweepWs &w) {
   size_t o_R = cv.take((size_t)K * 8);
   size_t o_g = cv.take(8);
   size_t o_P = cv.take(8);
-  size_t o_err = cv.take(8);
-  size_t o_pend = cv.take(32);
-  size_t o_st = 0, o_hs = 0, o_hc = 0, o_km = 0, o_e1 = 0, o_e2 = 0;
+  // status block (cleared with the histograms in one memset): [0] pending
+  // knapsacks, [8] walk-limit counter, [16] window counters, [32] list
+  // counters, [48] search-mode counts
+  size_t o_st = 0, o_hs = 0, o_hc = 0, o_km = 0, o_e1 = 0, o_e2 = 0, o_stat = 0;
   uint32_t cap = 0;
+  if (scd) o_st = cv.take((size_t)K * sizeof(KState));
+  o_stat = cv.take(64);
   if (scd) {
-    o_st = cv.take((size_t)K * sizeof(KState));
     o_hs = cv.take((size_t)K * KP_NB * 8);
     o_hc = cv.take((size_t)K * KP_NB * 4);
     o_km = cv.take((size_t)K);
@@ -451,15 +459,13 @@ kp_status carve_ws(Ctx *c, const Prepared &P, bool scd, SweepWs &w) {
     o_sk = cv.take((size_t)P.stage_grid() * scap * 2);
   }
   // users listed by a window pass of the uniform-row kernel (room for all)
-  size_t o_fl = 0, o_fc = 0, o_md = 0;
+  size_t o_fl = 0;
   uint32_t fcap = 0;
   if (scd && P.ell_D && P.pr.N < ((int64_t)1 << 32) - ((int64_t)1 << 28)) {
     // every user, plus the unused tails of the waves' reserved chunks
     fcap = (uint32_t)(P.pr.N + (int64_t)KP_LIST_CHUNK * P.ell_grid * 4);
     o_fl = cv.take((size_t)fcap * 4);
-    o_fc = cv.take(16);
   }
-  if (scd) o_md = cv.take(16);
   kp_status s = ensure_ws(c, cv.off);
   if (s != KP_OK) return s;
   char *b = (char *)c->ws;
@@ -468,9 +474,11 @@ kp_status carve_ws(Ctx *c, const Prepared &P, bool scd, SweepWs &w) {
   w.Rtmp = (double *)(b + o_R);
   w.gtmp = (double *)(b + o_g);
   w.Ptmp = (double *)(b + o_P);
-  w.err = (unsigned long long *)(b + o_err);
-  w.pending = (int *)(b + o_pend);
-  w.win = (unsigned int *)(b + o_pend + 16);
+  w.stat = b + o_stat;
+  w.stat_bytes = scd ? (o_hc + (size_t)K * KP_NB * 4) - o_stat : 64;
+  w.pending = (int *)(b + o_stat);
+  w.err = (unsigned long long *)(b + o_stat + 8);
+  w.win = (unsigned int *)(b + o_stat + 16);
   w.st = scd ? (KState *)(b + o_st) : nullptr;
   w.hist_sum = scd ? (double *)(b + o_hs) : nullptr;
   w.hist_cnt = scd ? (uint32_t *)(b + o_hc) : nullptr;
@@ -484,8 +492,27 @@ kp_status carve_ws(Ctx *c, const Prepared &P, bool scd, SweepWs &w) {
   w.stage_cap = scap;
   w.fcap = fcap;
   w.flist = fcap ? (unsigned int *)(b + o_fl) : nullptr;
-  w.fcount = fcap ? (unsigned int *)(b + o_fc) : nullptr;
-  w.modes = scd ? (int *)(b + o_md) : nullptr;
+  w.fcount = fcap ? (unsigned int *)(b + o_stat + 32) : nullptr;
+  w.modes = scd ? (int *)(b + o_stat + 48) : nullptr;
+  return KP_OK;
+}
+
+// Budgets of the problem on the device, in a buffer of the context that
+// keeps them between calls: copied only when they differ from the last copy.
+kp_status upload_B(Ctx *c, const Prepared &P, SweepWs &w) {
+  const int K = P.pr.K;
+  if (!c->B_dev || c->B_cap < K) {
+    if (c->B_dev) HIP_TRY(hipFree(c->B_dev));
+    c->B_dev = nullptr;
+    c->B_host.clear();
+    HIP_TRY(hipMalloc(&c->B_dev, (size_t)K * 8));
+    c->B_cap = K;
+  }
+  if (c->B_host != P.B) {
+    HIP_TRY(hipMemcpyAsync(c->B_dev, P.B.data(), (size_t)K * 8, hipMemcpyHostToDevice, c->stream));
+    c->B_host = P.B;
+  }
+  w.B = c->B_dev;
   return KP_OK;
 }
 
@@ -526,8 +553,9 @@ hipError_t timed_sweep(Ctx *c, const SweepArgs &a, const Prepared &P, bool scd, 
   if (P.ell_D && split) {
     SweepArgs ae = a;
     ae.ntiles = P.ell_ntiles;
-    err = hipMemsetAsync(ae.fcount, 0, 8, c->stream);   // [0] reserved slots, [1] listed users
-    if (err == hipSuccess) err = kp_launch_ell(ae, P.ell_D, P.ell_grid, 2, c->stream, &c->stats_grid);
+    // the list counters ([0] reserved slots, [1] listed users) were cleared
+    // with the status block
+    err = kp_launch_ell(ae, P.ell_D, P.ell_grid, 2, c->stream, &c->stats_grid);
     if (err == hipSuccess) {
       SweepArgs af = ae;
       af.want_stats = 0;
@@ -621,6 +649,7 @@ kp_status kp_destroy(void *ctx) {
   for (hipEvent_t e : c->ev_free) (void)hipEventDestroy(e);
   if (c->ws) (void)hipFree(c->ws);
   if (c->delta_dev) (void)hipFree(c->delta_dev);
+  if (c->B_dev) (void)hipFree(c->B_dev);
   if (c->pinned) (void)hipHostFree(c->pinned);
   delete c;
   return KP_OK;
@@ -629,6 +658,7 @@ kp_status kp_destroy(void *ctx) {
 kp_status kp_set_stream(void *ctx, void *hip_stream) {
   if (!ctx) return fail(KP_ERR_INVALID, "ctx is NULL");
   ((Ctx *)ctx)->stream = (hipStream_t)hip_stream;
+  ((Ctx *)ctx)->B_host.clear();   // the cached budgets were copied on the old stream
   return KP_OK;
 }
 
@@ -643,7 +673,7 @@ kp_status kp_eval_dual(void *ctx, const kp_problem *prob, const double *lambda, 
   if ((s = choose_kernel(c, P, false)) != KP_OK) return s;
   SweepWs w;
   if ((s = carve_ws(c, P, false, w)) != KP_OK) return s;
-  HIP_TRY(hipMemcpyAsync(w.B, P.B.data(), (size_t)P.pr.K * 8, hipMemcpyHostToDevice, c->stream));
+  if ((s = upload_B(c, P, w)) != KP_OK) return s;
   return eval_into(c, P, w, lambda, R ? R : w.Rtmp, g ? g : w.gtmp, primal ? primal : w.Ptmp, x);
 }
 
@@ -659,7 +689,7 @@ kp_status kp_dd_step(void *ctx, const kp_problem *prob, double alpha, double *la
   if ((s = choose_kernel(c, P, false)) != KP_OK) return s;
   SweepWs w;
   if ((s = carve_ws(c, P, false, w)) != KP_OK) return s;
-  HIP_TRY(hipMemcpyAsync(w.B, P.B.data(), (size_t)P.pr.K * 8, hipMemcpyHostToDevice, c->stream));
+  if ((s = upload_B(c, P, w)) != KP_OK) return s;
   double *Rd = R ? R : w.Rtmp;
   if ((s = eval_into(c, P, w, lambda_inout, Rd, g ? g : w.gtmp, primal ? primal : w.Ptmp, nullptr)) != KP_OK)
     return s;
@@ -700,7 +730,7 @@ kp_status kp_scd_sweep_masked(void *ctx, const kp_problem *prob, const double *l
   SweepWs w;
   if ((s = carve_ws(c, P, true, w)) != KP_OK) return s;
   const int K = P.pr.K;
-  HIP_TRY(hipMemcpyAsync(w.B, P.B.data(), (size_t)K * 8, hipMemcpyHostToDevice, c->stream));
+  if ((s = upload_B(c, P, w)) != KP_OK) return s;
   if (kmask) HIP_TRY(hipMemcpyAsync(w.kmask, kmask, (size_t)K, hipMemcpyHostToDevice, c->stream));
   // window hint from the previous call with the same K (performance only)
   if (!c->delta_dev || c->delta_K != K) {
@@ -725,10 +755,7 @@ kp_status kp_scd_sweep_masked(void *ctx, const kp_problem *prob, const double *l
     HIP_TRY(hipStreamSynchronize(c->stream));
     split = c->pinned[20] > 0 && c->pinned[21] == 0;
   }
-  HIP_TRY(hipMemsetAsync(w.hist_sum, 0, (size_t)K * KP_NB * 8, c->stream));
-  HIP_TRY(hipMemsetAsync(w.hist_cnt, 0, (size_t)K * KP_NB * 4, c->stream));
-  HIP_TRY(hipMemsetAsync(w.err, 0, 8, c->stream));
-  HIP_TRY(hipMemsetAsync(w.win, 0, 16, c->stream));
+  HIP_TRY(hipMemsetAsync(w.stat, 0, w.stat_bytes, c->stream));   // status, histograms
   double *Rd = R ? R : w.Rtmp;
   double *gd = g ? g : w.gtmp;
   double *Pd = primal ? primal : w.Ptmp;
@@ -751,23 +778,21 @@ kp_status kp_scd_sweep_masked(void *ctx, const kp_problem *prob, const double *l
     }
     HIP_TRY(kp_launch_scd_locate_select(w.st, K, w.B, Rd, nullptr, w.hist_sum, w.hist_cnt, w.ev1, w.ev2,
                                         w.emit_cap, w.pending, w.win, c->stream));
-    HIP_TRY(hipMemcpyAsync(c->pinned, w.pending, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipMemcpyAsync(c->pinned + 2, w.err, 8, hipMemcpyDeviceToHost, c->stream));
-    if (pass == 0 && window)
-      HIP_TRY(hipMemcpyAsync(c->pinned + 16, w.win, 16, hipMemcpyDeviceToHost, c->stream));
-    if (pass == 0 && split)
-      HIP_TRY(hipMemcpyAsync(c->pinned + 22, w.fcount + 1, 4, hipMemcpyDeviceToHost, c->stream));
+    // one copy of the status block: pending, walk-limit counter, window and
+    // list counters
+    int *st = c->pinned + 32;
+    HIP_TRY(hipMemcpyAsync(st, w.stat, 48, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     if (pass == 0 && window) {
-      c->win_tried += (unsigned)c->pinned[16];
-      c->win_above += (unsigned)c->pinned[17];
-      c->win_below += (unsigned)c->pinned[18];
-      c->win_emitted += (unsigned)c->pinned[19];
+      c->win_tried += (unsigned)st[4];
+      c->win_above += (unsigned)st[5];
+      c->win_below += (unsigned)st[6];
+      c->win_emitted += (unsigned)st[7];
     }
-    if (pass == 0 && split) c->win_listed += (unsigned)c->pinned[22];
-    if (*(unsigned long long *)(c->pinned + 2))
+    if (pass == 0 && split) c->win_listed += (unsigned)st[9];
+    if (*(unsigned long long *)(st + 2))
       return fail(KP_ERR_INTERNAL, "breakpoint walk exceeded its event limit");
-    if (c->pinned[0] == 0) break;
+    if (st[0] == 0) break;
   }
   HIP_TRY(kp_launch_scd_finish(w.st, K, lambda_in, lambda_out, c->delta_dev, c->stream));
   c->delta_valid = true;
@@ -1073,7 +1098,7 @@ kp_status kp_primal_fixup(void *ctx, const kp_problem *prob, const double *lambd
   double *Rv = (double *)(b + o_Rv), *Pv = (double *)(b + o_Pv);
   double *Gd = (double *)(b + o_G), *uv = (double *)(b + o_uv), *RB = (double *)(b + o_RB);
   int *map = (int *)(b + o_map);
-  HIP_TRY(hipMemcpyAsync(w.B, P.B.data(), (size_t)K * 8, hipMemcpyHostToDevice, c->stream));
+  if ((s = upload_B(c, P, w)) != KP_OK) return s;
   if ((s = eval_into(c, P, w, lambda, Rv, w.gtmp, Pv, xd)) != KP_OK) return s;
   std::vector<double> Rh(K);
   HIP_TRY(hipMemcpyAsync(Rh.data(), Rv, (size_t)K * 8, hipMemcpyDeviceToHost, c->stream));
