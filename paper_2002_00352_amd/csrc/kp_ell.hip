@@ -1,5 +1,7 @@
 // Host entry points of the lean sweep kernel (kp_ell_impl.h): LDS sizing,
 // dispatch to the per-mode instantiations, and the uniform-row check.
+#include <algorithm>
+#include <vector>
 #include "kp_ell_impl.h"
 
 size_t kp_ell_lds_bytes(int M, int K, int D, int L, int mode, int *region_out) {
@@ -30,6 +32,32 @@ size_t kp_ell_lds_bytes(int M, int K, int D, int L, int mode, int *region_out) {
   return s;
 }
 
+// Rank of the laminar matroid on M items (the most items any feasible x_i
+// selects): every set (subsets first) holds min(cap, its items outside its
+// maximal subsets + their ranks); items in no set count one each.
+int laminar_rank(const TreeDev &t, int M) {
+  std::vector<int> r(t.L, 0);
+  std::vector<char> inner(t.L, 0);   // contained in a later (larger) set
+  for (int l = 0; l < t.L; ++l) {
+    uint64_t covered = 0;
+    int sum = 0;
+    for (int c = 0; c < l; ++c) {
+      if (inner[c] || (t.mask[c] & ~t.mask[l]) != 0) continue;   // not a maximal subset of l
+      covered |= t.mask[c];
+      sum += r[c];
+      inner[c] = 1;
+    }
+    sum += __builtin_popcountll(t.mask[l] & ~covered);
+    r[l] = std::min(t.cap[l], sum);
+  }
+  uint64_t covered = 0;
+  int total = 0;
+  for (int l = 0; l < t.L; ++l)
+    if (!inner[l]) { covered |= t.mask[l]; total += r[l]; }
+  const uint64_t all = M >= 64 ? ~0ull : ((1ull << M) - 1);
+  return total + __builtin_popcountll(all & ~covered);
+}
+
 // mode: 0 evaluation, 1 full SCD pass, 2 window main pass, 3 listed users of a window pass.
 // grid is an upper bound (the size of the per-block buffers); *used receives
 // the grid launched (the blocks that can be resident at once, at most grid).
@@ -43,6 +71,7 @@ hipError_t kp_launch_ell(const SweepArgs &a, int D, int grid, int mode, hipStrea
   g.rows = g.region / (65 * 8);
   if (g.rows > g.K + 2) g.rows = g.K + 2;
   g.x4 = (((uintptr_t)a.pr.p | (uintptr_t)a.pr.col | (uintptr_t)a.pr.val) & 15) == 0;
+  g.compact = laminar_rank(a.tree, g.M) <= KP_SEL_MAX;
   switch (mode) {
     case KM_EVAL: return kp_launch_ell_mode<KM_EVAL>(a, g, lds, grid, D, stream, used);
     case KM_SCD: return kp_launch_ell_mode<KM_SCD>(a, g, lds, grid, D, stream, used);

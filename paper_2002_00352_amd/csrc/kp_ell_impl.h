@@ -87,6 +87,7 @@ struct EllGeom {
   int M, K, region;   // region: bytes of per-wave LDS
   int rows;           // statistics rows (of 65 doubles) per chunk
   int x4;             // p, col and val are 16-byte aligned: full tiles use 16-byte loads
+  int compact;        // at most KP_SEL_MAX items can be selected (the matroid's rank)
 };
 
 // Breakpoint phase of one user (one lane) from its per-lane LDS scratch:
@@ -641,6 +642,30 @@ k_ell(const SweepArgs a, const EllGeom g) {
     for (int j = 0; j < EM; ++j) {
       if (S >> j & 1) { Pi = Pi + (double)pv[j]; Gi = Gi + pt[j]; }
     }
+    // At most KP_SEL_MAX items can be selected (the laminar matroid's rank,
+    // g.compact): their stored entries are gathered from the staged tile
+    // (still intact) in item order, so the consumption sums below visit
+    // KP_SEL_MAX * D entries instead of M * D.  Unused slots hold (-1, 0).
+    int sk[KP_SEL_MAX * D];
+    float sv_[KP_SEL_MAX * D];
+    if (STAGED && g.compact) {
+      uint32_t sm = (uint32_t)S;
+      const int32_t *scl = sc + lane * M * D;
+      const float *svl = sv + lane * M * D;
+      #pragma unroll
+      for (int r = 0; r < KP_SEL_MAX; ++r) {
+        const int j = sm ? __ffs((int)sm) - 1 : 0;
+        const bool ok = sm != 0;
+        sm &= sm - 1u;
+        #pragma unroll
+        for (int t = 0; t < D; ++t) {
+          const int32_t c0 = scl[j * D + t];
+          const float v0 = svl[j * D + t];
+          sk[r * D + t] = ok ? c0 : -1;
+          sv_[r * D + t] = ok ? v0 : 0.0f;
+        }
+      }
+    }
     // ---- window filter (main window pass), before the arrays die ----
     bool listed = false;
     if (MODE == KM_WMAIN) {
@@ -709,20 +734,30 @@ k_ell(const SweepArgs a, const EllGeom g) {
           for (int q = 0; q < nq; ++q) rows[q * 65 + lane] = 0.0;
           if ((unsigned)(K - c0) < (unsigned)nq) rows[(K - c0) * 65 + lane] = Gi;
           if ((unsigned)(K + 1 - c0) < (unsigned)nq) rows[(K + 1 - c0) * 65 + lane] = Pi;
-          #pragma unroll
-          for (int j = 0; j < EM; ++j) {
+          if (g.compact) {
             #pragma unroll
-            for (int t = 0; t < D; ++t) {
-              const int q = cl[j * D + t] - c0;
-              // widened again here (an opaque copy): keeping the scoring's
-              // widened costs alive until now would cost 2 registers each
-              float v = vl[j * D + t];
-              __asm__("" : "+v"(v));
-              // unselected or foreign entries add +0 to row 0 (a consumption
-              // row, never -0): no branch
-              const bool ok = (S >> j & 1) && (unsigned)q < (unsigned)nq && q < K - c0;
-              __hip_atomic_fetch_add(&rows[(ok ? q : 0) * 65 + lane], ok ? (double)v : 0.0,
+            for (int e = 0; e < KP_SEL_MAX * D; ++e) {
+              const int q = sk[e] - c0;
+              const bool ok = (unsigned)q < (unsigned)nq && q < K - c0;
+              __hip_atomic_fetch_add(&rows[(ok ? q : 0) * 65 + lane], ok ? (double)sv_[e] : 0.0,
                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+            }
+          } else {
+            #pragma unroll
+            for (int j = 0; j < EM; ++j) {
+              #pragma unroll
+              for (int t = 0; t < D; ++t) {
+                const int q = cl[j * D + t] - c0;
+                // widened again here (an opaque copy): keeping the scoring's
+                // widened costs alive until now would cost 2 registers each
+                float v = vl[j * D + t];
+                __asm__("" : "+v"(v));
+                // unselected or foreign entries add +0 to row 0 (a consumption
+                // row, never -0): no branch
+                const bool ok = (S >> j & 1) && (unsigned)q < (unsigned)nq && q < K - c0;
+                __hip_atomic_fetch_add(&rows[(ok ? q : 0) * 65 + lane], ok ? (double)v : 0.0,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+              }
             }
           }
           __builtin_amdgcn_s_waitcnt(0);
@@ -730,11 +765,14 @@ k_ell(const SweepArgs a, const EllGeom g) {
           __asm__ volatile("" ::: "memory");
           int lg = 0;
           while ((2 << lg) * nq <= 64) ++lg;
-          const int q = lane >> lg, len = 64 >> lg;
+          const int q = lane >> lg, len = 64 >> lg, step = 1 << lg;
           double sum = 0.0;
           if (q < nq) {
-            const double *row = rows + q * 65 + (lane & ((1 << lg) - 1)) * len;
-            for (int u = 0; u < len; ++u) sum = sum + row[u];
+            // part i sums the entries i, i + step, ... of the row (parts on
+            // distinct banks)
+            const double *row = rows + q * 65 + (lane & (step - 1));
+            #pragma unroll 8
+            for (int u = 0; u < len; ++u) sum = sum + row[u * step];
           }
           for (int o = 1; o < (1 << lg); o <<= 1) sum = sum + __shfl_xor(sum, o, 64);
           if (q < nq && (lane & ((1 << lg) - 1)) == 0)

@@ -12,6 +12,7 @@
 #define KP_WIN_MAX_REL 0.03125 // windows wider than this fraction of lambda_k^t are not tried
 #define KP_LIST_CHUNK 256u     // list slots a wave reserves at a time in the window pass
 #define KP_LIST_HOLE 0xFFFFFFFFu  // unused list slot
+#define KP_SEL_MAX 4           // the uniform-row kernel gathers the selected entries when at most this many items can be selected
 
 // Laminar local constraints after pruning: only sets that can bind
 // (C_l < |S_l|), duplicates merged with the smaller cap, ordered subsets
