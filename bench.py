@@ -266,6 +266,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--dd-steps", type=int, default=10, help="DD sweeps timed after the SCD steps")
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
     ap.add_argument("--users", type=int, default=None, help="override N (testing only)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -373,6 +374,25 @@ def main():
         "lambda_final_head": [float(v) for v in lam[:4].cpu().numpy()],
         "gen_s": t_gen,
     }
+    # the DD sweep (Eq. 14) on the same instance: evaluation kernel + update
+    lam_dd = lam.clone()
+    kp.kp_dd_step(prob, 1e-12, lam_dd, ctx=ctx)
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(args.dd_steps):
+        kp.kp_dd_step(prob, 1e-12, lam_dd, ctx=ctx)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_d, n_d, bytes_d = ctx.timing()
+    ctx.set_timing(False)
+    if n_d:
+        dd_ms = ms_d / n_d
+        dd_gbs = bytes_d / n_d / (dd_ms * 1e-3) / 1e9
+        rec["dd_sweep"] = {"steps": args.dd_steps, "ms_per_step": (t1 - t0) * 1e3 / args.dd_steps,
+                           "user_solves_per_s": N * args.dd_steps / (t1 - t0),
+                           "kernel_avg_ms": dd_ms, "achieved_GBs": dd_gbs,
+                           "frac": dd_gbs / HBM_PEAK_GBS}
     del prob, arrs
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
