@@ -393,6 +393,26 @@ def main():
                            "user_solves_per_s": N * args.dd_steps / (t1 - t0),
                            "kernel_avg_ms": dd_ms, "achieved_GBs": dd_gbs,
                            "frac": dd_gbs / HBM_PEAK_GBS}
+    # the same DD steps through the autograd form (forward: evaluation kernel,
+    # backward: the gradient kernel from the saved consumption)
+    lam_ag = [lam.clone()]
+
+    def ag_step():
+        l = lam_ag[0].clone().requires_grad_(True)
+        kp.DualFn.apply(l, prob).backward()
+        with torch.no_grad():
+            lam_ag[0] = torch.clamp(l - 1e-12 * l.grad, min=0.0)
+    ag_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.dd_steps):
+        ag_step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    if "dd_sweep" in rec:
+        ag_ms = (t1 - t0) * 1e3 / args.dd_steps
+        rec["dd_sweep"]["autograd_ms_per_step"] = ag_ms
+        rec["dd_sweep"]["autograd_over_plain"] = ag_ms / rec["dd_sweep"]["ms_per_step"]
     del prob, arrs
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
