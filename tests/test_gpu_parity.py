@@ -347,6 +347,58 @@ def test_uniform_row_kernel_parity(name, mk):
         lam = want if t < 2 else np.random.default_rng(t).random(inst.K) * 2
 
 
+def _offset_problem(kp, torch, inst):
+    """The instance on the GPU with p, col and val placed one element past a
+    16-byte boundary (4-byte aligned views): the uniform-row kernel stages
+    every tile with 4-byte loads instead of 16-byte ones."""
+    def dev(a, dt):
+        a = np.ascontiguousarray(a, dt)
+        buf = torch.empty(a.size + 1, dtype={np.float32: torch.float32, np.int32: torch.int32}[dt],
+                          device="cuda")
+        view = buf[1:]
+        view.copy_(torch.from_numpy(a))
+        assert view.data_ptr() % 16 != 0
+        return view
+    rowptr = torch.from_numpy(np.ascontiguousarray(inst.rowptr, np.int64)).cuda()
+    return kp.Problem(dev(inst.p, np.float32), inst.B, inst.tree.parent, inst.tree.cap,
+                      inst.tree.leaf_of_item, rowptr=rowptr, col=dev(inst.col, np.int32),
+                      val=dev(inst.val, np.float32), N=inst.N, M=inst.M, K=inst.K)
+
+
+LEAN_EXTRA = [
+    ("c3-unaligned-N5000", lambda: kpgen.config_instance(3, N=5000), True),
+    ("topq6-rank6-N4100", lambda: kpgen.make_instance(4100, 10, 9, seed=47, Q=6, csr_d=2, budget_frac=0.1),
+     False),
+]
+
+
+@gpu
+@pytest.mark.parametrize("name,mk,offset", LEAN_EXTRA, ids=[c[0] for c in LEAN_EXTRA])
+def test_uniform_row_kernel_staging_and_rank(name, mk, offset):
+    """The uniform-row kernel's other paths: 4-byte staging of full tiles
+    when the arrays are not 16-byte aligned, and the consumption sums over
+    all entries when more than 4 items can be selected (top-6).  Decisions,
+    statistics and SCD updates (window trajectory) equal the oracle's."""
+    kp, torch = _kp()
+    print("case", name, flush=True)
+    inst = mk()
+    prob = _offset_problem(kp, torch, inst) if offset else kp.Problem.from_host(inst)
+    ctx = kp.Context()
+    lam = np.zeros(inst.K)
+    for t in range(6):
+        ev = kp.kp_eval_dual(prob, _lamd(torch, lam), want_x=True, ctx=ctx)
+        ref = oracle.eval_dual(inst, lam)
+        assert np.array_equal(ev["x"].cpu().numpy(), ref["x"])
+        assert np.array_equal(ev["R"].cpu().numpy(), ref["R"])
+        for key in ("g", "P"):
+            assert abs(ev[key].item() - ref[key]) <= REL * max(1.0, abs(ref[key]))
+        want = oracle.scd_sweep(inst, lam)
+        got = kp.kp_scd_sweep(prob, _lamd(torch, lam), ctx=ctx)["lam"].cpu().numpy()
+        assert np.array_equal(got, want), (t, np.flatnonzero(got != want))
+        lam = want
+    print("window searches", ctx.window_stats(), "listed", ctx.window_listed(), flush=True)
+
+
 WINDOW_CASES = [
     ("c3-N20000", lambda: kpgen.config_instance(3, N=20000)),
     ("csr-d1-topq-N9000", lambda: kpgen.make_instance(9000, 12, 9, seed=43, Q=3, csr_d=1, budget_frac=0.1)),
