@@ -79,6 +79,67 @@ __device__ __forceinline__ void issue_entries(Prefetch &f, const ProbDev &pr, in
   }
 }
 
+// A window that does not contain lambda_k^t (an alternation window around
+// lambda_k^{t-1}): move the user's lines to the window's centre c,
+// z'_j = p~_j - (c - lambda_k^t) b_jk.  Over the window (radius r around c)
+// a moving line moves by at most r b_jk, so no two lines cross in it (nor a
+// moving line and zero) when every such gap between lines that can turn
+// positive there exceeds r bmax plus a rounding margin; then the greedy set
+// is the same over the whole window, and it is Alg.1 on the moved lines (in
+// rank space, as a mask of ranks).  Returns false when the test does not
+// apply or fails; else true with *cw = the set's consumption of k, in item
+// order.  zu: p~ of the user's items, bu: its costs [M][K]; A: the items
+// moving with k.  M <= 16.
+__device__ __forceinline__ bool far_window_set(const double *zu, const float *bu, int M, int K, int k,
+                                               uint64_t A, double lk, double wlo, double whi, double bmk,
+                                               const TreeDev &T, double *cw) {
+  const double c = 0.5 * (wlo + whi);
+  const double r = fmax(whi - c, c - wlo);
+  const double dl = c - lk;
+  if (M > 16 || !(fabs(dl) > r)) return false;
+  const double Hs = r * bmk * (1.0 + 0x1p-30) + 0x1p-36 * (1.0 + (lk + fabs(dl) + r) * bmk);
+  auto moved = [&](int j) -> double {
+    const double b = (A >> j & 1) ? (double)bu[j * K + k] : 0.0;
+    const double s = dl * b;
+    return zu[j] - s;
+  };
+  uint64_t rk = 0;   // rank of every item by (z' desc, index asc), 4 bits each
+  for (int j = 0; j < M; ++j) rk |= (uint64_t)j << (4 * j);
+  uint64_t posc = 0;
+  double gmin = 1e300, zmax = 0.0;
+  for (int x = 0; x < M; ++x) {
+    const double zx = moved(x);
+    const bool mx = A >> x & 1, rx = zx > -Hs;
+    if (zx > 0.0) posc |= 1ull << x;
+    if (rx) zmax = fmax(zmax, fabs(zx));
+    if (rx && mx) gmin = fmin(gmin, fabs(zx));
+    for (int y = x + 1; y < M; ++y) {
+      const double zy = moved(y);
+      if (zy > zx) { rk += 1ull << (4 * x); rk -= 1ull << (4 * y); }
+      if (rx && zy > -Hs && (mx || (A >> y & 1))) gmin = fmin(gmin, fabs(zx - zy));
+    }
+  }
+  const double need = r * bmk * (1.0 + 0x1p-30) + 0x1p-36 * (1.0 + zmax + Hs + (lk + fabs(dl) + r) * bmk);
+  if (!(gmin > need)) return false;
+  uint32_t alive = 0;
+  for (int j = 0; j < M; ++j)
+    if (posc >> j & 1) alive |= 1u << ((rk >> (4 * j)) & 15);
+  for (int l = 0; l < T.L; ++l) {
+    const uint64_t m = T.mask[l];
+    uint32_t mr = 0;
+    for (int j = 0; j < M; ++j)
+      if (m >> j & 1) mr |= 1u << ((rk >> (4 * j)) & 15);
+    uint32_t x = alive & mr;
+    for (int q = 0; q < T.cap[l]; ++q) x &= x - 1u;
+    alive &= ~x;
+  }
+  double sum = 0.0;
+  for (int j = 0; j < M; ++j)
+    if ((A >> j & 1) && (alive >> ((rk >> (4 * j)) & 15) & 1)) sum = sum + (double)bu[j * K + k];
+  *cw = sum;
+  return true;
+}
+
 template <int FMT, bool SCD>
 __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g, const int bid,
                                            const int nblk, unsigned char *smem) {
@@ -419,8 +480,14 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
           if (walk && mode == KS_WINDOW) {
             // no breakpoint of this user inside the window: nothing to emit
             // and its consumption just above the window is v_ik (no correction)
+            double cw = 0.0;
             if (window_calm(ugap[2 * u], ugap[2 * u + 1], kst[k].hw, (double)bmk, lk)) {
               walk = false;
+            } else if (far_window_set(zu, bu, M, K, k, A, lk, kst[k].wlo, kst[k].whi, (double)bmk, a.tree, &cw)) {
+              // no breakpoint inside the window: its consumption just above
+              // the window is the window's set's
+              walk = false;
+              if (cw != v) atomicAdd(&kcorr[k], cw - v);
             } else {
               auto line = [&](int j, double &c, double &b) {
                 b = (A >> j & 1) ? (double)bu[j * K + k] : 0.0;
