@@ -278,6 +278,53 @@ def presolve(inst, users, max_iter=100, lam0=None):
     return lam, it
 
 
+def categorical_copies(tree):
+    """Categorical variables (Sec. 2, x_ij non-negative integers under the
+    laminar caps): the largest count of item j is the smallest cap on the
+    sets containing it.  Returns those counts (an item in no set has none:
+    ValueError)."""
+    M = len(tree.leaf_of_item)
+    sets = tree.sets()
+    u = []
+    for j in range(M):
+        caps = [int(tree.cap[l]) for l in range(tree.L) if j in sets[l]]
+        if not caps:
+            raise ValueError("item %d is in no set" % j)
+        u.append(min(caps))
+    return np.array(u, np.int64)
+
+
+def categorical_binary(inst):
+    """The binary instance equivalent to a categorical one: item j becomes
+    u_j identical items (its profit and costs) inside item j's innermost set,
+    so the caps count copies, ordered by item.  Returns (instance,
+    item_of_copy)."""
+    import dataclasses
+    from kpgen import Tree
+    u = categorical_copies(inst.tree)
+    item_of_copy = np.repeat(np.arange(inst.M), u)
+    Mc = len(item_of_copy)
+    N, M, K = inst.N, inst.M, inst.K
+    p = inst.p.reshape(N, M)[:, item_of_copy].reshape(-1).copy()
+    tree = Tree(inst.tree.parent.copy(), inst.tree.cap.copy(),
+                np.asarray(inst.tree.leaf_of_item)[item_of_copy].astype(np.int32))
+    bd = inst.b_dense().reshape(N, M, K)[:, item_of_copy, :]
+    out = dataclasses.replace(inst, M=Mc, p=p, b=bd.reshape(-1).copy(), rowptr=None, col=None,
+                              val=None, tree=tree)
+    if inst.b is None:
+        out = out.to_csr()
+    return out, item_of_copy
+
+
+def categorical_counts(x_bin, N, item_of_copy, M):
+    """x_ij = the number of item j's selected copies."""
+    x = np.asarray(x_bin).reshape(N, len(item_of_copy)).astype(np.int64)
+    out = np.zeros((N, M), np.int64)
+    for c, j in enumerate(item_of_copy):
+        out[:, j] += x[:, c]
+    return out
+
+
 def solve(inst, method="scd", lam0=None, tol=1e-3, max_iter=100, alpha=1e-3, fix_every=1,
           block=1):
     """Reference driver: coordinate descent (Alg.4 loop) or DD (Alg.2 loop)

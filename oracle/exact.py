@@ -170,3 +170,22 @@ def brute_global(inst) -> float:
         if np.all(use <= inst.B):
             best = max(best, sum(c[0] for c in combo))
     return best
+
+
+def brute_user_integer(z: Sequence, sets, caps) -> Tuple[object, List[Tuple[int, ...]]]:
+    """The integer local IP by enumeration (categorical variables, Sec. 2):
+    max sum_j z_j x_j over non-negative integer x with sum_{j in S_l} x_j <=
+    C_l.  Every item must lie in some set.  Returns (optimum, maximisers)."""
+    import itertools
+    M = len(z)
+    ub = [min(int(c) for s, c in zip(sets, caps) if j in s) for j in range(M)]
+    best, arg = None, []
+    for x in itertools.product(*[range(u + 1) for u in ub]):
+        if any(sum(x[j] for j in s) > c for s, c in zip(sets, caps)):
+            continue
+        v = sum(Fraction(z[j]) * x[j] for j in range(M))
+        if best is None or v > best:
+            best, arg = v, [x]
+        elif v == best:
+            arg.append(x)
+    return best, arg

@@ -116,7 +116,11 @@ __device__ __forceinline__ bool far_window_set(const double *zu, const float *bu
     for (int y = x + 1; y < M; ++y) {
       const double zy = moved(y);
       if (zy > zx) { rk += 1ull << (4 * x); rk -= 1ull << (4 * y); }
-      if (rx && zy > -Hs && (mx || (A >> y & 1))) gmin = fmin(gmin, fabs(zx - zy));
+      // pairs that can cross: at least one moves, and not two equal lines
+      // with equal costs in k (they coincide over the whole window)
+      const bool my = A >> y & 1;
+      if (rx && zy > -Hs && (mx || my) && !(zx == zy && bu[x * K + k] == bu[y * K + k]))
+        gmin = fmin(gmin, fabs(zx - zy));
     }
   }
   const double need = r * bmk * (1.0 + 0x1p-30) + 0x1p-36 * (1.0 + zmax + Hs + (lk + fabs(dl) + r) * bmk);
@@ -430,7 +434,14 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
           const double v = z[perm[u * M + r]];
           if (!(v > -H)) break;
           gmin = fabs(v) < gmin ? fabs(v) : gmin;
-          if (r > 0) gmin = prev - v < gmin ? prev - v : gmin;
+          if (r > 0) {
+            // two identical lines (equal p~ and equal costs in every
+            // knapsack, e.g. the copies of a categorical item) never cross
+            bool same = prev == v;
+            const float *ba = bu + (size_t)perm[u * M + r - 1] * K, *bb = bu + (size_t)perm[u * M + r] * K;
+            for (int k = 0; same && k < K; ++k) same = ba[k] == bb[k];
+            if (!same) gmin = prev - v < gmin ? prev - v : gmin;
+          }
           prev = v;
         }
         ugap[2 * u] = gmin;

@@ -674,3 +674,40 @@ def test_scd_alternating_trajectory(name, mk):
             assert np.array_equal(got, want), (t, np.flatnonzero(got != want), got, want)
         lam = want
     print("window searches", win.window_stats(), flush=True)
+
+
+CATEGORICAL_CASES = [("csr-d2", 2), ("dense", 0)]
+
+
+@gpu
+@pytest.mark.parametrize("name,csr_d", CATEGORICAL_CASES, ids=[c[0] for c in CATEGORICAL_CASES])
+def test_categorical_scd_trajectory(name, csr_d):
+    """Categorical variables (Sec. 2): the library's copies of every item
+    (paper_2002_00352_amd.categorical) give the oracle's counts x_ij,
+    consumption and SCD trajectory (the oracle expands the instance with its
+    own code)."""
+    kp, torch = _kp()
+    from paper_2002_00352_amd import categorical
+    print("case categorical", name, flush=True)
+    # root cap 5 over 6 items, a group of the first 3 with cap 3, item caps 1..3
+    parent = np.array([-1, 0] + [1, 1, 1, 0, 0, 0], np.int32)
+    cap = np.array([5, 3, 2, 1, 3, 2, 1, 3], np.int32)
+    leaf = np.arange(2, 8, dtype=np.int32)
+    tree = kpgen.Tree(parent, cap, leaf)
+    inst = kpgen.make_instance(3001, 6, 5, seed=61, csr_d=csr_d, tree=tree, budget_frac=0.1)
+    cp = categorical.expand(kp.Problem.from_host(inst))
+    binst, ioc = oracle.categorical_binary(inst)
+    assert np.array_equal(cp.item_of_copy, ioc) and cp.binary.M == binst.M == 12
+    ctx = kp.Context()
+    lam = np.zeros(inst.K)
+    for t in range(6):
+        ev = kp.kp_eval_dual(cp.binary, _lamd(torch, lam), want_x=True, ctx=ctx)
+        ref = oracle.eval_dual(binst, lam)
+        want_x = oracle.categorical_counts(ref["x"], inst.N, ioc, inst.M)
+        assert np.array_equal(cp.counts(ev["x"]).cpu().numpy(), want_x)
+        assert np.array_equal(ev["R"].cpu().numpy(), ref["R"])
+        want = oracle.scd_sweep(binst, lam)
+        got = kp.kp_scd_sweep(cp.binary, _lamd(torch, lam), ctx=ctx)["lam"].cpu().numpy()
+        assert np.array_equal(got, want), (t, np.flatnonzero(got != want))
+        lam = want
+    assert want_x.max() >= 2   # some item is taken more than once

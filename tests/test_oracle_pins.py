@@ -419,3 +419,59 @@ def test_presolve_saves_iterations_paper_claim():
         before += len(h0)
         after += len(h1)
     assert after <= 0.6 * before, (before, after)
+
+
+def _categorical_forest(rng, M):
+    """A random laminar forest for categorical items: a root over all items,
+    sometimes a group over a prefix, and a cap node per item (caps 1..3)."""
+    parent, cap = [-1], [int(rng.integers(1, 5))]
+    group = -1
+    if M >= 2 and rng.random() < 0.5:
+        parent.append(0)
+        cap.append(int(rng.integers(1, 4)))
+        group = 1
+    gsize = int(rng.integers(1, M + 1))
+    leaf = []
+    for j in range(M):
+        parent.append(group if (group >= 0 and j < gsize) else 0)
+        cap.append(int(rng.integers(1, 4)))
+        leaf.append(len(parent) - 1)
+    return kpgen.Tree(np.array(parent, np.int32), np.array(cap, np.int32), np.array(leaf, np.int32))
+
+
+def test_categorical_copies_give_the_integer_optimum():
+    """Categorical variables (Sec. 2): Alg.1 on the binary copies (item j as
+    u_j identical items inside its innermost set), counted per item, reaches
+    the optimum of the integer local IP found by enumeration, and the counts
+    meet every cap; ties and non-positive values included."""
+    rng = np.random.default_rng(31)
+    for trial in range(80):
+        M = int(rng.integers(1, 5))
+        tree = _categorical_forest(rng, M)
+        z = rng.integers(-3, 7, M) / 4.0
+        inst = make(np.zeros((1, M)), np.zeros((1, M, 1)), np.ones(1), tree)
+        binst, ioc = oracle.categorical_binary(inst)
+        xb = oracle.alg1(binst, z[ioc])
+        x = oracle.categorical_counts(xb, 1, ioc, M)[0]
+        sets = tree.sets()
+        best, _ = exact.brute_user_integer(list(z), sets, list(tree.cap))
+        assert all(sum(int(x[j]) for j in S) <= c for S, c in zip(sets, tree.cap)), (trial, x)
+        assert sum(Fraction(z[j]) * int(x[j]) for j in range(M)) == best, (trial, z, x, best)
+
+
+def test_categorical_copy_counts_match():
+    """The library's count of copies per item (the smallest cap on the
+    item's chain of sets) equals the oracle's, and an item in no set is
+    refused by both."""
+    import paper_2002_00352_amd.categorical as cat
+    rng = np.random.default_rng(32)
+    for trial in range(40):
+        M = int(rng.integers(1, 9))
+        tree = _categorical_forest(rng, M)
+        assert np.array_equal(cat.copy_counts(tree.parent, tree.cap, tree.leaf_of_item),
+                              oracle.categorical_copies(tree))
+    free = kpgen.Tree(np.array([-1], np.int32), np.array([2], np.int32), np.array([0, -1], np.int32))
+    with pytest.raises(ValueError):
+        cat.copy_counts(free.parent, free.cap, free.leaf_of_item)
+    with pytest.raises(ValueError):
+        oracle.categorical_copies(free)
