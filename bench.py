@@ -291,7 +291,7 @@ def main():
         summarize_pmc(a[0], a[1], a[2], a[3], a[4], int(a[5]), a[6], int(a[7]))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the sweep shards by users; see the design notes). Run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)

@@ -244,7 +244,7 @@ kp_status kp_get_window_stats(void *ctx, int64_t *tried, int64_t *above, int64_t
    NULL.  Diagnostic: the results do not depend on it. */
 kp_status kp_get_window_listed(void *ctx, int64_t *listed);
 
-/* Size limits of this build. */
+/* Size limits of the library. */
 int32_t kp_max_items(void);        /* 64 */
 int32_t kp_max_knapsacks_scd(void);/* largest K accepted by the SCD calls */
 
