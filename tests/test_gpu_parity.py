@@ -162,18 +162,24 @@ def test_unaligned_dense_costs():
 
 
 @gpu
-def test_empty_instance():
+@pytest.mark.parametrize("fmt", ["dense", "csr-uniform-rows"])
+def test_empty_instance(fmt):
+    """N = 0: no consumption, g = lambda.B, every SCD multiplier 0 (dense
+    costs, and per-item CSR rows that would take the uniform-row kernel)."""
     kp, torch = _kp()
     rng = np.random.default_rng(0)
-    inst = random_instance(rng, 4, 3, 2, Q=1)
+    inst = random_instance(rng, 4, 3, 2, Q=1) if fmt == "dense" else \
+        kpgen.make_instance(4, 3, 2, seed=5, Q=1, csr_d=1, budget_frac=0.5)
     prob = kp.Problem.from_host(inst)
     prob.s.N = 0
     lam = np.array([0.5, 0.25])
-    ev = kp.kp_eval_dual(prob, _lamd(torch, lam))
+    ctx = kp.Context()
+    ev = kp.kp_eval_dual(prob, _lamd(torch, lam), ctx=ctx)
     assert ev["R"].cpu().numpy().tolist() == [0.0, 0.0]
     assert ev["g"].item() == 0.5 * inst.B[0] + 0.25 * inst.B[1]
-    sw = kp.kp_scd_sweep(prob, _lamd(torch, lam))
-    assert sw["lam"].cpu().numpy().tolist() == [0.0, 0.0]
+    for _ in range(2):   # the second call may start with windows
+        sw = kp.kp_scd_sweep(prob, _lamd(torch, lam), ctx=ctx)
+        assert sw["lam"].cpu().numpy().tolist() == [0.0, 0.0]
 
 
 @gpu
