@@ -91,6 +91,7 @@ kp_status fail(kp_status st, const char *fmt, ...) {
   } while (0)
 
 constexpr int kTileBudget = 24 * 1024;   // bytes of staged costs per tile
+constexpr int kTileRowsMin = 160;        // item rows per tile at least, when the rows are long
 constexpr size_t kMaxLds = 160 * 1024;   // LDS per workgroup on gfx950
 constexpr int kMaxGrid = 2048;
 constexpr uint32_t kEmitCapDefault = 1u << 20;
@@ -299,7 +300,10 @@ kp_status prepare(const kp_problem *p, bool scd, Prepared &out, const Ctx *ctx =
   const size_t per_user = (size_t)M * p->K * 4;
   int U = (int)std::max<size_t>(1, std::min<size_t>(64, kTileBudget / per_user));
   U = std::min(U, std::max(1, 1024 / M));   // rows per tile <= the prefetched rows
-  if (U >= 4) U &= ~3;   // keeps 16-byte alignment of dense tiles when M*K is odd
+  // long rows (large K): enough rows to keep the block's threads busy
+  U = std::max(U, std::min((kTileRowsMin + M - 1) / M, std::max(1, 1024 / M)));
+  // dense tiles start 16-byte aligned when U*M*K is a multiple of 4
+  if (U >= 4 && (M * p->K) % 4 != 0) U &= ~3;
   int grid_override = 0;
   if (ctx) {
     auto it = ctx->tuning.find(std::make_tuple(M, p->K, p->b_format));
