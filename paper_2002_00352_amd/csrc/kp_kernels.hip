@@ -297,6 +297,10 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
       nnr = (int)((N - nu0) < U ? (N - nu0) : U) * M;
       issue_rows<FMT>(f, a.pr, nu0, nnr, K, tid, g.aligned);
     }
+    // at most one (pruned) set, e.g. top-Q: every row decides its own
+    // selection in the rank phase; the users' masks start empty
+    const bool fastsel = a.tree.L <= 1;
+    if (fastsel && tid < nu) Sm[tid] = 0ull;
     __syncthreads();
     // ---- phase A: scores ----
     if (FMT == 0) {
@@ -331,16 +335,24 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
     }
     __syncthreads();
     // ---- phase B1a: rank of every item of every user (one thread per row) ----
+    const uint64_t m1 = a.tree.L == 1 ? a.tree.mask[0] : 0ull;
+    const int c1 = a.tree.L == 1 ? a.tree.cap[0] : 0;
     for (int r = tid; r < nr; r += NT) {
       const int u = r / M, j = r - u * M;
       const double *z = pt + u * M;
       const double zj = z[j];
-      int rank = 0;
+      int rank = 0, rank1 = 0;
       for (int jj = 0; jj < M; ++jj) {
         const double zz = z[jj];
-        rank += (zz > zj) || (zz == zj && jj < j);
+        const int beats = (zz > zj) || (zz == zj && jj < j);
+        rank += beats;
+        rank1 += beats & (int)(m1 >> jj & 1);
       }
       perm[u * M + rank] = (uint8_t)j;
+      // Alg.1 with at most one set: a positive item is kept unless it is in
+      // the set behind cap better members of it (those are positive too)
+      if (fastsel && zj > 0.0 && (!(m1 >> j & 1) || rank1 < c1))
+        atomicOr((unsigned long long *)&Sm[u], 1ull << j);
     }
     // CSR: the next tile's entry range is known now that its row offsets have
     // landed; start those loads too
@@ -355,7 +367,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
       const double *z = pt + u * M;
       uint64_t pos = 0;
       for (int j = 0; j < M; ++j) if (z[j] > 0.0) pos |= 1ull << j;
-      const uint64_t S = greedy_mask(perm + u * M, M, pos, a.tree);
+      const uint64_t S = fastsel ? Sm[u] : greedy_mask(perm + u * M, M, pos, a.tree);
       Sm[u] = S;
       Pm[u] = pos;
       if (SCD) {
