@@ -79,6 +79,81 @@ __device__ __forceinline__ void issue_entries(Prefetch &f, const ProbDev &pr, in
   }
 }
 
+// The same test for at most one binding set (top-Q and the like: set mask
+// m1 with cap c1, or no set), for any M, in O(M c1) with no per-item
+// state: items outside the set are selected when positive, so a moving one
+// must keep its sign over the window; inside the set the selection at c is
+// the c1 best positive members T (picked by repeated maxima, ties to the
+// lower index), and it stays the same when T stays positive and the best
+// other member stays below T (one gap: every pair across it moves against
+// each other by at most r bmax), or, when fewer than c1 members are
+// positive, when no moving member outside T can turn positive.  Returns
+// false when the test does not apply or fails; else true with *cw = the
+// selection's consumption of k.
+__device__ __forceinline__ bool far_window_single(const double *zu, const float *bu, int M, int K, int k,
+                                                  uint64_t A, double lk, double wlo, double whi, double bmk,
+                                                  uint64_t m1, int c1, double *cw) {
+  const double c = 0.5 * (wlo + whi);
+  const double r = fmax(whi - c, c - wlo);
+  const double dl = c - lk;
+  if (!(fabs(dl) > r)) return false;
+  const double Hs = r * bmk * (1.0 + 0x1p-30) + 0x1p-36 * (1.0 + (lk + fabs(dl) + r) * bmk);
+  auto moved = [&](int j) -> double {
+    const double b = (A >> j & 1) ? (double)bu[j * K + k] : 0.0;
+    const double s = dl * b;
+    return zu[j] - s;
+  };
+  double zmax = 0.0;
+  for (int j = 0; j < M; ++j) {
+    const double z = moved(j);
+    if (z > -Hs) zmax = fmax(zmax, fabs(z));
+  }
+  const double bound = r * bmk * (1.0 + 0x1p-30) + 0x1p-36 * (1.0 + zmax + Hs + (lk + fabs(dl) + r) * bmk);
+  uint64_t sel = 0;
+  for (int j = 0; j < M; ++j) {
+    if (m1 >> j & 1) continue;
+    const double z = moved(j);
+    if ((A >> j & 1) && z > -Hs && !(fabs(z) > bound)) return false;   // may change sign
+    if (z > 0.0) sel |= 1ull << j;
+  }
+  uint64_t inT = 0;
+  int nt = 0;
+  double minT = INFINITY;
+  for (int round = 0; round <= c1; ++round) {
+    double best = -INFINITY;
+    int bj = -1;
+    for (int j = 0; j < M; ++j) {
+      if (!(m1 >> j & 1) || (inT >> j & 1)) continue;
+      const double z = moved(j);
+      if (z > best) { best = z; bj = j; }
+    }
+    if (bj < 0) break;
+    if (round < c1 && best > 0.0) {
+      inT |= 1ull << bj;
+      minT = best;
+      ++nt;
+      continue;
+    }
+    // bj: the best member outside T
+    if (nt == c1 && best > -Hs && !(minT - best > bound)) return false;
+    break;
+  }
+  if (nt > 0 && !(minT > bound)) return false;
+  if (nt < c1) {
+    // room is left: no moving member outside T may turn positive
+    for (int j = 0; j < M; ++j) {
+      if (!(m1 >> j & 1) || (inT >> j & 1) || !(A >> j & 1)) continue;
+      if (!(moved(j) < -bound)) return false;
+    }
+  }
+  sel |= inT;
+  double sum = 0.0;
+  for (int j = 0; j < M; ++j)
+    if ((sel >> j & 1) && (A >> j & 1)) sum = sum + (double)bu[j * K + k];
+  *cw = sum;
+  return true;
+}
+
 // A window that does not contain lambda_k^t (an alternation window around
 // lambda_k^{t-1}): move the user's lines to the window's centre c,
 // z'_j = p~_j - (c - lambda_k^t) b_jk.  Over the window (radius r around c)
@@ -506,7 +581,12 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
             double cw = 0.0;
             if (window_calm(ugap[2 * u], ugap[2 * u + 1], kst[k].hw, (double)bmk, lk)) {
               walk = false;
-            } else if (far_window_set(zu, bu, M, K, k, A, lk, kst[k].wlo, kst[k].whi, (double)bmk, a.tree, &cw)) {
+            } else if (a.tree.L <= 1
+                           ? far_window_single(zu, bu, M, K, k, A, lk, kst[k].wlo, kst[k].whi, (double)bmk,
+                                               a.tree.L == 1 ? a.tree.mask[0] : 0ull,
+                                               a.tree.L == 1 ? a.tree.cap[0] : 0, &cw)
+                           : far_window_set(zu, bu, M, K, k, A, lk, kst[k].wlo, kst[k].whi, (double)bmk, a.tree,
+                                            &cw)) {
               // no breakpoint inside the window: its consumption just above
               // the window is the window's set's
               walk = false;
