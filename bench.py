@@ -215,16 +215,18 @@ def bench_batched(args):
     seq_steps = min(args.steps, 3)
     lams = [torch.zeros(pr.K, dtype=torch.float64, device="cuda") for pr in probs]
     outs = [torch.zeros(pr.K, dtype=torch.float64, device="cuda") for pr in probs]
-    sctx = kp.Context()
+    # one context per instance, as a caller running them one by one would
+    # keep (each context carries its instance's window history)
+    sctxs = [kp.Context() for _ in probs]
     for _ in range(args.warmup):
         for i, pr in enumerate(probs):
-            kp.kp_scd_sweep(pr, lams[i], outs[i], ctx=sctx)
+            kp.kp_scd_sweep(pr, lams[i], outs[i], ctx=sctxs[i])
         lams, outs = outs, lams
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(seq_steps):
         for i, pr in enumerate(probs):
-            kp.kp_scd_sweep(pr, lams[i], outs[i], ctx=sctx)
+            kp.kp_scd_sweep(pr, lams[i], outs[i], ctx=sctxs[i])
         lams, outs = outs, lams
     torch.cuda.synchronize()
     seq_dt = (time.perf_counter() - t0) / seq_steps

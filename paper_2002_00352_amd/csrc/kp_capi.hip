@@ -58,6 +58,7 @@ hipError_t kp_launch_ell_check(const int64_t *rowptr, int64_t nrows, int D, unsi
 hipError_t kp_launch_sweep_batched(const SweepArgs *descs, const TileGeom *geoms,
                                    const int *block_off, int n_inst, int total_blocks, size_t lds,
                                    hipStream_t stream);
+hipError_t kp_launch_inst_active(const KState *st, const int *koff, int n, int *flags, hipStream_t stream);
 hipError_t kp_launch_batched_aux(int which, const void *tab, int n, KState *st, const void *lam_ptrs,
                                  const int *kinst, const int *klocal, double *hint, const uint64_t *eoff,
                                  const uint32_t *ecap, hipStream_t stream);
@@ -100,6 +101,7 @@ constexpr uint32_t kStageCap = 4096;    // staged events per block per pass (at 
 constexpr uint32_t kStageCapMax = 65536;
 constexpr uint32_t kEmitCapBatched = 1u << 16;   // emitted events per (instance, knapsack) per pass (at least)
 constexpr double kEmitBytesBatched = 8.0e9;        // bound on a batch's emission buffers
+constexpr size_t kBatchedLds = 40 * 1024;          // LDS per block of the batched launch (4 blocks per CU)
 
 struct Ctx {
   hipStream_t stream = nullptr;
@@ -1157,10 +1159,75 @@ struct BatchPlan {
   double *Bf = nullptr, *hs = nullptr, *e1 = nullptr, *e2 = nullptr, *stats = nullptr;
   uint32_t *hc = nullptr;
   unsigned long long *err = nullptr;
-  int *pinned = nullptr;
+  int *pinned = nullptr;     // [0] pending knapsacks, [2..3] error word, [16..] per-instance flags
   hipGraph_t graph[2] = {nullptr, nullptr};
   hipGraphExec_t exec[2] = {nullptr, nullptr};
+  // later passes: the blocks are split again among the instances still searching
+  int *koff = nullptr;      // [n+1] first flat knapsack of every instance
+  int *active = nullptr;    // [n] instance needs another pass (written by k_inst_active)
+  SweepArgs *rd = nullptr;  // [n] descriptors of the active instances
+  TileGeom *rg = nullptr;   // [n]
+  int *rboff = nullptr;     // [n+1]
+  unsigned char *up = nullptr;   // pinned upload buffer of rd, rg, rboff
+  int gmax = 0;             // blocks of a pass over every instance's tiles
+  double *s1 = nullptr, *s2 = nullptr;
+  uint16_t *sk = nullptr;
+  size_t stage_total = 0;   // staged events of the whole launch
+  std::vector<SweepArgs> hd[2];   // [dir] host descriptors of the later passes
+  std::vector<TileGeom> hg;
+  std::vector<int64_t> ntiles;
+  std::vector<double> pairs;      // users x knapsacks of every instance
+  std::vector<size_t> ilds;       // LDS of every instance's tiles
 };
+
+// Split of a later pass: the instances whose knapsacks still search share
+// every block (in proportion to their tiles), and the staging area of the
+// whole launch is divided among their blocks.  Returns the number of active
+// instances (0: nothing to sweep).
+int plan_resplit(BatchPlan *p, int dir, int *blocks, size_t *lds) {
+  const int n = p->n;
+  const int *flag = p->pinned + 16;
+  std::vector<int> act;
+  int64_t TA = 0;
+  for (int s = 0; s < n; ++s)
+    if (flag[s] && p->ntiles[s] > 0) { act.push_back(s); TA += p->ntiles[s]; }
+  const int na = (int)act.size();
+  if (na == 0) return 0;
+  const int G = (int)std::max<int64_t>(na, std::min<int64_t>(TA, p->gmax));
+  SweepArgs *d = (SweepArgs *)p->up;
+  TileGeom *g = (TileGeom *)(p->up + (size_t)n * sizeof(SweepArgs));
+  int *bo = (int *)(p->up + (size_t)n * (sizeof(SweepArgs) + sizeof(TileGeom)));
+  std::vector<int64_t> nb(na);
+  std::vector<double> want(na);
+  double tot = 0.0;
+  size_t L = 0;
+  for (int i = 0; i < na; ++i) {
+    const int s = act[i];
+    nb[i] = std::max<int64_t>(1, std::min<int64_t>(p->ntiles[s], std::llround((double)G * p->ntiles[s] / (double)TA)));
+    want[i] = std::min<double>(kStageCapMax, std::max<double>(kStageCap, p->pairs[s] / nb[i] / 64.0));
+    tot += want[i] * nb[i];
+    L = std::max(L, p->ilds[s]);
+  }
+  const double scale = tot > (double)p->stage_total ? (double)p->stage_total / tot : 1.0;
+  size_t so = 0;
+  bo[0] = 0;
+  for (int i = 0; i < na; ++i) {
+    const int s = act[i];
+    const uint32_t cap = (uint32_t)std::max(1.0, std::floor(want[i] * scale));
+    d[i] = p->hd[dir][s];
+    d[i].stage_v1 = p->s1 + so;
+    d[i].stage_v2 = p->s2 + so;
+    d[i].stage_k = p->sk + so;
+    d[i].stage_cap = cap;
+    so += (size_t)nb[i] * cap;
+    g[i] = p->hg[s];
+    bo[i + 1] = bo[i] + (int)nb[i];
+  }
+  if (so > p->stage_total) return -1;   // cannot happen: the caps were scaled to fit
+  *blocks = bo[na];
+  *lds = L;
+  return na;
+}
 
 kp_status plan_first_pass(BatchPlan *p, int dir, hipStream_t s) {
   HIP_TRY(kp_launch_batched_aux(p->window ? 3 : 1, nullptr, p->Kf, p->kst, p->lam_tab[dir], p->kin, p->klo, p->hint,
@@ -1171,8 +1238,10 @@ kp_status plan_first_pass(BatchPlan *p, int dir, hipStream_t s) {
   HIP_TRY(kp_launch_scd_locate_select(p->kst, p->Kf, p->Bf, p->stats, p->kin, p->hs, p->hc, p->e1, p->e2, p->cap, p->pend, nullptr, s));
   HIP_TRY(kp_launch_batched_aux(2, nullptr, p->Kf, p->kst, p->lam_tab[1 - dir], p->kin, p->klo, p->hint, nullptr,
                                 nullptr, s));
+  HIP_TRY(kp_launch_inst_active(p->kst, p->koff, p->n, p->active, s));
   HIP_TRY(hipMemcpyAsync(p->pinned, p->pend, sizeof(int), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(p->pinned + 2, p->err, 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(p->pinned + 16, p->active, (size_t)p->n * 4, hipMemcpyDeviceToHost, s));
   return KP_OK;
 }
 
@@ -1208,13 +1277,27 @@ kp_status plan_step(BatchPlan *p, int dir, double *stats_out, bool graph) {
       return fail(KP_ERR_INTERNAL, "breakpoint walk exceeded its event limit");
     if (p->pinned[0] == 0) break;
     if (pass >= kMaxPasses) return fail(KP_ERR_INTERNAL, "SCD threshold search exceeded %d passes", kMaxPasses);
-    if (p->T > 0) HIP_TRY(kp_launch_sweep_batched(p->d[dir][0], p->geom, p->boff, p->n, p->GB, p->lds, s));
+    if (p->T > 0) {
+      int blocks = 0;
+      size_t lds = 0;
+      const int na = plan_resplit(p, dir, &blocks, &lds);
+      if (na < 0) return fail(KP_ERR_INTERNAL, "batched staging split overflowed");
+      if (na > 0) {
+        const size_t nd = (size_t)p->n * sizeof(SweepArgs), ng = (size_t)p->n * sizeof(TileGeom);
+        HIP_TRY(hipMemcpyAsync(p->rd, p->up, (size_t)na * sizeof(SweepArgs), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(p->rg, p->up + nd, (size_t)na * sizeof(TileGeom), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(p->rboff, p->up + nd + ng, (size_t)(na + 1) * 4, hipMemcpyHostToDevice, s));
+        HIP_TRY(kp_launch_sweep_batched(p->rd, p->rg, p->rboff, na, blocks, lds, s));
+      }
+    }
     ++passes;
     HIP_TRY(kp_launch_scd_locate_select(p->kst, p->Kf, p->Bf, p->stats, p->kin, p->hs, p->hc, p->e1, p->e2, p->cap, p->pend, nullptr, s));
     HIP_TRY(kp_launch_batched_aux(2, nullptr, p->Kf, p->kst, p->lam_tab[1 - dir], p->kin, p->klo, p->hint, nullptr,
                                 nullptr, s));
+    HIP_TRY(kp_launch_inst_active(p->kst, p->koff, p->n, p->active, s));
     HIP_TRY(hipMemcpyAsync(p->pinned, p->pend, sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(p->pinned + 2, p->err, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(p->pinned + 16, p->active, (size_t)p->n * 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
   }
   if (c->timing && e0 && e1) {
@@ -1239,6 +1322,7 @@ void plan_free(BatchPlan *p) {
   }
   if (p->ws) (void)hipFree(p->ws);
   if (p->pinned) (void)hipHostFree(p->pinned);
+  if (p->up) (void)hipHostFree(p->up);
   delete p;
 }
 
@@ -1257,6 +1341,18 @@ kp_status plan_create(Ctx *c, const kp_problem *probs, int n, const double *cons
   BatchPlan *p = new BatchPlan();
   p->c = c;
   p->n = n;
+  // every block of the batched launch gets the largest LDS any instance
+  // needs, so instances with long rows take smaller tiles: the launch keeps
+  // kBatchedBlocksPerCu blocks per compute unit for everyone
+  for (auto &q : P) {
+    int U = q.U;
+    while (U > 1 && kp_sweep_lds_bytes(U, q.pr.M, q.pr.K, true, q.pr.fmt) > kBatchedLds) --U;
+    while (U > 1 && q.pr.fmt == KP_B_DENSE && ((int64_t)U * q.pr.M * q.pr.K) % 4 != 0) --U;
+    if (U != q.U) {
+      q.U = U;
+      q.ntiles = (q.pr.N + U - 1) / U;
+    }
+  }
   int64_t T = 0;
   int Kf = 0;
   for (auto &q : P) { T += q.ntiles; Kf += q.pr.K; }
@@ -1323,9 +1419,20 @@ kp_status plan_create(Ctx *c, const kp_problem *probs, int n, const double *cons
   const size_t o_e2 = cv.take((size_t)ioff[n] * 8);
   const size_t o_eo = cv.take((size_t)Kf * 8);
   const size_t o_ec = cv.take((size_t)Kf * 4);
-  const size_t o_s1 = cv.take((size_t)p->GB * kStageCap * 8);
-  const size_t o_s2 = cv.take((size_t)p->GB * kStageCap * 8);
-  const size_t o_sk = cv.take((size_t)p->GB * kStageCap * 2);
+  // staged events per block, per instance: scaled with the block's share of
+  // (user, knapsack) pairs as in the single-instance sweep (a block of a large
+  // instance that overflows its staging costs the whole batch another pass)
+  std::vector<uint32_t> scap(n);
+  std::vector<size_t> soff(n + 1, 0);
+  for (int s = 0; s < n; ++s) {
+    const int nb = boff[s + 1] - boff[s];
+    const double share = (double)P[s].pr.N * P[s].pr.K / std::max(1, nb) / 64.0;
+    scap[s] = (uint32_t)std::min<double>(kStageCapMax, std::max<double>(kStageCap, share));
+    soff[s + 1] = soff[s] + (size_t)nb * scap[s];
+  }
+  const size_t o_s1 = cv.take(soff[n] * 8);
+  const size_t o_s2 = cv.take(soff[n] * 8);
+  const size_t o_sk = cv.take(soff[n] * 2);
   const size_t o_err = cv.take(8);
   const size_t o_pend = cv.take(8);
   const size_t o_kin = cv.take((size_t)Kf * 4);
@@ -1336,6 +1443,11 @@ kp_status plan_create(Ctx *c, const kp_problem *probs, int n, const double *cons
   const size_t o_tab1 = cv.take((size_t)ncol * kp_coldesc_size());
   const size_t o_stat = cv.take((size_t)ncol * 8);
   const size_t o_hint = cv.take((size_t)Kf * 32);  // per knapsack: bucket width, last step, two past multipliers
+  const size_t o_koff = cv.take((size_t)(n + 1) * 4);
+  const size_t o_act = cv.take((size_t)n * 4);
+  const size_t o_rd = cv.take((size_t)n * sizeof(SweepArgs));
+  const size_t o_rg = cv.take((size_t)n * sizeof(TileGeom));
+  const size_t o_rbo = cv.take((size_t)(n + 1) * 4);
   if (c->max_ws && cv.off > c->max_ws) {
     plan_free(p);
     return fail(KP_ERR_NOMEM, "batched plan needs %zu bytes, above the context cap", cv.off);
@@ -1345,8 +1457,14 @@ kp_status plan_create(Ctx *c, const kp_problem *probs, int n, const double *cons
     plan_free(p);
     return fail(KP_ERR_NOMEM, "hipMalloc of %zu plan bytes failed", cv.off);
   }
-  if (hipHostMalloc((void **)&p->pinned, 64, hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc((void **)&p->pinned, 64 + (size_t)n * 4, hipHostMallocDefault) != hipSuccess) {
     p->pinned = nullptr;
+    plan_free(p);
+    return fail(KP_ERR_HIP, "hipHostMalloc failed");
+  }
+  if (hipHostMalloc((void **)&p->up, (size_t)n * (sizeof(SweepArgs) + sizeof(TileGeom)) + (size_t)(n + 1) * 4,
+                    hipHostMallocDefault) != hipSuccess) {
+    p->up = nullptr;
     plan_free(p);
     return fail(KP_ERR_HIP, "hipHostMalloc failed");
   }
@@ -1379,6 +1497,24 @@ kp_status plan_create(Ctx *c, const kp_problem *probs, int n, const double *cons
   p->coltab[0] = w + o_tab0;
   p->coltab[1] = w + o_tab1;
   p->stats = (double *)(w + o_stat);
+  p->koff = (int *)(w + o_koff);
+  p->active = (int *)(w + o_act);
+  p->rd = (SweepArgs *)(w + o_rd);
+  p->rg = (TileGeom *)(w + o_rg);
+  p->rboff = (int *)(w + o_rbo);
+  p->s1 = (double *)(w + o_s1);
+  p->s2 = (double *)(w + o_s2);
+  p->sk = (uint16_t *)(w + o_sk);
+  p->stage_total = soff[n];
+  p->gmax = gmax;
+  p->ntiles.resize(n);
+  p->pairs.resize(n);
+  p->ilds.resize(n);
+  for (int s = 0; s < n; ++s) {
+    p->ntiles[s] = P[s].ntiles;
+    p->pairs[s] = (double)P[s].pr.N * P[s].pr.K;
+    p->ilds[s] = kp_sweep_lds_bytes(P[s].U, P[s].pr.M, P[s].pr.K, true, P[s].pr.fmt);
+  }
   std::vector<SweepArgs> hd[2][2];
   for (int d = 0; d < 2; ++d) for (int f = 0; f < 2; ++f) hd[d][f].resize(n);
   std::vector<TileGeom> hg(n);
@@ -1404,10 +1540,10 @@ kp_status plan_create(Ctx *c, const kp_problem *probs, int n, const double *cons
     a.emit_v1 = p->e1 + ioff[s];
     a.emit_v2 = p->e2 + ioff[s];
     a.emit_cap = icap[s];
-    a.stage_v1 = (double *)(w + o_s1) + (size_t)boff[s] * kStageCap;
-    a.stage_v2 = (double *)(w + o_s2) + (size_t)boff[s] * kStageCap;
-    a.stage_k = (uint16_t *)(w + o_sk) + (size_t)boff[s] * kStageCap;
-    a.stage_cap = kStageCap;
+    a.stage_v1 = (double *)(w + o_s1) + soff[s];
+    a.stage_v2 = (double *)(w + o_s2) + soff[s];
+    a.stage_k = (uint16_t *)(w + o_sk) + soff[s];
+    a.stage_cap = scap[s];
     a.err = p->err;
     for (int d = 0; d < 2; ++d) {
       a.lam = d == 0 ? lam_a[s] : lam_b[s];
@@ -1443,6 +1579,7 @@ kp_status plan_create(Ctx *c, const kp_problem *probs, int n, const double *cons
     for (int f = 0; f < 2 && e == hipSuccess; ++f) e = up(p->d[d][f], hd[d][f].data(), (size_t)n * sizeof(SweepArgs));
   if (e == hipSuccess) e = up(p->geom, hg.data(), (size_t)n * sizeof(TileGeom));
   if (e == hipSuccess) e = up(p->boff, boff.data(), (size_t)(n + 1) * 4);
+  if (e == hipSuccess) e = up(p->koff, koff.data(), (size_t)(n + 1) * 4);
   if (e == hipSuccess) e = up(p->Bf, hB.data(), (size_t)Kf * 8);
   if (e == hipSuccess) e = up(p->kin, kin.data(), (size_t)Kf * 4);
   if (e == hipSuccess) e = up(p->klo, klo.data(), (size_t)Kf * 4);
@@ -1460,6 +1597,8 @@ kp_status plan_create(Ctx *c, const kp_problem *probs, int n, const double *cons
     plan_free(p);
     return fail(KP_ERR_HIP, "plan upload failed: %s", hipGetErrorString(e));
   }
+  for (int d = 0; d < 2; ++d) p->hd[d] = hd[d][0];
+  p->hg = hg;
   *out = p;
   return KP_OK;
 }

@@ -136,6 +136,12 @@ __device__ __forceinline__ void record_event(const SweepArgs &a, const KState &k
   }
 }
 
+// Does a knapsack in search state m need another pass over its users?
+__device__ __forceinline__ bool walk_mode(int m) {
+  return m == KS_EXP || m == KS_EMIT_BUCKET || m == KS_HULL_BUCKET || m == KS_REFINE ||
+         m == KS_EMIT_RANGE || m == KS_WINDOW;
+}
+
 // End of a sweep block: add its histograms to the global ones, reserve space
 // for its staged events with one atomic per knapsack and copy them there.
 // Every thread of the block calls this.

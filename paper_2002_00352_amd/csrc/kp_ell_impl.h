@@ -78,11 +78,6 @@ __host__ __device__ inline EllScratch ell_scratch(int M, int D, int K) {
   return x;
 }
 
-__device__ __forceinline__ bool walk_mode(int m) {
-  return m == KS_EXP || m == KS_EMIT_BUCKET || m == KS_HULL_BUCKET || m == KS_REFINE ||
-         m == KS_EMIT_RANGE || m == KS_WINDOW;
-}
-
 struct EllGeom {
   int M, K, region;   // region: bytes of per-wave LDS
   int rows;           // statistics rows (of 65 doubles) per chunk

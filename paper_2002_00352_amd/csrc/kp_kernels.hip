@@ -292,12 +292,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
     __shared__ int busy;
     if (tid == 0) busy = 0;
     __syncthreads();
-    for (int t = tid; t < K; t += NT) {
-      const int m = kmode[t];
-      if (m == KS_EXP || m == KS_EMIT_BUCKET || m == KS_HULL_BUCKET || m == KS_REFINE || m == KS_EMIT_RANGE ||
-          m == KS_WINDOW)
-        busy = 1;
-    }
+    for (int t = tid; t < K; t += NT)
+      if (walk_mode(kmode[t])) busy = 1;
     __syncthreads();
     if (!busy) return;
   }
@@ -1699,6 +1695,16 @@ __global__ void k_scd_init_flat(KState *st, int Kf, const double *const *lam_in,
   st[f] = s;
 }
 
+// Batched: flags[s] = 1 if instance s has a knapsack that needs another
+// pass over its users (knapsacks koff[s] .. koff[s+1]-1 of the flat state).
+__global__ void k_inst_active(const KState *st, const int *koff, int n, int *flags) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  int on = 0;
+  for (int f = koff[s]; f < koff[s + 1]; ++f) on |= walk_mode(st[f].mode) ? 1 : 0;
+  flags[s] = on;
+}
+
 __global__ void k_scd_finish_flat(const KState *st, int Kf, double *const *lam_out, const int *kinst,
                                   const int *klocal, double *hint) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1741,6 +1747,12 @@ hipError_t kp_launch_batched_aux(int which, const void *tab, int n, KState *st, 
     hipLaunchKernelGGL(k_scd_finish_flat, dim3((n + 63) / 64), dim3(64), 0, stream, (const KState *)st,
                        n, (double *const *)lam_ptrs, kinst, klocal, hint);
   }
+  return hipGetLastError();
+}
+
+hipError_t kp_launch_inst_active(const KState *st, const int *koff, int n, int *flags, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_inst_active, dim3((n + 63) / 64), dim3(64), 0, stream, st, koff, n, flags);
   return hipGetLastError();
 }
 
