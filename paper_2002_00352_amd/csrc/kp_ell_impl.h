@@ -288,11 +288,10 @@ __device__ __forceinline__ void scd_user(const SweepArgs &a, int M, int K, int L
           const uint64_t m = tmask[l];
           if ((m >> o & 1) && popc64(Sw & m) >= tcap[l]) { circ = Sw & m; tight = true; break; }
         }
+        // compared with the running maximum through cr_gt: a division only
+        // for a crossing that beats it
         if (!tight) {
-          if (co > 0.0) {
-            const double val = co / bo_d;
-            if (val > best) { best = val; bo = o; bs = -1; }
-          }
+          if (co > 0.0 && cr_gt(co, bo_d, best)) { best = co / bo_d; bo = o; bs = -1; }
         } else {
           while (circ) {
             const int s2 = __ffsll((long long)circ) - 1;
@@ -303,8 +302,7 @@ __device__ __forceinline__ void scd_user(const SweepArgs &a, int M, int K, int L
               const double cs = ptl[s2 * 64 + lane] + add_s;
               const double num = co - cs;
               const double den = bo_d - bs_d;
-              const double val = num / den;
-              if (val > best) { best = val; bo = o; bs = s2; }
+              if (cr_gt(num, den, best)) { best = num / den; bo = o; bs = s2; }
             }
           }
         }

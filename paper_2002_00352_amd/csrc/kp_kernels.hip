@@ -651,11 +651,12 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
                   const uint64_t m = a.tree.mask[l];
                   if ((m >> o & 1) && popc64(S & m) >= a.tree.cap[l]) { circ = S & m; tight = true; break; }
                 }
+                // candidates are compared with the running maximum through
+                // cr_gt (fma residuals), so a division is only taken for a
+                // crossing that beats it: the same decisions as comparing
+                // the divided crossings
                 if (!tight) {
-                  if (co > 0.0) {
-                    const double val = co / bo_d;
-                    if (val > best) { best = val; bo = o; bs = -1; }
-                  }
+                  if (co > 0.0 && cr_gt(co, bo_d, best)) { best = co / bo_d; bo = o; bs = -1; }
                 } else {
                   while (circ) {
                     const int s = __ffsll((long long)circ) - 1;
@@ -667,8 +668,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
                       const double cs = zu[s] + add_s;
                       const double num = co - cs;
                       const double den = bo_d - bs_d;
-                      const double val = num / den;
-                      if (val > best) { best = val; bo = o; bs = s; }
+                      if (cr_gt(num, den, best)) { best = num / den; bo = o; bs = s; }
                     }
                   }
                 }
