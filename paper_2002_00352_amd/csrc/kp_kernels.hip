@@ -378,6 +378,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
       for (int r = tid; r < nr; r += NT) {
         double accp = (double)pl[r];
         const float *br = bt + (size_t)r * K;
+        #pragma unroll 4
         for (int k = 0; k < K; ++k) {
           const double prod = lam[k] * (double)br[k];
           accp = accp - prod;
@@ -413,6 +414,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
       const double *z = pt + u * M;
       const double zj = z[j];
       int rank = 0, rank1 = 0;
+      #pragma unroll 4
       for (int jj = 0; jj < M; ++jj) {
         const double zz = z[jj];
         const int beats = (zz > zj) || (zz == zj && jj < j);
@@ -437,6 +439,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
       const int u = tid;
       const double *z = pt + u * M;
       uint64_t pos = 0;
+      #pragma unroll 4
       for (int j = 0; j < M; ++j) if (z[j] > 0.0) pos |= 1ull << j;
       const uint64_t S = fastsel ? Sm[u] : greedy_mask(perm + u * M, M, pos, a.tree);
       Sm[u] = S;
@@ -532,6 +535,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
       }
       double Pi = 0.0, Gi = 0.0;
       const float *pp = pl + u * M;
+      #pragma unroll 4
       for (int j = 0; j < M; ++j) {
         if (S >> j & 1) { Pi = Pi + (double)pp[j]; Gi = Gi + z[j]; }
       }
@@ -550,8 +554,11 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
       const uint64_t S0 = Sm[u];
       const float *bu = bt + (size_t)u * M * K;
       double v = 0.0;
-      for (int j = 0; j < M; ++j)
-        if (S0 >> j & 1) v = v + (double)bu[j * K + k];
+      #pragma unroll 4
+      for (int j = 0; j < M; ++j) {
+        const float bj = bu[j * K + k];
+        if (S0 >> j & 1) v = v + (double)bj;
+      }
       vk[q] = v;
       if (a.uv_out) {
         const int col = a.kv_map[k];
@@ -565,6 +572,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
           const double *zu = pt + u * M;
           uint64_t A = 0;   // moving lines: b_jk > 0
           float bmk = 0.0f;
+          #pragma unroll 4
           for (int j = 0; j < M; ++j) {
             const float bj = bu[j * K + k];
             if (bj > 0.0f) A |= 1ull << j;
@@ -694,6 +702,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
     if (a.want_stats) {
       for (int k = tid; k < K; k += NT) {
         double s = 0.0;
+        #pragma unroll 4
         for (int u = 0; u < nu; ++u) s = s + vk[u * K + k];
         acc[k] = acc[k] + s;
       }
