@@ -104,12 +104,14 @@ __device__ __forceinline__ bool far_window_single(const double *zu, const float 
     return zu[j] - s;
   };
   double zmax = 0.0;
+  #pragma unroll 4
   for (int j = 0; j < M; ++j) {
     const double z = moved(j);
     if (z > -Hs) zmax = fmax(zmax, fabs(z));
   }
   const double bound = r * bmk * (1.0 + 0x1p-30) + 0x1p-36 * (1.0 + zmax + Hs + (lk + fabs(dl) + r) * bmk);
   uint64_t sel = 0;
+  #pragma unroll 4
   for (int j = 0; j < M; ++j) {
     if (m1 >> j & 1) continue;
     const double z = moved(j);
@@ -122,6 +124,7 @@ __device__ __forceinline__ bool far_window_single(const double *zu, const float 
   for (int round = 0; round <= c1; ++round) {
     double best = -INFINITY;
     int bj = -1;
+    #pragma unroll 4
     for (int j = 0; j < M; ++j) {
       if (!(m1 >> j & 1) || (inT >> j & 1)) continue;
       const double z = moved(j);
@@ -141,6 +144,7 @@ __device__ __forceinline__ bool far_window_single(const double *zu, const float 
   if (nt > 0 && !(minT > bound)) return false;
   if (nt < c1) {
     // room is left: no moving member outside T may turn positive
+    #pragma unroll 4
     for (int j = 0; j < M; ++j) {
       if (!(m1 >> j & 1) || (inT >> j & 1) || !(A >> j & 1)) continue;
       if (!(moved(j) < -bound)) return false;
@@ -148,6 +152,7 @@ __device__ __forceinline__ bool far_window_single(const double *zu, const float 
   }
   sel |= inT;
   double sum = 0.0;
+  #pragma unroll 4
   for (int j = 0; j < M; ++j)
     if ((sel >> j & 1) && (A >> j & 1)) sum = sum + (double)bu[j * K + k];
   *cw = sum;
@@ -372,6 +377,9 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
     // selection in the rank phase; the users' masks start empty
     const bool fastsel = a.tree.L <= 1;
     if (fastsel && tid < nu) Sm[tid] = 0ull;
+    // window filter: every user's largest cost, gathered by the rank phase
+    // as the bits of a non-negative float in its gap slot
+    if (SCD && tid < nu) ((unsigned int *)ugap)[4 * tid] = 0u;
     __syncthreads();
     // ---- phase A: scores ----
     if (FMT == 0) {
@@ -422,6 +430,16 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
         rank1 += beats & (int)(m1 >> jj & 1);
       }
       perm[u * M + rank] = (uint8_t)j;
+      if (SCD && kcorr[K] > 0.0) {
+        // largest positive cost of the row (0 if none): the maximum below
+        // is taken over the users' rows as unsigned bits, which order like
+        // the floats for positive values
+        const float *br = bt + (size_t)r * K;
+        float mx = 0.0f;
+        #pragma unroll 4
+        for (int k = 0; k < K; ++k) mx = br[k] > mx ? br[k] : mx;
+        if (mx > 0.0f) atomicMax((unsigned int *)ugap + 4 * u, __float_as_uint(mx));
+      }
       // Alg.1 with at most one set: a positive item is kept unless it is in
       // the set behind cap better members of it (those are positive too)
       if (fastsel && zj > 0.0 && (!(m1 >> j & 1) || rank1 < c1))
@@ -509,9 +527,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
         // window filter of this user: the smallest gap between its p~ (in
         // rank order) and between them and zero, over the lines that can
         // turn positive inside the widest window
-        float bm = 0.0f;
+        const float bm = __uint_as_float(((const unsigned int *)ugap)[4 * u]);
         const float *bu = bt + (size_t)u * M * K;
-        for (int e = 0; e < M * K; ++e) bm = bu[e] > bm ? bu[e] : bm;
         const double hm = kcorr[K];
         const double H = hm * (double)bm * (1.0 + 0x1p-30) + 0x1p-36 * (1.0 + (double)bm * hm);
         double gmin = 1e300, prev = 0.0;
