@@ -571,10 +571,16 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
       const uint64_t S0 = Sm[u];
       const float *bu = bt + (size_t)u * M * K;
       double v = 0.0;
+      uint64_t A = 0;     // SCD: moving lines, b_jk > 0
+      float bmk = 0.0f;   // SCD: their largest cost
       #pragma unroll 4
       for (int j = 0; j < M; ++j) {
         const float bj = bu[j * K + k];
         if (S0 >> j & 1) v = v + (double)bj;
+        if (SCD) {
+          if (bj > 0.0f) A |= 1ull << j;
+          bmk = bj > bmk ? bj : bmk;
+        }
       }
       vk[q] = v;
       if (a.uv_out) {
@@ -587,14 +593,6 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
             mode == KS_REFINE || mode == KS_EMIT_RANGE || mode == KS_WINDOW) {
           const double lk = lam[k];
           const double *zu = pt + u * M;
-          uint64_t A = 0;   // moving lines: b_jk > 0
-          float bmk = 0.0f;
-          #pragma unroll 4
-          for (int j = 0; j < M; ++j) {
-            const float bj = bu[j * K + k];
-            if (bj > 0.0f) A |= 1ull << j;
-            bmk = bj > bmk ? bj : bmk;
-          }
           bool walk = A != 0;
           if (walk && mode == KS_WINDOW) {
             // no breakpoint of this user inside the window: nothing to emit
