@@ -83,8 +83,8 @@ __device__ __forceinline__ void issue_entries(Prefetch &f, const ProbDev &pr, in
 // m1 with cap c1, or no set), for any M, in O(M c1) with no per-item
 // state: items outside the set are selected when positive, so a moving one
 // must keep its sign over the window; inside the set the selection at c is
-// the c1 best positive members T (picked by repeated maxima, ties to the
-// lower index), and it stays the same when T stays positive and the best
+// the c1 best positive members T (picked by repeated maxima, two per pass
+// over the set, ties to the lower index), and it stays the same when T stays positive and the best
 // other member stays below T (one gap: every pair across it moves against
 // each other by at most r bmax), or, when fewer than c1 members are
 // positive, when no moving member outside T can turn positive.  Returns
@@ -103,43 +103,60 @@ __device__ __forceinline__ bool far_window_single(const double *zu, const float 
     const double s = dl * b;
     return zu[j] - s;
   };
-  double zmax = 0.0;
+  // one pass: zmax, the selection outside the set (whose moving members
+  // must keep their sign: the smallest |z'| among those that may be
+  // positive is checked against the bound below) and the two best members
+  // of the set (z' desc, index asc)
+  double zmax = 0.0, nearz = INFINITY;
+  bool anyn = false;
+  uint64_t sel = 0;
+  double v1 = -INFINITY, v2 = -INFINITY;
+  int j1 = -1, j2 = -1;
   #pragma unroll 4
   for (int j = 0; j < M; ++j) {
     const double z = moved(j);
     if (z > -Hs) zmax = fmax(zmax, fabs(z));
+    if (m1 >> j & 1) {
+      if (z > v1) { v2 = v1; j2 = j1; v1 = z; j1 = j; }
+      else if (z > v2) { v2 = z; j2 = j; }
+    } else {
+      if ((A >> j & 1) && z > -Hs) { nearz = fmin(nearz, fabs(z)); anyn = true; }
+      if (z > 0.0) sel |= 1ull << j;
+    }
   }
   const double bound = r * bmk * (1.0 + 0x1p-30) + 0x1p-36 * (1.0 + zmax + Hs + (lk + fabs(dl) + r) * bmk);
-  uint64_t sel = 0;
-  #pragma unroll 4
-  for (int j = 0; j < M; ++j) {
-    if (m1 >> j & 1) continue;
-    const double z = moved(j);
-    if ((A >> j & 1) && z > -Hs && !(fabs(z) > bound)) return false;   // may change sign
-    if (z > 0.0) sel |= 1ull << j;
-  }
+  if (anyn && !(nearz > bound)) return false;   // may change sign
+  // T: the c1 best positive members, taken two per pass over the set (the
+  // second best of a pass is the best once the first has joined T)
   uint64_t inT = 0;
   int nt = 0;
   double minT = INFINITY;
-  for (int round = 0; round <= c1; ++round) {
-    double best = -INFINITY;
-    int bj = -1;
+  for (;;) {
+    bool done = false;
+    for (int h = 0; h < 2 && !done; ++h) {
+      const double best = h == 0 ? v1 : v2;
+      const int bj = h == 0 ? j1 : j2;
+      if (bj < 0) { done = true; break; }
+      if (nt < c1 && best > 0.0) {
+        inT |= 1ull << bj;
+        minT = best;
+        ++nt;
+        continue;
+      }
+      // bj: the best member outside T
+      if (nt == c1 && best > -Hs && !(minT - best > bound)) return false;
+      done = true;
+    }
+    if (done) break;
+    v1 = -INFINITY; v2 = -INFINITY;
+    j1 = -1; j2 = -1;
     #pragma unroll 4
     for (int j = 0; j < M; ++j) {
       if (!(m1 >> j & 1) || (inT >> j & 1)) continue;
       const double z = moved(j);
-      if (z > best) { best = z; bj = j; }
+      if (z > v1) { v2 = v1; j2 = j1; v1 = z; j1 = j; }
+      else if (z > v2) { v2 = z; j2 = j; }
     }
-    if (bj < 0) break;
-    if (round < c1 && best > 0.0) {
-      inT |= 1ull << bj;
-      minT = best;
-      ++nt;
-      continue;
-    }
-    // bj: the best member outside T
-    if (nt == c1 && best > -Hs && !(minT - best > bound)) return false;
-    break;
   }
   if (nt > 0 && !(minT > bound)) return false;
   if (nt < c1) {
@@ -152,9 +169,10 @@ __device__ __forceinline__ bool far_window_single(const double *zu, const float 
   }
   sel |= inT;
   double sum = 0.0;
-  #pragma unroll 4
-  for (int j = 0; j < M; ++j)
-    if ((sel >> j & 1) && (A >> j & 1)) sum = sum + (double)bu[j * K + k];
+  for (uint64_t m = sel & A; m; m &= m - 1) {
+    const int j = __ffsll((long long)m) - 1;
+    sum = sum + (double)bu[j * K + k];
+  }
   *cw = sum;
   return true;
 }
@@ -745,7 +763,8 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs a, const TileGeom 
 
 // Batched: blocks [block_off[s], block_off[s+1]) work on instance s, whose
 // arguments are copied into LDS; one launch covers every instance.
-__global__ void __launch_bounds__(NT) k_sweep_batched(const SweepArgs *descs, const TileGeom *geoms,
+// three waves per SIMD (at most 168 VGPRs), as the single-instance kernel
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3, 8))) k_sweep_batched(const SweepArgs *descs, const TileGeom *geoms,
                                                       const int *block_off, int n_inst) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ SweepArgs sa;
