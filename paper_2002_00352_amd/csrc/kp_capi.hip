@@ -16,10 +16,10 @@
 #include "kp_internal.h"
 
 // launchers (kp_kernels.hip)
-size_t kp_sweep_lds_bytes(int U, int M, int K, bool scd, int fmt);
+size_t kp_sweep_lds_bytes(int U, int M, int K, bool scd, int fmt, bool hist = true);
 hipError_t kp_launch_sweep(const SweepArgs &a, int U, int grid, bool scd, hipStream_t stream,
                            int *used);
-int kp_sweep_resident_grid(int U, int M, int K, bool scd, int fmt);
+int kp_sweep_resident_grid(int U, int M, int K, bool scd, int fmt, bool hist = true);
 int kp_sweep_batched_resident(size_t lds);
 hipError_t kp_launch_reduce_stats(const double *partials, int nblk, int K, const double *lam,
                                   const double *B, double *R, double *g, double *P,
@@ -212,6 +212,11 @@ struct Prepared {
   int U = 1;
   int64_t ntiles = 0;
   int grid = 1;
+  // SCD passes in which no knapsack bins events (every search starts with a
+  // window): tiles and grid of the general kernel without the histograms
+  int U_nh = 1;
+  int64_t ntiles_nh = 0;
+  int grid_nh = 1;
   double bytes = 0.0;   // algorithmic input bytes of one sweep launch
   // uniform-row CSR kernel (0 = not used)
   int ell_D = 0;
@@ -219,7 +224,7 @@ struct Prepared {
   int ell_grid = 0;
   int ell_brk_grid = 0;   // smallest grid of the lean kernel's breakpoint launches
   double ell_bytes = 0.0;
-  int stage_grid() const { return std::max(grid, ell_grid); }
+  int stage_grid() const { return std::max(std::max(grid, grid_nh), ell_grid); }
 };
 
 kp_status prepare(const kp_problem *p, bool scd, Prepared &out, const Ctx *ctx = nullptr) {
@@ -314,6 +319,7 @@ kp_status prepare(const kp_problem *p, bool scd, Prepared &out, const Ctx *ctx =
       grid_override = it->second.second;
     }
   }
+  const int U0 = U;
   while (U > 1 && kp_sweep_lds_bytes(U, M, p->K, scd, p->b_format) > 64 * 1024) --U;
   if (kp_sweep_lds_bytes(U, M, p->K, scd, p->b_format) > kMaxLds)
     return fail(KP_ERR_UNSUPPORTED, "M*K = %d too large for one tile", M * p->K);
@@ -334,6 +340,22 @@ kp_status prepare(const kp_problem *p, bool scd, Prepared &out, const Ctx *ctx =
   if (p->N > 0) {
     const int res = kp_sweep_resident_grid(U, M, p->K, scd, p->b_format);
     if (res > 0) out.grid = std::min(out.grid, res);
+  }
+  out.U_nh = out.U;
+  out.ntiles_nh = out.ntiles;
+  out.grid_nh = out.grid;
+  if (scd && p->N > 0) {
+    // without the K x 64 histogram bins a tile can hold more users, and more
+    // blocks fit on a compute unit
+    int Un = U0;
+    while (Un > 1 && kp_sweep_lds_bytes(Un, M, p->K, true, p->b_format, false) > 64 * 1024) --Un;
+    const int64_t nt = (p->N + Un - 1) / Un;
+    int g = (int)std::max<int64_t>(1, std::min<int64_t>(nt, grid_override > 0 ? grid_override : kMaxGrid));
+    const int res = kp_sweep_resident_grid(Un, M, p->K, true, p->b_format, false);
+    if (res > 0) g = std::min(g, res);
+    out.U_nh = Un;
+    out.ntiles_nh = nt;
+    out.grid_nh = g;
   }
   return KP_OK;
 }
@@ -455,7 +477,8 @@ kp_status carve_ws(Ctx *c, const Prepared &P, bool scd, SweepWs &w) {
   // pairs so that large window passes do not overflow
   uint32_t scap = 0;
   if (scd) {
-    const int blocks = P.ell_D ? P.ell_brk_grid : P.stage_grid();
+    // (sized for the general kernel's smaller grid, the one with histograms)
+    const int blocks = P.ell_D ? P.ell_brk_grid : P.grid;
     const double share = (double)P.pr.N * K / std::max(1, blocks) / 64.0;
     scap = (uint32_t)std::min<double>(kStageCapMax, std::max<double>(kStageCap, share));
   }
@@ -533,6 +556,7 @@ double algo_bytes(const Prepared &P) {
 // uniform-row kernel as two launches (all users, then the listed ones).
 hipError_t timed_sweep(Ctx *c, const SweepArgs &a, const Prepared &P, bool scd, double bytes,
                        bool split = false) {
+  // a.no_hist: the general kernel's tiles and grid without histograms
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (c->timing && P.ell_D) {
     bytes = P.ell_bytes;
@@ -573,7 +597,8 @@ hipError_t timed_sweep(Ctx *c, const SweepArgs &a, const Prepared &P, bool scd, 
     ae.ntiles = P.ell_ntiles;
     err = kp_launch_ell(ae, P.ell_D, P.ell_grid, scd ? 1 : 0, c->stream, &c->stats_grid);
   } else {
-    err = kp_launch_sweep(a, P.U, P.grid, scd, c->stream, &c->stats_grid);
+    err = a.no_hist ? kp_launch_sweep(a, P.U_nh, P.grid_nh, scd, c->stream, &c->stats_grid)
+                    : kp_launch_sweep(a, P.U, P.grid, scd, c->stream, &c->stats_grid);
   }
   if (c->timing && e0 && e1) {
     (void)hipEventRecord(e1, c->stream);
@@ -754,12 +779,16 @@ kp_status kp_scd_sweep_masked(void *ctx, const kp_problem *prob, const double *l
                              c->delta_valid ? 1 : 0, window, c->stream));
   // the first pass runs split (all users, then the listed ones) when every
   // knapsack still searching starts with a window
-  bool split = false;
-  if (window && c->delta_valid && w.fcap) {
+  // (uniform-row kernel); the general kernel runs such a pass without the
+  // histograms of the other search modes
+  bool split = false, nohist = false;
+  const bool nh_gain = !P.ell_D && (P.U_nh != P.U || P.grid_nh != P.grid);
+  if (window && c->delta_valid && (w.fcap || nh_gain)) {
     HIP_TRY(kp_launch_count_modes(w.st, K, w.modes, c->stream));
     HIP_TRY(hipMemcpyAsync(c->pinned + 20, w.modes, 8, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
-    split = c->pinned[20] > 0 && c->pinned[21] == 0;
+    split = w.fcap && c->pinned[20] > 0 && c->pinned[21] == 0;
+    nohist = nh_gain && c->pinned[21] == 0;
   }
   HIP_TRY(hipMemsetAsync(w.stat, 0, w.stat_bytes, c->stream));   // status, histograms
   double *Rd = R ? R : w.Rtmp;
@@ -771,6 +800,10 @@ kp_status kp_scd_sweep_masked(void *ctx, const kp_problem *prob, const double *l
     if (P.pr.N > 0) {
       SweepArgs a = make_args(P, lambda_in, w, nullptr, pass == 0);
       a.pass = pass;
+      if (pass == 0 && nohist) {
+        a.no_hist = 1;
+        a.ntiles = P.ntiles_nh;
+      }
       HIP_TRY(timed_sweep(c, a, P, true, P.bytes, split && pass == 0));
     }
     if (pass == 0) {

@@ -150,7 +150,7 @@ __device__ __forceinline__ void publish_block(const SweepArgs &a, int K, double 
                                               uint32_t *kcnt, uint32_t *kpos, uint32_t *kovf,
                                               uint32_t *nstage, int tid, int nthreads, int bid,
                                               const double *kcorr = nullptr) {
-  for (int t = tid; t < K * KP_NB; t += nthreads) {
+  for (int t = tid; hc && t < K * KP_NB; t += nthreads) {
     if (hc[t]) {
       atomicAdd(&a.hist_sum[t], hs[t]);
       atomicAdd(&a.hist_cnt[t], hc[t]);

@@ -85,6 +85,7 @@ struct SweepArgs {
   int64_t ntiles;
   // statistics (first pass only)
   int want_stats;
+  int no_hist;             // SCD: no knapsack bins events (no EXP / REFINE mode): no histograms in LDS
   double *partials;        // [gridDim.x][K + 2]
   uint8_t *x_out;          // [N*M] or null
   // SCD

@@ -270,6 +270,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
   KState *kst = SCD ? (KState *)carve((size_t)K * sizeof(KState)) : nullptr;
   double *hs = nullptr;
   uint32_t *hc = nullptr;
+  const bool hist = !a.no_hist;   // histograms (exponential buckets, refinement bins) in LDS
   int *kmode = nullptr;
   uint32_t *kcnt = nullptr, *kpos = nullptr, *kovf = nullptr, *nstage = nullptr;
   unsigned long long *hmin = nullptr, *hmax = nullptr;
@@ -277,8 +278,10 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
   if (SCD) {
     kcorr = (double *)carve((size_t)K * 8 + 8);   // [K] window corrections, [K] widest window
     ugap = (double *)carve((size_t)U * 16);        // per user: gap and scale of the window filter
-    hs = (double *)carve((size_t)K * KP_NB * 8);
-    hc = (uint32_t *)carve((size_t)K * KP_NB * 4);
+    if (hist) {
+      hs = (double *)carve((size_t)K * KP_NB * 8);
+      hc = (uint32_t *)carve((size_t)K * KP_NB * 4);
+    }
     kmode = (int *)carve((size_t)K * 4);
     kcnt = (uint32_t *)carve((size_t)K * 4);
     kpos = (uint32_t *)carve((size_t)K * 4);
@@ -291,7 +294,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
   for (int t = tid; t < K; t += NT) lam[t] = a.lam[t];
   if (SCD) {
     for (int t = tid; t < K; t += NT) kst[t] = a.st[t];
-    for (int t = tid; t < K * KP_NB; t += NT) { hs[t] = 0.0; hc[t] = 0u; }
+    if (hist)
+      for (int t = tid; t < K * KP_NB; t += NT) { hs[t] = 0.0; hc[t] = 0u; }
     for (int t = tid; t < K; t += NT) {
       kmode[t] = a.st[t].mode;
       kcnt[t] = 0u;
@@ -612,6 +616,10 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
           const double lk = lam[k];
           const double *zu = pt + u * M;
           bool walk = A != 0;
+          if (walk && !hist && (mode == KS_EXP || mode == KS_REFINE)) {
+            atomicAdd(a.err, 1ull);   // launched without the histograms these modes need
+            walk = false;
+          }
           if (walk && mode == KS_WINDOW) {
             // no breakpoint of this user inside the window: nothing to emit
             // and its consumption just above the window is v_ik (no correction)
@@ -1820,7 +1828,7 @@ void kp_coldesc_fill(void *dst, const double *partials, const double *lam, const
 // ---------------------------------------------------------------------------
 // host-side launch helpers (called from the C ABI)
 // ---------------------------------------------------------------------------
-size_t kp_sweep_lds_bytes(int U, int M, int K, bool scd, int fmt) {
+size_t kp_sweep_lds_bytes(int U, int M, int K, bool scd, int fmt, bool hist = true) {
   auto r16 = [](size_t b) { return (b + 15) & ~(size_t)15; };
   const size_t R = (size_t)U * M, Q = (size_t)U * K;
   size_t s = r16(R * K * 4) + r16(R * 8) + r16(R) + r16((size_t)U * 8) * 2 + r16(Q * 8) +
@@ -1830,8 +1838,8 @@ size_t kp_sweep_lds_bytes(int U, int M, int K, bool scd, int fmt) {
   if (scd) s += r16(R);                            // per-item threshold elements
   if (fmt == 1) s += 2 * r16((size_t)NT * ECH * 4);  // staged CSR entries
   if (scd)
-    s += r16((size_t)K * sizeof(KState)) + r16((size_t)K * KP_NB * 8) +
-         r16((size_t)K * KP_NB * 4) + 4 * r16((size_t)K * 4) + 2 * r16((size_t)K * 8) + r16(16) +
+    s += r16((size_t)K * sizeof(KState)) + (hist ? r16((size_t)K * KP_NB * 8) + r16((size_t)K * KP_NB * 4) : 0) +
+         4 * r16((size_t)K * 4) + 2 * r16((size_t)K * 8) + r16(16) +
          r16((size_t)K * 8 + 8) + r16((size_t)U * 16);   // window corrections, per-user filter
   return s;
 }
@@ -1850,8 +1858,8 @@ int kp_sweep_batched_resident(size_t lds) {
 }
 
 // Blocks of the general sweep kernel that can be resident at once (0 if unknown).
-int kp_sweep_resident_grid(int U, int M, int K, bool scd, int fmt) {
-  const size_t lds = kp_sweep_lds_bytes(U, M, K, scd, fmt);
+int kp_sweep_resident_grid(int U, int M, int K, bool scd, int fmt, bool hist = true) {
+  const size_t lds = kp_sweep_lds_bytes(U, M, K, scd, fmt, hist);
   const void *fn = fmt == 0 ? (scd ? (const void *)k_sweep<0, true> : (const void *)k_sweep<0, false>)
                             : (scd ? (const void *)k_sweep<1, true> : (const void *)k_sweep<1, false>);
   if (lds > 64 * 1024 && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
@@ -1872,7 +1880,7 @@ hipError_t kp_launch_sweep(const SweepArgs &a, int U, int grid, bool scd, hipStr
   g.K = a.pr.K;
   g.aligned = a.pr.fmt == 0 && ((uintptr_t)a.pr.b & 15) == 0 &&
               (((int64_t)U * g.M * g.K) & 3) == 0;
-  const size_t lds = kp_sweep_lds_bytes(U, g.M, g.K, scd, a.pr.fmt);
+  const size_t lds = kp_sweep_lds_bytes(U, g.M, g.K, scd, a.pr.fmt, !(scd && a.no_hist));
   const void *fn = a.pr.fmt == 0 ? (scd ? (const void *)k_sweep<0, true> : (const void *)k_sweep<0, false>)
                                  : (scd ? (const void *)k_sweep<1, true> : (const void *)k_sweep<1, false>);
   if (lds > 64 * 1024) {
