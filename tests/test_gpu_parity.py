@@ -659,12 +659,15 @@ def test_batched_plan_window_trajectory():
 @pytest.mark.parametrize("name,mk", [
     ("c2-dense-N3000", lambda: kpgen.config_instance(2, N=3000)),
     ("c5-inst-dense", lambda: kpgen.batched_instances(run=0, n=40, max_N=6000)[39]),
-], ids=["c2-dense-N3000", "c5-inst-dense"])
+    ("c4-dense-K50-N2000", lambda: kpgen.config_instance(4, N=2000)),
+], ids=["c2-dense-N3000", "c5-inst-dense", "c4-dense-K50-N2000"])
 def test_scd_alternating_trajectory(name, mk):
     """Dense instances whose synchronous iterations alternate between two
     multiplier vectors: searches that start with a window around the
     multiplier of two iterations back (and the general kernel's window pass)
-    keep every update equal to the oracle's, window on and off."""
+    keep every update equal to the oracle's, window on and off.  With K = 50
+    the histogram bins limit the general kernel's tile (4 users of M = 20);
+    its window passes run without them, on 8-user tiles."""
     kp, torch = _kp()
     print("case", name, flush=True)
     inst = mk()
