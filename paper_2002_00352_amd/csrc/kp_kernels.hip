@@ -399,6 +399,11 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
     // selection in the rank phase; the users' masks start empty
     const bool fastsel = a.tree.L <= 1;
     if (fastsel && tid < nu) Sm[tid] = 0ull;
+    // with at most one set the threshold elements follow from two items per
+    // user, found by the rank phase: [0] the set's lowest selected member
+    // (set full) and [1] its best positive member left out
+    const bool fastau = SCD && fastsel && M >= 2;
+    if (fastau && tid < nu) { tau[tid * M] = -1; tau[tid * M + 1] = -1; }
     // window filter: every user's largest cost, gathered by the rank phase
     // as the bits of a non-negative float in its gap slot
     if (SCD && tid < nu) ((unsigned int *)ugap)[4 * tid] = 0u;
@@ -466,6 +471,10 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
       // the set behind cap better members of it (those are positive too)
       if (fastsel && zj > 0.0 && (!(m1 >> j & 1) || rank1 < c1))
         atomicOr((unsigned long long *)&Sm[u], 1ull << j);
+      if (fastau && zj > 0.0 && (m1 >> j & 1)) {
+        if (rank1 == c1 - 1) tau[u * M] = (int8_t)j;
+        else if (rank1 == c1) tau[u * M + 1] = (int8_t)j;
+      }
     }
     // CSR: the next tile's entry range is known now that its row offsets have
     // landed; start those loads too
@@ -484,7 +493,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
       const uint64_t S = fastsel ? Sm[u] : greedy_mask(perm + u * M, M, pos, a.tree);
       Sm[u] = S;
       Pm[u] = pos;
-      if (SCD) {
+      if (SCD && !fastau) {
         // Threshold element of every item o against the greedy solution G_o of
         // the other items (their order does not depend on lambda_k when o is
         // the only item that moves with it): o is selected exactly when its
@@ -671,7 +680,11 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
                 // one moving line: its only breakpoint is where it crosses its
                 // threshold element (a horizontal line) or the zero level
                 const int o = __ffsll((long long)A) - 1;
-                const int th = tau[u * M + o];
+                // with one set: the lowest selected member when o is out,
+                // the best member left out when o is in (set full), else zero
+                const int th = !fastau ? (int)tau[u * M + o]
+                               : (!(m1 >> o & 1) || tau[u * M] < 0) ? -1
+                               : (int)tau[u * M + ((S0 >> o & 1) ? 1 : 0)];
                 const double bo_d = (double)bu[o * K + k];
                 const double add_o = lk * bo_d;
                 const double co = zu[o] + add_o;
