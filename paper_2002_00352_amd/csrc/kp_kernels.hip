@@ -404,9 +404,13 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
     // (set full) and [1] its best positive member left out
     const bool fastau = SCD && fastsel && M >= 2;
     if (fastau && tid < nu) { tau[tid * M] = -1; tau[tid * M + 1] = -1; }
-    // window filter: every user's largest cost, gathered by the rank phase
-    // as the bits of a non-negative float in its gap slot
-    if (SCD && tid < nu) ((unsigned int *)ugap)[4 * tid] = 0u;
+    // window filter, per user: [0] the smallest gap (a minimum over the
+    // rows, taken on the bits of non-negative doubles), [1] the largest cost
+    // (a maximum over the rows, on the bits of a non-negative float)
+    if (SCD && tid < nu) {
+      ((unsigned long long *)ugap)[2 * tid] = (unsigned long long)__double_as_longlong(1e300);
+      ((unsigned int *)ugap)[4 * tid + 2] = 0u;
+    }
     __syncthreads();
     // ---- phase A: scores ----
     if (FMT == 0) {
@@ -465,7 +469,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
         float mx = 0.0f;
         #pragma unroll 4
         for (int k = 0; k < K; ++k) mx = br[k] > mx ? br[k] : mx;
-        if (mx > 0.0f) atomicMax((unsigned int *)ugap + 4 * u, __float_as_uint(mx));
+        if (mx > 0.0f) atomicMax((unsigned int *)ugap + 4 * u + 2, __float_as_uint(mx));
       }
       // Alg.1 with at most one set: a positive item is kept unless it is in
       // the set behind cap better members of it (those are positive too)
@@ -554,33 +558,6 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
           tu[o] = -1;
         }
       }
-      if (SCD && kcorr[K] > 0.0) {
-        // window filter of this user: the smallest gap between its p~ (in
-        // rank order) and between them and zero, over the lines that can
-        // turn positive inside the widest window
-        const float bm = __uint_as_float(((const unsigned int *)ugap)[4 * u]);
-        const float *bu = bt + (size_t)u * M * K;
-        const double hm = kcorr[K];
-        const double H = hm * (double)bm * (1.0 + 0x1p-30) + 0x1p-36 * (1.0 + (double)bm * hm);
-        double gmin = 1e300, prev = 0.0;
-        const double top = z[perm[u * M]];
-        for (int r = 0; r < M; ++r) {
-          const double v = z[perm[u * M + r]];
-          if (!(v > -H)) break;
-          gmin = fabs(v) < gmin ? fabs(v) : gmin;
-          if (r > 0) {
-            // two identical lines (equal p~ and equal costs in every
-            // knapsack, e.g. the copies of a categorical item) never cross
-            bool same = prev == v;
-            const float *ba = bu + (size_t)perm[u * M + r - 1] * K, *bb = bu + (size_t)perm[u * M + r] * K;
-            for (int k = 0; same && k < K; ++k) same = ba[k] == bb[k];
-            if (!same) gmin = prev - v < gmin ? prev - v : gmin;
-          }
-          prev = v;
-        }
-        ugap[2 * u] = gmin;
-        ugap[2 * u + 1] = fabs(top) + H;
-      }
       double Pi = 0.0, Gi = 0.0;
       const float *pp = pl + u * M;
       #pragma unroll 4
@@ -593,6 +570,34 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
       if (a.x_out) {
         uint8_t *xo = a.x_out + (u0 + u) * M;
         for (int j = 0; j < M; ++j) xo[j] = (uint8_t)(S >> j & 1);
+      }
+    }
+    if (SCD && kcorr[K] > 0.0) {
+      // window filter, one thread per rank position: the smallest gap
+      // between a user's p~ in rank order and between them and zero, over
+      // the lines that can turn positive inside the widest window (ranks
+      // descend, so those are a prefix of the ranks); two identical lines
+      // (equal p~ and equal costs in every knapsack, e.g. the copies of a
+      // categorical item) never cross
+      const double hm = kcorr[K];
+      for (int q = tid; q < nr; q += NT) {
+        const int u = q / M, rr = q - u * M;
+        const float bm = __uint_as_float(((const unsigned int *)ugap)[4 * u + 2]);
+        const double H = hm * (double)bm * (1.0 + 0x1p-30) + 0x1p-36 * (1.0 + (double)bm * hm);
+        const double *z = pt + u * M;
+        const int jv = perm[u * M + rr];
+        const double v = z[jv];
+        if (!(v > -H)) continue;
+        double c = fabs(v);
+        if (rr > 0) {
+          const int jp = perm[u * M + rr - 1];
+          const double prev = z[jp];
+          bool same = prev == v;
+          const float *ba = bt + ((size_t)u * M + jp) * K, *bb = bt + ((size_t)u * M + jv) * K;
+          for (int k = 0; same && k < K; ++k) same = ba[k] == bb[k];
+          if (!same) c = prev - v < c ? prev - v : c;
+        }
+        atomicMin((unsigned long long *)ugap + 2 * u, (unsigned long long)__double_as_longlong(c));
       }
     }
     __syncthreads();
@@ -633,7 +638,13 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
             // no breakpoint of this user inside the window: nothing to emit
             // and its consumption just above the window is v_ik (no correction)
             double cw = 0.0;
-            if (window_calm(ugap[2 * u], ugap[2 * u + 1], kst[k].hw, (double)bmk, lk)) {
+            // the filter's scale: |top p~| + H, with H from the user's
+            // largest cost and the widest window
+            const float bmu = __uint_as_float(((const unsigned int *)ugap)[4 * u + 2]);
+            const double hm = kcorr[K];
+            const double Hu = hm * (double)bmu * (1.0 + 0x1p-30) + 0x1p-36 * (1.0 + (double)bmu * hm);
+            const double gscale = fabs(zu[perm[u * M]]) + Hu;
+            if (window_calm(ugap[2 * u], gscale, kst[k].hw, (double)bmk, lk)) {
               walk = false;
             } else if (a.tree.L <= 1
                            ? far_window_single(zu, bu, M, K, k, A, lk, kst[k].wlo, kst[k].whi, (double)bmk,
