@@ -558,11 +558,13 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
           tu[o] = -1;
         }
       }
+      // sums over the selected items in ascending index order
       double Pi = 0.0, Gi = 0.0;
       const float *pp = pl + u * M;
-      #pragma unroll 4
-      for (int j = 0; j < M; ++j) {
-        if (S >> j & 1) { Pi = Pi + (double)pp[j]; Gi = Gi + z[j]; }
+      for (uint64_t m = S; m; m &= m - 1) {
+        const int j = __ffsll((long long)m) - 1;
+        Pi = Pi + (double)pp[j];
+        Gi = Gi + z[j];
       }
       uPG[2 * u] = Pi;
       uPG[2 * u + 1] = Gi;
@@ -609,14 +611,17 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
       double v = 0.0;
       uint64_t A = 0;     // SCD: moving lines, b_jk > 0
       float bmk = 0.0f;   // SCD: their largest cost
-      #pragma unroll 4
-      for (int j = 0; j < M; ++j) {
-        const float bj = bu[j * K + k];
-        if (S0 >> j & 1) v = v + (double)bj;
-        if (SCD) {
+      if (SCD) {
+        #pragma unroll 4
+        for (int j = 0; j < M; ++j) {
+          const float bj = bu[j * K + k];
+          if (S0 >> j & 1) v = v + (double)bj;
           if (bj > 0.0f) A |= 1ull << j;
           bmk = bj > bmk ? bj : bmk;
         }
+      } else {
+        // the selected items only, in ascending index order
+        for (uint64_t m = S0; m; m &= m - 1) v = v + (double)bu[(__ffsll((long long)m) - 1) * K + k];
       }
       vk[q] = v;
       if (a.uv_out) {
@@ -625,8 +630,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
       }
       if (SCD) {
         const int mode = kmode[k];
-        if (mode == KS_EXP || mode == KS_EMIT_BUCKET || mode == KS_HULL_BUCKET ||
-            mode == KS_REFINE || mode == KS_EMIT_RANGE || mode == KS_WINDOW) {
+        if (walk_mode(mode)) {
           const double lk = lam[k];
           const double *zu = pt + u * M;
           bool walk = A != 0;
