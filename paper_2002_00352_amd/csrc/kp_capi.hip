@@ -1608,10 +1608,31 @@ kp_status plan_create(Ctx *c, const kp_problem *probs, int n, const double *cons
   hipStream_t st = c->stream;
   auto up = [&](void *dst, const void *src, size_t bytes) { return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st); };
   hipError_t e = hipSuccess;
+  // block layout: instances with the costliest tiles first, so that their
+  // blocks start early and cheap ones fill the tail of the launch; every
+  // table indexed by position follows the same order
+  std::vector<int> ord(n);
+  for (int s = 0; s < n; ++s) ord[s] = s;
+  auto tile_cost = [&](int s) {
+    const Prepared &q = P[s];
+    const double c1 = q.tree.L == 1 ? (double)q.tree.cap[0] : (double)q.pr.M;
+    return (double)q.U * q.pr.M * q.pr.K * (1.0 + c1);
+  };
+  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return tile_cost(x) > tile_cost(y); });
+  std::vector<int> bpos(n + 1, 0);
+  std::vector<SweepArgs> pd[2][2];
+  std::vector<TileGeom> pg(n);
+  for (int d = 0; d < 2; ++d) for (int f = 0; f < 2; ++f) pd[d][f].resize(n);
+  for (int i = 0; i < n; ++i) {
+    const int si = ord[i];
+    bpos[i + 1] = bpos[i] + (boff[si + 1] - boff[si]);
+    for (int d = 0; d < 2; ++d) for (int f = 0; f < 2; ++f) pd[d][f][i] = hd[d][f][si];
+    pg[i] = hg[si];
+  }
   for (int d = 0; d < 2 && e == hipSuccess; ++d)
-    for (int f = 0; f < 2 && e == hipSuccess; ++f) e = up(p->d[d][f], hd[d][f].data(), (size_t)n * sizeof(SweepArgs));
-  if (e == hipSuccess) e = up(p->geom, hg.data(), (size_t)n * sizeof(TileGeom));
-  if (e == hipSuccess) e = up(p->boff, boff.data(), (size_t)(n + 1) * 4);
+    for (int f = 0; f < 2 && e == hipSuccess; ++f) e = up(p->d[d][f], pd[d][f].data(), (size_t)n * sizeof(SweepArgs));
+  if (e == hipSuccess) e = up(p->geom, pg.data(), (size_t)n * sizeof(TileGeom));
+  if (e == hipSuccess) e = up(p->boff, bpos.data(), (size_t)(n + 1) * 4);
   if (e == hipSuccess) e = up(p->koff, koff.data(), (size_t)(n + 1) * 4);
   if (e == hipSuccess) e = up(p->Bf, hB.data(), (size_t)Kf * 8);
   if (e == hipSuccess) e = up(p->kin, kin.data(), (size_t)Kf * 4);
