@@ -1211,10 +1211,11 @@ struct BatchPlan {
   std::vector<int64_t> ntiles;
   std::vector<double> pairs;      // users x knapsacks of every instance
   std::vector<size_t> ilds;       // LDS of every instance's tiles
+  std::vector<int> order;         // instances by decreasing tile cost (the block layout's order)
 };
 
 // Split of a later pass: the instances whose knapsacks still search share
-// every block (in proportion to their tiles), and the staging area of the
+// every block (in proportion to their tiles, costliest tiles first), and the staging area of the
 // whole launch is divided among their blocks.  Returns the number of active
 // instances (0: nothing to sweep).
 int plan_resplit(BatchPlan *p, int dir, int *blocks, size_t *lds) {
@@ -1222,7 +1223,7 @@ int plan_resplit(BatchPlan *p, int dir, int *blocks, size_t *lds) {
   const int *flag = p->pinned + 16;
   std::vector<int> act;
   int64_t TA = 0;
-  for (int s = 0; s < n; ++s)
+  for (int s : p->order)
     if (flag[s] && p->ntiles[s] > 0) { act.push_back(s); TA += p->ntiles[s]; }
   const int na = (int)act.size();
   if (na == 0) return 0;
@@ -1653,6 +1654,7 @@ kp_status plan_create(Ctx *c, const kp_problem *probs, int n, const double *cons
   }
   for (int d = 0; d < 2; ++d) p->hd[d] = hd[d][0];
   p->hg = hg;
+  p->order = ord;
   *out = p;
   return KP_OK;
 }
