@@ -1396,9 +1396,9 @@ kp_status plan_create(Ctx *c, const kp_problem *probs, int n, const double *cons
   // blocks are split among the instances in proportion to their tiles; many
   // more blocks than can be resident at once keep the split fine-grained, and
   // the hardware dispatcher balances them (every instance gets at least one)
-  int gmax = 8192;
+  int gmax = 32768;
   const int res = kp_sweep_batched_resident(lds);
-  if (res > 0) gmax = std::min(gmax, 16 * res);
+  if (res > 0) gmax = std::min(gmax, 64 * res);
   const int G = (int)std::max<int64_t>(n, std::min<int64_t>(T, gmax));
   // algorithmic bytes of one pass over every instance
   double bytes = 0.0;
