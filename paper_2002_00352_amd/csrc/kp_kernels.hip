@@ -84,12 +84,12 @@ __device__ __forceinline__ void issue_entries(Prefetch &f, const ProbDev &pr, in
 // state: items outside the set are selected when positive, so a moving one
 // must keep its sign over the window; inside the set the selection at c is
 // the c1 best positive members T (picked by repeated maxima, two per pass
-// over the set, ties to the lower index), and it stays the same when T stays positive and the best
-// other member stays below T (one gap: every pair across it moves against
-// each other by at most r bmax), or, when fewer than c1 members are
-// positive, when no moving member outside T can turn positive.  Returns
-// false when the test does not apply or fails; else true with *cw = the
-// selection's consumption of k.
+// over the set, ties to the lower index), and it stays the same when T
+// stays positive and the best other member stays below T (one gap: every
+// pair across it moves against each other by at most r bmax), or, when
+// fewer than c1 members are positive, when no moving member outside T can
+// turn positive.  Returns false when the test does not apply or fails; else
+// true with *cw = the selection's consumption of k.
 __device__ __forceinline__ bool far_window_single(const double *zu, const float *bu, int M, int K, int k,
                                                   uint64_t A, double lk, double wlo, double whi, double bmk,
                                                   uint64_t m1, int c1, double *cw) {
@@ -799,7 +799,7 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs a, const TileGeom 
 
 // Batched: blocks [block_off[s], block_off[s+1]) work on instance s, whose
 // arguments are copied into LDS; one launch covers every instance.
-// three waves per SIMD (at most 168 VGPRs), as the single-instance kernel
+// at most 168 VGPRs: three waves per SIMD
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3, 8))) k_sweep_batched(const SweepArgs *descs, const TileGeom *geoms,
                                                       const int *block_off, int n_inst) {
   extern __shared__ __align__(16) unsigned char smem[];
