@@ -581,6 +581,43 @@ def test_full_size_autograd_sampled_parity():
     assert np.array_equal(xg, ref["x"])
 
 
+@gpu
+def test_full_size_batched_matches_plain():
+    """The batched workload at full size (256 instances, 37M users) in the
+    benchmark's launch configuration (graph-replayed plan, cost-ordered block
+    layout, later passes re-split): every iteration's multipliers equal the
+    plain per-instance sweeps' bit for bit, and sampled users of three
+    instances take the oracle's decisions at the last multipliers."""
+    kp, torch = _kp()
+    from kpgen import device as kgd
+    print("batched workload full size", flush=True)
+    data = kgd.device_batched(0, 256)
+    probs = [kp.Problem(a["p"], B, tree.parent, tree.cap, tree.leaf_of_item, b=a["b"], N=m["N"], M=m["M"],
+                        K=m["K"]) for a, B, tree, m in data]
+    plan = kp.BatchedSCD(probs)
+    ctxs = [kp.Context() for _ in probs]
+    lams = [torch.zeros(pr.K, dtype=torch.float64, device="cuda") for pr in probs]
+    for t in range(5):
+        outs, _ = plan.step()
+        torch.cuda.synchronize()
+        for s, pr in enumerate(probs):
+            lams[s] = kp.kp_scd_sweep(pr, lams[s], ctx=ctxs[s])["lam"]
+        torch.cuda.synchronize()
+        for s in range(len(probs)):
+            assert torch.equal(outs[s], lams[s]), (t, s)
+        print("iteration", t, "equal", flush=True)
+    plan.close()
+    rng = np.random.default_rng(11)
+    for s in (0, 39, 128):
+        a, B, tree, m = data[s]
+        ev = kp.kp_eval_dual(probs[s], lams[s], want_x=True, ctx=ctxs[s])
+        users = np.sort(rng.choice(m["N"], min(2048, m["N"]), replace=False))
+        sub = kgd.host_users(m, B, tree, users)
+        ref = oracle.eval_dual(sub, lams[s].cpu().numpy())
+        xg = ev["x"].view(m["N"], m["M"])[torch.from_numpy(users).cuda()].cpu().numpy().reshape(-1)
+        assert np.array_equal(xg, ref["x"]), s
+
+
 PRESOLVE_CASES = [
     ("c3-N20000-n2000", lambda: kpgen.config_instance(3, N=20000), 2000),
     ("c1-dense-n1000", lambda: kpgen.config_instance(1), 1000),
