@@ -514,7 +514,7 @@ def _full_size_problem(kp, c):
 
 
 @gpu
-@pytest.mark.parametrize("c", [3, 2])
+@pytest.mark.parametrize("c", [3, 2, 4])
 def test_full_size_scd_sampled_parity(c):
     """At the benchmark's full size and launch configuration: decisions of
     sampled users equal the oracle's, g - P = lambda.(B - R), and every SCD
