@@ -321,7 +321,8 @@ def main():
         cap[np.asarray(tree.leaf_of_item)] = 2
     prob = kp.Problem(arrs["p"], B, tree.parent, cap, tree.leaf_of_item, b=arrs.get("b"),
                       rowptr=arrs.get("rowptr"), col=arrs.get("col"), val=arrs.get("val"),
-                      N=meta["N"], M=meta["M"], K=meta["K"])
+                      N=meta["N"], M=meta["M"], K=meta["K"],
+                      row_nnz=meta["csr_d"] if meta["csr_d"] else None)
     if args.workload == "c3cat":
         from paper_2002_00352_amd import categorical
         prob = categorical.expand(prob).binary

@@ -72,6 +72,13 @@ typedef struct {
   const int32_t *parent;      /* HOST [L], -1 = root, else a node id in [0,L) */
   const int32_t *cap;         /* HOST [L], >= 1 */
   const int32_t *leaf_of_item;/* HOST [M], innermost node containing item j, or -1 */
+  int32_t b_row_nnz;          /* CSR only: 0 = general rows; D in {1, 2} = the caller declares that
+                                 every item row holds exactly D stored entries, row r's at
+                                 [r*D, r*D + D) (rowptr[r] == r*D).  With M <= 16 the library then
+                                 runs a lean per-user kernel that never reads b_rowptr.
+                                 kp_csr_row_nnz finds D; kp_validate_inputs checks a declared D.
+                                 A false declaration is undefined behaviour, like an unsorted row.
+                                 Must be 0 for dense costs. */
 } kp_problem;
 
 /* Message for the last non-OK status returned on this thread. */
@@ -165,6 +172,11 @@ kp_status kp_batched_create(void *ctx, const kp_problem *probs, int32_t n,
                             const double *const *lam_a, double *const *lam_b, void **plan_out);
 kp_status kp_batched_step(void *plan, int32_t dir, double *stats, int32_t use_graph);
 kp_status kp_batched_destroy(void *plan);
+/* Launch shape of a batched plan's first pass: blocks, LDS bytes per block,
+   and the smallest and largest users per tile over its instances.  HOST
+   outputs, each may be NULL. */
+kp_status kp_batched_shape(void *plan, int32_t *blocks, int32_t *lds_bytes, int32_t *min_users_per_tile,
+                           int32_t *max_users_per_tile);
 
 /* Pre-solving by sampling (Sec. 5.3): SCD iterations on the sub-instance of
    the sampled users, with every budget scaled by n/N (B_k * (n / N) in
@@ -179,7 +191,8 @@ kp_status kp_presolve(void *ctx, const kp_problem *prob, const int64_t *users, i
 
 /* Optional full pass over p and b: KP_ERR_NONFINITE / KP_ERR_NEGATIVE if any
    value is NaN/Inf or negative, KP_OK otherwise (a CSR column outside [0,K) or
-   not ascending is KP_ERR_INVALID).  Synchronises the context stream. */
+   not ascending, or a declared b_row_nnz that some row does not meet, is
+   KP_ERR_INVALID).  Synchronises the context stream. */
 kp_status kp_validate_inputs(void *ctx, const kp_problem *prob);
 
 /* Host helper: explicit local sets {S_l, C_l} (set_offsets HOST [L+1] into
@@ -206,21 +219,42 @@ kp_status kp_get_timing(void *ctx, double *sweep_ms_total, int64_t *sweep_launch
 
 /* Tile-size override for one problem shape (M, K, b_format): users per tile
    and grid size (blocks) used by every later call on this context for that
-   shape; 0 keeps the built-in choice, (0, 0) removes the override.  x, lambda
-   and R do not depend on these values; g and P are FP64 sums whose grouping
-   follows the grid, so their last bits may.  Used by the autotuner. */
+   shape; 0 keeps the built-in choice, (0, 0) removes the override.  The
+   general kernel takes both (users per tile capped by its LDS); the
+   uniform-row kernel takes the grid only (one lane per user, 64 users per
+   wave); batched plans created later take the users per tile of each
+   instance's shape.  Grids are capped at the blocks that can be resident.
+   x, lambda and R do not depend on these values; g and P are FP64 sums whose
+   grouping follows the grid, so their last bits may.  Used by the autotuner. */
 kp_status kp_set_tuning(void *ctx, int32_t M, int32_t K, int32_t b_format, int32_t users_per_tile,
                         int32_t grid);
+/* Shape of the last sweep launch made through this context: kernel (0 the
+   general kernel, 1 the uniform-row kernel, -1 none yet), users per tile and
+   blocks launched.  HOST outputs, each may be NULL. */
+kp_status kp_get_launch_shape(void *ctx, int32_t *kernel, int32_t *users_per_tile, int32_t *grid);
+/* Tuning of batched plans created later on this context: LDS bytes per block
+   of the batched launch (instances with long rows take fewer users per tile
+   to fit it; 0 = 40 KB) and blocks per block that can be resident (the
+   finer the split, the better the dispatcher balances ragged instances;
+   0 = 64).  Results do not depend on these values (g and P up to the
+   grouping of their FP64 sums). */
+kp_status kp_set_batched_tuning(void *ctx, int32_t lds_bytes, int32_t block_mult);
 
-/* Kernel choice for CSR costs: when every item row holds the same number of
-   stored entries (1 or 2) at offsets r*D and M <= 16, a lean per-user kernel
-   is used that never reads b_rowptr during sweeps.  The structure check reads
-   b_rowptr once and is cached per (b_rowptr, N*M) in the context;
-   kp_forget_structure clears that cache (call it after rewriting a rowptr
-   array in place).  kp_set_kernel_choice(ctx, 0) forces the general kernel
-   (results are identical either way). */
+/* Kernel choice for CSR costs: a problem that declares b_row_nnz = D (every
+   item row holds D in {1, 2} entries at r*D) with M <= 16 runs the lean
+   per-user kernel, which never reads b_rowptr; any other CSR problem runs
+   the general kernel.  The library keeps no record of a problem's structure
+   between calls: the declaration travels with the problem.
+   kp_set_kernel_choice(ctx, 0) forces the general kernel for declared
+   problems too (results are identical either way). */
 kp_status kp_set_kernel_choice(void *ctx, int32_t allow_uniform_rows);
-kp_status kp_forget_structure(void *ctx);
+
+/* Structure query for per-item CSR costs (Sec. 2 layout): *D_out = D when
+   every row r of the N*M item rows holds exactly D in {1, 2} stored entries
+   at [r*D, r*D + D) (b_rowptr[r] == r*D for r = 0..N*M), else 0.  Reads
+   b_rowptr once on the device (8 bytes per item row); b_row_nnz of prob is
+   ignored.  D_out: HOST.  Synchronises the context stream. */
+kp_status kp_csr_row_nnz(void *ctx, const kp_problem *prob, int32_t *D_out);
 
 /* Threshold search of kp_scd_sweep (Alg.4 reduce, located near the
    previous multiplier).  After one sweep on a context, each

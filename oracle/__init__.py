@@ -248,16 +248,6 @@ def alg5_map_user(inst, lam, i, Q):
     return kk[:n], v1[:n], v2[:n]
 
 
-def metrics(g, P_hat, R, B):
-    """Duality gap (absolute and relative to the feasible primal) and the max
-    constraint-violation ratio."""
-    R = np.asarray(R, np.float64)
-    B = np.asarray(B, np.float64)
-    gap = g - P_hat
-    return dict(gap_abs=gap, gap_rel=gap / abs(P_hat) if P_hat != 0 else float("inf"),
-                max_viol=float(np.max(np.maximum(R - B, 0.0) / B)) if len(B) else 0.0)
-
-
 def presolve(inst, users, max_iter=100, lam0=None):
     """Pre-solving by sampling (Sec. 5.3): SCD on the sub-instance of the
     sampled users with every budget scaled by n / N, from lam0 until the

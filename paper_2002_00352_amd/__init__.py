@@ -30,6 +30,7 @@ STATUS = {0: "KP_OK", -1: "KP_ERR_INVALID", -2: "KP_ERR_NOT_LAMINAR", -3: "KP_ER
           -4: "KP_ERR_NEGATIVE", -5: "KP_ERR_UNSUPPORTED", -6: "KP_ERR_NOMEM", -7: "KP_ERR_HIP",
           -8: "KP_ERR_INTERNAL"}
 KP_B_DENSE, KP_B_CSR = 0, 1
+KP_ERR_INVALID, KP_ERR_UNSUPPORTED = -1, -5
 
 
 def build() -> str:
@@ -65,7 +66,7 @@ class kp_problem(ctypes.Structure):
         ("p", ctypes.c_void_p), ("b_format", ctypes.c_int32), ("b", ctypes.c_void_p),
         ("b_rowptr", ctypes.c_void_p), ("b_col", ctypes.c_void_p), ("b_val", ctypes.c_void_p),
         ("B", ctypes.c_void_p), ("L", ctypes.c_int32), ("parent", ctypes.c_void_p),
-        ("cap", ctypes.c_void_p), ("leaf_of_item", ctypes.c_void_p),
+        ("cap", ctypes.c_void_p), ("leaf_of_item", ctypes.c_void_p), ("b_row_nnz", ctypes.c_int32),
     ]
 
 
@@ -75,8 +76,9 @@ EXPORTS = ["kp_last_error", "kp_create", "kp_destroy", "kp_set_stream", "kp_eval
            "kp_primal_fixup", "kp_scd_sweep_batched", "kp_validate_inputs", "kp_tree_from_sets",
            "kp_max_items", "kp_max_knapsacks_scd", "kp_set_timing", "kp_get_timing",
            "kp_batched_create", "kp_batched_step", "kp_batched_destroy", "kp_set_tuning",
-           "kp_set_kernel_choice", "kp_forget_structure", "kp_set_window",
-           "kp_get_window_stats", "kp_presolve", "kp_get_window_listed"]
+           "kp_set_kernel_choice", "kp_csr_row_nnz", "kp_set_window",
+           "kp_get_window_stats", "kp_presolve", "kp_get_window_listed", "kp_get_launch_shape",
+           "kp_set_batched_tuning", "kp_batched_shape"]
 
 
 def lib():
@@ -106,12 +108,15 @@ def lib():
         L.kp_batched_destroy.argtypes = [vp]
         L.kp_set_tuning.argtypes = [vp, i32, i32, i32, i32, i32]
         L.kp_set_kernel_choice.argtypes = [vp, i32]
-        L.kp_forget_structure.argtypes = [vp]
+        L.kp_csr_row_nnz.argtypes = [vp, P, ctypes.POINTER(i32)]
         L.kp_set_window.argtypes = [vp, i32]
         L.kp_presolve.argtypes = [vp, P, vp, i64, i32, vp, ctypes.POINTER(i32)]
         L.kp_get_window_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64),
                                           ctypes.POINTER(i64), ctypes.POINTER(i64)]
         L.kp_get_window_listed.argtypes = [vp, ctypes.POINTER(i64)]
+        L.kp_get_launch_shape.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.kp_set_batched_tuning.argtypes = [vp, i32, i32]
+        L.kp_batched_shape.argtypes = [vp] + [ctypes.POINTER(i32)] * 4
         L.kp_set_timing.argtypes = [vp, i32]
         L.kp_get_timing.argtypes = [vp, vp, vp, vp]
         L.kp_max_items.restype = i32
@@ -163,6 +168,16 @@ class Context:
     def set_tuning(self, M: int, K: int, b_format: int, users_per_tile: int, grid: int):
         _check(lib().kp_set_tuning(self.h, M, K, b_format, users_per_tile, grid))
 
+    def launch_shape(self):
+        """(kernel, users per tile, blocks) of the last sweep launch: kernel 0
+        is the general kernel, 1 the uniform-row kernel, -1 none yet."""
+        k, u, g = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().kp_get_launch_shape(self.h, ctypes.byref(k), ctypes.byref(u), ctypes.byref(g)))
+        return k.value, u.value, g.value
+
+    def set_batched_tuning(self, lds_bytes: int, block_mult: int):
+        _check(lib().kp_set_batched_tuning(self.h, int(lds_bytes), int(block_mult)))
+
     def set_kernel_choice(self, allow_uniform_rows: bool):
         _check(lib().kp_set_kernel_choice(self.h, 1 if allow_uniform_rows else 0))
 
@@ -209,10 +224,16 @@ def default_context() -> Context:
 
 class Problem:
     """Device-resident instance: p, b (dense or CSR) as torch tensors on the
-    GPU; B and the local-constraint forest on the host."""
+    GPU; B and the local-constraint forest on the host.
+
+    row_nnz (CSR only): the entries every item row holds at offsets r*D
+    (1 or 2), 0 for general rows, or None to ask the library
+    (kp_csr_row_nnz, one device pass over rowptr at construction).  The
+    declaration lets the lean per-user kernel skip rowptr; it stays valid as
+    long as the arrays this object holds are not rewritten in place."""
 
     def __init__(self, p, B, parent, cap, leaf_of_item, *, b=None, rowptr=None, col=None,
-                 val=None, N=None, M=None, K=None):
+                 val=None, N=None, M=None, K=None, row_nnz=None):
         import torch
         self.p = p
         self.b, self.rowptr, self.col, self.val = b, rowptr, col, val
@@ -232,7 +253,12 @@ class Problem:
         s.B = _ptr(self.B)
         s.L = len(self.parent)
         s.parent, s.cap, s.leaf_of_item = _ptr(self.parent), _ptr(self.cap), _ptr(self.leaf)
+        s.b_row_nnz = 0
         self.s = s
+        if b is None and row_nnz is None:
+            row_nnz = kp_csr_row_nnz(self)
+        self.row_nnz = 0 if b is not None else int(row_nnz)
+        s.b_row_nnz = self.row_nnz
 
     @property
     def ref(self):
@@ -357,6 +383,13 @@ class BatchedSCD:
         _check(lib().kp_batched_create(self.ctx.h, arr, n, pa, pb, ctypes.byref(self.h)))
         self.stats = _dev_f64(sum(pr.K + 2 for pr in self.probs))
 
+    def shape(self):
+        """(blocks, LDS bytes per block, min and max users per tile) of the
+        plan's first pass."""
+        v = [ctypes.c_int32() for _ in range(4)]
+        _check(lib().kp_batched_shape(self.h, *[ctypes.byref(x) for x in v]))
+        return tuple(x.value for x in v)
+
     @property
     def lam(self):
         """Current multipliers (the buffer the last step wrote)."""
@@ -391,6 +424,15 @@ def kp_presolve(prob: Problem, users, lam, max_iter: int = 30, ctx: Optional[Con
     _check(lib().kp_presolve(ctx.h, prob.ref, u.ctypes.data, len(u), int(max_iter),
                              _ptr(lam), ctypes.byref(it)))
     return lam, it.value
+
+
+def kp_csr_row_nnz(prob: Problem, ctx: Optional[Context] = None) -> int:
+    """D when every item row of the CSR costs holds D in {1, 2} entries at
+    r*D, else 0 (one device pass over rowptr)."""
+    ctx = ctx or default_context()
+    D = ctypes.c_int32()
+    _check(lib().kp_csr_row_nnz(ctx.h, prob.ref, ctypes.byref(D)))
+    return D.value
 
 
 def kp_validate_inputs(prob: Problem, ctx: Optional[Context] = None):

@@ -120,15 +120,17 @@ struct Ctx {
   double sweep_ms = 0.0;
   int64_t sweep_launches = 0;
   double sweep_bytes = 0.0;
-  const int64_t *nnz_rowptr = nullptr;
-  int64_t nnz_rows = -1, nnz = 0;
   // tuned tile sizes per shape (M, K, format) -> (users per tile, grid)
   std::map<std::tuple<int, int, int>, std::pair<int, int>> tuning;
-  // uniform-row CSR structure found per (rowptr, rows): entries per row, or 0
-  std::map<std::pair<const int64_t *, int64_t>, std::pair<int, int64_t>> ell;
   bool ell_enabled = true;
   bool window_enabled = true;
   int stats_grid = 0;     // blocks of the last sweep launch (slots of the per-block partials)
+  // shape of the last sweep launch: kernel (0 general, 1 uniform-row), users
+  // per tile, blocks
+  int last_kernel = -1, last_U = 0, last_grid = 0;
+  // batched plans created later: LDS per block and blocks per resident block
+  // (0: built-in)
+  int bt_lds = 0, bt_mult = 0;
   std::map<std::tuple<int, int, int, int>, std::pair<int, int>> ell_grids;  // (D, M, K, L) -> resident grids
   int64_t win_tried = 0, win_above = 0, win_below = 0;   // window searches since creation
   int64_t win_emitted = 0;                                 // breakpoints emitted inside windows
@@ -218,6 +220,7 @@ struct Prepared {
   int64_t ntiles_nh = 0;
   int grid_nh = 1;
   double bytes = 0.0;   // algorithmic input bytes of one sweep launch
+  int row_nnz = 0;        // declared entries per CSR item row (0: general rows)
   // uniform-row CSR kernel (0 = not used)
   int ell_D = 0;
   int64_t ell_ntiles = 0;
@@ -237,6 +240,9 @@ kp_status prepare(const kp_problem *p, bool scd, Prepared &out, const Ctx *ctx =
     return fail(KP_ERR_UNSUPPORTED, "K = %d exceeds the SCD limit %d", p->K, KP_MAX_K_SCD);
   if (p->b_format != KP_B_DENSE && p->b_format != KP_B_CSR)
     return fail(KP_ERR_INVALID, "b_format must be KP_B_DENSE or KP_B_CSR");
+  if (p->b_row_nnz != 0 && (p->b_format != KP_B_CSR || (p->b_row_nnz != 1 && p->b_row_nnz != 2)))
+    return fail(KP_ERR_INVALID, "b_row_nnz must be 0, or 1 or 2 with CSR costs (got %d)", p->b_row_nnz);
+  out.row_nnz = p->b_row_nnz;
   if (p->N > 0) {
     if (!p->p) return fail(KP_ERR_INVALID, "p is NULL");
     if (p->b_format == KP_B_DENSE && !p->b) return fail(KP_ERR_INVALID, "b is NULL");
@@ -362,48 +368,14 @@ kp_status prepare(const kp_problem *p, bool scd, Prepared &out, const Ctx *ctx =
 
 constexpr int kEllGrid = 1024;
 
-// Decide whether the uniform-row CSR kernel applies: CSR, M <= 16, every item
-// row holding the same D in {1, 2} entries at r*D (checked once on the device
-// per rowptr array and cached), and its LDS fits.
+// Decide whether the uniform-row CSR kernel applies: CSR declared with D in
+// {1, 2} entries per item row at r*D (b_row_nnz), M <= 16, and its LDS fits.
 kp_status choose_kernel(Ctx *c, Prepared &P, bool scd) {
   P.ell_D = 0;
   P.ell_grid = 0;
-  if (!c->ell_enabled || P.pr.fmt != KP_B_CSR || P.pr.M > 16 || P.pr.N == 0) return KP_OK;
-  const int64_t nrows = P.pr.N * P.pr.M;
-  const auto key = std::make_pair(P.pr.rowptr, nrows);
-  auto it = c->ell.find(key);
-  int D = 0;
-  int64_t nnz = 0;
-  if (it != c->ell.end()) {
-    D = it->second.first;
-    nnz = it->second.second;
-  } else {
-    if (!c->pinned) {
-      if (hipHostMalloc((void **)&c->pinned, 256, hipHostMallocDefault) != hipSuccess) {
-        c->pinned = nullptr;
-        return fail(KP_ERR_HIP, "hipHostMalloc failed");
-      }
-    }
-    int64_t *h = (int64_t *)(c->pinned + 8);
-    HIP_TRY(hipMemcpyAsync(h, P.pr.rowptr + nrows, 8, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    nnz = *h;
-    if (nnz > 0 && nnz % nrows == 0 && nnz / nrows <= 2) {
-      const int Dc = (int)(nnz / nrows);
-      Carve cv;
-      size_t ob = cv.take(16);
-      kp_status s = ensure_ws(c, std::max(cv.off, c->ws_cap));
-      if (s != KP_OK) return s;
-      unsigned int *bad = (unsigned int *)((char *)c->ws + ob);
-      HIP_TRY(hipMemsetAsync(bad, 0, 4, c->stream));
-      HIP_TRY(kp_launch_ell_check(P.pr.rowptr, nrows, Dc, bad, c->stream));
-      HIP_TRY(hipMemcpyAsync(c->pinned + 12, bad, 4, hipMemcpyDeviceToHost, c->stream));
-      HIP_TRY(hipStreamSynchronize(c->stream));
-      if (c->pinned[12] == 0) D = Dc;
-    }
-    c->ell[key] = std::make_pair(D, nnz);
-  }
-  if (D == 0) return KP_OK;
+  if (!c->ell_enabled || P.pr.fmt != KP_B_CSR || P.pr.M > 16 || P.pr.N == 0 || P.row_nnz == 0) return KP_OK;
+  const int D = P.row_nnz;
+  const int64_t nnz = P.pr.N * P.pr.M * (int64_t)D;
   if (kp_ell_lds_bytes(P.pr.M, P.pr.K, D, P.tree.L, scd ? 1 : 0, nullptr) > kMaxLds) return KP_OK;
   P.ell_D = D;
   P.ell_ntiles = (P.pr.N + 63) / 64;
@@ -426,8 +398,43 @@ kp_status choose_kernel(Ctx *c, Prepared &P, bool scd) {
     c->ell_grids[gkey] = std::make_pair(gmax, gbrk);
   }
   P.ell_grid = (int)std::max<int64_t>(1, std::min<int64_t>((P.ell_ntiles + 3) / 4, std::min(gmax, kEllGrid)));
+  // a tuned grid for this shape (the kernel's users per tile are fixed: one
+  // lane per user, 64 per wave); never above what can be resident
+  auto tit = c->tuning.find(std::make_tuple((int)P.pr.M, (int)P.pr.K, (int)KP_B_CSR));
+  if (tit != c->tuning.end() && tit->second.second > 0)
+    P.ell_grid = std::max(1, std::min(tit->second.second, gmax));
   P.ell_brk_grid = std::max(1, std::min(gbrk, P.ell_grid));
   P.ell_bytes = (double)P.pr.N * P.pr.M * 4.0 + (double)nnz * 8.0;   // rowptr is not read
+  return KP_OK;
+}
+
+// Does every one of the nrows item rows hold exactly D in {1, 2} entries at
+// r*D?  *D_out = D, or 0.  Reads rowptr[nrows] and then (when the count fits)
+// every offset on the device; synchronous.
+kp_status check_rows(Ctx *c, const int64_t *rowptr, int64_t nrows, unsigned int *D_out) {
+  *D_out = 0;
+  if (!c->pinned) {
+    if (hipHostMalloc((void **)&c->pinned, 256, hipHostMallocDefault) != hipSuccess) {
+      c->pinned = nullptr;
+      return fail(KP_ERR_HIP, "hipHostMalloc failed");
+    }
+  }
+  int64_t *h = (int64_t *)(c->pinned + 8);
+  HIP_TRY(hipMemcpyAsync(h, rowptr + nrows, 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  const int64_t nnz = *h;
+  if (!(nnz > 0 && nnz % nrows == 0 && nnz / nrows <= 2)) return KP_OK;
+  const int Dc = (int)(nnz / nrows);
+  Carve cv;
+  const size_t ob = cv.take(16);
+  kp_status s = ensure_ws(c, std::max(cv.off, c->ws_cap));
+  if (s != KP_OK) return s;
+  unsigned int *bad = (unsigned int *)((char *)c->ws + ob);
+  HIP_TRY(hipMemsetAsync(bad, 0, 4, c->stream));
+  HIP_TRY(kp_launch_ell_check(rowptr, nrows, Dc, bad, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->pinned + 12, bad, 4, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (c->pinned[12] == 0) *D_out = (unsigned int)Dc;
   return KP_OK;
 }
 
@@ -561,18 +568,16 @@ hipError_t timed_sweep(Ctx *c, const SweepArgs &a, const Prepared &P, bool scd, 
   if (c->timing && P.ell_D) {
     bytes = P.ell_bytes;
   } else if (c->timing && P.pr.fmt == KP_B_CSR && P.pr.N > 0) {
-    // stored entries (col + val, 8 bytes each) -- read once per rowptr array
+    // stored entries (col + val, 8 bytes each): the count is declared, or
+    // read from rowptr[N*M] (only while timing is on)
     const int64_t nrows = P.pr.N * P.pr.M;
-    if (c->nnz_rowptr != P.pr.rowptr || c->nnz_rows != nrows) {
-      int64_t nnz = 0;
+    int64_t nnz = nrows * (int64_t)P.row_nnz;
+    if (!P.row_nnz) {
       hipError_t e = hipMemcpyAsync(&nnz, P.pr.rowptr + nrows, 8, hipMemcpyDeviceToHost, c->stream);
       if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
       if (e != hipSuccess) return e;
-      c->nnz_rowptr = P.pr.rowptr;
-      c->nnz_rows = nrows;
-      c->nnz = nnz;
     }
-    bytes += (double)c->nnz * 8.0;
+    bytes += (double)nnz * 8.0;
   }
   if (c->timing) {
     e0 = take_event(c);
@@ -606,6 +611,11 @@ hipError_t timed_sweep(Ctx *c, const SweepArgs &a, const Prepared &P, bool scd, 
     c->sweep_launches += 1;
     c->sweep_bytes += bytes;
     if (c->ev_pending.size() > 256) drain_events(c, true);
+  }
+  if (err == hipSuccess) {
+    c->last_kernel = P.ell_D ? 1 : 0;
+    c->last_U = P.ell_D ? 64 : (a.no_hist ? P.U_nh : P.U);
+    c->last_grid = c->stats_grid;
   }
   return err;
 }
@@ -936,7 +946,6 @@ kp_status kp_presolve(void *ctx, const kp_problem *prob, const int64_t *users, i
   if (rs == KP_OK && cur != lambda_inout)
     HIP_TRY(hipMemcpyAsync(lambda_inout, cur, (size_t)K * 8, hipMemcpyDeviceToDevice, c->stream));
   (void)hipStreamSynchronize(c->stream);
-  if (csr) c->ell.erase(std::make_pair((const int64_t *)sub.b_rowptr, n * (int64_t)M));
   c->delta_valid = false;
   if (rs != KP_OK) return rs;
   if (iterations_out) *iterations_out = it;
@@ -965,11 +974,20 @@ kp_status kp_validate_inputs(void *ctx, const kp_problem *prob) {
     HIP_TRY(hipStreamSynchronize(c->stream));
     HIP_TRY(kp_launch_validate(prob->b_val, nnz, flags, c->stream));
     HIP_TRY(kp_launch_validate_csr(prob->b_rowptr, prob->b_col, nrows, prob->K, flags, c->stream));
+    if (prob->b_row_nnz && nrows > 0 && nnz != nrows * (int64_t)prob->b_row_nnz) {
+      (void)hipStreamSynchronize(c->stream);
+      return fail(KP_ERR_INVALID, "b_row_nnz = %d declared, but rowptr[N*M] = %lld", prob->b_row_nnz,
+                  (long long)nnz);
+    }
+    if (prob->b_row_nnz && nrows > 0)
+      HIP_TRY(kp_launch_ell_check(prob->b_rowptr, nrows, prob->b_row_nnz, flags + 3, c->stream));
   }
-  HIP_TRY(hipMemcpyAsync(c->pinned, flags, 12, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->pinned, flags, 16, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   const unsigned int *f = (const unsigned int *)c->pinned;
   if (f[2]) return fail(KP_ERR_INVALID, "CSR rows must have ascending columns in [0,K)");
+  if (f[3]) return fail(KP_ERR_INVALID, "b_row_nnz = %d declared, but some row does not hold its entries at r*D",
+                        prob->b_row_nnz);
   if (f[0]) return fail(KP_ERR_NONFINITE, "p or b holds a NaN or Inf");
   if (f[1]) return fail(KP_ERR_NEGATIVE, "p or b holds a negative value");
   return KP_OK;
@@ -1040,6 +1058,26 @@ kp_status kp_set_tuning(void *ctx, int32_t M, int32_t K, int32_t b_format, int32
   return KP_OK;
 }
 
+kp_status kp_get_launch_shape(void *ctx, int32_t *kernel, int32_t *users_per_tile, int32_t *grid) {
+  if (!ctx) return fail(KP_ERR_INVALID, "ctx is NULL");
+  const Ctx *c = (const Ctx *)ctx;
+  if (kernel) *kernel = c->last_kernel;
+  if (users_per_tile) *users_per_tile = c->last_U;
+  if (grid) *grid = c->last_grid;
+  return KP_OK;
+}
+
+kp_status kp_set_batched_tuning(void *ctx, int32_t lds_bytes, int32_t block_mult) {
+  if (!ctx) return fail(KP_ERR_INVALID, "ctx is NULL");
+  if (lds_bytes < 0 || block_mult < 0) return fail(KP_ERR_INVALID, "negative tuning value");
+  if (lds_bytes > (int32_t)kMaxLds) return fail(KP_ERR_UNSUPPORTED, "LDS budget above %zu bytes", kMaxLds);
+  if (block_mult > 1024) return fail(KP_ERR_UNSUPPORTED, "block multiple above 1024");
+  Ctx *c = (Ctx *)ctx;
+  c->bt_lds = lds_bytes;
+  c->bt_mult = block_mult;
+  return KP_OK;
+}
+
 kp_status kp_set_kernel_choice(void *ctx, int32_t allow_uniform_rows) {
   if (!ctx) return fail(KP_ERR_INVALID, "ctx is NULL");
   ((Ctx *)ctx)->ell_enabled = allow_uniform_rows != 0;
@@ -1069,9 +1107,20 @@ kp_status kp_get_window_listed(void *ctx, int64_t *listed) {
   return KP_OK;
 }
 
-kp_status kp_forget_structure(void *ctx) {
+kp_status kp_csr_row_nnz(void *ctx, const kp_problem *prob, int32_t *D_out) {
   if (!ctx) return fail(KP_ERR_INVALID, "ctx is NULL");
-  ((Ctx *)ctx)->ell.clear();
+  if (!prob || !D_out) return fail(KP_ERR_INVALID, "NULL argument");
+  if (prob->b_format != KP_B_CSR) return fail(KP_ERR_INVALID, "kp_csr_row_nnz needs CSR costs");
+  if (prob->N < 0 || prob->M < 1) return fail(KP_ERR_INVALID, "bad N or M");
+  Ctx *c = (Ctx *)ctx;
+  *D_out = 0;
+  const int64_t nrows = prob->N * prob->M;
+  if (nrows == 0) return KP_OK;
+  if (!prob->b_rowptr) return fail(KP_ERR_INVALID, "b_rowptr is NULL");
+  unsigned int D = 0;
+  kp_status s = check_rows(c, prob->b_rowptr, nrows, &D);
+  if (s != KP_OK) return s;
+  *D_out = (int32_t)D;
   return KP_OK;
 }
 
@@ -1172,6 +1221,7 @@ kp_status kp_primal_fixup(void *ctx, const kp_problem *prob, const double *lambd
 struct BatchPlan {
   Ctx *c = nullptr;
   int n = 0, Kf = 0, GB = 0, ncol = 0;
+  int Umin = 0, Umax = 0;   // users per tile over the instances
   double bytes = 0.0;   // algorithmic bytes of one sweep pass over every instance
   int64_t T = 0;
   size_t lds = 0;
@@ -1378,9 +1428,10 @@ kp_status plan_create(Ctx *c, const kp_problem *probs, int n, const double *cons
   // every block of the batched launch gets the largest LDS any instance
   // needs, so instances with long rows take smaller tiles: the launch keeps
   // kBatchedBlocksPerCu blocks per compute unit for everyone
+  const size_t lds_budget = c->bt_lds > 0 ? (size_t)c->bt_lds : kBatchedLds;
   for (auto &q : P) {
     int U = q.U;
-    while (U > 1 && kp_sweep_lds_bytes(U, q.pr.M, q.pr.K, true, q.pr.fmt) > kBatchedLds) --U;
+    while (U > 1 && kp_sweep_lds_bytes(U, q.pr.M, q.pr.K, true, q.pr.fmt) > lds_budget) --U;
     while (U > 1 && q.pr.fmt == KP_B_DENSE && ((int64_t)U * q.pr.M * q.pr.K) % 4 != 0) --U;
     if (U != q.U) {
       q.U = U;
@@ -1398,7 +1449,7 @@ kp_status plan_create(Ctx *c, const kp_problem *probs, int n, const double *cons
   // the hardware dispatcher balances them (every instance gets at least one)
   int gmax = 32768;
   const int res = kp_sweep_batched_resident(lds);
-  if (res > 0) gmax = std::min(gmax, 64 * res);
+  if (res > 0) gmax = std::min(gmax, (c->bt_mult > 0 ? c->bt_mult : 64) * res);
   const int G = (int)std::max<int64_t>(n, std::min<int64_t>(T, gmax));
   // algorithmic bytes of one pass over every instance
   double bytes = 0.0;
@@ -1421,6 +1472,9 @@ kp_status plan_create(Ctx *c, const kp_problem *probs, int n, const double *cons
   }
   if (lds > kMaxLds) { plan_free(p); return fail(KP_ERR_UNSUPPORTED, "an instance needs too much LDS"); }
   p->T = T; p->Kf = Kf; p->GB = boff[n]; p->lds = lds; p->cap = kEmitCapBatched;
+  p->Umin = P[0].U;
+  p->Umax = P[0].U;
+  for (auto &q : P) { p->Umin = std::min(p->Umin, q.U); p->Umax = std::max(p->Umax, q.U); }
   p->bytes = bytes;
   const uint32_t cap = p->cap;
   // emission buffers per instance: room for two breakpoints per user and
@@ -1672,6 +1726,17 @@ kp_status kp_batched_create(void *ctx, const kp_problem *probs, int32_t n, const
 kp_status kp_batched_step(void *plan, int32_t dir, double *stats, int32_t use_graph) {
   if (!plan || (dir != 0 && dir != 1)) return fail(KP_ERR_INVALID, "bad plan or direction");
   return plan_step((BatchPlan *)plan, dir, stats, use_graph != 0);
+}
+
+kp_status kp_batched_shape(void *plan, int32_t *blocks, int32_t *lds_bytes, int32_t *min_users_per_tile,
+                           int32_t *max_users_per_tile) {
+  if (!plan) return fail(KP_ERR_INVALID, "plan is NULL");
+  const BatchPlan *p = (const BatchPlan *)plan;
+  if (blocks) *blocks = p->GB;
+  if (lds_bytes) *lds_bytes = (int32_t)p->lds;
+  if (min_users_per_tile) *min_users_per_tile = p->Umin;
+  if (max_users_per_tile) *max_users_per_tile = p->Umax;
+  return KP_OK;
 }
 
 kp_status kp_batched_destroy(void *plan) {

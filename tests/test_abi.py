@@ -31,7 +31,7 @@ def test_limits():
     assert kp.lib().kp_max_knapsacks_scd() >= 20
 
 
-def _host_problem(N=4, M=3, K=2, B=(1.0, 1.0), parent=(-1,), cap=(1,), leaf=None):
+def _host_problem(N=4, M=3, K=2, B=(1.0, 1.0), parent=(-1,), cap=(1,), leaf=None, fmt=0, row_nnz=0):
     s = kp.kp_problem()
     s.N, s.M, s.K = N, M, K
     keep = []
@@ -39,7 +39,12 @@ def _host_problem(N=4, M=3, K=2, B=(1.0, 1.0), parent=(-1,), cap=(1,), leaf=None
     keep.append(dummy)
     s.p = dummy.ctypes.data
     s.b = dummy.ctypes.data
-    s.b_format = 0
+    s.b_format = fmt
+    s.b_row_nnz = row_nnz
+    if fmt == 1:
+        rp = np.arange(N * M + 1, dtype=np.int64)
+        keep.append(rp)
+        s.b_rowptr, s.b_col, s.b_val = rp.ctypes.data, dummy.ctypes.data, dummy.ctypes.data
     Ba = np.array(B, np.float64)
     par = np.array(parent, np.int32)
     cp = np.array(cap, np.int32)
@@ -60,6 +65,9 @@ def _host_problem(N=4, M=3, K=2, B=(1.0, 1.0), parent=(-1,), cap=(1,), leaf=None
     (dict(M=65, leaf=[0] * 65), -5),          # over the item limit
     (dict(N=-1), -1),
     (dict(K=0, B=(1.0,)), -1),
+    (dict(row_nnz=1), -1),                    # a row count is declared for CSR costs only
+    (dict(fmt=1, row_nnz=3), -1),             # 1 or 2 entries per item row
+    (dict(fmt=1, row_nnz=-1), -1),
 ])
 def test_validation_rejects_bad_problems(kw, code):
     L = kp.lib()

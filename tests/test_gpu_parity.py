@@ -2,6 +2,8 @@
 inputs.  Bars: decisions x bit-exact; R bit-exact (values on the 2^-24 grid
 sum exactly in FP64); g and P within 1e-9 relative; DD and SCD multipliers
 bit-exact."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -291,28 +293,152 @@ def test_batched_plan_graph_replays(use_graph):
 
 
 @gpu
-def test_autotuner_choice_keeps_results(tmp_path):
-    """Every tile shape the autotuner may pick gives the same decisions,
-    consumption and SCD update; the choice is cached as JSON."""
+def test_autotuner_reaches_every_kernel(tmp_path):
+    """Every tuning candidate launches the shape it asks for, as the library
+    reports it: users per tile and grid of the general kernel (dense costs),
+    the grid of the uniform-row kernel (CSR with two entries per item row),
+    and the LDS budget and block split of a batched plan.  Every shape gives
+    the oracle's decisions, consumption and SCD updates."""
     kp, torch = _kp()
     from paper_2002_00352_amd import autotune
-    inst = kpgen.config_instance(3, N=5000)
+    # general kernel
+    inst = kpgen.config_instance(2, N=6000)
     prob = kp.Problem.from_host(inst)
     ctx = kp.Context()
     lam = np.full(inst.K, 0.3)
     want = oracle.scd_sweep(inst, lam)
     ref = oracle.eval_dual(inst, lam)
-    for u, g in [(4, 512), (16, 1024), (64, 4096)]:
+    shapes = []
+    for u, g in [(4, 512), (16, 64), (40, 96)]:
         autotune.apply(ctx, prob, (u, g))
         ev = kp.kp_eval_dual(prob, _lamd(torch, lam), want_x=True, ctx=ctx)
+        shape = ctx.launch_shape()
+        assert shape == (0, u, min(g, -(-inst.N // u))), (u, g, shape)
         assert np.array_equal(ev["x"].cpu().numpy(), ref["x"])
         assert np.array_equal(ev["R"].cpu().numpy(), ref["R"])
         got = kp.kp_scd_sweep(prob, _lamd(torch, lam), ctx=ctx)["lam"].cpu().numpy()
+        assert ctx.launch_shape()[:2] == (0, u)
         assert np.array_equal(got, want), (u, g)
+        shapes.append(shape)
+    assert len(set(shapes)) == 3
     path = str(tmp_path / "tune.json")
     choice = autotune.tune(prob, ctx=ctx, candidates=[(8, 512), (32, 2048)], path=path)
     assert choice in [(8, 512), (32, 2048)]
-    assert autotune.shape_key(prob) + "|scd" in autotune.load_cache(path)
+    rec = autotune.load_cache(path)[autotune.shape_key(prob) + "|scd"]
+    assert rec["kernel"] == "general" and len(rec["tried"]) == 2
+    # uniform-row kernel: the grid only
+    inst3 = kpgen.config_instance(3, N=20000)
+    prob3 = kp.Problem.from_host(inst3)
+    assert prob3.row_nnz == 2
+    ctx3 = kp.Context()
+    lam3 = np.full(inst3.K, 0.05)
+    want3 = oracle.scd_sweep(inst3, lam3)
+    ref3 = oracle.eval_dual(inst3, lam3)
+    grids = []
+    for g in (16, 48, 79):
+        autotune.apply(ctx3, prob3, (0, g))
+        ev = kp.kp_eval_dual(prob3, _lamd(torch, lam3), want_x=True, ctx=ctx3)
+        assert ctx3.launch_shape() == (1, 64, g), (g, ctx3.launch_shape())
+        assert np.array_equal(ev["x"].cpu().numpy(), ref3["x"])
+        assert np.array_equal(ev["R"].cpu().numpy(), ref3["R"])
+        got = kp.kp_scd_sweep(prob3, _lamd(torch, lam3), ctx=ctx3)["lam"].cpu().numpy()
+        assert ctx3.launch_shape()[0] == 1
+        assert np.array_equal(got, want3), g
+        grids.append(g)
+    choice3 = autotune.tune(prob3, ctx=ctx3, path=path)
+    assert choice3[0] == 0 and choice3[1] in autotune.ELL_GRIDS
+    assert autotune.load_cache(path)[autotune.shape_key(prob3) + "|scd"]["kernel"] == "uniform-row"
+    # batched plan: LDS budget and block split
+    rng = np.random.default_rng(91)
+    insts = [kpgen.make_instance(int(rng.integers(200, 3000)), int(rng.integers(4, 20)),
+                                 int(rng.integers(1, 9)), seed=900 + s, Q=int(rng.integers(1, 4)),
+                                 budget_frac=0.1) for s in range(6)]
+    probs = [kp.Problem.from_host(i) for i in insts]
+    bshapes = []
+    for lds, mult in [(16384, 4), (65536, 128)]:
+        bctx = kp.Context()
+        bctx.set_batched_tuning(lds, mult)
+        bs = kp.BatchedSCD(probs, ctx=bctx)
+        shape = bs.shape()
+        assert shape[1] <= lds, shape
+        bshapes.append(shape)
+        lams = [np.zeros(i.K) for i in insts]
+        for t in range(2):
+            outs, _ = bs.step()
+            for s_, inst_ in enumerate(insts):
+                w = oracle.scd_sweep(inst_, lams[s_])
+                assert np.array_equal(outs[s_].cpu().numpy(), w), (lds, mult, t, s_)
+                lams[s_] = w
+        bs.close()
+    assert bshapes[0] != bshapes[1]
+    assert bshapes[0][3] < bshapes[1][3], bshapes
+
+
+@gpu
+def test_structure_declaration_not_cached_by_address():
+    """A CSR instance with two entries per item row, freed, then one of the
+    same shape whose rows are not uniform, allocated on the same default
+    context at the recycled addresses (torch's caching allocator): the new
+    problem declares no uniform rows, runs the general kernel and matches the
+    oracle.  A false declaration is caught by input validation."""
+    kp, torch = _kp()
+    inst = kpgen.config_instance(3, N=20000)
+    prob = kp.Problem.from_host(inst)
+    assert prob.row_nnz == 2 and kp.kp_csr_row_nnz(prob) == 2
+    lam = np.full(inst.K, 0.05)
+    ev = kp.kp_eval_dual(prob, _lamd(torch, lam), want_x=True)
+    assert np.array_equal(ev["x"].cpu().numpy(), oracle.eval_dual(inst, lam)["x"])
+    assert kp.default_context().launch_shape()[0] == 1
+    addrs = (prob.rowptr.data_ptr(), prob.col.data_ptr(), prob.val.data_ptr())
+    del prob, ev
+    torch.cuda.synchronize()
+    # move one stored entry of every even row to the next row: same nnz, same
+    # array sizes, rows of 1 and 3 entries (columns kept distinct and ascending)
+    col = inst.col.reshape(-1, 2).copy()
+    val = inst.val.reshape(-1, 2).copy()
+    nrows = inst.N * inst.M
+    lens = np.full(nrows, 2, np.int64)
+    cols, vals = [], []
+    for r in range(0, nrows - 1, 2):
+        extra_c, extra_v = col[r, 1], val[r, 1]
+        nxt = sorted(set(col[r + 1].tolist()) | {int(extra_c)})
+        if len(nxt) != 3:          # the moved column is already in the next row
+            cols += [col[r].tolist(), col[r + 1].tolist()]
+            vals += [val[r].tolist(), val[r + 1].tolist()]
+            continue
+        lens[r], lens[r + 1] = 1, 3
+        vmap = {int(col[r + 1, 0]): val[r + 1, 0], int(col[r + 1, 1]): val[r + 1, 1], int(extra_c): extra_v}
+        cols += [[int(col[r, 0])], nxt]
+        vals += [[val[r, 0]], [vmap[c] for c in nxt]]
+    if nrows % 2:
+        cols.append(col[-1].tolist())
+        vals.append(val[-1].tolist())
+    bad = dataclasses.replace(inst, rowptr=np.concatenate([[0], np.cumsum(lens)]).astype(np.int64),
+                              col=np.array([c for r in cols for c in r], np.int32),
+                              val=np.array([v for r in vals for v in r], np.float32))
+    assert bad.rowptr[-1] == inst.rowptr[-1] and (lens != 2).any()
+    prob2 = kp.Problem.from_host(bad)
+    reused = (prob2.rowptr.data_ptr(), prob2.col.data_ptr(), prob2.val.data_ptr()) == addrs
+    print("addresses reused:", reused, flush=True)
+    assert prob2.row_nnz == 0
+    ctx = kp.default_context()
+    for t in range(3):
+        ev = kp.kp_eval_dual(prob2, _lamd(torch, lam), want_x=True)
+        assert ctx.launch_shape()[0] == 0
+        ref = oracle.eval_dual(bad, lam)
+        assert np.array_equal(ev["x"].cpu().numpy(), ref["x"])
+        assert np.array_equal(ev["R"].cpu().numpy(), ref["R"])
+        want = oracle.scd_sweep(bad, lam)
+        got = kp.kp_scd_sweep(prob2, _lamd(torch, lam))["lam"].cpu().numpy()
+        assert np.array_equal(got, want), t
+        lam = want
+    liar = kp.Problem(prob2.p, bad.B, bad.tree.parent, bad.tree.cap, bad.tree.leaf_of_item,
+                      rowptr=prob2.rowptr, col=prob2.col, val=prob2.val, N=bad.N, M=bad.M, K=bad.K,
+                      row_nnz=2)
+    with pytest.raises(kp.KPError) as e:
+        kp.kp_validate_inputs(liar)
+    assert e.value.status == kp.KP_ERR_INVALID
+    kp.kp_validate_inputs(kp.Problem.from_host(inst))
 
 
 ELL_CASES = [
@@ -509,6 +635,7 @@ def _full_size_problem(kp, c):
     arrs, B, tree, meta = kgd.device_instance(c, 0)
     prob = kp.Problem(arrs["p"], B, tree.parent, tree.cap, tree.leaf_of_item, b=arrs.get("b"),
                       rowptr=arrs.get("rowptr"), col=arrs.get("col"), val=arrs.get("val"),
+                      row_nnz=meta["csr_d"] if meta["csr_d"] else None,
                       N=meta["N"], M=meta["M"], K=meta["K"])
     return arrs, B, tree, meta, prob
 
