@@ -155,6 +155,71 @@ static inline void nadd(nsum *a, double v) {
 static inline double nval(const nsum *a) { return a->s + a->c; }
 
 /* ------------------------------------------------------------------------ */
+/* Exact sums of doubles.  Reading: the reduce of Alg.4 compares the total   */
+/* resource a threshold lets through with B_k -- a sum of real numbers -- so */
+/* the oracle forms it exactly: a two's-complement fixed-point integer whose */
+/* lowest bit is 2^-1088 (below every double, subnormals included) and whose */
+/* 34 limbs of 64 bits reach 2^1087 (every double, with room for the sum of  */
+/* up to 2^63 of them).  Adding a double places its 53-bit significand at    */
+/* its binary position and propagates the carry (or the borrow).             */
+/* ------------------------------------------------------------------------ */
+#define XLIMBS 34
+#define XLSB 1088
+typedef struct { uint64_t w[XLIMBS]; } xsum;
+
+static void xsum_zero(xsum *a) { memset(a->w, 0, sizeof a->w); }
+
+static void xsum_add(xsum *a, double v) {
+  if (v == 0.0) return;
+  int e;
+  double fr = frexp(fabs(v), &e);                    /* |v| = fr * 2^e, fr in [0.5, 1) */
+  uint64_t m = (uint64_t)ldexp(fr, 53);              /* |v| = m * 2^(e - 53), exact */
+  int pos = e - 53 + XLSB;                           /* bit position of m's lowest bit */
+  if (pos < 0) { m >>= -pos; pos = 0; }              /* subnormals: the dropped bits are zero */
+  int limb = pos / 64, sh = pos % 64;
+  uint64_t lo = m << sh, hi = sh ? m >> (64 - sh) : 0;
+  if (v > 0.0) {
+    uint64_t c;
+    uint64_t t = a->w[limb] + lo;
+    c = t < lo;
+    a->w[limb] = t;
+    for (int i = limb + 1; i < XLIMBS && (c || (i == limb + 1 && hi)); ++i) {
+      uint64_t add = (i == limb + 1) ? hi : 0;
+      uint64_t u = a->w[i] + add;
+      uint64_t c1 = u < add;
+      uint64_t u2 = u + c;
+      uint64_t c2 = u2 < c;
+      a->w[i] = u2;
+      c = c1 | c2;
+    }
+  } else {
+    uint64_t b;
+    uint64_t t = a->w[limb] - lo;
+    b = a->w[limb] < lo;
+    a->w[limb] = t;
+    for (int i = limb + 1; i < XLIMBS && (b || (i == limb + 1 && hi)); ++i) {
+      uint64_t sub = (i == limb + 1) ? hi : 0;
+      uint64_t u = a->w[i] - sub;
+      uint64_t b1 = a->w[i] < sub;
+      uint64_t u2 = u - b;
+      uint64_t b2 = u < b;
+      a->w[i] = u2;
+      b = b1 | b2;
+    }
+  }
+}
+
+/* sign of (a - v): -1, 0 or 1 */
+static int xsum_cmp(const xsum *a, double v) {
+  xsum d = *a;
+  xsum_add(&d, -v);
+  if (d.w[XLIMBS - 1] >> 63) return -1;
+  for (int i = 0; i < XLIMBS; ++i)
+    if (d.w[i]) return 1;
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Dual evaluation at lambda (Eq.5 and Alg.2 Map/Reduce):                     */
 /*  x_i = Alg1(p~_i); v_ik = sum_j b_ijk x_ij (j ascending);                  */
 /*  R_k = sum_i v_ik; P = sum p x; G_i = sum_j p~_ij x_ij;                    */
@@ -332,7 +397,8 @@ int64_t orc_scd_map(const orc_problem *pr, const double *lam, int64_t u0, int64_
 /* sum v2 fits in B_k.  Otherwise, Reading: walk the distinct v1 values in   */
 /* decreasing order with the running sum of v2 (including the value itself) */
 /* and return the first v1 at which that sum exceeds B_k -- the smallest    */
-/* lambda_k at which consumption just above it still fits the budget.        */
+/* lambda_k at which consumption just above it still fits the budget.  The  */
+/* sums are exact (xsum), so the threshold does not depend on their order.   */
 /* The pairs are sorted in place (v1 descending).                            */
 /* ------------------------------------------------------------------------ */
 typedef struct { double v1, v2; } pair_t;
@@ -342,18 +408,21 @@ static int cmp_pair_desc(const void *a, const void *b) {
 }
 
 double orc_scd_reduce(int64_t n, double *v1, double *v2, double Bk) {
-  double total = 0.0;
-  for (int64_t e = 0; e < n; ++e) total = total + v2[e];
-  if (total <= Bk) return 0.0;
+  xsum total;
+  xsum_zero(&total);
+  for (int64_t e = 0; e < n; ++e) xsum_add(&total, v2[e]);
+  if (xsum_cmp(&total, Bk) <= 0) return 0.0;
   pair_t *pp = (pair_t *)malloc(sizeof(pair_t) * (size_t)(n > 0 ? n : 1));
   for (int64_t e = 0; e < n; ++e) { pp[e].v1 = v1[e]; pp[e].v2 = v2[e]; }
   qsort(pp, (size_t)n, sizeof(pair_t), cmp_pair_desc);
-  double cum = 0.0, ans = pp[n - 1].v1;
+  xsum cum;
+  xsum_zero(&cum);
+  double ans = pp[n - 1].v1;
   int64_t e = 0;
   while (e < n) {
     double v = pp[e].v1;
-    while (e < n && pp[e].v1 == v) { cum = cum + pp[e].v2; ++e; }
-    if (cum > Bk) { ans = v; break; }
+    while (e < n && pp[e].v1 == v) { xsum_add(&cum, pp[e].v2); ++e; }
+    if (xsum_cmp(&cum, Bk) > 0) { ans = v; break; }
   }
   for (int64_t q = 0; q < n; ++q) { v1[q] = pp[q].v1; v2[q] = pp[q].v2; }
   free(pp);
@@ -623,6 +692,18 @@ int orc_alg5_map_user(const orc_problem *pr, const double *lam, int64_t i, int Q
 }
 
 int orc_max_items(void) { return MAXM; }
+
+/* Threads of the OpenMP loops over users (n >= 1); the results do not
+   depend on it.  Returns the thread count in effect. */
+int orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
+}
 
 /* Cost-adjusted profits of users [u0,u1) into out[(i-u0)*M + j]. */
 void orc_scores(const orc_problem *pr, const double *lam, int64_t u0, int64_t u1, double *out) {
