@@ -205,17 +205,28 @@ kp_status kp_tree_from_sets(int32_t M, int32_t L, const int32_t *set_offsets,
                             int32_t *parent_out, int32_t *cap_out,
                             int32_t *leaf_of_item_out);
 
-/* Optional timing of the sweep kernel: when on, every launch of the sweep
-   kernel made through this context is bracketed by HIP events on the
-   context's stream.  kp_get_timing waits for them and returns the summed
-   kernel time (ms), the launch count and the algorithmic input bytes of those
-   launches (p and b once per launch in the layout above: dense
-   4*N*M*(1+K) bytes; CSR 4*N*M + 8*(N*M+1) + 8*nnz bytes, with nnz read
-   once from rowptr[N*M]).
-   kp_set_timing resets the totals. */
+/* Optional timing of the sweep kernel: when on, every sweep pass made
+   through this context (the uniform-row kernel's window pass: both of its
+   launches) is bracketed by HIP events on the context's stream, and so is
+   every whole iteration of a batched plan created on it.  kp_get_timing
+   waits for them and returns the summed time (ms), the number of timed
+   intervals and their algorithmic input bytes: every byte of p and b in the
+   layout above once per interval (dense 4*N*M*(1+K); CSR
+   4*N*M + 8*(N*M+1) + 8*nnz, rowptr included even where the lean kernel does
+   not read it; a batched iteration: the sum over its instances).
+   kp_get_batched_passes: the sweep passes inside the timed batched
+   iterations.  kp_set_timing resets the totals. */
 kp_status kp_set_timing(void *ctx, int32_t on);
 kp_status kp_get_timing(void *ctx, double *sweep_ms_total, int64_t *sweep_launches,
                         double *sweep_bytes_total);
+kp_status kp_get_batched_passes(void *ctx, int64_t *passes);
+
+/* Streaming-read probe (the roofline's measured ceiling): reads bytes (a
+   multiple of 16) from the 16-byte aligned DEV buffer src once, with the
+   sweep's access width, on hip_stream, and XORs every 64-bit word into
+   *out (DEV [1], not cleared: the caller zeroes it).  Time it with events
+   on the same stream. */
+kp_status kp_stream_read(void *hip_stream, const void *src, size_t bytes, uint64_t *out);
 
 /* Tile-size override for one problem shape (M, K, b_format): users per tile
    and grid size (blocks) used by every later call on this context for that
@@ -255,6 +266,30 @@ kp_status kp_set_kernel_choice(void *ctx, int32_t allow_uniform_rows);
    b_rowptr once on the device (8 bytes per item row); b_row_nnz of prob is
    ignored.  D_out: HOST.  Synchronises the context stream. */
 kp_status kp_csr_row_nnz(void *ctx, const kp_problem *prob, int32_t *D_out);
+
+/* Alg.5's linear-time map (Sec. 5.1) in the SCD calls of this context (off
+   by default): for problems in its setting -- M = K, CSR declared with one
+   entry per item row (b_row_nnz = 1), at most one binding local set and it
+   holds every item (top-Q) -- every user whose item j's entry is knapsack j
+   takes Alg.5's single breakpoint per knapsack: with adj_j = max(p~_j, 0)
+   and qth, q1th the Q-th and (Q+1)-th largest adj (0 past the last item),
+   p_bar = q1th if adj_k >= qth else qth, and when p_k > p_bar the pair
+   ((p_k - p_bar) / b_kk, b_kk).  The breakpoint uses the raw profit p_k as
+   Alg.5 does, where the general map uses p~_k + lambda_k b_kk (reading A9),
+   so the two agree to rounding of that intercept (a few ulp), not bit for
+   bit.  Other users and problems keep the general map. */
+kp_status kp_set_alg5(void *ctx, int32_t on);
+
+/* Reduce of the SCD calls of this context: 0 (default) the exact threshold
+   of Alg.4's reduce; 1 Sec. 5.2's approximate reduce -- the increments are
+   summed per bucket of the breakpoints (a central bucket of half-width
+   delta_k around lambda_k^t and base-2 buckets growing away from it, ids
+   capped at +-31; delta_k the power of two 2^-20 of lambda_k^t, of 2^-20
+   when lambda_k^t is smaller), the bucket [lo, hi] where the running sum from
+   the top first exceeds B_k is found, and the threshold is
+   max(lo, hi - (B_k - above) / S_bucket * (hi - lo)) with lo clamped at 0;
+   0 when the total increment fits.  One pass per iteration, no windows. */
+kp_status kp_set_reduce(void *ctx, int32_t mode);
 
 /* Threshold search of kp_scd_sweep (Alg.4 reduce, located near the
    previous multiplier).  After one sweep on a context, each

@@ -11,6 +11,7 @@ brute-force and exact-arithmetic tools that pin the C oracle.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 from typing import Optional
@@ -55,6 +56,8 @@ def lib():
         L = ctypes.CDLL(_LIB)
         P = ctypes.POINTER(_Problem)
         vp, i64, i32, d = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_set_threads.restype = ctypes.c_int
         L.orc_eval.argtypes = [P, vp, vp, vp, vp, vp, vp]
         L.orc_eval.restype = ctypes.c_int
         L.orc_dd_update.argtypes = [ctypes.c_int, d, vp, vp, vp]
@@ -80,6 +83,12 @@ def lib():
         L.orc_alg1.restype = None
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's loops over users (results do not depend on
+    it); returns the count in effect."""
+    return int(lib().orc_set_threads(int(n)))
 
 
 def _ptr(a: Optional[np.ndarray]):
@@ -248,6 +257,101 @@ def alg5_map_user(inst, lam, i, Q):
     return kk[:n], v1[:n], v2[:n]
 
 
+def scd_sweep_alg5(inst, lam, Q):
+    """One SCD iteration whose map is Alg.5 (Sec. 5.1) for every user (the
+    setting M = K, item j consuming only knapsack j, one top-Q cap) and whose
+    reduce is Alg.4's: per knapsack, the pairs in user order, then the
+    threshold of scd_reduce."""
+    pr = _prob(inst)
+    K = pr.s.K
+    lam = np.ascontiguousarray(lam, np.float64)
+    v1s = [[] for _ in range(K)]
+    v2s = [[] for _ in range(K)]
+    for i in range(pr.s.N):
+        kk, a, b = alg5_map_user(pr, lam, i, Q)
+        for k, x, y in zip(kk.tolist(), a.tolist(), b.tolist()):
+            v1s[k].append(x)
+            v2s[k].append(y)
+    return np.array([scd_reduce(v1s[k], v2s[k], pr.B[k]) for k in range(K)], np.float64)
+
+
+def interp_delta(lam):
+    """Central bucket half-width of the interpolated reduce (reading A17):
+    a power of two 2^-20 of the multiplier (of 2^-20 when the multiplier is
+    smaller), the minimal bucket size around lambda_k^t of Sec. 5.2."""
+    return np.array([math.ldexp(1.0, math.frexp(max(float(l), 2.0 ** -20))[1] - 1 - 20) for l in lam])
+
+
+def _bucket_ids(v1, center, delta):
+    """Reading A17 of Sec. 5.2's bucket id: 0 when |v1 - center| < delta,
+    else sign * (1 + floor(log2(|v1 - center| / delta))), capped at 31; the
+    difference is the FP64 one and delta a power of two."""
+    d = np.asarray(v1, np.float64) - center
+    a = np.abs(d)
+    ids = np.zeros(len(d), np.int64)
+    big = a >= delta
+    if big.any():
+        ea = np.frexp(a[big])[1].astype(np.int64)
+        ed = math.frexp(delta)[1]
+        ids[big] = np.minimum(31, 1 + (ea - ed)) * np.where(d[big] < 0, -1, 1)
+    return ids
+
+
+def scd_reduce_interp(v1, v2, Bk, center, delta):
+    """Sec. 5.2's approximate reduce: v2 summed per bucket of v1 (the uneven
+    buckets of _bucket_ids around center = lambda_k^t); 0 when the total fits
+    B_k, else the bucket where the running sum from the top first exceeds
+    B_k, and inside it the point where a linear spread of its sum over its
+    interval [lo, hi] would bring the running sum to B_k:
+    v = hi - (B_k - above) / S_b * (hi - lo), with lo clamped at 0."""
+    v1 = np.asarray(v1, np.float64)
+    v2 = np.asarray(v2, np.float64)
+    total = 0.0
+    for x in v2:
+        total = total + float(x)
+    if total <= Bk:
+        return 0.0
+    ids = _bucket_ids(v1, center, delta)
+    sums = {}
+    for i, x in zip(ids.tolist(), v2.tolist()):
+        sums[i] = sums.get(i, 0.0) + x
+    above = 0.0
+    for b in range(31, -32, -1):
+        if b not in sums:
+            continue
+        if above + sums[b] > Bk:
+            if b == 0:
+                lo, hi = center - delta, center + delta
+            elif b > 0:
+                lo, hi = center + math.ldexp(delta, b - 1), center + math.ldexp(delta, b)
+            else:
+                lo, hi = center - math.ldexp(delta, -b), center - math.ldexp(delta, -b - 1)
+            lo = max(lo, 0.0)
+            frac = (Bk - above) / sums[b]
+            width = hi - lo
+            v = hi - frac * width
+            return max(v, lo)
+        above = above + sums[b]
+    return 0.0
+
+
+def scd_sweep_interp(inst, lam, ks=None):
+    """One SCD iteration whose reduce is Sec. 5.2's bucket interpolation
+    (the map is Alg.4's, as in scd_sweep) around lambda^t with the central
+    half-widths of interp_delta, restricted to coordinates ks when given."""
+    pr = _prob(inst)
+    lam = np.ascontiguousarray(lam, np.float64)
+    delta = interp_delta(lam)
+    kk, uu, v1, v2 = scd_map(pr, lam)
+    out = lam.copy()
+    for k in range(pr.s.K):
+        if ks is not None and k not in ks:
+            continue
+        sel = kk == k
+        out[k] = scd_reduce_interp(v1[sel], v2[sel], float(pr.B[k]), float(lam[k]), float(delta[k]))
+    return out
+
+
 def presolve(inst, users, max_iter=100, lam0=None):
     """Pre-solving by sampling (Sec. 5.3): SCD on the sub-instance of the
     sampled users with every budget scaled by n / N, from lam0 until the
@@ -323,7 +427,8 @@ def solve(inst, method="scd", lam0=None, tol=1e-3, max_iter=100, alpha=1e-3, fix
 
     method: "scd" synchronous CD (every coordinate from the same lambda^t),
     "cyclic" (one coordinate per iteration), "block" (`block` consecutive
-    coordinates per iteration) -- the CD variants of Sec. 4.3.2 -- or "dd".
+    coordinates per iteration) -- the CD variants of Sec. 4.3.2 --, "interp"
+    (synchronous CD with Sec. 5.2's interpolated reduce) or "dd".
     Tracks the best dual and best feasible primal seen.  Returns the trajectory."""
     pr = OracleProblem(inst)
     K = inst.K
@@ -344,13 +449,15 @@ def solve(inst, method="scd", lam0=None, tol=1e-3, max_iter=100, alpha=1e-3, fix
             break
         if method == "dd":
             new = dd_update(lam, alpha, ev["R"], inst.B)
+        elif method == "interp":
+            new = scd_sweep_interp(pr, lam)
         else:
             if method == "scd":
                 new = scd_sweep(pr, lam)
             else:
                 w = 1 if method == "cyclic" else block
                 new = scd_sweep(pr, lam, ks=[(t * w + q) % K for q in range(w)])
-        if method in ("scd", "dd") and np.array_equal(new, lam):
+        if method in ("scd", "dd", "interp") and np.array_equal(new, lam):
             break
         lam = new
     return hist

@@ -78,7 +78,8 @@ EXPORTS = ["kp_last_error", "kp_create", "kp_destroy", "kp_set_stream", "kp_eval
            "kp_batched_create", "kp_batched_step", "kp_batched_destroy", "kp_set_tuning",
            "kp_set_kernel_choice", "kp_csr_row_nnz", "kp_set_window",
            "kp_get_window_stats", "kp_presolve", "kp_get_window_listed", "kp_get_launch_shape",
-           "kp_set_batched_tuning", "kp_batched_shape"]
+           "kp_set_batched_tuning", "kp_batched_shape", "kp_get_batched_passes",
+           "kp_stream_read", "kp_set_alg5", "kp_set_reduce"]
 
 
 def lib():
@@ -110,6 +111,8 @@ def lib():
         L.kp_set_kernel_choice.argtypes = [vp, i32]
         L.kp_csr_row_nnz.argtypes = [vp, P, ctypes.POINTER(i32)]
         L.kp_set_window.argtypes = [vp, i32]
+        L.kp_set_alg5.argtypes = [vp, i32]
+        L.kp_set_reduce.argtypes = [vp, i32]
         L.kp_presolve.argtypes = [vp, P, vp, i64, i32, vp, ctypes.POINTER(i32)]
         L.kp_get_window_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64),
                                           ctypes.POINTER(i64), ctypes.POINTER(i64)]
@@ -117,6 +120,8 @@ def lib():
         L.kp_get_launch_shape.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.kp_set_batched_tuning.argtypes = [vp, i32, i32]
         L.kp_batched_shape.argtypes = [vp] + [ctypes.POINTER(i32)] * 4
+        L.kp_get_batched_passes.argtypes = [vp, ctypes.POINTER(i64)]
+        L.kp_stream_read.argtypes = [vp, vp, ctypes.c_size_t, vp]
         L.kp_set_timing.argtypes = [vp, i32]
         L.kp_get_timing.argtypes = [vp, vp, vp, vp]
         L.kp_max_items.restype = i32
@@ -165,6 +170,12 @@ class Context:
         _check(lib().kp_get_timing(self.h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by)))
         return ms.value, n.value, by.value
 
+    def batched_passes(self) -> int:
+        """Sweep passes inside the timed iterations of batched plans."""
+        n = ctypes.c_int64()
+        _check(lib().kp_get_batched_passes(self.h, ctypes.byref(n)))
+        return n.value
+
     def set_tuning(self, M: int, K: int, b_format: int, users_per_tile: int, grid: int):
         _check(lib().kp_set_tuning(self.h, M, K, b_format, users_per_tile, grid))
 
@@ -180,6 +191,15 @@ class Context:
 
     def set_kernel_choice(self, allow_uniform_rows: bool):
         _check(lib().kp_set_kernel_choice(self.h, 1 if allow_uniform_rows else 0))
+
+    def set_reduce(self, mode: str):
+        """"exact" (Alg.4's threshold) or "interp" (Sec. 5.2's bucket
+        interpolation)."""
+        _check(lib().kp_set_reduce(self.h, {"exact": 0, "interp": 1}[mode]))
+
+    def set_alg5(self, on: bool):
+        """Alg.5's map (Sec. 5.1) for the users in its setting."""
+        _check(lib().kp_set_alg5(self.h, 1 if on else 0))
 
     def set_window(self, on: bool):
         _check(lib().kp_set_window(self.h, 1 if on else 0))
@@ -433,6 +453,16 @@ def kp_csr_row_nnz(prob: Problem, ctx: Optional[Context] = None) -> int:
     D = ctypes.c_int32()
     _check(lib().kp_csr_row_nnz(ctx.h, prob.ref, ctypes.byref(D)))
     return D.value
+
+
+def kp_stream_read(t, out=None):
+    """Read the whole of tensor t once on the current stream (the streaming
+    read probe); returns the XOR of its 64-bit words as a device tensor."""
+    import torch
+    out = torch.zeros(1, dtype=torch.int64, device="cuda") if out is None else out
+    nbytes = t.numel() * t.element_size()
+    _check(lib().kp_stream_read(_stream_handle(), t.data_ptr(), nbytes - nbytes % 16, out.data_ptr()))
+    return out
 
 
 def kp_validate_inputs(prob: Problem, ctx: Optional[Context] = None):

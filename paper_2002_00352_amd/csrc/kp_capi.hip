@@ -25,7 +25,7 @@ hipError_t kp_launch_reduce_stats(const double *partials, int nblk, int K, const
                                   const double *B, double *R, double *g, double *P,
                                   hipStream_t stream);
 hipError_t kp_launch_scd_init(KState *st, int K, const double *lam_in, const uint8_t *kmask,
-                              double *hist, int hinted, int window, hipStream_t stream);
+                              double *hist, int hinted, int window, int interp, hipStream_t stream);
 hipError_t kp_launch_scd_locate_select(KState *st, int K, const double *B, const double *R,
                                        const int *rinst, double *hist_sum, uint32_t *hist_cnt,
                                        const double *ev1, const double *ev2, uint32_t emit_cap,
@@ -69,18 +69,22 @@ void kp_coldesc_fill(void *dst, const double *partials, const double *lam, const
 
 hipError_t kp_launch_validate_csr(const int64_t *rowptr, const int32_t *col, int64_t nrows, int K,
                                   unsigned int *flags, hipStream_t stream);
+hipError_t kp_launch_stream_read(const void *src, int64_t n16, unsigned long long *out, int grid,
+                                 hipStream_t stream);
 
 namespace {
 
-thread_local std::string g_err;
+// last error message of this thread (a fixed buffer: reporting an error
+// allocates nothing)
+thread_local char g_err[512];
 
 kp_status fail(kp_status st, const char *fmt, ...) {
-  char buf[512];
+  char buf[sizeof g_err];
   va_list ap;
   va_start(ap, fmt);
   vsnprintf(buf, sizeof buf, fmt, ap);
   va_end(ap);
-  g_err = buf;
+  memcpy(g_err, buf, sizeof g_err);
   return st;
 }
 
@@ -102,6 +106,7 @@ constexpr uint32_t kStageCapMax = 65536;
 constexpr uint32_t kEmitCapBatched = 1u << 16;   // emitted events per (instance, knapsack) per pass (at least)
 constexpr double kEmitBytesBatched = 8.0e9;        // bound on a batch's emission buffers
 constexpr size_t kBatchedLds = 40 * 1024;          // LDS per block of the batched launch (4 blocks per CU)
+constexpr int kMaxInputNodes = 4096;               // local-constraint nodes accepted in a problem
 
 struct Ctx {
   hipStream_t stream = nullptr;
@@ -120,10 +125,13 @@ struct Ctx {
   double sweep_ms = 0.0;
   int64_t sweep_launches = 0;
   double sweep_bytes = 0.0;
+  int64_t batched_passes = 0;     // sweep passes of the timed batched iterations
   // tuned tile sizes per shape (M, K, format) -> (users per tile, grid)
   std::map<std::tuple<int, int, int>, std::pair<int, int>> tuning;
   bool ell_enabled = true;
   bool window_enabled = true;
+  bool alg5 = false;      // Alg.5 map for the users in its setting
+  bool interp = false;    // approximate reduce: interpolation inside the threshold's bucket
   int stats_grid = 0;     // blocks of the last sweep launch (slots of the per-block partials)
   // shape of the last sweep launch: kernel (0 general, 1 uniform-row), users
   // per tile, blocks
@@ -210,7 +218,7 @@ kp_status ensure_ws(Ctx *c, size_t bytes) {
 struct Prepared {
   ProbDev pr;
   TreeDev tree;
-  std::vector<double> B;
+  const double *B = nullptr;   // the caller's host budgets [K] (valid during the call)
   int U = 1;
   int64_t ntiles = 0;
   int grid = 1;
@@ -250,7 +258,7 @@ kp_status prepare(const kp_problem *p, bool scd, Prepared &out, const Ctx *ctx =
       return fail(KP_ERR_INVALID, "CSR arrays must not be NULL");
   }
   if (!p->B) return fail(KP_ERR_INVALID, "B is NULL");
-  out.B.assign(p->B, p->B + p->K);
+  out.B = p->B;
   for (int k = 0; k < p->K; ++k)
     if (!(std::isfinite(out.B[k]) && out.B[k] > 0.0))
       return fail(KP_ERR_INVALID, "B[%d] = %g must be finite and > 0", k, out.B[k]);
@@ -269,34 +277,54 @@ kp_status prepare(const kp_problem *p, bool scd, Prepared &out, const Ctx *ctx =
     while (x >= 0 && steps <= L) { x = p->parent[x]; ++steps; }
     if (x >= 0) return fail(KP_ERR_INVALID, "parent links contain a cycle (node %d)", l);
   }
-  std::vector<uint64_t> mask(L, 0);
+  if (L > kMaxInputNodes)
+    return fail(KP_ERR_UNSUPPORTED, "L = %d local-constraint nodes exceed the limit %d", L, kMaxInputNodes);
+  // (fixed-size arrays: validation allocates nothing)
+  uint64_t mask[kMaxInputNodes];
+  for (int l = 0; l < L; ++l) mask[l] = 0;
   for (int j = 0; j < M; ++j) {
     const int lf = p->leaf_of_item[j];
     if (lf < -1 || lf >= L) return fail(KP_ERR_INVALID, "leaf_of_item[%d] = %d out of range", j, lf);
     for (int x = lf; x >= 0; x = p->parent[x]) mask[x] |= 1ull << j;
   }
   // keep sets that can bind; merge duplicates with the smaller cap
-  std::map<uint64_t, int> keep;
+  uint64_t nmask[KP_MAX_NODES];
+  int ncap[KP_MAX_NODES];
+  int nn = 0;
   for (int l = 0; l < L; ++l) {
     const int sz = __builtin_popcountll(mask[l]);
     if (p->cap[l] >= sz) continue;
-    auto it = keep.find(mask[l]);
-    if (it == keep.end()) keep[mask[l]] = p->cap[l];
-    else it->second = std::min(it->second, p->cap[l]);
+    int t = 0;
+    while (t < nn && nmask[t] != mask[l]) ++t;
+    if (t < nn) {
+      ncap[t] = std::min(ncap[t], p->cap[l]);
+      continue;
+    }
+    if (nn == KP_MAX_NODES)
+      return fail(KP_ERR_UNSUPPORTED, "more than %d binding local sets", KP_MAX_NODES);
+    nmask[nn] = mask[l];
+    ncap[nn] = p->cap[l];
+    ++nn;
   }
-  std::vector<std::pair<uint64_t, int>> nodes(keep.begin(), keep.end());
-  if ((int)nodes.size() > KP_MAX_NODES)
-    return fail(KP_ERR_UNSUPPORTED, "%zu binding local sets exceed the limit %d", nodes.size(), KP_MAX_NODES);
-  std::stable_sort(nodes.begin(), nodes.end(), [](const std::pair<uint64_t, int> &a, const std::pair<uint64_t, int> &b) {
-    const int sa = __builtin_popcountll(a.first), sb = __builtin_popcountll(b.first);
+  // subsets first: size ascending, then lowest item (insertion sort, stable)
+  auto before = [](uint64_t a, uint64_t b) {
+    const int sa = __builtin_popcountll(a), sb = __builtin_popcountll(b);
     if (sa != sb) return sa < sb;
-    return __builtin_ctzll(a.first) < __builtin_ctzll(b.first);
-  });
+    return __builtin_ctzll(a) < __builtin_ctzll(b);
+  };
+  for (int a = 1; a < nn; ++a) {
+    const uint64_t m = nmask[a];
+    const int cp = ncap[a];
+    int b = a - 1;
+    while (b >= 0 && before(m, nmask[b])) { nmask[b + 1] = nmask[b]; ncap[b + 1] = ncap[b]; --b; }
+    nmask[b + 1] = m;
+    ncap[b + 1] = cp;
+  }
   memset(&out.tree, 0, sizeof(out.tree));
-  out.tree.L = (int)nodes.size();
-  for (size_t t = 0; t < nodes.size(); ++t) {
-    out.tree.mask[t] = nodes[t].first;
-    out.tree.cap[t] = nodes[t].second;
+  out.tree.L = nn;
+  for (int t = 0; t < nn; ++t) {
+    out.tree.mask[t] = nmask[t];
+    out.tree.cap[t] = ncap[t];
   }
   ProbDev &pr = out.pr;
   memset(&pr, 0, sizeof(pr));
@@ -404,7 +432,8 @@ kp_status choose_kernel(Ctx *c, Prepared &P, bool scd) {
   if (tit != c->tuning.end() && tit->second.second > 0)
     P.ell_grid = std::max(1, std::min(tit->second.second, gmax));
   P.ell_brk_grid = std::max(1, std::min(gbrk, P.ell_grid));
-  P.ell_bytes = (double)P.pr.N * P.pr.M * 4.0 + (double)nnz * 8.0;   // rowptr is not read
+  // the ABI layout's bytes (p, col, val and rowptr), although the kernel never reads rowptr
+  P.ell_bytes = (double)P.pr.N * P.pr.M * 4.0 + (double)nnz * 8.0 + ((double)P.pr.N * P.pr.M + 1.0) * 8.0;
   return KP_OK;
 }
 
@@ -544,9 +573,9 @@ kp_status upload_B(Ctx *c, const Prepared &P, SweepWs &w) {
     HIP_TRY(hipMalloc(&c->B_dev, (size_t)K * 8));
     c->B_cap = K;
   }
-  if (c->B_host != P.B) {
-    HIP_TRY(hipMemcpyAsync(c->B_dev, P.B.data(), (size_t)K * 8, hipMemcpyHostToDevice, c->stream));
-    c->B_host = P.B;
+  if (c->B_host.size() != (size_t)K || memcmp(c->B_host.data(), P.B, (size_t)K * 8) != 0) {
+    c->B_host.assign(P.B, P.B + K);
+    HIP_TRY(hipMemcpyAsync(c->B_dev, c->B_host.data(), (size_t)K * 8, hipMemcpyHostToDevice, c->stream));
   }
   w.B = c->B_dev;
   return KP_OK;
@@ -620,6 +649,18 @@ hipError_t timed_sweep(Ctx *c, const SweepArgs &a, const Prepared &P, bool scd, 
   return err;
 }
 
+// Q of Alg.5's map for this problem (0: not in its setting or not asked
+// for): the uniform-row kernel with one entry per item row, M = K and at most
+// one binding set, which holds every item (no binding set: Q = M).  Whether a
+// user's entries sit in its items' own knapsacks is checked per user.
+int alg5_q(const Ctx *c, const Prepared &P) {
+  if (!c->alg5 || P.ell_D != 1 || P.pr.M != P.pr.K) return 0;
+  const uint64_t all = P.pr.M >= 64 ? ~0ull : ((1ull << P.pr.M) - 1);
+  if (P.tree.L == 0) return P.pr.M;
+  if (P.tree.L == 1 && P.tree.mask[0] == all) return P.tree.cap[0];
+  return 0;
+}
+
 SweepArgs make_args(const Prepared &P, const double *lam, const SweepWs &w, uint8_t *x,
                     bool stats) {
   SweepArgs a;
@@ -668,7 +709,7 @@ kp_status eval_into(Ctx *c, const Prepared &P, const SweepWs &w, const double *l
 // ===========================================================================
 extern "C" {
 
-const char *kp_last_error(void) { return g_err.c_str(); }
+const char *kp_last_error(void) { return g_err; }
 
 int32_t kp_max_items(void) { return KP_MAX_M; }
 int32_t kp_max_knapsacks_scd(void) { return KP_MAX_K_SCD; }
@@ -784,9 +825,9 @@ kp_status kp_scd_sweep_masked(void *ctx, const kp_problem *prob, const double *l
   if (!c->delta_valid)   // no history: NaN multipliers (all bits set)
     HIP_TRY(hipMemsetAsync(c->delta_dev + 2 * K, 0xFF, (size_t)K * 16, c->stream));
   // the window pass needs the statistics of the same pass (R at lambda_in)
-  const int window = (c->window_enabled && P.pr.N > 0) ? 1 : 0;
+  const int window = (c->window_enabled && P.pr.N > 0 && !c->interp) ? 1 : 0;
   HIP_TRY(kp_launch_scd_init(w.st, K, lambda_in, kmask ? w.kmask : nullptr, c->delta_dev,
-                             c->delta_valid ? 1 : 0, window, c->stream));
+                             c->delta_valid ? 1 : 0, window, c->interp ? 1 : 0, c->stream));
   // the first pass runs split (all users, then the listed ones) when every
   // knapsack still searching starts with a window
   // (uniform-row kernel); the general kernel runs such a pass without the
@@ -810,6 +851,7 @@ kp_status kp_scd_sweep_masked(void *ctx, const kp_problem *prob, const double *l
     if (P.pr.N > 0) {
       SweepArgs a = make_args(P, lambda_in, w, nullptr, pass == 0);
       a.pass = pass;
+      a.alg5_q = alg5_q(c, P);
       if (pass == 0 && nohist) {
         a.no_hist = 1;
         a.ntiles = P.ntiles_nh;
@@ -1084,6 +1126,19 @@ kp_status kp_set_kernel_choice(void *ctx, int32_t allow_uniform_rows) {
   return KP_OK;
 }
 
+kp_status kp_set_reduce(void *ctx, int32_t mode) {
+  if (!ctx) return fail(KP_ERR_INVALID, "ctx is NULL");
+  if (mode != 0 && mode != 1) return fail(KP_ERR_INVALID, "reduce mode must be 0 (exact) or 1 (interpolated)");
+  ((Ctx *)ctx)->interp = mode == 1;
+  return KP_OK;
+}
+
+kp_status kp_set_alg5(void *ctx, int32_t on) {
+  if (!ctx) return fail(KP_ERR_INVALID, "ctx is NULL");
+  ((Ctx *)ctx)->alg5 = on != 0;
+  return KP_OK;
+}
+
 kp_status kp_set_window(void *ctx, int32_t on) {
   if (!ctx) return fail(KP_ERR_INVALID, "ctx is NULL");
   ((Ctx *)ctx)->window_enabled = on != 0;
@@ -1132,6 +1187,22 @@ kp_status kp_set_timing(void *ctx, int32_t on) {
   c->sweep_ms = 0.0;
   c->sweep_launches = 0;
   c->sweep_bytes = 0.0;
+  c->batched_passes = 0;
+  return KP_OK;
+}
+
+kp_status kp_get_batched_passes(void *ctx, int64_t *passes) {
+  if (!ctx || !passes) return fail(KP_ERR_INVALID, "NULL argument");
+  *passes = ((const Ctx *)ctx)->batched_passes;
+  return KP_OK;
+}
+
+kp_status kp_stream_read(void *hip_stream, const void *src, size_t bytes, uint64_t *out) {
+  if (!src || !out) return fail(KP_ERR_INVALID, "NULL argument");
+  if (((uintptr_t)src & 15) != 0 || (bytes & 15) != 0)
+    return fail(KP_ERR_INVALID, "src must be 16-byte aligned and bytes a multiple of 16");
+  hipStream_t st = (hipStream_t)hip_stream;
+  HIP_TRY(kp_launch_stream_read(src, (int64_t)(bytes / 16), (unsigned long long *)out, 0, st));
   return KP_OK;
 }
 
@@ -1385,11 +1456,13 @@ kp_status plan_step(BatchPlan *p, int dir, double *stats_out, bool graph) {
     HIP_TRY(hipStreamSynchronize(s));
   }
   if (c->timing && e0 && e1) {
-    // the whole iteration (every pass and the search kernels between them)
+    // the whole iteration (every pass and the search kernels between them),
+    // with every input byte of every instance counted once
     (void)hipEventRecord(e1, s);
     c->ev_pending.push_back({e0, e1});
-    c->sweep_launches += passes;
-    c->sweep_bytes += passes * p->bytes;
+    c->sweep_launches += 1;
+    c->sweep_bytes += p->bytes;
+    c->batched_passes += passes;
     if (c->ev_pending.size() > 256) drain_events(c, true);
   }
   if (stats_out)
@@ -1417,8 +1490,9 @@ kp_status plan_create(Ctx *c, const kp_problem *probs, int n, const double *cons
   for (int s = 0; s < n; ++s) {
     kp_status st = prepare(&probs[s], true, P[s], c);
     if (st != KP_OK) {
-      std::string m = g_err;
-      return fail(st, "instance %d: %s", s, m.c_str());
+      char m[sizeof g_err];
+      memcpy(m, g_err, sizeof m);
+      return fail(st, "instance %d: %s", s, m);
     }
     if (!lam_a[s] || !lam_b[s]) return fail(KP_ERR_INVALID, "instance %d: lambda is NULL", s);
   }

@@ -91,6 +91,7 @@ struct EllGeom {
 // items with p~ > 0, perm the items ranked by (p~ desc, index asc).
 template <int D>
 __device__ __forceinline__ void scd_user(const SweepArgs &a, int M, int K, int L, int lane, bool act,
+                                         int alg5q, int64_t uidx,
                                          uint64_t S, uint64_t pos, uint64_t perm, double bmax,
                                          const double *ptl, const float *btl, const uint8_t *ktl,
                                          const uint16_t *mskl, const double *lam, const uint64_t *tmask,
@@ -191,6 +192,17 @@ __device__ __forceinline__ void scd_user(const SweepArgs &a, int M, int K, int L
     }
     zlev |= S & ~resolved;
   }
+  // Alg.5 (Sec. 5.1; a user whose item j consumes only knapsack j, M = K,
+  // one top-Q set): the Q-th and (Q+1)-th largest adjusted profits
+  // max(p~, 0) are read off the rank order Alg.1 already holds (0 past the
+  // last item); item k's only breakpoint is where its line p_k - lambda b_kk
+  // meets the (Q+1)-th when k is in the top Q (ties with the Q-th count as
+  // in it), else the Q-th
+  double qth = 0.0, q1th = 0.0;
+  if (alg5q > 0) {
+    if (alg5q <= M) qth = fmax(ptl[(int)((perm >> (4 * (alg5q - 1))) & 15) * 64 + lane], 0.0);
+    if (alg5q + 1 <= M) q1th = fmax(ptl[(int)((perm >> (4 * alg5q)) & 15) * 64 + lane], 0.0);
+  }
   // one breakpoint per (item, knapsack) that moves alone; queue the others
   uint64_t pending = 0;
   for (int j = 0; j < M; ++j) {
@@ -210,7 +222,15 @@ __device__ __forceinline__ void scd_user(const SweepArgs &a, int M, int K, int L
       const double add_o = lk * bo_d;
       const double co = ptl[j * 64 + lane] + add_o;
       double best = 0.0;
-      if (zlev >> j & 1) {
+      if (alg5q > 0) {
+        const double pk = (double)a.pr.p[uidx * M + j];
+        const double adj = fmax(ptl[j * 64 + lane], 0.0);
+        const double pbar = adj >= qth ? q1th : qth;
+        if (pk > pbar && bo_d > 0.0) {
+          const double num = pk - pbar;
+          best = num / bo_d;
+        }
+      } else if (zlev >> j & 1) {
         if (co > 0.0) best = co / bo_d;
       } else {
         const int th = (int)((tau >> (4 * j)) & 15);
@@ -823,7 +843,14 @@ k_ell(const SweepArgs a, const EllGeom g) {
           }
         }
       }
-      scd_user<D>(a, M, K, L, lane, act, S, pos, perm, bmax, ptl, btl, ktl, mskl, lam, tmask, tcap, kst,
+      // Alg.5's setting for this user: item j's only entry is knapsack j
+      bool diag = D == 1 && a.alg5_q > 0;
+      #pragma unroll
+      for (int j = 0; j < EM; ++j)
+        if (j < M) diag = diag && cl[j * D] == j;
+      const int64_t uidx = STAGED ? u0 + lane : (act ? (int64_t)a.flist[u0 + lane] : 0);
+      scd_user<D>(a, M, K, L, lane, act, diag ? a.alg5_q : 0, uidx, S, pos, perm, bmax, ptl, btl, ktl, mskl,
+                  lam, tmask, tcap, kst,
                   kmode, hwin, kcorr, hs, hc, hmin, hmax, kcnt, kovf, nstage);
       __builtin_amdgcn_s_waitcnt(0);
       __builtin_amdgcn_wave_barrier();

@@ -56,6 +56,7 @@ enum {
 };
 
 #define KS_FLAG_WINDOW 1u  // the key range of KS_SELECT_RANGE is a window: the threshold may lie outside
+#define KS_FLAG_INTERP 2u  // approximate reduce: interpolate inside the bucket that holds the threshold
 
 struct KState {
   int mode;
@@ -112,4 +113,7 @@ struct SweepArgs {
   unsigned int *flist;     // [fcap] user indices
   unsigned int *fcount;    // [0] reserved list slots (atomic; may exceed fcap), [1] listed users
   unsigned int fcap;
+  // Alg.5 map (uniform-row kernel, one entry per item row): Q of the single
+  // top-Q set, for users whose item j consumes only knapsack j (M = K); 0 = off
+  int alg5_q;
 };

@@ -893,7 +893,7 @@ __device__ __forceinline__ void choose_window(KState &s, double step, double pre
 }
 
 __global__ void k_scd_init(KState *st, int K, const double *lam_in, const uint8_t *kmask,
-                           double *hist, int hinted_in, int window) {
+                           double *hist, int hinted_in, int window, int interp) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= K) return;
   KState s;
@@ -918,7 +918,12 @@ __global__ void k_scd_init(KState *st, int K, const double *lam_in, const uint8_
     hist[3 * K + k] = prev;
     hist[2 * K + k] = lam_in[k];
   }
-  if (!hinted) {
+  if (interp) {
+    // interpolated reduce: a fixed fine central bucket, 2^-20 of the
+    // multiplier (of 2^-20 when it is smaller), a power of two
+    const double base = lam_in[k] > 0x1p-20 ? lam_in[k] : 0x1p-20;
+    d = ldexp(1.0, ilogb(base) - 20);
+  } else if (!hinted) {
     // no history: 2^-10 of the multiplier (or 2^-30 absolute), a power of two
     const double base = lam_in[k] > 0x1p-20 ? lam_in[k] : 0x1p-20;
     d = ldexp(1.0, ilogb(base) - 10);
@@ -937,7 +942,8 @@ __global__ void k_scd_init(KState *st, int K, const double *lam_in, const uint8_
   s.eoff = 0;
   s.ecap = 0;
   s.pad2 = 0;
-  if (window && hinted && s.mode == KS_EXP) choose_window(s, delta_hint[K + k], prev, drift);
+  if (interp) s.flags = KS_FLAG_INTERP;
+  else if (window && hinted && s.mode == KS_EXP) choose_window(s, delta_hint[K + k], prev, drift);
   st[k] = s;
 }
 
@@ -989,6 +995,26 @@ __global__ void k_scd_locate(KState *st, int K, const double *B, const double *R
       }
       s.bstar = bin - 32;
       s.F_above = cum;
+      if (s.flags & KS_FLAG_INTERP) {
+        // Sec. 5.2's approximate reduce: the bucket's increments spread
+        // linearly over its interval [lo, hi] (lo clamped at 0)
+        const int id = bin - 32;
+        const double c = s.center, d = s.delta;
+        double lo, hi;
+        if (id == 0) { lo = c - d; hi = c + d; }
+        else if (id > 0) { lo = c + ldexp(d, id - 1); hi = c + ldexp(d, id); }
+        else { lo = c - ldexp(d, -id); hi = c - ldexp(d, -id - 1); }
+        lo = fmax(lo, 0.0);
+        const double frac = (Bk - cum) / hsum[bin];
+        const double width = hi - lo;
+        const double prod = frac * width;
+        const double v = hi - prod;
+        s.mode = KS_DONE;
+        s.result = fmax(v, lo);
+        st[k] = s;
+        for (int b = 0; b < KP_NB; ++b) { hist_sum[(size_t)k * KP_NB + b] = 0.0; hist_cnt[(size_t)k * KP_NB + b] = 0u; }
+        return;
+      }
       const bool central = s.bstar >= -KP_CENTRAL_W && s.bstar <= KP_CENTRAL_W;
       if (central && !s.overflow) {
         s.mode = KS_SELECT_BUCKET;
@@ -1944,9 +1970,9 @@ hipError_t kp_launch_reduce_stats(const double *partials, int nblk, int K, const
 }
 
 hipError_t kp_launch_scd_init(KState *st, int K, const double *lam_in, const uint8_t *kmask,
-                              double *hist, int hinted, int window, hipStream_t stream) {
+                              double *hist, int hinted, int window, int interp, hipStream_t stream) {
   hipLaunchKernelGGL(k_scd_init, dim3((K + 63) / 64), dim3(64), 0, stream, st, K, lam_in, kmask,
-                     hist, hinted, window);
+                     hist, hinted, window, interp);
   return hipGetLastError();
 }
 
@@ -2032,5 +2058,55 @@ hipError_t kp_launch_validate_csr(const int64_t *rowptr, const int32_t *col, int
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(k_validate_csr, dim3((unsigned)blocks), dim3(256), 0, stream, rowptr, col,
                      nrows, K, flags);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Streaming-read probe: the achievable HBM read bandwidth for a buffer of
+// the sweep's size (the ceiling its roofline fraction is also quoted
+// against).  Every thread reads 16-byte words with four loads in flight,
+// folds them with XOR (so no load is dead) and every block XORs its result
+// into one word; XOR is order-free, so the word is deterministic.
+// ---------------------------------------------------------------------------
+#define SR_NT 256
+__global__ void __launch_bounds__(SR_NT) k_stream_read(const uint4 *src, int64_t n16, unsigned long long *out) {
+  uint4 acc = make_uint4(0u, 0u, 0u, 0u);
+  const int64_t stride = (int64_t)gridDim.x * SR_NT;
+  int64_t i = (int64_t)blockIdx.x * SR_NT + threadIdx.x;
+  for (; i + 3 * stride < n16; i += 4 * stride) {
+    const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+    acc.x ^= a.x ^ b.x ^ c.x ^ d.x;
+    acc.y ^= a.y ^ b.y ^ c.y ^ d.y;
+    acc.z ^= a.z ^ b.z ^ c.z ^ d.z;
+    acc.w ^= a.w ^ b.w ^ c.w ^ d.w;
+  }
+  for (; i < n16; i += stride) {
+    const uint4 a = src[i];
+    acc.x ^= a.x; acc.y ^= a.y; acc.z ^= a.z; acc.w ^= a.w;
+  }
+  unsigned long long v = ((unsigned long long)(acc.x ^ acc.z) << 32) | (unsigned long long)(acc.y ^ acc.w);
+  for (int off = 32; off > 0; off >>= 1) v ^= __shfl_xor(v, off, 64);
+  __shared__ unsigned long long part[SR_NT / 64];
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int w = 0; w < SR_NT / 64; ++w) t ^= part[w];
+    atomicXor(out, t);
+  }
+}
+
+// The resident blocks of the probe (at most `grid` when grid > 0).
+hipError_t kp_launch_stream_read(const void *src, int64_t n16, unsigned long long *out, int grid,
+                                 hipStream_t stream) {
+  int per_cu = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_stream_read, SR_NT, 0) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 8;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    cus = 256;
+  int g = per_cu * cus;
+  if (grid > 0 && grid < g) g = grid;
+  hipLaunchKernelGGL(k_stream_read, dim3(g), dim3(SR_NT), 0, stream, (const uint4 *)src, n16, out);
   return hipGetLastError();
 }

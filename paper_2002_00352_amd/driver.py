@@ -43,16 +43,23 @@ class DualFn:
 
 
 def solve(prob, method: str = "scd", lam0=None, tol: float = 1e-3, max_iter: int = 100,
-          alpha: float = 1e-3, block: int = 1, log=None, presolve_users=None, presolve_iter: int = 30):
+          alpha: float = 1e-3, block: int = 1, log=None, presolve_users=None, presolve_iter: int = 30,
+          ctx=None):
     """Iterate until the relative duality gap (best dual - best feasible
     primal) / |best feasible primal| <= tol, lambda stops changing, or
-    max_iter.  method: "scd" | "cyclic" | "block" | "dd".  The feasible primal
+    max_iter.  method: "scd" | "cyclic" | "block" | "interp" (synchronous CD
+    with Sec. 5.2's interpolated reduce, on a context of its own unless ctx
+    is given) | "dd".  The feasible primal
     of an iterate is P(x) when x already meets every budget, else the
     post-processed value.  presolve_users: sampled users whose pre-solve
     (Sec. 5.3) replaces lam0 as the starting point.  Returns (lambda, history)."""
     import torch
-    from . import kp_scd_sweep, kp_dd_step, kp_primal_fixup, kp_presolve
+    from . import Context, kp_scd_sweep, kp_dd_step, kp_primal_fixup, kp_presolve
     K = prob.K
+    sweep_ctx = ctx
+    if method == "interp" and sweep_ctx is None:
+        sweep_ctx = Context()
+        sweep_ctx.set_reduce("interp")
     B = prob.B
     lam = torch.zeros(K, dtype=torch.float64, device="cuda") if lam0 is None else \
         torch.as_tensor(np.asarray(lam0, np.float64)).to("cuda").clone()
@@ -73,7 +80,7 @@ def solve(prob, method: str = "scd", lam0=None, tol: float = 1e-3, max_iter: int
                 w = 1 if method == "cyclic" else block
                 kmask = np.zeros(K, np.uint8)
                 kmask[[(t * w + q) % K for q in range(w)]] = 1
-            st = kp_scd_sweep(prob, lam, kmask=kmask)
+            st = kp_scd_sweep(prob, lam, kmask=kmask, ctx=sweep_ctx)
             new = st["lam"]
             lam_t = lam
         R = st["R"].cpu().numpy()
@@ -94,7 +101,7 @@ def solve(prob, method: str = "scd", lam0=None, tol: float = 1e-3, max_iter: int
             log(rec)
         if gap <= tol:
             return lam_t, hist
-        if method in ("scd", "dd") and torch.equal(new, lam_t):
+        if method in ("scd", "dd", "interp") and torch.equal(new, lam_t):
             return lam_t, hist
         lam = new.clone() if method != "dd" else new
     return lam, hist

@@ -126,6 +126,63 @@ def test_scd_masked_cyclic_parity():
 
 
 @gpu
+def test_cd_modes_trajectories():
+    """Cyclic and block coordinate descent (Sec. 4.3.2) along whole driver
+    trajectories from lambda = 0 on the dense (general kernel) and the
+    hierarchical sparse (uniform-row kernel) workloads: every update equals
+    the oracle's masked sweep of the same coordinates bit for bit."""
+    kp, torch = _kp()
+    for inst in (kpgen.config_instance(2, N=3000), kpgen.config_instance(3, N=4000)):
+        prob = kp.Problem.from_host(inst)
+        K = inst.K
+        for w in (1, 4, K // 2):
+            ctx = kp.Context()
+            lam = np.zeros(K)
+            for t in range(6):
+                ks = [(t * w + q) % K for q in range(w)]
+                mask = np.zeros(K, np.uint8)
+                mask[ks] = 1
+                got = kp.kp_scd_sweep(prob, _lamd(torch, lam), kmask=mask, ctx=ctx)["lam"].cpu().numpy()
+                want = oracle.scd_sweep(inst, lam, ks=ks)
+                assert np.array_equal(got, want), (inst.name, w, t)
+                lam = want
+
+
+INTERP_CASES = [
+    ("c1-dense", lambda: kpgen.config_instance(1, N=6000)),
+    ("c3-csr-uniform-rows", lambda: kpgen.config_instance(3, N=20000)),
+    ("c2-dense-general", lambda: kpgen.config_instance(2, N=3000)),
+]
+
+
+@gpu
+@pytest.mark.parametrize("name,mk", INTERP_CASES, ids=[c[0] for c in INTERP_CASES])
+def test_interp_reduce_trajectory(name, mk):
+    """Sec. 5.2's interpolated reduce on the GPU (kp_set_reduce): along a
+    trajectory from lambda = 0, every update equals the oracle's interpolated
+    SCD (the same buckets around lambda^t and central half-widths) bit for
+    bit, and so do the drivers' iterates."""
+    kp, torch = _kp()
+    print("case", name, flush=True)
+    inst = mk()
+    prob = kp.Problem.from_host(inst)
+    ctx = kp.Context()
+    ctx.set_reduce("interp")
+    lam = np.zeros(inst.K)
+    for t in range(8):
+        want = oracle.scd_sweep_interp(inst, lam)
+        got = kp.kp_scd_sweep(prob, _lamd(torch, lam), ctx=ctx)["lam"].cpu().numpy()
+        assert np.array_equal(got, want), (t, np.flatnonzero(got != want), got, want)
+        lam = want
+    if name == "c1-dense":
+        # the drivers' iterates agree at every step they share
+        _, h = kp.solve(prob, "interp", tol=1e-3, max_iter=30)
+        ref = oracle.solve(inst, "interp", tol=1e-3, max_iter=30)
+        for a, b in zip(h, ref):
+            assert np.array_equal(a["lam"], b["lam"])
+
+
+@gpu
 def test_dual_autograd_matches_oracle_gradient():
     kp, torch = _kp()
     inst = kpgen.config_instance(4, N=3000)
@@ -612,6 +669,42 @@ def test_alg5_setting_scd_trajectory(K, Q):
     print("window searches", ctxs[0].window_stats(), flush=True)
 
 
+def _ulps(a, b):
+    return abs(int(np.float64(a).view(np.int64)) - int(np.float64(b).view(np.int64)))
+
+
+@gpu
+@pytest.mark.parametrize("K,Q", [(10, 3), (7, 2), (6, 6)])
+def test_alg5_map_trajectory(K, Q):
+    """Alg.5's map on the GPU (kp_set_alg5, Sec. 5.1): its SCD updates equal
+    the oracle's SCD with Alg.5's map bit for bit, window on and off, along a
+    trajectory; cross-checked against the general map (the event walk's
+    threshold-element path) from the same multipliers: every coordinate
+    within a few ulp, zero where it is zero."""
+    kp, torch = _kp()
+    print("case alg5 map K", K, "Q", Q, flush=True)
+    inst = _alg5_instance(6001, K, Q, seed=60 + K)
+    prob = kp.Problem.from_host(inst.to_csr())
+    assert prob.row_nnz == 1
+    ctxs = [kp.Context(), kp.Context()]
+    for c in ctxs:
+        c.set_alg5(True)
+    ctxs[1].set_window(False)
+    general = kp.Context()
+    lam = np.zeros(K)
+    for t in range(8):
+        want = oracle.scd_sweep_alg5(inst, lam, Q)
+        for ctx in ctxs:
+            got = kp.kp_scd_sweep(prob, _lamd(torch, lam), ctx=ctx)["lam"].cpu().numpy()
+            assert np.array_equal(got, want), (t, np.flatnonzero(got != want))
+        gen = kp.kp_scd_sweep(prob, _lamd(torch, lam), ctx=general)["lam"].cpu().numpy()
+        assert np.array_equal(gen, oracle.scd_sweep(inst, lam)), t
+        assert np.array_equal(gen == 0, want == 0), t
+        assert max(_ulps(x, y) for x, y in zip(gen, want)) <= 16, (t, gen, want)
+        lam = want
+    print("window searches", ctxs[0].window_stats(), flush=True)
+
+
 @gpu
 @pytest.mark.parametrize("c,N", [(1, 10_000), (2, 2049), (3, 3001), (4, 700)])
 def test_device_generator_matches_host(c, N):
@@ -686,26 +779,69 @@ def test_full_size_scd_sampled_parity(c):
 
 
 @gpu
-def test_full_size_autograd_sampled_parity():
-    """Configuration 4 at full size (N = 1e7, M = 20, K = 50): sampled users'
-    decisions at a random lambda equal the oracle's and the autograd gradient
-    is B - R."""
+def test_config4_autograd_as_specified():
+    """Configuration 4 at full size (N = 1e7, M = 20, K = 50, 41 GB) as
+    specified.  The autograd dual (DualFn) at 64 multipliers drawn
+    U(0, 0.5)^K, which price every item out (x = 0, R = 0, g = lambda.B and
+    the gradient is B exactly), and at 64 drawn U(0, 1/K)^K (reading A21): the
+    gradient is B - R of the same evaluation, sampled users' decisions equal
+    the oracle's (so do their consumptions), and the finite-difference
+    convexity bracket (reading A15) holds for the GPU's own g along a random
+    direction d at h = 1e-4:
+        grad(lam - h d).d <= (g(lam + h d) - g(lam - h d)) / 2h <= grad(lam + h d).d
+    (up to the FP64 rounding of g).  Then 200 dual-descent steps (Eq.14, step
+    per reading A14) driven by the autograd gradient equal kp_dd_step's
+    iterates bit for bit."""
     kp, torch = _kp()
     from kpgen import device as kgd
     print("config 4 full size", flush=True)
     arrs, B, tree, meta, prob = _full_size_problem(kp, 4)
     N, M, K = meta["N"], meta["M"], meta["K"]
-    lam_np = kpgen.random_lambdas(4000, 1, K, 1.0 / K)[0]
-    lam = torch.tensor(lam_np, device="cuda", requires_grad=True)
-    g = kp.DualFn.apply(lam, prob)
-    g.backward()
-    ev = kp.kp_eval_dual(prob, _lamd(torch, lam_np), want_x=True)
-    assert np.array_equal(lam.grad.cpu().numpy(), np.asarray(B) - ev["R"].cpu().numpy())
+    Bv = np.asarray(B, np.float64)
     users = np.sort(np.random.default_rng(8).choice(N, 2048, replace=False))
     sub = kgd.host_users(meta, B, tree, users)
-    ref = oracle.eval_dual(sub, lam_np)
-    xg = ev["x"].view(N, M)[torch.from_numpy(users).cuda()].cpu().numpy().reshape(-1)
-    assert np.array_equal(xg, ref["x"])
+    uidx = torch.from_numpy(users).cuda()
+    h = 1e-4
+    rng = np.random.default_rng(44)
+
+    def dual(lam_np):
+        lam = torch.tensor(lam_np, dtype=torch.float64, device="cuda", requires_grad=True)
+        g = kp.DualFn.apply(lam, prob)
+        g.backward()
+        return g.item(), lam.grad.cpu().numpy()
+
+    pts = [("U(0,0.5)", l) for l in kpgen.random_lambdas(4100, 64, K, 0.5)] + \
+          [("U(0,1/K)", l) for l in kpgen.random_lambdas(4101, 64, K, 1.0 / K)]
+    for t, (kind, lam_np) in enumerate(pts):
+        g, grad = dual(lam_np)
+        ev = kp.kp_eval_dual(prob, _lamd(torch, lam_np), want_x=True)
+        R = ev["R"].cpu().numpy()
+        assert np.array_equal(grad, Bv - R), (kind, t)
+        xg = ev["x"].view(N, M)[uidx].cpu().numpy().reshape(-1)
+        assert np.array_equal(xg, oracle.eval_dual(sub, lam_np)["x"]), (kind, t)
+        if kind == "U(0,0.5)":
+            assert not R.any() and np.array_equal(grad, Bv) and ev["P"].item() == 0.0, t
+        d = rng.uniform(-1.0, 1.0, K)
+        d[lam_np < 2 * h] = 0.0
+        gp, grp = dual(lam_np + h * d)
+        gm, grm = dual(lam_np - h * d)
+        fd = (gp - gm) / (2 * h)
+        slack = 1e-12 * (abs(gp) + abs(gm)) / h + 1e-12 * float(np.abs(grad * d).sum())
+        assert float(grm @ d) - slack <= fd <= float(grp @ d) + slack, (kind, t, float(grm @ d), fd, float(grp @ d))
+    # 200 DD steps: autograd-driven and kp_dd_step from the same start
+    alpha = 1e-3 * 1e4 / N
+    lam0 = kpgen.random_lambdas(4102, 1, K, 1.0 / K)[0]
+    a = torch.tensor(lam0, dtype=torch.float64, device="cuda")
+    b = a.clone()
+    for step in range(200):
+        l = a.clone().requires_grad_(True)
+        kp.DualFn.apply(l, prob).backward()
+        with torch.no_grad():
+            a = torch.clamp(l - alpha * l.grad, min=0.0)
+        kp.kp_dd_step(prob, alpha, b)
+        if step % 50 == 49:
+            assert np.array_equal(a.cpu().numpy(), b.cpu().numpy()), step
+    assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
 
 
 @gpu

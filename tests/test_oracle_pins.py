@@ -208,6 +208,77 @@ def test_scd_map_alg5_special_case():
             assert float(v2[m][0]) == float(d)
 
 
+def _alg5_inst(rng, N, K, Q):
+    p = rng.integers(1, 1 << 24, (N, K)) / float(1 << 24)
+    b = np.zeros((N, K, K))
+    for k in range(K):
+        b[:, k, k] = rng.integers(1, 1 << 24, N) / float(1 << 24)
+    return make(p, b, 0.15 * b.sum(axis=(0, 1)), kpgen.tree_topq(K, Q))
+
+
+@pytest.mark.parametrize("K,Q", [(6, 2), (10, 3), (5, 5), (1, 1)])
+def test_scd_sweep_alg5_matches_general_sweep(K, Q):
+    """SCD with Alg.5's map (Sec. 5.1) lands on the general SCD update up to
+    the rounding of the breakpoints' intercepts: every coordinate within a
+    few ulp, zero where the general update is zero, along a trajectory."""
+    rng = np.random.default_rng(100 + K)
+    inst = _alg5_inst(rng, 300, K, Q)
+    lam = np.zeros(K)
+    for t in range(5):
+        a5 = oracle.scd_sweep_alg5(inst, lam, Q)
+        gen = oracle.scd_sweep(inst, lam)
+        assert np.array_equal(a5 == 0, gen == 0), (t, a5, gen)
+        for x, y in zip(a5, gen):
+            assert _ulps(float(x), float(y)) <= 16, (t, x, y)
+        lam = gen if t % 2 else rng.random(K) * 0.6
+
+
+def test_interp_reduce_hand_example():
+    """Sec. 5.2's bucket interpolation on a hand-worked case.  Centre 1.0,
+    half-width 0.25: breakpoint 2.0 (increment 1) has |d| = 1 = 4 delta, so
+    bucket 3 = [1 + 0.25*4, 1 + 0.25*8) = [2, 3); breakpoint 1.1 (increment
+    2) is in the central bucket [0.75, 1.25].  With B = 2 the running sum
+    from the top is 1 after bucket 3 and 3 after the central one, so the
+    threshold is in the central bucket, half way: 1.25 - (2 - 1)/2 * 0.5 =
+    1.0 (the exact reduce gives the breakpoint 1.1).  Below the centre:
+    breakpoints 0.5 and 0.2 (increment 1 each), B = 0.5: |d| = 0.5 and 0.8
+    are both in [2 delta, 4 delta), bucket -2 = [1 - 0.25*4, 1 - 0.25*2] =
+    [0, 0.5] with sum 2, so 0.5 - (0.5 / 2) * 0.5 = 0.375."""
+    assert oracle.scd_reduce_interp([2.0, 1.1], [1.0, 2.0], 2.0, 1.0, 0.25) == 1.0
+    assert oracle.scd_reduce([2.0, 1.1], [1.0, 2.0], 2.0) == 1.1
+    assert oracle.scd_reduce_interp([0.5, 0.2], [1.0, 1.0], 0.5, 1.0, 0.25) == 0.375
+    assert oracle.scd_reduce_interp([0.5, 0.2], [1.0, 1.0], 2.0, 1.0, 0.25) == 0.0   # total fits
+
+
+def test_interp_reduce_brackets_the_exact_threshold():
+    """The interpolated threshold lies in the bucket interval that holds the
+    exact threshold of Alg.4's reduce (both lie where the running sum crosses
+    B_k), on random breakpoint sets on the 2^-24 grid."""
+    rng = np.random.default_rng(17)
+    for _ in range(300):
+        n = int(rng.integers(1, 80))
+        v1 = rng.integers(1, 1 << 24, n) / float(1 << 22)
+        v2 = rng.integers(1, 1 << 20, n) / float(1 << 24)
+        Bk = float(rng.random() * v2.sum() * 1.1)
+        c = float(rng.integers(1, 1 << 20) / float(1 << 18))
+        delta = 2.0 ** int(rng.integers(-12, 0))
+        exact = oracle.scd_reduce(v1, v2, Bk)
+        approx = oracle.scd_reduce_interp(v1, v2, Bk, c, delta)
+        if exact == 0.0:
+            assert approx == 0.0
+            continue
+        b = int(oracle._bucket_ids([exact], c, delta)[0])
+        if b == 0:
+            lo, hi = c - delta, c + delta
+        elif b > 0:
+            lo, hi = c + math.ldexp(delta, b - 1), c + math.ldexp(delta, b)
+        else:
+            lo, hi = c - math.ldexp(delta, -b), c - math.ldexp(delta, -b - 1)
+        lo = max(lo, 0.0)
+        if abs(b) < 31:
+            assert lo - 1e-12 <= approx <= hi + 1e-12, (exact, approx, lo, hi, b)
+
+
 # ---------------------------------------------------------- SCD Reduce -----
 
 def test_scd_reduce_vs_sort_and_scan():
@@ -228,6 +299,44 @@ def test_scd_reduce_vs_sort_and_scan():
                     want = v
                     break
         assert oracle.scd_reduce(v1, v2, Bk) == want
+
+
+def test_scd_reduce_sums_exactly():
+    """The reduce compares exact sums of the increments with B_k (the total
+    resource a threshold lets through), whatever their magnitudes: against a
+    sort-and-scan in rational arithmetic on increments spread over sixteen
+    decades and budgets placed within rounding of a running sum, where a
+    running FP64 sum would decide the other way, and on a two-term case
+    worked by hand (2^53 + 1 exceeds a budget of 2^53; in FP64 it rounds to
+    2^53 and would not)."""
+    assert oracle.scd_reduce([2.0, 1.0], [2.0 ** 53, 1.0], 2.0 ** 53) == 1.0
+    assert oracle.scd_reduce([2.0, 1.0], [2.0 ** 53, 1.0], 2.0 ** 53 + 2.0) == 0.0
+    rng = np.random.default_rng(31)
+    flips = 0
+    for _ in range(300):
+        n = int(rng.integers(2, 40))
+        v1 = rng.integers(1, 12, n) / 4.0
+        v2 = 10.0 ** rng.uniform(-8, 8, n)
+        order = np.argsort(-v1, kind="stable")
+        keys = sorted(set(v1.tolist()), reverse=True)
+        exact_cum = [sum(Fraction(d) for a, d in zip(v1, v2) if a >= v) for v in keys]
+        j = int(rng.integers(0, len(keys)))
+        Bk = float(exact_cum[j]) * (1.0 + float(rng.integers(-2, 3)) * 2.0 ** -52)
+        total = sum(Fraction(d) for d in v2)
+        if total <= Fraction(Bk):
+            want = 0.0
+        else:
+            want = next(v for v, c in zip(keys, exact_cum) if c > Fraction(Bk))
+        fp = 0.0
+        for v in keys:
+            for a, d in zip(v1, v2):
+                if a == v:
+                    fp = fp + d
+            if fp > Bk:
+                break
+        flips += (v if fp > Bk else 0.0) != want
+        assert oracle.scd_reduce(v1, v2, Bk) == want
+    assert flips > 0   # the cases do exercise sums that FP64 rounds the other way
 
 
 @pytest.mark.parametrize("hier", [False, True])
