@@ -104,6 +104,24 @@ kp_status kp_set_stream(void *ctx, void *hip_stream);
 kp_status kp_eval_dual(void *ctx, const kp_problem *prob, const double *lambda,
                        double *R, double *g, double *primal, uint8_t *x);
 
+/* kp_eval_dual for callers that cannot allocate device memory (code under
+   HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+   the same evaluation and the same outputs, with no context and no
+   workspace.  It calls no hipMalloc, hipFree or other allocating routine;
+   its scratch memory (the budgets and one row of K + 2 partial sums per
+   block) is a static 8 MiB device array that every GPU the library runs on
+   holds until the process ends.  Work is enqueued on hip_stream (hipStream_t
+   as void*, NULL = the null stream); lambda, R, g, primal (DEV, none NULL)
+   and x (DEV or NULL) as in kp_eval_dual.  Every call on one GPU shares that
+   GPU's scratch array, which keeps the last call's contents: calls that
+   overlap on one GPU (on different streams or host threads) race, so the
+   caller serialises them.  KP_ERR_UNSUPPORTED when the K + 2 partial sums of
+   one block do not fit the scratch array (K above about a million); the
+   grid is reduced to what fits.  Costs declared with b_row_nnz use the
+   lean per-user kernel; nothing is tuned. */
+kp_status kp_eval_dual_noalloc(void *hip_stream, const kp_problem *prob, const double *lambda,
+                               double *R, double *g, double *primal, uint8_t *x);
+
 /* One synchronous coordinate-descent iteration (Alg.4 with Alg.3's
    candidates): for every knapsack k, the consumption step function of every
    user as lambda_k alone moves (lines c_j - lambda_k b_ijk with

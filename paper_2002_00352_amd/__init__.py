@@ -78,7 +78,7 @@ EXPORTS = ["kp_last_error", "kp_create", "kp_destroy", "kp_set_stream", "kp_eval
            "kp_batched_create", "kp_batched_step", "kp_batched_destroy", "kp_set_tuning",
            "kp_set_kernel_choice", "kp_csr_row_nnz", "kp_set_window",
            "kp_get_window_stats", "kp_presolve", "kp_get_window_listed", "kp_get_launch_shape",
-           "kp_set_batched_tuning", "kp_batched_shape", "kp_get_batched_passes",
+           "kp_set_batched_tuning", "kp_batched_shape", "kp_eval_dual_noalloc", "kp_get_batched_passes",
            "kp_stream_read", "kp_set_alg5", "kp_set_reduce"]
 
 
@@ -96,6 +96,7 @@ def lib():
         L.kp_destroy.argtypes = [vp]
         L.kp_set_stream.argtypes = [vp, vp]
         L.kp_eval_dual.argtypes = [vp, P, vp, vp, vp, vp, vp]
+        L.kp_eval_dual_noalloc.argtypes = [vp, P, vp, vp, vp, vp, vp]
         L.kp_scd_sweep.argtypes = [vp, P, vp, vp, vp, vp, vp]
         L.kp_scd_sweep_masked.argtypes = [vp, P, vp, vp, vp, vp, vp, vp]
         L.kp_dd_step.argtypes = [vp, P, d, vp, vp, vp, vp]
@@ -315,6 +316,15 @@ def kp_eval_dual(prob: Problem, lam, want_x: bool = False, ctx: Optional[Context
     R, g, P = _dev_f64(prob.K), _dev_f64(1), _dev_f64(1)
     x = torch.empty(prob.N * prob.M, dtype=torch.uint8, device="cuda") if want_x else None
     _check(lib().kp_eval_dual(ctx.h, prob.ref, _ptr(lam), _ptr(R), _ptr(g), _ptr(P), _ptr(x)))
+    return dict(R=R, g=g, P=P, x=x)
+
+
+def kp_eval_dual_noalloc(prob: Problem, lam, R, g, P, x=None):
+    """The allocation-free evaluation on the current torch stream into
+    caller-provided tensors R [K], g [1], P [1] (FP64) and x (uint8 [N*M])
+    or None."""
+    _check(lib().kp_eval_dual_noalloc(_stream_handle(), prob.ref, _ptr(lam), _ptr(R), _ptr(g), _ptr(P),
+                                      _ptr(x)))
     return dict(R=R, g=g, P=P, x=x)
 
 

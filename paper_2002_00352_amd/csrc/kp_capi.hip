@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <string>
 #include <vector>
@@ -69,6 +70,7 @@ void kp_coldesc_fill(void *dst, const double *partials, const double *lam, const
 
 hipError_t kp_launch_validate_csr(const int64_t *rowptr, const int32_t *col, int64_t nrows, int K,
                                   unsigned int *flags, hipStream_t stream);
+hipError_t kp_launch_fill_f64(double *dst, int64_t n, double v, hipStream_t stream);
 hipError_t kp_launch_stream_read(const void *src, int64_t n16, unsigned long long *out, int grid,
                                  hipStream_t stream);
 
@@ -704,6 +706,39 @@ kp_status eval_into(Ctx *c, const Prepared &P, const SweepWs &w, const double *l
   return KP_OK;
 }
 
+}  // namespace
+
+// ---- scratch of the allocation-free entry point ----
+// Device memory for kp_eval_dual_noalloc: the budgets and the per-block
+// partial sums.  Every GPU the library runs on holds its own copy for the
+// life of the process; host code reaches it only through the address that
+// hipGetSymbolAddress returns for the current device (the array's name is a
+// host-side stand-in, not a device address).
+#define KP_NOALLOC_SCRATCH (8u << 20)
+#define KP_MAX_DEVICES 64
+static __device__ __align__(256) unsigned char scratch[KP_NOALLOC_SCRATCH];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[KP_MAX_DEVICES] = {};
+
+// The scratch array's device address on the current device (looked up once
+// per device, with that device current).
+kp_status noalloc_scratch(void **out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= KP_MAX_DEVICES) return fail(KP_ERR_UNSUPPORTED, "device %d above the limit %d", dev, KP_MAX_DEVICES);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(KP_ERR_HIP, "hipGetSymbolAddress of the scratch array failed: %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return KP_OK;
+}
 }  // namespace
 
 // ===========================================================================
@@ -1815,6 +1850,57 @@ kp_status kp_batched_shape(void *plan, int32_t *blocks, int32_t *lds_bytes, int3
 
 kp_status kp_batched_destroy(void *plan) {
   plan_free((BatchPlan *)plan);
+  return KP_OK;
+}
+
+kp_status kp_eval_dual_noalloc(void *hip_stream, const kp_problem *prob, const double *lambda,
+                               double *R, double *g, double *primal, uint8_t *x) {
+  if (!lambda || !R || !g || !primal) return fail(KP_ERR_INVALID, "lambda, R, g and primal must not be NULL");
+  Prepared P;
+  kp_status s = prepare(prob, false, P, nullptr);
+  if (s != KP_OK) return s;
+  const int K = P.pr.K;
+  // scratch layout: budgets [K], then one [K + 2] row of partial sums per block
+  const size_t off_part = ((size_t)K * 8 + 255) & ~(size_t)255;
+  const size_t row = (size_t)(K + 2) * 8;
+  if (off_part + row > KP_NOALLOC_SCRATCH)
+    return fail(KP_ERR_UNSUPPORTED, "K = %d needs more than the %u scratch bytes of kp_eval_dual_noalloc", K,
+                (unsigned)KP_NOALLOC_SCRATCH);
+  const int max_grid = (int)std::min<size_t>((KP_NOALLOC_SCRATCH - off_part) / row, (size_t)1 << 30);
+  void *scr = nullptr;
+  if ((s = noalloc_scratch(&scr)) != KP_OK) return s;
+  double *Bd = (double *)scr;
+  double *partials = (double *)((char *)scr + off_part);
+  hipStream_t st = (hipStream_t)hip_stream;
+  HIP_TRY(hipMemcpyAsync(Bd, P.B, (size_t)K * 8, hipMemcpyHostToDevice, st));
+  if (P.pr.N == 0) {
+    HIP_TRY(kp_launch_fill_f64(partials, K + 2, 0.0, st));
+    HIP_TRY(kp_launch_reduce_stats(partials, 1, K, lambda, Bd, R, g, primal, st));
+    return KP_OK;
+  }
+  SweepArgs a;
+  memset(&a, 0, sizeof(a));
+  a.pr = P.pr;
+  a.tree = P.tree;
+  a.lam = lambda;
+  a.want_stats = 1;
+  a.partials = partials;
+  a.x_out = x;
+  int used = 0;
+  const bool ell = P.row_nnz && P.pr.M <= 16 &&
+                   kp_ell_lds_bytes(P.pr.M, K, P.row_nnz, P.tree.L, 0, nullptr) <= kMaxLds;
+  if (ell) {
+    a.ntiles = (P.pr.N + 63) / 64;
+    const int res = kp_ell_resident_grid(P.row_nnz, 0, P.pr.M, K, P.tree.L);
+    if (res <= 0) return fail(KP_ERR_HIP, "occupancy query failed");
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((a.ntiles + 3) / 4,
+                                                                   std::min(std::min(res, kEllGrid), max_grid)));
+    HIP_TRY(kp_launch_ell(a, P.row_nnz, grid, 0, st, &used));
+  } else {
+    a.ntiles = P.ntiles;
+    HIP_TRY(kp_launch_sweep(a, P.U, std::min(P.grid, max_grid), false, st, &used));
+  }
+  HIP_TRY(kp_launch_reduce_stats(partials, used, K, lambda, Bd, R, g, primal, st));
   return KP_OK;
 }
 

@@ -2061,6 +2061,21 @@ hipError_t kp_launch_validate_csr(const int64_t *rowptr, const int32_t *col, int
   return hipGetLastError();
 }
 
+__global__ void k_fill_f64(double *dst, int64_t n, double v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = v;
+}
+
+// A fill kernel rather than hipMemsetAsync, for paths a caller may capture in
+// a HIP graph.
+hipError_t kp_launch_fill_f64(double *dst, int64_t n, double v, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)blocks), dim3(256), 0, stream, dst, n, v);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Streaming-read probe: the achievable HBM read bandwidth for a buffer of
 // the sweep's size (the ceiling its roofline fraction is also quoted
