@@ -28,7 +28,7 @@ hipError_t kp_launch_reduce_stats(const double *partials, int nblk, int K, const
 hipError_t kp_launch_scd_init(KState *st, int K, const double *lam_in, const uint8_t *kmask,
                               double *hist, int hinted, int window, int interp, hipStream_t stream);
 hipError_t kp_launch_scd_locate_select(KState *st, int K, const double *B, const double *R,
-                                       const int *rinst, double *hist_sum, uint32_t *hist_cnt,
+                                       const int *rinst, XSum *hist_sum, uint32_t *hist_cnt,
                                        const double *ev1, const double *ev2, uint32_t emit_cap,
                                        int *pending, unsigned int *win, hipStream_t stream);
 hipError_t kp_launch_scd_finish(const KState *st, int K, const double *lam_in, double *lam_out,
@@ -470,7 +470,8 @@ kp_status check_rows(Ctx *c, const int64_t *rowptr, int64_t nrows, unsigned int 
 }
 
 struct SweepWs {
-  double *partials, *B, *hist_sum, *ev1, *ev2, *Rtmp, *gtmp, *Ptmp, *sv1, *sv2;
+  double *partials, *B, *ev1, *ev2, *Rtmp, *gtmp, *Ptmp, *sv1, *sv2;
+  XSum *hist_sum;
   uint16_t *sk;
   uint32_t stage_cap;
   uint32_t *hist_cnt;
@@ -503,7 +504,7 @@ kp_status carve_ws(Ctx *c, const Prepared &P, bool scd, SweepWs &w) {
   if (scd) o_st = cv.take((size_t)K * sizeof(KState));
   o_stat = cv.take(64);
   if (scd) {
-    o_hs = cv.take((size_t)K * KP_NB * 8);
+    o_hs = cv.take((size_t)K * KP_NB * sizeof(XSum));
     o_hc = cv.take((size_t)K * KP_NB * 4);
     o_km = cv.take((size_t)K);
     cap = kEmitCapDefault;
@@ -547,7 +548,7 @@ kp_status carve_ws(Ctx *c, const Prepared &P, bool scd, SweepWs &w) {
   w.err = (unsigned long long *)(b + o_stat + 8);
   w.win = (unsigned int *)(b + o_stat + 16);
   w.st = scd ? (KState *)(b + o_st) : nullptr;
-  w.hist_sum = scd ? (double *)(b + o_hs) : nullptr;
+  w.hist_sum = scd ? (XSum *)(b + o_hs) : nullptr;
   w.hist_cnt = scd ? (uint32_t *)(b + o_hc) : nullptr;
   w.kmask = scd ? (uint8_t *)(b + o_km) : nullptr;
   w.ev1 = scd ? (double *)(b + o_e1) : nullptr;
@@ -1345,7 +1346,8 @@ struct BatchPlan {
   uint64_t *eoff = nullptr; // [Kf] start of each knapsack's emission buffer
   uint32_t *ecap = nullptr; // [Kf] its capacity
   bool window = true;       // iterations start with a window where the last step allows
-  double *Bf = nullptr, *hs = nullptr, *e1 = nullptr, *e2 = nullptr, *stats = nullptr;
+  double *Bf = nullptr, *e1 = nullptr, *e2 = nullptr, *stats = nullptr;
+  XSum *hs = nullptr;
   uint32_t *hc = nullptr;
   unsigned long long *err = nullptr;
   int *pinned = nullptr;     // [0] pending knapsacks, [2..3] error word, [16..] per-instance flags
@@ -1610,7 +1612,7 @@ kp_status plan_create(Ctx *c, const kp_problem *probs, int n, const double *cons
   const size_t o_part = cv.take(poff[n] * 8);
   const size_t o_B = cv.take((size_t)Kf * 8);
   const size_t o_st = cv.take((size_t)Kf * sizeof(KState));
-  const size_t o_hs = cv.take((size_t)Kf * KP_NB * 8);
+  const size_t o_hs = cv.take((size_t)Kf * KP_NB * sizeof(XSum));
   const size_t o_hc = cv.take((size_t)Kf * KP_NB * 4);
   const size_t o_e1 = cv.take((size_t)ioff[n] * 8);
   const size_t o_e2 = cv.take((size_t)ioff[n] * 8);
@@ -1681,7 +1683,7 @@ kp_status plan_create(Ctx *c, const kp_problem *probs, int n, const double *cons
     return fail(KP_ERR_HIP, "hipMemset failed");
   }
   p->Bf = (double *)(w + o_B);
-  p->hs = (double *)(w + o_hs);
+  p->hs = (XSum *)(w + o_hs);
   p->hc = (uint32_t *)(w + o_hc);
   p->e1 = (double *)(w + o_e1);
   p->e2 = (double *)(w + o_e2);
@@ -1807,7 +1809,7 @@ kp_status plan_create(Ctx *c, const kp_problem *probs, int n, const double *cons
   if (e == hipSuccess) e = up(p->lam_tab[1], lt1.data(), (size_t)n * 8);
   if (e == hipSuccess) e = up(p->coltab[0], tab0.data(), tab0.size());
   if (e == hipSuccess) e = up(p->coltab[1], tab1.data(), tab1.size());
-  if (e == hipSuccess) e = hipMemsetAsync(p->hs, 0, (size_t)Kf * KP_NB * 8, st);
+  if (e == hipSuccess) e = hipMemsetAsync(p->hs, 0, (size_t)Kf * KP_NB * sizeof(XSum), st);
   if (e == hipSuccess) e = hipMemsetAsync(p->hc, 0, (size_t)Kf * KP_NB * 4, st);
   if (e == hipSuccess) e = hipMemsetAsync(p->err, 0, 8, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);   // host tables go out of scope

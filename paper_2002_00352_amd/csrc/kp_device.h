@@ -27,6 +27,68 @@ __device__ __forceinline__ int exp_bucket(double v, double center, double delta)
 }
 
 
+// ---- exact sums (XSum) ----
+// x = sign (hi 2^-24 + lo 2^-56) with hi = floor(|x| 2^24) and lo the rest in
+// units of 2^-56 (|x| < 2^39): s - floor(s) is exact for s >= 0, and the
+// scalings by powers of two are exact, so lo is an integer on the grid.
+__device__ __forceinline__ void xs_parts(double x, long long &h, long long &l) {
+  const double s = fabs(x) * 0x1p24;
+  const double f = floor(s);
+  const double r = (s - f) * 0x1p32;
+  long long hi = (long long)f;
+  long long lo = (long long)rint(r);
+  if (lo == 0x100000000ll) { lo = 0; hi += 1; }
+  if (x < 0.0) { hi = -hi; lo = -lo; }
+  h = hi;
+  l = lo;
+}
+__device__ __forceinline__ XSum xs_of(double x) {
+  XSum r;
+  xs_parts(x, r.hi, r.lo);
+  return r;
+}
+__device__ __forceinline__ XSum xs_plus(XSum a, XSum b) {
+  XSum r;
+  r.hi = a.hi + b.hi;
+  r.lo = a.lo + b.lo;
+  return r;
+}
+__device__ __forceinline__ void xs_add(XSum &a, double x) { a = xs_plus(a, xs_of(x)); }
+__device__ __forceinline__ XSum xs_zero() {
+  XSum r;
+  r.hi = 0;
+  r.lo = 0;
+  return r;
+}
+__device__ __forceinline__ bool xs_nonzero(const XSum &a) { return a.hi != 0 || a.lo != 0; }
+// Integer adds: the same total whatever order the lanes and blocks add in.
+__device__ __forceinline__ void xs_atomic_add_sum(XSum *dst, const XSum &v) {
+  if (v.hi) atomicAdd((unsigned long long *)&dst->hi, (unsigned long long)v.hi);
+  if (v.lo) atomicAdd((unsigned long long *)&dst->lo, (unsigned long long)v.lo);
+}
+__device__ __forceinline__ void xs_atomic_add(XSum *dst, double x) { xs_atomic_add_sum(dst, xs_of(x)); }
+// The nearest doubles to the parts, added (exact when the total needs no
+// more than 53 bits, e.g. on the 2^-24 grid below 2^29).
+__device__ __forceinline__ double xs_to_double(const XSum &a) {
+  const long long H = a.hi + (a.lo >> 32);
+  const long long L = a.lo & 0xFFFFFFFFll;
+  const double h = (double)H * 0x1p-24;
+  const double l = (double)L * 0x1p-56;
+  return h + l;
+}
+// a > B exactly, for B >= 0 (B's own bits below 2^-56 are kept in the
+// comparison).
+__device__ __forceinline__ bool xs_gt(const XSum &a, double B) {
+  if (!(B < 0x1p38)) return xs_to_double(a) > B;   // outside the exact range (budgets below 2^38)
+  const long long H = a.hi + (a.lo >> 32);
+  const long long L = a.lo & 0xFFFFFFFFll;
+  const double sB = B * 0x1p24;
+  const double fB = floor(sB);
+  const double rB = (sB - fB) * 0x1p32;
+  const long long HB = (long long)fB;
+  return H > HB || (H == HB && (double)L > rB);
+}
+
 // Breakpoint arithmetic of the walks.  For lines z_a = c_a - lambda b_a and
 // z_b = c_b - lambda b_b with b_a > b_b, the crossing is
 // fl(fl(c_a - c_b) / fl(b_a - b_b)) and line a ranks above line b for lambda
@@ -96,15 +158,15 @@ __device__ __forceinline__ uint64_t greedy_mask(const uint8_t *perm, int M, uint
 // range, record a bucket's key hull, or bin a key range linearly.  Emitted
 // events go to the block's staging region (published by publish_block).
 __device__ __forceinline__ void record_event(const SweepArgs &a, const KState &ks, int k, double best,
-                                             double v2, int mode, double *hs, uint32_t *hc,
+                                             double v2, int mode, XSum *hs, uint32_t *hc,
                                              unsigned long long *hmin, unsigned long long *hmax,
                                              uint32_t *kcnt, uint32_t *kovf, uint32_t *nstage,
                                              int bid) {
   const uint64_t key = dkey(best);
   bool emit = false;
-  if (mode == KS_EXP) {
+  if (mode == KS_EXP && hs) {
     const int id = exp_bucket(best, ks.center, ks.delta);
-    atomicAdd(&hs[k * KP_NB + 32 + id], v2);
+    xs_atomic_add(&hs[k * KP_NB + 32 + id], v2);
     atomicAdd(&hc[k * KP_NB + 32 + id], 1u);
     emit = (id >= -KP_CENTRAL_W && id <= KP_CENTRAL_W);
   } else if (mode == KS_EMIT_BUCKET || mode == KS_HULL_BUCKET) {
@@ -114,9 +176,9 @@ __device__ __forceinline__ void record_event(const SweepArgs &a, const KState &k
       emit = (mode == KS_EMIT_BUCKET);
     }
   } else if (mode == KS_REFINE) {
-    if (key >= ks.klo && key <= ks.khi) {
+    if (hs && key >= ks.klo && key <= ks.khi) {
       const int bin = (int)((key - ks.klo) >> ks.shift);
-      atomicAdd(&hs[k * KP_NB + bin], v2);
+      xs_atomic_add(&hs[k * KP_NB + bin], v2);
       atomicAdd(&hc[k * KP_NB + bin], 1u);
     }
   } else {  // KS_EMIT_RANGE
@@ -145,21 +207,21 @@ __device__ __forceinline__ bool walk_mode(int m) {
 // End of a sweep block: add its histograms to the global ones, reserve space
 // for its staged events with one atomic per knapsack and copy them there.
 // Every thread of the block calls this.
-__device__ __forceinline__ void publish_block(const SweepArgs &a, int K, double *hs, uint32_t *hc,
+__device__ __forceinline__ void publish_block(const SweepArgs &a, int K, XSum *hs, uint32_t *hc,
                                               unsigned long long *hmin, unsigned long long *hmax,
                                               uint32_t *kcnt, uint32_t *kpos, uint32_t *kovf,
                                               uint32_t *nstage, int tid, int nthreads, int bid,
-                                              const double *kcorr = nullptr) {
+                                              const XSum *kcorr = nullptr) {
   for (int t = tid; hc && t < K * KP_NB; t += nthreads) {
     if (hc[t]) {
-      atomicAdd(&a.hist_sum[t], hs[t]);
+      xs_atomic_add_sum(&a.hist_sum[t], hs[t]);
       atomicAdd(&a.hist_cnt[t], hc[t]);
     }
   }
   for (int k = tid; k < K; k += nthreads) {
     if (kcnt[k]) kpos[k] = atomicAdd(&a.st[k].n_emit, kcnt[k]);
     if (kovf[k]) atomicOr(&a.st[k].overflow, 1);
-    if (kcorr && kcorr[k] != 0.0) atomicAdd(&a.st[k].corr, kcorr[k]);
+    if (kcorr && xs_nonzero(kcorr[k])) xs_atomic_add_sum(&a.st[k].corr, kcorr[k]);
     if (hmin[k] != ~0ull) {
       atomicMin((unsigned long long *)&a.st[k].hull_lo, hmin[k]);
       atomicMax((unsigned long long *)&a.st[k].hull_hi, hmax[k]);

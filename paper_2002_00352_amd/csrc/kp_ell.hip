@@ -24,9 +24,10 @@ size_t kp_ell_lds_bytes(int M, int K, int D, int L, int mode, int *region_out) {
              r16((size_t)EW * (K + 2) * 8);
   if (mode != KM_EVAL) s += r16((size_t)K * 4) + r16((size_t)K * 8 + 16);
   if (mode == KM_WMAIN) s += r16((size_t)(K + 1) * sizeof(LamW));
-  if (brk)
-    s += r16((size_t)K * 8) + r16((size_t)K * sizeof(KState)) + r16((size_t)K * KP_NB * 8) +
-         r16((size_t)K * KP_NB * 4) + 3 * r16((size_t)K * 4) + 2 * r16((size_t)K * 8) + r16(16);
+  if (brk)   // (the listed users' pass of a window pass bins nothing: no histograms)
+    s += r16((size_t)K * sizeof(XSum)) + r16((size_t)K * sizeof(KState)) +
+         (mode == KM_SCD ? r16((size_t)K * KP_NB * sizeof(XSum)) + r16((size_t)K * KP_NB * 4) : 0) +
+         3 * r16((size_t)K * 4) + 2 * r16((size_t)K * 8) + r16(16);
   s += (size_t)EW * region;
   if (region_out) *region_out = (int)region;
   return s;

@@ -96,7 +96,7 @@ __device__ __forceinline__ void scd_user(const SweepArgs &a, int M, int K, int L
                                          const double *ptl, const float *btl, const uint8_t *ktl,
                                          const uint16_t *mskl, const double *lam, const uint64_t *tmask,
                                          const int *tcap, const KState *kst, const int *kmode,
-                                         const double *hwin, double *kcorr, double *hs, uint32_t *hc,
+                                         const double *hwin, XSum *kcorr, XSum *hs, uint32_t *hc,
                                          unsigned long long *hmin, unsigned long long *hmax,
                                          uint32_t *kcnt, uint32_t *kovf, uint32_t *nstage) {
   if (!act) return;
@@ -248,7 +248,7 @@ __device__ __forceinline__ void scd_user(const SweepArgs &a, int M, int K, int L
         // consumption just above the window against the one at lambda^t
         const double above = (best > 0.0 && dkey(best) > kst[k].khi) ? bo_d : 0.0;
         const double now = (S >> j & 1) ? bo_d : 0.0;
-        if (above != now) atomicAdd(&kcorr[k], above - now);
+        if (above != now) xs_atomic_add(&kcorr[k], above - now);
       }
     }
   }
@@ -344,7 +344,10 @@ __device__ __forceinline__ void scd_user(const SweepArgs &a, int M, int K, int L
     if (mode == KS_WINDOW) {
       double now = 0.0;
       for (uint64_t m = S & A; m; m &= m - 1) now = now + bk(__ffsll((long long)m) - 1, k);
-      if (above != now) atomicAdd(&kcorr[k], above - now);
+      if (above != now) {
+        xs_atomic_add(&kcorr[k], above);
+        xs_atomic_add(&kcorr[k], -now);
+      }
     }
   }
 }
@@ -377,11 +380,11 @@ k_ell(const SweepArgs a, const EllGeom g) {
   int *tcap = (int *)carve((size_t)a.tree.L * 4 + 4);
   double *wacc = (double *)carve((size_t)EW * (K + 2) * 8);
   KState *kst = BREAK ? (KState *)carve((size_t)K * sizeof(KState)) : nullptr;
-  double *hs = nullptr;
+  XSum *hs = nullptr;
   uint32_t *hc = nullptr, *kcnt = nullptr, *kpos = nullptr, *kovf = nullptr, *nstage = nullptr;
   int *kmode = nullptr;
   unsigned long long *hmin = nullptr, *hmax = nullptr;
-  double *kcorr = nullptr;
+  XSum *kcorr = nullptr;
   double *hwin = nullptr;
   if (MODE != KM_EVAL) {
     kmode = (int *)carve((size_t)K * 4);
@@ -392,9 +395,11 @@ k_ell(const SweepArgs a, const EllGeom g) {
   // [K] = (0, 0) for the clamped reads
   LamW *lw = MODE == KM_WMAIN ? (LamW *)carve((size_t)(K + 1) * sizeof(LamW)) : nullptr;
   if (BREAK) {
-    kcorr = (double *)carve((size_t)K * 8);
-    hs = (double *)carve((size_t)K * KP_NB * 8);
-    hc = (uint32_t *)carve((size_t)K * KP_NB * 4);
+    kcorr = (XSum *)carve((size_t)K * sizeof(XSum));
+    if (MODE == KM_SCD) {   // the listed users' pass runs only when every search has a window
+      hs = (XSum *)carve((size_t)K * KP_NB * sizeof(XSum));
+      hc = (uint32_t *)carve((size_t)K * KP_NB * 4);
+    }
     kcnt = (uint32_t *)carve((size_t)K * 4);
     kpos = (uint32_t *)carve((size_t)K * 4);
     kovf = (uint32_t *)carve((size_t)K * 4);
@@ -425,9 +430,9 @@ k_ell(const SweepArgs a, const EllGeom g) {
       kst[t] = a.st[t];
       kcnt[t] = 0u; kpos[t] = 0u; kovf[t] = 0u;
       hmin[t] = ~0ull; hmax[t] = 0ull;
-      kcorr[t] = 0.0;
+      kcorr[t] = xs_zero();
     }
-    for (int t = tid; t < K * KP_NB; t += ENT) { hs[t] = 0.0; hc[t] = 0u; }
+    for (int t = tid; hs && t < K * KP_NB; t += ENT) { hs[t] = xs_zero(); hc[t] = 0u; }
     if (tid == 0) *nstage = 0u;
   }
   __syncthreads();

@@ -14,6 +14,15 @@
 #define KP_LIST_HOLE 0xFFFFFFFFu  // unused list slot
 #define KP_SEL_MAX 4           // the uniform-row kernel gathers the selected entries when at most this many items can be selected
 
+// An exact, order-free sum of the threshold search: hi counts units of
+// 2^-24 and lo units of 2^-56, so the value is hi 2^-24 + lo 2^-56.  Terms on
+// the 2^-56 grid (fp32 costs of at least 2^-33, their differences and sums
+// of a few of them) add exactly as integers, in any order; terms off that
+// grid round their last part to the nearest unit, the same way in every run.
+struct XSum {
+  long long hi, lo;
+};
+
 // Laminar local constraints after pruning: only sets that can bind
 // (C_l < |S_l|), duplicates merged with the smaller cap, ordered subsets
 // first (size ascending, then first item).
@@ -67,7 +76,7 @@ struct KState {
   uint32_t flags;      // KS_FLAG_*
   double center;       // lambda_k^t
   double delta;        // central bucket half-width (a power of two)
-  double F_above;      // sum of increments strictly above the current target
+  XSum fab;            // sum of increments strictly above the current target
   double result;       // lambda_k^{t+1} once mode == KS_DONE
   uint64_t klo, khi;   // inclusive key range
   uint64_t hull_lo, hull_hi;  // atomics: key hull of the bucket's events
@@ -76,7 +85,7 @@ struct KState {
   uint64_t eoff;       // batched: this knapsack's emission buffer (elements from the base), when ecap > 0
   uint32_t ecap;       // batched: its capacity (0: the uniform capacity of the call)
   uint32_t pad2;
-  double corr;         // KS_WINDOW (atomic): sum over users of C_ik(whi+) - v_ik(x(lambda^t))
+  XSum corr;           // KS_WINDOW: sum over users of C_ik(whi+) - v_ik(x(lambda^t))
 };
 
 struct SweepArgs {
@@ -91,7 +100,7 @@ struct SweepArgs {
   uint8_t *x_out;          // [N*M] or null
   // SCD
   KState *st;              // [K]
-  double *hist_sum;        // [K][KP_NB]
+  XSum *hist_sum;          // [K][KP_NB]
   uint32_t *hist_cnt;      // [K][KP_NB]
   double *emit_v1;         // [K][emit_cap]
   double *emit_v2;

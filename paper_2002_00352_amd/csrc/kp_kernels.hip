@@ -268,18 +268,20 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
   float *evl = (float *)carve(FMT == 1 ? (size_t)NT * ECH * 4 : 0);
   int64_t *ebase = (int64_t *)carve(16);                  // CSR: first entry of the next tile
   KState *kst = SCD ? (KState *)carve((size_t)K * sizeof(KState)) : nullptr;
-  double *hs = nullptr;
+  XSum *hs = nullptr;
   uint32_t *hc = nullptr;
   const bool hist = !a.no_hist;   // histograms (exponential buckets, refinement bins) in LDS
   int *kmode = nullptr;
   uint32_t *kcnt = nullptr, *kpos = nullptr, *kovf = nullptr, *nstage = nullptr;
   unsigned long long *hmin = nullptr, *hmax = nullptr;
-  double *kcorr = nullptr, *ugap = nullptr;
+  double *kwide = nullptr, *ugap = nullptr;
+  XSum *kxs = nullptr;
   if (SCD) {
-    kcorr = (double *)carve((size_t)K * 8 + 8);   // [K] window corrections, [K] widest window
+    kwide = (double *)carve(16);                   // the widest window
+    kxs = (XSum *)carve((size_t)K * sizeof(XSum)); // window corrections
     ugap = (double *)carve((size_t)U * 16);        // per user: gap and scale of the window filter
     if (hist) {
-      hs = (double *)carve((size_t)K * KP_NB * 8);
+      hs = (XSum *)carve((size_t)K * KP_NB * sizeof(XSum));
       hc = (uint32_t *)carve((size_t)K * KP_NB * 4);
     }
     kmode = (int *)carve((size_t)K * 4);
@@ -295,7 +297,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
   if (SCD) {
     for (int t = tid; t < K; t += NT) kst[t] = a.st[t];
     if (hist)
-      for (int t = tid; t < K * KP_NB; t += NT) { hs[t] = 0.0; hc[t] = 0u; }
+      for (int t = tid; t < K * KP_NB; t += NT) { hs[t] = xs_zero(); hc[t] = 0u; }
     for (int t = tid; t < K; t += NT) {
       kmode[t] = a.st[t].mode;
       kcnt[t] = 0u;
@@ -303,14 +305,14 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
       kovf[t] = 0u;
       hmin[t] = ~0ull;
       hmax[t] = 0ull;
-      kcorr[t] = 0.0;
+      kxs[t] = xs_zero();
     }
     if (tid == 0) {
       *nstage = 0u;
       double m = 0.0;
       for (int k = 0; k < K; ++k)
         if (a.st[k].mode == KS_WINDOW) m = a.st[k].hw > m ? a.st[k].hw : m;
-      kcorr[K] = m;
+      kwide[0] = m;
     }
   }
   const int64_t N = a.pr.N;
@@ -461,7 +463,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
         rank1 += beats & (int)(m1 >> jj & 1);
       }
       perm[u * M + rank] = (uint8_t)j;
-      if (SCD && kcorr[K] > 0.0) {
+      if (SCD && kwide[0] > 0.0) {
         // largest positive cost of the row (0 if none): the maximum below
         // is taken over the users' rows as unsigned bits, which order like
         // the floats for positive values
@@ -574,14 +576,14 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
         for (int j = 0; j < M; ++j) xo[j] = (uint8_t)(S >> j & 1);
       }
     }
-    if (SCD && kcorr[K] > 0.0) {
+    if (SCD && kwide[0] > 0.0) {
       // window filter, one thread per rank position: the smallest gap
       // between a user's p~ in rank order and between them and zero, over
       // the lines that can turn positive inside the widest window (ranks
       // descend, so those are a prefix of the ranks); two identical lines
       // (equal p~ and equal costs in every knapsack, e.g. the copies of a
       // categorical item) never cross
-      const double hm = kcorr[K];
+      const double hm = kwide[0];
       for (int q = tid; q < nr; q += NT) {
         const int u = q / M, rr = q - u * M;
         const float bm = __uint_as_float(((const unsigned int *)ugap)[4 * u + 2]);
@@ -645,7 +647,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
             // the filter's scale: |top p~| + H, with H from the user's
             // largest cost and the widest window
             const float bmu = __uint_as_float(((const unsigned int *)ugap)[4 * u + 2]);
-            const double hm = kcorr[K];
+            const double hm = kwide[0];
             const double Hu = hm * (double)bmu * (1.0 + 0x1p-30) + 0x1p-36 * (1.0 + (double)bmu * hm);
             const double gscale = fabs(zu[perm[u * M]]) + Hu;
             if (window_calm(ugap[2 * u], gscale, kst[k].hw, (double)bmk, lk)) {
@@ -659,7 +661,10 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
               // no breakpoint inside the window: its consumption just above
               // the window is the window's set's
               walk = false;
-              if (cw != v) atomicAdd(&kcorr[k], cw - v);
+              if (cw != v) {
+                xs_atomic_add(&kxs[k], cw);
+                xs_atomic_add(&kxs[k], -v);
+              }
             } else {
               auto line = [&](int j, double &c, double &b) {
                 b = (A >> j & 1) ? (double)bu[j * K + k] : 0.0;
@@ -761,7 +766,10 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
               }
               record_event(a, ks, k, best, v2, mode, hs, hc, hmin, hmax, kcnt, kovf, nstage, bid);
             }
-            if (mode == KS_WINDOW && above != v) atomicAdd(&kcorr[k], above - v);
+            if (mode == KS_WINDOW && above != v) {
+              xs_atomic_add(&kxs[k], above);
+              xs_atomic_add(&kxs[k], -v);
+            }
           }
         }
       }
@@ -787,7 +795,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
   if (a.want_stats) {
     for (int t = tid; t < K + 2; t += NT) a.partials[(size_t)bid * (K + 2) + t] = acc[t];
   }
-  if (SCD) publish_block(a, K, hs, hc, hmin, hmax, kcnt, kpos, kovf, nstage, tid, NT, bid, kcorr);
+  if (SCD) publish_block(a, K, hs, hc, hmin, hmax, kcnt, kpos, kovf, nstage, tid, NT, bid, kxs);
 }
 
 
@@ -929,7 +937,7 @@ __global__ void k_scd_init(KState *st, int K, const double *lam_in, const uint8_
     d = ldexp(1.0, ilogb(base) - 10);
   }
   s.delta = d;
-  s.F_above = 0.0;
+  s.fab = xs_zero();
   s.result = lam_in[k];
   s.klo = 0;
   s.khi = ~0ull;
@@ -938,7 +946,7 @@ __global__ void k_scd_init(KState *st, int K, const double *lam_in, const uint8_
   s.wlo = 0.0;
   s.whi = 0.0;
   s.hw = 0.0;
-  s.corr = 0.0;
+  s.corr = xs_zero();
   s.eoff = 0;
   s.ecap = 0;
   s.pad2 = 0;
@@ -955,7 +963,7 @@ __device__ __forceinline__ void restart_full(KState &s) {
   s.flags = 0;
   s.n_emit = 0;
   s.overflow = 0;
-  s.F_above = 0.0;
+  s.fab = xs_zero();
   s.klo = 0;
   s.khi = ~0ull;
   s.hull_lo = ~0ull;
@@ -972,29 +980,31 @@ __device__ __forceinline__ void set_refine(KState &s, uint64_t lo, uint64_t hi) 
 
 // After a pass: pick the bin holding the threshold and choose the next step.
 __global__ void k_scd_locate(KState *st, int K, const double *B, const double *R, const int *rinst,
-                             double *hist_sum, uint32_t *hist_cnt, uint32_t emit_cap, unsigned int *win) {
+                             XSum *hist_sum, uint32_t *hist_cnt, uint32_t emit_cap, unsigned int *win) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= K) return;
   KState s = st[k];
   if (s.ecap) emit_cap = s.ecap;   // batched: this knapsack's own buffer
   const double Bk = B[k];
-  const double *hsum = hist_sum + (size_t)k * KP_NB;
+  const XSum *hsum = hist_sum + (size_t)k * KP_NB;
   const uint32_t *hcnt = hist_cnt + (size_t)k * KP_NB;
+  // sums and comparisons with B_k are exact (XSum): the bin that holds the
+  // threshold does not depend on the order of any addition
   if (s.mode == KS_EXP) {
-    double total = 0.0;
-    for (int b = 0; b < KP_NB; ++b) total = total + hsum[b];
-    if (total <= Bk) {
+    XSum total = xs_zero();
+    for (int b = 0; b < KP_NB; ++b) total = xs_plus(total, hsum[b]);
+    if (!xs_gt(total, Bk)) {
       s.mode = KS_DONE;
       s.result = 0.0;
     } else {
-      double cum = 0.0;
+      XSum cum = xs_zero();
       int bin = 1;
       for (int b = KP_NB - 1; b >= 1; --b) {
-        if (hcnt[b] && cum + hsum[b] > Bk) { bin = b; break; }
-        cum = cum + hsum[b];
+        if (hcnt[b] && xs_gt(xs_plus(cum, hsum[b]), Bk)) { bin = b; break; }
+        cum = xs_plus(cum, hsum[b]);
       }
       s.bstar = bin - 32;
-      s.F_above = cum;
+      s.fab = cum;
       if (s.flags & KS_FLAG_INTERP) {
         // Sec. 5.2's approximate reduce: the bucket's increments spread
         // linearly over its interval [lo, hi] (lo clamped at 0)
@@ -1005,14 +1015,14 @@ __global__ void k_scd_locate(KState *st, int K, const double *B, const double *R
         else if (id > 0) { lo = c + ldexp(d, id - 1); hi = c + ldexp(d, id); }
         else { lo = c - ldexp(d, -id); hi = c - ldexp(d, -id - 1); }
         lo = fmax(lo, 0.0);
-        const double frac = (Bk - cum) / hsum[bin];
+        const double frac = (Bk - xs_to_double(cum)) / xs_to_double(hsum[bin]);
         const double width = hi - lo;
         const double prod = frac * width;
         const double v = hi - prod;
         s.mode = KS_DONE;
         s.result = fmax(v, lo);
         st[k] = s;
-        for (int b = 0; b < KP_NB; ++b) { hist_sum[(size_t)k * KP_NB + b] = 0.0; hist_cnt[(size_t)k * KP_NB + b] = 0u; }
+        for (int b = 0; b < KP_NB; ++b) { hist_sum[(size_t)k * KP_NB + b] = xs_zero(); hist_cnt[(size_t)k * KP_NB + b] = 0u; }
         return;
       }
       const bool central = s.bstar >= -KP_CENTRAL_W && s.bstar <= KP_CENTRAL_W;
@@ -1033,18 +1043,18 @@ __global__ void k_scd_locate(KState *st, int K, const double *B, const double *R
       set_refine(s, s.hull_lo, s.hull_hi);
     }
   } else if (s.mode == KS_REFINE) {
-    double cum = s.F_above;
+    XSum cum = s.fab;
     int bin = -1;
     for (int b = KP_NB - 1; b >= 0; --b) {
-      if (hcnt[b] && cum + hsum[b] > Bk) { bin = b; break; }
-      cum = cum + hsum[b];
+      if (hcnt[b] && xs_gt(xs_plus(cum, hsum[b]), Bk)) { bin = b; break; }
+      cum = xs_plus(cum, hsum[b]);
     }
     if (bin < 0) {  // cannot happen with exact sums; fall back to the lowest bin
       bin = 0;
-      cum = s.F_above;
-      for (int b = KP_NB - 1; b >= 1; --b) cum = cum + hsum[b];
+      cum = s.fab;
+      for (int b = KP_NB - 1; b >= 1; --b) cum = xs_plus(cum, hsum[b]);
     }
-    s.F_above = cum;
+    s.fab = cum;
     const uint64_t lo = s.klo + ((uint64_t)bin << s.shift);
     const uint64_t hi0 = lo + ((((uint64_t)1) << s.shift) - 1);
     const uint64_t hi = hi0 < s.khi ? hi0 : s.khi;
@@ -1068,19 +1078,19 @@ __global__ void k_scd_locate(KState *st, int K, const double *B, const double *R
     // consumption of knapsack k (batched: R of instance rinst[k] sits after
     // the R, g, P columns of the instances before it)
     const double Rk = rinst ? R[k + 2 * rinst[k]] : R[k];
-    const double above = Rk + s.corr;
+    const XSum above = xs_plus(xs_of(Rk), s.corr);
     if (win) { atomicAdd(&win[0], 1u); atomicAdd(&win[3], s.n_emit); }
-    if (s.overflow || above > Bk) {
+    if (s.overflow || xs_gt(above, Bk)) {
       if (win) atomicAdd(&win[1], 1u);
       restart_full(s);                  // the threshold lies above the window
     } else {
       s.mode = KS_SELECT_RANGE;         // [klo, khi] is the window
-      s.F_above = above;
+      s.fab = above;
       s.flags |= KS_FLAG_WINDOW;
     }
   }
   st[k] = s;
-  for (int b = 0; b < KP_NB; ++b) { hist_sum[(size_t)k * KP_NB + b] = 0.0; hist_cnt[(size_t)k * KP_NB + b] = 0u; }
+  for (int b = 0; b < KP_NB; ++b) { hist_sum[(size_t)k * KP_NB + b] = xs_zero(); hist_cnt[(size_t)k * KP_NB + b] = 0u; }
 }
 
 // Exact threshold among the emitted events of one knapsack (one block per k):
@@ -1093,12 +1103,12 @@ __global__ void __launch_bounds__(SEL_NT) k_scd_select(KState *st, const double 
                                                        uint32_t emit_cap, unsigned int *win) {
   const int k = blockIdx.x;
   __shared__ KState s;
-  __shared__ double hsum[256];
+  __shared__ XSum hsum[256];
   __shared__ uint32_t hcnt[256];
   __shared__ uint64_t skey[KP_SORT_MAX];
   __shared__ double sval[KP_SORT_MAX];
   __shared__ uint64_t lo, hi;
-  __shared__ double Fab;
+  __shared__ XSum Fab;
   __shared__ uint32_t nsel;
   __shared__ int done;
   __shared__ double result;
@@ -1116,23 +1126,26 @@ __global__ void __launch_bounds__(SEL_NT) k_scd_select(KState *st, const double 
   if (tid == 0) {
     lo = bucket ? 0ull : s.klo;
     hi = bucket ? ~0ull : s.khi;
-    Fab = s.F_above;
+    Fab = s.fab;
     done = 0;
   }
   __syncthreads();
   if (s.flags & KS_FLAG_WINDOW) {
     // the threshold lies in the window iff the window's increments take the
     // running sum past B_k
-    __shared__ double part[SEL_NT / 64];
-    double v = 0.0;
-    for (uint32_t e = tid; e < n; e += SEL_NT) v = v + V2[e];
-    for (int off = 32; off > 0; off >>= 1) v = v + __shfl_xor(v, off, 64);
+    __shared__ XSum part[SEL_NT / 64];
+    XSum v = xs_zero();
+    for (uint32_t e = tid; e < n; e += SEL_NT) xs_add(v, V2[e]);
+    for (int off = 32; off > 0; off >>= 1) {
+      v.hi = v.hi + __shfl_xor(v.hi, off, 64);
+      v.lo = v.lo + __shfl_xor(v.lo, off, 64);
+    }
     if ((tid & 63) == 0) part[tid >> 6] = v;
     __syncthreads();
     if (tid == 0) {
-      double tot = Fab;
-      for (int w = 0; w < SEL_NT / 64; ++w) tot = tot + part[w];
-      if (!(tot > Bk)) {
+      XSum tot = Fab;
+      for (int w = 0; w < SEL_NT / 64; ++w) tot = xs_plus(tot, part[w]);
+      if (!xs_gt(tot, Bk)) {
         if (s.wlo == 0.0) {             // every breakpoint is in the window
           st[k].result = 0.0;
           st[k].mode = KS_DONE;
@@ -1151,7 +1164,7 @@ __global__ void __launch_bounds__(SEL_NT) k_scd_select(KState *st, const double 
   // narrowing loop
   for (int it = 0; it < 80; ++it) {
     if (tid == 0) nsel = 0;
-    if (tid < 256) { hsum[tid] = 0.0; hcnt[tid] = 0u; }
+    if (tid < 256) { hsum[tid] = xs_zero(); hcnt[tid] = 0u; }
     __syncthreads();
     const uint64_t L0 = lo, H0 = hi;
     for (uint32_t e = tid; e < n; e += SEL_NT) {
@@ -1171,16 +1184,16 @@ __global__ void __launch_bounds__(SEL_NT) k_scd_select(KState *st, const double 
       const uint64_t key = dkey(v);
       if (key < L0 || key > H0) continue;
       const int bin = (int)((key - L0) >> shift);
-      atomicAdd(&hsum[bin], V2[e]);
+      xs_atomic_add(&hsum[bin], V2[e]);
       atomicAdd(&hcnt[bin], 1u);
     }
     __syncthreads();
     if (tid == 0) {
-      double cum = Fab;
+      XSum cum = Fab;
       int bin = -1;
       for (int b = 255; b >= 0; --b) {
-        if (hcnt[b] && cum + hsum[b] > Bk) { bin = b; break; }
-        cum = cum + hsum[b];
+        if (hcnt[b] && xs_gt(xs_plus(cum, hsum[b]), Bk)) { bin = b; break; }
+        cum = xs_plus(cum, hsum[b]);
       }
       if (bin < 0) { bin = 0; }
       Fab = cum;
@@ -1230,13 +1243,13 @@ __global__ void __launch_bounds__(SEL_NT) k_scd_select(KState *st, const double 
       }
     }
     if (tid == 0) {
-      double cum = Fab;
+      XSum cum = Fab;
       double ans = m ? kdbl(skey[m - 1]) : kdbl(lo);
       uint32_t e = 0;
       while (e < m) {
         const uint64_t key = skey[e];
-        while (e < m && skey[e] == key) { cum = cum + sval[e]; ++e; }
-        if (cum > Bk) { ans = kdbl(key); break; }
+        while (e < m && skey[e] == key) { xs_add(cum, sval[e]); ++e; }
+        if (xs_gt(cum, Bk)) { ans = kdbl(key); break; }
       }
       result = ans;
     }
@@ -1775,7 +1788,7 @@ __global__ void k_scd_init_flat(KState *st, int Kf, const double *const *lam_in,
   const double base = l > 0x1p-20 ? l : 0x1p-20;
   // bucket width: a power of two above the last step when there is one
   s.delta = (hint && hint[f] > 0.0) ? hint[f] : ldexp(1.0, ilogb(base) - 10);
-  s.F_above = 0.0;
+  s.fab = xs_zero();
   s.result = l;
   s.klo = 0;
   s.khi = ~0ull;
@@ -1784,7 +1797,7 @@ __global__ void k_scd_init_flat(KState *st, int Kf, const double *const *lam_in,
   s.wlo = 0.0;
   s.whi = 0.0;
   s.hw = 0.0;
-  s.corr = 0.0;
+  s.corr = xs_zero();
   s.eoff = eoff ? eoff[f] : 0;
   s.ecap = ecap ? ecap[f] : 0;
   s.pad2 = 0;
@@ -1892,9 +1905,9 @@ size_t kp_sweep_lds_bytes(int U, int M, int K, bool scd, int fmt, bool hist = tr
   if (scd) s += r16(R);                            // per-item threshold elements
   if (fmt == 1) s += 2 * r16((size_t)NT * ECH * 4);  // staged CSR entries
   if (scd)
-    s += r16((size_t)K * sizeof(KState)) + (hist ? r16((size_t)K * KP_NB * 8) + r16((size_t)K * KP_NB * 4) : 0) +
+    s += r16((size_t)K * sizeof(KState)) + (hist ? r16((size_t)K * KP_NB * sizeof(XSum)) + r16((size_t)K * KP_NB * 4) : 0) +
          4 * r16((size_t)K * 4) + 2 * r16((size_t)K * 8) + r16(16) +
-         r16((size_t)K * 8 + 8) + r16((size_t)U * 16);   // window corrections, per-user filter
+         r16(16) + r16((size_t)K * sizeof(XSum)) + r16((size_t)U * 16);   // widest window, corrections, per-user filter
   return s;
 }
 
@@ -1977,7 +1990,7 @@ hipError_t kp_launch_scd_init(KState *st, int K, const double *lam_in, const uin
 }
 
 hipError_t kp_launch_scd_locate_select(KState *st, int K, const double *B, const double *R,
-                                       const int *rinst, double *hist_sum, uint32_t *hist_cnt,
+                                       const int *rinst, XSum *hist_sum, uint32_t *hist_cnt,
                                        const double *ev1, const double *ev2, uint32_t emit_cap,
                                        int *pending, unsigned int *win, hipStream_t stream) {
   hipLaunchKernelGGL(k_scd_locate, dim3((K + 63) / 64), dim3(64), 0, stream, st, K, B, R, rinst, hist_sum,

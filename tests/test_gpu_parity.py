@@ -182,6 +182,72 @@ def test_interp_reduce_trajectory(name, mk):
             assert np.array_equal(a["lam"], b["lam"])
 
 
+def _off_grid(inst):
+    """The instance with every cost divided by 3 in fp32 (values off the
+    2^-24 grid, so FP64 sums of them round) and the budgets recomputed."""
+    if inst.b is not None:
+        b = (inst.b.astype(np.float64) / 3.0).astype(np.float32)
+        D = b.astype(np.float64).reshape(-1, inst.K).sum(axis=0)
+        out = dataclasses.replace(inst, b=b)
+    else:
+        val = (inst.val.astype(np.float64) / 3.0).astype(np.float32)
+        D = np.bincount(inst.col, weights=val.astype(np.float64), minlength=inst.K)
+        out = dataclasses.replace(inst, val=val)
+    frac = inst.B.sum() / max(1e-300, float((inst.b.astype(np.float64).reshape(-1, inst.K).sum(axis=0)
+                                              if inst.b is not None else
+                                              np.bincount(inst.col, weights=inst.val.astype(np.float64),
+                                                          minlength=inst.K)).sum()))
+    out.B = np.maximum(frac * D, 1e-3)
+    return out
+
+
+OFFGRID_CASES = [
+    ("c3-csr-uniform-rows", lambda: _off_grid(kpgen.config_instance(3, N=30000))),
+    ("c1-dense", lambda: _off_grid(kpgen.config_instance(1, N=8000))),
+    ("c2-dense-general", lambda: _off_grid(kpgen.config_instance(2, N=4000))),
+    ("laminar-dense-K9", lambda: _off_grid(random_instance(np.random.default_rng(71), 3000, 12, 9,
+                                                           tree=random_laminar(12, np.random.default_rng(72)),
+                                                           frac=0.15))),
+]
+
+
+@gpu
+@pytest.mark.parametrize("name,mk", OFFGRID_CASES, ids=[c[0] for c in OFFGRID_CASES])
+def test_off_grid_costs_trajectory_twice(name, mk):
+    """Costs off the 2^-24 grid (every cost divided by 3 in fp32): along an
+    SCD trajectory from lambda = 0, with the window search on, every update
+    equals the oracle's (whose reduce sums exactly) bit for bit; the same
+    trajectory on a second fresh context gives the same multipliers bit for
+    bit (the threshold sums are exact integer sums, order-free); decisions
+    are bit-exact and consumption within 1e-12 relative."""
+    kp, torch = _kp()
+    print("case", name, flush=True)
+    inst = mk()
+    prob = kp.Problem.from_host(inst)
+    runs = []
+    for rep in range(2):
+        ctx = kp.Context()
+        lam = np.zeros(inst.K)
+        traj = []
+        for t in range(7):
+            if rep == 0:
+                ev = kp.kp_eval_dual(prob, _lamd(torch, lam), want_x=True, ctx=ctx)
+                ref = oracle.eval_dual(inst, lam)
+                assert np.array_equal(ev["x"].cpu().numpy(), ref["x"]), t
+                R = ev["R"].cpu().numpy()
+                assert np.all(np.abs(R - ref["R"]) <= 1e-12 * np.maximum(1.0, np.abs(ref["R"]))), t
+                want = oracle.scd_sweep(inst, lam)
+            got = kp.kp_scd_sweep(prob, _lamd(torch, lam), ctx=ctx)["lam"].cpu().numpy()
+            if rep == 0:
+                assert np.array_equal(got, want), (t, np.flatnonzero(got != want))
+            traj.append(got)
+            lam = got
+        runs.append(traj)
+        print("window searches", ctx.window_stats(), flush=True)
+    for a, b in zip(*runs):
+        assert np.array_equal(a, b)
+
+
 @gpu
 def test_dual_autograd_matches_oracle_gradient():
     kp, torch = _kp()
