@@ -309,6 +309,17 @@ kp_status kp_set_alg5(void *ctx, int32_t on);
    0 when the total increment fits.  One pass per iteration, no windows. */
 kp_status kp_set_reduce(void *ctx, int32_t mode);
 
+/* Sampled start of the full threshold search (the search of a knapsack with
+   no window, e.g. the first sweeps from lambda^0): on problems with at least
+   min_users users (default 2^22; 0 = never) every stride-th user
+   (n = max(N/64, min(N/2, 2^20)) of them) is gathered into a buffer of the
+   context, the same search runs on that sample with every budget scaled by
+   n/N (the scaling of Sec. 5.3), and the full search places its central
+   buckets (half-width 2^-8 of the sample's threshold) around the sample's
+   threshold, so that one pass usually emits the threshold's breakpoints.
+   The result is the exact threshold either way. */
+kp_status kp_set_sampled_start(void *ctx, int64_t min_users);
+
 /* Threshold search of kp_scd_sweep (Alg.4 reduce, located near the
    previous multiplier).  After one sweep on a context, each
    knapsack whose last step was small against its multiplier starts with a

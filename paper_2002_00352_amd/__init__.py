@@ -79,7 +79,7 @@ EXPORTS = ["kp_last_error", "kp_create", "kp_destroy", "kp_set_stream", "kp_eval
            "kp_set_kernel_choice", "kp_csr_row_nnz", "kp_set_window",
            "kp_get_window_stats", "kp_presolve", "kp_get_window_listed", "kp_get_launch_shape",
            "kp_set_batched_tuning", "kp_batched_shape", "kp_eval_dual_noalloc", "kp_get_batched_passes",
-           "kp_stream_read", "kp_set_alg5", "kp_set_reduce"]
+           "kp_stream_read", "kp_set_alg5", "kp_set_reduce", "kp_set_sampled_start"]
 
 
 def lib():
@@ -114,6 +114,7 @@ def lib():
         L.kp_set_window.argtypes = [vp, i32]
         L.kp_set_alg5.argtypes = [vp, i32]
         L.kp_set_reduce.argtypes = [vp, i32]
+        L.kp_set_sampled_start.argtypes = [vp, i64]
         L.kp_presolve.argtypes = [vp, P, vp, i64, i32, vp, ctypes.POINTER(i32)]
         L.kp_get_window_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64),
                                           ctypes.POINTER(i64), ctypes.POINTER(i64)]
@@ -197,6 +198,11 @@ class Context:
         """"exact" (Alg.4's threshold) or "interp" (Sec. 5.2's bucket
         interpolation)."""
         _check(lib().kp_set_reduce(self.h, {"exact": 0, "interp": 1}[mode]))
+
+    def set_sampled_start(self, min_users: int):
+        """Full searches of problems with at least min_users users start from
+        a sample's threshold (0: never)."""
+        _check(lib().kp_set_sampled_start(self.h, int(min_users)))
 
     def set_alg5(self, on: bool):
         """Alg.5's map (Sec. 5.1) for the users in its setting."""

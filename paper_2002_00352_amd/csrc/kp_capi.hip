@@ -71,6 +71,9 @@ void kp_coldesc_fill(void *dst, const double *partials, const double *lam, const
 hipError_t kp_launch_validate_csr(const int64_t *rowptr, const int32_t *col, int64_t nrows, int K,
                                   unsigned int *flags, hipStream_t stream);
 hipError_t kp_launch_fill_f64(double *dst, int64_t n, double v, hipStream_t stream);
+hipError_t kp_launch_recenter(KState *st, int K, const double *lam_hat, hipStream_t stream);
+hipError_t kp_launch_strided_users(int64_t *users, int64_t n, int64_t stride, int64_t off, hipStream_t stream);
+hipError_t kp_launch_uniform_rowptr(int64_t *rowptr, int64_t nrows, int D, hipStream_t stream);
 hipError_t kp_launch_stream_read(const void *src, int64_t n16, unsigned long long *out, int grid,
                                  hipStream_t stream);
 
@@ -134,6 +137,13 @@ struct Ctx {
   bool window_enabled = true;
   bool alg5 = false;      // Alg.5 map for the users in its setting
   bool interp = false;    // approximate reduce: interpolation inside the threshold's bucket
+  // full searches of problems with at least this many users start from the
+  // threshold of a strided sample (0: never); the sample's search runs on a
+  // child context (no windows, no sampling) in a buffer of this context
+  int64_t sample_min = (int64_t)1 << 22;
+  struct Ctx *child = nullptr;
+  void *sbuf = nullptr;
+  size_t sbuf_cap = 0;
   int stats_grid = 0;     // blocks of the last sweep launch (slots of the per-block partials)
   // shape of the last sweep launch: kernel (0 general, 1 uniform-row), users
   // per tile, blocks
@@ -692,6 +702,125 @@ SweepArgs make_args(const Prepared &P, const double *lam, const SweepWs &w, uint
   return a;
 }
 
+kp_status kp_scd_sweep_masked_impl(Ctx *c, const kp_problem *prob, const double *lambda_in, double *lambda_out,
+                                   const uint8_t *kmask, double *R, double *g, double *primal);
+
+// Start the full searches of this sweep from a sample's thresholds: every
+// stride-th user (n = max(N/64, min(N/2, 2^20)) of them) is gathered into
+// the context's sample buffer, the same SCD search runs on that sample with
+// every budget scaled by n/N on the child context, and each knapsack in full
+// search mode centres its buckets on the sample's threshold.
+kp_status sample_center(Ctx *c, const kp_problem *prob, const Prepared &P, const SweepWs &w,
+                        const double *lambda_in, const uint8_t *kmask) {
+  const int64_t N = P.pr.N;
+  const int M = P.pr.M, K = P.pr.K;
+  const int64_t n = std::max<int64_t>(N / 64, std::min<int64_t>(N / 2, (int64_t)1 << 20));
+  if (n < 1 || n >= N) return KP_OK;
+  const int64_t stride = N / n;
+  const bool csr = P.pr.fmt == KP_B_CSR;
+  const int D = P.row_nnz;
+  Carve cv;
+  const size_t o_u = cv.take((size_t)n * 8);
+  const size_t o_p = cv.take((size_t)n * M * 4);
+  const size_t o_b = csr ? 0 : cv.take((size_t)n * M * K * 4);
+  const size_t o_len = (csr && !D) ? cv.take((size_t)n * M * 8) : 0;
+  const size_t o_rp = csr ? cv.take((size_t)(n * M + 1) * 8) : 0;
+  const size_t o_col = (csr && D) ? cv.take((size_t)n * M * D * 4) : 0;
+  const size_t o_val = (csr && D) ? cv.take((size_t)n * M * D * 4) : 0;
+  const size_t o_lam = cv.take((size_t)K * 8);
+  int64_t nnz = n * M * (int64_t)D;
+  size_t o_ent = 0;
+  if (csr && !D) {
+    // the sampled rows' lengths and offsets first, to size the entries
+    if (cv.off > c->sbuf_cap) {
+      if (c->sbuf) HIP_TRY(hipFree(c->sbuf));
+      c->sbuf = nullptr;
+      c->sbuf_cap = 0;
+      if (hipMalloc(&c->sbuf, cv.off) != hipSuccess) { c->sbuf = nullptr; return fail(KP_ERR_NOMEM, "hipMalloc failed"); }
+      c->sbuf_cap = cv.off;
+    }
+    char *b = (char *)c->sbuf;
+    HIP_TRY(kp_launch_strided_users((int64_t *)(b + o_u), n, stride, stride / 2, c->stream));
+    HIP_TRY(kp_launch_gather_csr_ptr(P.pr.rowptr, (int64_t *)(b + o_u), n, M, (int64_t *)(b + o_len),
+                                     (int64_t *)(b + o_rp), c->stream));
+    int64_t *h = (int64_t *)(c->pinned + 8);
+    HIP_TRY(hipMemcpyAsync(h, (int64_t *)(b + o_rp) + n * M, 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    nnz = *h;
+    o_ent = cv.take((size_t)std::max<int64_t>(nnz, 1) * 8);
+  }
+  if (cv.off > c->sbuf_cap) {
+    // (a grown buffer keeps nothing: the general-CSR offsets are rebuilt below)
+    if (c->sbuf) {
+      HIP_TRY(hipStreamSynchronize(c->stream));
+      HIP_TRY(hipFree(c->sbuf));
+    }
+    c->sbuf = nullptr;
+    c->sbuf_cap = 0;
+    if (hipMalloc(&c->sbuf, cv.off) != hipSuccess) { c->sbuf = nullptr; return fail(KP_ERR_NOMEM, "hipMalloc failed"); }
+    c->sbuf_cap = cv.off;
+  }
+  char *b = (char *)c->sbuf;
+  int64_t *users = (int64_t *)(b + o_u);
+  HIP_TRY(kp_launch_strided_users(users, n, stride, stride / 2, c->stream));
+  kp_problem sub = *prob;
+  sub.N = n;
+  sub.p = (const float *)(b + o_p);
+  if (!csr) {
+    sub.b = (const float *)(b + o_b);
+    HIP_TRY(kp_launch_gather_dense(P.pr.p, P.pr.b, users, n, M, K, (float *)(b + o_p), (float *)(b + o_b),
+                                   c->stream));
+  } else if (D) {
+    HIP_TRY(kp_launch_gather_dense(P.pr.p, nullptr, users, n, M, K, (float *)(b + o_p), nullptr, c->stream));
+    // a user's entries are M * D consecutive values of col and val
+    HIP_TRY(kp_launch_gather_dense((const float *)P.pr.col, nullptr, users, n, M * D, 1, (float *)(b + o_col),
+                                   nullptr, c->stream));
+    HIP_TRY(kp_launch_gather_dense(P.pr.val, nullptr, users, n, M * D, 1, (float *)(b + o_val), nullptr,
+                                   c->stream));
+    HIP_TRY(kp_launch_uniform_rowptr((int64_t *)(b + o_rp), n * M, D, c->stream));
+    sub.b_rowptr = (const int64_t *)(b + o_rp);
+    sub.b_col = (const int32_t *)(b + o_col);
+    sub.b_val = (const float *)(b + o_val);
+  } else {
+    HIP_TRY(kp_launch_gather_dense(P.pr.p, nullptr, users, n, M, K, (float *)(b + o_p), nullptr, c->stream));
+    int64_t *subptr = (int64_t *)(b + o_rp);
+    HIP_TRY(kp_launch_gather_csr_ptr(P.pr.rowptr, users, n, M, (int64_t *)(b + o_len), subptr, c->stream));
+    int32_t *scol = (int32_t *)(b + o_ent);
+    float *sval = (float *)(b + o_ent + (size_t)std::max<int64_t>(nnz, 1) * 4);
+    HIP_TRY(kp_launch_gather_csr(P.pr.rowptr, P.pr.col, P.pr.val, users, n, M, subptr, scol, sval, c->stream));
+    sub.b_rowptr = subptr;
+    sub.b_col = scol;
+    sub.b_val = sval;
+  }
+  std::vector<double> Bs(K);
+  const double scale = (double)n / (double)N;
+  for (int k = 0; k < K; ++k) Bs[k] = P.B[k] * scale;
+  sub.B = Bs.data();
+  if (!c->child) {
+    void *ch = nullptr;
+    kp_status st = kp_create(&ch, c->stream, c->max_ws);
+    if (st != KP_OK) return st;
+    c->child = (Ctx *)ch;
+  }
+  Ctx *ch = c->child;
+  ch->stream = c->stream;
+  ch->window_enabled = false;
+  ch->sample_min = 0;
+  ch->ell_enabled = c->ell_enabled;
+  ch->alg5 = c->alg5;
+  ch->delta_valid = false;
+  ch->B_host.clear();
+  double *lam_hat = (double *)(b + o_lam);
+  kp_status st = kp_scd_sweep_masked_impl(ch, &sub, lambda_in, lam_hat, kmask, nullptr, nullptr, nullptr);
+  if (st != KP_OK) {
+    char m[sizeof g_err];
+    memcpy(m, g_err, sizeof m);
+    return fail(st, "sample search: %s", m);
+  }
+  HIP_TRY(kp_launch_recenter(w.st, K, lam_hat, c->stream));
+  return KP_OK;
+}
+
 kp_status eval_into(Ctx *c, const Prepared &P, const SweepWs &w, const double *lam, double *R,
                     double *g, double *primal, uint8_t *x) {
   if (P.pr.N == 0) {
@@ -769,6 +898,8 @@ kp_status kp_destroy(void *ctx) {
   if (c->delta_dev) (void)hipFree(c->delta_dev);
   if (c->B_dev) (void)hipFree(c->B_dev);
   if (c->pinned) (void)hipHostFree(c->pinned);
+  if (c->sbuf) (void)hipFree(c->sbuf);
+  if (c->child) (void)kp_destroy(c->child);
   delete c;
   return KP_OK;
 }
@@ -839,8 +970,16 @@ kp_status kp_scd_sweep_masked(void *ctx, const kp_problem *prob, const double *l
                               double *lambda_out, const uint8_t *kmask, double *R, double *g,
                               double *primal) {
   if (!ctx) return fail(KP_ERR_INVALID, "ctx is NULL");
+  return kp_scd_sweep_masked_impl((Ctx *)ctx, prob, lambda_in, lambda_out, kmask, R, g, primal);
+}
+
+}  // extern "C"
+
+namespace {
+kp_status kp_scd_sweep_masked_impl(Ctx *c, const kp_problem *prob, const double *lambda_in,
+                                   double *lambda_out, const uint8_t *kmask, double *R, double *g,
+                                   double *primal) {
   if (!lambda_in || !lambda_out) return fail(KP_ERR_INVALID, "lambda is NULL");
-  Ctx *c = (Ctx *)ctx;
   Prepared P;
   kp_status s = prepare(prob, true, P, c);
   if (s != KP_OK) return s;
@@ -870,12 +1009,20 @@ kp_status kp_scd_sweep_masked(void *ctx, const kp_problem *prob, const double *l
   // histograms of the other search modes
   bool split = false, nohist = false;
   const bool nh_gain = !P.ell_D && (P.U_nh != P.U || P.grid_nh != P.grid);
-  if (window && c->delta_valid && (w.fcap || nh_gain)) {
+  const bool sample = c->sample_min > 0 && P.pr.N >= c->sample_min && !c->interp;
+  const bool counts = window && c->delta_valid && (w.fcap || nh_gain);
+  if (counts || sample) {
     HIP_TRY(kp_launch_count_modes(w.st, K, w.modes, c->stream));
     HIP_TRY(hipMemcpyAsync(c->pinned + 20, w.modes, 8, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
-    split = w.fcap && c->pinned[20] > 0 && c->pinned[21] == 0;
-    nohist = nh_gain && c->pinned[21] == 0;
+    if (counts) {
+      split = w.fcap && c->pinned[20] > 0 && c->pinned[21] == 0;
+      nohist = nh_gain && c->pinned[21] == 0;
+    }
+    // full searches (knapsacks without a window) start from a sample
+    if (sample && c->pinned[21] > 0) {
+      if ((s = sample_center(c, prob, P, w, lambda_in, kmask)) != KP_OK) return s;
+    }
   }
   HIP_TRY(hipMemsetAsync(w.stat, 0, w.stat_bytes, c->stream));   // status, histograms
   double *Rd = R ? R : w.Rtmp;
@@ -925,6 +1072,9 @@ kp_status kp_scd_sweep_masked(void *ctx, const kp_problem *prob, const double *l
   c->delta_valid = true;
   return KP_OK;
 }
+}  // namespace
+
+extern "C" {
 
 kp_status kp_scd_sweep(void *ctx, const kp_problem *prob, const double *lambda_in,
                        double *lambda_out, double *R, double *g, double *primal) {
@@ -1166,6 +1316,13 @@ kp_status kp_set_reduce(void *ctx, int32_t mode) {
   if (!ctx) return fail(KP_ERR_INVALID, "ctx is NULL");
   if (mode != 0 && mode != 1) return fail(KP_ERR_INVALID, "reduce mode must be 0 (exact) or 1 (interpolated)");
   ((Ctx *)ctx)->interp = mode == 1;
+  return KP_OK;
+}
+
+kp_status kp_set_sampled_start(void *ctx, int64_t min_users) {
+  if (!ctx) return fail(KP_ERR_INVALID, "ctx is NULL");
+  if (min_users < 0) return fail(KP_ERR_INVALID, "min_users must be >= 0");
+  ((Ctx *)ctx)->sample_min = min_users;
   return KP_OK;
 }
 

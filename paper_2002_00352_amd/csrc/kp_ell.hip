@@ -4,7 +4,7 @@
 #include <vector>
 #include "kp_ell_impl.h"
 
-size_t kp_ell_lds_bytes(int M, int K, int D, int L, int mode, int *region_out) {
+static size_t ell_lds(int M, int K, int D, int L, int mode, int waves, int *region_out) {
   auto r16 = [](size_t b) { return (b + 15) & ~(size_t)15; };
   const bool brk = mode == KM_SCD || mode == KM_WFAIL;
   size_t region = 0;
@@ -20,17 +20,29 @@ size_t kp_ell_lds_bytes(int M, int K, int D, int L, int mode, int *region_out) {
     region = region > need ? region : need;
   }
   region = r16(region);
+  const int ew = waves;
   size_t s = r16((size_t)(K + 1) * 8) + r16((size_t)L * 8 + 8) + r16((size_t)L * 4 + 4) +
-             r16((size_t)EW * (K + 2) * 8);
+             r16((size_t)ew * (K + 2) * 8);
   if (mode != KM_EVAL) s += r16((size_t)K * 4) + r16((size_t)K * 8 + 16);
   if (mode == KM_WMAIN) s += r16((size_t)(K + 1) * sizeof(LamW));
   if (brk)   // (the listed users' pass of a window pass bins nothing: no histograms)
     s += r16((size_t)K * sizeof(XSum)) + r16((size_t)K * sizeof(KState)) +
          (mode == KM_SCD ? r16((size_t)K * KP_NB * sizeof(XSum)) + r16((size_t)K * KP_NB * 4) : 0) +
          3 * r16((size_t)K * 4) + 2 * r16((size_t)K * 8) + r16(16);
-  s += (size_t)EW * region;
+  s += (size_t)ew * region;
   if (region_out) *region_out = (int)region;
   return s;
+}
+
+// Waves per block of a mode: 8 for the full-search pass when its LDS fits,
+// else 4.
+int kp_ell_waves(int M, int K, int D, int L, int mode) {
+  if (mode == KM_SCD && ell_lds(M, K, D, L, mode, 8, nullptr) <= (size_t)160 * 1024) return 8;
+  return EW;
+}
+
+size_t kp_ell_lds_bytes(int M, int K, int D, int L, int mode, int *region_out) {
+  return ell_lds(M, K, D, L, mode, kp_ell_waves(M, K, D, L, mode), region_out);
 }
 
 // Rank of the laminar matroid on M items (the most items any feasible x_i
@@ -73,6 +85,7 @@ hipError_t kp_launch_ell(const SweepArgs &a, int D, int grid, int mode, hipStrea
   if (g.rows > g.K + 2) g.rows = g.K + 2;
   g.x4 = (((uintptr_t)a.pr.p | (uintptr_t)a.pr.col | (uintptr_t)a.pr.val) & 15) == 0;
   g.compact = laminar_rank(a.tree, g.M) <= KP_SEL_MAX;
+  g.waves = kp_ell_waves(g.M, g.K, D, a.tree.L, mode);
   switch (mode) {
     case KM_EVAL: return kp_launch_ell_mode<KM_EVAL>(a, g, lds, grid, D, stream, used);
     case KM_SCD: return kp_launch_ell_mode<KM_SCD>(a, g, lds, grid, D, stream, used);
@@ -86,11 +99,12 @@ hipError_t kp_launch_ell(const SweepArgs &a, int D, int grid, int mode, hipStrea
 int kp_ell_resident_grid(int D, int mode, int M, int K, int L) {
   if (M < 1 || M > 16 || (D != 1 && D != 2) || mode < 0 || mode > 3) return 0;
   const size_t lds = kp_ell_lds_bytes(M, K, D, L, mode, nullptr);
+  const int w = kp_ell_waves(M, K, D, L, mode);
   switch (mode) {
-    case KM_EVAL: return kp_ell_resident_mode<KM_EVAL>(D, M, lds);
-    case KM_SCD: return kp_ell_resident_mode<KM_SCD>(D, M, lds);
-    case KM_WMAIN: return kp_ell_resident_mode<KM_WMAIN>(D, M, lds);
-    default: return kp_ell_resident_mode<KM_WFAIL>(D, M, lds);
+    case KM_EVAL: return kp_ell_resident_mode<KM_EVAL>(D, M, lds, w);
+    case KM_SCD: return kp_ell_resident_mode<KM_SCD>(D, M, lds, w);
+    case KM_WMAIN: return kp_ell_resident_mode<KM_WMAIN>(D, M, lds, w);
+    default: return kp_ell_resident_mode<KM_WFAIL>(D, M, lds, w);
   }
 }
 

@@ -19,8 +19,7 @@
 #include <string.h>
 #include "kp_device.h"
 
-#define EW 4                 // waves per block
-#define ENT (EW * 64)
+#define EW 4                 // waves per block (the full-search pass: 8 when its LDS allows)
 
 // wave-wide sum in a fixed butterfly order; every lane gets lane 0's value
 __device__ __forceinline__ double wave_sum(double v) {
@@ -83,6 +82,7 @@ struct EllGeom {
   int rows;           // statistics rows (of 65 doubles) per chunk
   int x4;             // p, col and val are 16-byte aligned: full tiles use 16-byte loads
   int compact;        // at most KP_SEL_MAX items can be selected (the matroid's rank)
+  int waves;          // waves per block of the launch
 };
 
 // Breakpoint phase of one user (one lane) from its per-lane LDS scratch:
@@ -359,15 +359,23 @@ __device__ __forceinline__ void scd_user(const SweepArgs &a, int M, int K, int L
 // every lane busy.
 enum { KM_EVAL = 0, KM_SCD = 1, KM_WMAIN = 2, KM_WFAIL = 3 };
 
+// Waves per block (WPB): 4; the full-search pass keeps K x 64 exact
+// histogram bins per block in LDS, so when its LDS allows it runs 8 waves per
+// block (one block per compute unit, two waves per SIMD) rather than 4 (which
+// its LDS would hold to one block).
+
 // The window main pass is held to 3 waves per SIMD, the occupancy its LDS
 // allows (without the hint it compiles just above the register limit).
 template <int MODE> struct EllWaves { static constexpr int value = MODE == 2 ? 3 : 1; };
 
 // EM: the item-count class (8, 10, 12, 16); EXACT: M equals EM, so every
 // test of an item index against M folds away.
-template <int D, int MODE, int EM, bool EXACT>
-__global__ void __launch_bounds__(ENT) __attribute__((amdgpu_waves_per_eu(EllWaves<MODE>::value, 8)))
+template <int D, int MODE, int EM, bool EXACT, int WPB>
+__global__ void __launch_bounds__(WPB * 64)
+__attribute__((amdgpu_waves_per_eu(EllWaves<MODE>::value, 8)))
 k_ell(const SweepArgs a, const EllGeom g) {
+  constexpr int EWM = WPB;
+  constexpr int ENT = EWM * 64;
   constexpr bool BREAK = (MODE == KM_SCD || MODE == KM_WFAIL);   // breakpoint phase
   constexpr bool STAGED = (MODE != KM_WFAIL);                    // contiguous tiles
   extern __shared__ __align__(16) unsigned char smem[];
@@ -378,7 +386,7 @@ k_ell(const SweepArgs a, const EllGeom g) {
   double *lam = (double *)carve((size_t)(K + 1) * 8);   // [K] = 0 for the clamped reads
   uint64_t *tmask = (uint64_t *)carve((size_t)a.tree.L * 8 + 8);
   int *tcap = (int *)carve((size_t)a.tree.L * 4 + 4);
-  double *wacc = (double *)carve((size_t)EW * (K + 2) * 8);
+  double *wacc = (double *)carve((size_t)EWM * (K + 2) * 8);
   KState *kst = BREAK ? (KState *)carve((size_t)K * sizeof(KState)) : nullptr;
   XSum *hs = nullptr;
   uint32_t *hc = nullptr, *kcnt = nullptr, *kpos = nullptr, *kovf = nullptr, *nstage = nullptr;
@@ -411,7 +419,7 @@ k_ell(const SweepArgs a, const EllGeom g) {
   for (int t = tid; t <= K; t += ENT) lam[t] = t < K ? a.lam[t] : 0.0;
   if (MODE == KM_WMAIN && tid == 0) lw[K] = LamW{0.0, 0.0f, 0.0f};
   for (int t = tid; t < a.tree.L; t += ENT) { tmask[t] = a.tree.mask[t]; tcap[t] = a.tree.cap[t]; }
-  for (int t = tid; t < EW * (K + 2); t += ENT) wacc[t] = 0.0;
+  for (int t = tid; t < EWM * (K + 2); t += ENT) wacc[t] = 0.0;
   if (MODE != KM_EVAL) {
     for (int t = tid; t < K; t += ENT) {
       kmode[t] = a.st[t].mode;
@@ -456,7 +464,7 @@ k_ell(const SweepArgs a, const EllGeom g) {
   __syncthreads();
   const int L = a.tree.L;
   const int64_t N = a.pr.N;
-  const int64_t W = (int64_t)gridDim.x * EW;
+  const int64_t W = (int64_t)gridDim.x * EWM;
   const int64_t ntiles = MODE == KM_WFAIL ? ((int64_t)nlisted + 63) / 64 : a.ntiles;
 
   // staging area of the wave (contiguous tiles); the statistics rows reuse it
@@ -468,7 +476,7 @@ k_ell(const SweepArgs a, const EllGeom g) {
   uint32_t ch_pos = 0, ch_end = 0;   // the wave's reserved list chunk (window main pass)
   uint32_t nlist = 0;                 // users the wave listed
   // tile indices fit 32 bits (the launcher rejects more than 2^31 - 1 tiles)
-  for (int tile = (int)blockIdx.x * EW + wv; tile < (int)ntiles; tile += (int)W) {
+  for (int tile = (int)blockIdx.x * EWM + wv; tile < (int)ntiles; tile += (int)W) {
     const int64_t u0 = (int64_t)tile * 64;
     float pv[EM];
     int cl[EM * D];
@@ -871,7 +879,7 @@ k_ell(const SweepArgs a, const EllGeom g) {
   if (a.want_stats && STAGED) {
     for (int c = tid; c < K + 2; c += ENT) {
       double s = 0.0;
-      for (int w = 0; w < EW; ++w) s = s + wacc[w * (K + 2) + c];
+      for (int w = 0; w < EWM; ++w) s = s + wacc[w * (K + 2) + c];
       a.partials[(size_t)blockIdx.x * (K + 2) + c] = s;
     }
   }
@@ -883,10 +891,10 @@ size_t kp_ell_lds_bytes(int M, int K, int D, int L, int mode, int *region_out);
 // Persistent launch: never more blocks than can be resident at once (the
 // tile loop strides over the rest), so no block waits for another to finish
 // and every CU stays busy to the end.  grid <= 0 asks for exactly that many.
-template <int D, int MODE, int EM, bool EXACT>
+template <int D, int MODE, int EM, bool EXACT, int WPB>
 static hipError_t launch_ell_t(const SweepArgs &a, const EllGeom &g, size_t lds, int grid,
                                hipStream_t stream, int *used) {
-  const void *fn = (const void *)k_ell<D, MODE, EM, EXACT>;
+  const void *fn = (const void *)k_ell<D, MODE, EM, EXACT, WPB>;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -899,58 +907,75 @@ static hipError_t launch_ell_t(const SweepArgs &a, const EllGeom &g, size_t lds,
       cus = 256;
   }
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, ENT, lds) != hipSuccess || per_cu < 1)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, WPB * 64, lds) != hipSuccess || per_cu < 1)
     per_cu = 1;
   const int resident = cus * per_cu;
   if (grid <= 0 || grid > resident) grid = resident;
   if (used) *used = grid;
-  hipLaunchKernelGGL((k_ell<D, MODE, EM, EXACT>), dim3(grid), dim3(ENT), lds, stream, a, g);
+  hipLaunchKernelGGL((k_ell<D, MODE, EM, EXACT, WPB>), dim3(grid), dim3(WPB * 64), lds, stream, a, g);
   return hipGetLastError();
+}
+
+template <int D, int MODE, int WPB>
+static hipError_t launch_ell_mw(const SweepArgs &a, const EllGeom &g, size_t lds, int grid,
+                                hipStream_t stream, int *used) {
+  switch (g.M) {
+    case 8: return launch_ell_t<D, MODE, 8, true, WPB>(a, g, lds, grid, stream, used);
+    case 10: return launch_ell_t<D, MODE, 10, true, WPB>(a, g, lds, grid, stream, used);
+    case 12: return launch_ell_t<D, MODE, 12, true, WPB>(a, g, lds, grid, stream, used);
+    case 16: return launch_ell_t<D, MODE, 16, true, WPB>(a, g, lds, grid, stream, used);
+    default: break;
+  }
+  if (g.M <= 8) return launch_ell_t<D, MODE, 8, false, WPB>(a, g, lds, grid, stream, used);
+  if (g.M <= 10) return launch_ell_t<D, MODE, 10, false, WPB>(a, g, lds, grid, stream, used);
+  if (g.M <= 12) return launch_ell_t<D, MODE, 12, false, WPB>(a, g, lds, grid, stream, used);
+  return launch_ell_t<D, MODE, 16, false, WPB>(a, g, lds, grid, stream, used);
 }
 
 template <int D, int MODE>
 static hipError_t launch_ell_m(const SweepArgs &a, const EllGeom &g, size_t lds, int grid,
                                hipStream_t stream, int *used) {
-  switch (g.M) {
-    case 8: return launch_ell_t<D, MODE, 8, true>(a, g, lds, grid, stream, used);
-    case 10: return launch_ell_t<D, MODE, 10, true>(a, g, lds, grid, stream, used);
-    case 12: return launch_ell_t<D, MODE, 12, true>(a, g, lds, grid, stream, used);
-    case 16: return launch_ell_t<D, MODE, 16, true>(a, g, lds, grid, stream, used);
-    default: break;
+  if constexpr (MODE == KM_SCD) {
+    if (g.waves == 8) return launch_ell_mw<D, MODE, 8>(a, g, lds, grid, stream, used);
   }
-  if (g.M <= 8) return launch_ell_t<D, MODE, 8, false>(a, g, lds, grid, stream, used);
-  if (g.M <= 10) return launch_ell_t<D, MODE, 10, false>(a, g, lds, grid, stream, used);
-  if (g.M <= 12) return launch_ell_t<D, MODE, 12, false>(a, g, lds, grid, stream, used);
-  return launch_ell_t<D, MODE, 16, false>(a, g, lds, grid, stream, used);
+  return launch_ell_mw<D, MODE, EW>(a, g, lds, grid, stream, used);
 }
 
-template <int D, int MODE, int EM, bool EXACT>
+template <int D, int MODE, int EM, bool EXACT, int WPB>
 static int resident_blocks_t(size_t lds) {
-  const void *fn = (const void *)k_ell<D, MODE, EM, EXACT>;
+  const void *fn = (const void *)k_ell<D, MODE, EM, EXACT, WPB>;
   if (lds > 64 * 1024 &&
       hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return 0;
   int per_cu = 0, dev = 0, cus = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, ENT, lds) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, WPB * 64, lds) != hipSuccess) return 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
   return per_cu * cus;
 }
 
-template <int D, int MODE>
-static int resident_blocks_m(int M, size_t lds) {
+template <int D, int MODE, int WPB>
+static int resident_blocks_mw(int M, size_t lds) {
   switch (M) {
-    case 8: return resident_blocks_t<D, MODE, 8, true>(lds);
-    case 10: return resident_blocks_t<D, MODE, 10, true>(lds);
-    case 12: return resident_blocks_t<D, MODE, 12, true>(lds);
-    case 16: return resident_blocks_t<D, MODE, 16, true>(lds);
+    case 8: return resident_blocks_t<D, MODE, 8, true, WPB>(lds);
+    case 10: return resident_blocks_t<D, MODE, 10, true, WPB>(lds);
+    case 12: return resident_blocks_t<D, MODE, 12, true, WPB>(lds);
+    case 16: return resident_blocks_t<D, MODE, 16, true, WPB>(lds);
     default: break;
   }
-  if (M <= 8) return resident_blocks_t<D, MODE, 8, false>(lds);
-  if (M <= 10) return resident_blocks_t<D, MODE, 10, false>(lds);
-  if (M <= 12) return resident_blocks_t<D, MODE, 12, false>(lds);
-  return resident_blocks_t<D, MODE, 16, false>(lds);
+  if (M <= 8) return resident_blocks_t<D, MODE, 8, false, WPB>(lds);
+  if (M <= 10) return resident_blocks_t<D, MODE, 10, false, WPB>(lds);
+  if (M <= 12) return resident_blocks_t<D, MODE, 12, false, WPB>(lds);
+  return resident_blocks_t<D, MODE, 16, false, WPB>(lds);
+}
+
+template <int D, int MODE>
+static int resident_blocks_m(int M, size_t lds, int waves) {
+  if constexpr (MODE == KM_SCD) {
+    if (waves == 8) return resident_blocks_mw<D, MODE, 8>(M, lds);
+  }
+  return resident_blocks_mw<D, MODE, EW>(M, lds);
 }
 
 // one translation unit per mode instantiates these (kp_ell_m<mode>.hip)
@@ -958,4 +983,4 @@ template <int MODE>
 hipError_t kp_launch_ell_mode(const SweepArgs &a, const EllGeom &g, size_t lds, int grid, int D,
                               hipStream_t stream, int *used);
 template <int MODE>
-int kp_ell_resident_mode(int D, int M, size_t lds);
+int kp_ell_resident_mode(int D, int M, size_t lds, int waves);

@@ -10,6 +10,6 @@ hipError_t kp_launch_ell_mode<KM_SCD>(const SweepArgs &a, const EllGeom &g, size
 }
 
 template <>
-int kp_ell_resident_mode<KM_SCD>(int D, int M, size_t lds) {
-  return D == 1 ? resident_blocks_m<1, KM_SCD>(M, lds) : resident_blocks_m<2, KM_SCD>(M, lds);
+int kp_ell_resident_mode<KM_SCD>(int D, int M, size_t lds, int waves) {
+  return D == 1 ? resident_blocks_m<1, KM_SCD>(M, lds, waves) : resident_blocks_m<2, KM_SCD>(M, lds, waves);
 }

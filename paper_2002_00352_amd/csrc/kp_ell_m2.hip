@@ -10,6 +10,6 @@ hipError_t kp_launch_ell_mode<KM_WMAIN>(const SweepArgs &a, const EllGeom &g, si
 }
 
 template <>
-int kp_ell_resident_mode<KM_WMAIN>(int D, int M, size_t lds) {
-  return D == 1 ? resident_blocks_m<1, KM_WMAIN>(M, lds) : resident_blocks_m<2, KM_WMAIN>(M, lds);
+int kp_ell_resident_mode<KM_WMAIN>(int D, int M, size_t lds, int waves) {
+  return D == 1 ? resident_blocks_m<1, KM_WMAIN>(M, lds, waves) : resident_blocks_m<2, KM_WMAIN>(M, lds, waves);
 }

@@ -932,9 +932,10 @@ __global__ void k_scd_init(KState *st, int K, const double *lam_in, const uint8_
     const double base = lam_in[k] > 0x1p-20 ? lam_in[k] : 0x1p-20;
     d = ldexp(1.0, ilogb(base) - 20);
   } else if (!hinted) {
-    // no history: 2^-10 of the multiplier (or 2^-30 absolute), a power of two
-    const double base = lam_in[k] > 0x1p-20 ? lam_in[k] : 0x1p-20;
-    d = ldexp(1.0, ilogb(base) - 10);
+    // no history: 2^-10 of the multiplier, a power of two; at a multiplier
+    // of 0 (or below 2^-20) 2^-20, so that the base-2 buckets around 0 reach
+    // 2^11 before they are capped
+    d = lam_in[k] > 0x1p-20 ? ldexp(1.0, ilogb(lam_in[k]) - 10) : 0x1p-20;
   }
   s.delta = d;
   s.fab = xs_zero();
@@ -1276,6 +1277,33 @@ __global__ void k_scd_finish(const KState *st, int K, const double *lam_in, doub
     delta_next[k] = ldexp(1.0, ilogb(w) + 1);
     delta_next[K + k] = w;
   }
+}
+
+// A full search (no window) centres its buckets on the threshold of a
+// sample of users (lam_hat, from the same search on the sample with its
+// budgets scaled): buckets of half-width 2^-8 of it around it, so the central
+// buckets emitted by the first pass usually hold the threshold.  Exactness
+// does not depend on it (the threshold is still located by the full
+// search's own sums).
+__global__ void k_scd_recenter(KState *st, int K, const double *lam_hat) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  const double c = lam_hat[k];
+  if (st[k].mode != KS_EXP || !(c > 0x1p-20)) return;
+  st[k].center = c;
+  st[k].delta = ldexp(1.0, ilogb(c) - 8);
+}
+
+// users[s] = s * stride + off (a strided sample)
+__global__ void k_strided_users(int64_t *users, int64_t n, int64_t stride, int64_t off) {
+  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n; s += (int64_t)gridDim.x * blockDim.x)
+    users[s] = s * stride + off;
+}
+
+// rowptr of a sample whose rows all hold D entries: r * D
+__global__ void k_uniform_rowptr(int64_t *rowptr, int64_t nrows, int D) {
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r <= nrows; r += (int64_t)gridDim.x * blockDim.x)
+    rowptr[r] = r * D;
 }
 
 // Knapsacks starting with a window and those needing another search mode.
@@ -1785,9 +1813,8 @@ __global__ void k_scd_init_flat(KState *st, int Kf, const double *const *lam_in,
   s.n_emit = 0;
   s.flags = 0;
   s.center = l;
-  const double base = l > 0x1p-20 ? l : 0x1p-20;
   // bucket width: a power of two above the last step when there is one
-  s.delta = (hint && hint[f] > 0.0) ? hint[f] : ldexp(1.0, ilogb(base) - 10);
+  s.delta = (hint && hint[f] > 0.0) ? hint[f] : (l > 0x1p-20 ? ldexp(1.0, ilogb(l) - 10) : 0x1p-20);
   s.fab = xs_zero();
   s.result = l;
   s.klo = 0;
@@ -2040,6 +2067,21 @@ hipError_t kp_launch_gather_csr(const int64_t *rowptr, const int32_t *col, const
                                 int32_t *scol, float *sval, hipStream_t stream) {
   hipLaunchKernelGGL(k_gather_csr, dim3(gather_blocks(n * M)), dim3(256), 0, stream, rowptr, col, val,
                      users, n, M, subptr, scol, sval);
+  return hipGetLastError();
+}
+
+hipError_t kp_launch_recenter(KState *st, int K, const double *lam_hat, hipStream_t stream) {
+  hipLaunchKernelGGL(k_scd_recenter, dim3((K + 63) / 64), dim3(64), 0, stream, st, K, lam_hat);
+  return hipGetLastError();
+}
+
+hipError_t kp_launch_strided_users(int64_t *users, int64_t n, int64_t stride, int64_t off, hipStream_t stream) {
+  hipLaunchKernelGGL(k_strided_users, dim3(gather_blocks(n)), dim3(256), 0, stream, users, n, stride, off);
+  return hipGetLastError();
+}
+
+hipError_t kp_launch_uniform_rowptr(int64_t *rowptr, int64_t nrows, int D, hipStream_t stream) {
+  hipLaunchKernelGGL(k_uniform_rowptr, dim3(gather_blocks(nrows + 1)), dim3(256), 0, stream, rowptr, nrows, D);
   return hipGetLastError();
 }
 

@@ -248,6 +248,47 @@ def test_off_grid_costs_trajectory_twice(name, mk):
         assert np.array_equal(a, b)
 
 
+SAMPLED_CASES = [
+    ("c3-csr-declared-rows", lambda: kpgen.config_instance(3, N=20000), None),
+    ("c2-dense", lambda: kpgen.config_instance(2, N=4000), None),
+    ("c3-csr-general-rows", lambda: kpgen.config_instance(3, N=6000), 0),
+    ("laminar-dense-K9", lambda: random_instance(np.random.default_rng(81), 5000, 12, 9,
+                                                 tree=random_laminar(12, np.random.default_rng(82)),
+                                                 frac=0.15), None),
+]
+
+
+@gpu
+@pytest.mark.parametrize("name,mk,row_nnz", SAMPLED_CASES, ids=[c[0] for c in SAMPLED_CASES])
+def test_sampled_start_trajectory(name, mk, row_nnz):
+    """Full searches that start from a strided sample's threshold
+    (kp_set_sampled_start, here on small instances): along SCD trajectories
+    from lambda = 0 -- with windows, and with every iteration a full search --
+    every update equals the oracle's bit for bit (the sample only places the
+    buckets), for uniform-row CSR, general CSR and dense costs."""
+    kp, torch = _kp()
+    print("case", name, flush=True)
+    inst = mk()
+    if row_nnz is None:
+        prob = kp.Problem.from_host(inst)
+    else:
+        host = kp.Problem.from_host(inst)
+        prob = kp.Problem(host.p, inst.B, inst.tree.parent, inst.tree.cap, inst.tree.leaf_of_item,
+                          rowptr=host.rowptr, col=host.col, val=host.val, N=inst.N, M=inst.M, K=inst.K,
+                          row_nnz=row_nnz)
+    ctxs = [kp.Context(), kp.Context()]
+    for c in ctxs:
+        c.set_sampled_start(1000)
+    ctxs[1].set_window(False)
+    lam = np.zeros(inst.K)
+    for t in range(6):
+        want = oracle.scd_sweep(inst, lam)
+        for ctx in ctxs:
+            got = kp.kp_scd_sweep(prob, _lamd(torch, lam), ctx=ctx)["lam"].cpu().numpy()
+            assert np.array_equal(got, want), (t, np.flatnonzero(got != want))
+        lam = want
+
+
 @gpu
 def test_dual_autograd_matches_oracle_gradient():
     kp, torch = _kp()
