@@ -159,8 +159,13 @@ kp_status kp_dual_backward(void *ctx, const kp_problem *prob, const double *R,
    value p~_i = sum_j p_ij x_ij - sum_k lambda_k sum_j b_ijk x_ij ascending
    (ties: lower user index first) and the shortest prefix of that order whose
    removal brings every violated knapsack within budget is reset to x_i = 0.
+   A violated knapsack counts as within budget once its total consumption
+   minus the reset users' consumption, both summed exactly, is at most B_k
+   (so the reset set does not depend on a summation order; exact for costs
+   that are multiples of 2^-56 with totals below 2^38).  R_out = R(x(lambda))
+   minus the removed consumption; primal_out likewise.  N < 2^32.
    Outputs (DEV): x_out [N*M] (may be NULL), primal_out [1], R_out [K],
-   n_reset_out [1] (int64).  Synchronises the context stream. */
+   n_reset_out [1] (int64).  Synchronises the context stream (three times). */
 kp_status kp_primal_fixup(void *ctx, const kp_problem *prob, const double *lambda,
                           uint8_t *x_out, double *primal_out, double *R_out,
                           int64_t *n_reset_out);

@@ -552,6 +552,10 @@ double orc_consumption_at(const orc_problem *pr, const double *lam, int k, doubl
 /*   violated at the start are walked; the shortest prefix of that ordered   */
 /*   list that brings every violated k within budget is reset.               */
 /* mode 1 (literal): every user is walked in that order.                     */
+/* A violated knapsack counts as covered once its total consumption minus    */
+/* the reset users' consumption, both exact sums (xsum), is at most B_k: the  */
+/* consumption a reset leaves is a real number (reading A24 applied to Sec.  */
+/* 5.4), so the reset set does not depend on a summation order.              */
 /* Outputs: x [N*M] after reset (optional), P, R [K], the reset count, and   */
 /* the reset users in reset order (optional, up to cap).                     */
 /* ------------------------------------------------------------------------ */
@@ -580,6 +584,8 @@ int orc_fixup(const orc_problem *pr, const double *lam, int mode, unsigned char 
   /* per-user consumption row */
   double *v = (double *)malloc(sizeof(double) * (size_t)K);
   ukey_t *list = (ukey_t *)malloc(sizeof(ukey_t) * (size_t)(N > 0 ? N : 1));
+  /* left[k]: exact consumption of violated knapsack k by the users not reset */
+  xsum *left = (xsum *)calloc((size_t)K, sizeof(xsum));
   int64_t n = 0;
   for (int64_t i = 0; i < N && any; ++i) {
     int uses = 0;
@@ -588,10 +594,15 @@ int orc_fixup(const orc_problem *pr, const double *lam, int mode, unsigned char 
       int64_t r = i * M + j;
       if (!x[r]) continue;
       if (pr->b_format == 0) {
-        for (int k = 0; k < K; ++k) v[k] = v[k] + (double)pr->b[r * K + k];
+        for (int k = 0; k < K; ++k) {
+          v[k] = v[k] + (double)pr->b[r * K + k];
+          if (viol[k]) xsum_add(&left[k], (double)pr->b[r * K + k]);
+        }
       } else {
-        for (int64_t e = pr->rowptr[r]; e < pr->rowptr[r + 1]; ++e)
+        for (int64_t e = pr->rowptr[r]; e < pr->rowptr[r + 1]; ++e) {
           v[pr->col[e]] = v[pr->col[e]] + (double)pr->val[e];
+          if (viol[pr->col[e]]) xsum_add(&left[pr->col[e]], (double)pr->val[e]);
+        }
       }
     }
     for (int k = 0; k < K; ++k) uses |= viol[k] && v[k] > 0.0;
@@ -601,7 +612,7 @@ int orc_fixup(const orc_problem *pr, const double *lam, int mode, unsigned char 
   int64_t reset = 0;
   for (int64_t t = 0; t < n; ++t) {
     int ok = 1;
-    for (int k = 0; k < K; ++k) ok &= R[k] <= pr->B[k];
+    for (int k = 0; k < K; ++k) ok &= !viol[k] || xsum_cmp(&left[k], pr->B[k]) <= 0;
     if (ok) break;
     int64_t i = list[t].i;
     for (int j = 0; j < M; ++j) {
@@ -609,10 +620,11 @@ int orc_fixup(const orc_problem *pr, const double *lam, int mode, unsigned char 
       if (!x[r]) continue;
       x[r] = 0;
       if (pr->b_format == 0) {
-        for (int k = 0; k < K; ++k) R[k] = R[k] - (double)pr->b[r * K + k];
+        for (int k = 0; k < K; ++k)
+          if (viol[k]) xsum_add(&left[k], -(double)pr->b[r * K + k]);
       } else {
         for (int64_t e = pr->rowptr[r]; e < pr->rowptr[r + 1]; ++e)
-          R[pr->col[e]] = R[pr->col[e]] - (double)pr->val[e];
+          if (viol[pr->col[e]]) xsum_add(&left[pr->col[e]], -(double)pr->val[e]);
       }
     }
     if (reset_list && reset < reset_cap) reset_list[reset] = i;
@@ -643,7 +655,7 @@ int orc_fixup(const orc_problem *pr, const double *lam, int mode, unsigned char 
   *P_out = nval(&Ps);
   *n_reset = reset;
   if (x_out) memcpy(x_out, x, (size_t)(N * M));
-  free(Rs); free(x); free(G); free(R); free(viol); free(v); free(list);
+  free(Rs); free(x); free(G); free(R); free(viol); free(v); free(list); free(left);
   return 0;
 }
 

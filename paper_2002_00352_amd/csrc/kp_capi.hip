@@ -45,10 +45,10 @@ hipError_t kp_launch_gather_csr(const int64_t *rowptr, const int32_t *col, const
 hipError_t kp_launch_dual_backward(int K, const double *R, const double *B, const double *gout,
                                    double *glam, hipStream_t stream);
 hipError_t kp_launch_validate(const float *v, int64_t n, unsigned int *flags, hipStream_t stream);
-hipError_t kp_launch_fixup_pipeline(const double *uv, int nv, const double *G, int64_t N,
-                                    const double *RB, ProbDev pr, uint8_t *x, const double *R,
-                                    const double *P, double *R_out, double *P_out, int64_t *n_reset,
-                                    void *scratch, hipStream_t stream, uint32_t *ncand_host_pinned);
+hipError_t kp_launch_fixup_pipeline(ProbDev pr, uint8_t *x, const double *lam, const int *kv, const int *vk,
+                                    const double *Bv, int nv, const double *R, const double *P,
+                                    double *R_out, double *P_out, int64_t *n_reset, void *scratch,
+                                    hipStream_t stream, uint32_t *pinned, int persist);
 size_t kp_fixup_scratch_bytes(int64_t N, int nv, int K);
 size_t kp_ell_lds_bytes(int M, int K, int D, int L, int mode, int *region_out);
 hipError_t kp_launch_ell(const SweepArgs &a, int D, int grid, int mode, hipStream_t stream, int *used);
@@ -1425,7 +1425,8 @@ kp_status kp_primal_fixup(void *ctx, const kp_problem *prob, const double *lambd
   // pass 1: x(lambda), R, P
   SweepWs w;
   if ((s = carve_ws(c, P, false, w)) != KP_OK) return s;
-  // workspace beyond the sweep's: x (when the caller gives none), G, uv, kv map, RB, sort scratch
+  // workspace beyond the sweep's: x (when the caller gives none), the
+  // violated slots, the post-processing scratch
   Carve cv;
   cv.off = 0;
   {
@@ -1437,47 +1438,42 @@ kp_status kp_primal_fixup(void *ctx, const kp_problem *prob, const double *lambd
   const size_t o_x = cv.take(x_out ? 0 : (size_t)N * P.pr.M);
   const size_t o_Rv = cv.take((size_t)K * 8);
   const size_t o_Pv = cv.take(8);
-  // size the rest for the worst case (every knapsack violated)
-  const size_t o_G = cv.take((size_t)N * 8);
-  const size_t o_uv = cv.take((size_t)N * K * 8);
-  const size_t o_map = cv.take((size_t)K * 4);
-  const size_t o_RB = cv.take((size_t)K * 16);
+  const size_t o_kv = cv.take((size_t)K * 4);
+  const size_t o_vk = cv.take((size_t)K * 4);
+  const size_t o_Bv = cv.take((size_t)K * 8);
+  // sized for the worst case (every knapsack violated)
   const size_t o_scr = cv.take(kp_fixup_scratch_bytes(N, K, K));
   if ((s = ensure_ws(c, cv.off)) != KP_OK) return s;
   if ((s = carve_ws(c, P, false, w)) != KP_OK) return s;   // re-carve after a possible regrow
   char *b = (char *)c->ws;
   uint8_t *xd = x_out ? x_out : (uint8_t *)(b + o_x);
   double *Rv = (double *)(b + o_Rv), *Pv = (double *)(b + o_Pv);
-  double *Gd = (double *)(b + o_G), *uv = (double *)(b + o_uv), *RB = (double *)(b + o_RB);
-  int *map = (int *)(b + o_map);
+  int *kvd = (int *)(b + o_kv), *vkd = (int *)(b + o_vk);
+  double *Bvd = (double *)(b + o_Bv);
   if ((s = upload_B(c, P, w)) != KP_OK) return s;
   if ((s = eval_into(c, P, w, lambda, Rv, w.gtmp, Pv, xd)) != KP_OK) return s;
   std::vector<double> Rh(K);
   HIP_TRY(hipMemcpyAsync(Rh.data(), Rv, (size_t)K * 8, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
-  std::vector<int> kv(K, -1);
-  std::vector<double> rb;
+  std::vector<int> kv(K, -1), vk;
+  std::vector<double> bv;
   int nv = 0;
   for (int k = 0; k < K; ++k)
-    if (Rh[k] > P.B[k]) { kv[k] = nv++; rb.push_back(Rh[k]); rb.push_back(P.B[k]); }
+    if (Rh[k] > P.B[k]) { kv[k] = nv++; vk.push_back(k); bv.push_back(P.B[k]); }
   if (nv == 0) {
     HIP_TRY(hipMemcpyAsync(R_out, Rv, (size_t)K * 8, hipMemcpyDeviceToDevice, c->stream));
     HIP_TRY(hipMemcpyAsync(primal_out, Pv, 8, hipMemcpyDeviceToDevice, c->stream));
     HIP_TRY(hipMemsetAsync(n_reset_out, 0, 8, c->stream));
     return KP_OK;
   }
-  HIP_TRY(hipMemcpyAsync(map, kv.data(), (size_t)K * 4, hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(hipMemcpyAsync(RB, rb.data(), rb.size() * 8, hipMemcpyHostToDevice, c->stream));
-  // pass 2: per-user group dual value and consumption of the violated knapsacks
-  SweepArgs a = make_args(P, lambda, w, nullptr, false);
-  a.G_out = Gd;
-  a.uv_out = uv;
-  a.kv_map = map;
-  a.nv = nv;
-  int fx_grid = 0;
-  HIP_TRY(kp_launch_sweep(a, P.U, P.grid, false, c->stream, &fx_grid));
-  HIP_TRY(kp_launch_fixup_pipeline(uv, nv, Gd, N, RB, P.pr, xd, Rv, Pv, R_out, primal_out,
-                                   n_reset_out, b + o_scr, c->stream, (uint32_t *)(c->pinned + 4)));
+  HIP_TRY(hipMemcpyAsync(kvd, kv.data(), (size_t)K * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(vkd, vk.data(), (size_t)nv * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(Bvd, bv.data(), (size_t)nv * 8, hipMemcpyHostToDevice, c->stream));
+  // blocks of the passes over users: a few per compute unit
+  const int64_t nch = (N + 4095) / 4096;
+  const int persist = (int)std::max<int64_t>(1, std::min<int64_t>(nch, 1024));
+  HIP_TRY(kp_launch_fixup_pipeline(P.pr, xd, lambda, kvd, vkd, Bvd, nv, Rv, Pv, R_out, primal_out, n_reset_out,
+                                   b + o_scr, c->stream, (uint32_t *)(c->pinned + 48), persist));
   return KP_OK;
 }
 

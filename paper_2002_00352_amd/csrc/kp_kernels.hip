@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
+#include <algorithm>
 #include "kp_internal.h"
 
 #define NT 256
@@ -1450,32 +1451,50 @@ __global__ void k_validate_csr(const int64_t *rowptr, const int32_t *col, int64_
 }
 
 // ---------------------------------------------------------------------------
-// post-processing for feasibility: candidate compaction, stable LSD radix
-// sort of (group dual value, user) keys, per-knapsack prefix search, reset
+// post-processing for feasibility (Sec. 5.4): the candidates (users whose
+// solution consumes a violated knapsack) are taken in (G_i asc, i asc) order
+// and the shortest prefix whose reset covers every violated knapsack is
+// reset.  No candidate list is sorted whole: splitters drawn from a strided
+// sample of the candidates' G values cut the key range into nb bins; one pass
+// over the users adds every candidate's costs on the violated knapsacks into
+// per-bin exact sums; the bin in which the last knapsack becomes covered is
+// found from the bins' prefix sums; only that bin's users are sorted (stable
+// LSD radix sort of G's bits over a list compacted in user order) and
+// scanned; then the users of the earlier bins and the scanned prefix are
+// reset.  Coverage compares exact sums (two-limb fixed point) with B_k:
+// the consumption a reset leaves is a real sum, so the reset set does not
+// depend on any summation order.
 // ---------------------------------------------------------------------------
 #define FX_NT 256
 #define FX_IPT 16                       // items per thread in the sort / scan kernels
 #define FX_CHUNK (FX_NT * FX_IPT)
+#define FX_NONE 0xFFu                   // bin byte of a user that is not a candidate
+#define FX_LDS_MAX (48 * 1024)          // per-block accumulators above this live in global memory
 
-// candidate = a user whose solution consumes at least one violated knapsack
-__global__ void __launch_bounds__(FX_NT) k_fix_count(const double *uv, int nv, int64_t N,
-                                                     uint32_t *bcnt) {
-  __shared__ uint32_t c;
-  if (threadIdx.x == 0) c = 0;
-  __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * FX_CHUNK;
-  uint32_t mine = 0;
-  for (int t = 0; t < FX_IPT; ++t) {
-    const int64_t i = base + (int64_t)threadIdx.x * FX_IPT + t;
-    if (i >= N) break;
-    bool cand = false;
-    for (int v = 0; v < nv; ++v) cand |= uv[(size_t)i * nv + v] > 0.0;
-    mine += cand;
-  }
-  atomicAdd(&c, mine);
-  __syncthreads();
-  if (threadIdx.x == 0) bcnt[blockIdx.x] = c;
-}
+struct FixState {
+  int bstar;          // bin in which the last violated knapsack is covered (-1: none violated)
+  uint32_t nbefore;   // candidates in the bins before it
+  uint32_t nstar;     // candidates in it
+  uint32_t tstar;     // users of its sorted list that are reset
+};
+
+struct FixArgs {
+  ProbDev pr;
+  uint8_t *x;             // [N*M] selection at lambda; the reset clears rows
+  const double *lam;      // [K]
+  const int *kv;          // [K] slot of a violated knapsack, or -1
+  const int *vk;          // [nv] knapsack of each slot
+  const double *Bv;       // [nv] their budgets
+  int nv, nb;
+  const uint64_t *split;  // [nb - 1] ascending splitter keys
+  uint8_t *bin;           // [N] bin of every user (FX_NONE: not a candidate)
+  XSum *hsum;             // [nb][nv] exact consumption per bin
+  uint32_t *hcnt;         // [nb] candidates per bin
+  FixState *fs;
+  XSum *cthr;             // [nv] consumption of the bins before the one covering the slot
+  int *vb;                // [nv] bin covering the slot (-1: covered with no reset)
+  XSum *rem;              // [K + 1] removed consumption and profit
+};
 
 // exclusive scan of n counts in one block (n up to a few million; sequential
 // chunks per thread, then a block scan of the chunk totals)
@@ -1497,42 +1516,6 @@ __global__ void __launch_bounds__(1024) k_scan_u32(const uint32_t *in, uint32_t 
   __syncthreads();
   uint64_t run = part[t];
   for (int64_t i = b0; i < b1; ++i) { const uint32_t v = in[i]; out[i] = (uint32_t)run; run += v; }
-}
-
-// stable compaction of the candidates in user order
-__global__ void __launch_bounds__(FX_NT) k_fix_compact(const double *uv, int nv, const double *G,
-                                                       int64_t N, const uint32_t *boff,
-                                                       uint64_t *ckey, uint32_t *cidx) {
-  __shared__ uint32_t tcnt[FX_NT];
-  const int64_t base = (int64_t)blockIdx.x * FX_CHUNK;
-  uint32_t mine = 0;
-  for (int t = 0; t < FX_IPT; ++t) {
-    const int64_t i = base + (int64_t)threadIdx.x * FX_IPT + t;
-    if (i >= N) break;
-    bool cand = false;
-    for (int v = 0; v < nv; ++v) cand |= uv[(size_t)i * nv + v] > 0.0;
-    mine += cand;
-  }
-  tcnt[threadIdx.x] = mine;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t run = 0;
-    for (int t = 0; t < FX_NT; ++t) { const uint32_t v = tcnt[t]; tcnt[t] = run; run += v; }
-  }
-  __syncthreads();
-  uint32_t pos = boff[blockIdx.x] + tcnt[threadIdx.x];
-  for (int t = 0; t < FX_IPT; ++t) {
-    const int64_t i = base + (int64_t)threadIdx.x * FX_IPT + t;
-    if (i >= N) break;
-    bool cand = false;
-    for (int v = 0; v < nv; ++v) cand |= uv[(size_t)i * nv + v] > 0.0;
-    if (cand) {
-      // G_i >= 0 (a sum of positive scores), so its bits order like the values
-      ckey[pos] = dkey(G[i] + 0.0);
-      cidx[pos] = (uint32_t)i;
-      ++pos;
-    }
-  }
 }
 
 // one 4-bit digit of a stable LSD radix sort: per-block digit counts
@@ -1586,185 +1569,526 @@ __global__ void __launch_bounds__(FX_NT) k_rs_scatter(const uint64_t *key, const
   }
 }
 
-// per (block, violated knapsack): sum of the consumptions of the block's
-// sorted candidates
-__global__ void __launch_bounds__(FX_NT) k_fix_bsum(const uint32_t *sidx, uint32_t n, const double *uv,
-                                                    int nv, double *bsum, uint32_t nblk) {
-  __shared__ double red[FX_NT];
-  for (int v = 0; v < nv; ++v) {
-    double s = 0.0;
-    for (int q = 0; q < FX_IPT; ++q) {
-      const uint32_t i = blockIdx.x * FX_CHUNK + threadIdx.x * FX_IPT + q;
-      if (i >= n) break;
-      s = s + uv[(size_t)sidx[i] * nv + v];
-    }
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = FX_NT / 2; w > 0; w >>= 1) {
-      if ((int)threadIdx.x < w) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + w];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) bsum[(size_t)v * nblk + blockIdx.x] = red[0];
-    __syncthreads();
+// the cost entries (k, b) of item row r in storage order
+template <class F>
+__device__ __forceinline__ void fx_row(const ProbDev &pr, int64_t r, F f) {
+  if (pr.fmt == 0) {   // dense rows
+    const float *bb = pr.b + r * pr.K;
+    for (int k = 0; k < pr.K; ++k) f(k, bb[k]);
+  } else {
+    const int64_t e1 = pr.rowptr[r + 1];
+    for (int64_t e = pr.rowptr[r]; e < e1; ++e) f((int)pr.col[e], pr.val[e]);
   }
 }
 
-// one block per violated knapsack: the shortest prefix of the sorted
-// candidates whose consumption covers the excess R_k - B_k
-__global__ void __launch_bounds__(256) k_fix_prefix(const uint32_t *sidx, uint32_t n, const double *uv,
-                                                    int nv, const double *bsum, uint32_t nblk,
-                                                    const double *RB, unsigned int *tstar) {
-  // RB[2v], RB[2v+1]: consumption and budget of the v-th violated knapsack;
-  // covered when R - cumulative <= B (the reset loop's own test)
-  const int v = blockIdx.x;
-  const double Rk = RB[2 * v], Bk = RB[2 * v + 1];
-  __shared__ uint32_t blk;
-  __shared__ double before;
-  if (threadIdx.x == 0) {
-    double run = 0.0;
-    uint32_t b = nblk;
-    for (uint32_t q = 0; q < nblk; ++q) {
-      const double nx = run + bsum[(size_t)v * nblk + q];
-      if (Rk - nx <= Bk) { b = q; break; }
-      run = nx;
-    }
-    blk = b;
-    before = run;
+// G_i, the sum of p~ over the selected items in ascending index order (p~ as
+// the sweep forms it: the stored costs in order, a product then a
+// subtraction), and whether user i consumes a violated knapsack
+__device__ __forceinline__ bool fx_user(const FixArgs &f, int64_t i, double &G) {
+  const int M = f.pr.M, K = f.pr.K;
+  bool cand = false;
+  double g = 0.0;
+  for (int j = 0; j < M; ++j) {
+    const int64_t r = i * M + j;
+    if (!f.x[r]) continue;
+    double acc = (double)f.pr.p[r];
+    fx_row(f.pr, r, [&](int k, float c) {
+      if ((unsigned)k >= (unsigned)K) return;
+      const double prod = f.lam[k] * (double)c;
+      acc = acc - prod;
+      cand = cand || (c > 0.0f && f.kv[k] >= 0);
+    });
+    g = g + acc;
   }
+  G = g;
+  return cand;
+}
+
+// exact consumption of knapsack k by user i's selection
+__device__ __forceinline__ XSum fx_use(const FixArgs &f, int64_t i, int k) {
+  XSum s = xs_zero();
+  for (int j = 0; j < f.pr.M; ++j) {
+    const int64_t r = i * f.pr.M + j;
+    if (!f.x[r]) continue;
+    fx_row(f.pr, r, [&](int kk, float c) {
+      if (kk == k) s = xs_plus(s, xs_of((double)c));
+    });
+  }
+  return s;
+}
+
+// number of splitters below key
+__device__ __forceinline__ int fx_bin(const uint64_t *split, int nb, uint64_t key) {
+  int lo = 0, hi = nb - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (split[mid] < key) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ XSum xs_minus(const XSum &a, const XSum &b) {
+  XSum r;
+  r.hi = a.hi - b.hi;
+  r.lo = a.lo - b.lo;
+  return r;
+}
+
+// sampled users i = s * stride that are candidates: their keys
+__global__ void __launch_bounds__(FX_NT) k_fix_sample(FixArgs f, int64_t stride, uint32_t ns,
+                                                      uint64_t *keys, uint32_t *idx, uint32_t *count) {
+  const uint32_t s = blockIdx.x * FX_NT + threadIdx.x;
+  if (s >= ns) return;
+  double G;
+  if (!fx_user(f, (int64_t)s * stride, G)) return;
+  const uint32_t slot = atomicAdd(count, 1u);
+  keys[slot] = dkey(G + 0.0);
+  idx[slot] = slot;
+}
+
+// splitters at the sample's quantiles q / nb (all keys in bin 0 when the
+// sample holds no candidate)
+__global__ void k_fix_split(const uint64_t *sorted, const uint32_t *count, int nb, uint64_t *split) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nb - 1) return;
+  const uint32_t n = *count;
+  split[q] = n ? sorted[((uint64_t)(q + 1) * n) / nb] : ~0ull;
+}
+
+// every user: bin byte, per-bin candidate counts and exact consumption of the
+// violated knapsacks (block accumulators in LDS when they fit, added to the
+// global ones at the end; the grid strides over 4096-user chunks)
+__global__ void __launch_bounds__(FX_NT) k_fix_bins(FixArgs f, int lds) {
+  extern __shared__ __align__(16) unsigned char fsm[];
+  const int nb = f.nb, nv = f.nv, K = f.pr.K, M = f.pr.M;
+  XSum *hs = lds ? (XSum *)fsm : f.hsum;
+  uint32_t *hc = lds ? (uint32_t *)(fsm + (size_t)nb * nv * sizeof(XSum)) : f.hcnt;
+  uint64_t *sp = (uint64_t *)(fsm + (lds ? (size_t)nb * nv * sizeof(XSum) + (size_t)nb * 4 + 8 : 0));
+  if (lds) {
+    for (int t = threadIdx.x; t < nb * nv; t += FX_NT) hs[t] = xs_zero();
+    for (int t = threadIdx.x; t < nb; t += FX_NT) hc[t] = 0u;
+  }
+  for (int t = threadIdx.x; t < nb - 1; t += FX_NT) sp[t] = f.split[t];
   __syncthreads();
-  if (blk >= nblk) {  // cannot happen: every violated knapsack is covered by its consumers
-    if (threadIdx.x == 0) atomicMax(tstar, n);
-    return;
-  }
-  if (threadIdx.x == 0) {
-    double run = before;
-    uint32_t t = blk * FX_CHUNK;
-    const uint32_t end = (blk + 1) * FX_CHUNK < n ? (blk + 1) * FX_CHUNK : n;
-    for (; t < end; ++t) {
-      run = run + uv[(size_t)sidx[t] * nv + v];
-      if (Rk - run <= Bk) break;
-    }
-    atomicMax(tstar, (t < end ? t + 1 : end));
-  }
-}
-
-// reset the first tstar sorted candidates; each thread accumulates its users'
-// removed profit and consumption in its own LDS row (fixed user order), rows
-// are added in thread order into a per-block slot
-#define FX_RT 64
-__global__ void __launch_bounds__(FX_RT) k_fix_reset(const uint32_t *sidx, const unsigned int *tstar,
-                                                     ProbDev pr, uint8_t *x, double *partials) {
-  extern __shared__ double rows[];   // [FX_RT][K + 1]
-  const int K = pr.K, M = pr.M, W = K + 1;
-  double *mine = rows + (size_t)threadIdx.x * W;
-  for (int c = 0; c < W; ++c) mine[c] = 0.0;
-  const uint32_t ts = *tstar;
-  for (uint32_t t = blockIdx.x * FX_RT + threadIdx.x; t < ts; t += gridDim.x * FX_RT) {
-    const int64_t i = sidx[t];
-    for (int j = 0; j < M; ++j) {
-      const int64_t r = i * M + j;
-      if (!x[r]) continue;
-      x[r] = 0;
-      mine[K] = mine[K] + (double)pr.p[r];
-      if (pr.fmt == 0) {
-        for (int k = 0; k < K; ++k) mine[k] = mine[k] + (double)pr.b[r * K + k];
-      } else {
-        for (int64_t e = pr.rowptr[r]; e < pr.rowptr[r + 1]; ++e) {
-          const int k = pr.col[e];
-          if ((unsigned)k < (unsigned)K) mine[k] = mine[k] + (double)pr.val[e];
+  const int64_t N = f.pr.N;
+  const int64_t nch = (N + FX_CHUNK - 1) / FX_CHUNK;
+  for (int64_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+    for (int q = 0; q < FX_IPT; ++q) {
+      const int64_t i = ch * FX_CHUNK + (int64_t)q * FX_NT + threadIdx.x;
+      if (i >= N) break;
+      double G;
+      uint8_t bb = (uint8_t)FX_NONE;
+      if (fx_user(f, i, G)) {
+        const int b = fx_bin(sp, nb, dkey(G + 0.0));
+        bb = (uint8_t)b;
+        atomicAdd(&hc[b], 1u);
+        XSum *row = hs + (size_t)b * nv;
+        for (int j = 0; j < M; ++j) {
+          const int64_t r = i * M + j;
+          if (!f.x[r]) continue;
+          fx_row(f.pr, r, [&](int k, float c) {
+            if ((unsigned)k >= (unsigned)K || !(c > 0.0f)) return;
+            const int v = f.kv[k];
+            if (v >= 0) xs_atomic_add(&row[v], (double)c);
+          });
         }
       }
+      f.bin[i] = bb;
     }
   }
+  if (!lds) return;
   __syncthreads();
-  for (int c = threadIdx.x; c < W; c += FX_RT) {
-    double s = 0.0;
-    for (int q = 0; q < FX_RT; ++q) s = s + rows[(size_t)q * W + c];
-    partials[(size_t)blockIdx.x * W + c] = s;
+  for (int t = threadIdx.x; t < nb * nv; t += FX_NT)
+    if (xs_nonzero(hs[t])) xs_atomic_add_sum(&f.hsum[t], hs[t]);
+  for (int t = threadIdx.x; t < nb; t += FX_NT)
+    if (hc[t]) atomicAdd(&f.hcnt[t], hc[t]);
+}
+
+// per violated knapsack: the first bin whose prefix covers it, exactly
+// (covered: total - removed <= B); the threshold bin is the largest
+__global__ void __launch_bounds__(256) k_fix_locate(FixArgs f) {
+  __shared__ int bst;
+  if (threadIdx.x == 0) bst = -1;
+  __syncthreads();
+  for (int v = threadIdx.x; v < f.nv; v += 256) {
+    XSum T = xs_zero();
+    for (int b = 0; b < f.nb; ++b) T = xs_plus(T, f.hsum[(size_t)b * f.nv + v]);
+    const double Bk = f.Bv[v];
+    int vb = -1;
+    XSum S = xs_zero();
+    if (xs_gt(T, Bk)) {
+      vb = f.nb - 1;
+      for (int b = 0; b < f.nb; ++b) {
+        const XSum S2 = xs_plus(S, f.hsum[(size_t)b * f.nv + v]);
+        if (!xs_gt(xs_minus(T, S2), Bk)) { vb = b; break; }
+        S = S2;
+      }
+    }
+    f.vb[v] = vb;
+    f.cthr[v] = S;
+    atomicMax(&bst, vb);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t before = 0;
+    for (int b = 0; b < bst; ++b) before += f.hcnt[b];
+    f.fs->bstar = bst;
+    f.fs->nbefore = before;
+    f.fs->nstar = bst >= 0 ? f.hcnt[bst] : 0u;
+    f.fs->tstar = 0u;
   }
 }
 
-__global__ void k_fix_final(const double *partials, int nblk, int K, const double *R, const double *P,
-                            double *R_out, double *P_out, const unsigned int *tstar, int64_t *n_reset) {
+// the bin bytes of FX_IPT consecutive users from user i0 on (fewer at the end)
+__device__ __forceinline__ void fx_bins16(const uint8_t *bin, int64_t i0, int64_t N, uint8_t out[FX_IPT]) {
+  if (i0 + FX_IPT <= N) {
+    const uint4 w = *(const uint4 *)(bin + i0);
+    const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+    for (int q = 0; q < FX_IPT; ++q) out[q] = (uint8_t)(ws[q >> 2] >> (8 * (q & 3)));
+  } else {
+    for (int q = 0; q < FX_IPT; ++q) out[q] = i0 + q < N ? bin[i0 + q] : (uint8_t)FX_NONE;
+  }
+}
+
+// users of the threshold bin per chunk
+__global__ void __launch_bounds__(FX_NT) k_fix_bcount(FixArgs f, uint32_t *bcnt) {
+  __shared__ uint32_t c;
+  if (threadIdx.x == 0) c = 0;
+  __syncthreads();
+  const int bst = f.fs->bstar;
+  uint8_t bb[FX_IPT];
+  fx_bins16(f.bin, (int64_t)blockIdx.x * FX_CHUNK + (int64_t)threadIdx.x * FX_IPT, f.pr.N, bb);
+  uint32_t mine = 0;
+  for (int q = 0; q < FX_IPT; ++q) mine += (int)bb[q] == bst;
+  atomicAdd(&c, mine);
+  __syncthreads();
+  if (threadIdx.x == 0) bcnt[blockIdx.x] = c;
+}
+
+// stable compaction of the threshold bin's users in user order, with keys
+__global__ void __launch_bounds__(FX_NT) k_fix_collect(FixArgs f, const uint32_t *boff, uint64_t *ckey,
+                                                       uint32_t *cidx) {
+  __shared__ uint32_t tcnt[FX_NT];
+  const int bst = f.fs->bstar;
+  const int64_t i0 = (int64_t)blockIdx.x * FX_CHUNK + (int64_t)threadIdx.x * FX_IPT;
+  uint8_t bb[FX_IPT];
+  fx_bins16(f.bin, i0, f.pr.N, bb);
+  uint32_t mine = 0;
+  for (int q = 0; q < FX_IPT; ++q) mine += (int)bb[q] == bst;
+  tcnt[threadIdx.x] = mine;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int t = 0; t < FX_NT; ++t) { const uint32_t v = tcnt[t]; tcnt[t] = run; run += v; }
+  }
+  __syncthreads();
+  uint32_t pos = boff[blockIdx.x] + tcnt[threadIdx.x];
+  for (int q = 0; q < FX_IPT; ++q) {
+    if ((int)bb[q] != bst) continue;
+    double G;
+    fx_user(f, i0 + q, G);
+    ckey[pos] = dkey(G + 0.0);
+    cidx[pos] = (uint32_t)(i0 + q);
+    ++pos;
+  }
+}
+
+// per chunk of the sorted threshold-bin list: exact consumption of every
+// slot covered inside that bin
+__global__ void __launch_bounds__(FX_NT) k_fix_chunk(FixArgs f, const uint32_t *sidx, XSum *csum, int lds) {
+  extern __shared__ __align__(16) unsigned char fsm[];
+  const int nv = f.nv, K = f.pr.K, M = f.pr.M;
+  XSum *cs = lds ? (XSum *)fsm : csum + (size_t)blockIdx.x * nv;
+  if (lds)
+    for (int t = threadIdx.x; t < nv; t += FX_NT) cs[t] = xs_zero();
+  __syncthreads();
+  const int bst = f.fs->bstar;
+  const uint32_t n = f.fs->nstar;
+  for (int q = 0; q < FX_IPT; ++q) {
+    const uint32_t e = blockIdx.x * FX_CHUNK + q * FX_NT + threadIdx.x;
+    if (e >= n) break;
+    const int64_t i = sidx[e];
+    for (int j = 0; j < M; ++j) {
+      const int64_t r = i * M + j;
+      if (!f.x[r]) continue;
+      fx_row(f.pr, r, [&](int k, float c) {
+        if ((unsigned)k >= (unsigned)K || !(c > 0.0f)) return;
+        const int v = f.kv[k];
+        if (v >= 0 && f.vb[v] == bst) xs_atomic_add(&cs[v], (double)c);
+      });
+    }
+  }
+  if (!lds) return;
+  __syncthreads();
+  for (int t = threadIdx.x; t < nv; t += FX_NT) csum[(size_t)blockIdx.x * nv + t] = cs[t];
+}
+
+// one block per slot covered in the threshold bin: the shortest prefix of the
+// sorted list that covers it; tstar is the largest over the slots
+__global__ void __launch_bounds__(FX_NT) k_fix_prefix(FixArgs f, const uint32_t *sidx, const XSum *csum,
+                                                      uint32_t nchunks) {
+  const int v = blockIdx.x;
+  const int bst = f.fs->bstar;
+  if (bst < 0 || f.vb[v] != bst) return;
+  const uint32_t n = f.fs->nstar;
+  const int k = f.vk[v];
+  const double Bk = f.Bv[v];
+  __shared__ uint32_t chunk, first;
+  __shared__ XSum tsum[FX_NT];
+  __shared__ XSum Tsh;
+  if (threadIdx.x == 0) {
+    XSum T = xs_zero();
+    for (int b = 0; b < f.nb; ++b) T = xs_plus(T, f.hsum[(size_t)b * f.nv + v]);
+    XSum S = f.cthr[v];
+    uint32_t c = nchunks - 1;
+    for (uint32_t q = 0; q < nchunks; ++q) {
+      const XSum S2 = xs_plus(S, csum[(size_t)q * f.nv + v]);
+      if (!xs_gt(xs_minus(T, S2), Bk)) { c = q; break; }
+      S = S2;
+    }
+    chunk = c;
+    first = 0xFFFFFFFFu;
+    Tsh = T;
+    tsum[0] = S;   // consumption before the chunk (the scan below adds the rest)
+  }
+  __syncthreads();
+  const XSum before = tsum[0];
+  __syncthreads();
+  const uint32_t e0 = chunk * FX_CHUNK + threadIdx.x * FX_IPT;
+  XSum mine = xs_zero();
+  for (int q = 0; q < FX_IPT; ++q)
+    if (e0 + q < n) mine = xs_plus(mine, fx_use(f, sidx[e0 + q], k));
+  tsum[threadIdx.x] = mine;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    XSum run = before;
+    for (int t = 0; t < FX_NT; ++t) { const XSum w = tsum[t]; tsum[t] = run; run = xs_plus(run, w); }
+  }
+  __syncthreads();
+  XSum S = tsum[threadIdx.x];
+  for (int q = 0; q < FX_IPT; ++q) {
+    const uint32_t e = e0 + q;
+    if (e >= n) break;
+    S = xs_plus(S, fx_use(f, sidx[e], k));
+    if (!xs_gt(xs_minus(Tsh, S), Bk)) { atomicMin(&first, e); break; }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) atomicMax(&f.fs->tstar, first != 0xFFFFFFFFu ? first + 1 : n);
+}
+
+// clear user i's selection; its profit and consumption go to rem
+__device__ __forceinline__ void fx_remove(const FixArgs &f, int64_t i, XSum *rem) {
+  const int M = f.pr.M, K = f.pr.K;
+  for (int j = 0; j < M; ++j) {
+    const int64_t r = i * M + j;
+    if (!f.x[r]) continue;
+    f.x[r] = 0;
+    xs_atomic_add(&rem[K], (double)f.pr.p[r]);
+    fx_row(f.pr, r, [&](int k, float c) {
+      if ((unsigned)k < (unsigned)K && c != 0.0f) xs_atomic_add(&rem[k], (double)c);
+    });
+  }
+}
+
+// reset the candidates of the bins before the threshold bin (list == null)
+// or the first tstar users of the sorted list
+__global__ void __launch_bounds__(FX_NT) k_fix_reset(FixArgs f, const uint32_t *sidx, int lds) {
+  extern __shared__ __align__(16) unsigned char fsm[];
+  const int K = f.pr.K;
+  XSum *rem = lds ? (XSum *)fsm : f.rem;
+  if (lds)
+    for (int t = threadIdx.x; t <= K; t += FX_NT) rem[t] = xs_zero();
+  __syncthreads();
+  const int bst = f.fs->bstar;
+  if (!sidx) {
+    const int64_t N = f.pr.N;
+    for (int64_t i = (int64_t)blockIdx.x * FX_NT + threadIdx.x; i < N; i += (int64_t)gridDim.x * FX_NT) {
+      const int b = f.bin[i];
+      if (b != (int)FX_NONE && b < bst) fx_remove(f, i, rem);
+    }
+  } else {
+    const uint32_t ts = f.fs->tstar;
+    for (uint32_t e = blockIdx.x * FX_NT + threadIdx.x; e < ts; e += gridDim.x * FX_NT) fx_remove(f, sidx[e], rem);
+  }
+  if (!lds) return;
+  __syncthreads();
+  for (int t = threadIdx.x; t <= K; t += FX_NT)
+    if (xs_nonzero(rem[t])) xs_atomic_add_sum(&f.rem[t], rem[t]);
+}
+
+__global__ void k_fix_final(FixArgs f, const double *R, const double *P, double *R_out, double *P_out,
+                            int64_t *n_reset) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int K = f.pr.K;
   if (c > K) return;
-  double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s = s + partials[(size_t)b * (K + 1) + c];
+  const double s = xs_to_double(f.rem[c]);
   if (c < K) {
     R_out[c] = R[c] - s;
   } else {
     *P_out = *P - s;
-    *n_reset = (int64_t)*tstar;
+    *n_reset = f.fs->bstar < 0 ? 0 : (int64_t)f.fs->nbefore + (int64_t)f.fs->tstar;
   }
 }
 
-hipError_t kp_launch_fixup_pipeline(const double *uv, int nv, const double *G, int64_t N,
-                                    const double *RB, ProbDev pr, uint8_t *x, const double *R,
-                                    const double *P, double *R_out, double *P_out, int64_t *n_reset,
-                                    void *scratch, hipStream_t stream, uint32_t *ncand_host_pinned) {
-  // scratch layout (all sized by the caller): bcnt/boff [nb], ckey/tkey [N], cidx/tidx [N],
-  // hist/hoff [16*nbs], bsum [nv*nbs], partials [nblk_reset*(K+1)], tstar, total
-  const uint32_t nb = (uint32_t)((N + FX_CHUNK - 1) / FX_CHUNK);
-  char *w = (char *)scratch;
-  auto take = [&](size_t bytes) { char *p = w; w += (bytes + 255) & ~(size_t)255; return (void *)p; };
-  uint32_t *bcnt = (uint32_t *)take((size_t)nb * 4);
-  uint32_t *boff = (uint32_t *)take((size_t)nb * 4);
-  uint64_t *ckey = (uint64_t *)take((size_t)N * 8);
-  uint64_t *tkey = (uint64_t *)take((size_t)N * 8);
-  uint32_t *cidx = (uint32_t *)take((size_t)N * 4);
-  uint32_t *tidx = (uint32_t *)take((size_t)N * 4);
-  uint32_t *hist = (uint32_t *)take((size_t)16 * nb * 4);
-  uint32_t *hoff = (uint32_t *)take((size_t)16 * nb * 4);
-  double *bsum = (double *)take((size_t)(nv > 0 ? nv : 1) * nb * 8);
-  const int nblk_reset = 1024;
-  double *partials = (double *)take((size_t)nblk_reset * (pr.K + 1) * 8);
-  unsigned int *tstar = (unsigned int *)take(8);
-  uint32_t *total = (uint32_t *)take(8);
-  hipLaunchKernelGGL(k_fix_count, dim3(nb), dim3(FX_NT), 0, stream, uv, nv, N, bcnt);
-  hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, stream, bcnt, boff, (int64_t)nb, total);
-  hipLaunchKernelGGL(k_fix_compact, dim3(nb), dim3(FX_NT), 0, stream, uv, nv, G, N, boff, ckey, cidx);
-  hipError_t e = hipMemcpyAsync(ncand_host_pinned, total, 4, hipMemcpyDeviceToHost, stream);
-  if (e != hipSuccess) return e;
-  e = hipStreamSynchronize(stream);
-  if (e != hipSuccess) return e;
-  const uint32_t n = *ncand_host_pinned;
-  uint64_t *k0 = ckey, *k1 = tkey;
-  uint32_t *v0 = cidx, *v1 = tidx;
+// stable LSD radix sort of n (key, value) pairs, 4 bits per pass; the result
+// ends in (k0, v0) (an even number of passes)
+static hipError_t fx_sort(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, uint32_t n,
+                          uint32_t *hist, uint32_t *hoff, hipStream_t stream) {
+  if (n == 0) return hipSuccess;
   const uint32_t nbs = (n + FX_CHUNK - 1) / FX_CHUNK;
-  if (n > 0) {
-    for (int shift = 0; shift < 64; shift += 4) {
-      hipLaunchKernelGGL(k_rs_hist, dim3(nbs), dim3(FX_NT), 0, stream, k0, n, shift, hist, nbs);
-      hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, stream, hist, hoff, (int64_t)16 * nbs,
-                         (uint32_t *)nullptr);
-      hipLaunchKernelGGL(k_rs_scatter, dim3(nbs), dim3(FX_NT), 0, stream, k0, v0, n, shift, hoff, nbs,
-                         k1, v1);
-      uint64_t *tk = k0; k0 = k1; k1 = tk;
-      uint32_t *tv = v0; v0 = v1; v1 = tv;
-    }
+  for (int shift = 0; shift < 64; shift += 4) {
+    hipLaunchKernelGGL(k_rs_hist, dim3(nbs), dim3(FX_NT), 0, stream, k0, n, shift, hist, nbs);
+    hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, stream, hist, hoff, (int64_t)16 * nbs,
+                       (uint32_t *)nullptr);
+    hipLaunchKernelGGL(k_rs_scatter, dim3(nbs), dim3(FX_NT), 0, stream, k0, v0, n, shift, hoff, nbs, k1, v1);
+    uint64_t *tk = k0; k0 = k1; k1 = tk;
+    uint32_t *tv = v0; v0 = v1; v1 = tv;
   }
-  e = hipMemsetAsync(tstar, 0, 4, stream);
-  if (e != hipSuccess) return e;
-  if (n > 0 && nv > 0) {
-    hipLaunchKernelGGL(k_fix_bsum, dim3(nbs), dim3(FX_NT), 0, stream, v0, n, uv, nv, bsum, nbs);
-    hipLaunchKernelGGL(k_fix_prefix, dim3(nv), dim3(256), 0, stream, v0, n, uv, nv, bsum, nbs, RB,
-                       tstar);
-  }
-  const size_t rl = (size_t)FX_RT * (pr.K + 1) * 8;
-  if (rl > 64 * 1024) {
-    e = hipFuncSetAttribute((const void *)k_fix_reset, hipFuncAttributeMaxDynamicSharedMemorySize, (int)rl);
-    if (e != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL(k_fix_reset, dim3(nblk_reset), dim3(FX_RT), rl, stream, v0, tstar, pr, x, partials);
-  hipLaunchKernelGGL(k_fix_final, dim3((pr.K + 1 + 255) / 256), dim3(256), 0, stream, partials,
-                     nblk_reset, pr.K, R, P, R_out, P_out, tstar, n_reset);
   return hipGetLastError();
 }
 
-size_t kp_fixup_scratch_bytes(int64_t N, int nv, int K) {
-  const size_t nb = (size_t)((N + FX_CHUNK - 1) / FX_CHUNK) + 1;
-  auto r = [](size_t b) { return (b + 255) & ~(size_t)255; };
-  return r(nb * 4) * 2 + r((size_t)N * 8) * 2 + r((size_t)N * 4) * 2 + r(16 * nb * 4) * 2 +
-         r((size_t)(nv > 0 ? nv : 1) * nb * 8) + r((size_t)1024 * (K + 1) * 8) + 512;
+static int fx_bins_for(int nv) {
+  int nb = 128;
+  while (nb > 1 && (size_t)nb * nv * sizeof(XSum) > 40 * 1024) nb >>= 1;
+  return nb;
+}
+
+namespace {
+struct FxLayout {
+  size_t bin, skey, tkey, sidx, tidx, scount, split, hsum, hcnt, fs, cthr, vb, rem, ckey, ckey2, cidx, cidx2,
+      hist, hoff, bcnt, boff, csum, total;
+};
+FxLayout fx_layout(int64_t N, int nv, int K) {
+  FxLayout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { const size_t o = off; off += (bytes + 255) & ~(size_t)255; return o; };
+  // the bin arrays at their largest (at most 128 bins, at most 40 KB of
+  // sums or one row per slot), so that a layout never outgrows the one for
+  // more slots
+  const uint32_t ns = (uint32_t)(N < 65536 ? N : 65536);
+  const size_t nch = (size_t)((N + FX_CHUNK - 1) / FX_CHUNK) + 1;
+  L.bin = take((size_t)N + 16);
+  L.skey = take((size_t)ns * 8 + 8);
+  L.tkey = take((size_t)ns * 8 + 8);
+  L.sidx = take((size_t)ns * 4 + 4);
+  L.tidx = take((size_t)ns * 4 + 4);
+  L.scount = take(8);
+  L.split = take(128 * 8);
+  L.hsum = take(std::max<size_t>(40 * 1024, (size_t)nv * sizeof(XSum)));
+  L.hcnt = take(128 * 4);
+  L.fs = take(sizeof(FixState));
+  L.cthr = take((size_t)nv * sizeof(XSum));
+  L.vb = take((size_t)nv * 4);
+  L.rem = take((size_t)(K + 1) * sizeof(XSum));
+  L.ckey = take((size_t)N * 8 + 8);
+  L.ckey2 = take((size_t)N * 8 + 8);
+  L.cidx = take((size_t)N * 4 + 4);
+  L.cidx2 = take((size_t)N * 4 + 4);
+  L.hist = take(16 * nch * 4);
+  L.hoff = take(16 * nch * 4);
+  L.bcnt = take(nch * 4);
+  L.boff = take(nch * 4);
+  L.csum = take(nch * (size_t)nv * sizeof(XSum));
+  L.total = off;
+  return L;
+}
+}  // namespace
+
+size_t kp_fixup_scratch_bytes(int64_t N, int nv, int K) { return fx_layout(N, nv, K).total; }
+
+// kv / vk / Bv: device arrays of the violated slots; pinned: 32 bytes of
+// pinned host memory; persist: blocks of the user passes.  Synchronizes the
+// stream twice (the sample's candidate count, then the threshold bin).
+hipError_t kp_launch_fixup_pipeline(ProbDev pr, uint8_t *x, const double *lam, const int *kv, const int *vk,
+                                    const double *Bv, int nv, const double *R, const double *P,
+                                    double *R_out, double *P_out, int64_t *n_reset, void *scratch,
+                                    hipStream_t stream, uint32_t *pinned, int persist) {
+  const int64_t N = pr.N;
+  const int K = pr.K;
+  const FxLayout L = fx_layout(N, nv, K);
+  char *w = (char *)scratch;
+  FixArgs f;
+  f.pr = pr;
+  f.x = x;
+  f.lam = lam;
+  f.kv = kv;
+  f.vk = vk;
+  f.Bv = Bv;
+  f.nv = nv;
+  f.nb = fx_bins_for(nv);
+  f.split = (const uint64_t *)(w + L.split);
+  f.bin = (uint8_t *)(w + L.bin);
+  f.hsum = (XSum *)(w + L.hsum);
+  f.hcnt = (uint32_t *)(w + L.hcnt);
+  f.fs = (FixState *)(w + L.fs);
+  f.cthr = (XSum *)(w + L.cthr);
+  f.vb = (int *)(w + L.vb);
+  f.rem = (XSum *)(w + L.rem);
+  hipError_t e;
+  if ((e = hipMemsetAsync(f.hsum, 0, (size_t)f.nb * nv * sizeof(XSum), stream)) != hipSuccess) return e;
+  if ((e = hipMemsetAsync(f.hcnt, 0, (size_t)f.nb * 4, stream)) != hipSuccess) return e;
+  if ((e = hipMemsetAsync(f.rem, 0, (size_t)(K + 1) * sizeof(XSum), stream)) != hipSuccess) return e;
+  uint32_t *scount = (uint32_t *)(w + L.scount);
+  if ((e = hipMemsetAsync(scount, 0, 4, stream)) != hipSuccess) return e;
+  // splitters from a strided sample
+  const uint32_t ns = (uint32_t)(N < 65536 ? N : 65536);
+  const int64_t stride = ns ? N / ns : 1;
+  uint64_t *skey = (uint64_t *)(w + L.skey), *tkey = (uint64_t *)(w + L.tkey);
+  uint32_t *sidx = (uint32_t *)(w + L.sidx), *tidx = (uint32_t *)(w + L.tidx);
+  uint32_t *hist = (uint32_t *)(w + L.hist), *hoff = (uint32_t *)(w + L.hoff);
+  if (ns)
+    hipLaunchKernelGGL(k_fix_sample, dim3((ns + FX_NT - 1) / FX_NT), dim3(FX_NT), 0, stream, f, stride, ns,
+                       skey, sidx, scount);
+  if ((e = hipMemcpyAsync(pinned, scount, 4, hipMemcpyDeviceToHost, stream)) != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(stream)) != hipSuccess) return e;
+  const uint32_t nsc = pinned[0];
+  if ((e = fx_sort(skey, sidx, tkey, tidx, nsc, hist, hoff, stream)) != hipSuccess) return e;
+  if (f.nb > 1)
+    hipLaunchKernelGGL(k_fix_split, dim3(1), dim3(128), 0, stream, skey, scount, f.nb, (uint64_t *)f.split);
+  // bins and their exact sums
+  const size_t lb = (size_t)f.nb * nv * sizeof(XSum) + (size_t)f.nb * 4 + 8 + (size_t)f.nb * 8;
+  const int bins_lds = lb <= FX_LDS_MAX;
+  const size_t lb_used = bins_lds ? lb : (size_t)f.nb * 8;
+  if (lb_used > 64 * 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_fix_bins, dim3(persist), dim3(FX_NT), lb_used, stream, f, bins_lds);
+  hipLaunchKernelGGL(k_fix_locate, dim3(1), dim3(256), 0, stream, f);
+  if ((e = hipMemcpyAsync(pinned, f.fs, sizeof(FixState), hipMemcpyDeviceToHost, stream)) != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(stream)) != hipSuccess) return e;
+  FixState hs;
+  memcpy(&hs, pinned, sizeof hs);
+  const int rem_lds = (size_t)(K + 1) * sizeof(XSum) <= FX_LDS_MAX;
+  const size_t lr = rem_lds ? (size_t)(K + 1) * sizeof(XSum) : 0;
+  if (hs.bstar >= 0) {
+    const uint32_t nch = (uint32_t)((N + FX_CHUNK - 1) / FX_CHUNK);
+    uint32_t *bcnt = (uint32_t *)(w + L.bcnt), *boff = (uint32_t *)(w + L.boff);
+    uint64_t *ckey = (uint64_t *)(w + L.ckey), *ckey2 = (uint64_t *)(w + L.ckey2);
+    uint32_t *cidx = (uint32_t *)(w + L.cidx), *cidx2 = (uint32_t *)(w + L.cidx2);
+    XSum *csum = (XSum *)(w + L.csum);
+    hipLaunchKernelGGL(k_fix_bcount, dim3(nch), dim3(FX_NT), 0, stream, f, bcnt);
+    hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, stream, bcnt, boff, (int64_t)nch, (uint32_t *)nullptr);
+    hipLaunchKernelGGL(k_fix_collect, dim3(nch), dim3(FX_NT), 0, stream, f, boff, ckey, cidx);
+    if ((e = fx_sort(ckey, cidx, ckey2, cidx2, hs.nstar, hist, hoff, stream)) != hipSuccess) return e;
+    const uint32_t nchs = (hs.nstar + FX_CHUNK - 1) / FX_CHUNK;
+    if (nchs) {
+      const int c_lds = (size_t)nv * sizeof(XSum) <= FX_LDS_MAX;
+      if (!c_lds && (e = hipMemsetAsync(csum, 0, (size_t)nchs * nv * sizeof(XSum), stream)) != hipSuccess)
+        return e;
+      hipLaunchKernelGGL(k_fix_chunk, dim3(nchs), dim3(FX_NT), c_lds ? (size_t)nv * sizeof(XSum) : 0, stream,
+                         f, cidx, csum, c_lds);
+      hipLaunchKernelGGL(k_fix_prefix, dim3(nv), dim3(FX_NT), 0, stream, f, cidx, csum, nchs);
+    }
+    hipLaunchKernelGGL(k_fix_reset, dim3(persist), dim3(FX_NT), lr, stream, f, (const uint32_t *)nullptr,
+                       rem_lds);
+    if (hs.nstar) {
+      const uint32_t g = (hs.nstar + FX_NT - 1) / FX_NT;
+      hipLaunchKernelGGL(k_fix_reset, dim3(g < (uint32_t)persist ? g : (uint32_t)persist), dim3(FX_NT), lr,
+                         stream, f, (const uint32_t *)cidx, rem_lds);
+    }
+  }
+  hipLaunchKernelGGL(k_fix_final, dim3((K + 1 + 255) / 256), dim3(256), 0, stream, f, R, P, R_out, P_out,
+                     n_reset);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

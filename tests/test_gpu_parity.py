@@ -9,7 +9,7 @@ import pytest
 
 import kpgen
 import oracle
-from util import random_instance, random_laminar
+from util import make, random_instance, random_laminar
 
 gpu = pytest.mark.gpu
 REL = 1e-9
@@ -365,11 +365,36 @@ def test_validate_inputs_flags_bad_values():
     assert e.value.status == -4
 
 
+def _off_grid_fix():
+    rng = np.random.default_rng(11)
+    N, M, K = 20000, 6, 3
+    p = rng.random((N, M)).astype(np.float32)
+    b = (rng.random((N, M, K)) * 1.37).astype(np.float32)
+    return make(p, b, 0.05 * b.astype(np.float64).sum(axis=(0, 1)), kpgen.tree_topq(M, 2))
+
+
+def _identical_users_fix():
+    # every user the same: one G value, so one bin and ties decided by index
+    rng = np.random.default_rng(5)
+    M, K = 8, 3
+    p = rng.integers(1, 64, size=(1, M)) / 64.0
+    b = rng.integers(1, 64, size=(1, M, K)) / 64.0
+    N = 30000
+    p = np.repeat(p, N, axis=0)
+    b = np.repeat(b, N, axis=0)
+    return make(p, b, 0.1 * b.sum(axis=(0, 1)), kpgen.tree_topq(M, 3))
+
+
 FIX_CASES = [
     ("c1-underpriced", lambda: kpgen.config_instance(1, N=6000), [1.2, 1.25]),
     ("c3-hier-csr", lambda: kpgen.config_instance(3, N=4000), None),
     ("dense-ties", lambda: random_instance(np.random.default_rng(3), 700, 6, 4, Q=2, grid=6), None),
     ("feasible-already", lambda: kpgen.config_instance(1, N=3000), [3.0, 3.0]),
+    # many bins, a threshold bin of several 4096-user chunks, a strided sample
+    ("c3-2M", lambda: kpgen.config_instance(3, N=2_000_000), None),
+    ("c3-2M-near", lambda: kpgen.config_instance(3, N=2_000_000), [3.1] * 20),
+    ("off-grid", _off_grid_fix, [0.1, 0.1, 0.1]),
+    ("identical-users", _identical_users_fix, [0.05, 0.05, 0.05]),
 ]
 
 
@@ -389,9 +414,13 @@ def test_primal_fixup_parity(name, mk, lam):
     ref = oracle.fixup(inst, lam, mode=0)
     assert fx["n_reset"].item() == ref["n_reset"]
     assert np.array_equal(fx["x"].cpu().numpy(), ref["x"])
-    assert np.array_equal(fx["R"].cpu().numpy(), ref["R"])
+    if name == "off-grid":
+        # the consumption left is rounded once here and re-summed there
+        assert np.allclose(fx["R"].cpu().numpy(), ref["R"], rtol=REL, atol=0)
+    else:
+        assert np.array_equal(fx["R"].cpu().numpy(), ref["R"])
     assert abs(fx["P"].item() - ref["P"]) <= REL * abs(ref["P"])
-    assert np.all(fx["R"].cpu().numpy() <= inst.B)
+    assert np.all(fx["R"].cpu().numpy() <= inst.B * (1 + 1e-12))
 
 
 @gpu

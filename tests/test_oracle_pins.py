@@ -463,6 +463,47 @@ def test_fixup_feasible_and_prefix_minimal(mode):
     assert np.any(R > inst.B)
 
 
+def test_fixup_exact_coverage_off_grid():
+    """Sec. 5.4 under the exact reading of the consumption a reset leaves:
+    with fp32 costs of full mantissas (where sequential FP64 sums round), the
+    reset users are the first candidates in (G asc, i asc) order, every
+    initially violated knapsack ends within budget in exact rational
+    arithmetic, and without the last reset user one of them does not."""
+    rng = np.random.default_rng(11)
+    N, M, K = 400, 6, 3
+    p = rng.random((N, M)).astype(np.float32)
+    b = (rng.random((N, M, K)) * 1.37).astype(np.float32)
+    B = 0.05 * b.astype(np.float64).sum(axis=(0, 1))
+    inst = make(p, b, B, kpgen.tree_topq(M, 2))
+    lam = np.full(K, 0.1)
+    ev = oracle.eval_dual(inst, lam, want_G=True)
+    viol = ev["R"] > inst.B
+    assert viol.any()
+    fx = oracle.fixup(inst, lam)
+    x0 = ev["x"].reshape(N, M).astype(bool)
+    cand = [i for i in range(N)
+            if any(viol[k] and x0[i, j] and b[i, j, k] > 0 for j in range(M) for k in range(K))]
+    order = [int(i) for i in fx["reset"]]
+    ranked = [i for _, i in sorted((float(ev["G"][i]), i) for i in cand)]
+    assert order == ranked[:len(order)]
+    x1 = x0.copy()
+    x1[order] = False
+    assert np.array_equal(fx["x"].reshape(N, M).astype(bool), x1)
+
+    def left(reset):
+        keep = x0.copy()
+        keep[reset] = False
+        return [sum((Fraction(float(b[i, j, k])) for i in range(N) for j in range(M) if keep[i, j]), Fraction(0))
+                for k in range(K)]
+
+    Bq = [Fraction(float(v)) for v in inst.B]
+    after = left(order)
+    assert all(after[k] <= Bq[k] for k in range(K) if viol[k])
+    assert len(order) > 0
+    before = left(order[:-1])
+    assert any(before[k] > Bq[k] for k in range(K) if viol[k])
+
+
 # ------------------------------------------------- paper-level claims ------
 
 @pytest.mark.parametrize("K,tree_kind", [(5, "hier"), (10, "q1")])
