@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <functional>
 #include <mutex>
 #include <tuple>
 #include <string>
@@ -45,10 +46,13 @@ hipError_t kp_launch_gather_csr(const int64_t *rowptr, const int32_t *col, const
 hipError_t kp_launch_dual_backward(int K, const double *R, const double *B, const double *gout,
                                    double *glam, hipStream_t stream);
 hipError_t kp_launch_validate(const float *v, int64_t n, unsigned int *flags, hipStream_t stream);
-hipError_t kp_launch_fixup_pipeline(ProbDev pr, uint8_t *x, const double *lam, const int *kv, const int *vk,
-                                    const double *Bv, int nv, const double *R, const double *P,
+hipError_t kp_launch_fixup_pipeline(ProbDev pr, int row_d, uint8_t *x, const double *lam, const int *kv,
+                                    const int *vk, const double *Bv, int nv, int nb, const double *R,
+                                    const double *P,
                                     double *R_out, double *P_out, int64_t *n_reset, void *scratch,
-                                    hipStream_t stream, uint32_t *pinned, int persist);
+                                    hipStream_t stream, uint32_t *pinned, int persist,
+                                    const std::function<hipError_t(const FixBins &)> &bins_pass);
+int kp_fixup_bins(int nv, size_t budget);
 size_t kp_fixup_scratch_bytes(int64_t N, int nv, int K);
 size_t kp_ell_lds_bytes(int M, int K, int D, int L, int mode, int *region_out);
 hipError_t kp_launch_ell(const SweepArgs &a, int D, int grid, int mode, hipStream_t stream, int *used);
@@ -1472,8 +1476,23 @@ kp_status kp_primal_fixup(void *ctx, const kp_problem *prob, const double *lambd
   // blocks of the passes over users: a few per compute unit
   const int64_t nch = (N + 4095) / 4096;
   const int persist = (int)std::max<int64_t>(1, std::min<int64_t>(nch, 1024));
-  HIP_TRY(kp_launch_fixup_pipeline(P.pr, xd, lambda, kvd, vkd, Bvd, nv, Rv, Pv, R_out, primal_out, n_reset_out,
-                                   b + o_scr, c->stream, (uint32_t *)(c->pinned + 48), persist));
+  // the per-user bin pass: the uniform-row kernel's evaluation with the bins
+  // (LDS for the sums kept to 24 KB, next to its staged tiles) when it
+  // applies, else a thread per user
+  std::function<hipError_t(const FixBins &)> lean;
+  int nb = kp_fixup_bins(nv, 40 * 1024);
+  if (P.ell_D) {
+    nb = kp_fixup_bins(nv, 24 * 1024);
+    lean = [&](const FixBins &fb) -> hipError_t {
+      SweepArgs a = make_args(P, lambda, w, nullptr, false);
+      a.ntiles = P.ell_ntiles;
+      a.fx = fb;
+      return kp_launch_ell(a, P.ell_D, P.ell_grid, 4, c->stream, nullptr);
+    };
+  }
+  HIP_TRY(kp_launch_fixup_pipeline(P.pr, P.row_nnz, xd, lambda, kvd, vkd, Bvd, nv, nb, Rv, Pv, R_out, primal_out,
+                                   n_reset_out, b + o_scr, c->stream, (uint32_t *)(c->pinned + 48), persist,
+                                   lean));
   return KP_OK;
 }
 

@@ -89,6 +89,18 @@ __device__ __forceinline__ bool xs_gt(const XSum &a, double B) {
   return H > HB || (H == HB && (double)L > rB);
 }
 
+// Bin of a post-processing key: the number of the nb - 1 ascending
+// splitters below it.
+__device__ __forceinline__ int fx_bin_of(const uint64_t *split, int nb, uint64_t key) {
+  int lo = 0, hi = nb - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (split[mid] < key) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
 // Breakpoint arithmetic of the walks.  For lines z_a = c_a - lambda b_a and
 // z_b = c_b - lambda b_b with b_a > b_b, the crossing is
 // fl(fl(c_a - c_b) / fl(b_a - b_b)) and line a ranks above line b for lambda

@@ -23,7 +23,7 @@ static size_t ell_lds(int M, int K, int D, int L, int mode, int waves, int *regi
   const int ew = waves;
   size_t s = r16((size_t)(K + 1) * 8) + r16((size_t)L * 8 + 8) + r16((size_t)L * 4 + 4) +
              r16((size_t)ew * (K + 2) * 8);
-  if (mode != KM_EVAL) s += r16((size_t)K * 4) + r16((size_t)K * 8 + 16);
+  if (mode != KM_EVAL && mode != KM_FIX) s += r16((size_t)K * 4) + r16((size_t)K * 8 + 16);
   if (mode == KM_WMAIN) s += r16((size_t)(K + 1) * sizeof(LamW));
   if (brk)   // (the listed users' pass of a window pass bins nothing: no histograms)
     s += r16((size_t)K * sizeof(XSum)) + r16((size_t)K * sizeof(KState)) +
@@ -71,16 +71,24 @@ int laminar_rank(const TreeDev &t, int M) {
   return total + __builtin_popcountll(all & ~covered);
 }
 
-// mode: 0 evaluation, 1 full SCD pass, 2 window main pass, 3 listed users of a window pass.
+// mode: 0 evaluation, 1 full SCD pass, 2 window main pass, 3 listed users of a window pass,
+// 4 evaluation with the post-processing bins (a.fx).
 // grid is an upper bound (the size of the per-block buffers); *used receives
 // the grid launched (the blocks that can be resident at once, at most grid).
 hipError_t kp_launch_ell(const SweepArgs &a, int D, int grid, int mode, hipStream_t stream, int *used) {
   EllGeom g;
   g.M = a.pr.M;
   g.K = a.pr.K;
-  if (g.M < 1 || g.M > 16 || (D != 1 && D != 2) || mode < 0 || mode > 3) return hipErrorInvalidValue;
+  if (g.M < 1 || g.M > 16 || (D != 1 && D != 2) || mode < 0 || mode > 4) return hipErrorInvalidValue;
   if (a.ntiles > 0x7fffffffLL) return hipErrorInvalidValue;  // the kernel's tile indices are 32-bit
-  const size_t lds = kp_ell_lds_bytes(g.M, g.K, D, a.tree.L, mode, &g.region);
+  if ((mode == KM_FIX) != (a.fx.bin != nullptr)) return hipErrorInvalidValue;
+  size_t lds = kp_ell_lds_bytes(g.M, g.K, D, a.tree.L, mode, &g.region);
+  if (mode == KM_FIX) {
+    // post-processing bins: slot map, splitters, bin sums and counts
+    auto r16 = [](size_t b) { return (b + 15) & ~(size_t)15; };
+    lds += r16((size_t)g.K * 4) + r16((size_t)a.fx.nb * 8) + r16((size_t)a.fx.nb * a.fx.nv * sizeof(XSum)) +
+           r16((size_t)a.fx.nb * 4);
+  }
   g.rows = g.region / (65 * 8);
   if (g.rows > g.K + 2) g.rows = g.K + 2;
   g.x4 = (((uintptr_t)a.pr.p | (uintptr_t)a.pr.col | (uintptr_t)a.pr.val) & 15) == 0;
@@ -90,6 +98,7 @@ hipError_t kp_launch_ell(const SweepArgs &a, int D, int grid, int mode, hipStrea
     case KM_EVAL: return kp_launch_ell_mode<KM_EVAL>(a, g, lds, grid, D, stream, used);
     case KM_SCD: return kp_launch_ell_mode<KM_SCD>(a, g, lds, grid, D, stream, used);
     case KM_WMAIN: return kp_launch_ell_mode<KM_WMAIN>(a, g, lds, grid, D, stream, used);
+    case KM_FIX: return kp_launch_ell_mode<KM_FIX>(a, g, lds, grid, D, stream, used);
     default: return kp_launch_ell_mode<KM_WFAIL>(a, g, lds, grid, D, stream, used);
   }
 }

@@ -352,12 +352,15 @@ __device__ __forceinline__ void scd_user(const SweepArgs &a, int M, int K, int L
   }
 }
 
-// Kernel modes: evaluation; full SCD pass (every search mode); the window
-// pass split in two -- the main kernel evaluates every user and lists the
+// Kernel modes: evaluation (and its post-processing variant); full SCD pass
+// (every search mode); the window pass split in two -- the main kernel
+// evaluates every user and lists the
 // users whose lines may cross inside some knapsack's window, the second kernel
 // gathers the listed users 64 per wave and runs their breakpoint phase with
 // every lane busy.
-enum { KM_EVAL = 0, KM_SCD = 1, KM_WMAIN = 2, KM_WFAIL = 3 };
+enum { KM_EVAL = 0, KM_SCD = 1, KM_WMAIN = 2, KM_WFAIL = 3, KM_FIX = 4 };
+// KM_FIX: the evaluation plus the post-processing's per-user bins (its own
+// instantiation, so the plain evaluation keeps its registers).
 
 // Waves per block (WPB): 4; the full-search pass keeps K x 64 exact
 // histogram bins per block in LDS, so when its LDS allows it runs 8 waves per
@@ -378,6 +381,7 @@ k_ell(const SweepArgs a, const EllGeom g) {
   constexpr int ENT = EWM * 64;
   constexpr bool BREAK = (MODE == KM_SCD || MODE == KM_WFAIL);   // breakpoint phase
   constexpr bool STAGED = (MODE != KM_WFAIL);                    // contiguous tiles
+  constexpr bool EV = (MODE == KM_EVAL || MODE == KM_FIX);       // evaluation only
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int M = EXACT ? EM : g.M, K = g.K;
@@ -394,7 +398,7 @@ k_ell(const SweepArgs a, const EllGeom g) {
   unsigned long long *hmin = nullptr, *hmax = nullptr;
   XSum *kcorr = nullptr;
   double *hwin = nullptr;
-  if (MODE != KM_EVAL) {
+  if (!EV) {
     kmode = (int *)carve((size_t)K * 4);
     hwin = (double *)carve((size_t)K * 8 + 16);  // [K] window half-widths (0: no window), [K] their max,
                                                  // [K+1] the largest multiplier with a window
@@ -415,12 +419,27 @@ k_ell(const SweepArgs a, const EllGeom g) {
     hmax = (unsigned long long *)carve((size_t)K * 8);
     nstage = (uint32_t *)carve(16);
   }
+  // post-processing bins: violated-slot map, splitters, the block's bin sums
+  int *fkv = nullptr;
+  uint64_t *fsp = nullptr;
+  XSum *fhs = nullptr;
+  uint32_t *fhc = nullptr;
+  if (MODE == KM_FIX) {
+    fkv = (int *)carve((size_t)K * 4);
+    fsp = (uint64_t *)carve((size_t)a.fx.nb * 8);
+    fhs = (XSum *)carve((size_t)a.fx.nb * a.fx.nv * sizeof(XSum));
+    fhc = (uint32_t *)carve((size_t)a.fx.nb * 4);
+    for (int t = tid; t < K; t += ENT) fkv[t] = a.fx.kv[t];
+    for (int t = tid; t < a.fx.nb - 1; t += ENT) fsp[t] = a.fx.split[t];
+    for (int t = tid; t < a.fx.nb * a.fx.nv; t += ENT) fhs[t] = xs_zero();
+    for (int t = tid; t < a.fx.nb; t += ENT) fhc[t] = 0u;
+  }
   unsigned char *wreg = smem + off + (size_t)wv * g.region;   // this wave's region
   for (int t = tid; t <= K; t += ENT) lam[t] = t < K ? a.lam[t] : 0.0;
   if (MODE == KM_WMAIN && tid == 0) lw[K] = LamW{0.0, 0.0f, 0.0f};
   for (int t = tid; t < a.tree.L; t += ENT) { tmask[t] = a.tree.mask[t]; tcap[t] = a.tree.cap[t]; }
   for (int t = tid; t < EWM * (K + 2); t += ENT) wacc[t] = 0.0;
-  if (MODE != KM_EVAL) {
+  if (!EV) {
     for (int t = tid; t < K; t += ENT) {
       kmode[t] = a.st[t].mode;
       hwin[t] = a.st[t].mode == KS_WINDOW ? a.st[t].hw : 0.0;
@@ -444,7 +463,7 @@ k_ell(const SweepArgs a, const EllGeom g) {
     if (tid == 0) *nstage = 0u;
   }
   __syncthreads();
-  if (MODE != KM_EVAL && tid == 0) {
+  if (!EV && tid == 0) {
     double m = 0.0, l = 0.0;
     for (int k = 0; k < K; ++k) {
       m = hwin[k] > m ? hwin[k] : m;
@@ -655,7 +674,7 @@ k_ell(const SweepArgs a, const EllGeom g) {
       S = S32;
     }
     double bmax = 0.0;
-    if (MODE != KM_EVAL) {
+    if (!EV) {
       // largest stored cost (exact in fp32; widened once)
       float bm = 0.0f;
       #pragma unroll
@@ -691,6 +710,34 @@ k_ell(const SweepArgs a, const EllGeom g) {
           sv_[r * D + t] = ok ? v0 : 0.0f;
         }
       }
+    }
+    // ---- post-processing bins (Sec. 5.4): a candidate's bin by G_i and its
+    // costs on the violated knapsacks into the bin's exact sums ----
+    if (MODE == KM_FIX && act) {
+      const int nv = a.fx.nv;
+      const int b = fx_bin_of(fsp, a.fx.nb, dkey(Gi + 0.0));
+      XSum *row = fhs + (size_t)b * nv;
+      bool cand = false;
+      auto add = [&](int k, float c) {
+        if ((unsigned)k >= (unsigned)K || !(c > 0.0f)) return;
+        const int v = fkv[k];
+        if (v < 0) return;
+        cand = true;
+        xs_atomic_add(&row[v], (double)c);
+      };
+      if (g.compact) {
+        #pragma unroll
+        for (int e = 0; e < KP_SEL_MAX * D; ++e) add(sk[e], sv_[e]);
+      } else {
+        #pragma unroll
+        for (int j = 0; j < EM; ++j) {
+          if (!(S >> j & 1)) continue;
+          #pragma unroll
+          for (int t = 0; t < D; ++t) add(cl[j * D + t], vl[j * D + t]);
+        }
+      }
+      if (cand) atomicAdd(&fhc[b], 1u);
+      a.fx.bin[u0 + lane] = cand ? (uint8_t)b : (uint8_t)0xFF;
     }
     // ---- window filter (main window pass), before the arrays die ----
     bool listed = false;
@@ -749,7 +796,7 @@ k_ell(const SweepArgs a, const EllGeom g) {
       __asm__ volatile("" ::: "memory");
       listed = act && fail;
     }
-    if (STAGED) {
+    if (STAGED && MODE != KM_FIX) {   // (the bin pass needs neither x nor the statistics)
       if (a.x_out && act) {
         uint8_t *xo = a.x_out + (u0 + lane) * M;
         for (int j = 0; j < M; ++j) xo[j] = (uint8_t)(S >> j & 1);
@@ -894,7 +941,13 @@ k_ell(const SweepArgs a, const EllGeom g) {
     if (lane == 0 && nlist) atomicAdd(a.fcount + 1, nlist);
   }
   __syncthreads();
-  if (a.want_stats && STAGED) {
+  if (MODE == KM_FIX) {
+    for (int t = tid; t < a.fx.nb * a.fx.nv; t += ENT)
+      if (xs_nonzero(fhs[t])) xs_atomic_add_sum(&a.fx.hsum[t], fhs[t]);
+    for (int t = tid; t < a.fx.nb; t += ENT)
+      if (fhc[t]) atomicAdd(&a.fx.hcnt[t], fhc[t]);
+  }
+  if (a.want_stats && STAGED && MODE != KM_FIX) {
     for (int c = tid; c < K + 2; c += ENT) {
       double s = 0.0;
       for (int w = 0; w < EWM; ++w) s = s + wacc[w * (K + 2) + c];

@@ -88,6 +88,19 @@ struct KState {
   XSum corr;           // KS_WINDOW: sum over users of C_ik(whi+) - v_ik(x(lambda^t))
 };
 
+// The post-processing's per-user pass (Sec. 5.4): every candidate (a user
+// whose selection consumes a violated knapsack) gets the bin of its group dual
+// value among nb bins cut by the splitters, and its costs on the violated
+// knapsacks are added into the bin's exact sums.
+struct FixBins {
+  uint8_t *bin;            // [N] bin per user (0xFF: not a candidate)
+  const int *kv;           // [K] slot of a violated knapsack, or -1
+  const uint64_t *split;   // [nb - 1] ascending splitter keys
+  XSum *hsum;              // [nb][nv] exact consumption per bin and slot
+  uint32_t *hcnt;          // [nb] candidates per bin
+  int nb, nv;
+};
+
 struct SweepArgs {
   ProbDev pr;
   TreeDev tree;
@@ -113,11 +126,8 @@ struct SweepArgs {
   uint32_t stage_cap;
   int pass;
   unsigned long long *err; // walk-limit counter
-  // per-user outputs for the post-processing (eval only)
-  double *G_out;           // [N] group dual value p~_i, or null
-  double *uv_out;          // [N][nv] consumption of the selected knapsacks, or null
-  const int *kv_map;       // [K] column in uv_out, or -1
-  int nv;
+  // post-processing bins (uniform-row kernel, evaluation only; fx.bin null otherwise)
+  FixBins fx;
   // window pass split in two kernels: users listed by the first
   unsigned int *flist;     // [fcap] user indices
   unsigned int *fcount;    // [0] reserved list slots (atomic; may exceed fcap), [1] listed users

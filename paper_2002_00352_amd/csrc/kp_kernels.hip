@@ -18,6 +18,7 @@
 #include <stdint.h>
 #include <string.h>
 #include <algorithm>
+#include <functional>
 #include "kp_internal.h"
 
 #define NT 256
@@ -571,7 +572,6 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
       }
       uPG[2 * u] = Pi;
       uPG[2 * u + 1] = Gi;
-      if (a.G_out) a.G_out[u0 + u] = Gi;
       if (a.x_out) {
         uint8_t *xo = a.x_out + (u0 + u) * M;
         for (int j = 0; j < M; ++j) xo[j] = (uint8_t)(S >> j & 1);
@@ -627,10 +627,6 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
         for (uint64_t m = S0; m; m &= m - 1) v = v + (double)bu[(__ffsll((long long)m) - 1) * K + k];
       }
       vk[q] = v;
-      if (a.uv_out) {
-        const int col = a.kv_map[k];
-        if (col >= 0) a.uv_out[(size_t)(u0 + u) * a.nv + col] = v;
-      }
       if (SCD) {
         const int mode = kmode[k];
         if (walk_mode(mode)) {
@@ -1486,6 +1482,7 @@ struct FixArgs {
   const int *vk;          // [nv] knapsack of each slot
   const double *Bv;       // [nv] their budgets
   int nv, nb;
+  int d;                  // CSR: entries in every row (row r's start at r * d), or 0
   const uint64_t *split;  // [nb - 1] ascending splitter keys
   uint8_t *bin;           // [N] bin of every user (FX_NONE: not a candidate)
   XSum *hsum;             // [nb][nv] exact consumption per bin
@@ -1569,12 +1566,16 @@ __global__ void __launch_bounds__(FX_NT) k_rs_scatter(const uint64_t *key, const
   }
 }
 
-// the cost entries (k, b) of item row r in storage order
+// the cost entries (k, b) of item row r in storage order (d > 0: every CSR
+// row holds d entries)
 template <class F>
-__device__ __forceinline__ void fx_row(const ProbDev &pr, int64_t r, F f) {
+__device__ __forceinline__ void fx_row(const ProbDev &pr, int d, int64_t r, F f) {
   if (pr.fmt == 0) {   // dense rows
     const float *bb = pr.b + r * pr.K;
     for (int k = 0; k < pr.K; ++k) f(k, bb[k]);
+  } else if (d > 0) {
+    const int64_t e0 = r * d;
+    for (int t = 0; t < d; ++t) f((int)pr.col[e0 + t], pr.val[e0 + t]);
   } else {
     const int64_t e1 = pr.rowptr[r + 1];
     for (int64_t e = pr.rowptr[r]; e < e1; ++e) f((int)pr.col[e], pr.val[e]);
@@ -1592,7 +1593,7 @@ __device__ __forceinline__ bool fx_user(const FixArgs &f, int64_t i, double &G) 
     const int64_t r = i * M + j;
     if (!f.x[r]) continue;
     double acc = (double)f.pr.p[r];
-    fx_row(f.pr, r, [&](int k, float c) {
+    fx_row(f.pr, f.d, r, [&](int k, float c) {
       if ((unsigned)k >= (unsigned)K) return;
       const double prod = f.lam[k] * (double)c;
       acc = acc - prod;
@@ -1610,22 +1611,11 @@ __device__ __forceinline__ XSum fx_use(const FixArgs &f, int64_t i, int k) {
   for (int j = 0; j < f.pr.M; ++j) {
     const int64_t r = i * f.pr.M + j;
     if (!f.x[r]) continue;
-    fx_row(f.pr, r, [&](int kk, float c) {
+    fx_row(f.pr, f.d, r, [&](int kk, float c) {
       if (kk == k) s = xs_plus(s, xs_of((double)c));
     });
   }
   return s;
-}
-
-// number of splitters below key
-__device__ __forceinline__ int fx_bin(const uint64_t *split, int nb, uint64_t key) {
-  int lo = 0, hi = nb - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (split[mid] < key) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo;
 }
 
 __device__ __forceinline__ XSum xs_minus(const XSum &a, const XSum &b) {
@@ -1680,14 +1670,14 @@ __global__ void __launch_bounds__(FX_NT) k_fix_bins(FixArgs f, int lds) {
       double G;
       uint8_t bb = (uint8_t)FX_NONE;
       if (fx_user(f, i, G)) {
-        const int b = fx_bin(sp, nb, dkey(G + 0.0));
+        const int b = fx_bin_of(sp, nb, dkey(G + 0.0));
         bb = (uint8_t)b;
         atomicAdd(&hc[b], 1u);
         XSum *row = hs + (size_t)b * nv;
         for (int j = 0; j < M; ++j) {
           const int64_t r = i * M + j;
           if (!f.x[r]) continue;
-          fx_row(f.pr, r, [&](int k, float c) {
+          fx_row(f.pr, f.d, r, [&](int k, float c) {
             if ((unsigned)k >= (unsigned)K || !(c > 0.0f)) return;
             const int v = f.kv[k];
             if (v >= 0) xs_atomic_add(&row[v], (double)c);
@@ -1812,7 +1802,7 @@ __global__ void __launch_bounds__(FX_NT) k_fix_chunk(FixArgs f, const uint32_t *
     for (int j = 0; j < M; ++j) {
       const int64_t r = i * M + j;
       if (!f.x[r]) continue;
-      fx_row(f.pr, r, [&](int k, float c) {
+      fx_row(f.pr, f.d, r, [&](int k, float c) {
         if ((unsigned)k >= (unsigned)K || !(c > 0.0f)) return;
         const int v = f.kv[k];
         if (v >= 0 && f.vb[v] == bst) xs_atomic_add(&cs[v], (double)c);
@@ -1885,7 +1875,7 @@ __device__ __forceinline__ void fx_remove(const FixArgs &f, int64_t i, XSum *rem
     if (!f.x[r]) continue;
     f.x[r] = 0;
     xs_atomic_add(&rem[K], (double)f.pr.p[r]);
-    fx_row(f.pr, r, [&](int k, float c) {
+    fx_row(f.pr, f.d, r, [&](int k, float c) {
       if ((unsigned)k < (unsigned)K && c != 0.0f) xs_atomic_add(&rem[k], (double)c);
     });
   }
@@ -1948,9 +1938,11 @@ static hipError_t fx_sort(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1
   return hipGetLastError();
 }
 
-static int fx_bins_for(int nv) {
+// bins of the post-processing: the most (a power of two, at most 128) whose
+// sums over nv slots fit in budget bytes
+int kp_fixup_bins(int nv, size_t budget) {
   int nb = 128;
-  while (nb > 1 && (size_t)nb * nv * sizeof(XSum) > 40 * 1024) nb >>= 1;
+  while (nb > 1 && (size_t)nb * nv * sizeof(XSum) > budget) nb >>= 1;
   return nb;
 }
 
@@ -1997,26 +1989,32 @@ FxLayout fx_layout(int64_t N, int nv, int K) {
 
 size_t kp_fixup_scratch_bytes(int64_t N, int nv, int K) { return fx_layout(N, nv, K).total; }
 
-// kv / vk / Bv: device arrays of the violated slots; pinned: 32 bytes of
-// pinned host memory; persist: blocks of the user passes.  Synchronizes the
-// stream twice (the sample's candidate count, then the threshold bin).
-hipError_t kp_launch_fixup_pipeline(ProbDev pr, uint8_t *x, const double *lam, const int *kv, const int *vk,
-                                    const double *Bv, int nv, const double *R, const double *P,
+// kv / vk / Bv: device arrays of the violated slots; nb: bins (at most 128,
+// nb * nv sums within 40 KB); pinned: 32 bytes of pinned host memory;
+// persist: blocks of the user passes; bins_pass: launches the per-user bin
+// pass (k_fix_bins when empty).  Synchronizes the stream twice (the
+// sample's candidate count, then the threshold bin).
+hipError_t kp_launch_fixup_pipeline(ProbDev pr, int row_d, uint8_t *x, const double *lam, const int *kv,
+                                    const int *vk, const double *Bv, int nv, int nb, const double *R,
+                                    const double *P,
                                     double *R_out, double *P_out, int64_t *n_reset, void *scratch,
-                                    hipStream_t stream, uint32_t *pinned, int persist) {
+                                    hipStream_t stream, uint32_t *pinned, int persist,
+                                    const std::function<hipError_t(const FixBins &)> &bins_pass) {
   const int64_t N = pr.N;
   const int K = pr.K;
   const FxLayout L = fx_layout(N, nv, K);
   char *w = (char *)scratch;
   FixArgs f;
   f.pr = pr;
+  f.d = pr.fmt == 0 ? 0 : row_d;
   f.x = x;
   f.lam = lam;
   f.kv = kv;
   f.vk = vk;
   f.Bv = Bv;
   f.nv = nv;
-  f.nb = fx_bins_for(nv);
+  if (nb < 1 || nb > 128 || (nb > 1 && (size_t)nb * nv * sizeof(XSum) > 40 * 1024)) return hipErrorInvalidValue;
+  f.nb = nb;
   f.split = (const uint64_t *)(w + L.split);
   f.bin = (uint8_t *)(w + L.bin);
   f.hsum = (XSum *)(w + L.hsum);
@@ -2047,11 +2045,23 @@ hipError_t kp_launch_fixup_pipeline(ProbDev pr, uint8_t *x, const double *lam, c
   if (f.nb > 1)
     hipLaunchKernelGGL(k_fix_split, dim3(1), dim3(128), 0, stream, skey, scount, f.nb, (uint64_t *)f.split);
   // bins and their exact sums
-  const size_t lb = (size_t)f.nb * nv * sizeof(XSum) + (size_t)f.nb * 4 + 8 + (size_t)f.nb * 8;
-  const int bins_lds = lb <= FX_LDS_MAX;
-  const size_t lb_used = bins_lds ? lb : (size_t)f.nb * 8;
-  if (lb_used > 64 * 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_fix_bins, dim3(persist), dim3(FX_NT), lb_used, stream, f, bins_lds);
+  if (bins_pass) {
+    FixBins fb;
+    fb.bin = f.bin;
+    fb.kv = kv;
+    fb.split = f.split;
+    fb.hsum = f.hsum;
+    fb.hcnt = f.hcnt;
+    fb.nb = f.nb;
+    fb.nv = nv;
+    if ((e = bins_pass(fb)) != hipSuccess) return e;
+  } else {
+    const size_t lb = (size_t)f.nb * nv * sizeof(XSum) + (size_t)f.nb * 4 + 8 + (size_t)f.nb * 8;
+    const int bins_lds = lb <= FX_LDS_MAX;
+    const size_t lb_used = bins_lds ? lb : (size_t)f.nb * 8;
+    if (lb_used > 64 * 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_fix_bins, dim3(persist), dim3(FX_NT), lb_used, stream, f, bins_lds);
+  }
   hipLaunchKernelGGL(k_fix_locate, dim3(1), dim3(256), 0, stream, f);
   if ((e = hipMemcpyAsync(pinned, f.fs, sizeof(FixState), hipMemcpyDeviceToHost, stream)) != hipSuccess) return e;
   if ((e = hipStreamSynchronize(stream)) != hipSuccess) return e;
