@@ -876,13 +876,17 @@ __global__ void __launch_bounds__(256) k_reduce_stats(const double *partials, in
 // last step), around lambda_k^{t-1}, 1.25x the drift wide.  hw is the
 // farthest window edge from lambda_k^t (the filters bound the lines'
 // movement by it).  step, prev, drift < 0 or NaN: unknown.
+// Half-widths are at least 2^-20 of the centre: near convergence a
+// multiplier's step or its 2-cycle drift can shrink to almost nothing and
+// then move by more than that once, and a window that misses costs a full
+// pass, while a few hundred more listed users cost little.
 __device__ __forceinline__ void choose_window(KState &s, double step, double prev, double drift) {
   double c = 0.0, h = 0.0;
   if (step > 0.0 && KP_WIN_MULT * step <= KP_WIN_MAX_REL * s.center) {
     c = s.center;
-    h = KP_WIN_MULT * step;
+    h = fmax(KP_WIN_MULT * step, s.center * 0x1p-20);
   } else if (step > 0.0 && drift >= 0.0 && prev >= 0.0 && drift * 8.0 <= step) {
-    const double floor_ = (prev > 0x1p-20 ? prev : 0x1p-20) * 0x1p-30;
+    const double floor_ = (prev > 0x1p-20 ? prev : 0x1p-20) * 0x1p-20;
     c = prev;
     h = KP_WIN_MULT * (drift > floor_ ? drift : floor_);
   } else {
