@@ -75,7 +75,8 @@ void kp_coldesc_fill(void *dst, const double *partials, const double *lam, const
 hipError_t kp_launch_validate_csr(const int64_t *rowptr, const int32_t *col, int64_t nrows, int K,
                                   unsigned int *flags, hipStream_t stream);
 hipError_t kp_launch_fill_f64(double *dst, int64_t n, double v, hipStream_t stream);
-hipError_t kp_launch_recenter(KState *st, int K, const double *lam_hat, hipStream_t stream);
+hipError_t kp_launch_recenter(KState *st, int K, const double *lam_hat, const double *lam_in, int window,
+                              hipStream_t stream);
 hipError_t kp_launch_strided_users(int64_t *users, int64_t n, int64_t stride, int64_t off, hipStream_t stream);
 hipError_t kp_launch_uniform_rowptr(int64_t *rowptr, int64_t nrows, int D, hipStream_t stream);
 hipError_t kp_launch_stream_read(const void *src, int64_t n16, unsigned long long *out, int grid,
@@ -821,7 +822,10 @@ kp_status sample_center(Ctx *c, const kp_problem *prob, const Prepared &P, const
     memcpy(m, g_err, sizeof m);
     return fail(st, "sample search: %s", m);
   }
-  HIP_TRY(kp_launch_recenter(w.st, K, lam_hat, c->stream));
+  // with windows on, the full searches start with a window around the
+  // sample's threshold
+  HIP_TRY(kp_launch_recenter(w.st, K, lam_hat, lambda_in, (c->window_enabled && !c->interp) ? 1 : 0,
+                             c->stream));
   return KP_OK;
 }
 

@@ -250,6 +250,9 @@ def test_off_grid_costs_trajectory_twice(name, mk):
 
 SAMPLED_CASES = [
     ("c3-csr-declared-rows", lambda: kpgen.config_instance(3, N=20000), None),
+    # many users: the sample's window over every user, exact tests and walks
+    # that stop below it
+    ("c3-csr-300k", lambda: kpgen.config_instance(3, N=300000), None),
     ("c2-dense", lambda: kpgen.config_instance(2, N=4000), None),
     ("c3-csr-general-rows", lambda: kpgen.config_instance(3, N=6000), 0),
     ("laminar-dense-K9", lambda: random_instance(np.random.default_rng(81), 5000, 12, 9,
@@ -263,9 +266,11 @@ SAMPLED_CASES = [
 def test_sampled_start_trajectory(name, mk, row_nnz):
     """Full searches that start from a strided sample's threshold
     (kp_set_sampled_start, here on small instances): along SCD trajectories
-    from lambda = 0 -- with windows, and with every iteration a full search --
-    every update equals the oracle's bit for bit (the sample only places the
-    buckets), for uniform-row CSR, general CSR and dense costs."""
+    from lambda = 0 -- with windows (the sample's threshold opens a window
+    away from lambda^t, a miss falls back to buckets around it), and with
+    every iteration a full search around it -- every update equals the
+    oracle's bit for bit (the sample only decides the cost), for uniform-row
+    CSR, general CSR and dense costs."""
     kp, torch = _kp()
     print("case", name, flush=True)
     inst = mk()
