@@ -253,9 +253,15 @@ def summarize_trace(trace_dir, bench_log, kernel_subs):
     trace = _csv_rows(os.path.join(trace_dir, "run_kernel_trace.csv"))
     n = rec["roofline"]["launches"]
     subs = kernel_subs.split("|")
+    # the timed passes end where the streaming ceiling's first read starts
+    # (the benchmark measures it right after them)
+    marks = [int(r["Start_Timestamp"]) for r in trace if "k_stream_read" in r["Kernel_Name"]]
+    end = min(marks) if marks else None
     per = []
     for sub in subs:
-        disp = sorted((r for r in trace if sub in r["Kernel_Name"]), key=lambda r: int(r["Start_Timestamp"]))
+        disp = sorted((r for r in trace if sub in r["Kernel_Name"]
+                       and (end is None or int(r["Start_Timestamp"]) < end)),
+                      key=lambda r: int(r["Start_Timestamp"]))
         per.append([(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6 for r in disp[-n:]])
     durs = [sum(x) for x in zip(*per)]
     avg = sum(durs) / len(durs)
@@ -265,6 +271,7 @@ def summarize_trace(trace_dir, bench_log, kernel_subs):
                    f"{float(r['TotalDurationNs']) * 1e-6:.1f} | {float(r['Percentage']):.2f} |")
     out.append("")
     out.append(f"Timed sweep passes (the last {n} dispatches of " + " + ".join(f"`{x}`" for x in subs) +
+               " before the streaming-ceiling probe" +
                f"): average {avg:.3f} ms per pass (kernels only), min {min(durs):.3f}, max {max(durs):.3f}; "
                + ", ".join(f"`{x}` {sum(p) / len(p):.3f} ms" for x, p in zip(subs, per)) + ".")
     out.append(f"bench.py's own HIP-event average per pass (both launches and the list reset "
@@ -283,8 +290,12 @@ def summarize_pmc(fetch_dir, write_dir, cfetch_dir, cwrite_dir, kernel_subs, lau
     scaled by what the same counter reads for a plain copy of known size;
     written with the hash of the kernel sources they were taken on."""
     def per_dispatch(d, counter, sub):
-        rows = [r for r in _csv_rows(os.path.join(d, "run_counter_collection.csv"))
-                if sub in r["Kernel_Name"] and r["Counter_Name"] == counter]
+        allrows = _csv_rows(os.path.join(d, "run_counter_collection.csv"))
+        # the timed passes end where the streaming ceiling's first read starts
+        marks = [int(r["Dispatch_Id"]) for r in allrows if "k_stream_read" in r["Kernel_Name"]]
+        end = min(marks) if (marks and sub) else None
+        rows = [r for r in allrows if sub in r["Kernel_Name"] and r["Counter_Name"] == counter
+                and (end is None or int(r["Dispatch_Id"]) < end)]
         vals = {}
         for r in rows:
             vals[r["Dispatch_Id"]] = vals.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
