@@ -256,15 +256,18 @@ kp_status kp_stream_read(void *hip_stream, const void *src, size_t bytes, uint64
    shape; 0 keeps the built-in choice, (0, 0) removes the override.  The
    general kernel takes both (users per tile capped by its LDS); the
    uniform-row kernel takes the grid only (one lane per user, 64 users per
-   wave); batched plans created later take the users per tile of each
-   instance's shape.  Grids are capped at the blocks that can be resident.
+   wave); dense evaluations with M <= 16 and K <= 16 run the lane-per-user
+   dense kernel unless the override names users per tile (then the general
+   kernel runs with them), and take its grid; batched plans created later
+   take the users per tile of each instance's shape.  Grids are capped at the blocks that can be resident.
    x, lambda and R do not depend on these values; g and P are FP64 sums whose
    grouping follows the grid, so their last bits may.  Used by the autotuner. */
 kp_status kp_set_tuning(void *ctx, int32_t M, int32_t K, int32_t b_format, int32_t users_per_tile,
                         int32_t grid);
 /* Shape of the last sweep launch made through this context: kernel (0 the
-   general kernel, 1 the uniform-row kernel, -1 none yet), users per tile and
-   blocks launched.  HOST outputs, each may be NULL. */
+   general kernel, 1 the uniform-row kernel, 2 the lane-per-user evaluation
+   of dense costs, -1 none yet), users per tile and blocks launched.  HOST
+   outputs, each may be NULL. */
 kp_status kp_get_launch_shape(void *ctx, int32_t *kernel, int32_t *users_per_tile, int32_t *grid);
 /* Tuning of batched plans created later on this context: LDS bytes per block
    of the batched launch (instances with long rows take fewer users per tile
@@ -277,10 +280,13 @@ kp_status kp_set_batched_tuning(void *ctx, int32_t lds_bytes, int32_t block_mult
 /* Kernel choice for CSR costs: a problem that declares b_row_nnz = D (every
    item row holds D in {1, 2} entries at r*D) with M <= 16 runs the lean
    per-user kernel, which never reads b_rowptr; any other CSR problem runs
-   the general kernel.  The library keeps no record of a problem's structure
-   between calls: the declaration travels with the problem.
-   kp_set_kernel_choice(ctx, 0) forces the general kernel for declared
-   problems too (results are identical either way). */
+   the general kernel.  Evaluations (kp_eval_dual, kp_dd_step, the first
+   pass of kp_primal_fixup) of dense costs with M <= 16 and K <= 16 run a
+   lane-per-user kernel (one wave per 64 users, costs staged in LDS).  The
+   library keeps no record of a problem's structure between calls: the
+   declaration travels with the problem.  kp_set_kernel_choice(ctx, 0)
+   forces the general kernel for both (x and R are identical either way; g
+   and P up to the grouping of their FP64 sums). */
 kp_status kp_set_kernel_choice(void *ctx, int32_t allow_uniform_rows);
 
 /* Structure query for per-item CSR costs (Sec. 2 layout): *D_out = D when

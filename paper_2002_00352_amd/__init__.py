@@ -20,7 +20,7 @@ _REPO = os.path.dirname(_HERE)
 LIB_PATH = os.path.join(_HERE, "libkp.so")
 SOURCES = [os.path.join(_HERE, "csrc", f) for f in
            ("kp_kernels.hip", "kp_ell.hip", "kp_ell_m0.hip", "kp_ell_m1.hip", "kp_ell_m2.hip",
-            "kp_ell_m3.hip", "kp_ell_m4.hip", "kp_capi.hip")]
+            "kp_ell_m3.hip", "kp_ell_m4.hip", "kp_dense.hip", "kp_capi.hip")]
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
                "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                "-Wno-unused-result"]

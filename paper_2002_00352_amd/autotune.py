@@ -25,7 +25,7 @@ USERS_PER_TILE = (4, 8, 16, 32, 48, 64)
 GRIDS = (512, 1024, 2048, 4096)
 ELL_GRIDS = (128, 256, 512, 768, 1024)          # the uniform-row kernel: grid only
 BATCHED = ((32768, 64), (40960, 32), (40960, 64), (40960, 128), (65536, 64))   # (LDS bytes, block multiple)
-KERNEL_NAMES = {0: "general", 1: "uniform-row"}
+KERNEL_NAMES = {0: "general", 1: "uniform-row", 2: "dense-lane"}
 
 
 def cache_path() -> str:
@@ -91,10 +91,15 @@ def _time(ctx: Context, prob: Problem, lam, scd: bool, reps: int) -> float:
 
 def candidates_for(kernel: int) -> List[Tuple[int, int]]:
     """(users per tile, grid) candidates of a kernel: the uniform-row kernel
-    tunes its grid only."""
+    tunes its grid only; for the lane-per-user dense evaluation, its grids
+    and the general kernel's tiles (a users-per-tile choice selects the
+    general kernel)."""
     if kernel == 1:
         return [(0, g) for g in ELL_GRIDS]
-    return [(u, g) for u in USERS_PER_TILE for g in GRIDS]
+    general = [(u, g) for u in USERS_PER_TILE for g in GRIDS]
+    if kernel == 2:
+        return [(0, g) for g in ELL_GRIDS] + general
+    return general
 
 
 def tune(prob: Problem, ctx: Optional[Context] = None, scd: bool = True, lam=None, reps: int = 2,

@@ -57,6 +57,9 @@ size_t kp_fixup_scratch_bytes(int64_t N, int nv, int K);
 size_t kp_ell_lds_bytes(int M, int K, int D, int L, int mode, int *region_out);
 hipError_t kp_launch_ell(const SweepArgs &a, int D, int grid, int mode, hipStream_t stream, int *used);
 int kp_ell_resident_grid(int D, int mode, int M, int K, int L);
+hipError_t kp_launch_dense(const SweepArgs &a, int grid, hipStream_t stream, int *used);
+int kp_dense_tile_users();
+int kp_dense_resident_grid(int M, int K, int L);
 hipError_t kp_launch_count_modes(const KState *st, int K, int *out, hipStream_t stream);
 hipError_t kp_launch_ell_check(const int64_t *rowptr, int64_t nrows, int D, unsigned int *bad,
                                hipStream_t stream);
@@ -157,6 +160,7 @@ struct Ctx {
   // (0: built-in)
   int bt_lds = 0, bt_mult = 0;
   std::map<std::tuple<int, int, int, int>, std::pair<int, int>> ell_grids;  // (D, M, K, L) -> resident grids
+  std::map<std::tuple<int, int, int>, int> dense_grids;                     // (M, K, L) -> resident grid
   int64_t win_tried = 0, win_above = 0, win_below = 0;   // window searches since creation
   int64_t win_emitted = 0;                                 // breakpoints emitted inside windows
   int64_t win_listed = 0;                                  // users listed by split window passes
@@ -251,8 +255,11 @@ struct Prepared {
   int64_t ell_ntiles = 0;
   int ell_grid = 0;
   int ell_brk_grid = 0;   // smallest grid of the lean kernel's breakpoint launches
+  // lane-per-user evaluation of dense costs (0 = not used)
+  int dense_grid = 0;
+  int64_t dense_ntiles = 0;
   double ell_bytes = 0.0;
-  int stage_grid() const { return std::max(std::max(grid, grid_nh), ell_grid); }
+  int stage_grid() const { return std::max(std::max(grid, grid_nh), std::max(ell_grid, dense_grid)); }
 };
 
 kp_status prepare(const kp_problem *p, bool scd, Prepared &out, const Ctx *ctx = nullptr) {
@@ -418,6 +425,33 @@ constexpr int kEllGrid = 1024;
 kp_status choose_kernel(Ctx *c, Prepared &P, bool scd) {
   P.ell_D = 0;
   P.ell_grid = 0;
+  P.dense_grid = 0;
+  P.dense_ntiles = 0;
+  if (!scd && c->ell_enabled && P.pr.fmt == KP_B_DENSE && P.pr.M <= 16 && P.pr.K <= 16 && P.pr.N > 0) {
+    // dense costs with few items and knapsacks: the lane-per-user
+    // evaluation, unless a tile size was asked for this shape (the general
+    // kernel's); a grid-only override sets its grid
+    auto tit = c->tuning.find(std::make_tuple((int)P.pr.M, (int)P.pr.K, (int)KP_B_DENSE));
+    const bool tiles = tit != c->tuning.end() && tit->second.first > 0;
+    if (!tiles) {
+      const auto key = std::make_tuple((int)P.pr.M, (int)P.pr.K, (int)P.tree.L);
+      auto it = c->dense_grids.find(key);
+      int res = 0;
+      if (it != c->dense_grids.end()) {
+        res = it->second;
+      } else {
+        res = kp_dense_resident_grid(P.pr.M, P.pr.K, P.tree.L);
+        if (res <= 0) return fail(KP_ERR_HIP, "occupancy query failed");
+        c->dense_grids[key] = res;
+      }
+      const int tu = kp_dense_tile_users();
+      P.dense_ntiles = (P.pr.N + tu - 1) / tu;
+      int g = (int)std::min<int64_t>(P.dense_ntiles, res);
+      if (tit != c->tuning.end() && tit->second.second > 0) g = std::min(tit->second.second, res);
+      P.dense_grid = std::max(1, g);
+    }
+    return KP_OK;
+  }
   if (!c->ell_enabled || P.pr.fmt != KP_B_CSR || P.pr.M > 16 || P.pr.N == 0 || P.row_nnz == 0) return KP_OK;
   const int D = P.row_nnz;
   const int64_t nnz = P.pr.N * P.pr.M * (int64_t)D;
@@ -648,6 +682,10 @@ hipError_t timed_sweep(Ctx *c, const SweepArgs &a, const Prepared &P, bool scd, 
     SweepArgs ae = a;
     ae.ntiles = P.ell_ntiles;
     err = kp_launch_ell(ae, P.ell_D, P.ell_grid, scd ? 1 : 0, c->stream, &c->stats_grid);
+  } else if (P.dense_grid && !scd) {
+    SweepArgs ae = a;
+    ae.ntiles = P.dense_ntiles;
+    err = kp_launch_dense(ae, P.dense_grid, c->stream, &c->stats_grid);
   } else {
     err = a.no_hist ? kp_launch_sweep(a, P.U_nh, P.grid_nh, scd, c->stream, &c->stats_grid)
                     : kp_launch_sweep(a, P.U, P.grid, scd, c->stream, &c->stats_grid);
@@ -660,8 +698,9 @@ hipError_t timed_sweep(Ctx *c, const SweepArgs &a, const Prepared &P, bool scd, 
     if (c->ev_pending.size() > 256) drain_events(c, true);
   }
   if (err == hipSuccess) {
-    c->last_kernel = P.ell_D ? 1 : 0;
-    c->last_U = P.ell_D ? 64 : (a.no_hist ? P.U_nh : P.U);
+    const bool dense = !P.ell_D && P.dense_grid && !scd;
+    c->last_kernel = P.ell_D ? 1 : (dense ? 2 : 0);
+    c->last_U = P.ell_D ? 64 : dense ? kp_dense_tile_users() : (a.no_hist ? P.U_nh : P.U);
     c->last_grid = c->stats_grid;
   }
   return err;

@@ -332,6 +332,65 @@ def test_unaligned_dense_costs():
     assert np.array_equal(got, oracle.scd_sweep(inst, lam))
 
 
+DENSE_LANE_CASES = [
+    ("M10-K10-top3-ragged", lambda: random_instance(np.random.default_rng(61), 4099, 10, 10, Q=3)),
+    ("M3-K1", lambda: random_instance(np.random.default_rng(62), 777, 3, 1, Q=1)),
+    ("M7-K16-laminar", lambda: random_instance(np.random.default_rng(63), 1500, 7, 16,
+                                               tree=random_laminar(7, np.random.default_rng(64)))),
+    ("M13-K5-ties", lambda: random_instance(np.random.default_rng(65), 2000, 13, 5, Q=4, grid=5)),
+    ("M16-K16-zeros", lambda: random_instance(np.random.default_rng(66), 640, 16, 16, Q=6, zero_frac=0.3)),
+    ("M12-K4-one-user", lambda: random_instance(np.random.default_rng(67), 1, 12, 4, Q=2)),
+    ("c2-like", lambda: kpgen.config_instance(2, N=8000)),
+]
+
+
+@gpu
+@pytest.mark.parametrize("name,mk", DENSE_LANE_CASES, ids=[c[0] for c in DENSE_LANE_CASES])
+def test_dense_lane_evaluation(name, mk):
+    """The lane-per-user evaluation of dense costs (M <= 16, K <= 16): it is
+    the kernel that runs, x and R equal the oracle's (and the general
+    kernel's) bit for bit, g and P within 1e-9; also from a cost array that
+    is not 16-byte aligned, and through DD steps."""
+    kp, torch = _kp()
+    print("case", name, flush=True)
+    inst = mk()
+    prob = kp.Problem.from_host(inst)
+    rng = np.random.default_rng(len(name))
+    lam = rng.uniform(0.0, 0.6, inst.K)
+    ref = oracle.eval_dual(inst, lam)
+    ctx = kp.Context()
+    ev = kp.kp_eval_dual(prob, _lamd(torch, lam), want_x=True, ctx=ctx)
+    assert ctx.launch_shape()[0] == 2, ctx.launch_shape()
+    assert np.array_equal(ev["x"].cpu().numpy(), ref["x"])
+    assert np.array_equal(ev["R"].cpu().numpy(), ref["R"])
+    assert abs(ev["g"].item() - ref["g"]) <= REL * max(1.0, abs(ref["g"]))
+    assert abs(ev["P"].item() - ref["P"]) <= REL * max(1.0, abs(ref["P"]))
+    gen = kp.Context()
+    gen.set_kernel_choice(False)
+    evg = kp.kp_eval_dual(prob, _lamd(torch, lam), want_x=True, ctx=gen)
+    assert gen.launch_shape()[0] == 0
+    assert np.array_equal(evg["x"].cpu().numpy(), ev["x"].cpu().numpy())
+    assert np.array_equal(evg["R"].cpu().numpy(), ev["R"].cpu().numpy())
+    # unaligned costs: the scalar staging path
+    big = torch.empty(inst.N * inst.M * inst.K + 1, dtype=torch.float32, device="cuda")
+    big[1:] = prob.b
+    prob2 = kp.Problem(prob.p, inst.B, inst.tree.parent, inst.tree.cap, inst.tree.leaf_of_item,
+                       b=big[1:], N=inst.N, M=inst.M, K=inst.K)
+    ev2 = kp.kp_eval_dual(prob2, _lamd(torch, lam), want_x=True, ctx=ctx)
+    assert ctx.launch_shape()[0] == 2
+    assert np.array_equal(ev2["x"].cpu().numpy(), ref["x"])
+    assert np.array_equal(ev2["R"].cpu().numpy(), ref["R"])
+    # dual descent steps (Eq.14) through the same kernel
+    l_gpu = _lamd(torch, lam)
+    l_ref = lam.copy()
+    alpha = 1e-3
+    for _ in range(3):
+        kp.kp_dd_step(prob, alpha, l_gpu, ctx=ctx)
+        r = oracle.eval_dual(inst, l_ref, want_x=False)
+        l_ref = oracle.dd_update(l_ref, alpha, r["R"], inst.B)
+        assert np.array_equal(l_gpu.cpu().numpy(), l_ref)
+
+
 @gpu
 @pytest.mark.parametrize("fmt", ["dense", "csr-uniform-rows"])
 def test_empty_instance(fmt):
