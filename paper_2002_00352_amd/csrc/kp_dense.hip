@@ -1,9 +1,9 @@
 // Lane-per-user evaluation of dense costs with few items and knapsacks
 // (M <= 16, K <= 16): the dual evaluation of Eq.5 with Alg.1 per user.
 //
-// One wave owns a tile of 64 users at a time, one lane per user, and a block
+// One wave owns a tile of 48 users at a time, one lane per user, and a block
 // is one wave, so blocks pack as tightly as the LDS of one tile allows.  The
-// tile's profits [64][M] and costs [64][M][K] (contiguous in the ABI layout)
+// tile's profits [TU][M] and costs [TU][M][K] (contiguous in the ABI layout)
 // are staged with coalesced direct-to-LDS loads; every lane then scores its
 // user (FP64, knapsacks ascending, a product then a subtraction: the sweep's
 // arithmetic), ranks its items by (p~ desc, index asc), runs Alg.1 in rank
@@ -17,9 +17,10 @@
 #include "kp_ell_impl.h"
 
 // users per tile (lanes past it stay idle): a smaller tile holds less LDS,
-// so more waves fit on a compute unit to hide the loads' latency
+// so more waves fit on a compute unit to hide the loads' latency (c2 DD:
+// 64 users 1.18 ms, 56 1.17, 48 1.13, 32 1.96)
 #ifndef KP_DENSE_TU
-#define KP_DENSE_TU 64
+#define KP_DENSE_TU 48
 #endif
 
 namespace {
