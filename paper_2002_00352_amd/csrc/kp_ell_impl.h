@@ -99,13 +99,15 @@ __device__ __forceinline__ void scd_user(const SweepArgs &a, int M, int K, int L
                                          const double *hwin, XSum *kcorr, XSum *hs, uint32_t *hc,
                                          unsigned long long *hmin, unsigned long long *hmax,
                                          uint32_t *kcnt, uint32_t *kovf, uint32_t *nstage) {
-  if (!act) return;
-  // cost of item j in knapsack k (j moves with k)
-  auto bk = [&](int j, int k) -> double {
-    if (D == 1) return (double)btl[j * 64 + lane];
-    const int t = ktl[(j * D) * 64 + lane] == k ? 0 : 1;
-    return (double)btl[(j * D + t) * 64 + lane];
+  // (every lane of the wave runs this function: inactive lanes skip their
+  // own user's work but take part in the walks of the others')
+  // cost of item j in knapsack k (j moves with k), from lane c's column
+  auto bkc = [&](int j, int k, int c) -> double {
+    if (D == 1) return (double)btl[j * 64 + c];
+    const int t = ktl[(j * D) * 64 + c] == k ? 0 : 1;
+    return (double)btl[(j * D + t) * 64 + c];
   };
+  auto bk = [&](int j, int k) -> double { return bkc(j, k, lane); };
   // Window filter per (user, knapsack): over knapsack k's window (within h of
   // lambda_k^t) item a's line moves by at most h b_ak against the fixed lines
   // of the items that do not move with k, and by at most h max(b_ak, b_bk)
@@ -205,7 +207,7 @@ __device__ __forceinline__ void scd_user(const SweepArgs &a, int M, int K, int L
   }
   // one breakpoint per (item, knapsack) that moves alone; queue the others
   uint64_t pending = 0;
-  for (int j = 0; j < M; ++j) {
+  for (int j = 0; act && j < M; ++j) {
     for (int t = 0; t < D; ++t) {
       const int k = ktl[(j * D + t) * 64 + lane];
       if (k >= K) continue;
@@ -252,33 +254,37 @@ __device__ __forceinline__ void scd_user(const SweepArgs &a, int M, int K, int L
       }
     }
   }
-  // knapsacks moving several items: in a window pass, keep the greedy set
-  // when it stays optimal at both edges; otherwise walk exactly from above
-  // every breakpoint
-  while (pending) {
-    const int k = __ffsll((long long)pending) - 1;
-    pending &= pending - 1;
+  // Knapsacks moving several items of a user: in a window pass, keep the
+  // greedy set when it stays optimal at both edges; otherwise walk exactly
+  // from above every breakpoint.  The wave's (user, knapsack) pairs are
+  // numbered in lane order and dealt out 64 at a time over all lanes, so a
+  // wave runs about (its pairs) / 64 rounds instead of its busiest lane's
+  // count; a lane works on another lane's user through that user's LDS
+  // column c and the greedy set, positive items and ranks it reads from that
+  // lane's registers.
+  auto walk_pair = [&](const int col, const int k, const uint64_t Sc, const uint64_t posc,
+                       const uint64_t permc) {
     const int mode = kmode[k];
-    const uint64_t A = mskl[k * 64 + lane];
+    const uint64_t A = mskl[k * 64 + col];
     const double lk = lam[k];
     if (mode == KS_WINDOW) {
       const double whi = kst[k].whi, wlo = kst[k].wlo;
       auto line = [&](int j, double &c, double &b) {
-        b = (A >> j & 1) ? bk(j, k) : 0.0;
+        b = (A >> j & 1) ? bkc(j, k, col) : 0.0;
         const double add = lk * b;
-        c = ptl[j * 64 + lane] + add;
+        c = ptl[j * 64 + col] + add;
       };
-      if (window_keeps(S, A, pos & ~S, line, tmask, tcap, L, whi, 1) &&
-          window_keeps(S, A, pos & ~S, line, tmask, tcap, L, wlo, wlo > 0.0 ? -1 : 1))
-        continue;
+      if (window_keeps(Sc, A, posc & ~Sc, line, tmask, tcap, L, whi, 1) &&
+          window_keeps(Sc, A, posc & ~Sc, line, tmask, tcap, L, wlo, wlo > 0.0 ? -1 : 1))
+        return;
     }
     // start: only horizontal positive lines, in p~ order
     uint64_t Sw = 0;
     {
       uint64_t blocked = 0;
-      const uint64_t elig = pos & ~A;
+      const uint64_t elig = posc & ~A;
       for (int r = 0; r < M; ++r) {
-        const int j = (int)((perm >> (4 * r)) & 15);
+        const int j = (int)((permc >> (4 * r)) & 15);
         const uint64_t bit = 1ull << j;
         if ((elig & bit) && !(blocked & bit)) {
           Sw |= bit;
@@ -299,9 +305,9 @@ __device__ __forceinline__ void scd_user(const SweepArgs &a, int M, int K, int L
       while (cand) {
         const int o = __ffsll((long long)cand) - 1;
         cand &= cand - 1;
-        const double bo_d = bk(o, k);
+        const double bo_d = bkc(o, k, col);
         const double add_o = lk * bo_d;
-        const double co = ptl[o * 64 + lane] + add_o;
+        const double co = ptl[o * 64 + col] + add_o;
         uint64_t circ = 0;
         bool tight = false;
         for (int l = 0; l < L; ++l) {
@@ -316,10 +322,10 @@ __device__ __forceinline__ void scd_user(const SweepArgs &a, int M, int K, int L
           while (circ) {
             const int s2 = __ffsll((long long)circ) - 1;
             circ &= circ - 1;
-            const double bs_d = (A >> s2 & 1) ? bk(s2, k) : 0.0;
+            const double bs_d = (A >> s2 & 1) ? bkc(s2, k, col) : 0.0;
             if (bs_d < bo_d) {
               const double add_s = lk * bs_d;
-              const double cs = ptl[s2 * 64 + lane] + add_s;
+              const double cs = ptl[s2 * 64 + col] + add_s;
               const double num = co - cs;
               const double den = bo_d - bs_d;
               if (cr_gt(num, den, best)) { best = num / den; bo = o; bs = s2; }
@@ -328,8 +334,8 @@ __device__ __forceinline__ void scd_user(const SweepArgs &a, int M, int K, int L
         }
       }
       if (bo < 0) break;
-      const double bo_d = bk(bo, k);
-      const double bsv = (bs >= 0 && (A >> bs & 1)) ? bk(bs, k) : 0.0;
+      const double bo_d = bkc(bo, k, col);
+      const double bsv = (bs >= 0 && (A >> bs & 1)) ? bkc(bs, k, col) : 0.0;
       const double v2 = bs >= 0 ? bo_d - bsv : bo_d;
       if (mode == KS_WINDOW) {
         const uint64_t key = dkey(best);
@@ -343,12 +349,44 @@ __device__ __forceinline__ void scd_user(const SweepArgs &a, int M, int K, int L
     }
     if (mode == KS_WINDOW) {
       double now = 0.0;
-      for (uint64_t m = S & A; m; m &= m - 1) now = now + bk(__ffsll((long long)m) - 1, k);
+      for (uint64_t m = Sc & A; m; m &= m - 1) now = now + bkc(__ffsll((long long)m) - 1, k, col);
       if (above != now) {
         xs_atomic_add(&kcorr[k], above);
         xs_atomic_add(&kcorr[k], -now);
       }
     }
+  };
+  // every lane's scratch column is written before any lane reads another's
+  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_wave_barrier();
+  __asm__ volatile("" ::: "memory");
+  const int cnt = __popcll(pending);
+  int incl = cnt;
+  #pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int t = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += t;
+  }
+  const int excl = incl - cnt;
+  const int total = __shfl(incl, 63, 64);
+  for (int base = 0; base < total; base += 64) {
+    const int idx = base + lane;
+    // the pair's owner: the last lane whose first pair is at or before idx
+    int lo = 0, hi = 63;
+    #pragma unroll
+    for (int st = 0; st < 6; ++st) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (__shfl(excl, mid, 64) <= idx) lo = mid;
+      else hi = mid - 1;
+    }
+    uint64_t po = (uint64_t)__shfl((long long)pending, lo, 64);
+    const int nth = idx - __shfl(excl, lo, 64);
+    const uint64_t So = (uint64_t)__shfl((long long)S, lo, 64);
+    const uint64_t poso = (uint64_t)__shfl((long long)pos, lo, 64);
+    const uint64_t permo = (uint64_t)__shfl((long long)perm, lo, 64);
+    if (idx >= total) continue;
+    for (int q = 0; q < nth; ++q) po &= po - 1;
+    walk_pair(lo, __ffsll((long long)po) - 1, So, poso, permo);
   }
 }
 
