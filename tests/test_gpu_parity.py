@@ -391,6 +391,54 @@ def test_dense_lane_evaluation(name, mk):
         assert np.array_equal(l_gpu.cpu().numpy(), l_ref)
 
 
+def _random_case(seed):
+    """A small instance of random shape: N 1..700, M 1..20, K 1..20, dense
+    or CSR (uniform rows declared, or general rows), top-Q or a random
+    laminar family, profits of one of the generator's distributions."""
+    rng = np.random.default_rng(seed)
+    N = int(rng.integers(1, 700))
+    M = int(rng.integers(1, 21))
+    K = int(rng.integers(1, 21))
+    tree = random_laminar(M, rng) if rng.random() < 0.5 else kpgen.tree_topq(M, int(rng.integers(1, M + 1)))
+    fmt = int(rng.integers(0, 3))   # 0 dense, 1 CSR with 1-2 entries per row (declared), 2 general CSR
+    d = int(rng.integers(1, min(K, 2) + 1))
+    inst = kpgen.make_instance(N, M, K, seed=5000 + seed, p_dist=["uniform", "exp1", "lognormal"][seed % 3],
+                               tree=tree, csr_d=0 if fmt == 0 else d, budget_frac=float(rng.uniform(0.05, 0.4)))
+    return inst, fmt, rng
+
+
+@gpu
+@pytest.mark.parametrize("seed", list(range(40)))
+def test_random_shapes_parity(seed):
+    """Random shapes (every kernel path: dense lane-per-user, uniform-row,
+    general dense and CSR): the evaluation (x, R bit-exact; g, P within
+    1e-9) and three SCD iterations from a random point (multipliers
+    bit-exact, windows on) equal the oracle's."""
+    kp, torch = _kp()
+    inst, fmt, rng = _random_case(seed)
+    print("case", seed, inst.N, inst.M, inst.K, fmt, flush=True)
+    if fmt == 2:
+        host = kp.Problem.from_host(inst)
+        prob = kp.Problem(host.p, inst.B, inst.tree.parent, inst.tree.cap, inst.tree.leaf_of_item,
+                          rowptr=host.rowptr, col=host.col, val=host.val, N=inst.N, M=inst.M, K=inst.K,
+                          row_nnz=0)
+    else:
+        prob = kp.Problem.from_host(inst)
+    lam = rng.uniform(0.0, 1.5, inst.K) * (rng.random(inst.K) < 0.8)
+    ctx = kp.Context()
+    ev = kp.kp_eval_dual(prob, _lamd(torch, lam), want_x=True, ctx=ctx)
+    ref = oracle.eval_dual(inst, lam)
+    assert np.array_equal(ev["x"].cpu().numpy(), ref["x"])
+    assert np.array_equal(ev["R"].cpu().numpy(), ref["R"])
+    assert abs(ev["g"].item() - ref["g"]) <= REL * max(1.0, abs(ref["g"]))
+    assert abs(ev["P"].item() - ref["P"]) <= REL * max(1.0, abs(ref["P"]))
+    for t in range(3):
+        want = oracle.scd_sweep(inst, lam)
+        got = kp.kp_scd_sweep(prob, _lamd(torch, lam), ctx=ctx)["lam"].cpu().numpy()
+        assert np.array_equal(got, want), (t, np.flatnonzero(got != want))
+        lam = want
+
+
 @gpu
 @pytest.mark.parametrize("fmt", ["dense", "csr-uniform-rows"])
 def test_empty_instance(fmt):
