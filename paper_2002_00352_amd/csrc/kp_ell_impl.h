@@ -10,9 +10,11 @@
 // greedy), its consumption / profit / dual sums, and for SCD every knapsack's
 // breakpoints: a knapsack moving one item of the user has at most one, at the
 // item's threshold element; knapsacks moving several items of the user are
-// queued and walked exactly once the one-item cases are done, so lanes walk
-// together.  Sums across users are atomic-free (fixed-order wave reductions,
-// waves added in order per block, blocks added in order by a second kernel).
+// queued, and once the one-item cases are done the wave's (user, knapsack)
+// pairs are walked exactly, dealt over all 64 lanes.  R, g and P are summed
+// in a fixed order (per-lane LDS columns, fixed-order row sums, waves added
+// in order per block, blocks added in order by a second kernel); the
+// threshold search's sums are exact two-limb integers (order-free atomics).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>

@@ -11,9 +11,13 @@
 //   phase B2 one thread per (user, knapsack) reduces consumption and, for SCD,
 //            walks the user's consumption step function in lambda_k (the
 //            breakpoints of Alg.3/4) and bins / emits them.
-// Sums across users are atomic-free: per (user,k) values go to LDS and are
-// added in user order, per block into a private slot, and slots are added in
-// block order by a second kernel.
+// R, g and P are summed in a fixed order: per (user,k) values go to LDS and
+// are added in user order, per block into a private slot, and slots are
+// added in block order by a second kernel.  The threshold search's sums
+// (histogram bins, window corrections) are exact two-limb integers added
+// with integer atomics, so their order does not matter.  This file also
+// holds the threshold search's state machine, the post-processing, the
+// batched plan's helpers and the input checks.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
