@@ -507,6 +507,10 @@ FIX_CASES = [
     ("c3-2M-near", lambda: kpgen.config_instance(3, N=2_000_000), [3.1] * 20),
     ("off-grid", _off_grid_fix, [0.1, 0.1, 0.1]),
     ("identical-users", _identical_users_fix, [0.05, 0.05, 0.05]),
+    # many violated knapsacks: one bin and LDS accumulators at 2000 slots,
+    # global-memory accumulators past 48 KB at 4000
+    ("wide-K2000", lambda: random_instance(np.random.default_rng(71), 300, 3, 2000, Q=2, frac=0.02), [1e-5] * 2000),
+    ("wide-K4000", lambda: random_instance(np.random.default_rng(72), 200, 2, 4000, Q=1, frac=0.02), [1e-5] * 4000),
 ]
 
 
