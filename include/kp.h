@@ -266,8 +266,8 @@ kp_status kp_set_tuning(void *ctx, int32_t M, int32_t K, int32_t b_format, int32
                         int32_t grid);
 /* Shape of the last sweep launch made through this context: kernel (0 the
    general kernel, 1 the uniform-row kernel, 2 the lane-per-user evaluation
-   of dense costs, -1 none yet), users per tile and blocks launched.  HOST
-   outputs, each may be NULL. */
+   of dense costs, 3 its SCD window pass, -1 none yet), users per tile and
+   blocks launched.  HOST outputs, each may be NULL. */
 kp_status kp_get_launch_shape(void *ctx, int32_t *kernel, int32_t *users_per_tile, int32_t *grid);
 /* Tuning of batched plans created later on this context: LDS bytes per block
    of the batched launch (instances with long rows take fewer users per tile
@@ -282,7 +282,10 @@ kp_status kp_set_batched_tuning(void *ctx, int32_t lds_bytes, int32_t block_mult
    per-user kernel, which never reads b_rowptr; any other CSR problem runs
    the general kernel.  Evaluations (kp_eval_dual, kp_dd_step, the first
    pass of kp_primal_fixup) of dense costs with M <= 16 and K <= 16 run a
-   lane-per-user kernel (one wave per 64 users, costs staged in LDS).  The
+   lane-per-user kernel (one wave per 48-user tile, costs staged in LDS), and
+   so do the SCD passes of such problems in which every threshold search
+   starts with a window around lambda_k^t (a window around lambda_k^{t-2} of
+   alternating multipliers, or any other search mode: the general kernel).  The
    library keeps no record of a problem's structure between calls: the
    declaration travels with the problem.  kp_set_kernel_choice(ctx, 0)
    forces the general kernel for both (x and R are identical either way; g

@@ -183,7 +183,8 @@ class Context:
 
     def launch_shape(self):
         """(kernel, users per tile, blocks) of the last sweep launch: kernel 0
-        is the general kernel, 1 the uniform-row kernel, -1 none yet."""
+        is the general kernel, 1 the uniform-row kernel, 2 the lane-per-user
+        evaluation of dense costs, 3 its SCD window pass, -1 none yet."""
         k, u, g = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         _check(lib().kp_get_launch_shape(self.h, ctypes.byref(k), ctypes.byref(u), ctypes.byref(g)))
         return k.value, u.value, g.value

@@ -25,7 +25,7 @@ USERS_PER_TILE = (4, 8, 16, 32, 48, 64)
 GRIDS = (512, 1024, 2048, 4096)
 ELL_GRIDS = (128, 256, 512, 768, 1024)          # the uniform-row kernel: grid only
 BATCHED = ((32768, 64), (40960, 32), (40960, 64), (40960, 128), (65536, 64))   # (LDS bytes, block multiple)
-KERNEL_NAMES = {0: "general", 1: "uniform-row", 2: "dense-lane"}
+KERNEL_NAMES = {0: "general", 1: "uniform-row", 2: "dense-lane", 3: "dense-lane window pass"}
 
 
 def cache_path() -> str:

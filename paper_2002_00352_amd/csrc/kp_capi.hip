@@ -57,9 +57,9 @@ size_t kp_fixup_scratch_bytes(int64_t N, int nv, int K);
 size_t kp_ell_lds_bytes(int M, int K, int D, int L, int mode, int *region_out);
 hipError_t kp_launch_ell(const SweepArgs &a, int D, int grid, int mode, hipStream_t stream, int *used);
 int kp_ell_resident_grid(int D, int mode, int M, int K, int L);
-hipError_t kp_launch_dense(const SweepArgs &a, int grid, hipStream_t stream, int *used);
+hipError_t kp_launch_dense(const SweepArgs &a, int grid, hipStream_t stream, int *used, bool win);
 int kp_dense_tile_users();
-int kp_dense_resident_grid(int M, int K, int L);
+int kp_dense_resident_grid(int M, int K, int L, bool win);
 hipError_t kp_launch_count_modes(const KState *st, int K, int *out, hipStream_t stream);
 hipError_t kp_launch_ell_check(const int64_t *rowptr, int64_t nrows, int D, unsigned int *bad,
                                hipStream_t stream);
@@ -258,8 +258,12 @@ struct Prepared {
   // lane-per-user evaluation of dense costs (0 = not used)
   int dense_grid = 0;
   int64_t dense_ntiles = 0;
+  // its SCD window pass (0 = not used)
+  int dwin_grid = 0;
   double ell_bytes = 0.0;
-  int stage_grid() const { return std::max(std::max(grid, grid_nh), std::max(ell_grid, dense_grid)); }
+  int stage_grid() const {
+    return std::max(std::max(std::max(grid, grid_nh), std::max(ell_grid, dense_grid)), dwin_grid);
+  }
 };
 
 kp_status prepare(const kp_problem *p, bool scd, Prepared &out, const Ctx *ctx = nullptr) {
@@ -427,20 +431,22 @@ kp_status choose_kernel(Ctx *c, Prepared &P, bool scd) {
   P.ell_grid = 0;
   P.dense_grid = 0;
   P.dense_ntiles = 0;
-  if (!scd && c->ell_enabled && P.pr.fmt == KP_B_DENSE && P.pr.M <= 16 && P.pr.K <= 16 && P.pr.N > 0) {
+  P.dwin_grid = 0;
+  if (c->ell_enabled && P.pr.fmt == KP_B_DENSE && P.pr.M <= 16 && P.pr.K <= 16 && P.pr.N > 0) {
     // dense costs with few items and knapsacks: the lane-per-user
-    // evaluation, unless a tile size was asked for this shape (the general
+    // evaluation (SCD: its window pass; the other passes run the general
+    // kernel), unless a tile size was asked for this shape (the general
     // kernel's); a grid-only override sets its grid
     auto tit = c->tuning.find(std::make_tuple((int)P.pr.M, (int)P.pr.K, (int)KP_B_DENSE));
     const bool tiles = tit != c->tuning.end() && tit->second.first > 0;
     if (!tiles) {
-      const auto key = std::make_tuple((int)P.pr.M, (int)P.pr.K, (int)P.tree.L);
+      const auto key = std::make_tuple((int)P.pr.M, (int)P.pr.K, (int)P.tree.L * 2 + (scd ? 1 : 0));
       auto it = c->dense_grids.find(key);
       int res = 0;
       if (it != c->dense_grids.end()) {
         res = it->second;
       } else {
-        res = kp_dense_resident_grid(P.pr.M, P.pr.K, P.tree.L);
+        res = kp_dense_resident_grid(P.pr.M, P.pr.K, P.tree.L, scd);
         if (res <= 0) return fail(KP_ERR_HIP, "occupancy query failed");
         c->dense_grids[key] = res;
       }
@@ -448,7 +454,7 @@ kp_status choose_kernel(Ctx *c, Prepared &P, bool scd) {
       P.dense_ntiles = (P.pr.N + tu - 1) / tu;
       int g = (int)std::min<int64_t>(P.dense_ntiles, res);
       if (tit != c->tuning.end() && tit->second.second > 0) g = std::min(tit->second.second, res);
-      P.dense_grid = std::max(1, g);
+      (scd ? P.dwin_grid : P.dense_grid) = std::max(1, g);
     }
     return KP_OK;
   }
@@ -532,7 +538,7 @@ struct SweepWs {
   uint32_t emit_cap;
   unsigned int *flist, *fcount;   // users listed by the window pass
   uint32_t fcap;
-  int *modes;           // [0] knapsacks with a window, [1] with another search mode
+  int *modes;           // [0] knapsacks with a window, [1] with another search mode, [2] alternation windows
   char *stat;           // status block, followed by the histograms (SCD)
   size_t stat_bytes;    // the status block and the histograms
 };
@@ -609,7 +615,7 @@ kp_status carve_ws(Ctx *c, const Prepared &P, bool scd, SweepWs &w) {
   w.stage_cap = scap;
   w.fcap = fcap;
   w.flist = fcap ? (unsigned int *)(b + o_fl) : nullptr;
-  w.fcount = fcap ? (unsigned int *)(b + o_stat + 32) : nullptr;
+  w.fcount = (unsigned int *)(b + o_stat + 32);
   w.modes = scd ? (int *)(b + o_stat + 48) : nullptr;
   return KP_OK;
 }
@@ -643,7 +649,7 @@ double algo_bytes(const Prepared &P) {
 // One sweep pass between timing events.  split: the window pass of the
 // uniform-row kernel as two launches (all users, then the listed ones).
 hipError_t timed_sweep(Ctx *c, const SweepArgs &a, const Prepared &P, bool scd, double bytes,
-                       bool split = false) {
+                       bool split = false, bool dwin = false) {
   // a.no_hist: the general kernel's tiles and grid without histograms
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (c->timing && P.ell_D) {
@@ -685,7 +691,11 @@ hipError_t timed_sweep(Ctx *c, const SweepArgs &a, const Prepared &P, bool scd, 
   } else if (P.dense_grid && !scd) {
     SweepArgs ae = a;
     ae.ntiles = P.dense_ntiles;
-    err = kp_launch_dense(ae, P.dense_grid, c->stream, &c->stats_grid);
+    err = kp_launch_dense(ae, P.dense_grid, c->stream, &c->stats_grid, false);
+  } else if (dwin) {
+    SweepArgs ae = a;
+    ae.ntiles = P.dense_ntiles;
+    err = kp_launch_dense(ae, P.dwin_grid, c->stream, &c->stats_grid, true);
   } else {
     err = a.no_hist ? kp_launch_sweep(a, P.U_nh, P.grid_nh, scd, c->stream, &c->stats_grid)
                     : kp_launch_sweep(a, P.U, P.grid, scd, c->stream, &c->stats_grid);
@@ -699,8 +709,8 @@ hipError_t timed_sweep(Ctx *c, const SweepArgs &a, const Prepared &P, bool scd, 
   }
   if (err == hipSuccess) {
     const bool dense = !P.ell_D && P.dense_grid && !scd;
-    c->last_kernel = P.ell_D ? 1 : (dense ? 2 : 0);
-    c->last_U = P.ell_D ? 64 : dense ? kp_dense_tile_users() : (a.no_hist ? P.U_nh : P.U);
+    c->last_kernel = P.ell_D ? 1 : dense ? 2 : dwin ? 3 : 0;
+    c->last_U = P.ell_D ? 64 : (dense || dwin) ? kp_dense_tile_users() : (a.no_hist ? P.U_nh : P.U);
     c->last_grid = c->stats_grid;
   }
   return err;
@@ -1054,17 +1064,21 @@ kp_status kp_scd_sweep_masked_impl(Ctx *c, const kp_problem *prob, const double 
   // knapsack still searching starts with a window
   // (uniform-row kernel); the general kernel runs such a pass without the
   // histograms of the other search modes
-  bool split = false, nohist = false;
+  bool split = false, nohist = false, dwin = false;
   const bool nh_gain = !P.ell_D && (P.U_nh != P.U || P.grid_nh != P.grid);
   const bool sample = c->sample_min > 0 && P.pr.N >= c->sample_min && !c->interp;
-  const bool counts = window && c->delta_valid && (w.fcap || nh_gain);
+  const bool counts = window && c->delta_valid && (w.fcap || nh_gain || P.dwin_grid);
   if (counts || sample) {
     HIP_TRY(kp_launch_count_modes(w.st, K, w.modes, c->stream));
-    HIP_TRY(hipMemcpyAsync(c->pinned + 20, w.modes, 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->pinned + 20, w.modes, 12, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     if (counts) {
       split = w.fcap && c->pinned[20] > 0 && c->pinned[21] == 0;
       nohist = nh_gain && c->pinned[21] == 0;
+      // dense costs: the lane-per-user window pass, when every window is
+      // centred on lambda^t (alternation windows away from it: the general
+      // kernel, whose per-(user, knapsack) tests stop early)
+      dwin = P.dwin_grid && c->pinned[21] == 0 && c->pinned[22] == 0;
     }
     // full searches (knapsacks without a window) start from a sample
     if (sample && c->pinned[21] > 0) {
@@ -1086,7 +1100,7 @@ kp_status kp_scd_sweep_masked_impl(Ctx *c, const kp_problem *prob, const double 
         a.no_hist = 1;
         a.ntiles = P.ntiles_nh;
       }
-      HIP_TRY(timed_sweep(c, a, P, true, P.bytes, split && pass == 0));
+      HIP_TRY(timed_sweep(c, a, P, true, P.bytes, split && pass == 0, dwin && pass == 0));
     }
     if (pass == 0) {
       if (P.pr.N > 0) {
@@ -1110,7 +1124,7 @@ kp_status kp_scd_sweep_masked_impl(Ctx *c, const kp_problem *prob, const double 
       c->win_below += (unsigned)st[6];
       c->win_emitted += (unsigned)st[7];
     }
-    if (pass == 0 && split) c->win_listed += (unsigned)st[9];
+    if (pass == 0 && (split || dwin)) c->win_listed += (unsigned)st[9];
     if (*(unsigned long long *)(st + 2))
       return fail(KP_ERR_INTERNAL, "breakpoint walk exceeded its event limit");
     if (st[0] == 0) break;

@@ -1,5 +1,6 @@
 // Lane-per-user evaluation of dense costs with few items and knapsacks
-// (M <= 16, K <= 16): the dual evaluation of Eq.5 with Alg.1 per user.
+// (M <= 16, K <= 16): the dual evaluation of Eq.5 with Alg.1 per user, and
+// the SCD window pass built on it.
 //
 // One wave owns a tile of 48 users at a time, one lane per user, and a block
 // is one wave, so blocks pack as tightly as the LDS of one tile allows.  The
@@ -13,6 +14,15 @@
 // (registers, tile after tile); the wave sums them in a fixed butterfly
 // order once, at the end, and a second kernel adds the blocks in order.  No
 // barrier or cross-lane step inside the tile loop.
+//
+// The SCD window pass (Sec. 5.2's threshold search, every open search with a
+// window around lambda_k^t) adds to the evaluation, per lane and per window
+// knapsack, a gap test: the user has no breakpoint in the window when every
+// line moving with k is farther than h_k b_jk (plus a rounding margin) from
+// its rank neighbours and from zero.  The (user, knapsack) pairs it leaves
+// open are dealt over the wave and walked exactly through the owner's LDS
+// column (the uniform-row kernel's walk); breakpoints inside the window are
+// staged per block and corrections C_ik(whi+) - v_ik added exactly.
 #include <type_traits>
 #include "kp_ell_impl.h"
 
@@ -30,34 +40,88 @@ static_assert(TU % 4 == 0 && TU <= 64, "users per tile: a multiple of 4, at most
 
 __host__ __device__ inline size_t dn_r16(size_t b) { return (b + 15) & ~(size_t)15; }
 
-// LDS of one block: lambda [K], the sets' masks and caps, one tile
-__host__ __device__ inline size_t dn_lds(int M, int K, int L) {
-  return dn_r16((size_t)K * 8) + dn_r16((size_t)L * 8 + 8) + dn_r16((size_t)L * 4 + 4) +
-         dn_r16((size_t)TU * M * 4) + (size_t)TU * M * K * 4;
+// LDS of one block: lambda [K], the sets' masks and caps, one tile; the
+// window pass adds the search states, its per-block event staging counters
+// and corrections, and the lanes' p~ columns [M][64] read by the walks.
+__host__ __device__ inline size_t dn_lds(int M, int K, int L, bool win) {
+  size_t s = dn_r16((size_t)K * 8) + dn_r16((size_t)L * 8 + 8) + dn_r16((size_t)L * 4 + 4) +
+             dn_r16((size_t)TU * M * 4) + dn_r16((size_t)TU * M * K * 4);
+  if (win)
+    s += dn_r16((size_t)K * sizeof(KState)) + dn_r16((size_t)K * 4) + dn_r16((size_t)(K + 1) * 8) +
+         dn_r16((size_t)K * sizeof(XSum)) + 3 * dn_r16((size_t)K * 4) + 2 * dn_r16((size_t)K * 8) + dn_r16(16) +
+         (size_t)M * 64 * 8;
+  return s;
 }
 
 // EM: the item-count class (8, 10, 12, 16), M <= EM; EK: 16, the bound of
 // the knapsack count (the per-lane sums; the scoring loops run to K).
 // (Unrolling the scoring over a compile-time knapsack class, lambda in
 // registers, measured slower: 1.30 against 1.19 ms on c2.)
-template <int EM, int EK>
-__global__ void __launch_bounds__(64) k_dense_eval(const SweepArgs a, int x4) {
+// WIN: the SCD window pass (every knapsack still searching has a window
+// around lambda_k^t, Sec. 5.2's threshold search started around its last
+// value): after the evaluation, every lane tests its user per window
+// knapsack -- calm when every moving item's line is farther than h_k b_jk
+// from its rank neighbours and from zero -- and the (user, knapsack) pairs
+// left undecided are dealt over the wave and walked exactly (lane_walk_pair).
+// EXACT: M equals EM, so every test of an item index against M folds away.
+template <int EM, int EK, bool WIN, bool EXACT>
+__global__ void __launch_bounds__(64) k_dense(const SweepArgs a, int x4) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = threadIdx.x;
-  const int M = a.pr.M, K = a.pr.K, L = a.tree.L;
-  double *lam = (double *)smem;
-  uint64_t *tmask = (uint64_t *)(smem + dn_r16((size_t)K * 8));
-  int *tcap = (int *)((unsigned char *)tmask + dn_r16((size_t)L * 8 + 8));
-  float *sp = (float *)((unsigned char *)tcap + dn_r16((size_t)L * 4 + 4));   // [TU][M]
-  float *sb = (float *)((unsigned char *)sp + dn_r16((size_t)TU * M * 4));    // [TU][M][K]
+  const int M = EXACT ? EM : a.pr.M, K = a.pr.K, L = a.tree.L;
+  size_t off = 0;
+  auto carve = [&](size_t bytes) { unsigned char *p = smem + off; off += dn_r16(bytes); return p; };
+  double *lam = (double *)carve((size_t)K * 8);
+  uint64_t *tmask = (uint64_t *)carve((size_t)L * 8 + 8);
+  int *tcap = (int *)carve((size_t)L * 4 + 4);
+  float *sp = (float *)carve((size_t)TU * M * 4);       // [TU][M]
+  float *sb = (float *)carve((size_t)TU * M * K * 4);   // [TU][M][K]
+  KState *kst = nullptr;
+  int *kmode = nullptr;
+  double *hwin = nullptr;
+  XSum *kcorr = nullptr;
+  uint32_t *kcnt = nullptr, *kpos = nullptr, *kovf = nullptr, *nstage = nullptr;
+  unsigned long long *hmin = nullptr, *hmax = nullptr;
+  double *ptl = nullptr;
+  if (WIN) {
+    kst = (KState *)carve((size_t)K * sizeof(KState));
+    kmode = (int *)carve((size_t)K * 4);
+    hwin = (double *)carve((size_t)(K + 1) * 8);   // [K] window half-widths (0: none), [K] their max
+    kcorr = (XSum *)carve((size_t)K * sizeof(XSum));
+    kcnt = (uint32_t *)carve((size_t)K * 4);
+    kpos = (uint32_t *)carve((size_t)K * 4);
+    kovf = (uint32_t *)carve((size_t)K * 4);
+    hmin = (unsigned long long *)carve((size_t)K * 8);
+    hmax = (unsigned long long *)carve((size_t)K * 8);
+    nstage = (uint32_t *)carve(16);
+    ptl = (double *)carve((size_t)M * 64 * 8);
+  }
   for (int t = lane; t < K; t += 64) lam[t] = a.lam[t];
   for (int t = lane; t < L; t += 64) { tmask[t] = a.tree.mask[t]; tcap[t] = a.tree.cap[t]; }
+  if (WIN) {
+    for (int t = lane; t < K; t += 64) {
+      kst[t] = a.st[t];
+      kmode[t] = a.st[t].mode;
+      hwin[t] = a.st[t].mode == KS_WINDOW ? a.st[t].hw : 0.0;
+      kcorr[t] = xs_zero();
+      kcnt[t] = 0u; kpos[t] = 0u; kovf[t] = 0u;
+      hmin[t] = ~0ull; hmax[t] = 0ull;
+    }
+    if (lane == 0) *nstage = 0u;
+  }
+  __syncthreads();
+  if (WIN && lane == 0) {
+    double m = 0.0;
+    for (int k = 0; k < K; ++k) m = hwin[k] > m ? hwin[k] : m;
+    hwin[K] = m;
+  }
   __syncthreads();
   const int64_t N = a.pr.N;
   double accR[EK];   // this lane's users: consumption of knapsack q (q < K)
   #pragma unroll
   for (int q = 0; q < EK; ++q) accR[q] = 0.0;
   double accG = 0.0, accP = 0.0;
+  uint32_t nwalk = 0;   // window pass: users of this wave with a pair to walk
   for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
     const int64_t u0 = tile * TU;
     const int nu = (int)((N - u0) < TU ? (N - u0) : TU);
@@ -83,8 +147,9 @@ __global__ void __launch_bounds__(64) k_dense_eval(const SweepArgs a, int x4) {
     const int row = lane < TU ? lane : 0;
     const float *pl = sp + row * M;
     const float *bl = sb + (size_t)row * M * K;
-    // ---- cost-adjusted profits ----
+    // ---- cost-adjusted profits (window pass: and the largest cost) ----
     double pt[EM];
+    float bm = 0.0f;
     #pragma unroll
     for (int j = 0; j < EM; ++j) {
       double acc = 0.0;
@@ -92,7 +157,9 @@ __global__ void __launch_bounds__(64) k_dense_eval(const SweepArgs a, int x4) {
         acc = (double)pl[j];
         const float *br = bl + j * K;
         for (int k = 0; k < K; ++k) {
-          const double prod = lam[k] * (double)br[k];
+          const float bv = br[k];
+          if (WIN) bm = fmaxf(bm, bv);
+          const double prod = lam[k] * (double)bv;
           acc = acc - prod;
         }
       }
@@ -157,6 +224,88 @@ __global__ void __launch_bounds__(64) k_dense_eval(const SweepArgs a, int x4) {
         }
       }
     }
+    if (WIN) {
+      // ---- window tests per knapsack ----
+      uint64_t pending = 0, perm = 0, pos = 0;
+      #pragma unroll
+      for (int j = 0; j < EM; ++j) {
+        if (j < M) {
+          ptl[j * 64 + lane] = pt[j];
+          perm |= (uint64_t)j << (4 * rk[j]);
+          if (pt[j] > 0.0) pos |= 1ull << j;
+        }
+      }
+      if (!act) pos = 0;
+      if (act) {
+        // lines below -H (H: the widest window times the user's largest
+        // cost) never turn positive in any window; gj: the distance from
+        // item j's line to the nearest other line above -H and to zero (its
+        // rank neighbours are the nearest lines)
+        const double bmax = (double)bm, hm = hwin[K];
+        const double H = hm * bmax * (1.0 + 0x1p-30) + 0x1p-36 * (1.0 + bmax * hm);
+        double top = -INFINITY;
+        #pragma unroll
+        for (int j = 0; j < EM; ++j)
+          if (j < M) top = fmax(top, pt[j]);
+        const double gscale = fabs(top) + H;
+        // (lines at or below -H are moved to -inf: no finite distance to them)
+        double gj[EM], pu[EM];
+        #pragma unroll
+        for (int j = 0; j < EM; ++j) {
+          pu[j] = (j < M && pt[j] > -H) ? pt[j] : -INFINITY;
+          gj[j] = pu[j] > -INFINITY ? fabs(pt[j]) : 1e300;
+        }
+        #pragma unroll
+        for (int j = 0; j < EM; ++j) {
+          #pragma unroll
+          for (int jj = j + 1; jj < EM; ++jj) {
+            const double d = fabs(pu[j] - pu[jj]);   // inf or NaN (-inf - -inf) unless both are lines
+            gj[j] = d < gj[j] ? d : gj[j];
+            gj[jj] = d < gj[jj] ? d : gj[jj];
+          }
+        }
+        for (int k = 0; k < K; ++k) {
+          if (kmode[k] != KS_WINDOW) continue;
+          float bk[EM];
+          uint32_t A = 0;
+          #pragma unroll
+          for (int j = 0; j < EM; ++j) {
+            bk[j] = j < M ? bl[j * K + k] : 0.0f;
+            if (bk[j] > 0.0f) A |= 1u << j;
+          }
+          if (!A) continue;   // no moving line: no breakpoint, no consumption
+          // every moving item's line must stay farther than h_k b_jk (plus a
+          // rounding margin) from its neighbours and from zero (h_k: the
+          // distance from lambda_k^t to the window's far edge)
+          const double lk = lam[k], h = hwin[k];
+          bool calm = true;
+          #pragma unroll
+          for (int j = 0; j < EM; ++j) {
+            if (A >> j & 1) {
+              const double b = (double)bk[j];
+              const double need = h * b * (1.0 + 0x1p-30) + 0x1p-36 * (1.0 + gscale + lk * b + h * b);
+              calm = calm & (gj[j] > need);
+            }
+          }
+          if (calm) continue;
+          pending |= 1ull << k;
+        }
+      }
+      nwalk += (uint32_t)__popcll(__ballot(pending != 0));
+      __builtin_amdgcn_s_waitcnt(0);   // every lane's p~ column is written before any lane reads another's
+      __builtin_amdgcn_wave_barrier();
+      __asm__ volatile("" ::: "memory");
+      lane_deal_pairs(lane, pending, (uint64_t)S, pos, perm,
+                      [&](int col, int k, uint64_t So, uint64_t poso, uint64_t permo) {
+        const float *bc = sb + (size_t)col * M * K + k;   // lane col's costs in k, stride K
+        uint64_t A = 0;
+        for (int j = 0; j < M; ++j)
+          if (bc[j * K] > 0.0f) A |= 1ull << j;
+        lane_walk_pair(a, M, L, col, k, A, So, poso, permo,
+                       [&](int j, int cc) { return (double)sb[((size_t)cc * M + j) * K + k]; }, ptl, lam, kst,
+                       kmode, tmask, tcap, kcorr, nullptr, nullptr, hmin, hmax, kcnt, kovf, nstage);
+      });
+    }
   }
   if (a.want_stats) {
     double mine = 0.0;   // lane q < K + 2: column q of the block
@@ -173,11 +322,16 @@ __global__ void __launch_bounds__(64) k_dense_eval(const SweepArgs a, int x4) {
     if (lane == K + 1) mine = sq;
     if (lane < K + 2) a.partials[(size_t)blockIdx.x * (K + 2) + lane] = mine;
   }
+  if (WIN) {
+    if (lane == 0 && nwalk && a.fcount) atomicAdd(a.fcount + 1, nwalk);
+    __syncthreads();
+    publish_block(a, K, nullptr, nullptr, hmin, hmax, kcnt, kpos, kovf, nstage, lane, 64, blockIdx.x, kcorr);
+  }
 }
 
-template <int EM, int EK>
+template <int EM, int EK, bool WIN, bool EXACT>
 hipError_t launch_dense_t(const SweepArgs &a, size_t lds, int grid, int x4, hipStream_t stream, int *used) {
-  const void *fn = (const void *)k_dense_eval<EM, EK>;
+  const void *fn = (const void *)k_dense<EM, EK, WIN, EXACT>;
   if (lds > 64 * 1024) {
     const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -190,13 +344,13 @@ hipError_t launch_dense_t(const SweepArgs &a, size_t lds, int grid, int x4, hipS
   const int resident = per_cu * cus;
   if (grid <= 0 || grid > resident) grid = resident;
   if (used) *used = grid;
-  hipLaunchKernelGGL((k_dense_eval<EM, EK>), dim3(grid), dim3(64), lds, stream, a, x4);
+  hipLaunchKernelGGL((k_dense<EM, EK, WIN, EXACT>), dim3(grid), dim3(64), lds, stream, a, x4);
   return hipGetLastError();
 }
 
-template <int EM, int EK>
+template <int EM, int EK, bool WIN, bool EXACT>
 int resident_dense_t(size_t lds) {
-  const void *fn = (const void *)k_dense_eval<EM, EK>;
+  const void *fn = (const void *)k_dense<EM, EK, WIN, EXACT>;
   if (lds > 64 * 1024 &&
       hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return 0;
@@ -227,25 +381,36 @@ auto dispatch_dense(int M, int K, F f) {
 int kp_dense_tile_users() { return TU; }
 
 // Evaluation (statistics into a.partials [grid][K + 2] and/or x) over
-// a.ntiles tiles of kp_dense_tile_users() users.  grid: an upper bound (the size of the
-// per-block buffers); *used receives the blocks launched (at most the
-// resident ones).
-hipError_t kp_launch_dense(const SweepArgs &a, int grid, hipStream_t stream, int *used) {
+// a.ntiles tiles of kp_dense_tile_users() users; win: the SCD window pass
+// (a.st: every knapsack in KS_WINDOW or finished; events staged per block
+// into a.stage_*, window corrections into a.st[k].corr, users with a pair
+// to walk counted into a.fcount[1] when a.fcount is set).  grid: an upper
+// bound (the size of the per-block buffers); *used receives the blocks
+// launched (at most the resident ones).
+hipError_t kp_launch_dense(const SweepArgs &a, int grid, hipStream_t stream, int *used, bool win) {
   const int M = a.pr.M, K = a.pr.K;
   if (a.pr.fmt != 0 || M < 1 || M > 16 || K < 1 || K > 16 || a.tree.L < 0) return hipErrorInvalidValue;
-  const size_t lds = dn_lds(M, K, a.tree.L);
+  if (win && (!a.st || !a.err || !a.stage_v1 || a.stage_cap == 0)) return hipErrorInvalidValue;
+  const size_t lds = dn_lds(M, K, a.tree.L, win);
   const int x4 = (((uintptr_t)a.pr.p | (uintptr_t)a.pr.b) & 15) == 0;
   return dispatch_dense(M, K, [&](auto em, auto ek) {
-    return launch_dense_t<decltype(em)::value, decltype(ek)::value>(a, lds, grid, x4, stream, used);
+    constexpr int EM = decltype(em)::value, EK = decltype(ek)::value;
+    if (M == EM)
+      return win ? launch_dense_t<EM, EK, true, true>(a, lds, grid, x4, stream, used)
+                 : launch_dense_t<EM, EK, false, true>(a, lds, grid, x4, stream, used);
+    return win ? launch_dense_t<EM, EK, true, false>(a, lds, grid, x4, stream, used)
+               : launch_dense_t<EM, EK, false, false>(a, lds, grid, x4, stream, used);
   });
 }
 
-// Blocks of the dense evaluation that can be resident at once; 0 when the
-// shape is outside the kernel's range or the query fails.
-int kp_dense_resident_grid(int M, int K, int L) {
+// Blocks of the dense evaluation (win: the window pass) that can be resident
+// at once; 0 when the shape is outside the kernel's range or the query fails.
+int kp_dense_resident_grid(int M, int K, int L, bool win) {
   if (M < 1 || M > 16 || K < 1 || K > 16) return 0;
-  const size_t lds = dn_lds(M, K, L);
+  const size_t lds = dn_lds(M, K, L, win);
   return dispatch_dense(M, K, [&](auto em, auto ek) {
-    return resident_dense_t<decltype(em)::value, decltype(ek)::value>(lds);
+    constexpr int EM = decltype(em)::value, EK = decltype(ek)::value;
+    if (M == EM) return win ? resident_dense_t<EM, EK, true, true>(lds) : resident_dense_t<EM, EK, false, true>(lds);
+    return win ? resident_dense_t<EM, EK, true, false>(lds) : resident_dense_t<EM, EK, false, false>(lds);
   });
 }

@@ -87,6 +87,158 @@ struct EllGeom {
   int waves;          // waves per block of the launch
 };
 
+// One (user, knapsack) pair of a lane-per-user breakpoint phase, run by
+// any lane of the wave for the user of lane col.  In a window pass the
+// user's greedy set at lambda^t is kept when it stays optimal at both edges
+// of the window; otherwise the pair is walked exactly from above every
+// breakpoint: the next breakpoint below is the highest crossing of an item
+// outside the current set with zero (a free item) or with a member of the
+// innermost full set holding it (Alg.1's exchange), fma-residual comparisons
+// deciding which is highest.  Breakpoints inside the window are emitted
+// (other search modes: binned or emitted by record_event), those above it
+// add up to C_ik(whi+), and C_ik(whi+) - v_ik goes into the window
+// correction.  A: the items moving with k; bkc(j, c): the cost in k of item
+// j of lane c's user (j in A); ptl: the lanes' p~ columns [M][64]; Sc, posc,
+// permc: the user's greedy set, positive items and rank order.
+template <class BKC>
+__device__ __forceinline__ void lane_walk_pair(const SweepArgs &a, int M, int L, int col, int k, uint64_t A,
+                                               uint64_t Sc, uint64_t posc, uint64_t permc, BKC bkc,
+                                               const double *ptl, const double *lam, const KState *kst,
+                                               const int *kmode, const uint64_t *tmask, const int *tcap,
+                                               XSum *kcorr, XSum *hs, uint32_t *hc, unsigned long long *hmin,
+                                               unsigned long long *hmax, uint32_t *kcnt, uint32_t *kovf,
+                                               uint32_t *nstage) {
+  const int mode = kmode[k];
+  const double lk = lam[k];
+  if (mode == KS_WINDOW) {
+    const double whi = kst[k].whi, wlo = kst[k].wlo;
+    auto line = [&](int j, double &c, double &b) {
+      b = (A >> j & 1) ? bkc(j, col) : 0.0;
+      const double add = lk * b;
+      c = ptl[j * 64 + col] + add;
+    };
+    if (window_keeps(Sc, A, posc & ~Sc, line, tmask, tcap, L, whi, 1) &&
+        window_keeps(Sc, A, posc & ~Sc, line, tmask, tcap, L, wlo, wlo > 0.0 ? -1 : 1))
+      return;
+  }
+  // start: only horizontal positive lines, in p~ order
+  uint64_t Sw = 0;
+  {
+    uint64_t blocked = 0;
+    const uint64_t elig = posc & ~A;
+    for (int r = 0; r < M; ++r) {
+      const int j = (int)((permc >> (4 * r)) & 15);
+      const uint64_t bit = 1ull << j;
+      if ((elig & bit) && !(blocked & bit)) {
+        Sw |= bit;
+        for (int l = 0; l < L; ++l) {
+          const uint64_t m = tmask[l];
+          if ((m & bit) && popc64(Sw & m) >= tcap[l]) blocked |= m;
+        }
+      }
+    }
+  }
+  double above = 0.0;
+  const int maxev = M * M + M + 8;
+  for (int ev = 0;; ++ev) {
+    if (ev >= maxev) { atomicAdd(a.err, 1ull); break; }
+    double best = 0.0;
+    int bo = -1, bs = -1;
+    uint64_t cand = A & ~Sw;
+    while (cand) {
+      const int o = __ffsll((long long)cand) - 1;
+      cand &= cand - 1;
+      const double bo_d = bkc(o, col);
+      const double add_o = lk * bo_d;
+      const double co = ptl[o * 64 + col] + add_o;
+      uint64_t circ = 0;
+      bool tight = false;
+      for (int l = 0; l < L; ++l) {
+        const uint64_t m = tmask[l];
+        if ((m >> o & 1) && popc64(Sw & m) >= tcap[l]) { circ = Sw & m; tight = true; break; }
+      }
+      // compared with the running maximum through cr_gt: a division only
+      // for a crossing that beats it
+      if (!tight) {
+        if (co > 0.0 && cr_gt(co, bo_d, best)) { best = co / bo_d; bo = o; bs = -1; }
+      } else {
+        while (circ) {
+          const int s2 = __ffsll((long long)circ) - 1;
+          circ &= circ - 1;
+          const double bs_d = (A >> s2 & 1) ? bkc(s2, col) : 0.0;
+          if (bs_d < bo_d) {
+            const double add_s = lk * bs_d;
+            const double cs = ptl[s2 * 64 + col] + add_s;
+            const double num = co - cs;
+            const double den = bo_d - bs_d;
+            if (cr_gt(num, den, best)) { best = num / den; bo = o; bs = s2; }
+          }
+        }
+      }
+    }
+    if (bo < 0) break;
+    const double bo_d = bkc(bo, col);
+    const double bsv = (bs >= 0 && (A >> bs & 1)) ? bkc(bs, col) : 0.0;
+    const double v2 = bs >= 0 ? bo_d - bsv : bo_d;
+    if (mode == KS_WINDOW) {
+      const uint64_t key = dkey(best);
+      if (key < kst[k].klo) break;          // every later breakpoint is lower
+      if (key > kst[k].khi) above = above + v2;
+      else record_event(a, kst[k], k, best, v2, mode, hs, hc, hmin, hmax, kcnt, kovf, nstage, blockIdx.x);
+    } else {
+      record_event(a, kst[k], k, best, v2, mode, hs, hc, hmin, hmax, kcnt, kovf, nstage, blockIdx.x);
+    }
+    Sw = (Sw | (1ull << bo)) & ~(bs >= 0 ? (1ull << bs) : 0ull);
+  }
+  if (mode == KS_WINDOW) {
+    double now = 0.0;
+    for (uint64_t m = Sc & A; m; m &= m - 1) now = now + bkc(__ffsll((long long)m) - 1, col);
+    if (above != now) {
+      xs_atomic_add(&kcorr[k], above);
+      xs_atomic_add(&kcorr[k], -now);
+    }
+  }
+}
+
+// The wave's (user, knapsack) pairs (bit k of a lane's `pending`) are
+// numbered in lane order and dealt out 64 at a time over all lanes, so a
+// wave runs about (its pairs) / 64 rounds instead of its busiest lane's
+// count; walk(col, k, S, pos, perm) works on lane col's user with the greedy
+// set, positive items and ranks read from that lane's registers.  Every lane
+// of the wave calls this.
+template <class W>
+__device__ __forceinline__ void lane_deal_pairs(int lane, uint64_t pending, uint64_t S, uint64_t pos,
+                                                uint64_t perm, W walk) {
+  const int cnt = __popcll(pending);
+  int incl = cnt;
+  #pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int t = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += t;
+  }
+  const int excl = incl - cnt;
+  const int total = __shfl(incl, 63, 64);
+  for (int base = 0; base < total; base += 64) {
+    const int idx = base + lane;
+    // the pair's owner: the last lane whose first pair is at or before idx
+    int lo = 0, hi = 63;
+    #pragma unroll
+    for (int st = 0; st < 6; ++st) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (__shfl(excl, mid, 64) <= idx) lo = mid;
+      else hi = mid - 1;
+    }
+    uint64_t po = (uint64_t)__shfl((long long)pending, lo, 64);
+    const int nth = idx - __shfl(excl, lo, 64);
+    const uint64_t So = (uint64_t)__shfl((long long)S, lo, 64);
+    const uint64_t poso = (uint64_t)__shfl((long long)pos, lo, 64);
+    const uint64_t permo = (uint64_t)__shfl((long long)perm, lo, 64);
+    if (idx >= total) continue;
+    for (int q = 0; q < nth; ++q) po &= po - 1;
+    walk(lo, __ffsll((long long)po) - 1, So, poso, permo);
+  }
+}
+
 // Breakpoint phase of one user (one lane) from its per-lane LDS scratch:
 // p~ (ptl), stored costs (btl) and their knapsacks (ktl), and the items
 // moving with each knapsack (mskl).  S is the greedy set at lambda^t, pos the
@@ -256,140 +408,16 @@ __device__ __forceinline__ void scd_user(const SweepArgs &a, int M, int K, int L
       }
     }
   }
-  // Knapsacks moving several items of a user: in a window pass, keep the
-  // greedy set when it stays optimal at both edges; otherwise walk exactly
-  // from above every breakpoint.  The wave's (user, knapsack) pairs are
-  // numbered in lane order and dealt out 64 at a time over all lanes, so a
-  // wave runs about (its pairs) / 64 rounds instead of its busiest lane's
-  // count; a lane works on another lane's user through that user's LDS
-  // column c and the greedy set, positive items and ranks it reads from that
-  // lane's registers.
-  auto walk_pair = [&](const int col, const int k, const uint64_t Sc, const uint64_t posc,
-                       const uint64_t permc) {
-    const int mode = kmode[k];
-    const uint64_t A = mskl[k * 64 + col];
-    const double lk = lam[k];
-    if (mode == KS_WINDOW) {
-      const double whi = kst[k].whi, wlo = kst[k].wlo;
-      auto line = [&](int j, double &c, double &b) {
-        b = (A >> j & 1) ? bkc(j, k, col) : 0.0;
-        const double add = lk * b;
-        c = ptl[j * 64 + col] + add;
-      };
-      if (window_keeps(Sc, A, posc & ~Sc, line, tmask, tcap, L, whi, 1) &&
-          window_keeps(Sc, A, posc & ~Sc, line, tmask, tcap, L, wlo, wlo > 0.0 ? -1 : 1))
-        return;
-    }
-    // start: only horizontal positive lines, in p~ order
-    uint64_t Sw = 0;
-    {
-      uint64_t blocked = 0;
-      const uint64_t elig = posc & ~A;
-      for (int r = 0; r < M; ++r) {
-        const int j = (int)((permc >> (4 * r)) & 15);
-        const uint64_t bit = 1ull << j;
-        if ((elig & bit) && !(blocked & bit)) {
-          Sw |= bit;
-          for (int l = 0; l < L; ++l) {
-            const uint64_t m = tmask[l];
-            if ((m & bit) && popc64(Sw & m) >= tcap[l]) blocked |= m;
-          }
-        }
-      }
-    }
-    double above = 0.0;
-    const int maxev = M * M + M + 8;
-    for (int ev = 0;; ++ev) {
-      if (ev >= maxev) { atomicAdd(a.err, 1ull); break; }
-      double best = 0.0;
-      int bo = -1, bs = -1;
-      uint64_t cand = A & ~Sw;
-      while (cand) {
-        const int o = __ffsll((long long)cand) - 1;
-        cand &= cand - 1;
-        const double bo_d = bkc(o, k, col);
-        const double add_o = lk * bo_d;
-        const double co = ptl[o * 64 + col] + add_o;
-        uint64_t circ = 0;
-        bool tight = false;
-        for (int l = 0; l < L; ++l) {
-          const uint64_t m = tmask[l];
-          if ((m >> o & 1) && popc64(Sw & m) >= tcap[l]) { circ = Sw & m; tight = true; break; }
-        }
-        // compared with the running maximum through cr_gt: a division only
-        // for a crossing that beats it
-        if (!tight) {
-          if (co > 0.0 && cr_gt(co, bo_d, best)) { best = co / bo_d; bo = o; bs = -1; }
-        } else {
-          while (circ) {
-            const int s2 = __ffsll((long long)circ) - 1;
-            circ &= circ - 1;
-            const double bs_d = (A >> s2 & 1) ? bkc(s2, k, col) : 0.0;
-            if (bs_d < bo_d) {
-              const double add_s = lk * bs_d;
-              const double cs = ptl[s2 * 64 + col] + add_s;
-              const double num = co - cs;
-              const double den = bo_d - bs_d;
-              if (cr_gt(num, den, best)) { best = num / den; bo = o; bs = s2; }
-            }
-          }
-        }
-      }
-      if (bo < 0) break;
-      const double bo_d = bkc(bo, k, col);
-      const double bsv = (bs >= 0 && (A >> bs & 1)) ? bkc(bs, k, col) : 0.0;
-      const double v2 = bs >= 0 ? bo_d - bsv : bo_d;
-      if (mode == KS_WINDOW) {
-        const uint64_t key = dkey(best);
-        if (key < kst[k].klo) break;          // every later breakpoint is lower
-        if (key > kst[k].khi) above = above + v2;
-        else record_event(a, kst[k], k, best, v2, mode, hs, hc, hmin, hmax, kcnt, kovf, nstage, blockIdx.x);
-      } else {
-        record_event(a, kst[k], k, best, v2, mode, hs, hc, hmin, hmax, kcnt, kovf, nstage, blockIdx.x);
-      }
-      Sw = (Sw | (1ull << bo)) & ~(bs >= 0 ? (1ull << bs) : 0ull);
-    }
-    if (mode == KS_WINDOW) {
-      double now = 0.0;
-      for (uint64_t m = Sc & A; m; m &= m - 1) now = now + bkc(__ffsll((long long)m) - 1, k, col);
-      if (above != now) {
-        xs_atomic_add(&kcorr[k], above);
-        xs_atomic_add(&kcorr[k], -now);
-      }
-    }
-  };
-  // every lane's scratch column is written before any lane reads another's
-  __builtin_amdgcn_s_waitcnt(0);
+  // Knapsacks moving several items of a user: dealt over the wave (see
+  // lane_deal_pairs) and walked through the owner's LDS column
+  __builtin_amdgcn_s_waitcnt(0);   // every lane's scratch column is written before any lane reads another's
   __builtin_amdgcn_wave_barrier();
   __asm__ volatile("" ::: "memory");
-  const int cnt = __popcll(pending);
-  int incl = cnt;
-  #pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int t = __shfl_up(incl, d, 64);
-    if (lane >= d) incl += t;
-  }
-  const int excl = incl - cnt;
-  const int total = __shfl(incl, 63, 64);
-  for (int base = 0; base < total; base += 64) {
-    const int idx = base + lane;
-    // the pair's owner: the last lane whose first pair is at or before idx
-    int lo = 0, hi = 63;
-    #pragma unroll
-    for (int st = 0; st < 6; ++st) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (__shfl(excl, mid, 64) <= idx) lo = mid;
-      else hi = mid - 1;
-    }
-    uint64_t po = (uint64_t)__shfl((long long)pending, lo, 64);
-    const int nth = idx - __shfl(excl, lo, 64);
-    const uint64_t So = (uint64_t)__shfl((long long)S, lo, 64);
-    const uint64_t poso = (uint64_t)__shfl((long long)pos, lo, 64);
-    const uint64_t permo = (uint64_t)__shfl((long long)perm, lo, 64);
-    if (idx >= total) continue;
-    for (int q = 0; q < nth; ++q) po &= po - 1;
-    walk_pair(lo, __ffsll((long long)po) - 1, So, poso, permo);
-  }
+  lane_deal_pairs(lane, pending, S, pos, perm, [&](int col, int k, uint64_t So, uint64_t poso, uint64_t permo) {
+    lane_walk_pair(a, M, L, col, k, (uint64_t)mskl[k * 64 + col], So, poso, permo,
+                   [&](int j, int c) { return bkc(j, k, c); }, ptl, lam, kst, kmode, tmask, tcap, kcorr, hs, hc,
+                   hmin, hmax, kcnt, kovf, nstage);
+  });
 }
 
 // Kernel modes: evaluation (and its post-processing variant); full SCD pass

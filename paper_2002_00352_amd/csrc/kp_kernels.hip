@@ -1329,17 +1329,24 @@ __global__ void k_uniform_rowptr(int64_t *rowptr, int64_t nrows, int D) {
 }
 
 // Knapsacks starting with a window and those needing another search mode.
+// out[0]: knapsacks searching with a window, out[1]: with another search
+// mode, out[2]: windows that do not contain lambda_k^t (alternation windows)
 __global__ void k_count_modes(const KState *st, int K, int *out) {
-  __shared__ int c[2];
-  if (threadIdx.x < 2) c[threadIdx.x] = 0;
+  __shared__ int c[3];
+  if (threadIdx.x < 3) c[threadIdx.x] = 0;
   __syncthreads();
   for (int k = threadIdx.x; k < K; k += blockDim.x) {
-    const int m = st[k].mode;
-    if (m == KS_WINDOW) atomicAdd(&c[0], 1);
-    else if (m != KS_DONE) atomicAdd(&c[1], 1);
+    const KState &s = st[k];
+    if (s.mode == KS_WINDOW) {
+      atomicAdd(&c[0], 1);
+      const double cen = 0.5 * (s.wlo + s.whi);
+      if (!(fabs(cen - s.center) <= fmax(s.whi - cen, cen - s.wlo))) atomicAdd(&c[2], 1);
+    } else if (s.mode != KS_DONE) {
+      atomicAdd(&c[1], 1);
+    }
   }
   __syncthreads();
-  if (threadIdx.x < 2) out[threadIdx.x] = c[threadIdx.x];
+  if (threadIdx.x < 3) out[threadIdx.x] = c[threadIdx.x];
 }
 
 __global__ void k_count_pending(const KState *st, int K, int *pending) {

@@ -1238,6 +1238,73 @@ def test_scd_alternating_trajectory(name, mk):
     print("window searches", win.window_stats(), flush=True)
 
 
+def _free_tree(M):
+    """No local constraint: every item with a positive adjusted profit is taken."""
+    return kpgen.Tree(np.zeros(0, np.int32), np.zeros(0, np.int32), np.full(M, -1, np.int32))
+
+
+# (name, instance, iterations, the iteration after which lambda jumps,
+# whether the windows centre on lambda^t, None: not checked): the first group
+# converges (its windows around lambda^t run the lane-per-user window pass),
+# the second alternates between two multiplier vectors (windows around
+# lambda^{t-2}: the general kernel)
+DENSE_WINDOW_CASES = [
+    ("c1-N10000", lambda: kpgen.config_instance(1, N=10000), 16, 12, True),
+    ("M10-K2-hier-N8000", lambda: kpgen.make_instance(8000, 10, 2, seed=84, p_dist="exp1", budget_frac=0.05,
+                                                      tree=kpgen.tree_hier_2_2_3(10)), 16, 12, True),
+    ("M16-K2-laminar-N6000", lambda: kpgen.make_instance(6000, 16, 2, seed=85, budget_frac=0.08,
+                                                         tree=random_laminar(16, np.random.default_rng(9))),
+     16, 12, True),
+    ("M5-K2-free-N5000", lambda: kpgen.make_instance(5000, 5, 2, seed=72, budget_frac=0.15, tree=_free_tree(5)),
+     16, 12, True),
+    ("M12-K2-top4-lognormal-N6001", lambda: kpgen.make_instance(6001, 12, 2, seed=77, Q=4, p_dist="lognormal",
+                                                                budget_frac=0.1), 16, 12, True),
+    ("M3-K2-top1-N9000", lambda: kpgen.make_instance(9000, 3, 2, seed=79, Q=1, budget_frac=0.2), 16, 12, True),
+    ("M8-K1-top3-N37", lambda: kpgen.make_instance(37, 8, 1, seed=74, Q=3, budget_frac=0.2), 12, 8, None),
+    ("c2-N6000", lambda: kpgen.config_instance(2, N=6000), 10, 6, False),
+    ("M10-K6-hier-N4000", lambda: kpgen.make_instance(4000, 10, 6, seed=75, p_dist="exp1", budget_frac=0.08,
+                                                      tree=kpgen.tree_hier_2_2_3(10)), 10, 6, False),
+]
+
+
+@gpu
+@pytest.mark.parametrize("name,mk,iters,jump,centred", DENSE_WINDOW_CASES, ids=[c[0] for c in DENSE_WINDOW_CASES])
+def test_dense_window_pass_trajectory(name, mk, iters, jump, centred):
+    """The lane-per-user window pass of dense costs (M, K <= 16): windows
+    around lambda^t decided per item by the distance to its rank neighbours
+    and to zero, the rest walked exactly with the pairs dealt over the wave.
+    Every update equals the oracle's, as do the general kernel's (kernel
+    choice off) and the full search's, with a jump that puts the thresholds
+    outside the windows; both window kernels try the same searches.
+    Alternation windows (away from lambda^t) go to the general kernel."""
+    kp, torch = _kp()
+    print("case", name, flush=True)
+    inst = mk()
+    prob = kp.Problem.from_host(inst)
+    lane = kp.Context()
+    gen = kp.Context()
+    gen.set_kernel_choice(False)
+    full = kp.Context()
+    full.set_window(False)
+    lam = np.zeros(inst.K)
+    kernels = []
+    for t in range(iters):
+        want = oracle.scd_sweep(inst, lam)
+        for ctx in (lane, gen, full):
+            got = kp.kp_scd_sweep(prob, _lamd(torch, lam), ctx=ctx)["lam"].cpu().numpy()
+            assert np.array_equal(got, want), (t, np.flatnonzero(got != want), got, want)
+            if ctx is lane:
+                kernels.append(ctx.launch_shape()[0])
+        lam = want
+        if t == jump:   # the next windows miss
+            lam = lam * np.where(np.arange(inst.K) % 2 == 0, 1.5, 0.5)
+    print("window searches lane", lane.window_stats(), "general", gen.window_stats(),
+          "users walked", lane.window_listed(), "kernels", kernels, flush=True)
+    if centred is not None:
+        assert (3 in kernels) == centred
+    assert lane.window_stats()[0] == gen.window_stats()[0] > 0
+
+
 CATEGORICAL_CASES = [("csr-d2", 2), ("dense", 0)]
 
 
