@@ -21,7 +21,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-WORKLOADS = {"c1": 1, "c2": 2, "c3": 3, "c4": 4, "c5": 5, "c3cat": 3, "alg5": 0, "cdmodes": 0}
+WORKLOADS = {"c1": 1, "c2": 2, "c3": 3, "c4": 4, "c5": 5, "c3cat": 3, "alg5": 0, "cdmodes": 0, "c1big": 1}
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_2002_00352_amd/csrc/kp_kernels.hip", "paper_2002_00352_amd/csrc/kp_ell.hip",
                   "paper_2002_00352_amd/csrc/kp_ell_impl.h", "paper_2002_00352_amd/csrc/kp_device.h",
@@ -50,19 +50,19 @@ def traffic_for(workload, bytes_per_launch):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(cfg_id, seconds, lam):
+def cpu_baseline(cfg_id, seconds, lam, n_max=None):
     """The oracle's SCD sweep (the paper's candidates and map/reduce, as the
     oracle runs them) timed on a bounded prefix of the same workload
     (host-generated users) at the multipliers the GPU's timed steps reached,
     on all host threads and on one.  The prefix grows until one sweep on all
     threads takes about `seconds`; the one-thread figure uses a prefix 1/8 as
-    long."""
+    long (n_max: the workload's users, default the configuration's)."""
     import numpy as np
     import kpgen
     import oracle
     threads = oracle.set_threads(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
     lam = np.asarray(lam, np.float64)
-    n_max = kpgen.CONFIGS[cfg_id]["N"]
+    n_max = n_max or kpgen.CONFIGS[cfg_id]["N"]
     n, dt = 20_000, 0.0
     while True:
         inst = kpgen.config_instance(cfg_id, N=n)
@@ -587,6 +587,8 @@ def main():
     cfg_id = WORKLOADS[args.workload]
     if args.workload == "c3cat" and args.users is None:
         args.users = 20_000_000   # the copies' index arrays of the expansion stay a few GB
+    if args.workload == "c1big" and args.users is None:
+        args.users = 10_000_000   # c1's recipe (dense, M = 10, K = 2, top-1) at c2's size: it converges
     t_gen = time.perf_counter()
     arrs, B, tree, meta = kgd.device_instance(cfg_id, 0, N=args.users)
     cap = tree.cap
@@ -599,6 +601,8 @@ def main():
                       rowptr=arrs.get("rowptr"), col=arrs.get("col"), val=arrs.get("val"),
                       N=meta["N"], M=meta["M"], K=meta["K"],
                       row_nnz=meta["csr_d"] if meta["csr_d"] else None)
+    if args.workload == "c1big":
+        meta = dict(meta, name="c1 recipe at scale: plain SCD N=%d M=10 K=2 top-1 dense, U(0,1)" % meta["N"])
     if args.workload == "c3cat":
         from paper_2002_00352_amd import categorical
         prob = categorical.expand(prob).binary
@@ -645,7 +649,8 @@ def main():
     ceiling = stream_ceiling([t for t in (prob.p, prob.b, None if lean else prob.rowptr, prob.col, prob.val)
                               if t is not None])
     physical = traffic / (avg_ms * 1e-3) / 1e9 if traffic else None
-    kernel_name = "k_ell window pass (all users, then the listed ones)" if lean else "k_sweep (scd)"
+    kernel_name = {1: "k_ell window pass (all users, then the listed ones)",
+                   3: "k_dense window pass (lane per user)"}.get(ctx.launch_shape()[0], "k_sweep (scd)")
     rec = {
         "metric": "user-subproblem solves/s per SCD sweep",
         "value": value,
@@ -733,7 +738,7 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         if args.workload != "c3cat":
-            rec["cpu_baseline"] = cpu_baseline(cfg_id, args.cpu_seconds, lam_warm)
+            rec["cpu_baseline"] = cpu_baseline(cfg_id, args.cpu_seconds, lam_warm, n_max=N)
         rec["time_to_gap"] = time_to_gap()
     print(json.dumps(rec), flush=True)
 
