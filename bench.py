@@ -251,7 +251,10 @@ def summarize_trace(trace_dir, bench_log, kernel_subs):
     rec = next(json.loads(l) for l in open(bench_log) if l.startswith("{"))
     stats = _csv_rows(os.path.join(trace_dir, "run_kernel_stats.csv"))
     trace = _csv_rows(os.path.join(trace_dir, "run_kernel_trace.csv"))
-    n = rec["roofline"]["launches"]
+    # the batched line times whole iterations: its timed passes are the last
+    # steps * passes_per_step dispatches of the batched kernel
+    batched = rec["roofline"]["kernel"].startswith("k_sweep_batched")
+    n = round(rec["steps"] * rec["passes_per_step"]) if batched else rec["roofline"]["launches"]
     subs = kernel_subs.split("|")
     # the timed passes end where the streaming ceiling's first read starts
     # (the benchmark measures it right after them)
@@ -270,14 +273,24 @@ def summarize_trace(trace_dir, bench_log, kernel_subs):
         out.append(f"| `{r['Name'][:60]}` | {r['Calls']} | {float(r['AverageNs']) * 1e-6:.3f} | "
                    f"{float(r['TotalDurationNs']) * 1e-6:.1f} | {float(r['Percentage']):.2f} |")
     out.append("")
-    out.append(f"Timed sweep passes (the last {n} dispatches of " + " + ".join(f"`{x}`" for x in subs) +
-               " before the streaming-ceiling probe" +
-               f"): average {avg:.3f} ms per pass (kernels only), min {min(durs):.3f}, max {max(durs):.3f}; "
-               + ", ".join(f"`{x}` {sum(p) / len(p):.3f} ms" for x, p in zip(subs, per)) + ".")
-    out.append(f"bench.py's own HIP-event average per pass (both launches and the list reset "
-               f"between the events): {rec['roofline']['avg_launch_ms']:.3f} ms; "
-               f"{rec['roofline']['algo_bytes_per_launch'] / 1e9:.2f} GB algorithmic bytes per pass "
-               f"-> {rec['roofline']['algo_bytes_per_launch'] / (avg * 1e-3) / 1e9:.1f} GB/s from the trace.")
+    if batched:
+        it_ms = sum(durs) / rec["steps"]
+        out.append(f"Timed iterations (the last {n} dispatches of " + " + ".join(f"`{x}`" for x in subs) +
+                   f", {rec['steps']} iterations): {it_ms:.3f} ms of sweep kernels per iteration; passes "
+                   f"{min(durs):.3f} to {max(durs):.3f} ms.")
+        out.append(f"bench.py's own HIP-event time per iteration (every pass and the search kernels): "
+                   f"{rec['roofline']['avg_launch_ms']:.3f} ms; "
+                   f"{rec['roofline']['algo_bytes_per_launch'] / 1e9:.2f} GB algorithmic bytes per iteration "
+                   f"-> {rec['roofline']['algo_bytes_per_launch'] / (it_ms * 1e-3) / 1e9:.1f} GB/s from the trace.")
+    else:
+        out.append(f"Timed sweep passes (the last {n} dispatches of " + " + ".join(f"`{x}`" for x in subs) +
+                   " before the streaming-ceiling probe" +
+                   f"): average {avg:.3f} ms per pass (kernels only), min {min(durs):.3f}, max {max(durs):.3f}; "
+                   + ", ".join(f"`{x}` {sum(p) / len(p):.3f} ms" for x, p in zip(subs, per)) + ".")
+        out.append(f"bench.py's own HIP-event average per pass (both launches and the list reset "
+                   f"between the events): {rec['roofline']['avg_launch_ms']:.3f} ms; "
+                   f"{rec['roofline']['algo_bytes_per_launch'] / 1e9:.2f} GB algorithmic bytes per pass "
+                   f"-> {rec['roofline']['algo_bytes_per_launch'] / (avg * 1e-3) / 1e9:.1f} GB/s from the trace.")
     out.append(f"bench line: value {rec['value']:.4g} {rec['unit']}, ms_per_step {rec['ms_per_step']:.2f}, "
                f"passes_per_step {rec['passes_per_step']}.")
     print("\n".join(out))
