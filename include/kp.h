@@ -184,11 +184,15 @@ kp_status kp_scd_sweep_batched(void *ctx, const kp_problem *probs, int32_t n,
    and lam_b[s] (HOST arrays of n DEV pointers, each [K_s]).
    kp_batched_step(plan, dir, stats, use_graph) runs one SCD iteration from
    lam_a into lam_b (dir 0) or from lam_b into lam_a (dir 1); stats as in
-   kp_scd_sweep_batched (DEV, may be NULL).  With use_graph != 0 the first
-   pass of the iteration (init, sweep, statistics, threshold search, update)
-   is captured once per direction as a HIP graph and replayed; further
-   refinement passes, when a threshold is not resolved in the first pass, run
-   eagerly.  The plan borrows the context's stream and owns its workspace;
+   kp_scd_sweep_batched (DEV, may be NULL).  With use_graph != 0 the
+   iteration (init, sweep, statistics, threshold search, update) is captured
+   once per direction as a HIP graph and replayed: the first pass and five
+   later passes, each later pass splitting the blocks among the instances
+   whose threshold is still open on the device (a pass with none open does
+   no work; plans of more than 1706 instances capture the first pass
+   only); passes beyond those run eagerly, split on the host.  With
+   use_graph == 0 every pass is launched eagerly.  The plan borrows the
+   context's stream and owns its workspace;
    the caller keeps the instances' buffers alive until kp_batched_destroy.
    Synchronises the stream at the end of every step. */
 kp_status kp_batched_create(void *ctx, const kp_problem *probs, int32_t n,

@@ -20,7 +20,7 @@ _REPO = os.path.dirname(_HERE)
 LIB_PATH = os.path.join(_HERE, "libkp.so")
 SOURCES = [os.path.join(_HERE, "csrc", f) for f in
            ("kp_kernels.hip", "kp_ell.hip", "kp_ell_m0.hip", "kp_ell_m1.hip", "kp_ell_m2.hip",
-            "kp_ell_m3.hip", "kp_ell_m4.hip", "kp_dense.hip", "kp_capi.hip")]
+            "kp_ell_m3.hip", "kp_ell_m4.hip", "kp_dense.hip", "kp_batched.hip", "kp_capi.hip")]
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
                "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                "-Wno-unused-result"]
@@ -394,7 +394,9 @@ def kp_scd_sweep_batched(probs: Sequence[Problem], lams_in, lams_out=None,
 
 class BatchedSCD:
     """Repeated SCD iterations over a batch of instances: device tables built
-    once, each iteration's first pass replayed from a captured HIP graph."""
+    once, each iteration (its first pass and up to five later passes, split
+    among the open instances on the device) replayed from a captured HIP
+    graph; a search still open after them continues from the host."""
 
     def __init__(self, probs: Sequence[Problem], lam0=None, use_graph: bool = True,
                  ctx: Optional[Context] = None):

@@ -65,8 +65,10 @@ hipError_t kp_launch_ell_check(const int64_t *rowptr, int64_t nrows, int D, unsi
                                hipStream_t stream);
 hipError_t kp_launch_sweep_batched(const SweepArgs *descs, const TileGeom *geoms,
                                    const int *block_off, int n_inst, int total_blocks, size_t lds,
-                                   hipStream_t stream);
+                                   hipStream_t stream, const int *n_dev = nullptr);
 hipError_t kp_launch_inst_active(const KState *st, const int *koff, int n, int *flags, hipStream_t stream);
+size_t kp_resplit_lds(int n);
+hipError_t kp_launch_plan_resplit(const ResplitArgs &r, hipStream_t stream);
 hipError_t kp_launch_batched_aux(int which, const void *tab, int n, KState *st, const void *lam_ptrs,
                                  const int *kinst, const int *klocal, double *hint, const uint64_t *eoff,
                                  const uint32_t *ecap, hipStream_t stream);
@@ -116,6 +118,7 @@ constexpr uint32_t kEmitCapDefault = 1u << 20;
 constexpr int kMaxPasses = 96;
 constexpr uint32_t kStageCap = 4096;    // staged events per block per pass (at least)
 constexpr uint32_t kStageCapMax = 65536;
+constexpr int kGraphLaterPasses = 5;     // later passes captured with the first in a batched iteration's graph
 constexpr uint32_t kEmitCapBatched = 1u << 16;   // emitted events per (instance, knapsack) per pass (at least)
 constexpr double kEmitBytesBatched = 8.0e9;        // bound on a batch's emission buffers
 constexpr size_t kBatchedLds = 40 * 1024;          // LDS per block of the batched launch (4 blocks per CU)
@@ -1599,6 +1602,15 @@ struct BatchPlan {
   std::vector<double> pairs;      // users x knapsacks of every instance
   std::vector<size_t> ilds;       // LDS of every instance's tiles
   std::vector<int> order;         // instances by decreasing tile cost (the block layout's order)
+  // the later passes split on the device (graph capture of whole iterations)
+  SweepArgs *dhd[2] = {nullptr, nullptr};   // [dir] hd on the device
+  TileGeom *dhg = nullptr;
+  int *dord = nullptr;
+  int64_t *dnt = nullptr;
+  double *dpairs = nullptr;
+  int *ctl = nullptr;       // [0] open instances of the pass, [1] passes with work, [2] split overflow
+  int glater = 0;           // later passes in the iteration's graph (0: only the first pass)
+  int gfix = 0;             // blocks of such a pass (an upper bound on any split's)
 };
 
 // Split of a later pass: the instances whose knapsacks still search share
@@ -1650,6 +1662,45 @@ int plan_resplit(BatchPlan *p, int dir, int *blocks, size_t *lds) {
   return na;
 }
 
+// The later passes of a whole-iteration graph: each splits the open
+// instances' blocks on the device, sweeps them (blocks past the split exit),
+// and runs the threshold search; a pass with nothing open does no work.
+kp_status plan_later_passes_dev(BatchPlan *p, int dir, hipStream_t s) {
+  for (int j = 0; j < p->glater; ++j) {
+    ResplitArgs r;
+    r.order = p->dord;
+    r.active = p->active;
+    r.ntiles = p->dnt;
+    r.pairs = p->dpairs;
+    r.hd = p->dhd[dir];
+    r.hg = p->dhg;
+    r.n = p->n;
+    r.gmax = p->gmax;
+    r.cap_min = kStageCap;
+    r.cap_max = kStageCapMax;
+    r.stage_total = p->stage_total;
+    r.s1 = p->s1;
+    r.s2 = p->s2;
+    r.sk = p->sk;
+    r.rd = p->rd;
+    r.rg = p->rg;
+    r.rboff = p->rboff;
+    r.ctl = p->ctl;
+    r.reset = j == 0 ? 1 : 0;
+    HIP_TRY(kp_launch_plan_resplit(r, s));
+    if (p->T > 0) HIP_TRY(kp_launch_sweep_batched(p->rd, p->rg, p->rboff, p->n, p->gfix, p->lds, s, p->ctl));
+    HIP_TRY(kp_launch_scd_locate_select(p->kst, p->Kf, p->Bf, p->stats, p->kin, p->hs, p->hc, p->e1, p->e2, p->cap, p->pend, nullptr, s));
+    HIP_TRY(kp_launch_batched_aux(2, nullptr, p->Kf, p->kst, p->lam_tab[1 - dir], p->kin, p->klo, p->hint, nullptr,
+                                  nullptr, s));
+    HIP_TRY(kp_launch_inst_active(p->kst, p->koff, p->n, p->active, s));
+  }
+  HIP_TRY(hipMemcpyAsync(p->pinned, p->pend, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(p->pinned + 2, p->err, 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(p->pinned + 16, p->active, (size_t)p->n * 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(p->pinned + 8, p->ctl, 12, hipMemcpyDeviceToHost, s));
+  return KP_OK;
+}
+
 kp_status plan_first_pass(BatchPlan *p, int dir, hipStream_t s) {
   HIP_TRY(kp_launch_batched_aux(p->window ? 3 : 1, nullptr, p->Kf, p->kst, p->lam_tab[dir], p->kin, p->klo, p->hint,
                                 p->eoff, p->ecap, s));
@@ -1676,10 +1727,12 @@ kp_status plan_step(BatchPlan *p, int dir, double *stats_out, bool graph) {
     if (e0 && e1) (void)hipEventRecord(e0, s);
   }
   int passes = 1;
+  int first_later = 1;   // index of the first later pass run from the host
   if (graph) {
     if (!p->exec[dir]) {
       HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
       kp_status st = plan_first_pass(p, dir, s);
+      if (st == KP_OK && p->glater > 0) st = plan_later_passes_dev(p, dir, s);
       hipGraph_t g = nullptr;
       hipError_t e = hipStreamEndCapture(s, &g);
       if (st != KP_OK) return st;
@@ -1693,7 +1746,12 @@ kp_status plan_step(BatchPlan *p, int dir, double *stats_out, bool graph) {
     if (st != KP_OK) return st;
   }
   HIP_TRY(hipStreamSynchronize(s));
-  for (int pass = 1;; ++pass) {
+  if (graph && p->glater > 0) {
+    if (p->pinned[10]) return fail(KP_ERR_INTERNAL, "batched staging split overflowed");
+    passes += p->pinned[9];
+    first_later = 1 + p->glater;
+  }
+  for (int pass = first_later;; ++pass) {
     if (*(unsigned long long *)(p->pinned + 2))
       return fail(KP_ERR_INTERNAL, "breakpoint walk exceeded its event limit");
     if (p->pinned[0] == 0) break;
@@ -1876,6 +1934,14 @@ kp_status plan_create(Ctx *c, const kp_problem *probs, int n, const double *cons
   const size_t o_rd = cv.take((size_t)n * sizeof(SweepArgs));
   const size_t o_rg = cv.take((size_t)n * sizeof(TileGeom));
   const size_t o_rbo = cv.take((size_t)(n + 1) * 4);
+  // tables of the device-side split (whole-iteration graphs)
+  const size_t o_dhd0 = cv.take((size_t)n * sizeof(SweepArgs));
+  const size_t o_dhd1 = cv.take((size_t)n * sizeof(SweepArgs));
+  const size_t o_dhg = cv.take((size_t)n * sizeof(TileGeom));
+  const size_t o_dord = cv.take((size_t)n * 4);
+  const size_t o_dnt = cv.take((size_t)n * 8);
+  const size_t o_dpr = cv.take((size_t)n * 8);
+  const size_t o_ctl = cv.take(16);
   if (c->max_ws && cv.off > c->max_ws) {
     plan_free(p);
     return fail(KP_ERR_NOMEM, "batched plan needs %zu bytes, above the context cap", cv.off);
@@ -1930,6 +1996,13 @@ kp_status plan_create(Ctx *c, const kp_problem *probs, int n, const double *cons
   p->rd = (SweepArgs *)(w + o_rd);
   p->rg = (TileGeom *)(w + o_rg);
   p->rboff = (int *)(w + o_rbo);
+  p->dhd[0] = (SweepArgs *)(w + o_dhd0);
+  p->dhd[1] = (SweepArgs *)(w + o_dhd1);
+  p->dhg = (TileGeom *)(w + o_dhg);
+  p->dord = (int *)(w + o_dord);
+  p->dnt = (int64_t *)(w + o_dnt);
+  p->dpairs = (double *)(w + o_dpr);
+  p->ctl = (int *)(w + o_ctl);
   p->s1 = (double *)(w + o_s1);
   p->s2 = (double *)(w + o_s2);
   p->sk = (uint16_t *)(w + o_sk);
@@ -2038,6 +2111,13 @@ kp_status plan_create(Ctx *c, const kp_problem *probs, int n, const double *cons
   if (e == hipSuccess) e = up(p->lam_tab[1], lt1.data(), (size_t)n * 8);
   if (e == hipSuccess) e = up(p->coltab[0], tab0.data(), tab0.size());
   if (e == hipSuccess) e = up(p->coltab[1], tab1.data(), tab1.size());
+  if (e == hipSuccess) e = up(p->dhd[0], hd[0][0].data(), (size_t)n * sizeof(SweepArgs));
+  if (e == hipSuccess) e = up(p->dhd[1], hd[1][0].data(), (size_t)n * sizeof(SweepArgs));
+  if (e == hipSuccess) e = up(p->dhg, hg.data(), (size_t)n * sizeof(TileGeom));
+  if (e == hipSuccess) e = up(p->dord, ord.data(), (size_t)n * 4);
+  if (e == hipSuccess) e = up(p->dnt, p->ntiles.data(), (size_t)n * 8);
+  if (e == hipSuccess) e = up(p->dpairs, p->pairs.data(), (size_t)n * 8);
+  if (e == hipSuccess) e = hipMemsetAsync(p->ctl, 0, 16, st);
   if (e == hipSuccess) e = hipMemsetAsync(p->hs, 0, (size_t)Kf * KP_NB * sizeof(XSum), st);
   if (e == hipSuccess) e = hipMemsetAsync(p->hc, 0, (size_t)Kf * KP_NB * 4, st);
   if (e == hipSuccess) e = hipMemsetAsync(p->err, 0, 8, st);
@@ -2049,6 +2129,11 @@ kp_status plan_create(Ctx *c, const kp_problem *probs, int n, const double *cons
   for (int d = 0; d < 2; ++d) p->hd[d] = hd[d][0];
   p->hg = hg;
   p->order = ord;
+  // whole-iteration graphs hold this many later passes split on the device
+  // (a split's blocks never exceed max(n, gmax) + 2n); further passes, rare,
+  // run from the host
+  p->glater = kp_resplit_lds(n) ? kGraphLaterPasses : 0;
+  p->gfix = std::max(n, gmax) + 2 * n;
   *out = p;
   return KP_OK;
 }

@@ -136,3 +136,25 @@ struct SweepArgs {
   // top-Q set, for users whose item j consumes only knapsack j (M = K); 0 = off
   int alg5_q;
 };
+
+// Device-side split of a batched plan's later pass among the instances still
+// searching (k_plan_resplit): the tables it reads, the descriptors it writes.
+struct ResplitArgs {
+  const int *order;          // [n] instance at each position of the block layout
+  const int *active;         // [n] instance still searching (by instance)
+  const int64_t *ntiles;     // [n] tiles of every instance
+  const double *pairs;       // [n] users x knapsacks of every instance
+  const SweepArgs *hd;       // [n] later-pass descriptors (by instance)
+  const TileGeom *hg;        // [n] tile geometry (by instance)
+  int n, gmax;
+  uint32_t cap_min, cap_max; // staged events per block: bounds
+  size_t stage_total;        // staged events of the whole launch
+  double *s1, *s2;           // staging areas of the launch
+  uint16_t *sk;
+  SweepArgs *rd;             // [n] out: descriptors of the open instances
+  TileGeom *rg;              // [n] out
+  int *rboff;                // [n + 1] out: first block of every open instance
+  int *ctl;                  // [0] out: open instances, [1] passes with work (cleared when reset),
+                             // [2] staging overflow flag
+  int reset;                 // first later pass of the iteration: clear ctl[1]
+};

@@ -807,14 +807,20 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs a, const TileGeom 
 }
 
 // Batched: blocks [block_off[s], block_off[s+1]) work on instance s, whose
-// arguments are copied into LDS; one launch covers every instance.
+// arguments are copied into LDS; one launch covers every instance.  n_dev:
+// the instance count read from the device (a split made there; blocks past
+// the last instance's range exit at once), else n_inst.
 // at most 168 VGPRs: three waves per SIMD
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3, 8))) k_sweep_batched(const SweepArgs *descs, const TileGeom *geoms,
-                                                      const int *block_off, int n_inst) {
+                                                      const int *block_off, int n_inst, const int *n_dev) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ SweepArgs sa;
   __shared__ TileGeom sg;
   __shared__ int inst;
+  if (n_dev) {
+    n_inst = *n_dev;
+    if (n_inst <= 0 || (int)blockIdx.x >= block_off[n_inst]) return;
+  }
   if (threadIdx.x == 0) {
     int lo = 0, hi = n_inst - 1;
     while (lo < hi) {   // last s with block_off[s] <= blockIdx.x
@@ -2233,14 +2239,15 @@ __global__ void k_scd_finish_flat(const KState *st, int Kf, double *const *lam_o
 }
 
 hipError_t kp_launch_sweep_batched(const SweepArgs *descs, const TileGeom *geoms, const int *block_off,
-                                   int n_inst, int total_blocks, size_t lds, hipStream_t stream) {
+                                   int n_inst, int total_blocks, size_t lds, hipStream_t stream,
+                                   const int *n_dev) {
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void *)k_sweep_batched,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_sweep_batched, dim3(total_blocks), dim3(NT), lds, stream, descs, geoms,
-                     block_off, n_inst);
+                     block_off, n_inst, n_dev);
   return hipGetLastError();
 }
 

@@ -585,20 +585,32 @@ def test_batched_sweep_parity():
 def test_batched_plan_graph_replays(use_graph):
     """A batched plan stepped several times (graph replays alternating the
     two multiplier buffers, with host work in between) follows the oracle's
-    SCD trajectory for every instance at every step."""
+    SCD trajectory for every instance at every step.  With the graph, an
+    iteration's later passes are split on the device and replayed with the
+    first; they run the same passes as the host-split plan."""
     kp, torch = _kp()
     insts = kpgen.batched_instances(run=1, n=12, max_N=2000)
     probs = [kp.Problem.from_host(i) for i in insts]
-    plan = kp.BatchedSCD(probs, use_graph=use_graph)
+    ctx = kp.Context()
+    ref_ctx = kp.Context()
+    ctx.set_timing(True)       # (passes are counted over timed iterations)
+    ref_ctx.set_timing(True)
+    plan = kp.BatchedSCD(probs, use_graph=use_graph, ctx=ctx)
+    ref = kp.BatchedSCD(probs, use_graph=False, ctx=ref_ctx)
     lams = [np.zeros(i.K) for i in insts]
-    for t in range(4):
+    for t in range(6):
         outs, stats = plan.step()
+        routs, _ = ref.step()
         torch.cuda.synchronize()
         for s, inst in enumerate(insts):
             want = oracle.scd_sweep(inst, lams[s])
             assert np.array_equal(outs[s].cpu().numpy(), want), (use_graph, t, s)
+            assert np.array_equal(routs[s].cpu().numpy(), want), (t, s)
             lams[s] = want
+        assert ctx.batched_passes() == ref_ctx.batched_passes(), t
+    print("passes", ctx.batched_passes(), flush=True)
     plan.close()
+    ref.close()
 
 
 @gpu
