@@ -1086,6 +1086,16 @@ kp_status kp_scd_sweep_masked_impl(Ctx *c, const kp_problem *prob, const double 
     // full searches (knapsacks without a window) start from a sample
     if (sample && c->pinned[21] > 0) {
       if ((s = sample_center(c, prob, P, w, lambda_in, kmask)) != KP_OK) return s;
+      // the sample's threshold may have opened windows for all of them:
+      // choose the first pass's kernel again
+      if (counts && window) {
+        HIP_TRY(kp_launch_count_modes(w.st, K, w.modes, c->stream));
+        HIP_TRY(hipMemcpyAsync(c->pinned + 20, w.modes, 12, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        split = w.fcap && c->pinned[20] > 0 && c->pinned[21] == 0;
+        nohist = nh_gain && c->pinned[21] == 0;
+        dwin = P.dwin_grid && c->pinned[21] == 0 && c->pinned[22] == 0;
+      }
     }
   }
   HIP_TRY(hipMemsetAsync(w.stat, 0, w.stat_bytes, c->stream));   // status, histograms
