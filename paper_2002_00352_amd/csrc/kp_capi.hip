@@ -61,6 +61,7 @@ hipError_t kp_launch_dense(const SweepArgs &a, int grid, hipStream_t stream, int
 int kp_dense_tile_users();
 int kp_dense_resident_grid(int M, int K, int L, bool win);
 hipError_t kp_launch_count_modes(const KState *st, int K, int *out, hipStream_t stream);
+hipError_t kp_launch_dense_probe(const SweepArgs &a, int *out, hipStream_t stream);
 hipError_t kp_launch_ell_check(const int64_t *rowptr, int64_t nrows, int D, unsigned int *bad,
                                hipStream_t stream);
 hipError_t kp_launch_sweep_batched(const SweepArgs *descs, const TileGeom *geoms,
@@ -1071,31 +1072,35 @@ kp_status kp_scd_sweep_masked_impl(Ctx *c, const kp_problem *prob, const double 
   const bool nh_gain = !P.ell_D && (P.U_nh != P.U || P.grid_nh != P.grid);
   const bool sample = c->sample_min > 0 && P.pr.N >= c->sample_min && !c->interp;
   const bool counts = window && c->delta_valid && (w.fcap || nh_gain || P.dwin_grid);
-  if (counts || sample) {
+  // the search-mode counts, and for dense costs the probe of the users'
+  // lines (read back together), decide the first pass's kernel
+  auto count_and_choose = [&]() -> kp_status {
     HIP_TRY(kp_launch_count_modes(w.st, K, w.modes, c->stream));
-    HIP_TRY(hipMemcpyAsync(c->pinned + 20, w.modes, 12, hipMemcpyDeviceToHost, c->stream));
+    const bool probe = counts && P.dwin_grid;
+    if (probe) HIP_TRY(kp_launch_dense_probe(make_args(P, lambda_in, w, nullptr, true), w.modes + 3, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->pinned + 20, w.modes, 16, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     if (counts) {
       split = w.fcap && c->pinned[20] > 0 && c->pinned[21] == 0;
       nohist = nh_gain && c->pinned[21] == 0;
-      // dense costs: the lane-per-user window pass, when every window is
-      // centred on lambda^t (alternation windows away from it: the general
-      // kernel, whose per-(user, knapsack) tests stop early)
-      dwin = P.dwin_grid && c->pinned[21] == 0 && c->pinned[22] == 0;
+      // dense costs: the lane-per-user window pass when every window is
+      // centred on lambda^t, or when almost no sampled user has a line that
+      // can turn positive in any window (its gap test then settles every
+      // pair, whatever the windows); alternation windows otherwise go to the
+      // general kernel, whose per-(user, knapsack) tests stop early
+      dwin = probe && c->pinned[21] == 0 &&
+             (c->pinned[22] == 0 || c->pinned[23] * 64 <= KP_PROBE_USERS);
     }
+    return KP_OK;
+  };
+  if (counts || sample) {
+    if ((s = count_and_choose()) != KP_OK) return s;
     // full searches (knapsacks without a window) start from a sample
     if (sample && c->pinned[21] > 0) {
       if ((s = sample_center(c, prob, P, w, lambda_in, kmask)) != KP_OK) return s;
       // the sample's threshold may have opened windows for all of them:
       // choose the first pass's kernel again
-      if (counts && window) {
-        HIP_TRY(kp_launch_count_modes(w.st, K, w.modes, c->stream));
-        HIP_TRY(hipMemcpyAsync(c->pinned + 20, w.modes, 12, hipMemcpyDeviceToHost, c->stream));
-        HIP_TRY(hipStreamSynchronize(c->stream));
-        split = w.fcap && c->pinned[20] > 0 && c->pinned[21] == 0;
-        nohist = nh_gain && c->pinned[21] == 0;
-        dwin = P.dwin_grid && c->pinned[21] == 0 && c->pinned[22] == 0;
-      }
+      if (counts && window && (s = count_and_choose()) != KP_OK) return s;
     }
   }
   HIP_TRY(hipMemsetAsync(w.stat, 0, w.stat_bytes, c->stream));   // status, histograms

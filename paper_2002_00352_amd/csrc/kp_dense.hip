@@ -250,10 +250,12 @@ __global__ void __launch_bounds__(64) k_dense(const SweepArgs a, int x4) {
         const double gscale = fabs(top) + H;
         // (lines at or below -H are moved to -inf: no finite distance to them)
         double gj[EM], pu[EM];
+        bool anyup = false;   // some line can turn positive in some window
         #pragma unroll
         for (int j = 0; j < EM; ++j) {
           pu[j] = (j < M && pt[j] > -H) ? pt[j] : -INFINITY;
           gj[j] = pu[j] > -INFINITY ? fabs(pt[j]) : 1e300;
+          anyup = anyup | (pu[j] > -INFINITY);
         }
         #pragma unroll
         for (int j = 0; j < EM; ++j) {
@@ -264,7 +266,8 @@ __global__ void __launch_bounds__(64) k_dense(const SweepArgs a, int x4) {
             gj[jj] = d < gj[jj] ? d : gj[jj];
           }
         }
-        for (int k = 0; k < K; ++k) {
+        // (a user without such a line is calm in every window)
+        for (int k = 0; anyup && k < K; ++k) {
           if (kmode[k] != KS_WINDOW) continue;
           float bk[EM];
           uint32_t A = 0;
@@ -377,6 +380,44 @@ auto dispatch_dense(int M, int K, F f) {
 }
 
 }  // namespace
+
+// Probe for the window pass of dense costs when some window does not
+// contain lambda_k^t: on 4096 users spread over the instance, count those
+// with a line above -H (H: the widest window's reach times the user's
+// largest cost).  A user without one is settled by the window pass's gap
+// test whatever its windows (no line can turn positive in any of them); the
+// host runs the lane-per-user pass when almost every sampled user is such.
+__global__ void __launch_bounds__(64) k_dense_probe(const float *p, const float *b, const double *lam,
+                                                    const KState *st, int64_t N, int M, int K, int *out) {
+  const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (i >= KP_PROBE_USERS) return;
+  const int64_t u = i * N / KP_PROBE_USERS;
+  double hm = 0.0;
+  for (int k = 0; k < K; ++k)
+    if (st[k].mode == KS_WINDOW) hm = fmax(hm, st[k].hw);
+  const float *pu = p + u * M;
+  const float *bu = b + u * M * K;
+  float bm = 0.0f;
+  for (int e = 0; e < M * K; ++e) bm = fmaxf(bm, bu[e]);
+  const double H = hm * (double)bm * (1.0 + 0x1p-30) + 0x1p-36 * (1.0 + (double)bm * hm);
+  bool up = false;
+  for (int j = 0; j < M; ++j) {
+    double acc = (double)pu[j];
+    for (int k = 0; k < K; ++k) {
+      const double prod = lam[k] * (double)bu[j * K + k];
+      acc = acc - prod;
+    }
+    up = up || acc > -H;
+  }
+  if (up) atomicAdd(out, 1);
+}
+
+hipError_t kp_launch_dense_probe(const SweepArgs &a, int *out, hipStream_t stream) {
+  if (a.pr.fmt != 0 || a.pr.N <= 0 || !a.st) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_dense_probe, dim3(KP_PROBE_USERS / 64), dim3(64), 0, stream, a.pr.p, a.pr.b, a.lam, a.st,
+                     (int64_t)a.pr.N, a.pr.M, a.pr.K, out);
+  return hipGetLastError();
+}
 
 int kp_dense_tile_users() { return TU; }
 

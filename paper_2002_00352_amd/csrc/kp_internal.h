@@ -8,6 +8,7 @@
 #define KP_MAX_K_SCD 64        // per-block LDS histograms bound K for the SCD calls
 #define KP_CENTRAL_W 2         // exponential buckets |id| <= W are emitted in the first pass
 #define KP_SORT_MAX 4096       // candidates sorted in LDS by the selection kernel
+#define KP_PROBE_USERS 4096   // users sampled by the dense window pass's probe
 #define KP_WIN_MULT 1.25       // window half-width around lambda_k^t, in units of the last step
 #define KP_WIN_MAX_REL 0.03125 // windows wider than this fraction of lambda_k^t are not tried
 #define KP_LIST_CHUNK 256u     // list slots a wave reserves at a time in the window pass

@@ -1336,7 +1336,8 @@ __global__ void k_uniform_rowptr(int64_t *rowptr, int64_t nrows, int D) {
 
 // Knapsacks starting with a window and those needing another search mode.
 // out[0]: knapsacks searching with a window, out[1]: with another search
-// mode, out[2]: windows that do not contain lambda_k^t (alternation windows)
+// mode, out[2]: windows that do not contain lambda_k^t (alternation windows);
+// out[3] is cleared (the dense window pass's probe counts into it)
 __global__ void k_count_modes(const KState *st, int K, int *out) {
   __shared__ int c[3];
   if (threadIdx.x < 3) c[threadIdx.x] = 0;
@@ -1353,6 +1354,7 @@ __global__ void k_count_modes(const KState *st, int K, int *out) {
   }
   __syncthreads();
   if (threadIdx.x < 3) out[threadIdx.x] = c[threadIdx.x];
+  if (threadIdx.x == 3) out[3] = 0;
 }
 
 __global__ void k_count_pending(const KState *st, int K, int *pending) {

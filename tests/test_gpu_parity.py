@@ -1256,10 +1256,11 @@ def _free_tree(M):
 
 
 # (name, instance, iterations, the iteration after which lambda jumps,
-# whether the windows centre on lambda^t, None: not checked): the first group
-# converges (its windows around lambda^t run the lane-per-user window pass),
-# the second alternates between two multiplier vectors (windows around
-# lambda^{t-2}: the general kernel)
+# whether some pass must run the lane-per-user window pass, None: not
+# checked): the first group converges (windows around lambda^t), the second
+# alternates between two multiplier vectors (windows around lambda^{t-2}: the
+# lane-per-user pass where the probe finds every sampled user's lines far
+# below zero, as at c2's upper multipliers, else the general kernel)
 DENSE_WINDOW_CASES = [
     ("c1-N10000", lambda: kpgen.config_instance(1, N=10000), 16, 12, True),
     ("M10-K2-hier-N8000", lambda: kpgen.make_instance(8000, 10, 2, seed=84, p_dist="exp1", budget_frac=0.05,
@@ -1273,22 +1274,24 @@ DENSE_WINDOW_CASES = [
                                                                 budget_frac=0.1), 16, 12, True),
     ("M3-K2-top1-N9000", lambda: kpgen.make_instance(9000, 3, 2, seed=79, Q=1, budget_frac=0.2), 16, 12, True),
     ("M8-K1-top3-N37", lambda: kpgen.make_instance(37, 8, 1, seed=74, Q=3, budget_frac=0.2), 12, 8, None),
-    ("c2-N6000", lambda: kpgen.config_instance(2, N=6000), 10, 6, False),
+    ("c2-N6000", lambda: kpgen.config_instance(2, N=6000), 10, 6, True),
     ("M10-K6-hier-N4000", lambda: kpgen.make_instance(4000, 10, 6, seed=75, p_dist="exp1", budget_frac=0.08,
-                                                      tree=kpgen.tree_hier_2_2_3(10)), 10, 6, False),
+                                                      tree=kpgen.tree_hier_2_2_3(10)), 10, 6, None),
 ]
 
 
 @gpu
-@pytest.mark.parametrize("name,mk,iters,jump,centred", DENSE_WINDOW_CASES, ids=[c[0] for c in DENSE_WINDOW_CASES])
-def test_dense_window_pass_trajectory(name, mk, iters, jump, centred):
+@pytest.mark.parametrize("name,mk,iters,jump,lane_pass", DENSE_WINDOW_CASES, ids=[c[0] for c in DENSE_WINDOW_CASES])
+def test_dense_window_pass_trajectory(name, mk, iters, jump, lane_pass):
     """The lane-per-user window pass of dense costs (M, K <= 16): windows
     around lambda^t decided per item by the distance to its rank neighbours
     and to zero, the rest walked exactly with the pairs dealt over the wave.
     Every update equals the oracle's, as do the general kernel's (kernel
     choice off) and the full search's, with a jump that puts the thresholds
     outside the windows; both window kernels try the same searches.
-    Alternation windows (away from lambda^t) go to the general kernel."""
+    Alternation windows (away from lambda^t) go to the lane-per-user pass
+    only when a probe of the users finds (almost) every line far below
+    zero."""
     kp, torch = _kp()
     print("case", name, flush=True)
     inst = mk()
@@ -1312,8 +1315,8 @@ def test_dense_window_pass_trajectory(name, mk, iters, jump, centred):
             lam = lam * np.where(np.arange(inst.K) % 2 == 0, 1.5, 0.5)
     print("window searches lane", lane.window_stats(), "general", gen.window_stats(),
           "users walked", lane.window_listed(), "kernels", kernels, flush=True)
-    if centred is not None:
-        assert (3 in kernels) == centred
+    if lane_pass is not None:
+        assert (3 in kernels) == lane_pass
     assert lane.window_stats()[0] == gen.window_stats()[0] > 0
 
 
