@@ -111,20 +111,26 @@ __device__ __forceinline__ bool far_window_single(const double *zu, const float 
   };
   // one pass: zmax, the selection outside the set (whose moving members
   // must keep their sign: the smallest |z'| among those that may be
-  // positive is checked against the bound below) and the two best members
-  // of the set (z' desc, index asc)
+  // positive is checked against the bound below), and the set's positive
+  // members with their smallest z' and the best other members (all of them;
+  // moving ones)
   double zmax = 0.0, nearz = INFINITY;
   bool anyn = false;
   uint64_t sel = 0;
-  double v1 = -INFINITY, v2 = -INFINITY;
-  int j1 = -1, j2 = -1;
+  uint64_t posm = 0;
+  double minpos = INFINITY, bestneg = -INFINITY, bestnegA = -INFINITY;
   #pragma unroll 4
   for (int j = 0; j < M; ++j) {
     const double z = moved(j);
     if (z > -Hs) zmax = fmax(zmax, fabs(z));
     if (m1 >> j & 1) {
-      if (z > v1) { v2 = v1; j2 = j1; v1 = z; j1 = j; }
-      else if (z > v2) { v2 = z; j2 = j; }
+      if (z > 0.0) {
+        posm |= 1ull << j;
+        minpos = fmin(minpos, z);
+      } else {
+        bestneg = fmax(bestneg, z);
+        if (A >> j & 1) bestnegA = fmax(bestnegA, z);
+      }
     } else {
       if ((A >> j & 1) && z > -Hs) { nearz = fmin(nearz, fabs(z)); anyn = true; }
       if (z > 0.0) sel |= 1ull << j;
@@ -132,12 +138,38 @@ __device__ __forceinline__ bool far_window_single(const double *zu, const float 
   }
   const double bound = r * bmk * (1.0 + 0x1p-30) + 0x1p-36 * (1.0 + zmax + Hs + (lk + fabs(dl) + r) * bmk);
   if (anyn && !(nearz > bound)) return false;   // may change sign
-  // T: the c1 best positive members, taken two per pass over the set (the
-  // second best of a pass is the best once the first has joined T)
+  const int npos = popc64(posm);
+  if (npos <= c1) {
+    // at most c1 positive members: T is all of them, the best member left
+    // out the best of the others (the same tests as below, no more passes)
+    if (npos == c1 && bestneg > -Hs && !(minpos - bestneg > bound)) return false;
+    if (npos > 0 && !(minpos > bound)) return false;
+    if (npos < c1 && !(bestnegA < -bound)) return false;
+    sel |= posm;
+    double sum = 0.0;
+    for (uint64_t m = sel & A; m; m &= m - 1) {
+      const int j = __ffsll((long long)m) - 1;
+      sum = sum + (double)bu[j * K + k];
+    }
+    *cw = sum;
+    return true;
+  }
+  // more: T, the c1 best positive members (z' desc, index asc), taken two
+  // per pass over the set (the second best of a pass is the best once the
+  // first has joined T)
   uint64_t inT = 0;
   int nt = 0;
   double minT = INFINITY;
   for (;;) {
+    double v1 = -INFINITY, v2 = -INFINITY;
+    int j1 = -1, j2 = -1;
+    #pragma unroll 4
+    for (int j = 0; j < M; ++j) {
+      if (!(m1 >> j & 1) || (inT >> j & 1)) continue;
+      const double z = moved(j);
+      if (z > v1) { v2 = v1; j2 = j1; v1 = z; j1 = j; }
+      else if (z > v2) { v2 = z; j2 = j; }
+    }
     bool done = false;
     for (int h = 0; h < 2 && !done; ++h) {
       const double best = h == 0 ? v1 : v2;
@@ -154,15 +186,6 @@ __device__ __forceinline__ bool far_window_single(const double *zu, const float 
       done = true;
     }
     if (done) break;
-    v1 = -INFINITY; v2 = -INFINITY;
-    j1 = -1; j2 = -1;
-    #pragma unroll 4
-    for (int j = 0; j < M; ++j) {
-      if (!(m1 >> j & 1) || (inT >> j & 1)) continue;
-      const double z = moved(j);
-      if (z > v1) { v2 = v1; j2 = j1; v1 = z; j1 = j; }
-      else if (z > v2) { v2 = z; j2 = j; }
-    }
   }
   if (nt > 0 && !(minT > bound)) return false;
   if (nt < c1) {
