@@ -53,6 +53,12 @@ __device__ __forceinline__ XSum xs_plus(XSum a, XSum b) {
   r.lo = a.lo + b.lo;
   return r;
 }
+__device__ __forceinline__ XSum xs_minus(const XSum &a, const XSum &b) {
+  XSum r;
+  r.hi = a.hi - b.hi;
+  r.lo = a.lo - b.lo;
+  return r;
+}
 __device__ __forceinline__ void xs_add(XSum &a, double x) { a = xs_plus(a, xs_of(x)); }
 __device__ __forceinline__ XSum xs_zero() {
   XSum r;

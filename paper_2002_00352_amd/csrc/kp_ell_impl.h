@@ -194,8 +194,7 @@ __device__ __forceinline__ void lane_walk_pair(const SweepArgs &a, int M, int L,
     double now = 0.0;
     for (uint64_t m = Sc & A; m; m &= m - 1) now = now + bkc(__ffsll((long long)m) - 1, col);
     if (above != now) {
-      xs_atomic_add(&kcorr[k], above);
-      xs_atomic_add(&kcorr[k], -now);
+      xs_atomic_add_sum(&kcorr[k], xs_minus(xs_of(above), xs_of(now)));
     }
   }
 }

@@ -686,8 +686,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
               // the window is the window's set's
               walk = false;
               if (cw != v) {
-                xs_atomic_add(&kxs[k], cw);
-                xs_atomic_add(&kxs[k], -v);
+                xs_atomic_add_sum(&kxs[k], xs_minus(xs_of(cw), xs_of(v)));
               }
             } else {
               auto line = [&](int j, double &c, double &b) {
@@ -791,8 +790,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
               record_event(a, ks, k, best, v2, mode, hs, hc, hmin, hmax, kcnt, kovf, nstage, bid);
             }
             if (mode == KS_WINDOW && above != v) {
-              xs_atomic_add(&kxs[k], above);
-              xs_atomic_add(&kxs[k], -v);
+              xs_atomic_add_sum(&kxs[k], xs_minus(xs_of(above), xs_of(v)));
             }
           }
         }
@@ -1679,13 +1677,6 @@ __device__ __forceinline__ XSum fx_use(const FixArgs &f, int64_t i, int k) {
     });
   }
   return s;
-}
-
-__device__ __forceinline__ XSum xs_minus(const XSum &a, const XSum &b) {
-  XSum r;
-  r.hi = a.hi - b.hi;
-  r.lo = a.lo - b.lo;
-  return r;
 }
 
 // sampled users i = s * stride that are candidates: their keys
