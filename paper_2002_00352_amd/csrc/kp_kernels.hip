@@ -85,67 +85,57 @@ __device__ __forceinline__ void issue_entries(Prefetch &f, const ProbDev &pr, in
   }
 }
 
-// The same test for at most one binding set (top-Q and the like: set mask
-// m1 with cap c1, or no set), for any M, in O(M c1) with no per-item
-// state: items outside the set are selected when positive, so a moving one
-// must keep its sign over the window; inside the set the selection at c is
-// the c1 best positive members T (picked by repeated maxima, two per pass
-// over the set, ties to the lower index), and it stays the same when T
-// stays positive and the best other member stays below T (one gap: every
-// pair across it moves against each other by at most r bmax), or, when
-// fewer than c1 members are positive, when no moving member outside T can
-// turn positive.  Returns false when the test does not apply or fails; else
-// true with *cw = the selection's consumption of k.
-__device__ __forceinline__ bool far_window_single(const double *zu, const float *bu, int M, int K, int k,
-                                                  uint64_t A, double lk, double wlo, double whi, double bmk,
-                                                  uint64_t m1, int c1, double *cw) {
-  const double c = 0.5 * (wlo + whi);
-  const double r = fmax(whi - c, c - wlo);
-  const double dl = c - lk;
-  if (!(fabs(dl) > r)) return false;
-  const double Hs = r * bmk * (1.0 + 0x1p-30) + 0x1p-36 * (1.0 + (lk + fabs(dl) + r) * bmk);
+// The far-window test for at most one binding set (far_window_single) in
+// two parts.  First pass: zmax, the selection outside the set (whose moving
+// members must keep their sign: the smallest |z'| among those that may be
+// positive is checked against the bound), and the set's positive members
+// with their smallest z' and the best other members (all of them; moving
+// ones).  Lines at or below -Hs
+// never turn positive in the window (Hs may be an upper bound of the
+// window's reach: the tests only grow more cautious).
+struct FarPass {
+  double zmax = 0.0, nearz = INFINITY;
+  bool anyn = false;
+  uint64_t sel = 0, posm = 0;
+  double minpos = INFINITY, bestneg = -INFINITY, bestnegA = -INFINITY;
+};
+__device__ __forceinline__ void far_item(FarPass &f, double z, int j, bool moving, bool member, double Hs) {
+  if (z > -Hs) f.zmax = fmax(f.zmax, fabs(z));
+  if (member) {
+    if (z > 0.0) {
+      f.posm |= 1ull << j;
+      f.minpos = fmin(f.minpos, z);
+    } else {
+      f.bestneg = fmax(f.bestneg, z);
+      if (moving) f.bestnegA = fmax(f.bestnegA, z);
+    }
+  } else {
+    if (moving && z > -Hs) { f.nearz = fmin(f.nearz, fabs(z)); f.anyn = true; }
+    if (z > 0.0) f.sel |= 1ull << j;
+  }
+}
+// The rest of the test from its first pass (Hs: the exact reach r bmk plus
+// margin): at most c1 positive members -- T is all of them, the best member
+// left out the best of the others; more -- T by passes over the set.
+__device__ __forceinline__ bool far_finish(const FarPass &f, const double *zu, const float *bu, int M, int K,
+                                           int k, uint64_t A, double lk, double dl, double r, double bmk,
+                                           double Hs, uint64_t m1, int c1, double *cw) {
+  const double bound = r * bmk * (1.0 + 0x1p-30) + 0x1p-36 * (1.0 + f.zmax + Hs + (lk + fabs(dl) + r) * bmk);
+  if (f.anyn && !(f.nearz > bound)) return false;   // may change sign
   auto moved = [&](int j) -> double {
     const double b = (A >> j & 1) ? (double)bu[j * K + k] : 0.0;
     const double s = dl * b;
     return zu[j] - s;
   };
-  // one pass: zmax, the selection outside the set (whose moving members
-  // must keep their sign: the smallest |z'| among those that may be
-  // positive is checked against the bound below), and the set's positive
-  // members with their smallest z' and the best other members (all of them;
-  // moving ones)
-  double zmax = 0.0, nearz = INFINITY;
-  bool anyn = false;
-  uint64_t sel = 0;
-  uint64_t posm = 0;
-  double minpos = INFINITY, bestneg = -INFINITY, bestnegA = -INFINITY;
-  #pragma unroll 4
-  for (int j = 0; j < M; ++j) {
-    const double z = moved(j);
-    if (z > -Hs) zmax = fmax(zmax, fabs(z));
-    if (m1 >> j & 1) {
-      if (z > 0.0) {
-        posm |= 1ull << j;
-        minpos = fmin(minpos, z);
-      } else {
-        bestneg = fmax(bestneg, z);
-        if (A >> j & 1) bestnegA = fmax(bestnegA, z);
-      }
-    } else {
-      if ((A >> j & 1) && z > -Hs) { nearz = fmin(nearz, fabs(z)); anyn = true; }
-      if (z > 0.0) sel |= 1ull << j;
-    }
-  }
-  const double bound = r * bmk * (1.0 + 0x1p-30) + 0x1p-36 * (1.0 + zmax + Hs + (lk + fabs(dl) + r) * bmk);
-  if (anyn && !(nearz > bound)) return false;   // may change sign
-  const int npos = popc64(posm);
+  uint64_t sel = f.sel;
+  const int npos = popc64(f.posm);
   if (npos <= c1) {
     // at most c1 positive members: T is all of them, the best member left
     // out the best of the others (the same tests as below, no more passes)
-    if (npos == c1 && bestneg > -Hs && !(minpos - bestneg > bound)) return false;
-    if (npos > 0 && !(minpos > bound)) return false;
-    if (npos < c1 && !(bestnegA < -bound)) return false;
-    sel |= posm;
+    if (npos == c1 && f.bestneg > -Hs && !(f.minpos - f.bestneg > bound)) return false;
+    if (npos > 0 && !(f.minpos > bound)) return false;
+    if (npos < c1 && !(f.bestnegA < -bound)) return false;
+    sel |= f.posm;
     double sum = 0.0;
     for (uint64_t m = sel & A; m; m &= m - 1) {
       const int j = __ffsll((long long)m) - 1;
@@ -204,6 +194,35 @@ __device__ __forceinline__ bool far_window_single(const double *zu, const float 
   }
   *cw = sum;
   return true;
+}
+
+// The same test for at most one binding set (top-Q and the like: set mask
+// m1 with cap c1, or no set), for any M, in O(M c1) with no per-item
+// state: items outside the set are selected when positive, so a moving one
+// must keep its sign over the window; inside the set the selection at c is
+// the c1 best positive members T (picked by repeated maxima, two per pass
+// over the set, ties to the lower index), and it stays the same when T
+// stays positive and the best other member stays below T (one gap: every
+// pair across it moves against each other by at most r bmax), or, when
+// fewer than c1 members are positive, when no moving member outside T can
+// turn positive.  Returns false when the test does not apply or fails; else
+// true with *cw = the selection's consumption of k.
+__device__ __forceinline__ bool far_window_single(const double *zu, const float *bu, int M, int K, int k,
+                                                  uint64_t A, double lk, double wlo, double whi, double bmk,
+                                                  uint64_t m1, int c1, double *cw) {
+  const double c = 0.5 * (wlo + whi);
+  const double r = fmax(whi - c, c - wlo);
+  const double dl = c - lk;
+  if (!(fabs(dl) > r)) return false;
+  const double Hs = r * bmk * (1.0 + 0x1p-30) + 0x1p-36 * (1.0 + (lk + fabs(dl) + r) * bmk);
+  FarPass f;
+  #pragma unroll 4
+  for (int j = 0; j < M; ++j) {
+    const double b = (A >> j & 1) ? (double)bu[j * K + k] : 0.0;
+    const double s = dl * b;
+    far_item(f, zu[j] - s, j, (A >> j & 1) != 0, (m1 >> j & 1) != 0, Hs);
+  }
+  return far_finish(f, zu, bu, M, K, k, A, lk, dl, r, bmk, Hs, m1, c1, cw);
 }
 
 // A window that does not contain lambda_k^t (an alternation window around
@@ -641,13 +660,50 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
       double v = 0.0;
       uint64_t A = 0;     // SCD: moving lines, b_jk > 0
       float bmk = 0.0f;   // SCD: their largest cost
+      // a window away from lambda_k^t with at most one binding set: the
+      // far-window test's first pass runs in the same pass over the items
+      // (its cut at -Hs taken with the user's largest cost over every
+      // knapsack, an upper bound of bmk: only more cautious)
+      bool fused = false, fused_ok = false;
+      double fused_cw = 0.0;
       if (SCD) {
-        #pragma unroll 4
-        for (int j = 0; j < M; ++j) {
-          const float bj = bu[j * K + k];
-          if (S0 >> j & 1) v = v + (double)bj;
-          if (bj > 0.0f) A |= 1ull << j;
-          bmk = bj > bmk ? bj : bmk;
+        double fr = 0.0, fdl = 0.0;
+        if (kmode[k] == KS_WINDOW && a.tree.L <= 1 && kwide[0] > 0.0) {
+          const double wlo = kst[k].wlo, whi = kst[k].whi;
+          const double c = 0.5 * (wlo + whi);
+          fr = fmax(whi - c, c - wlo);
+          fdl = c - lam[k];
+          fused = fabs(fdl) > fr;
+        }
+        if (fused) {
+          const double *zu = pt + u * M;
+          const double lk = lam[k];
+          const uint64_t m1 = a.tree.L == 1 ? a.tree.mask[0] : 0ull;
+          const double bmu = (double)__uint_as_float(((const unsigned int *)ugap)[4 * u + 2]);
+          const double Hup = fr * bmu * (1.0 + 0x1p-30) + 0x1p-36 * (1.0 + (lk + fabs(fdl) + fr) * bmu);
+          FarPass f;
+          #pragma unroll 4
+          for (int j = 0; j < M; ++j) {
+            const float bj = bu[j * K + k];
+            if (S0 >> j & 1) v = v + (double)bj;
+            const bool mov = bj > 0.0f;
+            if (mov) A |= 1ull << j;
+            bmk = bj > bmk ? bj : bmk;
+            const double b = mov ? (double)bj : 0.0;
+            const double sh = fdl * b;
+            far_item(f, zu[j] - sh, j, mov, (m1 >> j & 1) != 0, Hup);
+          }
+          const double Hs = fr * (double)bmk * (1.0 + 0x1p-30) + 0x1p-36 * (1.0 + (lk + fabs(fdl) + fr) * (double)bmk);
+          fused_ok = far_finish(f, zu, bu, M, K, k, A, lk, fdl, fr, (double)bmk, Hs, m1,
+                                a.tree.L == 1 ? a.tree.cap[0] : 0, &fused_cw);
+        } else {
+          #pragma unroll 4
+          for (int j = 0; j < M; ++j) {
+            const float bj = bu[j * K + k];
+            if (S0 >> j & 1) v = v + (double)bj;
+            if (bj > 0.0f) A |= 1ull << j;
+            bmk = bj > bmk ? bj : bmk;
+          }
         }
       } else {
         // the selected items only, in ascending index order
@@ -667,7 +723,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
           if (walk && mode == KS_WINDOW) {
             // no breakpoint of this user inside the window: nothing to emit
             // and its consumption just above the window is v_ik (no correction)
-            double cw = 0.0;
+            double cw = fused_cw;
             // the filter's scale: |top p~| + H, with H from the user's
             // largest cost and the widest window
             const float bmu = __uint_as_float(((const unsigned int *)ugap)[4 * u + 2]);
@@ -676,12 +732,13 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
             const double gscale = fabs(zu[perm[u * M]]) + Hu;
             if (window_calm(ugap[2 * u], gscale, kst[k].hw, (double)bmk, lk)) {
               walk = false;
-            } else if (a.tree.L <= 1
-                           ? far_window_single(zu, bu, M, K, k, A, lk, kst[k].wlo, kst[k].whi, (double)bmk,
-                                               a.tree.L == 1 ? a.tree.mask[0] : 0ull,
-                                               a.tree.L == 1 ? a.tree.cap[0] : 0, &cw)
-                           : far_window_set(zu, bu, M, K, k, A, lk, kst[k].wlo, kst[k].whi, (double)bmk, a.tree,
-                                            &cw)) {
+            } else if (fused ? fused_ok
+                             : a.tree.L <= 1
+                                 ? far_window_single(zu, bu, M, K, k, A, lk, kst[k].wlo, kst[k].whi, (double)bmk,
+                                                     a.tree.L == 1 ? a.tree.mask[0] : 0ull,
+                                                     a.tree.L == 1 ? a.tree.cap[0] : 0, &cw)
+                                 : far_window_set(zu, bu, M, K, k, A, lk, kst[k].wlo, kst[k].whi, (double)bmk,
+                                                  a.tree, &cw)) {
               // no breakpoint inside the window: its consumption just above
               // the window is the window's set's
               walk = false;
