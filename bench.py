@@ -247,7 +247,11 @@ def summarize_trace(trace_dir, bench_log, kernel_subs):
     """Markdown summary of a rocprofv3 --kernel-trace --stats run of bench.py:
     the per-kernel statistics and the average duration of the timed sweep
     passes (the last `launches` dispatches of each kernel of a pass;
-    kernel_subs: "|"-separated name fragments of the kernels of one pass)."""
+    kernel_subs: "|"-separated name fragments of the kernels of one pass; a
+    fragment "a,b" takes the dispatches of either kernel (passes that run
+    one or the other); a trailing "#n" sets the number of dispatches taken,
+    e.g. every dispatch of the timed iterations of a graph-captured batched
+    plan)."""
     rec = next(json.loads(l) for l in open(bench_log) if l.startswith("{"))
     stats = _csv_rows(os.path.join(trace_dir, "run_kernel_stats.csv"))
     trace = _csv_rows(os.path.join(trace_dir, "run_kernel_trace.csv"))
@@ -255,6 +259,9 @@ def summarize_trace(trace_dir, bench_log, kernel_subs):
     # steps * passes_per_step dispatches of the batched kernel
     batched = rec["roofline"]["kernel"].startswith("k_sweep_batched")
     n = round(rec["steps"] * rec["passes_per_step"]) if batched else rec["roofline"]["launches"]
+    if "#" in kernel_subs:
+        kernel_subs, cnt = kernel_subs.rsplit("#", 1)
+        n = int(cnt)
     subs = kernel_subs.split("|")
     # the timed passes end where the streaming ceiling's first read starts
     # (the benchmark measures it right after them)
@@ -262,7 +269,7 @@ def summarize_trace(trace_dir, bench_log, kernel_subs):
     end = min(marks) if marks else None
     per = []
     for sub in subs:
-        disp = sorted((r for r in trace if sub in r["Kernel_Name"]
+        disp = sorted((r for r in trace if any(x in r["Kernel_Name"] for x in sub.split(","))
                        and (end is None or int(r["Start_Timestamp"]) < end)),
                       key=lambda r: int(r["Start_Timestamp"]))
         per.append([(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6 for r in disp[-n:]])
