@@ -666,7 +666,13 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const TileGeom &g
       // knapsack, an upper bound of bmk: only more cautious)
       bool fused = false, fused_ok = false;
       double fused_cw = 0.0;
-      if (SCD) {
+      // a user with no line above -H (its gap record untouched) is calm in
+      // every window: only its consumption is needed (A stays empty, so no
+      // test or walk follows)
+      const bool settled = SCD && kmode[k] == KS_WINDOW && kwide[0] > 0.0 && !(ugap[2 * u] < 1e300);
+      if (settled) {
+        for (uint64_t m = S0; m; m &= m - 1) v = v + (double)bu[(__ffsll((long long)m) - 1) * K + k];
+      } else if (SCD) {
         double fr = 0.0, fdl = 0.0;
         if (kmode[k] == KS_WINDOW && a.tree.L <= 1 && kwide[0] > 0.0) {
           const double wlo = kst[k].wlo, whi = kst[k].whi;
