@@ -248,7 +248,7 @@ def summarize_trace(trace_dir, bench_log, kernel_subs):
     the per-kernel statistics and the average duration of the timed sweep
     passes (the last `launches` dispatches of each kernel of a pass;
     kernel_subs: "|"-separated name fragments of the kernels of one pass; a
-    fragment "a,b" takes the dispatches of either kernel (passes that run
+    fragment "a/b" takes the dispatches of either kernel (passes that run
     one or the other); a trailing "#n" sets the number of dispatches taken,
     e.g. every dispatch of the timed iterations of a graph-captured batched
     plan)."""
@@ -269,7 +269,7 @@ def summarize_trace(trace_dir, bench_log, kernel_subs):
     end = min(marks) if marks else None
     per = []
     for sub in subs:
-        disp = sorted((r for r in trace if any(x in r["Kernel_Name"] for x in sub.split(","))
+        disp = sorted((r for r in trace if any(x in r["Kernel_Name"] for x in sub.split("/"))
                        and (end is None or int(r["Start_Timestamp"]) < end)),
                       key=lambda r: int(r["Start_Timestamp"]))
         per.append([(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6 for r in disp[-n:]])
