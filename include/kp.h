@@ -288,8 +288,10 @@ kp_status kp_set_batched_tuning(void *ctx, int32_t lds_bytes, int32_t block_mult
    pass of kp_primal_fixup) of dense costs with M <= 16 and K <= 16 run a
    lane-per-user kernel (one wave per 48-user tile, costs staged in LDS), and
    so do the SCD passes of such problems in which every threshold search
-   starts with a window around lambda_k^t (a window around lambda_k^{t-2} of
-   alternating multipliers, or any other search mode: the general kernel).  The
+   starts with a window around lambda_k^t, or with windows away from it when
+   a probe of 4096 users finds (almost) every line too far below zero to turn
+   positive in any window (otherwise windows around lambda_k^{t-2} of
+   alternating multipliers, and any other search mode: the general kernel).  The
    library keeps no record of a problem's structure between calls: the
    declaration travels with the problem.  kp_set_kernel_choice(ctx, 0)
    forces the general kernel for both (x and R are identical either way; g

@@ -542,7 +542,8 @@ struct SweepWs {
   uint32_t emit_cap;
   unsigned int *flist, *fcount;   // users listed by the window pass
   uint32_t fcap;
-  int *modes;           // [0] knapsacks with a window, [1] with another search mode, [2] alternation windows
+  int *modes;           // [0] knapsacks with a window, [1] with another search mode, [2] alternation
+                        // windows, [3] dense probe: sampled users with a line above -H
   char *stat;           // status block, followed by the histograms (SCD)
   size_t stat_bytes;    // the status block and the histograms
 };
