@@ -57,6 +57,18 @@ __device__ __forceinline__ void stage_x4(const void *src, int nbytes, void *dst,
     __builtin_amdgcn_global_load_lds((const void *)(s + c), (lds_void_t *)(d + c), 16, 0, 0);
 }
 
+// Sum of the entries 0, ST, 2 ST, ... of a 64-entry statistics row in four
+// interleaved chains combined in a fixed order.  The stride is a constant,
+// so the reads carry immediate offsets and are issued back to back.
+template <int ST>
+__device__ __forceinline__ double row_part_sum(const double *row) {
+  constexpr int LEN = 64 / ST;
+  double c[4] = {0.0, 0.0, 0.0, 0.0};
+  #pragma unroll
+  for (int u = 0; u < LEN; ++u) c[u & 3] = c[u & 3] + row[u * ST];
+  return (c[0] + c[1]) + (c[2] + c[3]);
+}
+
 // lambda_k and the window bound wA_k (fp32, rounded up) of the window main pass
 struct LamW {
   double lam;
@@ -440,7 +452,7 @@ template <int MODE> struct EllWaves { static constexpr int value = MODE == 2 ? 3
 
 // EM: the item-count class (8, 10, 12, 16); EXACT: M equals EM, so every
 // test of an item index against M folds away.
-template <int D, int MODE, int EM, bool EXACT, int WPB>
+template <int D, int MODE, int EM, bool EXACT, int WPB, bool CMP>
 __global__ void __launch_bounds__(WPB * 64)
 __attribute__((amdgpu_waves_per_eu(EllWaves<MODE>::value, 8)))
 k_ell(const SweepArgs a, const EllGeom g) {
@@ -452,6 +464,9 @@ k_ell(const SweepArgs a, const EllGeom g) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int M = EXACT ? EM : g.M, K = g.K;
+  // g.compact, fixed at compile time for the kernels instantiated for one
+  // item count: the other path's arrays then need no registers
+  const bool compact = EXACT ? CMP : g.compact != 0;
   size_t off = 0;
   auto carve = [&](size_t bytes) { unsigned char *p = smem + off; off += (bytes + 15) & ~(size_t)15; return p; };
   double *lam = (double *)carve((size_t)(K + 1) * 8);   // [K] = 0 for the clamped reads
@@ -760,7 +775,7 @@ k_ell(const SweepArgs a, const EllGeom g) {
     // KP_SEL_MAX * D entries instead of M * D.  Unused slots hold (-1, 0).
     int sk[KP_SEL_MAX * D];
     float sv_[KP_SEL_MAX * D];
-    if (STAGED && g.compact) {
+    if (STAGED && compact) {
       uint32_t sm = (uint32_t)S;
       const int32_t *scl = sc + lane * M * D;
       const float *svl = sv + lane * M * D;
@@ -778,6 +793,13 @@ k_ell(const SweepArgs a, const EllGeom g) {
         }
       }
     }
+    // Last read of the staged tile: the statistics rows and the breakpoint
+    // phase's scratch are written over it (as other types, which the
+    // compiler would otherwise take for separate memory), and another
+    // lane's reads must not move below those writes.  LDS operations of a
+    // wave run in program order, so keeping the compiler's order suffices.
+    __builtin_amdgcn_wave_barrier();
+    __asm__ volatile("" ::: "memory");
     // ---- post-processing bins (Sec. 5.4): a candidate's bin by G_i and its
     // costs on the violated knapsacks into the bin's exact sums ----
     if (MODE == KM_FIX && act) {
@@ -792,7 +814,7 @@ k_ell(const SweepArgs a, const EllGeom g) {
         cand = true;
         xs_atomic_add(&row[v], (double)c);
       };
-      if (g.compact) {
+      if (compact) {
         #pragma unroll
         for (int e = 0; e < KP_SEL_MAX * D; ++e) add(sk[e], sv_[e]);
       } else {
@@ -883,7 +905,7 @@ k_ell(const SweepArgs a, const EllGeom g) {
           for (int q = 0; q < nq; ++q) rows[q * 65 + lane] = 0.0;
           if ((unsigned)(K - c0) < (unsigned)nq) rows[(K - c0) * 65 + lane] = Gi;
           if ((unsigned)(K + 1 - c0) < (unsigned)nq) rows[(K + 1 - c0) * 65 + lane] = Pi;
-          if (g.compact) {
+          if (compact) {
             #pragma unroll
             for (int e = 0; e < KP_SEL_MAX * D; ++e) {
               const int q = sk[e] - c0;
@@ -914,23 +936,21 @@ k_ell(const SweepArgs a, const EllGeom g) {
           __asm__ volatile("" ::: "memory");
           int lg = 0;
           while ((2 << lg) * nq <= 64) ++lg;
-          const int q = lane >> lg, len = 64 >> lg, step = 1 << lg;
+          const int q = lane >> lg, step = 1 << lg;
           double sum = 0.0;
           if (q < nq) {
             // part i sums the entries i, i + step, ... of the row (parts on
-            // distinct banks) in four interleaved chains, combined in a
-            // fixed order
+            // distinct banks)
             const double *row = rows + q * 65 + (lane & (step - 1));
-            double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
-            int u = 0;
-            for (; u + 4 <= len; u += 4) {
-              c0 = c0 + row[u * step];
-              c1 = c1 + row[(u + 1) * step];
-              c2 = c2 + row[(u + 2) * step];
-              c3 = c3 + row[(u + 3) * step];
+            switch (lg) {
+              case 0: sum = row_part_sum<1>(row); break;
+              case 1: sum = row_part_sum<2>(row); break;
+              case 2: sum = row_part_sum<4>(row); break;
+              case 3: sum = row_part_sum<8>(row); break;
+              case 4: sum = row_part_sum<16>(row); break;
+              case 5: sum = row_part_sum<32>(row); break;
+              default: sum = row_part_sum<64>(row); break;
             }
-            for (; u < len; ++u) c0 = c0 + row[u * step];
-            sum = (c0 + c1) + (c2 + c3);
           }
           for (int o = 1; o < (1 << lg); o <<= 1) sum = sum + __shfl_xor(sum, o, 64);
           if (q < nq && (lane & ((1 << lg) - 1)) == 0)
@@ -1029,10 +1049,10 @@ size_t kp_ell_lds_bytes(int M, int K, int D, int L, int mode, int *region_out);
 // Persistent launch: never more blocks than can be resident at once (the
 // tile loop strides over the rest), so no block waits for another to finish
 // and every CU stays busy to the end.  grid <= 0 asks for exactly that many.
-template <int D, int MODE, int EM, bool EXACT, int WPB>
+template <int D, int MODE, int EM, bool EXACT, int WPB, bool CMP = false>
 static hipError_t launch_ell_t(const SweepArgs &a, const EllGeom &g, size_t lds, int grid,
                                hipStream_t stream, int *used) {
-  const void *fn = (const void *)k_ell<D, MODE, EM, EXACT, WPB>;
+  const void *fn = (const void *)k_ell<D, MODE, EM, EXACT, WPB, CMP>;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -1050,18 +1070,29 @@ static hipError_t launch_ell_t(const SweepArgs &a, const EllGeom &g, size_t lds,
   const int resident = cus * per_cu;
   if (grid <= 0 || grid > resident) grid = resident;
   if (used) *used = grid;
-  hipLaunchKernelGGL((k_ell<D, MODE, EM, EXACT, WPB>), dim3(grid), dim3(WPB * 64), lds, stream, a, g);
+  hipLaunchKernelGGL((k_ell<D, MODE, EM, EXACT, WPB, CMP>), dim3(grid), dim3(WPB * 64), lds, stream, a, g);
   return hipGetLastError();
+}
+
+// The kernels for one item count, with the statistics path of g.compact
+// (the listed users' pass keeps no statistics: one kernel)
+template <int D, int MODE, int EM, int WPB>
+static hipError_t launch_ell_x(const SweepArgs &a, const EllGeom &g, size_t lds, int grid,
+                               hipStream_t stream, int *used) {
+  if constexpr (MODE != KM_WFAIL) {
+    if (g.compact) return launch_ell_t<D, MODE, EM, true, WPB, true>(a, g, lds, grid, stream, used);
+  }
+  return launch_ell_t<D, MODE, EM, true, WPB, false>(a, g, lds, grid, stream, used);
 }
 
 template <int D, int MODE, int WPB>
 static hipError_t launch_ell_mw(const SweepArgs &a, const EllGeom &g, size_t lds, int grid,
                                 hipStream_t stream, int *used) {
   switch (g.M) {
-    case 8: return launch_ell_t<D, MODE, 8, true, WPB>(a, g, lds, grid, stream, used);
-    case 10: return launch_ell_t<D, MODE, 10, true, WPB>(a, g, lds, grid, stream, used);
-    case 12: return launch_ell_t<D, MODE, 12, true, WPB>(a, g, lds, grid, stream, used);
-    case 16: return launch_ell_t<D, MODE, 16, true, WPB>(a, g, lds, grid, stream, used);
+    case 8: return launch_ell_x<D, MODE, 8, WPB>(a, g, lds, grid, stream, used);
+    case 10: return launch_ell_x<D, MODE, 10, WPB>(a, g, lds, grid, stream, used);
+    case 12: return launch_ell_x<D, MODE, 12, WPB>(a, g, lds, grid, stream, used);
+    case 16: return launch_ell_x<D, MODE, 16, WPB>(a, g, lds, grid, stream, used);
     default: break;
   }
   if (g.M <= 8) return launch_ell_t<D, MODE, 8, false, WPB>(a, g, lds, grid, stream, used);
@@ -1079,9 +1110,9 @@ static hipError_t launch_ell_m(const SweepArgs &a, const EllGeom &g, size_t lds,
   return launch_ell_mw<D, MODE, EW>(a, g, lds, grid, stream, used);
 }
 
-template <int D, int MODE, int EM, bool EXACT, int WPB>
+template <int D, int MODE, int EM, bool EXACT, int WPB, bool CMP = false>
 static int resident_blocks_t(size_t lds) {
-  const void *fn = (const void *)k_ell<D, MODE, EM, EXACT, WPB>;
+  const void *fn = (const void *)k_ell<D, MODE, EM, EXACT, WPB, CMP>;
   if (lds > 64 * 1024 &&
       hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return 0;
@@ -1093,13 +1124,25 @@ static int resident_blocks_t(size_t lds) {
   return per_cu * cus;
 }
 
+// the larger of the two statistics paths' counts (an upper bound for the
+// per-block buffers; a launch never exceeds its own kernel's count)
+template <int D, int MODE, int EM, int WPB>
+static int resident_blocks_x(size_t lds) {
+  const int r = resident_blocks_t<D, MODE, EM, true, WPB, false>(lds);
+  if constexpr (MODE != KM_WFAIL) {
+    const int c = resident_blocks_t<D, MODE, EM, true, WPB, true>(lds);
+    return c > r ? c : r;
+  }
+  return r;
+}
+
 template <int D, int MODE, int WPB>
 static int resident_blocks_mw(int M, size_t lds) {
   switch (M) {
-    case 8: return resident_blocks_t<D, MODE, 8, true, WPB>(lds);
-    case 10: return resident_blocks_t<D, MODE, 10, true, WPB>(lds);
-    case 12: return resident_blocks_t<D, MODE, 12, true, WPB>(lds);
-    case 16: return resident_blocks_t<D, MODE, 16, true, WPB>(lds);
+    case 8: return resident_blocks_x<D, MODE, 8, WPB>(lds);
+    case 10: return resident_blocks_x<D, MODE, 10, WPB>(lds);
+    case 12: return resident_blocks_x<D, MODE, 12, WPB>(lds);
+    case 16: return resident_blocks_x<D, MODE, 16, WPB>(lds);
     default: break;
   }
   if (M <= 8) return resident_blocks_t<D, MODE, 8, false, WPB>(lds);
