@@ -726,10 +726,18 @@ def main():
     if n_d:
         dd_ms = ms_d / n_d
         dd_gbs = bytes_d / n_d / (dd_ms * 1e-3) / 1e9
+        # frac counts the ABI's bytes (the rule above); read_GBs / frac_read
+        # count the bytes the kernel reads (the lean kernel skips rowptr),
+        # ceiling_frac: the streaming probe's time over the same arrays
+        # against the sweep's
         rec["dd_sweep"] = {"steps": args.dd_steps, "ms_per_step": (t1 - t0) * 1e3 / args.dd_steps,
                            "user_solves_per_s": N * args.dd_steps / (t1 - t0),
                            "kernel_avg_ms": dd_ms, "achieved_GBs": dd_gbs,
-                           "frac": dd_gbs / HBM_PEAK_GBS}
+                           "frac": dd_gbs / HBM_PEAK_GBS,
+                           "read_bytes": ceiling["bytes"],
+                           "read_GBs": ceiling["bytes"] / (dd_ms * 1e-3) / 1e9,
+                           "frac_read": ceiling["bytes"] / (dd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                           "ceiling_frac": ceiling["ms"] / dd_ms}
     # the same DD steps through the autograd form (forward: evaluation kernel,
     # backward: the gradient kernel from the saved consumption)
     lam_ag = [lam.clone()]

@@ -32,6 +32,10 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 typedef __attribute__((address_space(3))) void lds_void_t;
 
+// Cache policy of the staging loads: nontemporal (every input byte is read
+// once per pass, so keeping it in the caches only evicts other data).
+#define KP_STAGE_NT 2
+
 // Copy n dwords from global src to LDS dst (coalesced; lanes past the end
 // reload the last dword into the padded tail of dst).
 __device__ __forceinline__ void stage_dwords(const void *src, int n, void *dst, int lane) {
@@ -40,7 +44,7 @@ __device__ __forceinline__ void stage_dwords(const void *src, int n, void *dst, 
   for (int c = 0; c * 64 < n; ++c) {
     int i = c * 64 + lane;
     i = i < n ? i : n - 1;
-    __builtin_amdgcn_global_load_lds((const void *)(s + i), (lds_void_t *)(d + c * 64), 4, 0, 0);
+    __builtin_amdgcn_global_load_lds((const void *)(s + i), (lds_void_t *)(d + c * 64), 4, 0, KP_STAGE_NT);
   }
 }
 
@@ -52,9 +56,9 @@ __device__ __forceinline__ void stage_x4(const void *src, int nbytes, void *dst,
   unsigned char *d = (unsigned char *)dst;
   int c = 0;
   for (; c + 1024 <= nbytes; c += 1024)
-    __builtin_amdgcn_global_load_lds((const void *)(s + c), (lds_void_t *)(d + c), 16, 0, 0);
+    __builtin_amdgcn_global_load_lds((const void *)(s + c), (lds_void_t *)(d + c), 16, 0, KP_STAGE_NT);
   if (c < nbytes && lane * 16 < nbytes - c)
-    __builtin_amdgcn_global_load_lds((const void *)(s + c), (lds_void_t *)(d + c), 16, 0, 0);
+    __builtin_amdgcn_global_load_lds((const void *)(s + c), (lds_void_t *)(d + c), 16, 0, KP_STAGE_NT);
 }
 
 // Sum of the entries 0, ST, 2 ST, ... of a 64-entry statistics row in four

@@ -2592,21 +2592,22 @@ hipError_t kp_launch_fill_f64(double *dst, int64_t n, double v, hipStream_t stre
 // into one word; XOR is order-free, so the word is deterministic.
 // ---------------------------------------------------------------------------
 #define SR_NT 256
+typedef unsigned int sr_v4u __attribute__((ext_vector_type(4)));
 __global__ void __launch_bounds__(SR_NT) k_stream_read(const uint4 *src, int64_t n16, unsigned long long *out) {
-  uint4 acc = make_uint4(0u, 0u, 0u, 0u);
+  // eight nontemporal 16-byte loads per thread in flight (the sweep kernels'
+  // staging uses the same cache policy)
+  const sr_v4u *s = (const sr_v4u *)src;
+  sr_v4u acc = {0u, 0u, 0u, 0u};
   const int64_t stride = (int64_t)gridDim.x * SR_NT;
   int64_t i = (int64_t)blockIdx.x * SR_NT + threadIdx.x;
-  for (; i + 3 * stride < n16; i += 4 * stride) {
-    const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
-    acc.x ^= a.x ^ b.x ^ c.x ^ d.x;
-    acc.y ^= a.y ^ b.y ^ c.y ^ d.y;
-    acc.z ^= a.z ^ b.z ^ c.z ^ d.z;
-    acc.w ^= a.w ^ b.w ^ c.w ^ d.w;
+  for (; i + 7 * stride < n16; i += 8 * stride) {
+    sr_v4u v[8];
+    #pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = __builtin_nontemporal_load(s + i + u * stride);
+    #pragma unroll
+    for (int u = 0; u < 8; ++u) acc ^= v[u];
   }
-  for (; i < n16; i += stride) {
-    const uint4 a = src[i];
-    acc.x ^= a.x; acc.y ^= a.y; acc.z ^= a.z; acc.w ^= a.w;
-  }
+  for (; i < n16; i += stride) acc ^= __builtin_nontemporal_load(s + i);
   unsigned long long v = ((unsigned long long)(acc.x ^ acc.z) << 32) | (unsigned long long)(acc.y ^ acc.w);
   for (int off = 32; off > 0; off >>= 1) v ^= __shfl_xor(v, off, 64);
   __shared__ unsigned long long part[SR_NT / 64];
