@@ -768,6 +768,11 @@ ELL_CASES = [
     ("csr-d2-laminar-M16", lambda: kpgen.make_instance(1500, 16, 7, seed=42, csr_d=2, budget_frac=0.08,
                                                        tree=random_laminar(16, np.random.default_rng(4)))),
     ("c3-single-user", lambda: kpgen.config_instance(3, N=1)),
+    # K = 40 with M = 16, D = 2: 33 or more statistics rows in one chunk (one
+    # lane per row part) and a short remainder chunk; top-4 takes the
+    # compact statistics path, top-6 the other one
+    ("csr-d2-M16-K40-top4", lambda: kpgen.make_instance(2100, 16, 40, seed=43, Q=4, csr_d=2, budget_frac=0.1)),
+    ("csr-d2-M16-K40-top6", lambda: kpgen.make_instance(2100, 16, 40, seed=44, Q=6, csr_d=2, budget_frac=0.1)),
 ]
 
 
