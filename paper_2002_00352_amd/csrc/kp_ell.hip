@@ -34,10 +34,13 @@ static size_t ell_lds(int M, int K, int D, int L, int mode, int waves, int *regi
   return s;
 }
 
-// Waves per block of a mode: 8 for the full-search pass when its LDS fits,
-// else 4.
+// Waves per block of a mode: 8 for the full-search pass of the kernels
+// instantiated for the exact item count when its LDS fits, else 4 (with 8
+// waves a block may hold 256 registers per lane, and the kernels for a
+// class of item counts would spill).
 int kp_ell_waves(int M, int K, int D, int L, int mode) {
-  if (mode == KM_SCD && ell_lds(M, K, D, L, mode, 8, nullptr) <= (size_t)160 * 1024) return 8;
+  const bool exact = M == 8 || M == 10 || M == 12 || M == 16;
+  if (mode == KM_SCD && exact && ell_lds(M, K, D, L, mode, 8, nullptr) <= (size_t)160 * 1024) return 8;
   return EW;
 }
 

@@ -450,15 +450,21 @@ enum { KM_EVAL = 0, KM_SCD = 1, KM_WMAIN = 2, KM_WFAIL = 3, KM_FIX = 4 };
 // block (one block per compute unit, two waves per SIMD) rather than 4 (which
 // its LDS would hold to one block).
 
-// The window main pass is held to 3 waves per SIMD, the occupancy its LDS
-// allows (without the hint it compiles just above the register limit).
-template <int MODE> struct EllWaves { static constexpr int value = MODE == 2 ? 3 : 1; };
+// The window main pass of the exact kernels up to 10 items is held to 3
+// waves per SIMD, the occupancy its LDS allows (without the hint it compiles
+// just above the register limit).  The larger ones would spill registers
+// under that limit; a build of one of them that spilled gave wrong window
+// sums where the same source without the limit did not, so they keep every
+// register they need.
+template <int MODE, int EM, bool EXACT> struct EllWaves {
+  static constexpr int value = (MODE == 2 && EXACT && EM <= 10) ? 3 : 1;
+};
 
 // EM: the item-count class (8, 10, 12, 16); EXACT: M equals EM, so every
 // test of an item index against M folds away.
 template <int D, int MODE, int EM, bool EXACT, int WPB, bool CMP>
 __global__ void __launch_bounds__(WPB * 64)
-__attribute__((amdgpu_waves_per_eu(EllWaves<MODE>::value, 8)))
+__attribute__((amdgpu_waves_per_eu(EllWaves<MODE, EM, EXACT>::value, 8)))
 k_ell(const SweepArgs a, const EllGeom g) {
   constexpr int EWM = WPB;
   constexpr int ENT = EWM * 64;
@@ -1099,10 +1105,14 @@ static hipError_t launch_ell_mw(const SweepArgs &a, const EllGeom &g, size_t lds
     case 16: return launch_ell_x<D, MODE, 16, WPB>(a, g, lds, grid, stream, used);
     default: break;
   }
-  if (g.M <= 8) return launch_ell_t<D, MODE, 8, false, WPB>(a, g, lds, grid, stream, used);
-  if (g.M <= 10) return launch_ell_t<D, MODE, 10, false, WPB>(a, g, lds, grid, stream, used);
-  if (g.M <= 12) return launch_ell_t<D, MODE, 12, false, WPB>(a, g, lds, grid, stream, used);
-  return launch_ell_t<D, MODE, 16, false, WPB>(a, g, lds, grid, stream, used);
+  if constexpr (WPB != EW) {
+    return hipErrorInvalidValue;   // 8-wave blocks are launched only for the exact item counts
+  } else {
+    if (g.M <= 8) return launch_ell_t<D, MODE, 8, false, WPB>(a, g, lds, grid, stream, used);
+    if (g.M <= 10) return launch_ell_t<D, MODE, 10, false, WPB>(a, g, lds, grid, stream, used);
+    if (g.M <= 12) return launch_ell_t<D, MODE, 12, false, WPB>(a, g, lds, grid, stream, used);
+    return launch_ell_t<D, MODE, 16, false, WPB>(a, g, lds, grid, stream, used);
+  }
 }
 
 template <int D, int MODE>
@@ -1149,10 +1159,14 @@ static int resident_blocks_mw(int M, size_t lds) {
     case 16: return resident_blocks_x<D, MODE, 16, WPB>(lds);
     default: break;
   }
-  if (M <= 8) return resident_blocks_t<D, MODE, 8, false, WPB>(lds);
-  if (M <= 10) return resident_blocks_t<D, MODE, 10, false, WPB>(lds);
-  if (M <= 12) return resident_blocks_t<D, MODE, 12, false, WPB>(lds);
-  return resident_blocks_t<D, MODE, 16, false, WPB>(lds);
+  if constexpr (WPB != EW) {
+    return 0;
+  } else {
+    if (M <= 8) return resident_blocks_t<D, MODE, 8, false, WPB>(lds);
+    if (M <= 10) return resident_blocks_t<D, MODE, 10, false, WPB>(lds);
+    if (M <= 12) return resident_blocks_t<D, MODE, 12, false, WPB>(lds);
+    return resident_blocks_t<D, MODE, 16, false, WPB>(lds);
+  }
 }
 
 template <int D, int MODE>
