@@ -453,9 +453,9 @@ enum { KM_EVAL = 0, KM_SCD = 1, KM_WMAIN = 2, KM_WFAIL = 3, KM_FIX = 4 };
 // The window main pass of the exact kernels up to 10 items is held to 3
 // waves per SIMD, the occupancy its LDS allows (without the hint it compiles
 // just above the register limit).  The larger ones would spill registers
-// under that limit; a build of one of them that spilled gave wrong window
-// sums where the same source without the limit did not, so they keep every
-// register they need.
+// under that limit; a build of one of them that spilled gave wrong
+// multipliers after a window pass where the same source without the limit
+// did not, so they keep every register they need.
 template <int MODE, int EM, bool EXACT> struct EllWaves {
   static constexpr int value = (MODE == 2 && EXACT && EM <= 10) ? 3 : 1;
 };
