@@ -249,10 +249,13 @@ kp_status kp_get_timing(void *ctx, double *sweep_ms_total, int64_t *sweep_launch
 kp_status kp_get_batched_passes(void *ctx, int64_t *passes);
 
 /* Streaming-read probe (the roofline's measured ceiling): reads bytes (a
-   multiple of 16) from the 16-byte aligned DEV buffer src once, with the
-   sweep's access width, on hip_stream, and XORs every 64-bit word into
-   *out (DEV [1], not cleared: the caller zeroes it).  Time it with events
-   on the same stream. */
+   multiple of 16) from the 16-byte aligned DEV buffer src once with
+   nontemporal 16-byte loads (the cache policy of the sweep kernels' staging),
+   on hip_stream, and XORs a checksum into *out (DEV [1], not cleared: the
+   caller zeroes it): with (x, y, z, w) the XOR of all 16-byte words as four
+   32-bit words, ((x ^ z) << 32) | (y ^ w).  Time it with events on the
+   same stream.  KP_ERR_INVALID for NULL pointers, a misaligned src or bytes
+   not a multiple of 16. */
 kp_status kp_stream_read(void *hip_stream, const void *src, size_t bytes, uint64_t *out);
 
 /* Tile-size override for one problem shape (M, K, b_format): users per tile

@@ -475,8 +475,10 @@ def kp_csr_row_nnz(prob: Problem, ctx: Optional[Context] = None) -> int:
 
 
 def kp_stream_read(t, out=None):
-    """Read the whole of tensor t once on the current stream (the streaming
-    read probe); returns the XOR of its 64-bit words as a device tensor."""
+    """Read tensor t once on the current stream (the streaming read probe;
+    bytes past the last whole 16-byte word are not read); returns its
+    checksum as a device tensor: with (x, y, z, w) the XOR of its 16-byte
+    words as four 32-bit words, ((x ^ z) << 32) | (y ^ w)."""
     import torch
     out = torch.zeros(1, dtype=torch.int64, device="cuda") if out is None else out
     nbytes = t.numel() * t.element_size()

@@ -1360,3 +1360,22 @@ def test_categorical_scd_trajectory(name, csr_d):
         assert np.array_equal(got, want), (t, np.flatnonzero(got != want))
         lam = want
     assert want_x.max() >= 2   # some item is taken more than once
+
+
+@gpu
+@pytest.mark.parametrize("nbytes", [16, 16 * 7 + 5, 16 * (1 << 20) + 48, 64 << 20])
+def test_stream_read_checksum(nbytes):
+    """The streaming-read probe reads every whole 16-byte word once: its
+    checksum equals the host's XOR of the same words (sizes below one load
+    per thread, with a ragged tail past the unrolled loads, and 64 MB)."""
+    kp, torch = _kp()
+    print("case", nbytes, flush=True)
+    rng = np.random.default_rng(nbytes)
+    host = rng.integers(0, 256, nbytes, dtype=np.uint8)
+    t = torch.from_numpy(host).cuda()
+    got = int(kp.kp_stream_read(t).cpu().numpy().view(np.uint64)[0])
+    n16 = nbytes // 16
+    words = host[:n16 * 16].view("<u4").reshape(-1, 4)
+    acc = np.bitwise_xor.reduce(words, axis=0).astype(np.uint64)
+    want = int(((acc[0] ^ acc[2]) << np.uint64(32)) | (acc[1] ^ acc[3]))
+    assert got == want
