@@ -55,8 +55,11 @@ __host__ __device__ inline size_t dn_lds(int M, int K, int L, bool win) {
 
 // EM: the item-count class (8, 10, 12, 16), M <= EM; EK: 16, the bound of
 // the knapsack count (the per-lane sums; the scoring loops run to K).
-// (Unrolling the scoring over a compile-time knapsack class, lambda in
-// registers, measured slower: 1.30 against 1.19 ms on c2.)
+// KX: the knapsack count when it is fixed at compile time (2 or 10, with M
+// equal to EM), else 0: every loop over the knapsacks then has a constant
+// trip count and unrolls (c2 DD: 0.94 -> 0.81-0.82 ms).  (Unrolling the
+// scoring over the knapsack class instead, each step guarded by k < K and
+// lambda in registers, measured slower: 1.12 against 0.94 ms on c2.)
 // WIN: the SCD window pass (every knapsack still searching has a window
 // around lambda_k^t, Sec. 5.2's threshold search started around its last
 // value): after the evaluation, every lane tests its user per window
@@ -64,11 +67,11 @@ __host__ __device__ inline size_t dn_lds(int M, int K, int L, bool win) {
 // from its rank neighbours and from zero -- and the (user, knapsack) pairs
 // left undecided are dealt over the wave and walked exactly (lane_walk_pair).
 // EXACT: M equals EM, so every test of an item index against M folds away.
-template <int EM, int EK, bool WIN, bool EXACT>
+template <int EM, int EK, bool WIN, bool EXACT, int KX>
 __global__ void __launch_bounds__(64) k_dense(const SweepArgs a, int x4) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = threadIdx.x;
-  const int M = EXACT ? EM : a.pr.M, K = a.pr.K, L = a.tree.L;
+  const int M = EXACT ? EM : a.pr.M, K = KX ? KX : a.pr.K, L = a.tree.L;
   size_t off = 0;
   auto carve = [&](size_t bytes) { unsigned char *p = smem + off; off += dn_r16(bytes); return p; };
   double *lam = (double *)carve((size_t)K * 8);
@@ -332,9 +335,9 @@ __global__ void __launch_bounds__(64) k_dense(const SweepArgs a, int x4) {
   }
 }
 
-template <int EM, int EK, bool WIN, bool EXACT>
+template <int EM, int EK, bool WIN, bool EXACT, int KX = 0>
 hipError_t launch_dense_t(const SweepArgs &a, size_t lds, int grid, int x4, hipStream_t stream, int *used) {
-  const void *fn = (const void *)k_dense<EM, EK, WIN, EXACT>;
+  const void *fn = (const void *)k_dense<EM, EK, WIN, EXACT, KX>;
   if (lds > 64 * 1024) {
     const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -347,13 +350,13 @@ hipError_t launch_dense_t(const SweepArgs &a, size_t lds, int grid, int x4, hipS
   const int resident = per_cu * cus;
   if (grid <= 0 || grid > resident) grid = resident;
   if (used) *used = grid;
-  hipLaunchKernelGGL((k_dense<EM, EK, WIN, EXACT>), dim3(grid), dim3(64), lds, stream, a, x4);
+  hipLaunchKernelGGL((k_dense<EM, EK, WIN, EXACT, KX>), dim3(grid), dim3(64), lds, stream, a, x4);
   return hipGetLastError();
 }
 
-template <int EM, int EK, bool WIN, bool EXACT>
+template <int EM, int EK, bool WIN, bool EXACT, int KX = 0>
 int resident_dense_t(size_t lds) {
-  const void *fn = (const void *)k_dense<EM, EK, WIN, EXACT>;
+  const void *fn = (const void *)k_dense<EM, EK, WIN, EXACT, KX>;
   if (lds > 64 * 1024 &&
       hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return 0;
@@ -436,9 +439,16 @@ hipError_t kp_launch_dense(const SweepArgs &a, int grid, hipStream_t stream, int
   const int x4 = (((uintptr_t)a.pr.p | (uintptr_t)a.pr.b) & 15) == 0;
   return dispatch_dense(M, K, [&](auto em, auto ek) {
     constexpr int EM = decltype(em)::value, EK = decltype(ek)::value;
-    if (M == EM)
+    if (M == EM) {
+      if (K == 10)
+        return win ? launch_dense_t<EM, EK, true, true, 10>(a, lds, grid, x4, stream, used)
+                   : launch_dense_t<EM, EK, false, true, 10>(a, lds, grid, x4, stream, used);
+      if (K == 2)
+        return win ? launch_dense_t<EM, EK, true, true, 2>(a, lds, grid, x4, stream, used)
+                   : launch_dense_t<EM, EK, false, true, 2>(a, lds, grid, x4, stream, used);
       return win ? launch_dense_t<EM, EK, true, true>(a, lds, grid, x4, stream, used)
                  : launch_dense_t<EM, EK, false, true>(a, lds, grid, x4, stream, used);
+    }
     return win ? launch_dense_t<EM, EK, true, false>(a, lds, grid, x4, stream, used)
                : launch_dense_t<EM, EK, false, false>(a, lds, grid, x4, stream, used);
   });
@@ -451,7 +461,11 @@ int kp_dense_resident_grid(int M, int K, int L, bool win) {
   const size_t lds = dn_lds(M, K, L, win);
   return dispatch_dense(M, K, [&](auto em, auto ek) {
     constexpr int EM = decltype(em)::value, EK = decltype(ek)::value;
-    if (M == EM) return win ? resident_dense_t<EM, EK, true, true>(lds) : resident_dense_t<EM, EK, false, true>(lds);
+    if (M == EM) {
+      if (K == 10) return win ? resident_dense_t<EM, EK, true, true, 10>(lds) : resident_dense_t<EM, EK, false, true, 10>(lds);
+      if (K == 2) return win ? resident_dense_t<EM, EK, true, true, 2>(lds) : resident_dense_t<EM, EK, false, true, 2>(lds);
+      return win ? resident_dense_t<EM, EK, true, true>(lds) : resident_dense_t<EM, EK, false, true>(lds);
+    }
     return win ? resident_dense_t<EM, EK, true, false>(lds) : resident_dense_t<EM, EK, false, false>(lds);
   });
 }

@@ -341,6 +341,11 @@ DENSE_LANE_CASES = [
     ("M16-K16-zeros", lambda: random_instance(np.random.default_rng(66), 640, 16, 16, Q=6, zero_frac=0.3)),
     ("M12-K4-one-user", lambda: random_instance(np.random.default_rng(67), 1, 12, 4, Q=2)),
     ("c2-like", lambda: kpgen.config_instance(2, N=8000)),
+    # exact item and knapsack counts (the kernels with K fixed at compile time)
+    ("M8-K10-top2", lambda: random_instance(np.random.default_rng(68), 3001, 8, 10, Q=2)),
+    ("M16-K10-top4", lambda: random_instance(np.random.default_rng(69), 2500, 16, 10, Q=4)),
+    ("M12-K2-laminar", lambda: random_instance(np.random.default_rng(70), 4000, 12, 2,
+                                               tree=random_laminar(12, np.random.default_rng(71)))),
 ]
 
 
@@ -1282,6 +1287,8 @@ DENSE_WINDOW_CASES = [
     ("c2-N6000", lambda: kpgen.config_instance(2, N=6000), 10, 6, True),
     ("M10-K6-hier-N4000", lambda: kpgen.make_instance(4000, 10, 6, seed=75, p_dist="exp1", budget_frac=0.08,
                                                       tree=kpgen.tree_hier_2_2_3(10)), 10, 6, None),
+    ("M8-K2-top2-N5000", lambda: kpgen.make_instance(5000, 8, 2, seed=86, Q=2, budget_frac=0.1), 16, 12, None),
+    ("M12-K10-top3-N4000", lambda: kpgen.make_instance(4000, 12, 10, seed=87, Q=3, budget_frac=0.08), 10, 6, None),
 ]
 
 
