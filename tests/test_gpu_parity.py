@@ -778,6 +778,11 @@ ELL_CASES = [
     # compact statistics path, top-6 the other one
     ("csr-d2-M16-K40-top4", lambda: kpgen.make_instance(2100, 16, 40, seed=43, Q=4, csr_d=2, budget_frac=0.1)),
     ("csr-d2-M16-K40-top6", lambda: kpgen.make_instance(2100, 16, 40, seed=44, Q=6, csr_d=2, budget_frac=0.1)),
+    # M = 10 with the knapsack count compiled in: K = 10 on the non-compact
+    # statistics path, K = 20 with one entry per item row and laminar sets
+    ("csr-d2-M10-K10-top6", lambda: kpgen.make_instance(3333, 10, 10, seed=45, Q=6, csr_d=2, budget_frac=0.1)),
+    ("csr-d1-M10-K20-laminar", lambda: kpgen.make_instance(2999, 10, 20, seed=46, csr_d=1, budget_frac=0.08,
+                                                           tree=random_laminar(10, np.random.default_rng(5)))),
 ]
 
 
